@@ -1,0 +1,657 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU oracle of the lattice Boltzmann method for
+ * antiplane shear with dynamic mode III crack growth (arXiv:2206.12412).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the CPU
+ * baseline of the benchmark; never by the product path.  Slow and literal on
+ * purpose: loops over j, i, alpha; no blocking, no fusion beyond the order in
+ * which the paper states the steps.
+ *
+ * One time step (Sec. 3 and Sec. 4.1):
+ *   1. streaming of the post-collision populations along the D2Q5 links
+ *      (eq. LBE, left-hand side); a population whose link is severed by the
+ *      crack or leaves the plate is bounced back (traction-free), plus a
+ *      traction term on loaded links;
+ *   2. particle velocity wdot = sum_alpha f^alpha          (eq. distrib-macro);
+ *   3. Euler update w += dt * wdot                          (eq. integration);
+ *   4. BGK collision towards f_eq(w, wdot)                  (eq. LBE, eq. f-eq);
+ *   5. crack step appended after the integration (Alg. 1): evaluate the
+ *      criterion with K from eq. (sif), advance the tip, find the intersected
+ *      links by the breadth-first CheckLinks search, sever them.
+ *
+ * Readings taken where the paper is silent or garbled (each is listed in the
+ * design notes of the repository):
+ *   - f_eq^kappa = lambda w / (2 c^2): the printed lambda w / c^2 makes the
+ *     zeroth moment of f_eq differ from wdot (eq. f-eq vs eq. distrib-macro);
+ *   - lambda = c_s^2 / (dt (1/omega - 1/2)), which is the printed formula for
+ *     mu = rho, tau = dt, dh = 1;
+ *   - bounce-back at the link midpoint; a traction t* adds
+ *     (dt / (rho dh)) t* to the reflected population (momentum balance);
+ *   - a vertical link is severed when the closed crack segment touches it;
+ *   - K uses the column i_K = floor(a - r_min), r = a - i_K, r_min from
+ *     eq. r(v) with the speed of the previous step.
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NPOP 5
+static const int EX[NPOP] = {0, 1, 0, -1, 0};
+static const int EY[NPOP] = {0, 0, 1, 0, -1};
+static const int OPP[NPOP] = {0, 3, 4, 1, 2};
+
+typedef struct { int32_t i, j, o; } link_t;  /* o: 0 vertical, 1 horizontal */
+
+struct orc_sim {
+  orc_config cfg;
+  double *tau;                       /* private copy of the traction history */
+  double cs, c, dt, lambda, A0, Ak, coef;
+  int32_t j0;
+  double yc;
+  double *f, *fn, *w;
+  uint8_t *cutV, *cutH;
+  double tip, v;
+  int64_t step;
+  int32_t flags;
+  /* boundary points of the previous increment (Alg. 1, B_prev) */
+  int32_t *bprev, nbprev, capbprev;
+  /* traces */
+  double *trK, *trA, *trV;
+  int32_t *trF;
+  /* cut events */
+  int64_t *evs;
+  int32_t *evi, *evj, *evo;
+  int64_t nev, capev;
+  /* scratch for the breadth-first search */
+  uint8_t *inq, *vis;
+  int32_t *queue, *touched;
+};
+
+static inline size_t IDX(const orc_sim *s, int i, int j) {
+  return (size_t)j * (size_t)s->cfg.nx + (size_t)i;
+}
+static inline double *POP(orc_sim *s, double *base, int a) {
+  return base + (size_t)a * (size_t)s->cfg.nx * (size_t)s->cfg.ny;
+}
+
+/* ---------------------------------------------------------------- links -- */
+
+/* Link between site (i, j) and its neighbour in direction (dx, dy), |dx|+|dy| = 1.
+ * Returns 0 if the neighbour lies outside the plate (walls mode). */
+static int link_of(const orc_sim *s, int i, int j, int dx, int dy, link_t *L) {
+  const int nx = s->cfg.nx, ny = s->cfg.ny;
+  int ni = i + dx, nj = j + dy;
+  if (s->cfg.periodic) {
+    ni = (ni + nx) % nx;
+    nj = (nj + ny) % ny;
+  } else if (ni < 0 || ni >= nx || nj < 0 || nj >= ny) {
+    return 0;
+  }
+  if (dy == 0) { /* horizontal link, stored at its left end (i, i+1 mod nx) */
+    L->o = 1;
+    L->j = j;
+    L->i = (dx > 0) ? i : ni;
+  } else {       /* vertical link, stored at its lower end */
+    L->o = 0;
+    L->i = i;
+    L->j = (dy > 0) ? j : nj;
+  }
+  return 1;
+}
+
+static int is_cut(const orc_sim *s, const link_t *L) {
+  size_t k = (size_t)L->j * (size_t)s->cfg.nx + (size_t)L->i;
+  return L->o == 0 ? s->cutV[k] : s->cutH[k];
+}
+
+static void set_cut(orc_sim *s, const link_t *L) {
+  size_t k = (size_t)L->j * (size_t)s->cfg.nx + (size_t)L->i;
+  if (L->o == 0) s->cutV[k] = 1; else s->cutH[k] = 1;
+}
+
+/* Segment-segment intersection of closed segments (touching counts). */
+static int orient(double px, double py, double qx, double qy, double rx, double ry) {
+  double d = (qx - px) * (ry - py) - (qy - py) * (rx - px);
+  return (d > 0) - (d < 0);
+}
+static int on_segment(double px, double py, double qx, double qy, double rx, double ry) {
+  /* r collinear with p-q: is it inside the bounding box of p-q? */
+  return fmin(px, qx) <= rx && rx <= fmax(px, qx) && fmin(py, qy) <= ry && ry <= fmax(py, qy);
+}
+static int segments_intersect(double p1x, double p1y, double p2x, double p2y,
+                              double q1x, double q1y, double q2x, double q2y) {
+  int d1 = orient(q1x, q1y, q2x, q2y, p1x, p1y);
+  int d2 = orient(q1x, q1y, q2x, q2y, p2x, p2y);
+  int d3 = orient(p1x, p1y, p2x, p2y, q1x, q1y);
+  int d4 = orient(p1x, p1y, p2x, p2y, q2x, q2y);
+  if (d1 * d2 < 0 && d3 * d4 < 0) return 1;
+  if (d1 == 0 && on_segment(q1x, q1y, q2x, q2y, p1x, p1y)) return 1;
+  if (d2 == 0 && on_segment(q1x, q1y, q2x, q2y, p2x, p2y)) return 1;
+  if (d3 == 0 && on_segment(p1x, p1y, p2x, p2y, q1x, q1y)) return 1;
+  if (d4 == 0 && on_segment(p1x, p1y, p2x, p2y, q2x, q2y)) return 1;
+  return 0;
+}
+
+/* Does the crack segment (a0, yc)-(a1, yc) intersect the link from site p to
+ * its neighbour n?  Links are the straight lines between lattice points. */
+static int seg_hits_link(const orc_sim *s, double a0, double a1, int pi, int pj, int ni, int nj) {
+  return segments_intersect(a0, s->yc, a1, s->yc, (double)pi, (double)pj, (double)ni, (double)nj);
+}
+
+/* ------------------------------------------------------------- creation -- */
+
+orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
+  int32_t e = 0;
+  if (cfg->nx < 1 || cfg->ny < 1) e = -1;
+  else if (!(cfg->kappa > 0) || !(cfg->omega > 0 && cfg->omega < 2)) e = -1;
+  else if (!(cfg->mu > 0) || !(cfg->rho > 0)) e = -1;
+  /* omega = 1 is the leapfrog scheme: stable only for kappa > sqrt(2). */
+  else if (cfg->kappa * cfg->kappa <= 2.0) e = -4;
+  else if (cfg->has_crack && (cfg->ny < 2 || cfg->ny % 2 != 0)) e = -1;
+  else if (cfg->has_crack && !(cfg->crack_x0 >= -0.5 && cfg->crack_tip >= cfg->crack_x0 &&
+                               cfg->crack_tip <= cfg->nx - 0.5)) e = -5;
+  else if (cfg->growth != ORC_GROW_NONE && (!cfg->has_crack || cfg->periodic)) e = -1;
+  else if (cfg->growth == ORC_GROW_PRESCRIBED && !(cfg->v_rel >= 0 && cfg->v_rel < 1)) e = -1;
+  else if (cfg->growth == ORC_GROW_SIF && !(cfg->K_C > 0 && cfg->v_max >= 0 && cfg->v_max < 1))
+    e = -1;
+  else if (cfg->has_crack && !(cfg->r0 > 0)) e = -1;
+  else if (cfg->has_crack && cfg->k_band < 1) e = -1;
+  else if (cfg->n_hist < 0 || (cfg->n_hist > 0 && !cfg->tau_hist)) e = -1;
+  if (e) {
+    if (err) *err = e;
+    return NULL;
+  }
+  orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+  s->cfg = *cfg;
+  const size_t n = (size_t)cfg->nx * (size_t)cfg->ny;
+  s->tau = NULL;
+  if (cfg->n_hist > 0) {
+    s->tau = (double *)malloc(sizeof(double) * (size_t)cfg->n_hist);
+    memcpy(s->tau, cfg->tau_hist, sizeof(double) * (size_t)cfg->n_hist);
+  }
+  s->cfg.tau_hist = s->tau;
+  s->cfg.w0 = NULL;
+  s->cfg.wdot0 = NULL;
+
+  /* Lattice constants (Sec. 3): c = kappa c_s, dt = dh / c with dh = 1. */
+  s->cs = sqrt(cfg->mu / cfg->rho);
+  s->c = cfg->kappa * s->cs;
+  s->dt = 1.0 / s->c;
+  s->lambda = s->cs * s->cs / (s->dt * (1.0 / cfg->omega - 0.5));
+  s->A0 = 2.0 * s->lambda / (s->c * s->c);
+  s->Ak = s->lambda / (2.0 * s->c * s->c);
+  s->coef = s->dt / (cfg->rho * 1.0);
+  s->j0 = cfg->ny / 2 - 1;
+  s->yc = s->j0 + 0.5;
+
+  s->f = (double *)calloc(NPOP * n, sizeof(double));
+  s->fn = (double *)calloc(NPOP * n, sizeof(double));
+  s->w = (double *)calloc(n, sizeof(double));
+  s->cutV = (uint8_t *)calloc(n, 1);
+  s->cutH = (uint8_t *)calloc(n, 1);
+  s->inq = (uint8_t *)calloc(n, 1);
+  s->vis = (uint8_t *)calloc(n, 1);
+  s->queue = (int32_t *)malloc(sizeof(int32_t) * n);
+  s->touched = (int32_t *)malloc(sizeof(int32_t) * n);
+
+  /* Initial state: at rest or the given fields, populations in equilibrium. */
+  for (int j = 0; j < cfg->ny; ++j)
+    for (int i = 0; i < cfg->nx; ++i) {
+      size_t x = IDX(s, i, j);
+      double w = cfg->w0 ? cfg->w0[x] : 0.0;
+      double wd = cfg->wdot0 ? cfg->wdot0[x] : 0.0;
+      s->w[x] = w;
+      POP(s, s->f, 0)[x] = wd - s->A0 * w;
+      for (int a = 1; a < NPOP; ++a) POP(s, s->f, a)[x] = s->Ak * w;
+    }
+
+  /* Initial crack: every link intersected by the segment x0..a0 is severed. */
+  s->tip = cfg->crack_tip;
+  s->v = 0.0;
+  s->capbprev = 64;
+  s->bprev = (int32_t *)malloc(sizeof(int32_t) * 2 * s->capbprev);
+  s->nbprev = 0;
+  if (cfg->has_crack) {
+    for (int j = 0; j < cfg->ny; ++j)
+      for (int i = 0; i < cfg->nx; ++i) {
+        link_t L;
+        if (link_of(s, i, j, 0, 1, &L) && seg_hits_link(s, cfg->crack_x0, cfg->crack_tip, i, j, i, j + 1))
+          set_cut(s, &L);
+        if (link_of(s, i, j, 1, 0, &L) && seg_hits_link(s, cfg->crack_x0, cfg->crack_tip, i, j, i + 1, j))
+          set_cut(s, &L);
+      }
+    /* B_prev: the pair of sites around the crack line at the tip column. */
+    int c = (int)floor(cfg->crack_tip);
+    if (c < 0) c = 0;
+    if (c > cfg->nx - 1) c = cfg->nx - 1;
+    s->bprev[0] = c; s->bprev[1] = s->j0;
+    s->bprev[2] = c; s->bprev[3] = s->j0 + 1;
+    s->nbprev = 2;
+  }
+
+  if (cfg->trace_cap > 0) {
+    s->trK = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
+    s->trA = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
+    s->trV = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
+    s->trF = (int32_t *)calloc((size_t)cfg->trace_cap, sizeof(int32_t));
+  }
+  s->capev = 16;
+  s->evs = (int64_t *)malloc(sizeof(int64_t) * s->capev);
+  s->evi = (int32_t *)malloc(sizeof(int32_t) * s->capev);
+  s->evj = (int32_t *)malloc(sizeof(int32_t) * s->capev);
+  s->evo = (int32_t *)malloc(sizeof(int32_t) * s->capev);
+  if (err) *err = 0;
+  return s;
+}
+
+void orc_free(orc_sim *s) {
+  if (!s) return;
+  free(s->tau); free(s->f); free(s->fn); free(s->w); free(s->cutV); free(s->cutH);
+  free(s->inq); free(s->vis); free(s->queue); free(s->touched); free(s->bprev);
+  free(s->trK); free(s->trA); free(s->trV); free(s->trF);
+  free(s->evs); free(s->evi); free(s->evj); free(s->evo);
+  free(s);
+}
+
+/* ------------------------------------------------------------ LBM sweep -- */
+
+/* Traction t* on the boundary seen by the population of site (i, j) that is
+ * pulled along alpha, when that link is severed or leaves the plate. */
+static double traction(const orc_sim *s, int j, int alpha, int outside, double tau) {
+  if (s->cfg.periodic) return 0.0;
+  if (outside) {
+    /* top edge (outward normal +y) carries sigma_yz = tau, bottom edge -tau;
+     * the lateral edges are traction-free */
+    if (alpha == 4 && j == s->cfg.ny - 1) return tau;
+    if (alpha == 2 && j == 0) return -tau;
+    return 0.0;
+  }
+  /* severed link: crack faces, loaded only in the face-traction test mode;
+   * the face above the crack has outward normal -y, the one below +y */
+  if (alpha == 2) return s->cfg.face_traction;
+  if (alpha == 4) return -s->cfg.face_traction;
+  return 0.0;
+}
+
+static double tau_at(const orc_sim *s, int64_t n) {
+  if (s->cfg.n_hist <= 0) return 0.0;
+  return s->tau[n < s->cfg.n_hist ? n : s->cfg.n_hist - 1];
+}
+
+static int sweep_threads(const orc_sim *s) {
+#ifdef _OPENMP
+  return s->cfg.threads > 0 ? s->cfg.threads : omp_get_max_threads();
+#else
+  (void)s;
+  return 1;
+#endif
+}
+
+static void lbm_sweep(orc_sim *s) {
+  const int nx = s->cfg.nx, ny = s->cfg.ny;
+  const double tau = tau_at(s, s->step);
+  const double omega = s->cfg.omega;
+#pragma omp parallel for schedule(static) num_threads(sweep_threads(s))
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      const size_t x = IDX(s, i, j);
+      double fin[NPOP];
+      fin[0] = POP(s, s->f, 0)[x];
+      for (int a = 1; a < NPOP; ++a) {
+        /* pull from the upstream neighbour y = x - c^alpha */
+        link_t L;
+        int inside = link_of(s, i, j, -EX[a], -EY[a], &L);
+        if (inside && !is_cut(s, &L)) {
+          int si = i - EX[a], sj = j - EY[a];
+          if (s->cfg.periodic) { si = (si + nx) % nx; sj = (sj + ny) % ny; }
+          fin[a] = POP(s, s->f, a)[IDX(s, si, sj)];
+        } else {
+          /* bounce-back: the population that left x towards y returns */
+          fin[a] = POP(s, s->f, OPP[a])[x] + s->coef * traction(s, j, a, !inside, tau);
+        }
+      }
+      double wd = fin[0] + fin[1] + fin[2] + fin[3] + fin[4];
+      double wn = s->w[x] + s->dt * wd;
+      double feq[NPOP];
+      feq[0] = wd - s->A0 * wn;
+      for (int a = 1; a < NPOP; ++a) feq[a] = s->Ak * wn;
+      for (int a = 0; a < NPOP; ++a) POP(s, s->fn, a)[x] = fin[a] - omega * (fin[a] - feq[a]);
+      s->w[x] = wn;
+    }
+  }
+  double *t = s->f; s->f = s->fn; s->fn = t;
+}
+
+/* -------------------------------------------------------- crack handling -- */
+
+double orc_sif(double delta, double r, double mu) {
+  return delta * (mu / 4.0) * sqrt(2.0 * M_PI / r);
+}
+
+/* K at the current tip from the displacement jump across the crack faces. */
+static double evaluate_K(const orc_sim *s, double vK, int32_t *undef) {
+  const int nx = s->cfg.nx;
+  const double rmin = s->cfg.r0 / (1.0 - vK);
+  const double iKf = floor(s->tip - rmin);
+  const int band = s->cfg.k_band;
+  *undef = 1;
+  if (!(iKf - (band - 1) >= 0.0) || !(iKf <= nx - 1) || iKf - (band - 1) < s->cfg.crack_x0)
+    return NAN;
+  const int iK = (int)iKf;
+  *undef = 0;
+  if (band == 1) {
+    double delta = fabs(s->w[IDX(s, iK, s->j0 + 1)] - s->w[IDX(s, iK, s->j0)]);
+    return orc_sif(delta, s->tip - iK, s->cfg.mu);
+  }
+  /* several columns: least-squares fit of delta_i = (4K/mu) sqrt(r_i / 2 pi) */
+  double num = 0.0, den = 0.0;
+  for (int b = 0; b < band; ++b) {
+    int i = iK - b;
+    double r = s->tip - i;
+    double sq = sqrt(r / (2.0 * M_PI));
+    double delta = fabs(s->w[IDX(s, i, s->j0 + 1)] - s->w[IDX(s, i, s->j0)]);
+    num += delta * sq;
+    den += sq * sq;
+  }
+  return (s->cfg.mu / 4.0) * num / den;
+}
+
+/* Alg. 1, CheckLinks: breadth-first search from the neighbours of the
+ * previous boundary points; every link of a popped point is tested against
+ * the new segment; a hit adds both ends to B and the neighbours of the far
+ * end to the queue.  Returns the intersected links (and B through bout). */
+static int32_t check_links_bfs(orc_sim *s, double a0, double a1, const int32_t *bprev, int32_t nb,
+                               link_t *hits, int32_t caphits, int32_t *bout, int32_t *nbout,
+                               int32_t capb) {
+  const int nx = s->cfg.nx;
+  int32_t head = 0, tail = 0, nt = 0, nh = 0;
+  *nbout = 0;
+  /* Q <- N(B_prev) */
+  for (int p = 0; p < nb; ++p)
+    for (int a = 1; a < NPOP; ++a) {
+      link_t L;
+      int pi = bprev[2 * p], pj = bprev[2 * p + 1];
+      if (!link_of(s, pi, pj, EX[a], EY[a], &L)) continue;
+      size_t k = IDX(s, pi + EX[a], pj + EY[a]);
+      if (!s->inq[k]) { s->inq[k] = 1; s->queue[tail++] = (int32_t)k; s->touched[nt++] = (int32_t)k; }
+    }
+  while (head < tail) {
+    const int32_t k = s->queue[head++]; /* pop p */
+    const int pi = k % nx, pj = k / nx;
+    s->vis[k] = 1;                     /* mark as visited */
+    for (int a = 1; a < NPOP; ++a) {
+      link_t L;
+      if (!link_of(s, pi, pj, EX[a], EY[a], &L)) continue;
+      const int ni = pi + EX[a], nj = pj + EY[a];
+      if (!seg_hits_link(s, a0, a1, pi, pj, ni, nj)) continue;
+      /* B <- B u {p, n_p} */
+      int seen = 0;
+      for (int h = 0; h < nh; ++h)
+        if (hits[h].i == L.i && hits[h].j == L.j && hits[h].o == L.o) seen = 1;
+      if (!seen && nh < caphits) hits[nh++] = L;
+      const int ends[2][2] = {{pi, pj}, {ni, nj}};
+      for (int e = 0; e < 2; ++e) {
+        int dup = 0;
+        for (int b = 0; b < *nbout; ++b)
+          if (bout[2 * b] == ends[e][0] && bout[2 * b + 1] == ends[e][1]) dup = 1;
+        if (!dup && *nbout < capb) {
+          bout[2 * *nbout] = ends[e][0];
+          bout[2 * *nbout + 1] = ends[e][1];
+          ++*nbout;
+        }
+      }
+      /* Q <- Q u N(n_p) \ V */
+      for (int b = 1; b < NPOP; ++b) {
+        link_t M;
+        if (!link_of(s, ni, nj, EX[b], EY[b], &M)) continue;
+        size_t q = IDX(s, ni + EX[b], nj + EY[b]);
+        if (!s->vis[q] && !s->inq[q]) { s->inq[q] = 1; s->queue[tail++] = (int32_t)q; s->touched[nt++] = (int32_t)q; }
+      }
+    }
+  }
+  for (int t = 0; t < nt; ++t) { s->inq[s->touched[t]] = 0; s->vis[s->touched[t]] = 0; }
+  return nh;
+}
+
+double orc_eval_K(const orc_sim *s, double vK) {
+  int32_t undef;
+  return evaluate_K(s, vK, &undef);
+}
+
+static void record_event(orc_sim *s, const link_t *L) {
+  if (s->nev == s->capev) {
+    s->capev *= 2;
+    s->evs = (int64_t *)realloc(s->evs, sizeof(int64_t) * s->capev);
+    s->evi = (int32_t *)realloc(s->evi, sizeof(int32_t) * s->capev);
+    s->evj = (int32_t *)realloc(s->evj, sizeof(int32_t) * s->capev);
+    s->evo = (int32_t *)realloc(s->evo, sizeof(int32_t) * s->capev);
+  }
+  s->evs[s->nev] = s->step;
+  s->evi[s->nev] = L->i;
+  s->evj[s->nev] = L->j;
+  s->evo[s->nev] = L->o;
+  s->nev++;
+}
+
+/* Alg. 1, CrackGrowth, appended after the time integration of the step. */
+static void crack_step(orc_sim *s) {
+  const orc_config *cfg = &s->cfg;
+  const double vK = (cfg->growth == ORC_GROW_PRESCRIBED) ? cfg->v_rel : s->v;
+  int32_t undef = 0;
+  const double K = evaluate_K(s, vK, &undef);
+  int32_t flags = s->flags & ORC_FLAG_WALL;
+  if (undef) flags |= ORC_FLAG_K_UNDEF;
+
+  /* EvaluateCriterion */
+  int grow = 0;
+  double v = 0.0;
+  if (!(s->flags & ORC_FLAG_WALL)) {
+    if (cfg->growth == ORC_GROW_PRESCRIBED) {
+      grow = 1;
+      v = cfg->v_rel;
+    } else if (cfg->growth == ORC_GROW_SIF && K > cfg->K_C) {
+      /* eq. (v-tanh): crack speed regularised by the overshoot of K */
+      double q = K / cfg->K_C;
+      double q2 = q * q;
+      v = cfg->v_max * tanh(sqrt(q2 * q2 - 1.0));
+      grow = 1;
+    }
+  }
+  if (grow) {
+    /* cr_tip <- cr_tip + v dt along +x; the increment is Delta a = (v c_s) dt */
+    const double a_prev = s->tip;
+    double a_new = a_prev + (v * s->cs) * s->dt;
+    if (a_new >= cfg->nx - 0.5) {
+      a_new = cfg->nx - 0.5;
+      flags |= ORC_FLAG_WALL;
+    }
+    link_t hits[16];
+    int32_t bnew[32];
+    int32_t nbnew = 0;
+    int32_t nh = check_links_bfs(s, a_prev, a_new, s->bprev, s->nbprev, hits, 16, bnew, &nbnew, 16);
+    /* ProcessPoints: sever the intersected links (no exchange along them) */
+    for (int h = 0; h < nh; ++h) {
+      if (!is_cut(s, &hits[h])) {
+        set_cut(s, &hits[h]);
+        record_event(s, &hits[h]);
+      }
+    }
+    if (nbnew > 0) {
+      if (nbnew > s->capbprev) {
+        s->capbprev = nbnew;
+        s->bprev = (int32_t *)realloc(s->bprev, sizeof(int32_t) * 2 * s->capbprev);
+      }
+      memcpy(s->bprev, bnew, sizeof(int32_t) * 2 * nbnew);
+      s->nbprev = nbnew;
+    }
+    s->tip = a_new;
+    flags |= ORC_FLAG_GREW;
+  }
+  s->v = v;
+  s->flags = flags;
+  if (s->step < cfg->trace_cap) {
+    s->trK[s->step] = K;
+    s->trA[s->step] = s->tip;
+    s->trV[s->step] = v;
+    s->trF[s->step] = flags;
+  }
+}
+
+int32_t orc_step(orc_sim *s, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) {
+    lbm_sweep(s);
+    if (s->cfg.has_crack) crack_step(s);
+    s->step++;
+  }
+  return 0;
+}
+
+/* --------------------------------------------------------------- adjoint -- */
+
+double orc_adjoint_step(orc_sim *s, double *lam_f, double *lam_w) {
+  /* The step is affine in (f, w) and in tau; this applies the transpose of
+   * its linear part, site by site, in the order collision -> Euler -> moment
+   * -> streaming reversed. */
+  const int nx = s->cfg.nx, ny = s->cfg.ny;
+  const size_t n = (size_t)nx * ny;
+  const double om = s->cfg.omega;
+  double *gin = (double *)malloc(sizeof(double) * NPOP * n);
+  /* adjoint of collision, Euler update and moment, per site */
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t x = IDX(s, i, j);
+      double l[NPOP];
+      for (int a = 0; a < NPOP; ++a) l[a] = lam_f[a * n + x];
+      double G = lam_w[x] + om * (-s->A0 * l[0] + s->Ak * (l[1] + l[2] + l[3] + l[4]));
+      double gwd = om * l[0] + s->dt * G;
+      for (int a = 0; a < NPOP; ++a) gin[a * n + x] = (1.0 - om) * l[a] + gwd;
+      lam_w[x] = G;
+    }
+  /* adjoint of streaming with bounce-back */
+  double dtau = 0.0;
+  for (int a = 0; a < NPOP; ++a)
+    for (size_t x = 0; x < n; ++x) lam_f[a * n + x] = 0.0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t x = IDX(s, i, j);
+      lam_f[0 * n + x] += gin[0 * n + x];
+      for (int a = 1; a < NPOP; ++a) {
+        link_t L;
+        int inside = link_of(s, i, j, -EX[a], -EY[a], &L);
+        double g = gin[a * n + x];
+        if (inside && !is_cut(s, &L)) {
+          int si = i - EX[a], sj = j - EY[a];
+          if (s->cfg.periodic) { si = (si + nx) % nx; sj = (sj + ny) % ny; }
+          lam_f[a * n + IDX(s, si, sj)] += g;
+        } else {
+          lam_f[OPP[a] * n + x] += g;
+          if (!inside && !s->cfg.periodic) {
+            if (a == 4 && j == ny - 1) dtau += s->coef * g;
+            if (a == 2 && j == 0) dtau -= s->coef * g;
+          }
+        }
+      }
+    }
+  free(gin);
+  return dtau;
+}
+
+/* ------------------------------------------------------------- queries -- */
+
+void orc_get_fields(const orc_sim *s, double *w, double *wdot) {
+  const size_t n = (size_t)s->cfg.nx * s->cfg.ny;
+  for (size_t x = 0; x < n; ++x) {
+    if (w) w[x] = s->w[x];
+    if (wdot) {
+      double acc = 0.0;
+      for (int a = 0; a < NPOP; ++a) acc += s->f[a * n + x];
+      wdot[x] = acc;
+    }
+  }
+}
+
+void orc_get_pops(const orc_sim *s, double *f) {
+  memcpy(f, s->f, sizeof(double) * NPOP * (size_t)s->cfg.nx * s->cfg.ny);
+}
+
+void orc_set_state(orc_sim *s, const double *f, const double *w) {
+  const size_t n = (size_t)s->cfg.nx * s->cfg.ny;
+  if (f) memcpy(s->f, f, sizeof(double) * NPOP * n);
+  if (w) memcpy(s->w, w, sizeof(double) * n);
+}
+
+void orc_get_mask(const orc_sim *s, uint8_t *cutV, uint8_t *cutH) {
+  const size_t n = (size_t)s->cfg.nx * s->cfg.ny;
+  if (cutV) memcpy(cutV, s->cutV, n);
+  if (cutH) memcpy(cutH, s->cutH, n);
+}
+
+void orc_crack(const orc_sim *s, double *tip, double *v, int64_t *step, int32_t *flags) {
+  if (tip) *tip = s->tip;
+  if (v) *v = s->v;
+  if (step) *step = s->step;
+  if (flags) *flags = s->flags;
+}
+
+int64_t orc_traces(const orc_sim *s, double *K, double *tip, double *v, int32_t *flags,
+                   int64_t cap) {
+  int64_t n = s->step < s->cfg.trace_cap ? s->step : s->cfg.trace_cap;
+  if (n > cap) n = cap;
+  for (int64_t k = 0; k < n; ++k) {
+    if (K) K[k] = s->trK[k];
+    if (tip) tip[k] = s->trA[k];
+    if (v) v[k] = s->trV[k];
+    if (flags) flags[k] = s->trF[k];
+  }
+  return n;
+}
+
+int64_t orc_events(const orc_sim *s, int64_t *step, int32_t *i, int32_t *j, int32_t *orient,
+                   int64_t cap) {
+  int64_t n = s->nev < cap ? s->nev : cap;
+  for (int64_t k = 0; k < n; ++k) {
+    if (step) step[k] = s->evs[k];
+    if (i) i[k] = s->evi[k];
+    if (j) j[k] = s->evj[k];
+    if (orient) orient[k] = s->evo[k];
+  }
+  return s->nev;
+}
+
+void orc_constants(const orc_sim *s, double out[7]) {
+  out[0] = s->cs; out[1] = s->c; out[2] = s->dt; out[3] = s->lambda;
+  out[4] = s->A0; out[5] = s->Ak; out[6] = s->coef;
+}
+
+void orc_check_links(const orc_sim *s_in, double a_prev, double a_new, int32_t b_col,
+                     int32_t *bfs_links, int32_t *n_bfs, int32_t *all_links, int32_t *n_all,
+                     int32_t cap) {
+  orc_sim *s = (orc_sim *)s_in;
+  link_t hits[64];
+  int32_t bp[4] = {b_col, s->j0, b_col, s->j0 + 1};
+  int32_t bout[128], nbout = 0;
+  int32_t nh = check_links_bfs(s, a_prev, a_new, bp, 2, hits, 64, bout, &nbout, 64);
+  *n_bfs = 0;
+  for (int h = 0; h < nh && h < cap; ++h) {
+    bfs_links[3 * h] = hits[h].i; bfs_links[3 * h + 1] = hits[h].j; bfs_links[3 * h + 2] = hits[h].o;
+    ++*n_bfs;
+  }
+  *n_all = 0;
+  for (int j = 0; j < s->cfg.ny; ++j)
+    for (int i = 0; i < s->cfg.nx; ++i) {
+      link_t L;
+      if (link_of(s, i, j, 0, 1, &L) && seg_hits_link(s, a_prev, a_new, i, j, i, j + 1) && *n_all < cap) {
+        all_links[3 * *n_all] = L.i; all_links[3 * *n_all + 1] = L.j; all_links[3 * *n_all + 2] = 0;
+        ++*n_all;
+      }
+      if (link_of(s, i, j, 1, 0, &L) && seg_hits_link(s, a_prev, a_new, i, j, i + 1, j) && *n_all < cap) {
+        all_links[3 * *n_all] = L.i; all_links[3 * *n_all + 1] = L.j; all_links[3 * *n_all + 2] = 1;
+        ++*n_all;
+      }
+    }
+}
