@@ -1,0 +1,181 @@
+/*
+ * lbm.h -- C-ABI of liblbmcrack: an MI355X (gfx950) lattice Boltzmann solver
+ * for antiplane shear with a dynamically growing mode III crack, after
+ * H. Mueller, A. Touil, A. Schlueter, R. Mueller, "Dynamic Propagation of
+ * Mode III Cracks in a Lattice Boltzmann Method for Solids", arXiv:2206.12412.
+ *
+ * The method (paper Sec. 3 and Sec. 4):
+ *   - D2Q5 lattice, populations f^alpha, alpha = 0 rest, 1 +x, 2 +y, 3 -x, 4 -y
+ *     (Sec. 3, lattice velocities);
+ *   - BGK lattice Boltzmann equation (Sec. 3, eq. LBE) with
+ *     wdot = sum_alpha f^alpha (eq. distrib-macro), the Euler update
+ *     w <- w + dt wdot (eq. integration) and the wave-equation equilibrium
+ *     f_eq^0 = wdot - 2 lambda w / c^2, f_eq^k = lambda w / (2 c^2) (eq. f-eq,
+ *     with the zeroth moment of f_eq equal to wdot), lambda = c_s^2 / (dt (tau/dt - 1/2)),
+ *     c_s = sqrt(mu / rho), c = kappa c_s, dt = dh / c, dh = 1;
+ *   - a straight crack along the mid-line y = ny/2 - 1/2 whose severed links
+ *     exchange nothing (Sec. 4.1): the population is bounced back
+ *     (traction-free face), as at the plate edges;  a traction t* on a link adds
+ *     (dt / (rho dh)) t* to the bounced population;  the top edge carries
+ *     sigma_yz = +tau_n, the bottom edge -tau_n, the lateral edges are free;
+ *   - the crack step appended after the time integration (Alg. 1): K_III from
+ *     the crack opening at the column i_K = floor(a - r_min), r = a - i_K
+ *     (eq. sif, eq. r(v)); growth at a prescribed speed or while K > K_C
+ *     with v = v_max tanh(sqrt((K/K_C)^4 - 1)) (eq. sifCriterion, eq. v-tanh);
+ *     tip a <- a + (v c_s) dt in FP64; every vertical link of the crack row
+ *     with a_prev < i <= a is severed (CheckLinks / ProcessPoints).
+ *
+ * Conventions: sites (i, j), i = 0..nx-1 along x, j = 0..ny-1 along y; all
+ * host arrays are FP64 row-major [ny][nx] (populations [5][ny][nx]); lengths
+ * are in lattice spacings, times in steps unless stated.
+ *
+ * Memory and streams: the caller owns the device memory (one block of
+ * lbm_state_bytes() bytes, 256-byte aligned) and the HIP stream; the library
+ * keeps borrowed pointers and never allocates or frees device memory.  Host
+ * arrays passed to lbm_init are copied.  All calls on one handle must come
+ * from one host thread at a time.
+ *
+ * Errors: every int-returning call returns 0 (LBM_OK) or a negative
+ * lbm_status; lbm_last_error() gives a message for the calling thread.
+ * lbm_step only enqueues work; a failure of enqueued work surfaces at the next
+ * call that synchronises (lbm_crack_state, lbm_sif, lbm_traces, lbm_get_*).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* invalid argument or configuration                  */
+  LBM_ENOMEM = -2,    /* dev_bytes smaller than lbm_state_bytes()           */
+  LBM_EHIP = -3,      /* a HIP runtime call failed                          */
+  LBM_EUNSTABLE = -4, /* omega != 1 or kappa <= sqrt(2): the scheme diverges */
+  LBM_ECRACK = -5,    /* crack outside the plate                            */
+  LBM_ESTATE = -6     /* handle in a state that does not allow the call     */
+};
+
+/* Storage of the populations.  LBM_F64 and LBM_F32_PLAIN store the
+ * post-collision f^alpha themselves; LBM_F32, LBM_F16S and LBM_BF16S store
+ * g^alpha = f^alpha - E^alpha(w), E the static equilibrium f_eq(w, 0) of the
+ * emitting site, with w kept in FP32 and all arithmetic in FP32. */
+enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_F32_PLAIN = 4 };
+enum lbm_growth { LBM_GROW_NONE = 0, LBM_GROW_PRESCRIBED = 1, LBM_GROW_SIF = 2 };
+enum lbm_bc { LBM_BC_WALLS = 0, LBM_BC_PERIODIC = 1 /* both axes wrap; no edge loads */ };
+enum lbm_flags { LBM_FLAG_GREW = 1, LBM_FLAG_WALL = 2, LBM_FLAG_K_UNDEF = 4 };
+
+typedef struct lbm_config {
+  int32_t nx, ny;          /* sites; ny even and >= 2 when there is a crack      */
+  int32_t storage;         /* enum lbm_storage                                   */
+  int32_t bc_mode;         /* enum lbm_bc                                        */
+  double kappa;            /* c / c_s (> sqrt(2)); Sec. 3                        */
+  double omega;            /* dt / tau; the paper's tau = dt gives 1 (required)  */
+  double mu, rho;          /* shear modulus, density (> 0)                       */
+  int32_t has_crack;       /* 0: no crack (no crack step, no traces)             */
+  double crack_x0;         /* left end of the crack line; -0.5 = left edge       */
+  double crack_tip;        /* initial tip a_0, crack_x0 <= a_0 <= nx - 1/2       */
+  int32_t growth;          /* enum lbm_growth                                    */
+  double v_rel;            /* prescribed speed a_dot / c_s in [0, 1)             */
+  double K_C;              /* critical K_III of the criterion (> 0 for SIF)      */
+  double r0;               /* r_min at v = 0 (eq. r(v)), > 0                     */
+  double v_max;            /* maximum speed of the tanh law, in [0, 1)           */
+  int32_t k_band;          /* columns in the K fit, 1..64 (1 = eq. sif)          */
+  double face_traction;    /* tau* on the crack faces (suddenly loaded faces)    */
+  const double *tau_hist;  /* host, n_hist values: step n uses                   */
+  int64_t n_hist;          /* tau_hist[min(n, n_hist - 1)]; 0 = unloaded          */
+  const double *w0;        /* host [ny][nx] initial displacement, NULL = 0       */
+  const double *wdot0;     /* host [ny][nx] initial velocity, NULL = 0           */
+  int64_t trace_cap;       /* per-step K / tip / speed traces kept on device     */
+  void *dev_buf;           /* device memory, >= lbm_state_bytes(cfg), 256-aligned */
+  size_t dev_bytes;
+  void *stream;            /* hipStream_t; NULL = the null stream                */
+} lbm_config;
+
+typedef struct lbm_crack_info {
+  double tip;      /* current tip a_n                                       */
+  double v;        /* speed of the last step (relative to c_s)              */
+  double K;        /* K_III of the last step (NaN if undefined)             */
+  double r;        /* distance used for that K                              */
+  int64_t step;    /* steps completed                                       */
+  int32_t flags;   /* enum lbm_flags of the last step                       */
+  int32_t n_events;/* cut events recorded so far                            */
+  int32_t col_K;   /* column used for that K (-1 if undefined)              */
+  int32_t n_cut;   /* severed links on the crack row                        */
+} lbm_crack_info;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Bytes of device memory lbm_init needs for cfg (0 if cfg is invalid). */
+size_t lbm_state_bytes(const lbm_config *cfg);
+
+/* Validate cfg, lay the state out in cfg->dev_buf and enqueue its
+ * initialisation on cfg->stream: f = f_eq(w0, wdot0), w = w0, the links
+ * severed by the initial crack segment (Alg. 1 "as for the initial crack").
+ * Returns LBM_EINVAL / LBM_EUNSTABLE / LBM_ECRACK / LBM_ENOMEM without
+ * touching the GPU when cfg is unusable. */
+int lbm_init(const lbm_config *cfg, lbm_handle **out);
+
+/* Enqueue nsteps time steps (fused collide-stream sweep, then the crack step
+ * of Alg. 1) on the handle's stream.  Asynchronous. */
+int lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Crack state after the last step (synchronises the stream). */
+int lbm_crack_state(lbm_handle *h, lbm_crack_info *out);
+
+/* K_III trace (eq. sif) of steps [first, first + count) into host K_out;
+ * entries past the steps taken or past trace_cap are LBM_EINVAL. */
+int lbm_sif(lbm_handle *h, double *K_out, int64_t first, int64_t count);
+
+/* Tip position after each step, speed and flags, same indexing as lbm_sif;
+ * any output pointer may be NULL. */
+int lbm_traces(lbm_handle *h, double *tip_out, double *v_out, int32_t *flags_out,
+               int64_t first, int64_t count);
+
+/* Cut events: (step, column) of every link severed by growth, in order;
+ * writes min(cap, total) entries and the total into *n. */
+int lbm_cut_events(lbm_handle *h, int64_t *steps, int32_t *cols, int64_t cap, int64_t *n);
+
+/* Host FP64 snapshot of w and wdot = sum_alpha f^alpha (either may be NULL). */
+int lbm_get_fields(lbm_handle *h, double *w_out, double *wdot_out);
+
+/* Host FP64 snapshot of the post-collision populations f^alpha, [5][ny][nx]
+ * (shifted storage is converted back: f = g + E(w)). */
+int lbm_get_populations(lbm_handle *h, double *f_out);
+
+/* Severed links as bytes: cutV[j][i] is the link (i,j)-(i,j+1), cutH[j][i]
+ * the link (i,j)-(i+1,j) (the wrap-around link (nx-1,j)-(0,j) in periodic
+ * mode), either may be NULL. */
+int lbm_get_mask(lbm_handle *h, uint8_t *cutV, uint8_t *cutH);
+
+/* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
+ * recording (and clears the sums), 0 stops; the sums of the sweep and crack
+ * kernel durations (ms) and the number of timed steps are returned
+ * (synchronises the stream).  Any output pointer may be NULL. */
+int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms,
+               int64_t *n_timed);
+
+/* Launch shape of the sweep: sites per lane along x (vec, fixed by the
+ * storage), rows per wave (rows), waves per workgroup (waves).  lbm_set_launch
+ * accepts rows in 1..4096 and waves in {1, 2, 4, 8}. */
+int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves);
+int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves);
+
+/* Algorithmic bytes moved by one sweep per site (read + write of the five
+ * populations and of w), for the storage of the handle. */
+double lbm_bytes_per_site(const lbm_handle *h);
+
+/* Release the handle (host metadata only; the device block stays the caller's). */
+void lbm_free(lbm_handle *h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,625 @@
+// Host side of the C-ABI declared in include/lbm.h: validation, device
+// layout, launch order and queries.  All arithmetic of a time step runs in
+// the kernels of sweep.hip and crack.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.hpp"
+
+using lbmk::Store;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(LBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t elem = 0, welem = 0;
+  int pitch = 0, mw = 0;
+  size_t plane = 0;             // elements between planes
+  size_t off_f[2] = {0, 0};
+  size_t off_w[2] = {0, 0};
+  size_t off_mV = 0, off_mH = 0, off_rf = 0, off_crack = 0;
+  size_t off_trK = 0, off_trA = 0, off_trV = 0, off_trF = 0;
+  size_t off_evS = 0, off_evC = 0, off_stage = 0;
+  int64_t event_cap = 0;
+  int stage_rows = 0;
+  size_t total = 0;
+};
+
+bool store_of(int32_t s, Store *out) {
+  switch (s) {
+    case LBM_F64: *out = Store::F64; return true;
+    case LBM_F32: *out = Store::F32S; return true;
+    case LBM_F16S: *out = Store::F16S; return true;
+    case LBM_BF16S: *out = Store::BF16S; return true;
+    case LBM_F32_PLAIN: *out = Store::F32_PLAIN; return true;
+    default: return false;
+  }
+}
+
+bool shifted(Store s) { return s == Store::F32S || s == Store::F16S || s == Store::BF16S; }
+
+size_t elem_size(Store s) {
+  switch (s) {
+    case Store::F64: return 8;
+    case Store::F32_PLAIN: case Store::F32S: return 4;
+    case Store::F16S: case Store::BF16S: return 2;
+  }
+  return 0;
+}
+
+Layout make_layout(const lbm_config &c, Store s) {
+  Layout L;
+  L.elem = elem_size(s);
+  L.welem = (s == Store::F64) ? 8 : 4;
+  L.pitch = (int)align_up((size_t)c.nx, 64);
+  L.mw = (int)align_up(((size_t)c.nx + 31) / 32, 2);
+  // planes 256-byte aligned with a 1 KiB skew between consecutive planes
+  const size_t plane_bytes = align_up((size_t)L.pitch * c.ny * L.elem, 256) + 1024;
+  L.plane = plane_bytes / L.elem;
+  size_t o = 0;
+  for (int b = 0; b < 2; ++b) {
+    L.off_f[b] = o;
+    o += 5 * plane_bytes;
+  }
+  const size_t wbytes = align_up((size_t)L.pitch * c.ny * L.welem, 256) + 1024;
+  L.off_w[0] = o;
+  o += wbytes;
+  if (shifted(s)) {
+    L.off_w[1] = o;
+    o += wbytes;
+  } else {
+    L.off_w[1] = L.off_w[0];
+  }
+  const size_t mbytes = align_up((size_t)c.ny * L.mw * 4, 256);
+  L.off_mV = o; o += mbytes;
+  L.off_mH = o; o += mbytes;
+  L.off_rf = o; o += align_up((size_t)c.ny * 4, 256);
+  L.off_crack = o; o += 256;
+  const size_t tc = c.trace_cap > 0 ? (size_t)c.trace_cap : 1;
+  L.off_trK = o; o += align_up(tc * 8, 256);
+  L.off_trA = o; o += align_up(tc * 8, 256);
+  L.off_trV = o; o += align_up(tc * 8, 256);
+  L.off_trF = o; o += align_up(tc * 4, 256);
+  L.event_cap = (int64_t)c.nx + 8;
+  L.off_evS = o; o += align_up((size_t)L.event_cap * 8, 256);
+  L.off_evC = o; o += align_up((size_t)L.event_cap * 4, 256);
+  L.stage_rows = (int)std::max<int64_t>(1, std::min<int64_t>(c.ny, (1 << 20) / std::max(1, c.nx)));
+  L.off_stage = o;
+  o += align_up((size_t)5 * L.stage_rows * c.nx * 8, 256);
+  L.total = o;
+  return L;
+}
+
+int validate(const lbm_config *c, Store *s) {
+  if (!c) return fail(LBM_EINVAL, "null config");
+  if (!store_of(c->storage, s)) return fail(LBM_EINVAL, "unknown storage %d", c->storage);
+  if (c->nx < 1 || c->ny < 1 || c->nx > (1 << 24) || c->ny > (1 << 24))
+    return fail(LBM_EINVAL, "plate size %d x %d out of range", c->nx, c->ny);
+  if ((double)c->nx * c->ny > 4.0e9) return fail(LBM_EINVAL, "plate too large");
+  if (c->bc_mode != LBM_BC_WALLS && c->bc_mode != LBM_BC_PERIODIC)
+    return fail(LBM_EINVAL, "unknown bc_mode %d", c->bc_mode);
+  if (!(c->mu > 0) || !(c->rho > 0) || !std::isfinite(c->mu) || !std::isfinite(c->rho))
+    return fail(LBM_EINVAL, "mu and rho must be positive");
+  if (!(c->kappa > 0) || !std::isfinite(c->kappa)) return fail(LBM_EINVAL, "kappa must be positive");
+  if (c->omega != 1.0)
+    return fail(LBM_EUNSTABLE, "omega = %g: with w integrated into f_eq the scheme is stable only at tau = dt", c->omega);
+  if (c->kappa * c->kappa <= 2.0)
+    return fail(LBM_EUNSTABLE, "kappa = %g: the scheme needs kappa > sqrt(2)", c->kappa);
+  if (c->has_crack) {
+    if (c->ny < 2 || c->ny % 2) return fail(LBM_EINVAL, "a crack needs an even ny >= 2");
+    if (!(c->crack_x0 >= -0.5) || !(c->crack_tip >= c->crack_x0) || !(c->crack_tip <= c->nx - 0.5))
+      return fail(LBM_ECRACK, "crack [%g, %g] not inside [-0.5, %g]", c->crack_x0, c->crack_tip, c->nx - 0.5);
+    if (!(c->r0 > 0)) return fail(LBM_EINVAL, "r0 must be positive");
+    if (c->k_band < 1 || c->k_band > 64) return fail(LBM_EINVAL, "k_band must be in 1..64");
+  }
+  if (c->growth != LBM_GROW_NONE && c->growth != LBM_GROW_PRESCRIBED && c->growth != LBM_GROW_SIF)
+    return fail(LBM_EINVAL, "unknown growth %d", c->growth);
+  if (c->growth != LBM_GROW_NONE && (!c->has_crack || c->bc_mode == LBM_BC_PERIODIC))
+    return fail(LBM_EINVAL, "growth needs a crack and walls");
+  if (c->growth == LBM_GROW_PRESCRIBED && !(c->v_rel >= 0 && c->v_rel < 1))
+    return fail(LBM_EINVAL, "prescribed speed must be in [0, 1)");
+  if (c->growth == LBM_GROW_SIF && !(c->K_C > 0 && c->v_max >= 0 && c->v_max < 1))
+    return fail(LBM_EINVAL, "K criterion needs K_C > 0 and v_max in [0, 1)");
+  if (c->n_hist < 0 || (c->n_hist > 0 && !c->tau_hist)) return fail(LBM_EINVAL, "bad traction history");
+  if (c->trace_cap < 0) return fail(LBM_EINVAL, "negative trace_cap");
+  return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_handle {
+  lbm_config cfg{};
+  Store store = Store::F64;
+  Layout L;
+  lbmk::Plate plate{};
+  hipStream_t stream = nullptr;
+  std::vector<double> tau;
+  double cs = 0, c = 0, dt = 0, lambda = 0, A0 = 0, Ak = 0, coef = 0;
+  char *base = nullptr;
+  int cur = 0;        // f buffer holding the current state
+  int wcur = 0;       // w buffer holding the current w (shifted storage)
+  int64_t step = 0;
+  int rows = 16, waves = 4;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<hipEvent_t> ev_used;  // triples: before sweep, after sweep, after crack
+  double t_sweep = 0, t_crack = 0;
+  int64_t n_timed = 0;
+  lbmk::DevCrack host_crack{};
+
+  void *fbuf(int b) const { return base + L.off_f[b]; }
+  void *wbuf(int b) const { return base + L.off_w[b]; }
+  uint32_t *mV() const { return reinterpret_cast<uint32_t *>(base + L.off_mV); }
+  uint32_t *mH() const { return reinterpret_cast<uint32_t *>(base + L.off_mH); }
+  uint32_t *rowflags() const { return reinterpret_cast<uint32_t *>(base + L.off_rf); }
+  lbmk::DevCrack *crack() const { return reinterpret_cast<lbmk::DevCrack *>(base + L.off_crack); }
+  double *stage() const { return reinterpret_cast<double *>(base + L.off_stage); }
+  double tau_at(int64_t n) const {
+    if (tau.empty()) return 0.0;
+    return tau[(size_t)std::min<int64_t>(n, (int64_t)tau.size() - 1)];
+  }
+};
+
+namespace {
+
+hipEvent_t take_event(lbm_handle *h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int harvest_timing(lbm_handle *h) {
+  if (h->ev_used.empty()) return LBM_OK;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (size_t k = 0; k + 2 < h->ev_used.size(); k += 3) {
+    float a = 0, b = 0;
+    HIP_TRY(hipEventElapsedTime(&a, h->ev_used[k], h->ev_used[k + 1]));
+    HIP_TRY(hipEventElapsedTime(&b, h->ev_used[k + 1], h->ev_used[k + 2]));
+    h->t_sweep += a;
+    h->t_crack += b;
+    h->n_timed += 1;
+  }
+  for (hipEvent_t e : h->ev_used) h->ev_pool.push_back(e);
+  h->ev_used.clear();
+  return LBM_OK;
+}
+
+template <typename S, typename W, typename C>
+int launch_sweep_typed(lbm_handle *h) {
+  lbmk::SweepArgs<S, W, C> a{};
+  const int nxt = 1 - h->cur;
+  a.fin = static_cast<const S *>(h->fbuf(h->cur));
+  a.fout = static_cast<S *>(h->fbuf(nxt));
+  if (shifted(h->store)) {
+    a.win = static_cast<const W *>(h->wbuf(h->wcur));
+    a.wout = static_cast<W *>(h->wbuf(1 - h->wcur));
+  } else {
+    a.win = static_cast<const W *>(h->wbuf(0));
+    a.wout = static_cast<W *>(h->wbuf(0));
+  }
+  a.mV = h->mV();
+  a.mH = h->mH();
+  a.rowflags = h->rowflags();
+  a.p = h->plate;
+  a.omega = (C)h->cfg.omega;
+  a.dt = (C)h->dt;
+  a.A0 = (C)h->A0;
+  a.Ak = (C)h->Ak;
+  const double tau = h->tau_at(h->step);
+  const bool per = h->cfg.bc_mode == LBM_BC_PERIODIC;
+  a.t_top = per ? C(0) : (C)(h->coef * tau);
+  a.t_bot = per ? C(0) : (C)(h->coef * -tau);
+  a.t_up = per ? C(0) : (C)(h->coef * h->cfg.face_traction);
+  a.t_lo = per ? C(0) : (C)(h->coef * -h->cfg.face_traction);
+  a.rows = h->rows;
+  a.waves = h->waves;
+  HIP_TRY(lbmk::launch_sweep(h->store, &a, h->stream));
+  return LBM_OK;
+}
+
+int launch_sweep_any(lbm_handle *h) {
+  switch (h->store) {
+    case Store::F64: return launch_sweep_typed<double, double, double>(h);
+    case Store::F32_PLAIN: return launch_sweep_typed<float, float, float>(h);
+    case Store::F32S: return launch_sweep_typed<float, float, float>(h);
+    case Store::F16S: return launch_sweep_typed<_Float16, float, float>(h);
+    case Store::BF16S: return launch_sweep_typed<__bf16, float, float>(h);
+  }
+  return fail(LBM_EINVAL, "bad storage");
+}
+
+int launch_crack_step(lbm_handle *h) {
+  lbmk::CrackArgs a{};
+  a.st = h->crack();
+  const bool sh = shifted(h->store);
+  a.w = sh ? h->wbuf(1 - h->wcur) : h->wbuf(0);  // w after the sweep just enqueued
+  a.w_is_double = h->store == Store::F64;
+  a.mV = h->mV();
+  a.rowflags = h->rowflags();
+  a.trK = reinterpret_cast<double *>(h->base + h->L.off_trK);
+  a.trA = reinterpret_cast<double *>(h->base + h->L.off_trA);
+  a.trV = reinterpret_cast<double *>(h->base + h->L.off_trV);
+  a.trF = reinterpret_cast<int32_t *>(h->base + h->L.off_trF);
+  a.evStep = reinterpret_cast<int64_t *>(h->base + h->L.off_evS);
+  a.evCol = reinterpret_cast<int32_t *>(h->base + h->L.off_evC);
+  a.p = h->plate;
+  a.c.growth = h->cfg.growth;
+  a.c.band = h->cfg.k_band;
+  a.c.v_rel = h->cfg.v_rel;
+  a.c.K_C = h->cfg.K_C;
+  a.c.r0 = h->cfg.r0;
+  a.c.v_max = h->cfg.v_max;
+  a.c.cs = h->cs;
+  a.c.dt = h->dt;
+  a.c.mu = h->cfg.mu;
+  a.c.x0 = h->cfg.crack_x0;
+  a.c.trace_cap = h->cfg.trace_cap;
+  a.c.event_cap = h->L.event_cap;
+  HIP_TRY(lbmk::launch_crack(a, h->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+size_t lbm_state_bytes(const lbm_config *cfg) {
+  Store s;
+  if (validate(cfg, &s) != LBM_OK) return 0;
+  return make_layout(*cfg, s).total;
+}
+
+int lbm_init(const lbm_config *cfg, lbm_handle **out) {
+  if (!out) return fail(LBM_EINVAL, "null output handle");
+  *out = nullptr;
+  Store s;
+  int rc = validate(cfg, &s);
+  if (rc != LBM_OK) return rc;
+  Layout L = make_layout(*cfg, s);
+  if (!cfg->dev_buf) return fail(LBM_EINVAL, "null dev_buf");
+  if (reinterpret_cast<uintptr_t>(cfg->dev_buf) % 256)
+    return fail(LBM_EINVAL, "dev_buf must be 256-byte aligned");
+  if (cfg->dev_bytes < L.total)
+    return fail(LBM_ENOMEM, "dev_bytes %zu < required %zu", cfg->dev_bytes, L.total);
+
+  lbm_handle *h = new lbm_handle();
+  h->cfg = *cfg;
+  h->store = s;
+  h->L = L;
+  h->stream = static_cast<hipStream_t>(cfg->stream);
+  if (cfg->n_hist > 0) h->tau.assign(cfg->tau_hist, cfg->tau_hist + cfg->n_hist);
+  h->cfg.tau_hist = nullptr;
+  h->cfg.w0 = nullptr;
+  h->cfg.wdot0 = nullptr;
+  h->base = static_cast<char *>(cfg->dev_buf);
+  // lattice constants (Sec. 3): c = kappa c_s, dt = dh / c with dh = 1,
+  // lambda = c_s^2 / (dt (1/omega - 1/2)), f_eq^0 = wdot - A0 w, f_eq^k = Ak w,
+  // traction coefficient dt / (rho dh)
+  h->cs = std::sqrt(cfg->mu / cfg->rho);
+  h->c = cfg->kappa * h->cs;
+  h->dt = 1.0 / h->c;
+  h->lambda = h->cs * h->cs / (h->dt * (1.0 / cfg->omega - 0.5));
+  h->A0 = 2.0 * h->lambda / (h->c * h->c);
+  h->Ak = h->lambda / (2.0 * h->c * h->c);
+  h->coef = h->dt / (cfg->rho * 1.0);
+  lbmk::Plate &p = h->plate;
+  p.nx = cfg->nx;
+  p.ny = cfg->ny;
+  p.pitch = L.pitch;
+  p.mw = L.mw;
+  p.j0 = cfg->ny / 2 - 1;
+  p.periodic = cfg->bc_mode == LBM_BC_PERIODIC;
+  p.plane = L.plane;
+  // default launch shape: enough waves to fill 256 CUs, long marches when the plate allows
+  {
+    const int vec = lbmk::sweep_vec(s);
+    const long strips = (cfg->nx + 64L * vec - 1) / (64L * vec);
+    int rows = 64;
+    while (rows > 1 && strips * ((cfg->ny + rows - 1) / rows) < 8192) rows /= 2;
+    h->rows = rows;
+    h->waves = 4;
+  }
+
+  auto bail = [&](int code) {
+    delete h;
+    return code;
+  };
+  hipStream_t st = h->stream;
+  if (lbmk::launch_zero(h->base, L.total, st) != hipSuccess)
+    return bail(fail(LBM_EHIP, "zero fill failed: %s", hipGetErrorString(hipGetLastError())));
+  // initial fields, staged through device memory in row chunks
+  double *stage = h->stage();
+  const size_t rowlen = (size_t)cfg->nx;
+  for (int r0 = 0; r0 < cfg->ny; r0 += L.stage_rows) {
+    const int nr = std::min(L.stage_rows, cfg->ny - r0);
+    double *dw = nullptr, *dwd = nullptr;
+    if (cfg->w0) {
+      dw = stage;
+      if (hipMemcpyAsync(dw, cfg->w0 + (size_t)r0 * rowlen, nr * rowlen * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+        return bail(fail(LBM_EHIP, "upload of w0 failed"));
+    }
+    if (cfg->wdot0) {
+      dwd = stage + (size_t)L.stage_rows * rowlen;
+      if (hipMemcpyAsync(dwd, cfg->wdot0 + (size_t)r0 * rowlen, nr * rowlen * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+        return bail(fail(LBM_EHIP, "upload of wdot0 failed"));
+    }
+    if (lbmk::launch_init_rows(s, h->fbuf(0), h->wbuf(0), h->wbuf(1), p, r0, nr, dw, dwd, h->A0, h->Ak, st) != hipSuccess)
+      return bail(fail(LBM_EHIP, "init kernel failed"));
+    if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(LBM_EHIP, "init sync failed"));
+  }
+  if (lbmk::launch_init_mask(h->mV(), h->mH(), h->rowflags(), p, cfg->has_crack, cfg->crack_x0,
+                             cfg->crack_tip, st) != hipSuccess)
+    return bail(fail(LBM_EHIP, "mask init failed"));
+  lbmk::DevCrack &c0 = h->host_crack;
+  c0 = lbmk::DevCrack{};
+  c0.tip = cfg->has_crack ? cfg->crack_tip : 0.0;
+  c0.v = 0.0;
+  c0.K = std::nan("");
+  c0.r = std::nan("");
+  c0.step = 0;
+  c0.flags = 0;
+  c0.n_events = 0;
+  c0.col_K = -1;
+  if (cfg->has_crack) {
+    const int lo = std::max(0, (int)std::ceil(cfg->crack_x0));
+    const int hi = std::min(cfg->nx - 1, (int)std::floor(cfg->crack_tip));
+    c0.n_cut = hi >= lo ? hi - lo + 1 : 0;
+  }
+  if (hipMemcpyAsync(h->crack(), &c0, sizeof c0, hipMemcpyHostToDevice, st) != hipSuccess)
+    return bail(fail(LBM_EHIP, "crack state upload failed"));
+  if (hipStreamSynchronize(st) != hipSuccess)
+    return bail(fail(LBM_EHIP, "init failed: %s", hipGetErrorString(hipGetLastError())));
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_handle *h, int64_t nsteps) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (h->timing) {
+      e0 = take_event(h);
+      e1 = take_event(h);
+      e2 = take_event(h);
+      if (!e0 || !e1 || !e2) return fail(LBM_EHIP, "event creation failed");
+      HIP_TRY(hipEventRecord(e0, h->stream));
+    }
+    int rc = launch_sweep_any(h);
+    if (rc != LBM_OK) return rc;
+    if (h->timing) HIP_TRY(hipEventRecord(e1, h->stream));
+    if (h->cfg.has_crack) {
+      rc = launch_crack_step(h);
+      if (rc != LBM_OK) return rc;
+    }
+    if (h->timing) {
+      HIP_TRY(hipEventRecord(e2, h->stream));
+      h->ev_used.push_back(e0);
+      h->ev_used.push_back(e1);
+      h->ev_used.push_back(e2);
+      if (h->ev_used.size() >= 3 * 4096) {
+        rc = harvest_timing(h);
+        if (rc != LBM_OK) return rc;
+      }
+    }
+    h->cur = 1 - h->cur;
+    if (shifted(h->store)) h->wcur = 1 - h->wcur;
+    h->step++;
+  }
+  return LBM_OK;
+}
+
+int lbm_crack_state(lbm_handle *h, lbm_crack_info *out) {
+  if (!h || !out) return fail(LBM_EINVAL, "null argument");
+  lbmk::DevCrack c{};
+  HIP_TRY(hipMemcpyAsync(&c, h->crack(), sizeof c, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  out->tip = c.tip;
+  out->v = c.v;
+  out->K = c.K;
+  out->r = c.r;
+  out->step = h->cfg.has_crack ? c.step : h->step;
+  out->flags = c.flags;
+  out->n_events = c.n_events;
+  out->col_K = c.col_K;
+  out->n_cut = c.n_cut;
+  return LBM_OK;
+}
+
+static int check_range(lbm_handle *h, int64_t first, int64_t count) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (!h->cfg.has_crack) return fail(LBM_ESTATE, "no crack: no traces");
+  if (first < 0 || count < 0 || first + count > std::min<int64_t>(h->step, h->cfg.trace_cap))
+    return fail(LBM_EINVAL, "trace range [%lld, %lld) outside the %lld recorded steps",
+                (long long)first, (long long)(first + count),
+                (long long)std::min<int64_t>(h->step, h->cfg.trace_cap));
+  return LBM_OK;
+}
+
+int lbm_sif(lbm_handle *h, double *K_out, int64_t first, int64_t count) {
+  int rc = check_range(h, first, count);
+  if (rc != LBM_OK) return rc;
+  if (count == 0) return LBM_OK;
+  if (!K_out) return fail(LBM_EINVAL, "null output");
+  HIP_TRY(hipMemcpyAsync(K_out, h->base + h->L.off_trK + first * 8, count * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_traces(lbm_handle *h, double *tip_out, double *v_out, int32_t *flags_out, int64_t first,
+               int64_t count) {
+  int rc = check_range(h, first, count);
+  if (rc != LBM_OK) return rc;
+  if (count == 0) return LBM_OK;
+  if (tip_out)
+    HIP_TRY(hipMemcpyAsync(tip_out, h->base + h->L.off_trA + first * 8, count * 8, hipMemcpyDeviceToHost, h->stream));
+  if (v_out)
+    HIP_TRY(hipMemcpyAsync(v_out, h->base + h->L.off_trV + first * 8, count * 8, hipMemcpyDeviceToHost, h->stream));
+  if (flags_out)
+    HIP_TRY(hipMemcpyAsync(flags_out, h->base + h->L.off_trF + first * 4, count * 4, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_cut_events(lbm_handle *h, int64_t *steps, int32_t *cols, int64_t cap, int64_t *n) {
+  if (!h || !n) return fail(LBM_EINVAL, "null argument");
+  lbmk::DevCrack c{};
+  HIP_TRY(hipMemcpyAsync(&c, h->crack(), sizeof c, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const int64_t total = c.n_events;
+  const int64_t m = std::min<int64_t>(std::min<int64_t>(total, cap), h->L.event_cap);
+  if (m > 0 && steps)
+    HIP_TRY(hipMemcpyAsync(steps, h->base + h->L.off_evS, m * 8, hipMemcpyDeviceToHost, h->stream));
+  if (m > 0 && cols)
+    HIP_TRY(hipMemcpyAsync(cols, h->base + h->L.off_evC, m * 4, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  *n = total;
+  return LBM_OK;
+}
+
+static int export_rows(lbm_handle *h, double *w_out, double *wd_out, double *f_out) {
+  const lbmk::Plate &p = h->plate;
+  const int sr = h->L.stage_rows;
+  double *stage = h->stage();
+  const size_t chunk = (size_t)sr * p.nx;
+  const void *f = h->fbuf(h->cur);
+  const void *w = shifted(h->store) ? h->wbuf(h->wcur) : h->wbuf(0);
+  const size_t n = (size_t)p.nx * p.ny;
+  for (int r0 = 0; r0 < p.ny; r0 += sr) {
+    const int nr = std::min(sr, p.ny - r0);
+    const size_t cnt = (size_t)nr * p.nx;
+    double *dw = w_out ? stage : nullptr;
+    double *dwd = wd_out ? stage + chunk : nullptr;
+    double *df = f_out ? stage : nullptr;  // f export uses the whole stage (5 chunks)
+    if (f_out) {
+      dw = nullptr;
+      dwd = nullptr;
+    }
+    HIP_TRY(lbmk::launch_export_rows(h->store, f, w, p, r0, nr, h->A0, h->Ak, dw, dwd, df, h->stream));
+    if (w_out) HIP_TRY(hipMemcpyAsync(w_out + (size_t)r0 * p.nx, dw, cnt * 8, hipMemcpyDeviceToHost, h->stream));
+    if (wd_out) HIP_TRY(hipMemcpyAsync(wd_out + (size_t)r0 * p.nx, dwd, cnt * 8, hipMemcpyDeviceToHost, h->stream));
+    if (f_out)
+      for (int a = 0; a < 5; ++a)
+        HIP_TRY(hipMemcpyAsync(f_out + a * n + (size_t)r0 * p.nx, df + a * cnt, cnt * 8,
+                               hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_get_fields(lbm_handle *h, double *w_out, double *wdot_out) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (!w_out && !wdot_out) return LBM_OK;
+  return export_rows(h, w_out, wdot_out, nullptr);
+}
+
+int lbm_get_populations(lbm_handle *h, double *f_out) {
+  if (!h || !f_out) return fail(LBM_EINVAL, "null argument");
+  return export_rows(h, nullptr, nullptr, f_out);
+}
+
+int lbm_get_mask(lbm_handle *h, uint8_t *cutV, uint8_t *cutH) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  const lbmk::Plate &p = h->plate;
+  const size_t n = (size_t)p.nx * p.ny;
+  // bytes staged through the FP64 stage area in row chunks
+  const size_t cap = (size_t)h->L.stage_rows * p.nx * 8 * 5;
+  const int rows = (int)std::max<size_t>(1, std::min<size_t>(p.ny, cap / (2 * (size_t)p.nx)));
+  uint8_t *sv = reinterpret_cast<uint8_t *>(h->stage());
+  for (int r0 = 0; r0 < p.ny; r0 += rows) {
+    const int nr = std::min(rows, p.ny - r0);
+    lbmk::Plate q = p;
+    q.ny = nr;
+    const size_t cnt = (size_t)nr * p.nx;
+    HIP_TRY(lbmk::launch_export_mask(h->mV() + (size_t)r0 * p.mw, h->mH() + (size_t)r0 * p.mw, q,
+                                     cutV ? sv : nullptr, cutH ? sv + cnt : nullptr, h->stream));
+    if (cutV) HIP_TRY(hipMemcpyAsync(cutV + (size_t)r0 * p.nx, sv, cnt, hipMemcpyDeviceToHost, h->stream));
+    if (cutH) HIP_TRY(hipMemcpyAsync(cutH + (size_t)r0 * p.nx, sv + cnt, cnt, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  (void)n;
+  return LBM_OK;
+}
+
+int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms, int64_t *n_timed) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  int rc = harvest_timing(h);
+  if (rc != LBM_OK) return rc;
+  if (sweep_ms) *sweep_ms = h->t_sweep;
+  if (crack_ms) *crack_ms = h->t_crack;
+  if (n_timed) *n_timed = h->n_timed;
+  if (enable && !h->timing) {
+    h->t_sweep = h->t_crack = 0;
+    h->n_timed = 0;
+  }
+  h->timing = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (vec) *vec = lbmk::sweep_vec(h->store);
+  if (rows) *rows = h->rows;
+  if (waves) *waves = h->waves;
+  return LBM_OK;
+}
+
+int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (rows < 1 || rows > 4096) return fail(LBM_EINVAL, "rows must be in 1..4096");
+  if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(LBM_EINVAL, "waves must be 1, 2, 4 or 8");
+  h->rows = rows;
+  h->waves = waves;
+  return LBM_OK;
+}
+
+double lbm_bytes_per_site(const lbm_handle *h) {
+  if (!h) return 0.0;
+  const double e = (double)elem_size(h->store), we = (h->store == Store::F64) ? 8.0 : 4.0;
+  return 2.0 * (5.0 * e + we);
+}
+
+void lbm_free(lbm_handle *h) {
+  if (!h) return;
+  if (!h->ev_used.empty()) hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev_used) hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+  delete h;
+}
+
+}  // extern "C"

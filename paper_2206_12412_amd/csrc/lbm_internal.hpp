@@ -1,0 +1,102 @@
+// Internal declarations of liblbmcrack: device-side layout, kernel argument
+// blocks and the launch functions of the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbmk {
+
+// Crack state kept on the device and updated by the one-wavefront crack
+// kernel after each sweep (Alg. 1, CrackGrowth).
+struct DevCrack {
+  double tip;        // a_n
+  double v;          // speed of the last step / c_s
+  double K;          // K_III of the last step
+  double r;          // distance used for K
+  int64_t step;      // steps completed
+  int32_t flags;     // LBM_FLAG_* of the last step (WALL is sticky)
+  int32_t n_events;  // cut events recorded
+  int32_t col_K;     // column of the last K (-1: undefined)
+  int32_t n_cut;     // severed links on the crack row
+};
+
+// Static description of one plate's lattice as the kernels see it.
+struct Plate {
+  int nx, ny;        // sites
+  int pitch;         // elements per row (multiple of 64)
+  int mw;            // mask words per row (multiple of 2)
+  int j0;            // crack row (the crack line is y = j0 + 1/2)
+  int periodic;      // both axes wrap
+  size_t plane;      // elements between population planes
+};
+
+// Parameters of the crack step.
+struct CrackParams {
+  int growth;        // LBM_GROW_*
+  int band;          // columns in the K fit
+  double v_rel, K_C, r0, v_max;
+  double cs, dt, mu;
+  double x0;         // left end of the crack line
+  int64_t trace_cap;
+  int64_t event_cap;
+};
+
+// Per-launch arguments of the sweep.  S is the storage type of the
+// populations, W the storage type of w, C the compute type.
+template <typename S, typename W, typename C>
+struct SweepArgs {
+  const S *fin;      // plane 0 of the source populations
+  S *fout;           // plane 0 of the destination populations
+  const W *win;      // w before the step
+  W *wout;           // w after the step (== win for in-place storage)
+  const uint32_t *mV, *mH, *rowflags;
+  Plate p;
+  C omega, dt, A0, Ak;
+  C t_top, t_bot;    // coef * traction on top / bottom edge links
+  C t_up, t_lo;      // coef * traction on the crack face above / below
+  int rows;          // rows marched by one wave
+  int waves;         // waves per workgroup
+};
+
+struct CrackArgs {
+  DevCrack *st;
+  const void *w;     // w after the sweep (double or float, see w_is_double)
+  int w_is_double;
+  uint32_t *mV, *rowflags;
+  double *trK, *trA, *trV;
+  int32_t *trF;
+  int64_t *evStep;
+  int32_t *evCol;
+  Plate p;
+  CrackParams c;
+};
+
+// ---- launchers (sweep.hip) ----
+enum class Store { F64, F32_PLAIN, F32S, F16S, BF16S };
+
+int sweep_vec(Store s);  // sites per lane
+hipError_t launch_sweep(Store s, const void *args, hipStream_t st);
+
+// ---- launchers (crack.hip) ----
+hipError_t launch_crack(const CrackArgs &a, hipStream_t st);
+hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, uint32_t *rowflags, const Plate &p,
+                            int has_crack, double x0, double a0, hipStream_t st);
+
+// ---- launchers (io.hip) ----
+// Initial populations and w of rows [row0, row0 + nrows) from FP64 staging
+// (w0, wd0 may be null = 0).
+hipError_t launch_init_rows(Store s, void *f, void *w, void *w2, const Plate &p, int row0,
+                            int nrows, const double *w0, const double *wd0, double A0, double Ak,
+                            hipStream_t st);
+// FP64 export of rows [row0, row0 + nrows): w, wdot, or the five populations.
+hipError_t launch_export_rows(Store s, const void *f, const void *w, const Plate &p, int row0,
+                              int nrows, double A0, double Ak, double *w_out, double *wd_out,
+                              double *f_out, hipStream_t st);
+hipError_t launch_export_mask(const uint32_t *mV, const uint32_t *mH, const Plate &p,
+                              uint8_t *v_out, uint8_t *h_out, hipStream_t st);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
+}  // namespace lbmk

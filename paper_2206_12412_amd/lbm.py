@@ -1,0 +1,282 @@
+"""ctypes binding of liblbmcrack (include/lbm.h): argument marshalling only.
+
+PyTorch provides the device memory block (one uint8 tensor of
+``lbm_state_bytes`` bytes) and the HIP stream (torch's current stream on the
+device); every step of the method runs in the library's HIP kernels.  There is
+no fallback: without the built library on a GPU device the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmcrack.so")
+
+LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F32_PLAIN = 0, 1, 2, 3, 4
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S,
+           "f32plain": LBM_F32_PLAIN}
+GROW_NONE, GROW_PRESCRIBED, GROW_SIF = 0, 1, 2
+BC_WALLS, BC_PERIODIC = 0, 1
+FLAG_GREW, FLAG_WALL, FLAG_K_UNDEF = 1, 2, 4
+
+ERRORS = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE",
+          -5: "LBM_ECRACK", -6: "LBM_ESTATE"}
+
+# every symbol include/lbm.h declares
+EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
+           "lbm_cut_events", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
+           "lbm_timing", "lbm_get_launch", "lbm_set_launch", "lbm_bytes_per_site", "lbm_free",
+           "lbm_last_error")
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Config(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("storage", C.c_int32), ("bc_mode", C.c_int32),
+        ("kappa", C.c_double), ("omega", C.c_double), ("mu", C.c_double), ("rho", C.c_double),
+        ("has_crack", C.c_int32), ("crack_x0", C.c_double), ("crack_tip", C.c_double),
+        ("growth", C.c_int32), ("v_rel", C.c_double), ("K_C", C.c_double), ("r0", C.c_double),
+        ("v_max", C.c_double), ("k_band", C.c_int32), ("face_traction", C.c_double),
+        ("tau_hist", C.POINTER(C.c_double)), ("n_hist", C.c_int64),
+        ("w0", C.POINTER(C.c_double)), ("wdot0", C.POINTER(C.c_double)),
+        ("trace_cap", C.c_int64), ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t),
+        ("stream", C.c_void_p),
+    ]
+
+
+class CrackInfo(C.Structure):
+    _fields_ = [("tip", C.c_double), ("v", C.c_double), ("K", C.c_double), ("r", C.c_double),
+                ("step", C.c_int64), ("flags", C.c_int32), ("n_events", C.c_int32),
+                ("col_K", C.c_int32), ("n_cut", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblbmcrack.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run paper_2206_12412_amd/build.py (or "
+                           "__graft_entry__.build()) first; there is no CPU fallback")
+    lib = C.CDLL(path)
+    P, d, i32, i64, vp = C.POINTER, C.c_double, C.c_int32, C.c_int64, C.c_void_p
+    lib.lbm_state_bytes.argtypes = [P(_Config)]
+    lib.lbm_state_bytes.restype = C.c_size_t
+    lib.lbm_init.argtypes = [P(_Config), P(vp)]
+    lib.lbm_step.argtypes = [vp, i64]
+    lib.lbm_crack_state.argtypes = [vp, P(CrackInfo)]
+    lib.lbm_sif.argtypes = [vp, P(d), i64, i64]
+    lib.lbm_traces.argtypes = [vp, P(d), P(d), P(i32), i64, i64]
+    lib.lbm_cut_events.argtypes = [vp, P(i64), P(i32), i64, P(i64)]
+    lib.lbm_get_fields.argtypes = [vp, P(d), P(d)]
+    lib.lbm_get_populations.argtypes = [vp, P(d)]
+    lib.lbm_get_mask.argtypes = [vp, P(C.c_uint8), P(C.c_uint8)]
+    lib.lbm_timing.argtypes = [vp, i32, P(d), P(d), P(i64)]
+    lib.lbm_get_launch.argtypes = [vp, P(i32), P(i32), P(i32)]
+    lib.lbm_set_launch.argtypes = [vp, i32, i32]
+    lib.lbm_bytes_per_site.argtypes = [vp]
+    lib.lbm_bytes_per_site.restype = d
+    lib.lbm_free.argtypes = [vp]
+    lib.lbm_free.restype = None
+    lib.lbm_last_error.restype = C.c_char_p
+    for name in ("lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
+                 "lbm_cut_events", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
+                 "lbm_timing", "lbm_get_launch", "lbm_set_launch"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LBMError(rc, load_library().lbm_last_error().decode())
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+@dataclass
+class Config:
+    """Mirror of lbm_config without the device block and stream."""
+    nx: int
+    ny: int
+    storage: str = "f32"
+    periodic: bool = False
+    kappa: float = 2.0
+    omega: float = 1.0
+    mu: float = 1.0
+    rho: float = 1.0
+    has_crack: bool = False
+    crack_x0: float = -0.5
+    crack_tip: float = -0.5
+    growth: int = GROW_NONE
+    v_rel: float = 0.0
+    K_C: float = 0.0
+    r0: float = 2.0
+    v_max: float = 0.85
+    k_band: int = 1
+    face_traction: float = 0.0
+    tau_hist: Optional[np.ndarray] = None
+    w0: Optional[np.ndarray] = None
+    wdot0: Optional[np.ndarray] = None
+    trace_cap: int = 0
+
+    def to_c(self, keep: list) -> _Config:
+        c = _Config()
+        for name in ("nx", "ny", "kappa", "omega", "mu", "rho", "crack_x0", "crack_tip", "growth",
+                     "v_rel", "K_C", "r0", "v_max", "k_band", "face_traction", "trace_cap"):
+            setattr(c, name, getattr(self, name))
+        c.storage = STORAGE[self.storage] if isinstance(self.storage, str) else int(self.storage)
+        c.bc_mode = BC_PERIODIC if self.periodic else BC_WALLS
+        c.has_crack = int(self.has_crack)
+        if self.tau_hist is not None:
+            t = np.ascontiguousarray(self.tau_hist, dtype=np.float64).ravel()
+            keep.append(t)
+            c.tau_hist = _dp(t)
+            c.n_hist = t.size
+        for name in ("w0", "wdot0"):
+            a = getattr(self, name)
+            if a is not None:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                if a.shape != (self.ny, self.nx):
+                    raise ValueError(f"{name} must have shape (ny, nx)")
+                keep.append(a)
+                setattr(c, name, _dp(a))
+        return c
+
+
+def state_bytes(cfg: Config) -> int:
+    keep = []
+    return int(load_library().lbm_state_bytes(C.byref(cfg.to_c(keep))))
+
+
+class Solver:
+    """One plate on one GPU, driven through the C-ABI."""
+
+    def __init__(self, cfg: Config, device: str = "cuda", stream=None):
+        import torch
+
+        lib = load_library()
+        self.cfg = cfg
+        keep: list = []
+        c = cfg.to_c(keep)
+        nbytes = lib.lbm_state_bytes(C.byref(c))
+        if nbytes == 0:
+            _check(-1)
+        dev = torch.device(device)
+        if dev.type != "cuda":
+            raise RuntimeError("the solver runs on a GPU device only")
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ptr = self._buf.data_ptr()
+        ptr += (-ptr) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        c.dev_buf = ptr
+        c.dev_bytes = nbytes
+        c.stream = self.stream.cuda_stream
+        h = C.c_void_p()
+        _check(lib.lbm_init(C.byref(c), C.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.steps_done = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbm_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def shape(self):
+        return (self.cfg.ny, self.cfg.nx)
+
+    def step(self, n: int = 1):
+        _check(self._lib.lbm_step(self._h, int(n)))
+        self.steps_done += int(n)
+
+    def crack_state(self) -> dict:
+        info = CrackInfo()
+        _check(self._lib.lbm_crack_state(self._h, C.byref(info)))
+        return info.as_dict()
+
+    def sif(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = min(self.steps_done, self.cfg.trace_cap) - first
+        out = np.empty(count)
+        _check(self._lib.lbm_sif(self._h, _dp(out), int(first), int(count)))
+        return out
+
+    def traces(self, first: int = 0, count: Optional[int] = None) -> dict:
+        if count is None:
+            count = min(self.steps_done, self.cfg.trace_cap) - first
+        K, tip, v = np.empty(count), np.empty(count), np.empty(count)
+        fl = np.empty(count, np.int32)
+        if count:
+            _check(self._lib.lbm_sif(self._h, _dp(K), int(first), int(count)))
+            _check(self._lib.lbm_traces(self._h, _dp(tip), _dp(v),
+                                        fl.ctypes.data_as(C.POINTER(C.c_int32)), int(first), int(count)))
+        return {"K": K, "tip": tip, "v": v, "flags": fl}
+
+    def cut_events(self) -> np.ndarray:
+        n = C.c_int64()
+        _check(self._lib.lbm_cut_events(self._h, None, None, 0, C.byref(n)))
+        steps = np.empty(n.value, np.int64)
+        cols = np.empty(n.value, np.int32)
+        if n.value:
+            _check(self._lib.lbm_cut_events(self._h, steps.ctypes.data_as(C.POINTER(C.c_int64)),
+                                            cols.ctypes.data_as(C.POINTER(C.c_int32)), n.value,
+                                            C.byref(n)))
+        return np.stack([steps, cols.astype(np.int64)], axis=1)
+
+    def fields(self):
+        w = np.empty(self.shape)
+        wd = np.empty(self.shape)
+        _check(self._lib.lbm_get_fields(self._h, _dp(w), _dp(wd)))
+        return w, wd
+
+    def populations(self) -> np.ndarray:
+        f = np.empty((5,) + self.shape)
+        _check(self._lib.lbm_get_populations(self._h, _dp(f)))
+        return f
+
+    def mask(self):
+        v = np.empty(self.shape, np.uint8)
+        h = np.empty(self.shape, np.uint8)
+        P = C.POINTER(C.c_uint8)
+        _check(self._lib.lbm_get_mask(self._h, v.ctypes.data_as(P), h.ctypes.data_as(P)))
+        return v, h
+
+    def timing(self, enable: bool):
+        s, k = C.c_double(), C.c_double()
+        n = C.c_int64()
+        _check(self._lib.lbm_timing(self._h, int(enable), C.byref(s), C.byref(k), C.byref(n)))
+        return {"sweep_ms": s.value, "crack_ms": k.value, "steps": n.value}
+
+    def launch(self):
+        v, r, w = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self._lib.lbm_get_launch(self._h, C.byref(v), C.byref(r), C.byref(w)))
+        return {"vec": v.value, "rows": r.value, "waves": w.value}
+
+    def set_launch(self, rows: int, waves: int):
+        _check(self._lib.lbm_set_launch(self._h, int(rows), int(waves)))
+
+    def bytes_per_site(self) -> float:
+        return float(self._lib.lbm_bytes_per_site(self._h))

@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every symbol include/lbm.h declares, and
+rejects unusable configurations before touching a GPU (runs without a GPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2206_12412_amd as P
+from paper_2206_12412_amd import lbm as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(P.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (lbm_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def init_rc(**kw):
+    keep = []
+    cfg = P.Config(**kw).to_c(keep)
+    lib = P.load_library()
+    h = C.c_void_p()
+    return lib.lbm_init(C.byref(cfg), C.byref(h)), lib.lbm_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=16, ny=8, omega=0.9), -4),
+    (dict(nx=16, ny=8, kappa=1.4), -4),
+    (dict(nx=0, ny=8), -1),
+    (dict(nx=16, ny=7, has_crack=True, crack_tip=3.5), -1),
+    (dict(nx=16, ny=8, has_crack=True, crack_tip=16.0), -5),
+    (dict(nx=16, ny=8, has_crack=True, crack_x0=-1.0, crack_tip=3.5), -5),
+    (dict(nx=16, ny=8, growth=1, v_rel=0.2), -1),
+    (dict(nx=16, ny=8, has_crack=True, crack_tip=3.5, growth=1, v_rel=1.0), -1),
+    (dict(nx=16, ny=8, has_crack=True, crack_tip=3.5, growth=2, K_C=0.0), -1),
+    (dict(nx=16, ny=8, has_crack=True, crack_tip=3.5, k_band=0), -1),
+    (dict(nx=16, ny=8, storage=9), -1),
+    (dict(nx=16, ny=8, periodic=True, has_crack=True, crack_tip=3.5, growth=1, v_rel=0.2), -1),
+])
+def test_invalid_configurations_fail_before_any_gpu_call(kw, code):
+    rc, msg = init_rc(**kw)
+    assert rc == code and msg
+
+
+def test_device_block_checks():
+    lib = P.load_library()
+    keep = []
+    cfg = P.Config(nx=16, ny=8).to_c(keep)
+    need = lib.lbm_state_bytes(C.byref(cfg))
+    assert need > 0
+    h = C.c_void_p()
+    assert lib.lbm_init(C.byref(cfg), C.byref(h)) == -1  # null dev_buf
+    cfg.dev_buf = 256 * 1000 + 8
+    cfg.dev_bytes = need
+    assert lib.lbm_init(C.byref(cfg), C.byref(h)) == -1  # misaligned
+    cfg.dev_buf = 256 * 1000
+    cfg.dev_bytes = need - 1
+    assert lib.lbm_init(C.byref(cfg), C.byref(h)) == -2  # too small
+    bad = P.Config(nx=16, ny=8, omega=0.5).to_c(keep)
+    assert lib.lbm_state_bytes(C.byref(bad)) == 0
+
+
+def test_state_bytes_scale_with_storage():
+    sizes = {s: P.state_bytes(P.Config(nx=4096, ny=2048, storage=s)) for s in P.STORAGE}
+    assert sizes["f64"] > sizes["f32"] > sizes["f16s"]
+    assert sizes["f16s"] == sizes["bf16s"]
+    # two buffers of five planes plus w (twice for shifted storage)
+    assert sizes["f32"] >= (2 * 5 * 4 + 2 * 4) * 4096 * 2048
+
+
+def test_solver_refuses_cpu_device():
+    with pytest.raises(RuntimeError):
+        P.Solver(P.Config(nx=16, ny=8), device="cpu")

@@ -1,0 +1,231 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Bars: FP64 fields within 1e-12 relative (normwise, max norm), FP32 fields
+within 1e-5; crack-tip positions, cut events and the cut mask bit-exact under
+a prescribed speed; K_III within 1e-12 (FP64).  Under the K criterion the tip
+path is the list of (step, column) cut events, compared together with the
+guard margins that make that comparison meaningful.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2206_12412_amd import Config, Solver  # noqa: E402
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32plain": 2e-3, "f16s": 2e-3, "bf16s": 3e-2}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def pair(storage="f64", **kw):
+    say(f"case storage={storage} {kw.get('nx')}x{kw.get('ny')} growth={kw.get('growth', 0)}")
+    ref = O.Oracle(O.OracleConfig(**kw))
+    gkw = dict(kw)
+    gkw.pop("threads", None)
+    per = gkw.pop("periodic", False)
+    gpu = Solver(Config(storage=storage, periodic=per, **gkw), device="cuda:0")
+    return ref, gpu
+
+
+def relerr(a, b):
+    scale = np.abs(b).max()
+    return np.abs(a - b).max() / (scale if scale > 0 else 1.0)
+
+
+def plain_kw(nx, ny, ell, v=0.3, tau=1e-3, steps=0, **extra):
+    kw = dict(nx=nx, ny=ny, has_crack=True, crack_x0=-0.5, crack_tip=ell - 0.5,
+              growth=O.GROW_PRESCRIBED, v_rel=v, tau_hist=np.array([tau]), trace_cap=steps)
+    kw.update(extra)
+    return kw
+
+
+def compare_run(storage, kw, steps, checkpoints=None, exact_crack=True, tol=None):
+    tol = TOL[storage] if tol is None else tol
+    ref, gpu = pair(storage, **kw)
+    checkpoints = checkpoints or [steps]
+    done = 0
+    worst = 0.0
+    for n in checkpoints:
+        ref.step(n - done)
+        gpu.step(n - done)
+        done = n
+        w_r, wd_r = ref.fields()
+        w_g, wd_g = gpu.fields()
+        e = relerr(w_g, w_r)
+        worst = max(worst, e)
+        assert e <= tol, (storage, n, e)
+        if storage == "f64":
+            assert relerr(wd_g, wd_r) <= 1e-12, (n, relerr(wd_g, wd_r))
+    if kw.get("has_crack"):
+        tr_r, tr_g = ref.traces(), gpu.traces()
+        if exact_crack:
+            np.testing.assert_array_equal(tr_g["tip"], tr_r["tip"])
+            np.testing.assert_array_equal(tr_g["flags"], tr_r["flags"])
+            assert gpu.cut_events()[:, 0].tolist() == ref.events()[:, 0].tolist()
+            assert gpu.cut_events()[:, 1].tolist() == ref.events()[:, 1].tolist()
+            mv_r, mh_r = ref.mask()
+            mv_g, mh_g = gpu.mask()
+            np.testing.assert_array_equal(mv_g, mv_r)
+            np.testing.assert_array_equal(mh_g, mh_r)
+        Kr, Kg = tr_r["K"], tr_g["K"]
+        assert np.array_equal(np.isnan(Kr), np.isnan(Kg))
+        ok = ~np.isnan(Kr)
+        if ok.any():
+            kerr = np.abs(Kg[ok] - Kr[ok]).max() / max(np.abs(Kr[ok]).max(), 1e-300)
+            ktol = {"f64": 1e-12, "f32": 1e-5, "f32plain": 5e-3, "f16s": 1e-3, "bf16s": 2e-2}[storage]
+            assert kerr <= ktol, (storage, kerr)
+    gpu.close()
+    return worst
+
+
+# ---------------------------------------------------------------- plain run --
+
+def test_plain_fp64_full_workload_bit_exact_tip_and_fields():
+    """256 x 128, 64-site crack at 0.3 c_s for 2000 steps, FP64."""
+    p = synth.config_plain_fp64()
+    kw = plain_kw(p.nx, p.ny, p.ell, p.v_rel, p.tau, p.steps)
+    worst = compare_run("f64", kw, p.steps, [500, 1000, 1279, 1280, 2000])
+    say(f"plain f64 worst rel err {worst:.3e}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s", "f32plain"])
+def test_plain_workload_reduced_precision(storage):
+    p = synth.config_plain_fp64()
+    kw = plain_kw(p.nx, p.ny, p.ell, p.v_rel, p.tau, p.steps)
+    worst = compare_run(storage, kw, p.steps, [500, 1000, 2000])
+    say(f"plain {storage} worst rel err {worst:.3e}")
+
+
+def test_fp64_is_bit_identical_to_the_oracle():
+    """Same operations in the same order without contraction: the FP64 state
+    equals the oracle's bit for bit."""
+    kw = plain_kw(100, 40, 20, v=0.45, steps=300)
+    ref, gpu = pair("f64", **kw)
+    ref.step(300)
+    gpu.step(300)
+    np.testing.assert_array_equal(gpu.populations(), ref.pops())
+    np.testing.assert_array_equal(gpu.fields()[0], ref.fields()[0])
+    np.testing.assert_array_equal(gpu.traces()["K"], ref.traces()["K"])
+
+
+# ------------------------------------------------- sizes, tiles, ragged ends --
+
+@pytest.mark.parametrize("nx,ny,ell", [(77, 34, 9), (130, 10, 40), (1000, 66, 300), (257, 2, 64),
+                                       (1, 2, 0), (65, 130, 64), (513, 36, 1), (33, 8, 33)])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+def test_ragged_sizes(nx, ny, ell, storage):
+    steps = 150
+    kw = plain_kw(nx, ny, max(ell, 0), v=0.6, steps=steps)
+    rng = np.random.default_rng(nx * 1000 + ny)
+    kw["wdot0"] = rng.normal(0, 1e-4, (ny, nx))
+    # noise-only fields: the stored 16-bit wdot is rounded by u = 2^-11 each
+    # step; a random walk over n steps, max-norm factor 4: 4 u sqrt(n)
+    tol = 4 * 2.0 ** -11 * math.sqrt(steps) if storage == "f16s" else None
+    compare_run(storage, kw, steps, [1, 7, steps], tol=tol)
+
+
+@pytest.mark.parametrize("rows,waves", [(1, 1), (3, 2), (16, 4), (64, 8), (1000, 1)])
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16s"])
+def test_launch_shapes_give_identical_results(rows, waves, storage):
+    kw = plain_kw(300, 90, 70, v=0.5, steps=120)
+    base = Solver(Config(storage=storage, **kw), device="cuda:0")
+    other = Solver(Config(storage=storage, **kw), device="cuda:0")
+    other.set_launch(rows, waves)
+    base.step(120)
+    other.step(120)
+    np.testing.assert_array_equal(base.populations(), other.populations())
+    np.testing.assert_array_equal(base.fields()[0], other.fields()[0])
+
+
+# ----------------------------------------------------------- special modes --
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_periodic_lattice(storage):
+    nx, ny = 200, 60
+    I, J = np.meshgrid(np.arange(nx), np.arange(ny))
+    w0 = 0.3 * np.cos(2 * np.pi * (3 * I / nx + 2 * J / ny))
+    rng = np.random.default_rng(4)
+    kw = dict(nx=nx, ny=ny, periodic=True, w0=w0, wdot0=rng.normal(0, 1e-2, (ny, nx)),
+              has_crack=True, crack_x0=40.0, crack_tip=120.7)
+    compare_run(storage, kw, 400, [1, 50, 400])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_face_loaded_stationary_crack(storage):
+    kw = dict(nx=256, ny=128, has_crack=True, crack_tip=127.5, face_traction=1e-3, trace_cap=300)
+    compare_run(storage, kw, 300, [100, 300])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_centre_crack_k_band_and_traction_history(storage):
+    rng = np.random.default_rng(9)
+    kw = dict(nx=180, ny=64, has_crack=True, crack_x0=30.2, crack_tip=80.0, growth=O.GROW_PRESCRIBED,
+              v_rel=0.7, k_band=5, r0=3.0, tau_hist=rng.uniform(-2e-3, 2e-3, 97), trace_cap=400,
+              mu=2.0, rho=0.5, kappa=2.5)
+    compare_run(storage, kw, 400, [37, 400])
+
+
+def test_no_crack_plate():
+    """Uniformly step-loaded plate without a crack.  Its early-time field is a
+    1-D step response whose FP32 error plateaus near 3e-5 of max|w| for any
+    FP32 rounding (of the stored values or of the arithmetic alike; a float32
+    emulation of the same scheme gives the identical number), so FP32 is held
+    to 5e-5 here; FP64 keeps its 1e-12 bar."""
+    kw = dict(nx=120, ny=50, tau_hist=np.array([1e-3]))
+    compare_run("f64", kw, 200)
+    compare_run("f32", kw, 200, tol=5e-5)
+
+
+# ----------------------------------------------------------- K criterion --
+
+def sif_margins(ref_tr, Kc):
+    K = ref_tr["K"]
+    ok = ~np.isnan(K)
+    kmargin = np.abs(K[ok] / Kc - 1).min()
+    a = ref_tr["tip"]
+    amargin = np.abs(a - np.round(a)).min()
+    return kmargin, amargin
+
+
+def test_sif_criterion_reduced_workload():
+    """The K-criterion workload scaled to 512 x 256 (crack 128, K_C = 1.5
+    K_static): FP64 cut events identical to the oracle; FP32 cut events
+    identical wherever the guard margins exceed the FP32 error band."""
+    p = synth.config_sif_fp32().scaled(512, 256, 128, 6000)
+    p.K_C = 1.5 * synth.k_static_edge(p.tau, p.ell)
+    kw = dict(nx=p.nx, ny=p.ny, has_crack=True, crack_tip=p.crack_tip, growth=O.GROW_SIF,
+              K_C=p.K_C, r0=p.r0, v_max=p.v_max, tau_hist=p.traction_history(),
+              wdot0=p.wdot0(), trace_cap=p.steps)
+    ref, g64 = pair("f64", **kw)
+    ref.step(p.steps)
+    g64.step(p.steps)
+    ev_r = ref.events()[:, :2].tolist()
+    assert len(ev_r) > 10
+    assert g64.cut_events().tolist() == ev_r
+    tr_r, tr_g = ref.traces(), g64.traces()
+    ok = ~np.isnan(tr_r["K"])
+    assert np.abs(tr_g["K"][ok] - tr_r["K"][ok]).max() <= 1e-12 * np.abs(tr_r["K"][ok]).max()
+    np.testing.assert_allclose(tr_g["tip"], tr_r["tip"], rtol=0, atol=1e-9)
+    km, am = sif_margins(tr_r, p.K_C)
+    _, g32 = pair("f32", **kw)
+    g32.step(p.steps)
+    tr32 = g32.traces()
+    kerr = np.abs(tr32["K"][ok] - tr_r["K"][ok]).max() / np.abs(tr_r["K"][ok]).max()
+    say(f"sif reduced: {len(ev_r)} cuts; margins |K/K_C-1| >= {km:.2e}, dist(a, Z) >= {am:.2e}; "
+        f"f32 K err {kerr:.2e}")
+    if km > 10 * kerr and am > 1e-6:
+        assert g32.cut_events().tolist() == ev_r
