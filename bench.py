@@ -1,0 +1,239 @@
+"""Benchmark of the crack LBM hot path on one MI355X.
+
+A step is one time step of the method: the fused collide-stream sweep over the
+whole plate followed by the crack step (K_III, criterion, tip advance, newly
+severed links).  Default workload: the 16384 x 8192 plate (134M sites) with a
+4096-site edge crack driven at 0.5 c_s, run with populations stored as FP64,
+FP32, FP16 and BF16 (the last three shifted by the static equilibrium, FP32
+arithmetic).  The JSON line reports FP16-storage GLUPS as `value`, next to the
+FP32 GLUPS, the ratio, each storage's K_III and field error against the FP64
+run of the same steps, the HBM roofline of the sweep kernel and the oracle's
+CPU throughput on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--storage f16s] [--workload precision]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GLUPS and % of HBM roofline, fp16-storage vs fp32 at stated K_III error"
+
+
+def plate_config(p, storage, trace_cap):
+    from paper_2206_12412_amd import Config
+    return Config(nx=p.nx, ny=p.ny, storage=storage, kappa=p.kappa, mu=p.mu, rho=p.rho,
+                  has_crack=True, crack_x0=p.crack_x0, crack_tip=p.crack_tip, growth=p.growth,
+                  v_rel=p.v_rel, K_C=p.K_C, r0=p.r0, v_max=p.v_max,
+                  tau_hist=p.traction_history(), wdot0=p.wdot0(), trace_cap=trace_cap)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "lbm_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2206_12412_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(storage: str, workload: str, sites: int):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size), or None when
+    no summary exists for this kernel source."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{storage}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def run_storage(p, storage, steps, warmup, torch, timing=True):
+    from paper_2206_12412_amd import Solver
+    # warm-up on a throw-away plate (clocks, code objects, page tables)
+    if warmup > 0:
+        s = Solver(plate_config(p, storage, 0))
+        s.step(warmup)
+        torch.cuda.synchronize()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    s = Solver(plate_config(p, storage, steps))
+    torch.cuda.synchronize()
+    if timing:
+        s.timing(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(s.stream)
+    s.step(steps)
+    stop.record(s.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    tm = s.timing(False) if timing else None
+    out = {
+        "ms": ms,
+        "glups": p.sites * steps / (ms * 1e-3) / 1e9,
+        "bytes_per_site": s.bytes_per_site(),
+        "launch": s.launch(),
+        "K": s.sif(0, steps),
+        "tip": s.traces(0, steps)["tip"],
+        "w": s.fields()[0],
+    }
+    if tm is not None and tm["steps"]:
+        out["sweep_ms"] = tm["sweep_ms"] / tm["steps"]
+        out["crack_ms"] = tm["crack_ms"] / tm["steps"]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(p, budget_s: float):
+    """The oracle as it stands on this host's cores, on the same plate."""
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    s = O.Oracle(O.OracleConfig(
+        nx=p.nx, ny=p.ny, kappa=p.kappa, mu=p.mu, rho=p.rho, has_crack=True, crack_x0=p.crack_x0,
+        crack_tip=p.crack_tip, growth=p.growth, v_rel=p.v_rel, K_C=p.K_C, r0=p.r0,
+        v_max=p.v_max, tau_hist=p.traction_history(), trace_cap=0, threads=threads))
+    s.step(1)  # first touch of the pages
+    n, t0 = 0, time.perf_counter()
+    while True:
+        s.step(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    s.close()
+    return {"value": p.sites * n / el / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of the full {p.nx}x{p.ny} plate, FP64, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="precision", choices=["precision", "sif", "plain"])
+    ap.add_argument("--storage", default="f16s")
+    ap.add_argument("--compare", default="f64,f32,f16s,bf16s",
+                    help="storages run; the first is the error reference")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2206_12412_amd import load_library
+
+    load_library()  # fails loudly when the HIP library is not built
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
+         "plain": synth.config_plain_fp64}[args.workload]()
+    steps = args.steps if args.steps is not None else p.steps
+    storages = [s for s in args.compare.split(",") if s]
+    if args.storage not in storages:
+        storages.append(args.storage)
+    ref_name = storages[0]
+
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"calibration copy of {n} bytes done", file=sys.stderr, flush=True)
+        del a, b
+
+    results = {}
+    for st in storages:
+        print(f"bench: {p.name} storage={st} steps={steps} warmup={args.warmup}", file=sys.stderr,
+              flush=True)
+        results[st] = run_storage(p, st, steps, args.warmup, torch)
+        print(f"bench: {st}: {results[st]['glups']:.1f} GLUPS", file=sys.stderr, flush=True)
+
+    ref = results[ref_name]
+    ok = ~np.isnan(ref["K"])
+    Kscale = np.abs(ref["K"][ok]).max() if ok.any() else 0.0
+    if not Kscale > 0:  # nothing has reached the crack yet
+        ok[:] = False
+    per = {}
+    for st, r in results.items():
+        e = {"glups": round(r["glups"], 2), "ms_per_step": round(r["ms"] / steps, 4),
+             "bytes_per_site": r["bytes_per_site"], "launch": r["launch"]}
+        if "sweep_ms" in r:
+            gbs = p.sites * r["bytes_per_site"] / (r["sweep_ms"] * 1e-3) / 1e9
+            e["sweep_ms"] = round(r["sweep_ms"], 4)
+            e["sweep_GBps"] = round(gbs, 1)
+            e["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+        if st != ref_name:
+            dK = np.abs(r["K"][ok] - ref["K"][ok])
+            e["K_err_rel_max"] = float(dK.max() / Kscale) if ok.any() else None
+            e["K_err_rel_final"] = float(abs(r["K"][-1] - ref["K"][-1]) / abs(ref["K"][-1])) \
+                if ok[-1] and ref["K"][-1] != 0 else None
+            dw = r["w"] - ref["w"]
+            e["w_err_rel_max"] = float(np.abs(dw).max() / np.abs(ref["w"]).max())
+            e["w_err_rel_rms"] = float(np.sqrt(np.mean(dw * dw)) / np.sqrt(np.mean(ref["w"] ** 2)))
+            e["tip_path_identical"] = bool(np.array_equal(r["tip"], ref["tip"]))
+        per[st] = e
+
+    head = results[args.storage]
+    bps = head["bytes_per_site"]
+    achieved = p.sites * bps / (head["sweep_ms"] * 1e-3) / 1e9
+    traffic = traffic_for(args.storage, args.workload, p.sites)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": f"sweep_kernel ({args.storage})",
+                "algorithmic_bytes_per_launch": p.sites * bps}
+
+    line = {
+        "metric": METRIC,
+        "value": round(head["glups"], 2),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"] / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage != "f64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": p.name, "nx": p.nx, "ny": p.ny, "crack_sites": p.ell,
+                   "growth": "prescribed" if p.growth == 1 else "sif", "v_rel": p.v_rel,
+                   "tau": p.tau, "storage": args.storage, "parallelism": "single-gpu"},
+        "storages": per,
+        "error_reference": ref_name,
+    }
+    if "f32" in results and args.storage != "f32":
+        line["vs_f32_glups"] = round(head["glups"] / results["f32"]["glups"], 3)
+    line["roofline"] = roofline
+    if not args.no_cpu:
+        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

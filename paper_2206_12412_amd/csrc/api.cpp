@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbm.h"
+#include "lbm.h"
 #include "lbm_internal.hpp"
 
 using lbmk::Store;
@@ -90,18 +90,14 @@ Layout make_layout(const lbm_config &c, Store s) {
     o += 5 * plane_bytes;
   }
   const size_t wbytes = align_up((size_t)L.pitch * c.ny * L.welem, 256) + 1024;
-  L.off_w[0] = o;
-  o += wbytes;
-  if (shifted(s)) {
-    L.off_w[1] = o;
+  for (int b = 0; b < 2; ++b) {
+    L.off_w[b] = o;
     o += wbytes;
-  } else {
-    L.off_w[1] = L.off_w[0];
   }
   const size_t mbytes = align_up((size_t)c.ny * L.mw * 4, 256);
   L.off_mV = o; o += mbytes;
   L.off_mH = o; o += mbytes;
-  L.off_rf = o; o += align_up((size_t)c.ny * 4, 256);
+  L.off_rf = o; o += 256;
   L.off_crack = o; o += 256;
   const size_t tc = c.trace_cap > 0 ? (size_t)c.trace_cap : 1;
   L.off_trK = o; o += align_up(tc * 8, 256);
@@ -164,8 +160,7 @@ struct lbm_handle {
   std::vector<double> tau;
   double cs = 0, c = 0, dt = 0, lambda = 0, A0 = 0, Ak = 0, coef = 0;
   char *base = nullptr;
-  int cur = 0;        // f buffer holding the current state
-  int wcur = 0;       // w buffer holding the current w (shifted storage)
+  int cur = 0;        // buffer (populations and w) holding the current state
   int64_t step = 0;
   int rows = 16, waves = 4;
   bool timing = false;
@@ -179,7 +174,7 @@ struct lbm_handle {
   void *wbuf(int b) const { return base + L.off_w[b]; }
   uint32_t *mV() const { return reinterpret_cast<uint32_t *>(base + L.off_mV); }
   uint32_t *mH() const { return reinterpret_cast<uint32_t *>(base + L.off_mH); }
-  uint32_t *rowflags() const { return reinterpret_cast<uint32_t *>(base + L.off_rf); }
+  lbmk::MaskRows *mrows() const { return reinterpret_cast<lbmk::MaskRows *>(base + L.off_rf); }
   lbmk::DevCrack *crack() const { return reinterpret_cast<lbmk::DevCrack *>(base + L.off_crack); }
   double *stage() const { return reinterpret_cast<double *>(base + L.off_stage); }
   double tau_at(int64_t n) const {
@@ -223,16 +218,11 @@ int launch_sweep_typed(lbm_handle *h) {
   const int nxt = 1 - h->cur;
   a.fin = static_cast<const S *>(h->fbuf(h->cur));
   a.fout = static_cast<S *>(h->fbuf(nxt));
-  if (shifted(h->store)) {
-    a.win = static_cast<const W *>(h->wbuf(h->wcur));
-    a.wout = static_cast<W *>(h->wbuf(1 - h->wcur));
-  } else {
-    a.win = static_cast<const W *>(h->wbuf(0));
-    a.wout = static_cast<W *>(h->wbuf(0));
-  }
+  a.win = static_cast<const W *>(h->wbuf(h->cur));
+  a.wout = static_cast<W *>(h->wbuf(nxt));
   a.mV = h->mV();
   a.mH = h->mH();
-  a.rowflags = h->rowflags();
+  a.mrows = h->mrows();
   a.p = h->plate;
   a.omega = (C)h->cfg.omega;
   a.dt = (C)h->dt;
@@ -264,11 +254,10 @@ int launch_sweep_any(lbm_handle *h) {
 int launch_crack_step(lbm_handle *h) {
   lbmk::CrackArgs a{};
   a.st = h->crack();
-  const bool sh = shifted(h->store);
-  a.w = sh ? h->wbuf(1 - h->wcur) : h->wbuf(0);  // w after the sweep just enqueued
+  a.w = h->wbuf(1 - h->cur);  // w after the sweep just enqueued
   a.w_is_double = h->store == Store::F64;
   a.mV = h->mV();
-  a.rowflags = h->rowflags();
+  a.mrows = h->mrows();
   a.trK = reinterpret_cast<double *>(h->base + h->L.off_trK);
   a.trA = reinterpret_cast<double *>(h->base + h->L.off_trA);
   a.trV = reinterpret_cast<double *>(h->base + h->L.off_trV);
@@ -345,11 +334,14 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   p.j0 = cfg->ny / 2 - 1;
   p.periodic = cfg->bc_mode == LBM_BC_PERIODIC;
   p.plane = L.plane;
-  // default launch shape: enough waves to fill 256 CUs, long marches when the plate allows
+  // default launch shape (measured on MI355X for plates much larger than the
+  // caches): one row per wave streams the plate in address order; 16-bit
+  // storage does better with two rows per wave.  Small plates get whatever
+  // keeps >= 8192 waves in flight.
   {
     const int vec = lbmk::sweep_vec(s);
     const long strips = (cfg->nx + 64L * vec - 1) / (64L * vec);
-    int rows = 64;
+    int rows = (s == Store::F16S || s == Store::BF16S) ? 2 : 1;
     while (rows > 1 && strips * ((cfg->ny + rows - 1) / rows) < 8192) rows /= 2;
     h->rows = rows;
     h->waves = 4;
@@ -382,7 +374,7 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
       return bail(fail(LBM_EHIP, "init kernel failed"));
     if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(LBM_EHIP, "init sync failed"));
   }
-  if (lbmk::launch_init_mask(h->mV(), h->mH(), h->rowflags(), p, cfg->has_crack, cfg->crack_x0,
+  if (lbmk::launch_init_mask(h->mV(), h->mH(), h->mrows(), p, cfg->has_crack, cfg->crack_x0,
                              cfg->crack_tip, st) != hipSuccess)
     return bail(fail(LBM_EHIP, "mask init failed"));
   lbmk::DevCrack &c0 = h->host_crack;
@@ -438,7 +430,6 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
       }
     }
     h->cur = 1 - h->cur;
-    if (shifted(h->store)) h->wcur = 1 - h->wcur;
     h->step++;
   }
   return LBM_OK;
@@ -518,7 +509,7 @@ static int export_rows(lbm_handle *h, double *w_out, double *wd_out, double *f_o
   double *stage = h->stage();
   const size_t chunk = (size_t)sr * p.nx;
   const void *f = h->fbuf(h->cur);
-  const void *w = shifted(h->store) ? h->wbuf(h->wcur) : h->wbuf(0);
+  const void *w = h->wbuf(h->cur);
   const size_t n = (size_t)p.nx * p.ny;
   for (int r0 = 0; r0 < p.ny; r0 += sr) {
     const int nr = std::min(sr, p.ny - r0);

@@ -117,7 +117,12 @@ __global__ void __launch_bounds__(64) crack_kernel(const CrackArgs a) {
         any = true;
       }
     }
-    if (any) a.rowflags[p.j0] |= 2u;
+    if (any) {
+      MaskRows mr = *a.mrows;
+      if (p.j0 < mr.vlo || mr.vlo > mr.vhi) mr.vlo = p.j0;
+      if (p.j0 > mr.vhi) mr.vhi = p.j0;
+      *a.mrows = mr;
+    }
     c.tip = a_new;
     flags |= kFlagGrew;
   }
@@ -136,11 +141,12 @@ __global__ void __launch_bounds__(64) crack_kernel(const CrackArgs a) {
   *a.st = c;
 }
 
-// Mask words of every row and the per-row flags: all links intact except the
-// vertical links of the crack row at the columns lo..hi (the initial crack
-// segment x0 .. a0 touches exactly those, Alg. 1 "as for the initial crack").
-__global__ void init_mask_kernel(uint32_t *mV, uint32_t *mH, uint32_t *rowflags, Plate p,
-                                 int lo, int hi) {
+// Mask words of every row: all links intact except the vertical links of the
+// crack row at the columns lo..hi (the initial crack segment x0 .. a0 touches
+// exactly those, Alg. 1 "as for the initial crack").  With a crack the
+// mask-row range names the crack row from the start (growth cuts only there).
+__global__ void init_mask_kernel(uint32_t *mV, uint32_t *mH, MaskRows *mrows, Plate p, int lo,
+                                 int hi, int has_crack) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t words = (size_t)p.ny * p.mw;
   if (t < words) {
@@ -156,7 +162,7 @@ __global__ void init_mask_kernel(uint32_t *mV, uint32_t *mH, uint32_t *rowflags,
     mV[t] = v;
     mH[t] = 0u;
   }
-  if (t < (size_t)p.ny) rowflags[t] = ((int)t == p.j0 && hi >= lo) ? 2u : 0u;
+  if (t == 0) *mrows = has_crack ? MaskRows{p.j0, p.j0, 1, 0} : MaskRows{1, 0, 1, 0};
 }
 
 }  // namespace
@@ -166,7 +172,7 @@ hipError_t launch_crack(const CrackArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, uint32_t *rowflags, const Plate &p,
+hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const Plate &p,
                             int has_crack, double x0, double a0, hipStream_t st) {
   int lo = 1, hi = 0;  // empty
   if (has_crack) {
@@ -176,9 +182,9 @@ hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, uint32_t *rowflags, cons
     if (hi > p.nx - 1) hi = p.nx - 1;
   }
   const size_t words = (size_t)p.ny * p.mw;
-  const size_t n = words > (size_t)p.ny ? words : (size_t)p.ny;
-  const unsigned blocks = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(init_mask_kernel, dim3(blocks), dim3(256), 0, st, mV, mH, rowflags, p, lo, hi);
+  const unsigned blocks = (unsigned)((words + 255) / 256);
+  hipLaunchKernelGGL(init_mask_kernel, dim3(blocks), dim3(256), 0, st, mV, mH, mrows, p, lo, hi,
+                     has_crack);
   return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ __global__ void init_rows_kernel(S *f, W *w, W *w2, Plate p, int row0, int nrows
     f[x] = cvt_out<S>(wdv - A0 * wv);
     for (int a = 1; a < 5; ++a) f[a * p.plane + x] = cvt_out<S>(Ak * wv);
     w[x] = static_cast<W>(wv);
+    w2[x] = static_cast<W>(wv);
   } else {
     const W ws = static_cast<W>(wv);
     const double dw = wv - (double)ws;  // part of w0 that the stored w cannot hold

@@ -44,15 +44,25 @@ struct CrackParams {
   int64_t event_cap;
 };
 
+// Rows of the cut bitmask that may hold a severed link: vertical links in
+// rows vlo..vhi, horizontal links in rows hlo..hhi (lo > hi: none).  Kept on
+// the device next to the mask and widened by the crack kernel; the sweep
+// reads it once per wave, so rows away from the crack never touch the mask.
+struct MaskRows {
+  int32_t vlo, vhi, hlo, hhi;
+};
+
 // Per-launch arguments of the sweep.  S is the storage type of the
-// populations, W the storage type of w, C the compute type.
+// populations, W the storage type of w, C the compute type.  The source and
+// destination buffers are distinct (populations and w are double-buffered).
 template <typename S, typename W, typename C>
 struct SweepArgs {
   const S *fin;      // plane 0 of the source populations
   S *fout;           // plane 0 of the destination populations
   const W *win;      // w before the step
-  W *wout;           // w after the step (== win for in-place storage)
-  const uint32_t *mV, *mH, *rowflags;
+  W *wout;           // w after the step
+  const uint32_t *mV, *mH;
+  const MaskRows *mrows;
   Plate p;
   C omega, dt, A0, Ak;
   C t_top, t_bot;    // coef * traction on top / bottom edge links
@@ -65,7 +75,8 @@ struct CrackArgs {
   DevCrack *st;
   const void *w;     // w after the sweep (double or float, see w_is_double)
   int w_is_double;
-  uint32_t *mV, *rowflags;
+  uint32_t *mV;
+  MaskRows *mrows;
   double *trK, *trA, *trV;
   int32_t *trF;
   int64_t *evStep;
@@ -82,7 +93,7 @@ hipError_t launch_sweep(Store s, const void *args, hipStream_t st);
 
 // ---- launchers (crack.hip) ----
 hipError_t launch_crack(const CrackArgs &a, hipStream_t st);
-hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, uint32_t *rowflags, const Plate &p,
+hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const Plate &p,
                             int has_crack, double x0, double a0, hipStream_t st);
 
 // ---- launchers (io.hip) ----
