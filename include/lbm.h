@@ -160,10 +160,14 @@ int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms
                int64_t *n_timed);
 
 /* Launch shape of the sweep: sites per lane along x (vec, fixed by the
- * storage), rows per wave (rows), waves per workgroup (waves).  lbm_set_launch
- * accepts rows in 1..4096 and waves in {1, 2, 4, 8}. */
-int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves);
-int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves);
+ * storage), rows marched per wave (rows), waves per workgroup (waves) and the
+ * cap on resident waves per SIMD (occupancy; 0 = no cap), which the library
+ * enforces by reserving LDS per workgroup.  lbm_set_launch accepts rows in
+ * 1..4096, waves in {1, 2, 4, 8} and occupancy in 0..8.  Results do not
+ * depend on the launch shape. */
+int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves,
+                   int32_t *occupancy);
+int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy);
 
 /* Algorithmic bytes moved by one sweep per site (read + write of the five
  * populations and of w), for the storage of the handle. */

@@ -119,7 +119,12 @@ int validate(const lbm_config *c, Store *s) {
   if (!store_of(c->storage, s)) return fail(LBM_EINVAL, "unknown storage %d", c->storage);
   if (c->nx < 1 || c->ny < 1 || c->nx > (1 << 24) || c->ny > (1 << 24))
     return fail(LBM_EINVAL, "plate size %d x %d out of range", c->nx, c->ny);
-  if ((double)c->nx * c->ny > 4.0e9) return fail(LBM_EINVAL, "plate too large");
+  // in-plane byte offsets are 32-bit: one plane (populations or w) < 4 GiB
+  {
+    const size_t e = (c->storage == LBM_F64) ? 8 : 4;
+    if (align_up((size_t)c->nx, 64) * (size_t)c->ny * e >= (size_t(1) << 32))
+      return fail(LBM_EINVAL, "plate of %d x %d sites: one plane would exceed 4 GiB", c->nx, c->ny);
+  }
   if (c->bc_mode != LBM_BC_WALLS && c->bc_mode != LBM_BC_PERIODIC)
     return fail(LBM_EINVAL, "unknown bc_mode %d", c->bc_mode);
   if (!(c->mu > 0) || !(c->rho > 0) || !std::isfinite(c->mu) || !std::isfinite(c->rho))
@@ -162,7 +167,8 @@ struct lbm_handle {
   char *base = nullptr;
   int cur = 0;        // buffer (populations and w) holding the current state
   int64_t step = 0;
-  int rows = 16, waves = 4;
+  int rows = 1, waves = 4, occ = 0;
+  int lds_per_cu = 65536;
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<hipEvent_t> ev_used;  // triples: before sweep, after sweep, after crack
@@ -236,6 +242,21 @@ int launch_sweep_typed(lbm_handle *h) {
   a.t_lo = per ? C(0) : (C)(h->coef * -h->cfg.face_traction);
   a.rows = h->rows;
   a.waves = h->waves;
+  a.lds_bytes = 0;
+  if (h->occ > 0) {
+    // resident workgroups per CU = occ waves per SIMD x 4 SIMDs / waves per group
+    const int groups = std::max(1, (h->occ * 4) / h->waves);
+    a.lds_bytes = std::min(65536, (h->lds_per_cu / groups) / 256 * 256);
+  }
+  // links can be severed only on the crack row j0 (vertical links between
+  // rows j0 and j0 + 1): those two rows go to the boundary kernel
+  if (h->cfg.has_crack) {
+    a.skip_lo = h->plate.j0;
+    a.skip_hi = h->plate.j0 + 1;
+  } else {
+    a.skip_lo = 1;
+    a.skip_hi = 0;
+  }
   HIP_TRY(lbmk::launch_sweep(h->store, &a, h->stream));
   return LBM_OK;
 }
@@ -334,17 +355,24 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   p.j0 = cfg->ny / 2 - 1;
   p.periodic = cfg->bc_mode == LBM_BC_PERIODIC;
   p.plane = L.plane;
-  // default launch shape (measured on MI355X for plates much larger than the
-  // caches): one row per wave streams the plate in address order; 16-bit
-  // storage does better with two rows per wave.  Small plates get whatever
-  // keeps >= 8192 waves in flight.
+  // default launch shape, measured on MI355X on plates much larger than the
+  // caches: one row per wave streams the plate in address order, and capping
+  // the resident waves per SIMD (3 for 8-byte and 4-byte storage, 4 for
+  // 16-bit storage) keeps fewer DRAM rows open at once.  Small plates lower
+  // the march length until >= 8192 waves are in flight anyway.
   {
-    const int vec = lbmk::sweep_vec(s);
-    const long strips = (cfg->nx + 64L * vec - 1) / (64L * vec);
-    int rows = (s == Store::F16S || s == Store::BF16S) ? 2 : 1;
-    while (rows > 1 && strips * ((cfg->ny + rows - 1) / rows) < 8192) rows /= 2;
-    h->rows = rows;
-    h->waves = 4;
+    const bool half = (s == Store::F16S || s == Store::BF16S);
+    h->rows = 1;
+    h->waves = (s == Store::F32S || s == Store::F32_PLAIN) ? 2 : 4;
+    h->occ = half ? 4 : 3;
+  }
+
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess && lds > 0)
+      h->lds_per_cu = lds;
   }
 
   auto bail = [&](int code) {
@@ -582,20 +610,23 @@ int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms
   return LBM_OK;
 }
 
-int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves) {
+int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves, int32_t *occupancy) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (vec) *vec = lbmk::sweep_vec(h->store);
   if (rows) *rows = h->rows;
   if (waves) *waves = h->waves;
+  if (occupancy) *occupancy = h->occ;
   return LBM_OK;
 }
 
-int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves) {
+int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (rows < 1 || rows > 4096) return fail(LBM_EINVAL, "rows must be in 1..4096");
   if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(LBM_EINVAL, "waves must be 1, 2, 4 or 8");
+  if (occupancy < 0 || occupancy > 8) return fail(LBM_EINVAL, "occupancy must be in 0..8");
   h->rows = rows;
   h->waves = waves;
+  h->occ = occupancy;
   return LBM_OK;
 }
 

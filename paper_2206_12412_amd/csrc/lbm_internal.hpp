@@ -67,8 +67,12 @@ struct SweepArgs {
   C omega, dt, A0, Ak;
   C t_top, t_bot;    // coef * traction on top / bottom edge links
   C t_up, t_lo;      // coef * traction on the crack face above / below
-  int rows;          // rows marched by one wave
-  int waves;         // waves per workgroup
+  int rows;          // rows marched by one wave of the interior kernel
+  int waves;         // waves per workgroup of the interior kernel
+  int lds_bytes;     // LDS reserved per interior workgroup (caps resident waves; 0 = none)
+  // rows the interior kernel leaves to the boundary kernel besides the two
+  // edge rows: the rows next to severable links (crack rows), lo > hi = none
+  int skip_lo, skip_hi;
 };
 
 struct CrackArgs {

@@ -88,8 +88,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_get_populations.argtypes = [vp, P(d)]
     lib.lbm_get_mask.argtypes = [vp, P(C.c_uint8), P(C.c_uint8)]
     lib.lbm_timing.argtypes = [vp, i32, P(d), P(d), P(i64)]
-    lib.lbm_get_launch.argtypes = [vp, P(i32), P(i32), P(i32)]
-    lib.lbm_set_launch.argtypes = [vp, i32, i32]
+    lib.lbm_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+    lib.lbm_set_launch.argtypes = [vp, i32, i32, i32]
     lib.lbm_bytes_per_site.argtypes = [vp]
     lib.lbm_bytes_per_site.restype = d
     lib.lbm_free.argtypes = [vp]
@@ -271,12 +271,12 @@ class Solver:
         return {"sweep_ms": s.value, "crack_ms": k.value, "steps": n.value}
 
     def launch(self):
-        v, r, w = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(self._lib.lbm_get_launch(self._h, C.byref(v), C.byref(r), C.byref(w)))
-        return {"vec": v.value, "rows": r.value, "waves": w.value}
+        v, r, w, o = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self._lib.lbm_get_launch(self._h, C.byref(v), C.byref(r), C.byref(w), C.byref(o)))
+        return {"vec": v.value, "rows": r.value, "waves": w.value, "occupancy": o.value}
 
-    def set_launch(self, rows: int, waves: int):
-        _check(self._lib.lbm_set_launch(self._h, int(rows), int(waves)))
+    def set_launch(self, rows: int, waves: int, occupancy: int = 0):
+        _check(self._lib.lbm_set_launch(self._h, int(rows), int(waves), int(occupancy)))
 
     def bytes_per_site(self) -> float:
         return float(self._lib.lbm_bytes_per_site(self._h))

@@ -138,13 +138,15 @@ def test_ragged_sizes(nx, ny, ell, storage):
     compare_run(storage, kw, steps, [1, 7, steps], tol=tol)
 
 
-@pytest.mark.parametrize("rows,waves", [(1, 1), (3, 2), (16, 4), (64, 8), (1000, 1)])
+@pytest.mark.parametrize("rows,waves,occ", [(1, 1, 0), (3, 2, 2), (16, 4, 0), (64, 8, 3),
+                                            (1000, 1, 8), (2, 4, 4)])
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16s"])
-def test_launch_shapes_give_identical_results(rows, waves, storage):
+def test_launch_shapes_give_identical_results(rows, waves, occ, storage):
     kw = plain_kw(300, 90, 70, v=0.5, steps=120)
     base = Solver(Config(storage=storage, **kw), device="cuda:0")
     other = Solver(Config(storage=storage, **kw), device="cuda:0")
-    other.set_launch(rows, waves)
+    other.set_launch(rows, waves, occ)
+    assert other.launch()["occupancy"] == occ
     base.step(120)
     other.step(120)
     np.testing.assert_array_equal(base.populations(), other.populations())
