@@ -40,7 +40,7 @@ def plate_config(p, storage, trace_cap):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "lbm_internal.hpp"):
+    for f in ("sweep.hip", "sweep_core.hpp", "lbm_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2206_12412_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -87,13 +87,15 @@ def run_storage(p, storage, steps, warmup, torch, timing=True):
         "ms": ms,
         "glups": p.sites * steps / (ms * 1e-3) / 1e9,
         "bytes_per_site": s.bytes_per_site(),
+        "interior_sites": s.interior_sites(),
         "launch": s.launch(),
         "K": s.sif(0, steps),
         "tip": s.traces(0, steps)["tip"],
         "w": s.fields()[0],
     }
     if tm is not None and tm["steps"]:
-        out["sweep_ms"] = tm["sweep_ms"] / tm["steps"]
+        out["interior_ms"] = tm["interior_ms"] / tm["steps"]
+        out["boundary_ms"] = tm["boundary_ms"] / tm["steps"]
         out["crack_ms"] = tm["crack_ms"] / tm["steps"]
     s.close()
     del s
@@ -122,6 +124,76 @@ def cpu_baseline(p, budget_s: float):
             "sample": f"{n} steps of the full {p.nx}x{p.ny} plate, FP64, {el:.1f} s"}
 
 
+def _read_csv(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name: str) -> str:
+    for key in ("sweep_interior", "sweep_boundary", "crack_kernel", "copyBuffer", "init_rows",
+                "export_rows", "zero_kernel", "init_mask"):
+        if key in name:
+            return key
+    return name[:40]
+
+
+def summarize_trace(dirpath: str, out_md: str, command: str):
+    """Markdown summary of a `rocprofv3 --kernel-trace --stats` run."""
+    rows = _read_csv(os.path.join(dirpath, "run_kernel_stats.csv"))
+    lines = [f"# Kernel trace: {os.path.basename(out_md)}", "", "Command:", "",
+             f"    {command}", "", "| kernel | calls | avg us | min us | max us | % time | full name |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} | `{r['Name'][:110]}` |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, copy_bytes: int,
+                  command: str):
+    """HBM bytes per interior-sweep launch from FETCH_SIZE and WRITE_SIZE runs,
+    each scaled by the same counter's reading for a device copy of copy_bytes."""
+    import synth
+    p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
+         "plain": synth.config_plain_fp64}[workload]()
+    out = {"storage": storage, "workload": workload, "kernel_source_sha": kernel_source_hash(),
+           "command": command, "copy_bytes": copy_bytes}
+    total = 0.0
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _read_csv(os.path.join(d, "run_counter_collection.csv"))
+                if r["Counter_Name"] == counter]
+        copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
+        factor = copy_bytes / (copy * 1024.0)
+        vals = [float(r["Counter_Value"]) for r in rows if "sweep_interior" in r["Kernel_Name"]]
+        kib = sum(vals) / len(vals)
+        out[counter] = {"KiB_per_launch": kib, "copy_KiB": copy, "factor": factor,
+                        "bytes_per_launch": kib * 1024.0 * factor, "launches": len(vals)}
+        total += kib * 1024.0 * factor
+    e = {"f64": 8, "f32": 4, "f32plain": 4, "f16s": 2, "bf16s": 2}[storage]
+    we = 8 if storage == "f64" else 4
+    interior = p.nx * (p.ny - 4)
+    out["bytes_per_launch"] = total
+    out["algorithmic_bytes_per_launch"] = interior * 2 * (5 * e + we)
+    out["traffic_over_algorithmic"] = total / out["algorithmic_bytes_per_launch"]
+    base = os.path.join(ROOT, "profiles", f"sweep_{storage}_{workload}_traffic")
+    with open(base + ".json", "w") as fh:
+        json.dump(out, fh, indent=1)
+    f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    with open(base + ".md", "w") as fh:
+        fh.write(f"# HBM traffic of sweep_interior ({storage}, {workload} workload)\n\n"
+                 f"Commands (one run per counter, C = FETCH_SIZE then WRITE_SIZE):\n\n    {command}\n\n"
+                 f"| counter | KiB / launch | copy of {copy_bytes} B reads | scale | bytes / launch |\n"
+                 f"|---|---|---|---|---|\n"
+                 f"| FETCH_SIZE | {f['KiB_per_launch']:.1f} | {f['copy_KiB']:.1f} KiB | {f['factor']:.4f} | {f['bytes_per_launch']:.4e} |\n"
+                 f"| WRITE_SIZE | {w['KiB_per_launch']:.1f} | {w['copy_KiB']:.1f} KiB | {w['factor']:.4f} | {w['bytes_per_launch']:.4e} |\n\n"
+                 f"Total {total:.4e} B per launch against {out['algorithmic_bytes_per_launch']:.4e} algorithmic "
+                 f"({interior} interior sites x {2 * (5 * e + we)} B): ratio {out['traffic_over_algorithmic']:.4f}.\n"
+                 f"Kernel source sha256[:16] = {out['kernel_source_sha']}.\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,11 +207,23 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"),
+                    help="write a markdown summary of a rocprofv3 kernel-trace directory and exit")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB", "COMMAND"),
+                    help="write profiles/sweep_<storage>_<workload>_traffic.{json,md} and exit")
     args = ap.parse_args()
 
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_pmc:
+        fd, wd, mib, cmd = args.summarize_pmc
+        summarize_pmc(fd, wd, args.storage, args.workload, int(mib) << 20, cmd)
+        return
+
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding design notes); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the sharding design is described, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -182,10 +266,12 @@ def main():
     for st, r in results.items():
         e = {"glups": round(r["glups"], 2), "ms_per_step": round(r["ms"] / steps, 4),
              "bytes_per_site": r["bytes_per_site"], "launch": r["launch"]}
-        if "sweep_ms" in r:
-            gbs = p.sites * r["bytes_per_site"] / (r["sweep_ms"] * 1e-3) / 1e9
-            e["sweep_ms"] = round(r["sweep_ms"], 4)
-            e["sweep_GBps"] = round(gbs, 1)
+        if "interior_ms" in r:
+            gbs = r["interior_sites"] * r["bytes_per_site"] / (r["interior_ms"] * 1e-3) / 1e9
+            e["interior_kernel_ms"] = round(r["interior_ms"], 4)
+            e["boundary_kernel_ms"] = round(r["boundary_ms"], 4)
+            e["crack_kernel_ms"] = round(r["crack_ms"], 4)
+            e["interior_GBps"] = round(gbs, 1)
             e["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
         if st != ref_name:
             dK = np.abs(r["K"][ok] - ref["K"][ok])
@@ -200,12 +286,14 @@ def main():
 
     head = results[args.storage]
     bps = head["bytes_per_site"]
-    achieved = p.sites * bps / (head["sweep_ms"] * 1e-3) / 1e9
+    alg = head["interior_sites"] * bps  # algorithmic bytes of one interior-kernel launch
+    achieved = alg / (head["interior_ms"] * 1e-3) / 1e9
     traffic = traffic_for(args.storage, args.workload, p.sites)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": f"sweep_kernel ({args.storage})",
-                "algorithmic_bytes_per_launch": p.sites * bps}
+                "traffic": traffic, "kernel": f"sweep_interior ({args.storage})",
+                "algorithmic_bytes_per_launch": alg,
+                "kernel_ms": round(head["interior_ms"], 4)}
 
     line = {
         "metric": METRIC,

@@ -152,12 +152,17 @@ int lbm_get_populations(lbm_handle *h, double *f_out);
  * mode), either may be NULL. */
 int lbm_get_mask(lbm_handle *h, uint8_t *cutV, uint8_t *cutH);
 
-/* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
- * recording (and clears the sums), 0 stops; the sums of the sweep and crack
- * kernel durations (ms) and the number of timed steps are returned
- * (synchronises the stream).  Any output pointer may be NULL. */
-int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms,
-               int64_t *n_timed);
+/* Kernel timing with HIP events on the handle's stream.  A step launches the
+ * interior sweep kernel (every row away from the plate edges and the crack
+ * rows), the boundary-row sweep kernel and the crack kernel; enable = 1 starts
+ * recording (and clears the sums), 0 stops.  Returns the summed durations (ms)
+ * of the three kernels and the number of timed steps (synchronises the
+ * stream).  Any output pointer may be NULL. */
+int lbm_timing(lbm_handle *h, int32_t enable, double *interior_ms, double *boundary_ms,
+               double *crack_ms, int64_t *n_timed);
+
+/* Sites updated by the interior sweep kernel (all but the edge and crack rows). */
+int64_t lbm_interior_sites(const lbm_handle *h);
 
 /* Launch shape of the sweep: sites per lane along x (vec, fixed by the
  * storage), rows marched per wave (rows), waves per workgroup (waves) and the
@@ -175,6 +180,52 @@ double lbm_bytes_per_site(const lbm_handle *h);
 
 /* Release the handle (host metadata only; the device block stays the caller's). */
 void lbm_free(lbm_handle *h);
+
+/* ---------------------------------------------------------------- batches --
+ * Many independent plates (each its own lbm_config: size, load, crack rule)
+ * advanced together by batched kernels; every plate of a batch must use the
+ * same storage.  Each plate's arithmetic is the single-plate arithmetic, so a
+ * plate evolves bit for bit as it does alone.  dev_buf/dev_bytes/stream of
+ * the plate configs are ignored: the batch places every plate inside its own
+ * device block (lbm_batch_state_bytes bytes, 256-byte aligned, caller-owned)
+ * and runs on the given stream. */
+typedef struct lbm_batch lbm_batch;
+
+size_t lbm_batch_state_bytes(const lbm_config *cfgs, int32_t n);
+int lbm_batch_init(const lbm_config *cfgs, int32_t n, void *dev_buf, size_t dev_bytes, void *stream,
+                   lbm_batch **out);
+
+/* nsteps steps; each step is one batched interior launch, one batched
+ * boundary-row launch and one batched crack launch (one wavefront per plate).
+ * Asynchronous. */
+int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* nsteps steps in ONE cooperative (persistent) launch: waves walk the task
+ * list of all plates with a grid stride; grid barriers separate the sweep, the
+ * crack step and the next sweep.  The barrier waits a bounded time; a time-out
+ * ends every wave and returns LBM_EHIP (the state is then invalid).
+ * Synchronises the stream. */
+int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps);
+
+/* Handle of plate k for queries (lbm_crack_state, lbm_sif, lbm_get_fields,
+ * ...); owned by the batch (no lbm_free, no lbm_step on it).  NULL if k is out
+ * of range. */
+lbm_handle *lbm_batch_plate(lbm_batch *b, int32_t k);
+
+/* Launch shape of the batched interior kernel (as lbm_set_launch) and the
+ * grid of the last persistent launch (blocks of 4 waves). */
+int lbm_batch_set_launch(lbm_batch *b, int32_t rows, int32_t waves, int32_t occupancy);
+int lbm_batch_get_launch(lbm_batch *b, int32_t *rows, int32_t *waves, int32_t *occupancy,
+                         int32_t *persistent_blocks);
+
+/* Whole-step timing with HIP events (per-step launches: one interval per
+ * step; persistent runs: one interval per run). */
+int lbm_batch_timing(lbm_batch *b, int32_t enable, double *ms, int64_t *n_timed);
+
+/* Total sites of all plates. */
+int64_t lbm_batch_sites(const lbm_batch *b);
+
+void lbm_batch_free(lbm_batch *b);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *lbm_last_error(void);

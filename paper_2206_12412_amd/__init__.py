@@ -1,9 +1,9 @@
 """MI355X (gfx950) lattice Boltzmann solver for antiplane shear with dynamic
 mode III cracks (arXiv:2206.12412), behind the C-ABI of include/lbm.h."""
-from .lbm import (BC_PERIODIC, BC_WALLS, EXPORTS, FLAG_GREW, FLAG_K_UNDEF, FLAG_WALL, GROW_NONE,
+from .lbm import (BC_PERIODIC, Batch, BC_WALLS, EXPORTS, FLAG_GREW, FLAG_K_UNDEF, FLAG_WALL, GROW_NONE,
                   GROW_PRESCRIBED, GROW_SIF, LIB_PATH, STORAGE, Config, CrackInfo, LBMError, Solver,
                   load_library, state_bytes)
 
-__all__ = ["BC_PERIODIC", "BC_WALLS", "EXPORTS", "FLAG_GREW", "FLAG_K_UNDEF", "FLAG_WALL",
+__all__ = ["BC_PERIODIC", "Batch", "BC_WALLS", "EXPORTS", "FLAG_GREW", "FLAG_K_UNDEF", "FLAG_WALL",
            "GROW_NONE", "GROW_PRESCRIBED", "GROW_SIF", "LIB_PATH", "STORAGE", "Config", "CrackInfo",
            "LBMError", "Solver", "load_library", "state_bytes"]

@@ -171,10 +171,11 @@ struct lbm_handle {
   int lds_per_cu = 65536;
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<hipEvent_t> ev_used;  // triples: before sweep, after sweep, after crack
-  double t_sweep = 0, t_crack = 0;
+  std::vector<hipEvent_t> ev_used;  // per step: before, after interior, after boundary, after crack
+  double t_int = 0, t_bnd = 0, t_crack = 0;
   int64_t n_timed = 0;
   lbmk::DevCrack host_crack{};
+  bool in_batch = false;  // stepped by a batch; lbm_step refuses it
 
   void *fbuf(int b) const { return base + L.off_f[b]; }
   void *wbuf(int b) const { return base + L.off_w[b]; }
@@ -205,12 +206,14 @@ hipEvent_t take_event(lbm_handle *h) {
 int harvest_timing(lbm_handle *h) {
   if (h->ev_used.empty()) return LBM_OK;
   HIP_TRY(hipStreamSynchronize(h->stream));
-  for (size_t k = 0; k + 2 < h->ev_used.size(); k += 3) {
-    float a = 0, b = 0;
+  for (size_t k = 0; k + 3 < h->ev_used.size(); k += 4) {
+    float a = 0, b = 0, c = 0;
     HIP_TRY(hipEventElapsedTime(&a, h->ev_used[k], h->ev_used[k + 1]));
     HIP_TRY(hipEventElapsedTime(&b, h->ev_used[k + 1], h->ev_used[k + 2]));
-    h->t_sweep += a;
-    h->t_crack += b;
+    HIP_TRY(hipEventElapsedTime(&c, h->ev_used[k + 2], h->ev_used[k + 3]));
+    h->t_int += a;
+    h->t_bnd += b;
+    h->t_crack += c;
     h->n_timed += 1;
   }
   for (hipEvent_t e : h->ev_used) h->ev_pool.push_back(e);
@@ -219,7 +222,7 @@ int harvest_timing(lbm_handle *h) {
 }
 
 template <typename S, typename W, typename C>
-int launch_sweep_typed(lbm_handle *h) {
+int launch_sweep_typed(lbm_handle *h, int part) {
   lbmk::SweepArgs<S, W, C> a{};
   const int nxt = 1 - h->cur;
   a.fin = static_cast<const S *>(h->fbuf(h->cur));
@@ -257,22 +260,22 @@ int launch_sweep_typed(lbm_handle *h) {
     a.skip_lo = 1;
     a.skip_hi = 0;
   }
-  HIP_TRY(lbmk::launch_sweep(h->store, &a, h->stream));
+  HIP_TRY(lbmk::launch_sweep(h->store, &a, part, h->stream));
   return LBM_OK;
 }
 
-int launch_sweep_any(lbm_handle *h) {
+int launch_sweep_any(lbm_handle *h, int part) {
   switch (h->store) {
-    case Store::F64: return launch_sweep_typed<double, double, double>(h);
-    case Store::F32_PLAIN: return launch_sweep_typed<float, float, float>(h);
-    case Store::F32S: return launch_sweep_typed<float, float, float>(h);
-    case Store::F16S: return launch_sweep_typed<_Float16, float, float>(h);
-    case Store::BF16S: return launch_sweep_typed<__bf16, float, float>(h);
+    case Store::F64: return launch_sweep_typed<double, double, double>(h, part);
+    case Store::F32_PLAIN: return launch_sweep_typed<float, float, float>(h, part);
+    case Store::F32S: return launch_sweep_typed<float, float, float>(h, part);
+    case Store::F16S: return launch_sweep_typed<_Float16, float, float>(h, part);
+    case Store::BF16S: return launch_sweep_typed<__bf16, float, float>(h, part);
   }
   return fail(LBM_EINVAL, "bad storage");
 }
 
-int launch_crack_step(lbm_handle *h) {
+lbmk::CrackArgs crack_args(const lbm_handle *h) {
   lbmk::CrackArgs a{};
   a.st = h->crack();
   a.w = h->wbuf(1 - h->cur);  // w after the sweep just enqueued
@@ -298,6 +301,11 @@ int launch_crack_step(lbm_handle *h) {
   a.c.x0 = h->cfg.crack_x0;
   a.c.trace_cap = h->cfg.trace_cap;
   a.c.event_cap = h->L.event_cap;
+  return a;
+}
+
+int launch_crack_step(lbm_handle *h) {
+  const lbmk::CrackArgs a = crack_args(h);
   HIP_TRY(lbmk::launch_crack(a, h->stream));
   return LBM_OK;
 }
@@ -430,29 +438,31 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
 
 int lbm_step(lbm_handle *h, int64_t nsteps) {
   if (!h) return fail(LBM_EINVAL, "null handle");
+  if (h->in_batch) return fail(LBM_ESTATE, "this plate is stepped by its batch (lbm_batch_step)");
   if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
   for (int64_t k = 0; k < nsteps; ++k) {
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (h->timing) {
-      e0 = take_event(h);
-      e1 = take_event(h);
-      e2 = take_event(h);
-      if (!e0 || !e1 || !e2) return fail(LBM_EHIP, "event creation failed");
-      HIP_TRY(hipEventRecord(e0, h->stream));
+      for (auto &e : ev) {
+        e = take_event(h);
+        if (!e) return fail(LBM_EHIP, "event creation failed");
+      }
+      HIP_TRY(hipEventRecord(ev[0], h->stream));
     }
-    int rc = launch_sweep_any(h);
+    int rc = launch_sweep_any(h, 0);
     if (rc != LBM_OK) return rc;
-    if (h->timing) HIP_TRY(hipEventRecord(e1, h->stream));
+    if (h->timing) HIP_TRY(hipEventRecord(ev[1], h->stream));
+    rc = launch_sweep_any(h, 1);
+    if (rc != LBM_OK) return rc;
+    if (h->timing) HIP_TRY(hipEventRecord(ev[2], h->stream));
     if (h->cfg.has_crack) {
       rc = launch_crack_step(h);
       if (rc != LBM_OK) return rc;
     }
     if (h->timing) {
-      HIP_TRY(hipEventRecord(e2, h->stream));
-      h->ev_used.push_back(e0);
-      h->ev_used.push_back(e1);
-      h->ev_used.push_back(e2);
-      if (h->ev_used.size() >= 3 * 4096) {
+      HIP_TRY(hipEventRecord(ev[3], h->stream));
+      for (auto &e : ev) h->ev_used.push_back(e);
+      if (h->ev_used.size() >= 4 * 4096) {
         rc = harvest_timing(h);
         if (rc != LBM_OK) return rc;
       }
@@ -595,15 +605,17 @@ int lbm_get_mask(lbm_handle *h, uint8_t *cutV, uint8_t *cutH) {
   return LBM_OK;
 }
 
-int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms, int64_t *n_timed) {
+int lbm_timing(lbm_handle *h, int32_t enable, double *interior_ms, double *boundary_ms,
+               double *crack_ms, int64_t *n_timed) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   int rc = harvest_timing(h);
   if (rc != LBM_OK) return rc;
-  if (sweep_ms) *sweep_ms = h->t_sweep;
+  if (interior_ms) *interior_ms = h->t_int;
+  if (boundary_ms) *boundary_ms = h->t_bnd;
   if (crack_ms) *crack_ms = h->t_crack;
   if (n_timed) *n_timed = h->n_timed;
   if (enable && !h->timing) {
-    h->t_sweep = h->t_crack = 0;
+    h->t_int = h->t_bnd = h->t_crack = 0;
     h->n_timed = 0;
   }
   h->timing = enable != 0;
@@ -630,6 +642,13 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
   return LBM_OK;
 }
 
+int64_t lbm_interior_sites(const lbm_handle *h) {
+  if (!h) return 0;
+  const int lo = h->cfg.has_crack ? h->plate.j0 : 1;
+  const int hi = h->cfg.has_crack ? h->plate.j0 + 1 : 0;
+  return lbmk::interior_sites(h->plate, lo, hi);
+}
+
 double lbm_bytes_per_site(const lbm_handle *h) {
   if (!h) return 0.0;
   const double e = (double)elem_size(h->store), we = (h->store == Store::F64) ? 8.0 : 4.0;
@@ -642,6 +661,327 @@ void lbm_free(lbm_handle *h) {
   for (hipEvent_t e : h->ev_used) hipEventDestroy(e);
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   delete h;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches --
+
+struct lbm_batch {
+  std::vector<lbm_handle *> plates;
+  Store store = Store::F32S;
+  hipStream_t stream = nullptr;
+  char *base = nullptr;
+  size_t off_desc = 0, off_tau = 0, off_sync = 0, total = 0;
+  std::vector<size_t> off_plate;
+  std::vector<size_t> off_tau_plate;
+  std::vector<lbmk::BatchPlate> desc;
+  int64_t n_int = 0, n_bnd = 0;
+  int rows = 1, waves = 4, occ = 0, lds_per_cu = 65536;
+  int cur = 0;
+  int64_t step = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool, ev_used;
+  double t_ms = 0;
+  int64_t n_timed = 0;
+  int persistent_blocks = 0;
+};
+
+namespace {
+
+struct BatchLayout {
+  std::vector<size_t> off_plate, off_tau_plate;
+  size_t off_desc = 0, off_tau = 0, off_sync = 0, total = 0;
+};
+
+int batch_layout(const lbm_config *cfgs, int32_t n, BatchLayout *B, Store *store) {
+  if (!cfgs || n < 1 || n > 65536) return fail(LBM_EINVAL, "a batch needs 1..65536 plates");
+  size_t o = 0;
+  for (int k = 0; k < n; ++k) {
+    Store s;
+    int rc = validate(&cfgs[k], &s);
+    if (rc != LBM_OK) return fail(rc, "plate %d: %s", k, g_err.c_str());
+    if (k == 0) *store = s;
+    else if (s != *store) return fail(LBM_EINVAL, "plate %d: every plate of a batch needs the same storage", k);
+    B->off_plate.push_back(o);
+    o += align_up(make_layout(cfgs[k], s).total, 256);
+  }
+  B->off_desc = o;
+  o += align_up(sizeof(lbmk::BatchPlate) * n, 256);
+  B->off_tau = o;
+  for (int k = 0; k < n; ++k) {
+    B->off_tau_plate.push_back(o);
+    o += align_up(sizeof(double) * (size_t)std::max<int64_t>(cfgs[k].n_hist, 1), 256);
+  }
+  B->off_sync = o;
+  o += 256;
+  B->total = o;
+  return LBM_OK;
+}
+
+int batch_build_desc(lbm_batch *b) {
+  const int n = (int)b->plates.size();
+  const int vec = lbmk::sweep_vec(b->store);
+  b->desc.assign(n, lbmk::BatchPlate{});
+  int64_t ti = 0, tb = 0;
+  for (int k = 0; k < n; ++k) {
+    const lbm_handle *h = b->plates[k];
+    lbmk::BatchPlate &d = b->desc[k];
+    d.f[0] = h->fbuf(0);
+    d.f[1] = h->fbuf(1);
+    d.w[0] = h->wbuf(0);
+    d.w[1] = h->wbuf(1);
+    d.mV = h->mV();
+    d.mH = h->mH();
+    d.mrows = h->mrows();
+    d.p = h->plate;
+    d.omega = h->cfg.omega;
+    d.dt = h->dt;
+    d.A0 = h->A0;
+    d.Ak = h->Ak;
+    d.coef = h->coef;
+    d.face = h->cfg.bc_mode == LBM_BC_PERIODIC ? 0.0 : h->cfg.face_traction;
+    d.tau = reinterpret_cast<const double *>(b->base + b->off_tau_plate[k]);
+    d.n_hist = (int64_t)h->tau.size();
+    d.has_crack = h->cfg.has_crack;
+    d.skip_lo = h->cfg.has_crack ? h->plate.j0 : 1;
+    d.skip_hi = h->cfg.has_crack ? h->plate.j0 + 1 : 0;
+    // the same task maps as the single-plate kernels (sweep_core.hpp)
+    const int sw = 64 * vec;
+    d.n_strips = (h->plate.nx + sw - 1) / sw;
+    d.rows = b->rows;
+    const bool has_skip = d.skip_lo <= d.skip_hi;
+    d.lo1 = 1;
+    d.hi1 = has_skip ? d.skip_lo - 1 : h->plate.ny - 2;
+    d.lo2 = has_skip ? d.skip_hi + 1 : h->plate.ny;
+    d.hi2 = h->plate.ny - 2;
+    d.nc1 = d.hi1 >= d.lo1 ? (d.hi1 - d.lo1 + d.rows) / d.rows : 0;
+    d.nc2 = d.hi2 >= d.lo2 ? (d.hi2 - d.lo2 + d.rows) / d.rows : 0;
+    d.nb = 0;
+    auto add = [&](int j) {
+      if (j < 0 || j >= h->plate.ny) return;
+      for (int q = 0; q < d.nb; ++q)
+        if (d.brow[q] == j) return;
+      d.brow[d.nb++] = j;
+    };
+    add(0);
+    add(h->plate.ny - 1);
+    for (int j = d.skip_lo; j <= d.skip_hi && d.nb < 4; ++j) add(j);
+    d.itask0 = ti;
+    d.btask0 = tb;
+    ti += (int64_t)d.n_strips * (d.nc1 + d.nc2);
+    tb += (int64_t)d.n_strips * d.nb;
+    d.crack = crack_args(h);
+  }
+  b->n_int = ti;
+  b->n_bnd = tb;
+  HIP_TRY(hipMemcpyAsync(b->base + b->off_desc, b->desc.data(), sizeof(lbmk::BatchPlate) * n,
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+void batch_sync_handles(lbm_batch *b) {
+  for (lbm_handle *h : b->plates) {
+    h->cur = b->cur;
+    h->step = b->step;
+  }
+}
+
+int batch_lds(const lbm_batch *b) {
+  if (b->occ <= 0) return 0;
+  const int groups = std::max(1, (b->occ * 4) / b->waves);
+  return std::min(65536, (b->lds_per_cu / groups) / 256 * 256);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_state_bytes(const lbm_config *cfgs, int32_t n) {
+  BatchLayout B;
+  Store s;
+  if (batch_layout(cfgs, n, &B, &s) != LBM_OK) return 0;
+  return B.total;
+}
+
+int lbm_batch_init(const lbm_config *cfgs, int32_t n, void *dev_buf, size_t dev_bytes, void *stream,
+                   lbm_batch **out) {
+  if (!out) return fail(LBM_EINVAL, "null output batch");
+  *out = nullptr;
+  BatchLayout B;
+  Store s;
+  int rc = batch_layout(cfgs, n, &B, &s);
+  if (rc != LBM_OK) return rc;
+  if (!dev_buf || reinterpret_cast<uintptr_t>(dev_buf) % 256)
+    return fail(LBM_EINVAL, "dev_buf must be a 256-byte aligned device pointer");
+  if (dev_bytes < B.total) return fail(LBM_ENOMEM, "dev_bytes %zu < required %zu", dev_bytes, B.total);
+  lbm_batch *b = new lbm_batch();
+  b->store = s;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->base = static_cast<char *>(dev_buf);
+  b->off_plate = B.off_plate;
+  b->off_tau_plate = B.off_tau_plate;
+  b->off_desc = B.off_desc;
+  b->off_tau = B.off_tau;
+  b->off_sync = B.off_sync;
+  b->total = B.total;
+  auto bail = [&](int code) {
+    for (lbm_handle *h : b->plates) lbm_free(h);
+    delete b;
+    return code;
+  };
+  for (int k = 0; k < n; ++k) {
+    lbm_config c = cfgs[k];
+    c.dev_buf = b->base + B.off_plate[k];
+    c.dev_bytes = (k + 1 < n ? B.off_plate[k + 1] : B.off_desc) - B.off_plate[k];
+    c.stream = stream;
+    lbm_handle *h = nullptr;
+    rc = lbm_init(&c, &h);
+    if (rc != LBM_OK) return bail(fail(rc, "plate %d: %s", k, g_err.c_str()));
+    h->in_batch = true;
+    b->plates.push_back(h);
+    if (!h->tau.empty() &&
+        hipMemcpy(b->base + B.off_tau_plate[k], h->tau.data(), sizeof(double) * h->tau.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(LBM_EHIP, "upload of the traction history failed"));
+  }
+  // launch shape: that of a plate of the batch's storage
+  b->rows = 1;
+  b->waves = b->plates[0]->waves;
+  b->occ = b->plates[0]->occ;
+  b->lds_per_cu = b->plates[0]->lds_per_cu;
+  rc = batch_build_desc(b);
+  if (rc != LBM_OK) return bail(rc);
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
+  if (!b) return fail(LBM_EINVAL, "null batch");
+  if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
+  const auto *d = reinterpret_cast<const lbmk::BatchPlate *>(b->base + b->off_desc);
+  const int lds = batch_lds(b);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (b->timing) {
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(LBM_EHIP, "event creation failed");
+      HIP_TRY(hipEventRecord(e0, b->stream));
+    }
+    HIP_TRY(lbmk::launch_batch_step(b->store, d, (int)b->plates.size(), b->n_int, b->n_bnd, b->cur,
+                                    b->step, b->waves, lds, b->stream));
+    if (b->timing) {
+      HIP_TRY(hipEventRecord(e1, b->stream));
+      b->ev_used.push_back(e0);
+      b->ev_used.push_back(e1);
+    }
+    b->cur = 1 - b->cur;
+    b->step++;
+  }
+  batch_sync_handles(b);
+  return LBM_OK;
+}
+
+int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps) {
+  if (!b) return fail(LBM_EINVAL, "null batch");
+  if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
+  if (nsteps == 0) return LBM_OK;
+  const auto *d = reinterpret_cast<const lbmk::BatchPlate *>(b->base + b->off_desc);
+  unsigned *sync = reinterpret_cast<unsigned *>(b->base + b->off_sync);
+  HIP_TRY(lbmk::launch_zero(sync, 256, b->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (b->timing) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      return fail(LBM_EHIP, "event creation failed");
+    HIP_TRY(hipEventRecord(e0, b->stream));
+  }
+  int blocks = 0;
+  hipError_t e = lbmk::launch_batch_persistent(b->store, d, (int)b->plates.size(), b->n_int, b->n_bnd,
+                                               b->cur, b->step, nsteps, sync, &blocks, b->stream);
+  if (e != hipSuccess) return fail(LBM_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
+  b->persistent_blocks = blocks;
+  if (b->timing) {
+    HIP_TRY(hipEventRecord(e1, b->stream));
+    b->ev_used.push_back(e0);
+    b->ev_used.push_back(e1);
+  }
+  unsigned flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, sync + 2, sizeof flag, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->cur = (int)((b->cur + nsteps) & 1);
+  b->step += nsteps;
+  batch_sync_handles(b);
+  if (flag) return fail(LBM_EHIP, "grid barrier timed out: the persistent run is invalid");
+  return LBM_OK;
+}
+
+lbm_handle *lbm_batch_plate(lbm_batch *b, int32_t k) {
+  if (!b || k < 0 || k >= (int32_t)b->plates.size()) {
+    fail(LBM_EINVAL, "no plate %d in this batch", k);
+    return nullptr;
+  }
+  return b->plates[k];
+}
+
+int lbm_batch_set_launch(lbm_batch *b, int32_t rows, int32_t waves, int32_t occupancy) {
+  if (!b) return fail(LBM_EINVAL, "null batch");
+  if (rows < 1 || rows > 4096) return fail(LBM_EINVAL, "rows must be in 1..4096");
+  if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(LBM_EINVAL, "waves must be 1, 2, 4 or 8");
+  if (occupancy < 0 || occupancy > 8) return fail(LBM_EINVAL, "occupancy must be in 0..8");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->rows = rows;
+  b->waves = waves;
+  b->occ = occupancy;
+  return batch_build_desc(b);
+}
+
+int lbm_batch_get_launch(lbm_batch *b, int32_t *rows, int32_t *waves, int32_t *occupancy,
+                         int32_t *persistent_blocks) {
+  if (!b) return fail(LBM_EINVAL, "null batch");
+  if (rows) *rows = b->rows;
+  if (waves) *waves = b->waves;
+  if (occupancy) *occupancy = b->occ;
+  if (persistent_blocks) *persistent_blocks = b->persistent_blocks;
+  return LBM_OK;
+}
+
+int lbm_batch_timing(lbm_batch *b, int32_t enable, double *ms, int64_t *n_timed) {
+  if (!b) return fail(LBM_EINVAL, "null batch");
+  if (!b->ev_used.empty()) {
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (size_t k = 0; k + 1 < b->ev_used.size(); k += 2) {
+      float t = 0;
+      HIP_TRY(hipEventElapsedTime(&t, b->ev_used[k], b->ev_used[k + 1]));
+      b->t_ms += t;
+      b->n_timed += 1;
+    }
+    for (hipEvent_t e : b->ev_used) hipEventDestroy(e);
+    b->ev_used.clear();
+  }
+  if (ms) *ms = b->t_ms;
+  if (n_timed) *n_timed = b->n_timed;
+  if (enable && !b->timing) {
+    b->t_ms = 0;
+    b->n_timed = 0;
+  }
+  b->timing = enable != 0;
+  return LBM_OK;
+}
+
+int64_t lbm_batch_sites(const lbm_batch *b) {
+  if (!b) return 0;
+  int64_t s = 0;
+  for (const lbm_handle *h : b->plates) s += (int64_t)h->plate.nx * h->plate.ny;
+  return s;
+}
+
+void lbm_batch_free(lbm_batch *b) {
+  if (!b) return;
+  if (!b->ev_used.empty()) hipStreamSynchronize(b->stream);
+  for (hipEvent_t e : b->ev_used) hipEventDestroy(e);
+  for (lbm_handle *h : b->plates) lbm_free(h);
+  delete b;
 }
 
 }  // extern "C"

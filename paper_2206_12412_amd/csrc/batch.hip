@@ -1,0 +1,248 @@
+// Batched plates: many independent plates of uneven sizes, loads and crack
+// rules stepped together.  Each plate keeps its own state block and its own
+// task map; a global task index runs over the interior tasks of all plates,
+// then over their boundary tasks, and the plate of a task is found by a
+// binary search over the plates' first task indices.  Per-site arithmetic is
+// the single-plate code (sweep_core.hpp, crack_core.hpp), so a plate of a
+// batch evolves bit for bit as it does alone.
+//
+// Two ways to run a step:
+//   per-step launches: one batched interior kernel, one batched boundary
+//     kernel and one batched crack kernel (one wavefront per plate);
+//   persistent: one cooperative launch runs many steps; every wave walks the
+//     task list with a grid stride, and two grid barriers per step separate
+//     the sweep from the crack step and the crack step from the next sweep.
+//     The barrier spins on a generation counter with a bounded number of
+//     tries: on time-out it raises an error flag, after which no barrier
+//     waits, so every wave always reaches the end of the kernel.
+#include "crack_core.hpp"
+#include "sweep_core.hpp"
+
+namespace lbmk {
+namespace {
+
+__device__ __forceinline__ int plate_of(const BatchPlate *__restrict__ d, int n, int64_t task,
+                                        bool interior) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {  // last plate whose first task is <= task
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t first = interior ? d[mid].itask0 : d[mid].btask0;
+    if (first <= task) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename S, typename W, typename C>
+__device__ __forceinline__ SweepArgs<S, W, C> args_of(const BatchPlate &d, int cur, int64_t step) {
+  SweepArgs<S, W, C> a;
+  a.fin = static_cast<const S *>(d.f[cur]);
+  a.fout = static_cast<S *>(const_cast<void *>(d.f[1 - cur]));
+  a.win = static_cast<const W *>(d.w[cur]);
+  a.wout = static_cast<W *>(const_cast<void *>(d.w[1 - cur]));
+  a.mV = d.mV;
+  a.mH = d.mH;
+  a.mrows = d.mrows;
+  a.p = d.p;
+  a.omega = (C)d.omega;
+  a.dt = (C)d.dt;
+  a.A0 = (C)d.A0;
+  a.Ak = (C)d.Ak;
+  const double tau = d.n_hist > 0 ? d.tau[step < d.n_hist ? step : d.n_hist - 1] : 0.0;
+  a.t_top = d.p.periodic ? C(0) : (C)(d.coef * tau);
+  a.t_bot = d.p.periodic ? C(0) : (C)(d.coef * -tau);
+  a.t_up = d.p.periodic ? C(0) : (C)(d.coef * d.face);
+  a.t_lo = d.p.periodic ? C(0) : (C)(d.coef * -d.face);
+  a.rows = d.rows;
+  a.waves = 4;
+  a.lds_bytes = 0;
+  a.skip_lo = d.skip_lo;
+  a.skip_hi = d.skip_hi;
+  return a;
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+__device__ __forceinline__ void interior_task(const BatchPlate *__restrict__ d, int n, int64_t task,
+                                              int cur, int64_t step) {
+  const int k = plate_of(d, n, task, true);
+  const BatchPlate &q = d[k];
+  const int64_t local = task - q.itask0;
+  const int strip = (int)(local % q.n_strips);
+  const int chunk = (int)(local / q.n_strips);
+  int jb, jlast;
+  if (chunk < q.nc1) {
+    jb = q.lo1 + chunk * q.rows;
+    jlast = min(jb + q.rows - 1, q.hi1);
+  } else {
+    jb = q.lo2 + (chunk - q.nc1) * q.rows;
+    jlast = min(jb + q.rows - 1, q.hi2);
+  }
+  if (jb > jlast) return;
+  const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
+  core::interior_rows<S, W, C, VEC, SHIFT>(a.fin, a.fout, a.win, a.wout, a, strip, jb, jlast);
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+__device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, int n, int64_t task,
+                                              int cur, int64_t step) {
+  const int k = plate_of(d, n, task, false);
+  const BatchPlate &q = d[k];
+  const int64_t local = task - q.btask0;
+  const int strip = (int)(local % q.n_strips);
+  const int r = (int)(local / q.n_strips);
+  const int j = q.brow[r];
+  const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
+  core::boundary_row<S, W, C, VEC, SHIFT>(a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a,
+                                         strip, j);
+}
+
+__device__ __forceinline__ void crack_task(const BatchPlate *__restrict__ d, int k, int cur) {
+  if (!d[k].has_crack) return;
+  CrackArgs c = d[k].crack;
+  c.w = d[k].w[1 - cur];  // w after the sweep of this step
+  core::crack_step_wave(c);
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+__global__ void __launch_bounds__(512)
+batch_interior(const BatchPlate *__restrict__ d, int n, int64_t n_tasks, int cur, int64_t step,
+               int waves) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t task = (int64_t)blockIdx.x * waves + wave;
+  if (task >= n_tasks) return;
+  interior_task<S, W, C, VEC, SHIFT>(d, n, task, cur, step);
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+__global__ void __launch_bounds__(256)
+batch_boundary(const BatchPlate *__restrict__ d, int n, int64_t n_tasks, int cur, int64_t step) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t task = (int64_t)blockIdx.x * 4 + wave;
+  if (task >= n_tasks) return;
+  boundary_task<S, W, C, VEC, SHIFT>(d, n, task, cur, step);
+}
+
+__global__ void __launch_bounds__(256) batch_crack(const BatchPlate *__restrict__ d, int n, int cur) {
+  const int k = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (k >= n) return;
+  crack_task(d, k, cur);
+}
+
+// Grid-wide barrier: sync[0] counts arrivals, sync[1] is the generation,
+// sync[2] the time-out flag.
+__device__ __forceinline__ void grid_barrier(unsigned *sync, unsigned nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      const unsigned gen = __hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      const unsigned arrived = atomicAdd(&sync[0], 1u);
+      if (arrived == nblocks - 1) {
+        __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        unsigned tries = 0;
+        while (__hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++tries > (1u << 24) ||
+              __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            atomicExch(&sync[2], 1u);
+            break;
+          }
+        }
+      }
+      __threadfence();
+    }
+  }
+  __syncthreads();
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+__global__ void __launch_bounds__(256)
+batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t n_bnd, int cur0,
+                 int64_t step0, int64_t nsteps, unsigned *sync) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const int cur = (int)((cur0 + s) & 1);
+    const int64_t step = step0 + s;
+    for (int64_t t = gw; t < n_int + n_bnd; t += nw) {
+      if (t < n_int) interior_task<S, W, C, VEC, SHIFT>(d, n, t, cur, step);
+      else boundary_task<S, W, C, VEC, SHIFT>(d, n, t - n_int, cur, step);
+    }
+    grid_barrier(sync, gridDim.x);
+    for (int64_t k = gw; k < n; k += nw) crack_task(d, (int)k, cur);
+    grid_barrier(sync, gridDim.x);
+  }
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+hipError_t step_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur, int64_t step,
+                  int waves, int lds, hipStream_t st) {
+  if (n_int > 0) {
+    const unsigned blocks = (unsigned)((n_int + waves - 1) / waves);
+    hipLaunchKernelGGL((batch_interior<S, W, C, VEC, SHIFT>), dim3(blocks), dim3(64 * waves), lds, st,
+                       d, n, n_int, cur, step, waves);
+  }
+  if (n_bnd > 0) {
+    const unsigned blocks = (unsigned)((n_bnd + 3) / 4);
+    hipLaunchKernelGGL((batch_boundary<S, W, C, VEC, SHIFT>), dim3(blocks), dim3(256), 0, st, d, n,
+                       n_bnd, cur, step);
+  }
+  hipLaunchKernelGGL(batch_crack, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, d, n, cur);
+  return hipGetLastError();
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+hipError_t persistent_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
+                        int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
+                        hipStream_t st) {
+  auto kernel = batch_persistent<S, W, C, VEC, SHIFT>;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), 256, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
+  const int64_t want = (n_int + n_bnd + 3) / 4;
+  int blocks = per_cu * cus;
+  if (want < blocks) blocks = (int)(want > 0 ? want : 1);
+  *blocks_used = blocks;
+  void *args[] = {(void *)&d, (void *)&n, (void *)&n_int, (void *)&n_bnd, (void *)&cur,
+                  (void *)&step, (void *)&nsteps, (void *)&sync};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), dim3(blocks), dim3(256),
+                                    args, 0, st);
+}
+
+}  // namespace
+
+hipError_t launch_batch_step(Store s, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+                             int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
+                             hipStream_t st) {
+  switch (s) {
+    case Store::F64: return step_t<double, double, double, 2, false>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F32_PLAIN: return step_t<float, float, float, 4, false>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F32S: return step_t<float, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F16S: return step_t<_Float16, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::BF16S: return step_t<__bf16, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_persistent(Store s, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+                                   int64_t n_bnd_tasks, int cur, int64_t step, int64_t nsteps,
+                                   unsigned *sync, int *blocks_used, hipStream_t st) {
+  switch (s) {
+    case Store::F64: return persistent_t<double, double, double, 2, false>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F32_PLAIN: return persistent_t<float, float, float, 4, false>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F32S: return persistent_t<float, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F16S: return persistent_t<_Float16, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::BF16S: return persistent_t<__bf16, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbmk

@@ -89,16 +89,52 @@ struct CrackArgs {
   CrackParams c;
 };
 
+// One plate of a batch as the batched kernels see it (device memory).  The
+// per-step values (buffer parity, step index) come with each launch.
+struct BatchPlate {
+  const void *f[2];     // population buffers (plane 0), indexed by parity
+  const void *w[2];     // w buffers, indexed by parity
+  const uint32_t *mV, *mH;
+  MaskRows *mrows;
+  Plate p;
+  double omega, dt, A0, Ak, coef;
+  double face;          // crack-face traction (0 in periodic mode)
+  const double *tau;    // device copy of the traction history
+  int64_t n_hist;
+  int has_crack, skip_lo, skip_hi;
+  // task maps (same fields as the single-plate maps)
+  int n_strips, rows, lo1, hi1, lo2, hi2, nc1, nc2;
+  int nb, brow[4];
+  int64_t itask0, btask0;  // first interior / boundary task of this plate in the batch
+  CrackArgs crack;      // w is set per step from the parity
+};
+
 // ---- launchers (sweep.hip) ----
 enum class Store { F64, F32_PLAIN, F32S, F16S, BF16S };
 
 int sweep_vec(Store s);  // sites per lane
-hipError_t launch_sweep(Store s, const void *args, hipStream_t st);
+// part 0: the interior kernel, part 1: the boundary-row kernel
+hipError_t launch_sweep(Store s, const void *args, int part, hipStream_t st);
+// sites the interior kernel updates
+int64_t interior_sites(const Plate &p, int skip_lo, int skip_hi);
 
 // ---- launchers (crack.hip) ----
 hipError_t launch_crack(const CrackArgs &a, hipStream_t st);
 hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const Plate &p,
                             int has_crack, double x0, double a0, hipStream_t st);
+
+// ---- launchers (batch.hip) ----
+// One step of every plate: batched interior kernel, batched boundary kernel,
+// batched crack kernel.  cur = parity of the source buffers, step = step index.
+hipError_t launch_batch_step(Store s, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+                             int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
+                             hipStream_t st);
+// nsteps steps in one cooperative launch with grid barriers; sync[0..3] is a
+// zeroed device scratch (barrier counter, generation, error flag).  Returns
+// hipErrorCooperativeLaunchTooLarge if the grid cannot be co-resident.
+hipError_t launch_batch_persistent(Store s, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+                                   int64_t n_bnd_tasks, int cur, int64_t step, int64_t nsteps,
+                                   unsigned *sync, int *blocks_used, hipStream_t st);
 
 // ---- launchers (io.hip) ----
 // Initial populations and w of rows [row0, row0 + nrows) from FP64 staging

@@ -1,505 +1,78 @@
-// Fused collide-stream sweep of the D2Q5 wave-equation LBM for gfx950.
-//
-// One step updates every site (paper Sec. 3): pull-stream with bounce-back on
-// severed or outside links (eq. LBE, streaming part; Sec. 4.1 "no information
-// is exchanged" along a severed link), wdot = sum of the populations
-// (eq. distrib-macro), w += dt wdot (eq. integration), BGK collision towards
-// f_eq(w, wdot) (eq. LBE, f-eq).
-//
-// Layout: populations structure-of-arrays, plane a at fin + a * plane, rows of
-// `pitch` elements (multiple of 64, 256-byte aligned); w in its own plane;
-// populations and w are double-buffered (source -> destination).  In-plane
-// byte offsets are 32-bit (a plane spans < 4 GiB) and every plane base is
-// wave-uniform, so loads and stores can use the scalar-base addressing mode.
-//
-// Work split: a wave owns a strip of 64 * VEC consecutive sites of a row; lane
-// l holds sites i0 .. i0 + VEC - 1, i0 = strip * 64 * VEC + l * VEC, so every
-// plane row is read and written with one 16-byte (8-byte for 16-bit storage)
-// access per lane.  x-neighbours across lanes come from DPP wave shifts
-// (v_mov_b32_dpp wave_shr / wave_shl); the strip-edge elements come from one
-// per-row halo load whose lanes 0..2 carry them (read back with readlane).
-//
-// Two kernels share a step and write disjoint sites:
-//   interior: rows 1 .. ny-2 without the rows next to severable links, where
-//     every vertical link is intact; only the left/right plate edges (or the
-//     periodic wrap) need per-lane fix-ups, and it marches `rows` rows per
-//     wave keeping rows j-1, j of w in registers;
-//   boundary: the edge rows and the crack rows; bounce-back, traction, the
-//     per-link cut bitmask (read only in the rows the mask-row range names)
-//     and periodic wrap-around.
-#include <algorithm>
-
-#include "lbm_internal.hpp"
+// Single-plate sweep kernels and their launchers.  A step launches the
+// interior kernel (interior rows, no bounce-back code) and the boundary-row
+// kernel (edge rows and crack rows); both read the source buffers and write
+// disjoint sites of the destination buffers.  The arithmetic lives in
+// sweep_core.hpp.
+#include "sweep_core.hpp"
 
 namespace lbmk {
 namespace {
 
-template <typename S, int N>
-struct alignas(N * sizeof(S)) Pack {
-  S v[N];
-};
-
-__device__ __forceinline__ float to_c(float x) { return x; }
-__device__ __forceinline__ double to_c(double x) { return x; }
-__device__ __forceinline__ float to_c(_Float16 x) { return static_cast<float>(x); }
-__device__ __forceinline__ float to_c(__bf16 x) { return static_cast<float>(x); }
-
-template <typename S> __device__ __forceinline__ S from_c(float x);
-template <> __device__ __forceinline__ float from_c<float>(float x) { return x; }
-template <> __device__ __forceinline__ _Float16 from_c<_Float16>(float x) { return static_cast<_Float16>(x); }
-template <> __device__ __forceinline__ __bf16 from_c<__bf16>(float x) { return static_cast<__bf16>(x); }
-template <typename S> __device__ __forceinline__ S from_c(double x);
-template <> __device__ __forceinline__ double from_c<double>(double x) { return x; }
-
-// Lane l receives the value of lane l-1 (lane 0 receives 0).
-__device__ __forceinline__ float lane_prev(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
-}
-// Lane l receives the value of lane l+1 (lane 63 receives 0).
-__device__ __forceinline__ float lane_next(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
-}
-__device__ __forceinline__ double lane_prev(double x) {
-  int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double lane_next(double x) {
-  int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-// Value of lane k, broadcast (k is a compile-time constant here).
-__device__ __forceinline__ float lane_value(float x, int k) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
-}
-__device__ __forceinline__ double lane_value(double x, int k) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), k);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), k);
-  return __hiloint2double(hi, lo);
-}
-
-// base + off with the byte offset formed in 32 bits (a plane spans < 4 GiB), so
-// that a uniform base and a 32-bit per-lane offset address the access
-template <typename S>
-__device__ __forceinline__ const S *at(const S *base, uint32_t off) {
-  return reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + off * (uint32_t)sizeof(S));
-}
-template <typename S>
-__device__ __forceinline__ S *at(S *base, uint32_t off) {
-  return reinterpret_cast<S *>(reinterpret_cast<char *>(base) + off * (uint32_t)sizeof(S));
-}
-
-template <typename S, typename C, int VEC>
-__device__ __forceinline__ void load_row(const S *__restrict__ base, uint32_t off, C (&out)[VEC]) {
-  const Pack<S, VEC> pk = *reinterpret_cast<const Pack<S, VEC> *>(at(base, off));
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) out[k] = to_c(pk.v[k]);
-}
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-// Rows are written once per step and read back only in the next step, after
-// the whole plate has streamed through the caches: store them non-temporally.
-template <typename S, typename C, int VEC>
-__device__ __forceinline__ void store_row(S *__restrict__ base, uint32_t off, const C (&in)[VEC]) {
-  Pack<S, VEC> pk;
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) pk.v[k] = from_c<S>(in[k]);
-  S *ptr = at(base, off);
-  if constexpr (sizeof(pk) % 16 == 0) {
-#pragma unroll
-    for (int c = 0; c < (int)(sizeof(pk) / 16); ++c) {
-      u32x4 v;
-      __builtin_memcpy(&v, reinterpret_cast<const char *>(&pk) + 16 * c, 16);
-      __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(ptr) + c);
-    }
-  } else {
-    static_assert(sizeof(pk) == 8, "rows are stored in 8- or 16-byte pieces");
-    u32x2 v;
-    __builtin_memcpy(&v, &pk, 8);
-    __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(ptr));
-  }
-}
-
-template <typename C, int VEC>
-__device__ __forceinline__ void zero_row(C (&out)[VEC]) {
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) out[k] = C(0);
-}
-
-__device__ __forceinline__ bool in_range(int j, int lo, int hi) { return j >= lo && j <= hi; }
-
-// One site: wdot, Euler update and collision from the pulled populations.
-// gl, gr, gd, gu are the values pulled along +x, -x, +y, -y (already bounced
-// where the link is severed); for shifted storage wl .. wup are the w of the
-// emitting sites (w0 where bounced); bd / bu say that the +y / -y pull bounced
-// and then carries the traction term td / tu.
-//
-// SHIFT = false: the stored values are the post-collision populations f
-// themselves (FP64 and plain FP32), evaluated in the paper's order of
-// operations without contraction.  SHIFT = true: the stored values are
-// g = f - E(w_emit), E the static equilibrium (E^0 = -A0 w, E^k = Ak w) of
-// the emitting site; wdot and the collision are the same arithmetic regrouped
-// in these variables so that no large term cancels in FP32 (A0 = 4 Ak).
-template <typename C, bool SHIFT, typename A>
-__device__ __forceinline__ void site_update(const A &a, C f0, C gl, C gr, C gd, C gu, C w0, C wl,
-                                            C wr, C wdn, C wup, bool bd, bool bu, C td, C tu,
-                                            C &o0, C &o1, C &o2, C &o3, C &o4, C &wo) {
-  if constexpr (SHIFT) {
-#pragma clang fp contract(fast)
-    const C wd = f0 + ((gl + gr) + (gd + gu)) +
-                 a.Ak * (((wl - w0) + (wr - w0)) + ((wdn - w0) + (wup - w0))) + (td + tu);
-    const C wn = w0 + a.dt * wd;
-    const C om1 = C(1) - a.omega;
-    o0 = om1 * (f0 + a.A0 * (wn - w0)) + a.omega * wd;
-    o1 = om1 * (gl + a.Ak * (wl - wn));
-    o2 = om1 * (gd + a.Ak * (wdn - wn) + td);
-    o3 = om1 * (gr + a.Ak * (wr - wn));
-    o4 = om1 * (gu + a.Ak * (wup - wn) + tu);
-    wo = wn;
-  } else {
-#pragma clang fp contract(off)
-    const C fi2 = bd ? gd + td : gd;
-    const C fi4 = bu ? gu + tu : gu;
-    const C wd = f0 + gl + fi2 + gr + fi4;
-    const C wn = w0 + a.dt * wd;
-    const C e0 = wd - a.A0 * wn;
-    const C ek = a.Ak * wn;
-    o0 = f0 - a.omega * (f0 - e0);
-    o1 = gl - a.omega * (gl - ek);
-    o2 = fi2 - a.omega * (fi2 - ek);
-    o3 = gr - a.omega * (gr - ek);
-    o4 = fi4 - a.omega * (fi4 - ek);
-    wo = wn;
-  }
-}
-
-// ----------------------------------------------------------------- interior --
-// Every strip of the rows 1 .. ny-2 except the rows next to severable links.
-// Vertical links are all intact here; the left and right plate edges (or the
-// periodic wrap) and the ragged end of the last strip are per-lane fix-ups.
 template <typename S, typename W, typename C, int VEC, bool SHIFT>
 __global__ void __launch_bounds__(512)
 sweep_interior(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict__ win,
-               W *__restrict__ wout, const SweepArgs<S, W, C> a) {
-  const Plate p = a.p;
-  const int lane = threadIdx.x & 63;
+               W *__restrict__ wout, const SweepArgs<S, W, C> a, const core::InteriorMap m) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  constexpr int SW = 64 * VEC;
-  const int n_strips = (p.nx + SW - 1) / SW;
-  // interior rows: 1 .. skip_lo-1 and skip_hi+1 .. ny-2, cut into chunks
-  const bool has_skip = a.skip_lo <= a.skip_hi;
-  const int lo1 = 1, hi1 = has_skip ? a.skip_lo - 1 : p.ny - 2;
-  const int lo2 = has_skip ? a.skip_hi + 1 : p.ny;
-  const int hi2 = p.ny - 2;
-  const int nc1 = hi1 >= lo1 ? (hi1 - lo1 + a.rows) / a.rows : 0;
   const int task = blockIdx.x * a.waves + wave;
-  const int strip = task % n_strips;
-  const int chunk = task / n_strips;
+  const int strip = task % m.n_strips;
+  const int chunk = task / m.n_strips;
   int jb, jlast;
-  if (chunk < nc1) {
-    jb = lo1 + chunk * a.rows;
-    jlast = min(jb + a.rows - 1, hi1);
+  if (chunk < m.nc1) {
+    jb = m.lo1 + chunk * m.rows;
+    jlast = min(jb + m.rows - 1, m.hi1);
   } else {
-    jb = lo2 + (chunk - nc1) * a.rows;
-    jlast = min(jb + a.rows - 1, hi2);
+    jb = m.lo2 + (chunk - m.nc1) * m.rows;
+    jlast = min(jb + m.rows - 1, m.hi2);
   }
   if (jb > jlast) return;
-  const int last = p.nx - 1;
-  const int is = strip * SW;
-  const int i0 = is + lane * VEC;
-  const bool act = i0 < p.nx;
-  const uint32_t il = act ? i0 : is;  // inactive lanes read their strip's first vector
-  const bool left_edge = strip == 0;          // holds site 0
-  const bool right_edge = is + SW > last;     // holds site nx-1 (and maybe padding)
-  const uint32_t pitch = p.pitch;
-  const size_t P = p.plane;
-  const S *__restrict__ F0 = fin;
-  const S *__restrict__ F1 = fin + P;
-  const S *__restrict__ F2 = fin + 2 * P;
-  const S *__restrict__ F3 = fin + 3 * P;
-  const S *__restrict__ F4 = fin + 4 * P;
-  // halo: lane 0 the site left of the strip (plane 1; the periodic wrap for
-  // the first strip), lane 1 the site right of it (plane 3), lane 2 site 0
-  // (plane 3: the periodic neighbour of the last site)
-  const S *__restrict__ Fh = (lane == 0) ? F1 : F3;
-  const uint32_t hx = (lane == 0) ? (is > 0 ? is - 1 : (p.periodic ? last : 0))
-                                  : (lane == 1 && is + SW <= last ? is + SW : 0);
-
-  C wm[VEC], wc[VEC];
-  if (SHIFT) {
-    load_row<W, C, VEC>(win, (uint32_t)jb * pitch + il, wc);
-    load_row<W, C, VEC>(win, (uint32_t)(jb - 1) * pitch + il, wm);
-  }
-  for (int j = jb; j <= jlast; ++j) {
-    const uint32_t o = (uint32_t)j * pitch + il;
-    C f0[VEC], f1[VEC], f3[VEC], f2d[VEC], f4u[VEC], wp[VEC], wself[VEC];
-    load_row<S, C, VEC>(F0, o, f0);
-    load_row<S, C, VEC>(F1, o, f1);
-    load_row<S, C, VEC>(F3, o, f3);
-    load_row<S, C, VEC>(F2, o - pitch, f2d);
-    load_row<S, C, VEC>(F4, o + pitch, f4u);
-    if (SHIFT) load_row<W, C, VEC>(win, o + pitch, wp);
-    else load_row<W, C, VEC>(win, o, wself);
-    const uint32_t ho = (uint32_t)j * pitch + hx;
-    const C hs = to_c(*at(Fh, ho));
-    C hw = C(0);
-    if (SHIFT) hw = to_c(*at(win, ho));
-
-    // pulled x-neighbours of every site: gl[k] along +x, gr[k] along -x
-    C gl[VEC], gr[VEC], wl[VEC], wr[VEC];
-    {
-      const C f1L = lane_prev(f1[VEC - 1]);
-      const C f3R = lane_next(f3[0]);
-      const C s_left = lane_value(hs, 0), s_right = lane_value(hs, 1);
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        gl[k] = (k == 0) ? ((lane == 0) ? s_left : f1L) : f1[k - 1];
-        gr[k] = (k == VEC - 1) ? ((lane == 63) ? s_right : f3R) : f3[k + 1];
-      }
-      if (SHIFT) {
-        const C wL = lane_prev(wc[VEC - 1]);
-        const C wR = lane_next(wc[0]);
-        const C w_left = lane_value(hw, 0), w_right = lane_value(hw, 1);
-#pragma unroll
-        for (int k = 0; k < VEC; ++k) {
-          wl[k] = (k == 0) ? ((lane == 0) ? w_left : wL) : wc[k - 1];
-          wr[k] = (k == VEC - 1) ? ((lane == 63) ? w_right : wR) : wc[k + 1];
-        }
-      }
-      // the left edge bounces site 0 (or wraps to nx-1, which the halo holds)
-      if (left_edge && !p.periodic && lane == 0) {
-        gl[0] = f3[0];
-        if (SHIFT) wl[0] = wc[0];
-      }
-      // the right edge bounces site nx-1 or wraps to site 0
-      if (right_edge) {
-        const C s_wrap = lane_value(hs, 2);
-        const C w_wrap = SHIFT ? lane_value(hw, 2) : C(0);
-#pragma unroll
-        for (int k = 0; k < VEC; ++k) {
-          if (i0 + k == last) {
-            gr[k] = p.periodic ? s_wrap : f1[k];
-            if (SHIFT) wr[k] = p.periodic ? w_wrap : wc[k];
-          }
-        }
-      }
-    }
-
-    C o0[VEC], o1[VEC], o2[VEC], o3[VEC], o4[VEC], wo[VEC];
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      const C w0 = SHIFT ? wc[k] : wself[k];
-      const C wdn = SHIFT ? wm[k] : w0;
-      const C wup = SHIFT ? wp[k] : w0;
-      site_update<C, SHIFT>(a, f0[k], gl[k], gr[k], f2d[k], f4u[k], w0, SHIFT ? wl[k] : w0,
-                            SHIFT ? wr[k] : w0, wdn, wup, false, false, C(0), C(0), o0[k], o1[k],
-                            o2[k], o3[k], o4[k], wo[k]);
-    }
-    if (right_edge) {
-#pragma unroll
-      for (int k = 0; k < VEC; ++k)
-        if (i0 + k > last) o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
-    }
-    if (act) {
-      store_row<S, C, VEC>(fout, o, o0);
-      store_row<S, C, VEC>(fout + P, o, o1);
-      store_row<S, C, VEC>(fout + 2 * P, o, o2);
-      store_row<S, C, VEC>(fout + 3 * P, o, o3);
-      store_row<S, C, VEC>(fout + 4 * P, o, o4);
-      store_row<W, C, VEC>(wout, o, wo);
-    }
-    if (SHIFT) {
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        wm[k] = wc[k];
-        wc[k] = wp[k];
-      }
-    }
-  }
+  core::interior_rows<S, W, C, VEC, SHIFT>(fin, fout, win, wout, a, strip, jb, jlast);
 }
 
-// ----------------------------------------------------------------- boundary --
-// Every strip of the boundary rows brow (the edge rows and the crack rows).
 template <typename S, typename W, typename C, int VEC, bool SHIFT>
 __global__ void __launch_bounds__(256)
 sweep_boundary(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict__ win,
                W *__restrict__ wout, const uint32_t *__restrict__ mV,
                const uint32_t *__restrict__ mH, const MaskRows *__restrict__ mrows,
-               const SweepArgs<S, W, C> a, const int4 brow, const int n_brow) {
-  const Plate p = a.p;
-  const int lane = threadIdx.x & 63;
+               const SweepArgs<S, W, C> a, const core::BoundaryMap m) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  constexpr int SW = 64 * VEC;
-  const int n_strips = (p.nx + SW - 1) / SW;
   const int task = blockIdx.x * 4 + wave;
-  if (task >= n_strips * n_brow) return;
-  const int r = task / n_strips;
-  const int j = r == 0 ? brow.x : (r == 1 ? brow.y : (r == 2 ? brow.z : brow.w));
-  const int strip = task % n_strips;
-  const int is = strip * SW;
-  const int i0 = is + lane * VEC;
-  const bool act = i0 < p.nx;
-  const uint32_t il = act ? i0 : is;  // inactive lanes read their strip's first vector
-  const int last = p.nx - 1;
-  const uint32_t pitch = p.pitch;
-  const size_t P = p.plane;
-  const MaskRows mr = *mrows;
-  const int jm = j > 0 ? j - 1 : (p.periodic ? p.ny - 1 : -1);
-  const int jp = j < p.ny - 1 ? j + 1 : (p.periodic ? 0 : -1);
-  const uint32_t o = (uint32_t)j * pitch + il;
-  const uint32_t rj = (uint32_t)j * pitch;
-
-  C f0[VEC], f1[VEC], f3[VEC], f2d[VEC], f4u[VEC], f2own[VEC], f4own[VEC];
-  C wc[VEC], wm[VEC], wp[VEC];
-  load_row<S, C, VEC>(fin, o, f0);
-  load_row<S, C, VEC>(fin + P, o, f1);
-  load_row<S, C, VEC>(fin + 3 * P, o, f3);
-  load_row<W, C, VEC>(win, o, wc);
-  if (jm >= 0) {
-    load_row<S, C, VEC>(fin + 2 * P, (uint32_t)jm * pitch + il, f2d);
-    if (SHIFT) load_row<W, C, VEC>(win, (uint32_t)jm * pitch + il, wm);
-    else zero_row(wm);
-  } else {
-    zero_row(f2d);
-    zero_row(wm);
-  }
-  if (jp >= 0) {
-    load_row<S, C, VEC>(fin + 4 * P, (uint32_t)jp * pitch + il, f4u);
-    if (SHIFT) load_row<W, C, VEC>(win, (uint32_t)jp * pitch + il, wp);
-    else zero_row(wp);
-  } else {
-    zero_row(f4u);
-    zero_row(wp);
-  }
-  // own-row f^2 / f^4 for the bounced vertical pulls
-  const bool up_mask = in_range(j, mr.vlo, mr.vhi);
-  const bool dn_mask = jm >= 0 && in_range(jm, mr.vlo, mr.vhi);
-  if (jp < 0 || up_mask) load_row<S, C, VEC>(fin + 2 * P, o, f2own);
-  else zero_row(f2own);
-  if (jm < 0 || dn_mask) load_row<S, C, VEC>(fin + 4 * P, o, f4own);
-  else zero_row(f4own);
-  // halo: lane 0 left of the strip (or the periodic wrap), lane 1 right of
-  // the strip, lane 2 site 0 (the periodic neighbour of the last site)
-  const int hl = is > 0 ? is - 1 : (p.periodic ? last : 0);
-  const int hr = is + SW <= last ? is + SW : 0;
-  const uint32_t hx = (lane == 0) ? hl : (lane == 1 ? hr : 0);
-  const S *__restrict__ Fh = (lane == 0) ? fin + P : fin + 3 * P;
-  const C hs = to_c(*at(Fh, rj + hx));
-  const C hw = to_c(*at(win, rj + hx));
-  // severed-link bits of the lane's sites (bit k = site i0 + k)
-  const uint32_t lanebits = (1u << VEC) - 1u;
-  uint32_t bup = 0u, bdn = 0u, bri = 0u, ble = 0u;
-  if (up_mask) bup = (mV[(size_t)j * p.mw + (il >> 5)] >> (il & 31)) & lanebits;
-  if (dn_mask) bdn = (mV[(size_t)jm * p.mw + (il >> 5)] >> (il & 31)) & lanebits;
-  if (in_range(j, mr.hlo, mr.hhi)) {
-    const uint32_t *h = mH + (size_t)j * p.mw;
-    bri = (h[il >> 5] >> (il & 31)) & lanebits;
-    const int ilm = il > 0 ? (int)il - 1 : (p.periodic ? last : -1);
-    const uint32_t l0 = ilm >= 0 ? (h[ilm >> 5] >> (ilm & 31)) & 1u : 0u;
-    ble = ((bri << 1) | l0) & lanebits;
-  }
-
-  const C s_left = lane_value(hs, 0), s_right = lane_value(hs, 1), s_wrap = lane_value(hs, 2);
-  const C w_left = lane_value(hw, 0), w_right = lane_value(hw, 1), w_wrap = lane_value(hw, 2);
-  C f1L = lane_prev(f1[VEC - 1]);
-  C f3R = lane_next(f3[0]);
-  C wL = lane_prev(wc[VEC - 1]);
-  C wR = lane_next(wc[0]);
-  if (lane == 0) {
-    f1L = s_left;
-    wL = w_left;
-  }
-  if (lane == 63) {
-    f3R = s_right;
-    wR = w_right;
-  }
-
-  C o0[VEC], o1[VEC], o2[VEC], o3[VEC], o4[VEC], wo[VEC];
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) {
-    const int i = i0 + k;
-    const C w0 = wc[k];
-    // pull along +x (f^1 from i-1)
-    const bool bl = (i == 0 && !p.periodic) || ((ble >> k) & 1u);
-    const C gl = bl ? f3[k] : ((k == 0) ? f1L : f1[k - 1]);
-    const C wl = (!SHIFT || bl) ? w0 : ((k == 0) ? wL : wc[k - 1]);
-    // pull along -x (f^3 from i+1)
-    const bool br = (i == last && !p.periodic) || ((bri >> k) & 1u);
-    const bool wrap = (i == last) && !br;
-    const C gr = br ? f1[k] : (wrap ? s_wrap : ((k == VEC - 1) ? f3R : f3[k + 1]));
-    const C wr = (!SHIFT || br) ? w0 : (wrap ? w_wrap : ((k == VEC - 1) ? wR : wc[k + 1]));
-    // pull along +y (f^2 from j-1)
-    const bool bd = (jm < 0) || ((bdn >> k) & 1u);
-    const C td = (jm < 0) ? a.t_bot : (bd ? a.t_up : C(0));
-    const C gd = bd ? f4own[k] : f2d[k];
-    const C wdn = (!SHIFT || bd) ? w0 : wm[k];
-    // pull along -y (f^4 from j+1)
-    const bool bu = (jp < 0) || ((bup >> k) & 1u);
-    const C tu = (jp < 0) ? a.t_top : (bu ? a.t_lo : C(0));
-    const C gu = bu ? f2own[k] : f4u[k];
-    const C wup = (!SHIFT || bu) ? w0 : wp[k];
-    site_update<C, SHIFT>(a, f0[k], gl, gr, gd, gu, w0, wl, wr, wdn, wup, bd, bu, td, tu, o0[k],
-                          o1[k], o2[k], o3[k], o4[k], wo[k]);
-    if (i > last) {  // padding past the row end stays zero
-      o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
-    }
-  }
-  if (act) {
-    store_row<S, C, VEC>(fout, o, o0);
-    store_row<S, C, VEC>(fout + P, o, o1);
-    store_row<S, C, VEC>(fout + 2 * P, o, o2);
-    store_row<S, C, VEC>(fout + 3 * P, o, o3);
-    store_row<S, C, VEC>(fout + 4 * P, o, o4);
-    store_row<W, C, VEC>(wout, o, wo);
-  }
+  if (task >= m.n_strips * m.nb) return;
+  const int strip = task % m.n_strips;
+  const int j = m.brow[task / m.n_strips];
+  core::boundary_row<S, W, C, VEC, SHIFT>(fin, fout, win, wout, mV, mH, mrows, a, strip, j);
 }
 
 template <typename S, typename W, typename C, int VEC, bool SHIFT>
-hipError_t launch_t(const void *args, hipStream_t st) {
+hipError_t launch_t(const void *args, int part, hipStream_t st) {
   const auto &a = *static_cast<const SweepArgs<S, W, C> *>(args);
-  constexpr int SW = 64 * VEC;
-  const int nx = a.p.nx, ny = a.p.ny;
-  const int n_strips = (nx + SW - 1) / SW;
-  // boundary rows: the two edge rows and the skipped rows, each once
-  int rows_b[4], nb = 0;
-  auto add = [&](int j) {
-    if (j < 0 || j >= ny) return;
-    for (int k = 0; k < nb; ++k)
-      if (rows_b[k] == j) return;
-    rows_b[nb++] = j;
-  };
-  add(0);
-  add(ny - 1);
-  for (int j = a.skip_lo; j <= a.skip_hi && nb < 4; ++j) add(j);
-  // interior rows lie strictly between the edge rows, around the skipped rows
-  const bool has_skip = a.skip_lo <= a.skip_hi;
-  const int hi1 = has_skip ? a.skip_lo - 1 : ny - 2;
-  const int lo2 = has_skip ? a.skip_hi + 1 : ny;
-  const int len1 = std::max(hi1 - 1 + 1, 0), len2 = std::max(ny - 2 - lo2 + 1, 0);
-  const long chunks = (len1 + a.rows - 1) / a.rows + (len2 + a.rows - 1) / a.rows;
-  const long tasks_i = (long)n_strips * chunks;
-  if (tasks_i > 0) {
-    const unsigned blocks = (unsigned)((tasks_i + a.waves - 1) / a.waves);
-    hipLaunchKernelGGL((sweep_interior<S, W, C, VEC, SHIFT>), dim3(blocks), dim3(64 * a.waves),
-                       a.lds_bytes, st, a.fin, a.fout, a.win, a.wout, a);
-  }
-  const long tasks_b = (long)n_strips * nb;
-  if (tasks_b > 0) {
-    const int4 brow = make_int4(rows_b[0], nb > 1 ? rows_b[1] : 0, nb > 2 ? rows_b[2] : 0,
-                                nb > 3 ? rows_b[3] : 0);
-    const unsigned blocks = (unsigned)((tasks_b + 3) / 4);
-    hipLaunchKernelGGL((sweep_boundary<S, W, C, VEC, SHIFT>), dim3(blocks), dim3(256), 0, st,
-                       a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a, brow, nb);
+  if (part == 0) {
+    const core::InteriorMap m = core::interior_map(a.p.nx, a.p.ny, VEC, a.rows, a.skip_lo, a.skip_hi);
+    const long tasks = core::interior_task_count(m);
+    if (tasks > 0) {
+      const unsigned blocks = (unsigned)((tasks + a.waves - 1) / a.waves);
+      hipLaunchKernelGGL((sweep_interior<S, W, C, VEC, SHIFT>), dim3(blocks), dim3(64 * a.waves),
+                         a.lds_bytes, st, a.fin, a.fout, a.win, a.wout, a, m);
+    }
+  } else {
+    const core::BoundaryMap m = core::boundary_map(a.p.nx, a.p.ny, VEC, a.skip_lo, a.skip_hi);
+    const long tasks = core::boundary_task_count(m);
+    if (tasks > 0) {
+      const unsigned blocks = (unsigned)((tasks + 3) / 4);
+      hipLaunchKernelGGL((sweep_boundary<S, W, C, VEC, SHIFT>), dim3(blocks), dim3(256), 0, st,
+                         a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a, m);
+    }
   }
   return hipGetLastError();
 }
 
 }  // namespace
+
+int64_t interior_sites(const Plate &p, int skip_lo, int skip_hi) {
+  int rows = p.ny - 2;
+  for (int j = skip_lo; j <= skip_hi; ++j)
+    if (j >= 1 && j <= p.ny - 2) --rows;
+  return rows > 0 ? (int64_t)rows * p.nx : 0;
+}
 
 int sweep_vec(Store s) {
   switch (s) {
@@ -512,13 +85,13 @@ int sweep_vec(Store s) {
   return 0;
 }
 
-hipError_t launch_sweep(Store s, const void *args, hipStream_t st) {
+hipError_t launch_sweep(Store s, const void *args, int part, hipStream_t st) {
   switch (s) {
-    case Store::F64: return launch_t<double, double, double, 2, false>(args, st);
-    case Store::F32_PLAIN: return launch_t<float, float, float, 4, false>(args, st);
-    case Store::F32S: return launch_t<float, float, float, 4, true>(args, st);
-    case Store::F16S: return launch_t<_Float16, float, float, 4, true>(args, st);
-    case Store::BF16S: return launch_t<__bf16, float, float, 4, true>(args, st);
+    case Store::F64: return launch_t<double, double, double, 2, false>(args, part, st);
+    case Store::F32_PLAIN: return launch_t<float, float, float, 4, false>(args, part, st);
+    case Store::F32S: return launch_t<float, float, float, 4, true>(args, part, st);
+    case Store::F16S: return launch_t<_Float16, float, float, 4, true>(args, part, st);
+    case Store::BF16S: return launch_t<__bf16, float, float, 4, true>(args, part, st);
   }
   return hipErrorInvalidValue;
 }

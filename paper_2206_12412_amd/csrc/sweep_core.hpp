@@ -1,0 +1,496 @@
+// Device building blocks of the fused collide-stream sweep (gfx950), shared
+// by the single-plate kernels (sweep.hip) and the batched kernels (batch.hip).
+//
+// One step updates every site (paper Sec. 3): pull-stream with bounce-back on
+// severed or outside links (eq. LBE, streaming part; Sec. 4.1 "no information
+// is exchanged" along a severed link), wdot = sum of the populations
+// (eq. distrib-macro), w += dt wdot (eq. integration), BGK collision towards
+// f_eq(w, wdot) (eq. LBE, f-eq).
+//
+// Layout: populations structure-of-arrays, plane a at fin + a * plane, rows of
+// `pitch` elements (multiple of 64, 256-byte aligned); w in its own plane;
+// populations and w are double-buffered (source -> destination).  In-plane
+// byte offsets are 32-bit (a plane spans < 4 GiB) and every plane base is
+// wave-uniform, so loads and stores can use the scalar-base addressing mode.
+//
+// Work split: a wave owns a strip of 64 * VEC consecutive sites of a row; lane
+// l holds sites i0 .. i0 + VEC - 1, i0 = strip * 64 * VEC + l * VEC, so every
+// plane row is read and written with one 16-byte (8-byte for 16-bit storage)
+// access per lane.  x-neighbours across lanes come from DPP wave shifts
+// (v_mov_b32_dpp wave_shr / wave_shl); the strip-edge elements come from one
+// per-row halo load whose lanes 0..2 carry them (read back with readlane).
+//
+// Interior rows (every vertical link intact) and boundary rows (plate edges,
+// crack rows) are separate work items with separate code, so the interior
+// code carries no bounce-back logic and few registers.
+#pragma once
+
+#include <algorithm>
+
+#include "lbm_internal.hpp"
+
+namespace lbmk {
+namespace core {
+
+template <typename S, int N>
+struct alignas(N * sizeof(S)) Pack {
+  S v[N];
+};
+
+__device__ __forceinline__ float to_c(float x) { return x; }
+__device__ __forceinline__ double to_c(double x) { return x; }
+__device__ __forceinline__ float to_c(_Float16 x) { return static_cast<float>(x); }
+__device__ __forceinline__ float to_c(__bf16 x) { return static_cast<float>(x); }
+
+template <typename S> __device__ __forceinline__ S from_c(float x);
+template <> __device__ __forceinline__ float from_c<float>(float x) { return x; }
+template <> __device__ __forceinline__ _Float16 from_c<_Float16>(float x) { return static_cast<_Float16>(x); }
+template <> __device__ __forceinline__ __bf16 from_c<__bf16>(float x) { return static_cast<__bf16>(x); }
+template <typename S> __device__ __forceinline__ S from_c(double x);
+template <> __device__ __forceinline__ double from_c<double>(double x) { return x; }
+
+// Lane l receives the value of lane l-1 (lane 0 receives 0).
+__device__ __forceinline__ float lane_prev(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+// Lane l receives the value of lane l+1 (lane 63 receives 0).
+__device__ __forceinline__ float lane_next(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_prev(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_next(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// Value of lane k, broadcast (k is a compile-time constant here).
+__device__ __forceinline__ float lane_value(float x, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
+}
+__device__ __forceinline__ double lane_value(double x, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), k);
+  return __hiloint2double(hi, lo);
+}
+
+// base + off with the byte offset formed in 32 bits (a plane spans < 4 GiB), so
+// that a uniform base and a 32-bit per-lane offset address the access
+template <typename S>
+__device__ __forceinline__ const S *at(const S *base, uint32_t off) {
+  return reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + off * (uint32_t)sizeof(S));
+}
+template <typename S>
+__device__ __forceinline__ S *at(S *base, uint32_t off) {
+  return reinterpret_cast<S *>(reinterpret_cast<char *>(base) + off * (uint32_t)sizeof(S));
+}
+
+template <typename S, typename C, int VEC>
+__device__ __forceinline__ void load_row(const S *__restrict__ base, uint32_t off, C (&out)[VEC]) {
+  const Pack<S, VEC> pk = *reinterpret_cast<const Pack<S, VEC> *>(at(base, off));
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) out[k] = to_c(pk.v[k]);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Rows are written once per step and read back only in the next step, after
+// the whole plate has streamed through the caches: store them non-temporally.
+template <typename S, typename C, int VEC>
+__device__ __forceinline__ void store_row(S *__restrict__ base, uint32_t off, const C (&in)[VEC]) {
+  Pack<S, VEC> pk;
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) pk.v[k] = from_c<S>(in[k]);
+  S *ptr = at(base, off);
+  if constexpr (sizeof(pk) % 16 == 0) {
+#pragma unroll
+    for (int c = 0; c < (int)(sizeof(pk) / 16); ++c) {
+      u32x4 v;
+      __builtin_memcpy(&v, reinterpret_cast<const char *>(&pk) + 16 * c, 16);
+      __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(ptr) + c);
+    }
+  } else {
+    static_assert(sizeof(pk) == 8, "rows are stored in 8- or 16-byte pieces");
+    u32x2 v;
+    __builtin_memcpy(&v, &pk, 8);
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(ptr));
+  }
+}
+
+template <typename C, int VEC>
+__device__ __forceinline__ void zero_row(C (&out)[VEC]) {
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) out[k] = C(0);
+}
+
+__device__ __forceinline__ bool in_range(int j, int lo, int hi) { return j >= lo && j <= hi; }
+
+// One site: wdot, Euler update and collision from the pulled populations.
+// gl, gr, gd, gu are the values pulled along +x, -x, +y, -y (already bounced
+// where the link is severed); for shifted storage wl .. wup are the w of the
+// emitting sites (w0 where bounced); bd / bu say that the +y / -y pull bounced
+// and then carries the traction term td / tu.
+//
+// SHIFT = false: the stored values are the post-collision populations f
+// themselves (FP64 and plain FP32), evaluated in the paper's order of
+// operations without contraction.  SHIFT = true: the stored values are
+// g = f - E(w_emit), E the static equilibrium (E^0 = -A0 w, E^k = Ak w) of
+// the emitting site; wdot and the collision are the same arithmetic regrouped
+// in these variables so that no large term cancels in FP32 (A0 = 4 Ak).
+template <typename C, bool SHIFT, typename A>
+__device__ __forceinline__ void site_update(const A &a, C f0, C gl, C gr, C gd, C gu, C w0, C wl,
+                                            C wr, C wdn, C wup, bool bd, bool bu, C td, C tu,
+                                            C &o0, C &o1, C &o2, C &o3, C &o4, C &wo) {
+  if constexpr (SHIFT) {
+#pragma clang fp contract(fast)
+    const C wd = f0 + ((gl + gr) + (gd + gu)) +
+                 a.Ak * (((wl - w0) + (wr - w0)) + ((wdn - w0) + (wup - w0))) + (td + tu);
+    const C wn = w0 + a.dt * wd;
+    const C om1 = C(1) - a.omega;
+    o0 = om1 * (f0 + a.A0 * (wn - w0)) + a.omega * wd;
+    o1 = om1 * (gl + a.Ak * (wl - wn));
+    o2 = om1 * (gd + a.Ak * (wdn - wn) + td);
+    o3 = om1 * (gr + a.Ak * (wr - wn));
+    o4 = om1 * (gu + a.Ak * (wup - wn) + tu);
+    wo = wn;
+  } else {
+#pragma clang fp contract(off)
+    const C fi2 = bd ? gd + td : gd;
+    const C fi4 = bu ? gu + tu : gu;
+    const C wd = f0 + gl + fi2 + gr + fi4;
+    const C wn = w0 + a.dt * wd;
+    const C e0 = wd - a.A0 * wn;
+    const C ek = a.Ak * wn;
+    o0 = f0 - a.omega * (f0 - e0);
+    o1 = gl - a.omega * (gl - ek);
+    o2 = fi2 - a.omega * (fi2 - ek);
+    o3 = gr - a.omega * (gr - ek);
+    o4 = fi4 - a.omega * (fi4 - ek);
+    wo = wn;
+  }
+}
+
+// ------------------------------------------------------------- task maps --
+// Interior work of a plate: the strips of 64 * VEC sites times the chunks of
+// `rows` consecutive interior rows, which are 1 .. skip_lo-1 and
+// skip_hi+1 .. ny-2 (the rows skip_lo .. skip_hi and the two edge rows belong
+// to the boundary work).  Task t -> strip t % n_strips, chunk t / n_strips.
+struct InteriorMap {
+  int n_strips, rows, lo1, hi1, lo2, hi2, nc1, nc2;
+};
+
+__host__ __device__ inline InteriorMap interior_map(int nx, int ny, int vec, int rows, int skip_lo,
+                                                    int skip_hi) {
+  InteriorMap m;
+  m.n_strips = (nx + 64 * vec - 1) / (64 * vec);
+  m.rows = rows;
+  const bool has_skip = skip_lo <= skip_hi;
+  m.lo1 = 1;
+  m.hi1 = has_skip ? skip_lo - 1 : ny - 2;
+  m.lo2 = has_skip ? skip_hi + 1 : ny;
+  m.hi2 = ny - 2;
+  m.nc1 = m.hi1 >= m.lo1 ? (m.hi1 - m.lo1 + rows) / rows : 0;
+  m.nc2 = m.hi2 >= m.lo2 ? (m.hi2 - m.lo2 + rows) / rows : 0;
+  return m;
+}
+
+__host__ __device__ inline long interior_task_count(const InteriorMap &m) {
+  return (long)m.n_strips * (m.nc1 + m.nc2);
+}
+
+// Boundary work of a plate: every strip of each boundary row (the two edge
+// rows and the skipped rows, each once).  Task t -> row brow[t / n_strips].
+struct BoundaryMap {
+  int n_strips, nb;
+  int brow[4];
+};
+
+__host__ __device__ inline BoundaryMap boundary_map(int nx, int ny, int vec, int skip_lo,
+                                                    int skip_hi) {
+  BoundaryMap m;
+  m.n_strips = (nx + 64 * vec - 1) / (64 * vec);
+  m.nb = 0;
+  auto add = [&](int j) {
+    if (j < 0 || j >= ny) return;
+    for (int k = 0; k < m.nb; ++k)
+      if (m.brow[k] == j) return;
+    m.brow[m.nb++] = j;
+  };
+  add(0);
+  add(ny - 1);
+  for (int j = skip_lo; j <= skip_hi && m.nb < 4; ++j) add(j);
+  for (int k = m.nb; k < 4; ++k) m.brow[k] = 0;
+  return m;
+}
+
+__host__ __device__ inline long boundary_task_count(const BoundaryMap &m) {
+  return (long)m.n_strips * m.nb;
+}
+
+// ----------------------------------------------------------------- interior --
+// Rows jb .. jlast of one strip, all of them interior rows (every vertical
+// link intact); the left and right plate edges (or the periodic wrap) and the
+// ragged end of the last strip are per-lane fix-ups.
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+__device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__restrict__ fout,
+                                              const W *__restrict__ win, W *__restrict__ wout,
+                                              const SweepArgs<S, W, C> &a, const int strip,
+                                              const int jb, const int jlast) {
+  const Plate p = a.p;
+  const int lane = threadIdx.x & 63;
+  constexpr int SW = 64 * VEC;
+  const int last = p.nx - 1;
+  const int is = strip * SW;
+  const int i0 = is + lane * VEC;
+  const bool act = i0 < p.nx;
+  const uint32_t il = act ? i0 : is;  // inactive lanes read their strip's first vector
+  const bool left_edge = strip == 0;          // holds site 0
+  const bool right_edge = is + SW > last;     // holds site nx-1 (and maybe padding)
+  const uint32_t pitch = p.pitch;
+  const size_t P = p.plane;
+  const S *__restrict__ F0 = fin;
+  const S *__restrict__ F1 = fin + P;
+  const S *__restrict__ F2 = fin + 2 * P;
+  const S *__restrict__ F3 = fin + 3 * P;
+  const S *__restrict__ F4 = fin + 4 * P;
+  // halo: lane 0 the site left of the strip (plane 1; the periodic wrap for
+  // the first strip), lane 1 the site right of it (plane 3), lane 2 site 0
+  // (plane 3: the periodic neighbour of the last site)
+  const S *__restrict__ Fh = (lane == 0) ? F1 : F3;
+  const uint32_t hx = (lane == 0) ? (is > 0 ? is - 1 : (p.periodic ? last : 0))
+                                  : (lane == 1 && is + SW <= last ? is + SW : 0);
+
+  C wm[VEC], wc[VEC];
+  if (SHIFT) {
+    load_row<W, C, VEC>(win, (uint32_t)jb * pitch + il, wc);
+    load_row<W, C, VEC>(win, (uint32_t)(jb - 1) * pitch + il, wm);
+  }
+  for (int j = jb; j <= jlast; ++j) {
+    const uint32_t o = (uint32_t)j * pitch + il;
+    C f0[VEC], f1[VEC], f3[VEC], f2d[VEC], f4u[VEC], wp[VEC], wself[VEC];
+    load_row<S, C, VEC>(F0, o, f0);
+    load_row<S, C, VEC>(F1, o, f1);
+    load_row<S, C, VEC>(F3, o, f3);
+    load_row<S, C, VEC>(F2, o - pitch, f2d);
+    load_row<S, C, VEC>(F4, o + pitch, f4u);
+    if (SHIFT) load_row<W, C, VEC>(win, o + pitch, wp);
+    else load_row<W, C, VEC>(win, o, wself);
+    const uint32_t ho = (uint32_t)j * pitch + hx;
+    const C hs = to_c(*at(Fh, ho));
+    C hw = C(0);
+    if (SHIFT) hw = to_c(*at(win, ho));
+
+    // pulled x-neighbours of every site: gl[k] along +x, gr[k] along -x
+    C gl[VEC], gr[VEC], wl[VEC], wr[VEC];
+    {
+      const C f1L = lane_prev(f1[VEC - 1]);
+      const C f3R = lane_next(f3[0]);
+      const C s_left = lane_value(hs, 0), s_right = lane_value(hs, 1);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        gl[k] = (k == 0) ? ((lane == 0) ? s_left : f1L) : f1[k - 1];
+        gr[k] = (k == VEC - 1) ? ((lane == 63) ? s_right : f3R) : f3[k + 1];
+      }
+      if (SHIFT) {
+        const C wL = lane_prev(wc[VEC - 1]);
+        const C wR = lane_next(wc[0]);
+        const C w_left = lane_value(hw, 0), w_right = lane_value(hw, 1);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          wl[k] = (k == 0) ? ((lane == 0) ? w_left : wL) : wc[k - 1];
+          wr[k] = (k == VEC - 1) ? ((lane == 63) ? w_right : wR) : wc[k + 1];
+        }
+      }
+      // the left edge bounces site 0 (or wraps to nx-1, which the halo holds)
+      if (left_edge && !p.periodic && lane == 0) {
+        gl[0] = f3[0];
+        if (SHIFT) wl[0] = wc[0];
+      }
+      // the right edge bounces site nx-1 or wraps to site 0
+      if (right_edge) {
+        const C s_wrap = lane_value(hs, 2);
+        const C w_wrap = SHIFT ? lane_value(hw, 2) : C(0);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          if (i0 + k == last) {
+            gr[k] = p.periodic ? s_wrap : f1[k];
+            if (SHIFT) wr[k] = p.periodic ? w_wrap : wc[k];
+          }
+        }
+      }
+    }
+
+    C o0[VEC], o1[VEC], o2[VEC], o3[VEC], o4[VEC], wo[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      const C w0 = SHIFT ? wc[k] : wself[k];
+      const C wdn = SHIFT ? wm[k] : w0;
+      const C wup = SHIFT ? wp[k] : w0;
+      site_update<C, SHIFT>(a, f0[k], gl[k], gr[k], f2d[k], f4u[k], w0, SHIFT ? wl[k] : w0,
+                            SHIFT ? wr[k] : w0, wdn, wup, false, false, C(0), C(0), o0[k], o1[k],
+                            o2[k], o3[k], o4[k], wo[k]);
+    }
+    if (right_edge) {
+#pragma unroll
+      for (int k = 0; k < VEC; ++k)
+        if (i0 + k > last) o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
+    }
+    if (act) {
+      store_row<S, C, VEC>(fout, o, o0);
+      store_row<S, C, VEC>(fout + P, o, o1);
+      store_row<S, C, VEC>(fout + 2 * P, o, o2);
+      store_row<S, C, VEC>(fout + 3 * P, o, o3);
+      store_row<S, C, VEC>(fout + 4 * P, o, o4);
+      store_row<W, C, VEC>(wout, o, wo);
+    }
+    if (SHIFT) {
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        wm[k] = wc[k];
+        wc[k] = wp[k];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- boundary --
+// Row j of one strip with the full boundary treatment: bounce-back at the
+// plate edges and on severed links (read from the cut bitmask in the rows the
+// mask-row range names), traction terms, periodic wrap-around.
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+__device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__restrict__ fout,
+                                             const W *__restrict__ win, W *__restrict__ wout,
+                                             const uint32_t *__restrict__ mV,
+                                             const uint32_t *__restrict__ mH,
+                                             const MaskRows *__restrict__ mrows,
+                                             const SweepArgs<S, W, C> &a, const int strip,
+                                             const int j) {
+  const Plate p = a.p;
+  const int lane = threadIdx.x & 63;
+  constexpr int SW = 64 * VEC;
+  const int is = strip * SW;
+  const int i0 = is + lane * VEC;
+  const bool act = i0 < p.nx;
+  const uint32_t il = act ? i0 : is;  // inactive lanes read their strip's first vector
+  const int last = p.nx - 1;
+  const uint32_t pitch = p.pitch;
+  const size_t P = p.plane;
+  const MaskRows mr = *mrows;
+  const int jm = j > 0 ? j - 1 : (p.periodic ? p.ny - 1 : -1);
+  const int jp = j < p.ny - 1 ? j + 1 : (p.periodic ? 0 : -1);
+  const uint32_t o = (uint32_t)j * pitch + il;
+  const uint32_t rj = (uint32_t)j * pitch;
+
+  C f0[VEC], f1[VEC], f3[VEC], f2d[VEC], f4u[VEC], f2own[VEC], f4own[VEC];
+  C wc[VEC], wm[VEC], wp[VEC];
+  load_row<S, C, VEC>(fin, o, f0);
+  load_row<S, C, VEC>(fin + P, o, f1);
+  load_row<S, C, VEC>(fin + 3 * P, o, f3);
+  load_row<W, C, VEC>(win, o, wc);
+  if (jm >= 0) {
+    load_row<S, C, VEC>(fin + 2 * P, (uint32_t)jm * pitch + il, f2d);
+    if (SHIFT) load_row<W, C, VEC>(win, (uint32_t)jm * pitch + il, wm);
+    else zero_row(wm);
+  } else {
+    zero_row(f2d);
+    zero_row(wm);
+  }
+  if (jp >= 0) {
+    load_row<S, C, VEC>(fin + 4 * P, (uint32_t)jp * pitch + il, f4u);
+    if (SHIFT) load_row<W, C, VEC>(win, (uint32_t)jp * pitch + il, wp);
+    else zero_row(wp);
+  } else {
+    zero_row(f4u);
+    zero_row(wp);
+  }
+  // own-row f^2 / f^4 for the bounced vertical pulls
+  const bool up_mask = in_range(j, mr.vlo, mr.vhi);
+  const bool dn_mask = jm >= 0 && in_range(jm, mr.vlo, mr.vhi);
+  if (jp < 0 || up_mask) load_row<S, C, VEC>(fin + 2 * P, o, f2own);
+  else zero_row(f2own);
+  if (jm < 0 || dn_mask) load_row<S, C, VEC>(fin + 4 * P, o, f4own);
+  else zero_row(f4own);
+  // halo: lane 0 left of the strip (or the periodic wrap), lane 1 right of
+  // the strip, lane 2 site 0 (the periodic neighbour of the last site)
+  const int hl = is > 0 ? is - 1 : (p.periodic ? last : 0);
+  const int hr = is + SW <= last ? is + SW : 0;
+  const uint32_t hx = (lane == 0) ? hl : (lane == 1 ? hr : 0);
+  const S *__restrict__ Fh = (lane == 0) ? fin + P : fin + 3 * P;
+  const C hs = to_c(*at(Fh, rj + hx));
+  const C hw = to_c(*at(win, rj + hx));
+  // severed-link bits of the lane's sites (bit k = site i0 + k)
+  const uint32_t lanebits = (1u << VEC) - 1u;
+  uint32_t bup = 0u, bdn = 0u, bri = 0u, ble = 0u;
+  if (up_mask) bup = (mV[(size_t)j * p.mw + (il >> 5)] >> (il & 31)) & lanebits;
+  if (dn_mask) bdn = (mV[(size_t)jm * p.mw + (il >> 5)] >> (il & 31)) & lanebits;
+  if (in_range(j, mr.hlo, mr.hhi)) {
+    const uint32_t *h = mH + (size_t)j * p.mw;
+    bri = (h[il >> 5] >> (il & 31)) & lanebits;
+    const int ilm = il > 0 ? (int)il - 1 : (p.periodic ? last : -1);
+    const uint32_t l0 = ilm >= 0 ? (h[ilm >> 5] >> (ilm & 31)) & 1u : 0u;
+    ble = ((bri << 1) | l0) & lanebits;
+  }
+
+  const C s_left = lane_value(hs, 0), s_right = lane_value(hs, 1), s_wrap = lane_value(hs, 2);
+  const C w_left = lane_value(hw, 0), w_right = lane_value(hw, 1), w_wrap = lane_value(hw, 2);
+  C f1L = lane_prev(f1[VEC - 1]);
+  C f3R = lane_next(f3[0]);
+  C wL = lane_prev(wc[VEC - 1]);
+  C wR = lane_next(wc[0]);
+  if (lane == 0) {
+    f1L = s_left;
+    wL = w_left;
+  }
+  if (lane == 63) {
+    f3R = s_right;
+    wR = w_right;
+  }
+
+  C o0[VEC], o1[VEC], o2[VEC], o3[VEC], o4[VEC], wo[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    const int i = i0 + k;
+    const C w0 = wc[k];
+    // pull along +x (f^1 from i-1)
+    const bool bl = (i == 0 && !p.periodic) || ((ble >> k) & 1u);
+    const C gl = bl ? f3[k] : ((k == 0) ? f1L : f1[k - 1]);
+    const C wl = (!SHIFT || bl) ? w0 : ((k == 0) ? wL : wc[k - 1]);
+    // pull along -x (f^3 from i+1)
+    const bool br = (i == last && !p.periodic) || ((bri >> k) & 1u);
+    const bool wrap = (i == last) && !br;
+    const C gr = br ? f1[k] : (wrap ? s_wrap : ((k == VEC - 1) ? f3R : f3[k + 1]));
+    const C wr = (!SHIFT || br) ? w0 : (wrap ? w_wrap : ((k == VEC - 1) ? wR : wc[k + 1]));
+    // pull along +y (f^2 from j-1)
+    const bool bd = (jm < 0) || ((bdn >> k) & 1u);
+    const C td = (jm < 0) ? a.t_bot : (bd ? a.t_up : C(0));
+    const C gd = bd ? f4own[k] : f2d[k];
+    const C wdn = (!SHIFT || bd) ? w0 : wm[k];
+    // pull along -y (f^4 from j+1)
+    const bool bu = (jp < 0) || ((bup >> k) & 1u);
+    const C tu = (jp < 0) ? a.t_top : (bu ? a.t_lo : C(0));
+    const C gu = bu ? f2own[k] : f4u[k];
+    const C wup = (!SHIFT || bu) ? w0 : wp[k];
+    site_update<C, SHIFT>(a, f0[k], gl, gr, gd, gu, w0, wl, wr, wdn, wup, bd, bu, td, tu, o0[k],
+                          o1[k], o2[k], o3[k], o4[k], wo[k]);
+    if (i > last) {  // padding past the row end stays zero
+      o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
+    }
+  }
+  if (act) {
+    store_row<S, C, VEC>(fout, o, o0);
+    store_row<S, C, VEC>(fout + P, o, o1);
+    store_row<S, C, VEC>(fout + 2 * P, o, o2);
+    store_row<S, C, VEC>(fout + 3 * P, o, o3);
+    store_row<S, C, VEC>(fout + 4 * P, o, o4);
+    store_row<W, C, VEC>(wout, o, wo);
+  }
+}
+
+}  // namespace core
+}  // namespace lbmk

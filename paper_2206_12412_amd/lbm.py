@@ -30,8 +30,11 @@ ERRORS = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
            "lbm_cut_events", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
-           "lbm_timing", "lbm_get_launch", "lbm_set_launch", "lbm_bytes_per_site", "lbm_free",
-           "lbm_last_error")
+           "lbm_timing", "lbm_interior_sites", "lbm_get_launch", "lbm_set_launch",
+           "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
+           "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
+           "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
+           "lbm_batch_free")
 
 
 class LBMError(RuntimeError):
@@ -87,7 +90,9 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_get_fields.argtypes = [vp, P(d), P(d)]
     lib.lbm_get_populations.argtypes = [vp, P(d)]
     lib.lbm_get_mask.argtypes = [vp, P(C.c_uint8), P(C.c_uint8)]
-    lib.lbm_timing.argtypes = [vp, i32, P(d), P(d), P(i64)]
+    lib.lbm_timing.argtypes = [vp, i32, P(d), P(d), P(d), P(i64)]
+    lib.lbm_interior_sites.argtypes = [vp]
+    lib.lbm_interior_sites.restype = i64
     lib.lbm_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
     lib.lbm_set_launch.argtypes = [vp, i32, i32, i32]
     lib.lbm_bytes_per_site.argtypes = [vp]
@@ -95,6 +100,23 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_free.argtypes = [vp]
     lib.lbm_free.restype = None
     lib.lbm_last_error.restype = C.c_char_p
+    lib.lbm_batch_state_bytes.argtypes = [P(_Config), i32]
+    lib.lbm_batch_state_bytes.restype = C.c_size_t
+    lib.lbm_batch_init.argtypes = [P(_Config), i32, vp, C.c_size_t, vp, P(vp)]
+    lib.lbm_batch_step.argtypes = [vp, i64]
+    lib.lbm_batch_run_persistent.argtypes = [vp, i64]
+    lib.lbm_batch_plate.argtypes = [vp, i32]
+    lib.lbm_batch_plate.restype = vp
+    lib.lbm_batch_set_launch.argtypes = [vp, i32, i32, i32]
+    lib.lbm_batch_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+    lib.lbm_batch_timing.argtypes = [vp, i32, P(d), P(i64)]
+    lib.lbm_batch_sites.argtypes = [vp]
+    lib.lbm_batch_sites.restype = i64
+    lib.lbm_batch_free.argtypes = [vp]
+    lib.lbm_batch_free.restype = None
+    for name in ("lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
+                 "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
+        getattr(lib, name).restype = i32
     for name in ("lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
                  "lbm_cut_events", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
                  "lbm_timing", "lbm_get_launch", "lbm_set_launch"):
@@ -265,10 +287,17 @@ class Solver:
         return v, h
 
     def timing(self, enable: bool):
-        s, k = C.c_double(), C.c_double()
+        """Start (True) or stop (False) per-kernel HIP-event timing; returns the
+        summed interior / boundary / crack kernel times and the timed steps."""
+        i, b, k = C.c_double(), C.c_double(), C.c_double()
         n = C.c_int64()
-        _check(self._lib.lbm_timing(self._h, int(enable), C.byref(s), C.byref(k), C.byref(n)))
-        return {"sweep_ms": s.value, "crack_ms": k.value, "steps": n.value}
+        _check(self._lib.lbm_timing(self._h, int(enable), C.byref(i), C.byref(b), C.byref(k),
+                                    C.byref(n)))
+        return {"interior_ms": i.value, "boundary_ms": b.value, "crack_ms": k.value,
+                "sweep_ms": i.value + b.value, "steps": n.value}
+
+    def interior_sites(self) -> int:
+        return int(self._lib.lbm_interior_sites(self._h))
 
     def launch(self):
         v, r, w, o = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
@@ -280,3 +309,97 @@ class Solver:
 
     def bytes_per_site(self) -> float:
         return float(self._lib.lbm_bytes_per_site(self._h))
+
+
+class _PlateView(Solver):
+    """Query handle of one plate of a batch (owned by the batch)."""
+
+    def __init__(self, batch, k: int, cfg: Config, h):  # noqa: super().__init__ not called
+        self.cfg = cfg
+        self._h = h
+        self._lib = batch._lib
+        self._batch = batch
+        self.stream = batch.stream
+
+    @property
+    def steps_done(self):
+        return self._batch.steps_done
+
+    @steps_done.setter
+    def steps_done(self, v):
+        pass
+
+    def close(self):
+        self._h = None
+
+    def step(self, n: int = 1):
+        raise RuntimeError("plates of a batch are stepped through the batch")
+
+
+class Batch:
+    """Many plates (same storage) advanced together on one GPU."""
+
+    def __init__(self, cfgs, device: str = "cuda", stream=None):
+        import torch
+
+        lib = load_library()
+        self.cfgs = list(cfgs)
+        keep: list = []
+        arr = (_Config * len(self.cfgs))(*[c.to_c(keep) for c in self.cfgs])
+        nbytes = lib.lbm_batch_state_bytes(arr, len(self.cfgs))
+        if nbytes == 0:
+            _check(-1)
+        dev = torch.device(device)
+        if dev.type != "cuda":
+            raise RuntimeError("the batch runs on a GPU device only")
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ptr = self._buf.data_ptr()
+        ptr += (-ptr) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        b = C.c_void_p()
+        _check(lib.lbm_batch_init(arr, len(self.cfgs), ptr, nbytes, self.stream.cuda_stream,
+                                  C.byref(b)))
+        self._b = b
+        self._lib = lib
+        self.steps_done = 0
+        self.plates = []
+        for k, c in enumerate(self.cfgs):
+            h = lib.lbm_batch_plate(b, k)
+            self.plates.append(_PlateView(self, k, c, C.c_void_p(h)))
+
+    def close(self):
+        if getattr(self, "_b", None):
+            for p in self.plates:
+                p.close()
+            self._lib.lbm_batch_free(self._b)
+            self._b = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, n: int = 1):
+        _check(self._lib.lbm_batch_step(self._b, int(n)))
+        self.steps_done += int(n)
+
+    def run_persistent(self, n: int):
+        _check(self._lib.lbm_batch_run_persistent(self._b, int(n)))
+        self.steps_done += int(n)
+
+    def set_launch(self, rows: int, waves: int, occupancy: int = 0):
+        _check(self._lib.lbm_batch_set_launch(self._b, int(rows), int(waves), int(occupancy)))
+
+    def launch(self):
+        r, w, o, pb = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self._lib.lbm_batch_get_launch(self._b, C.byref(r), C.byref(w), C.byref(o),
+                                              C.byref(pb)))
+        return {"rows": r.value, "waves": w.value, "occupancy": o.value,
+                "persistent_blocks": pb.value}
+
+    def timing(self, enable: bool):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(self._lib.lbm_batch_timing(self._b, int(enable), C.byref(ms), C.byref(n)))
+        return {"ms": ms.value, "intervals": n.value}
+
+    def sites(self) -> int:
+        return int(self._lib.lbm_batch_sites(self._b))
