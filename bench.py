@@ -15,6 +15,7 @@ CPU throughput on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -124,6 +125,95 @@ def cpu_baseline(p, budget_s: float):
             "sample": f"{n} steps of the full {p.nx}x{p.ny} plate, FP64, {el:.1f} s"}
 
 
+def run_batched(args, torch):
+    """64 uneven plates: one batch (per-step launches and one persistent
+    launch) against the same plates stepped one after another, each as its own
+    single-plate solver.  Every plate's final field must agree bitwise."""
+    import synth
+    from paper_2206_12412_amd import Batch, Solver
+
+    plates = synth.config_batched()
+    steps = args.steps if args.steps is not None else plates[0].steps
+    storage = args.batch_storage
+    cfgs = [plate_config(p, storage, steps) for p in plates]
+    sites = sum(p.sites for p in plates)
+    say = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    b = Batch(cfgs)
+    tuned = None
+    if not args.no_tune:
+        say(f"batched: autotuning the launch shape ({len(plates)} plates, {sites} sites)")
+        tuned = b.autotune(trial_steps=4)
+        say(f"batched: tuned {tuned}")
+    if args.warmup > 0:
+        w = Batch([dataclasses.replace(c, trace_cap=0) for c in cfgs])
+        w.set_launch(b.launch()["rows"], b.launch()["waves"], b.launch()["occupancy"])
+        w.step(args.warmup)
+        w.run_persistent(args.warmup)
+        torch.cuda.synchronize()
+        w.close()
+        del w
+    say(f"batched: per-step launches, {steps} steps")
+    ms_step = timed(lambda: b.step(steps))
+    bp = Batch(cfgs)
+    shape = b.launch()
+    bp.set_launch(shape["rows"], shape["waves"], shape["occupancy"])
+    say(f"batched: one persistent launch, {steps} steps")
+    ms_pers = timed(lambda: bp.run_persistent(steps))
+    pers_blocks = bp.launch()["persistent_blocks"]
+    say("batched: the same plates one after another")
+    ms_seq = 0.0
+    equal_seq = equal_pers = 0
+    for k, c in enumerate(cfgs):
+        s1 = Solver(c)
+        ms_seq += timed(lambda: s1.step(steps))
+        w1 = s1.fields()[0]
+        equal_seq += int(np.array_equal(w1, b.plates[k].fields()[0]))
+        equal_pers += int(np.array_equal(w1, bp.plates[k].fields()[0]))
+        s1.close()
+        del s1
+    bps = 2.0 * (5 * {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[storage] +
+                 (8 if storage == "f64" else 4))
+    g = lambda ms: sites * steps / (ms * 1e-3) / 1e9  # noqa: E731
+    best_ms = min(ms_step, ms_pers)
+    achieved = sites * bps / (best_ms / steps * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(g(best_ms), 2), "unit": "GLUPS", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(best_ms / steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if storage == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": f"batched-{len(plates)}-plates", "plates": len(plates),
+                   "sites": sites, "storage": storage, "parallelism": "single-gpu",
+                   "mode": "per-step" if ms_step <= ms_pers else "persistent"},
+        "batched_per_step_glups": round(g(ms_step), 2),
+        "batched_persistent_glups": round(g(ms_pers), 2),
+        "sequential_glups": round(g(ms_seq), 2),
+        "speedup_vs_sequential": round(ms_seq / best_ms, 3),
+        "launch": shape, "autotune": tuned, "persistent_blocks": pers_blocks,
+        "bitwise_equal_plates": {"per_step": equal_seq, "persistent": equal_pers,
+                                 "of": len(plates)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole batched step (all kernels)"},
+    }
+    b.close()
+    bp.close()
+    if not args.no_cpu:
+        say("batched: oracle CPU baseline")
+        line["cpu_baseline"] = cpu_baseline(plates[0], args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def _read_csv(path):
     import csv
     with open(path) as fh:
@@ -153,7 +243,7 @@ def summarize_trace(dirpath: str, out_md: str, command: str):
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, copy_bytes: int,
-                  command: str):
+                  command: str, out_dir: str):
     """HBM bytes per interior-sweep launch from FETCH_SIZE and WRITE_SIZE runs,
     each scaled by the same counter's reading for a device copy of copy_bytes."""
     import synth
@@ -178,7 +268,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
     out["bytes_per_launch"] = total
     out["algorithmic_bytes_per_launch"] = interior * 2 * (5 * e + we)
     out["traffic_over_algorithmic"] = total / out["algorithmic_bytes_per_launch"]
-    base = os.path.join(ROOT, "profiles", f"sweep_{storage}_{workload}_traffic")
+    base = os.path.join(out_dir, f"sweep_{storage}_{workload}_traffic")
     with open(base + ".json", "w") as fh:
         json.dump(out, fh, indent=1)
     f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
@@ -199,7 +289,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="precision", choices=["precision", "sif", "plain"])
+    ap.add_argument("--workload", default="precision",
+                    choices=["precision", "sif", "plain", "batched"])
+    ap.add_argument("--batch-storage", default="f32", help="storage of the batched workload")
+    ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch shape")
     ap.add_argument("--storage", default="f16s")
     ap.add_argument("--compare", default="f64,f32,f16s,bf16s",
                     help="storages run; the first is the error reference")
@@ -209,6 +302,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"),
                     help="write a markdown summary of a rocprofv3 kernel-trace directory and exit")
+    ap.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"),
+                    help="where --summarize-pmc writes its summary")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB", "COMMAND"),
                     help="write profiles/sweep_<storage>_<workload>_traffic.{json,md} and exit")
     args = ap.parse_args()
@@ -218,7 +313,7 @@ def main():
         return
     if args.summarize_pmc:
         fd, wd, mib, cmd = args.summarize_pmc
-        summarize_pmc(fd, wd, args.storage, args.workload, int(mib) << 20, cmd)
+        summarize_pmc(fd, wd, args.storage, args.workload, int(mib) << 20, cmd, args.out_dir)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -233,6 +328,9 @@ def main():
     load_library()  # fails loudly when the HIP library is not built
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.workload == "batched":
+        run_batched(args, torch)
+        return
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
          "plain": synth.config_plain_fp64}[args.workload]()
     steps = args.steps if args.steps is not None else p.steps

@@ -174,6 +174,18 @@ int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves,
                    int32_t *occupancy);
 int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy);
 
+/* Launch-shape search.  Times every shape of a fixed grid (rows in {1, 2, 4,
+ * 8}, waves in {1, 2, 4, 8}, occupancy in {0, 2, 3, 4, 5, 6}) over trial_steps
+ * whole steps each (after one untimed step), with HIP events on the handle's
+ * stream, and leaves the fastest shape set on h.  The search ADVANCES h by
+ * 96 * (trial_steps + 1) steps, so run it on a scratch handle built from the
+ * production config and copy the result with lbm_set_launch (results never
+ * depend on the launch shape).  trial_steps must be in 1..1000.  Outputs: the
+ * chosen shape and its mean step time in ms (any pointer may be NULL).
+ * Synchronises the stream. */
+int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *rows, int32_t *waves,
+                 int32_t *occupancy, double *ms_per_step);
+
 /* Algorithmic bytes moved by one sweep per site (read + write of the five
  * populations and of w), for the storage of the handle. */
 double lbm_bytes_per_site(const lbm_handle *h);
@@ -217,6 +229,11 @@ lbm_handle *lbm_batch_plate(lbm_batch *b, int32_t k);
 int lbm_batch_set_launch(lbm_batch *b, int32_t rows, int32_t waves, int32_t occupancy);
 int lbm_batch_get_launch(lbm_batch *b, int32_t *rows, int32_t *waves, int32_t *occupancy,
                          int32_t *persistent_blocks);
+
+/* lbm_autotune for a batch (per-step launches): same grid, same contract;
+ * the batch advances by 96 * (trial_steps + 1) steps. */
+int lbm_batch_autotune(lbm_batch *b, int32_t trial_steps, int32_t *rows, int32_t *waves,
+                       int32_t *occupancy, double *ms_per_step);
 
 /* Whole-step timing with HIP events (per-step launches: one interval per
  * step; persistent runs: one interval per run). */

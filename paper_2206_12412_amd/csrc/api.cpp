@@ -310,6 +310,61 @@ int launch_crack_step(lbm_handle *h) {
   return LBM_OK;
 }
 
+// Times each launch shape of a fixed grid over trial_steps whole steps and
+// keeps the fastest.  set(rows, waves, occ) applies a shape, run(n) enqueues n
+// steps on the stream.
+template <typename Set, typename Run>
+int tune_shapes(hipStream_t st, int32_t trial_steps, Set set, Run run, int32_t *rows_out,
+                int32_t *waves_out, int32_t *occ_out, double *ms_out) {
+  if (trial_steps < 1 || trial_steps > 1000) return fail(LBM_EINVAL, "trial_steps must be in 1..1000");
+  static const int kRows[] = {1, 2, 4, 8};
+  static const int kWaves[] = {1, 2, 4, 8};
+  static const int kOcc[] = {0, 2, 3, 4, 5, 6};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(LBM_EHIP, "event creation failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(LBM_EHIP, "event creation failed");
+  }
+  int rc = LBM_OK;
+  float best = -1.0f;
+  int br = 1, bw = 4, bo = 0;
+  for (int r : kRows) {
+    for (int w : kWaves) {
+      for (int o : kOcc) {
+        rc = set(r, w, o);
+        if (rc == LBM_OK) rc = run(1);
+        if (rc == LBM_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(LBM_EHIP, "event record failed");
+        if (rc == LBM_OK) rc = run(trial_steps);
+        if (rc == LBM_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(LBM_EHIP, "event record failed");
+        float t = 0.0f;
+        if (rc == LBM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+          rc = fail(LBM_EHIP, "event timing failed");
+        if (rc != LBM_OK) break;
+        if (best < 0.0f || t < best) {
+          best = t;
+          br = r;
+          bw = w;
+          bo = o;
+        }
+      }
+      if (rc != LBM_OK) break;
+    }
+    if (rc != LBM_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != LBM_OK) return rc;
+  rc = set(br, bw, bo);
+  if (rc != LBM_OK) return rc;
+  if (rows_out) *rows_out = br;
+  if (waves_out) *waves_out = bw;
+  if (occ_out) *occ_out = bo;
+  if (ms_out) *ms_out = (double)best / trial_steps;
+  return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -642,6 +697,19 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
   return LBM_OK;
 }
 
+int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *rows, int32_t *waves,
+                 int32_t *occupancy, double *ms_per_step) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (h->in_batch) return fail(LBM_ESTATE, "plate belongs to a batch: tune the batch");
+  const bool was_timing = h->timing;
+  h->timing = false;
+  const int rc = tune_shapes(
+      h->stream, trial_steps, [h](int r, int w, int o) { return lbm_set_launch(h, r, w, o); },
+      [h](int64_t n) { return lbm_step(h, n); }, rows, waves, occupancy, ms_per_step);
+  h->timing = was_timing;
+  return rc;
+}
+
 int64_t lbm_interior_sites(const lbm_handle *h) {
   if (!h) return 0;
   const int lo = h->cfg.has_crack ? h->plate.j0 : 1;
@@ -944,6 +1012,18 @@ int lbm_batch_get_launch(lbm_batch *b, int32_t *rows, int32_t *waves, int32_t *o
   if (occupancy) *occupancy = b->occ;
   if (persistent_blocks) *persistent_blocks = b->persistent_blocks;
   return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch *b, int32_t trial_steps, int32_t *rows, int32_t *waves,
+                       int32_t *occupancy, double *ms_per_step) {
+  if (!b) return fail(LBM_EINVAL, "null batch");
+  const bool was_timing = b->timing;
+  b->timing = false;
+  const int rc = tune_shapes(
+      b->stream, trial_steps, [b](int r, int w, int o) { return lbm_batch_set_launch(b, r, w, o); },
+      [b](int64_t n) { return lbm_batch_step(b, n); }, rows, waves, occupancy, ms_per_step);
+  b->timing = was_timing;
+  return rc;
 }
 
 int lbm_batch_timing(lbm_batch *b, int32_t enable, double *ms, int64_t *n_timed) {

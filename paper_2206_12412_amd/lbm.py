@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import dataclasses
 from dataclasses import dataclass
 from typing import Optional
 
@@ -34,7 +35,7 @@ EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_si
            "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
            "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
            "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
-           "lbm_batch_free")
+           "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune")
 
 
 class LBMError(RuntimeError):
@@ -114,7 +115,9 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_sites.restype = i64
     lib.lbm_batch_free.argtypes = [vp]
     lib.lbm_batch_free.restype = None
-    for name in ("lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
+    lib.lbm_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
+    lib.lbm_batch_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
+    for name in ("lbm_autotune", "lbm_batch_autotune", "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
                  "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
         getattr(lib, name).restype = i32
     for name in ("lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
@@ -187,6 +190,12 @@ class Config:
 def state_bytes(cfg: Config) -> int:
     keep = []
     return int(load_library().lbm_state_bytes(C.byref(cfg.to_c(keep))))
+
+
+def _tune(fn, handle, trial_steps: int) -> dict:
+    r, w, o, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+    _check(fn(handle, int(trial_steps), C.byref(r), C.byref(w), C.byref(o), C.byref(ms)))
+    return {"rows": r.value, "waves": w.value, "occupancy": o.value, "ms_per_step": ms.value}
 
 
 class Solver:
@@ -307,6 +316,20 @@ class Solver:
     def set_launch(self, rows: int, waves: int, occupancy: int = 0):
         _check(self._lib.lbm_set_launch(self._h, int(rows), int(waves), int(occupancy)))
 
+    def autotune(self, trial_steps: int = 8) -> dict:
+        """Searches the launch-shape grid on a scratch plate built from this
+        plate's config (this plate's state is untouched) and applies the
+        fastest shape here."""
+        scratch = Solver(dataclasses.replace(self.cfg, trace_cap=0), device=str(self._buf.device),
+                         stream=self.stream)
+        try:
+            out = _tune(self._lib.lbm_autotune, scratch._h, trial_steps)
+        finally:
+            scratch.close()
+            del scratch
+        self.set_launch(out["rows"], out["waves"], out["occupancy"])
+        return out
+
     def bytes_per_site(self) -> float:
         return float(self._lib.lbm_bytes_per_site(self._h))
 
@@ -334,6 +357,12 @@ class _PlateView(Solver):
 
     def step(self, n: int = 1):
         raise RuntimeError("plates of a batch are stepped through the batch")
+
+    def set_launch(self, rows: int, waves: int, occupancy: int = 0):
+        raise RuntimeError("the launch shape of a batch is set on the batch")
+
+    def autotune(self, trial_steps: int = 8) -> dict:
+        raise RuntimeError("a batch is tuned as a whole (Batch.autotune)")
 
 
 class Batch:
@@ -387,6 +416,19 @@ class Batch:
 
     def set_launch(self, rows: int, waves: int, occupancy: int = 0):
         _check(self._lib.lbm_batch_set_launch(self._b, int(rows), int(waves), int(occupancy)))
+
+    def autotune(self, trial_steps: int = 4) -> dict:
+        """lbm_batch_autotune on a scratch batch of the same plates; applies
+        the fastest shape to this batch."""
+        scratch = Batch([dataclasses.replace(c, trace_cap=0) for c in self.cfgs],
+                        device=str(self._buf.device), stream=self.stream)
+        try:
+            out = _tune(self._lib.lbm_batch_autotune, scratch._b, trial_steps)
+        finally:
+            scratch.close()
+            del scratch
+        self.set_launch(out["rows"], out["waves"], out["occupancy"])
+        return out
 
     def launch(self):
         r, w, o, pb = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()

@@ -132,3 +132,35 @@ def test_plates_of_a_batch_are_not_stepped_alone():
         _check(b._lib.lbm_step(b.plates[0]._h, 1))
     with pytest.raises(LBMError):
         Batch([Config(nx=16, ny=8, storage="f32"), Config(nx=16, ny=8, storage="f64")])
+
+
+def test_autotune_picks_a_grid_shape_and_leaves_the_plate_alone():
+    cfg = plate_configs("f32", 40)[1]
+    s = Solver(cfg)
+    s.step(20)
+    w_before = s.fields()[0]
+    t = s.autotune(trial_steps=2)
+    say(f"tuned single plate: {t}")
+    assert t["rows"] in (1, 2, 4, 8) and t["waves"] in (1, 2, 4, 8)
+    assert t["occupancy"] in (0, 2, 3, 4, 5, 6) and t["ms_per_step"] > 0
+    got = s.launch()
+    assert (got["rows"], got["waves"], got["occupancy"]) == (t["rows"], t["waves"], t["occupancy"])
+    np.testing.assert_array_equal(s.fields()[0], w_before)
+    s.step(20)
+    ref = Solver(cfg)
+    ref.step(40)
+    same_state(s, ref, "tuned plate")
+
+
+def test_batch_autotune_keeps_results():
+    cfgs = plate_configs("f32", 30)
+    b = Batch(cfgs)
+    t = b.autotune(trial_steps=1)
+    say(f"tuned batch: {t}")
+    b.step(30)
+    ref = Batch(cfgs)
+    ref.step(30)
+    for k in range(len(cfgs)):
+        same_state(b.plates[k], ref.plates[k], f"plate {k}")
+    with pytest.raises(RuntimeError):
+        b.plates[0].autotune()
