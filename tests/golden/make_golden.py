@@ -55,7 +55,6 @@ def run(p: synth.Plate, snaps, fname, nsamp=256):
     tr = s.traces()
     out["K"] = [float(x) for x in tr["K"]]
     out["tip"] = [float(x) for x in tr["tip"]]
-    out["v"] = [float(x) for x in tr["v"]]
     out["flags"] = [int(x) for x in tr["flags"]]
     out["events"] = s.events()[:, :2].tolist()
     with open(os.path.join(HERE, fname), "w") as fh:
@@ -67,4 +66,4 @@ if __name__ == "__main__":
     if "plain" in which:
         run(synth.config_plain_fp64(), [500, 1000, 1500, 2000], "plain_fp64_256x128.json")
     if "sif" in which:
-        run(synth.config_sif_fp32(), [5000, 10000, 20000], "sif_4096x2048.json")
+        run(synth.config_sif_fp32(), [2000, 3200, 5000, 10000, 20000], "sif_4096x2048.json")

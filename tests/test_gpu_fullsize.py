@@ -1,0 +1,215 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark uses (the library's default launch shape).
+
+* 16384 x 8192 plate (134M sites): after T steps a site depends only on the
+  sites within lattice distance T, so the oracle run on a window of half-width
+  T + 1 + d around a site reproduces the full plate's values on the central
+  (2d + 1)^2 block exactly (the window's artificial edges cannot reach it).
+  The plate is excited with seeded velocity noise so that every window holds a
+  non-trivial field.
+* 4096 x 2048 K-criterion run: compared with the oracle's stored run of all
+  20000 steps (tests/golden/sif_4096x2048.json, written by the oracle only).
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2206_12412_amd import Config, Solver  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------- 134M-site windows --
+
+T_WIN = 200
+D_BLOCK = 6
+
+
+@pytest.fixture(scope="module")
+def big_plate():
+    p = synth.config_precision()
+    rng = np.random.default_rng(7)
+    wd0 = rng.normal(0.0, 1e-4, size=(p.ny, p.nx))
+    return p, wd0
+
+
+def window_oracle(p, wd0, ic, jc, T, d):
+    """Oracle run on the window around (ic, jc); returns (w, wdot) of the
+    central block and the block's plate coordinates."""
+    R = T + 1 + d
+    j0 = p.ny // 2 - 1
+    x_lo, x_hi = max(0, ic - R), min(p.nx - 1, ic + R)
+    crack_rows = abs(jc - j0) <= R + 1 or abs(jc - (j0 + 1)) <= R + 1
+    if crack_rows:
+        h = R + 2
+        y_lo, y_hi = j0 - h + 1, j0 + h
+        assert y_lo >= 0 and y_hi <= p.ny - 1
+    else:
+        y_lo, y_hi = max(0, jc - R), min(p.ny - 1, jc + R)
+    nxw, nyw = x_hi - x_lo + 1, y_hi - y_lo + 1
+    kw = dict(nx=nxw, ny=nyw, tau_hist=p.traction_history(), wdot0=wd0[y_lo:y_hi + 1, x_lo:x_hi + 1])
+    if crack_rows:
+        # the crack enters through the window's left edge (unless the plate's
+        # own edge is in the window, where it starts anyway)
+        tip = p.crack_tip - x_lo
+        if tip + 0.25 * T < -0.5:  # the tip never reaches this window
+            kw.update(has_crack=True, crack_x0=-0.5, crack_tip=-0.5)
+        elif tip >= nxw - 0.5:  # the crack crosses the whole window during the run
+            kw.update(has_crack=True, crack_x0=-0.5, crack_tip=nxw - 0.5)
+        else:
+            assert -0.5 < tip and tip + 0.25 * T <= nxw - 0.5, "keep the tip inside the window"
+            kw.update(has_crack=True, crack_x0=-0.5, crack_tip=tip, growth=p.growth,
+                      v_rel=p.v_rel, trace_cap=T)
+    s = O.Oracle(O.OracleConfig(**kw))
+    s.step(T)
+    w, wd = s.fields()
+    bi = slice(ic - d - x_lo, ic + d + 1 - x_lo)
+    bj = slice(jc - d - y_lo, jc + d + 1 - y_lo)
+    return w[bj, bi], wd[bj, bi], (slice(jc - d, jc + d + 1), slice(ic - d, ic + d + 1))
+
+
+# 16-bit storage: each step rounds the stored values to within one 16-bit ulp
+# (2^-11 relative for FP16); over T steps the error of w stays below
+# 4 * 2^-11 * sqrt(T) relative (the bound the ragged-size tests use)
+F16_TOL = 4 * 2.0 ** -11 * math.sqrt(T_WIN)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5), ("f16s", F16_TOL),
+                                         ("f16s-sr", F16_TOL)])
+def test_precision_plate_windows(big_plate, storage, tol):
+    p, wd0 = big_plate
+    T, d = T_WIN, D_BLOCK
+    say(f"134M-site plate, storage {storage}, {T} steps")
+    rounding = "stochastic" if storage.endswith("-sr") else "nearest"
+    s = Solver(Config(nx=p.nx, ny=p.ny, storage=storage.replace("-sr", ""), rounding=rounding,
+                      has_crack=True, crack_x0=p.crack_x0,
+                      crack_tip=p.crack_tip, growth=p.growth, v_rel=p.v_rel,
+                      tau_hist=p.traction_history(), wdot0=wd0, trace_cap=T))
+    s.step(T)
+    w_g, wd_g = s.fields()
+    tip_g = s.traces()["tip"]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    # exact tip: a0 + (n + 1) v c_s dt with v c_s dt = 0.25 (no rounding)
+    assert np.array_equal(tip_g, p.crack_tip + 0.25 * (np.arange(T) + 1))
+    j0 = p.ny // 2 - 1
+    tip_mid = int(p.crack_tip + 0.25 * T / 2)
+    centres = [(tip_mid, j0), (tip_mid + 3, j0 + 1), (int(p.crack_tip) - 900, j0 + 1),
+               (0, p.ny - 1), (p.nx - 1, p.ny - 1), (p.nx // 2, 0), (p.nx - 1, j0),
+               (5000, 6000)]
+    worst = 0.0
+    for ic, jc in centres:
+        # a block at a plate edge is shifted inwards so that it holds the edge sites
+        ic = min(max(ic, d), p.nx - 1 - d)
+        jc = min(max(jc, d), p.ny - 1 - d)
+        w_o, wd_o, (bj, bi) = window_oracle(p, wd0, ic, jc, T, d)
+        scale = max(np.abs(w_o).max(), 1e-30)
+        e = np.abs(w_g[bj, bi] - w_o).max() / scale
+        ed = np.abs(wd_g[bj, bi] - wd_o).max() / max(np.abs(wd_o).max(), 1e-30)
+        worst = max(worst, e)
+        say(f"  window ({ic},{jc}): w rel err {e:.2e}, wdot rel err {ed:.2e}")
+        assert e <= tol, (storage, ic, jc, e)
+    say(f"  worst {worst:.2e}")
+
+
+# ------------------------------------------------ K-criterion full workload --
+
+@pytest.fixture(scope="module")
+def sif_golden():
+    path = os.path.join(HERE, "golden", "sif_4096x2048.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def run_sif(storage, g):
+    p = synth.config_sif_fp32()
+    s = Solver(Config(nx=p.nx, ny=p.ny, storage=storage, has_crack=True, crack_x0=p.crack_x0,
+                      crack_tip=p.crack_tip, growth=p.growth, K_C=p.K_C, r0=p.r0, v_max=p.v_max,
+                      tau_hist=p.traction_history(), wdot0=p.wdot0(), trace_cap=p.steps))
+    sites = np.array(g["sites"])
+    snaps = {}
+    done = 0
+    for n in sorted(int(k) for k in g["snapshots"]):
+        s.step(n - done)
+        done = n
+        w, wd = s.fields()
+        snaps[n] = (w[sites[:, 1], sites[:, 0]], wd[sites[:, 1], sites[:, 0]])
+    tr = s.traces()
+    ev = s.cut_events()
+    s.close()
+    return p, snaps, tr, ev
+
+
+def test_sif_workload_fp64_reproduces_the_oracle(sif_golden):
+    """FP64: same fields (1e-12 of max|w|), K trace within 1e-12, the same
+    3072 cut events at the same steps."""
+    g = sif_golden
+    say("4096x2048 K criterion, FP64, 20000 steps")
+    p, snaps, tr, ev = run_sif("f64", g)
+    for n, (w, wd) in snaps.items():
+        ref = g["snapshots"][str(n)]
+        e = np.abs(w - np.array(ref["w"])).max() / ref["w_absmax"]
+        say(f"  step {n}: sampled w rel err {e:.2e}")
+        assert e <= 1e-12
+    K_ref = np.array(g["K"])
+    ok = ~np.isnan(K_ref)
+    kerr = np.abs(tr["K"][ok] - K_ref[ok]).max() / np.abs(K_ref[ok]).max()
+    say(f"  K rel err {kerr:.2e}; events {len(ev)} vs {len(g['events'])}")
+    assert kerr <= 1e-12
+    assert ev.tolist() == g["events"]
+    np.testing.assert_allclose(tr["tip"], g["tip"], rtol=0, atol=1e-9)
+
+
+def test_sif_workload_fp32_cut_sequence_and_margins(sif_golden):
+    """FP32: fields within 1e-5 before the crack grows; the cut sequence
+    equals the oracle's up to the first step at which the oracle's guard
+    margin |K/K_C - 1| falls inside the measured FP32 K error band."""
+    g = sif_golden
+    say("4096x2048 K criterion, FP32 (shifted storage), 20000 steps")
+    p, snaps, tr, ev = run_sif("f32", g)
+    first_growth = int(np.argmax((np.array(g["flags"]) & 1) != 0))
+    for n, (w, wd) in snaps.items():
+        ref = g["snapshots"][str(n)]
+        e = np.abs(w - np.array(ref["w"])).max() / ref["w_absmax"]
+        say(f"  step {n}: sampled w rel err {e:.2e}")
+        if n < first_growth:
+            assert e <= 1e-5
+    K_ref = np.array(g["K"])
+    ok = ~np.isnan(K_ref)
+    pre = ok & (np.arange(len(K_ref)) < first_growth)
+    kerr = np.abs(tr["K"][pre] - K_ref[pre]).max() / np.abs(K_ref[pre]).max()
+    margin = np.abs(K_ref / p.K_C - 1)
+    band = 10 * kerr
+    risky = np.nonzero(ok & (margin < band))[0]
+    horizon = int(risky[0]) if len(risky) else len(K_ref)
+    ref_ev = [e for e in g["events"] if e[0] < horizon]
+    got_ev = [e for e in ev.tolist() if e[0] < horizon]
+    same = 0
+    for a, b in zip(ref_ev, ev.tolist()):
+        if a != b:
+            break
+        same += 1
+    say(f"  pre-growth K rel err {kerr:.2e}; first step with margin < {band:.1e}: {horizon}; "
+        f"events identical before it: {got_ev == ref_ev} ({len(ref_ev)}); leading identical "
+        f"events overall: {same} of {len(g['events'])}")
+    assert got_ev == ref_ev
+    assert kerr <= 1e-5
