@@ -32,8 +32,12 @@ METRIC = "GLUPS and % of HBM roofline, fp16-storage vs fp32 at stated K_III erro
 
 
 def plate_config(p, storage, trace_cap):
+    """Solver config of plate p; a storage name ending in "-sr" selects
+    stochastic rounding of the 16-bit stores."""
     from paper_2206_12412_amd import Config
-    return Config(nx=p.nx, ny=p.ny, storage=storage, kappa=p.kappa, mu=p.mu, rho=p.rho,
+    rounding = "stochastic" if storage.endswith("-sr") else "nearest"
+    storage = storage[:-3] if storage.endswith("-sr") else storage
+    return Config(nx=p.nx, ny=p.ny, storage=storage, rounding=rounding, kappa=p.kappa, mu=p.mu, rho=p.rho,
                   has_crack=True, crack_x0=p.crack_x0, crack_tip=p.crack_tip, growth=p.growth,
                   v_rel=p.v_rel, K_C=p.K_C, r0=p.r0, v_max=p.v_max,
                   tau_hist=p.traction_history(), wdot0=p.wdot0(), trace_cap=trace_cap)
@@ -61,7 +65,13 @@ def traffic_for(storage: str, workload: str, sites: int):
     return t.get("bytes_per_launch")
 
 
-def run_storage(p, storage, steps, warmup, torch, timing=True):
+def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None):
+    """Time `steps` steps of plate p in this storage.  The run is cut at the
+    checkpoints, where w is exported (outside the timed intervals); each
+    segment is timed with HIP events on the solver's stream between two
+    synchronisations, and the step time is the sum over the segments.  With
+    a reference run, the field errors against its snapshots are returned
+    instead of the snapshots."""
     from paper_2206_12412_amd import Solver
     # warm-up on a throw-away plate (clocks, code objects, page tables)
     if warmup > 0:
@@ -73,17 +83,31 @@ def run_storage(p, storage, steps, warmup, torch, timing=True):
         torch.cuda.empty_cache()
     s = Solver(plate_config(p, storage, steps))
     torch.cuda.synchronize()
-    if timing:
-        s.timing(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(s.stream)
-    s.step(steps)
-    stop.record(s.stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    tm = s.timing(False) if timing else None
+    s.timing(True)
+    ms = 0.0
+    done = 0
+    snaps, errs = {}, {}
+    for n in checkpoints:
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(s.stream)
+        s.step(n - done)
+        stop.record(s.stream)
+        torch.cuda.synchronize()
+        ms += start.elapsed_time(stop)
+        done = n
+        w = s.fields()[0]
+        if ref is None:
+            snaps[n] = w
+        else:
+            r = ref["snaps"][n]
+            d = w - r
+            rms_r = float(np.sqrt(np.mean(r * r)))
+            errs[n] = {"rms_rel": float(np.sqrt(np.mean(d * d))) / rms_r if rms_r > 0 else None,
+                       "max_rel": float(np.abs(d).max() / np.abs(r).max()) if rms_r > 0 else None}
+        del w
+    tm = s.timing(False)
     out = {
         "ms": ms,
         "glups": p.sites * steps / (ms * 1e-3) / 1e9,
@@ -92,9 +116,10 @@ def run_storage(p, storage, steps, warmup, torch, timing=True):
         "launch": s.launch(),
         "K": s.sif(0, steps),
         "tip": s.traces(0, steps)["tip"],
-        "w": s.fields()[0],
+        "snaps": snaps,
+        "field_errors": errs,
     }
-    if tm is not None and tm["steps"]:
+    if tm["steps"]:
         out["interior_ms"] = tm["interior_ms"] / tm["steps"]
         out["boundary_ms"] = tm["boundary_ms"] / tm["steps"]
         out["crack_ms"] = tm["crack_ms"] / tm["steps"]
@@ -102,6 +127,29 @@ def run_storage(p, storage, steps, warmup, torch, timing=True):
     del s
     torch.cuda.empty_cache()
     return out
+
+
+def k_errors(K, K_ref):
+    """K_III error statistics against the reference trace (steps where the
+    reference K is defined and non-zero)."""
+    ok = ~np.isnan(K_ref) & (K_ref != 0)
+    if not ok.any():
+        return {"K_err_rel_max": None}
+    Kmax = np.abs(K_ref[ok]).max()
+    d = np.abs(K - K_ref)
+    # the closing tenth of the run, where K is fully developed
+    late = ok & (np.arange(len(K_ref)) >= int(0.9 * len(K_ref)))
+    strong = ok & (np.abs(K_ref) >= 0.5 * Kmax)
+    return {
+        # max_n |K_n - K_n^ref| / max_n |K^ref|
+        "K_err_rel_max": float(d[ok].max() / Kmax),
+        # |K - K^ref| / |K^ref| at the last step
+        "K_err_rel_final": float(d[-1] / abs(K_ref[-1])) if ok[-1] else None,
+        # max_n |K_n - K_n^ref| / |K_n^ref| over the closing tenth of the run
+        "K_err_rel_late_max": float((d[late] / np.abs(K_ref[late])).max()) if late.any() else None,
+        # the same over every step with |K^ref| >= max |K^ref| / 2
+        "K_err_rel_strong_max": float((d[strong] / np.abs(K_ref[strong])).max()),
+    }
 
 
 def cpu_baseline(p, budget_s: float):
@@ -182,7 +230,7 @@ def run_batched(args, torch):
         equal_pers += int(np.array_equal(w1, bp.plates[k].fields()[0]))
         s1.close()
         del s1
-    bps = 2.0 * (5 * {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[storage] +
+    bps = 2.0 * (5 * {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[storage.replace("-sr", "")] +
                  (8 if storage == "f64" else 4))
     g = lambda ms: sites * steps / (ms * 1e-3) / 1e9  # noqa: E731
     best_ms = min(ms_step, ms_pers)
@@ -262,7 +310,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
         out[counter] = {"KiB_per_launch": kib, "copy_KiB": copy, "factor": factor,
                         "bytes_per_launch": kib * 1024.0 * factor, "launches": len(vals)}
         total += kib * 1024.0 * factor
-    e = {"f64": 8, "f32": 4, "f32plain": 4, "f16s": 2, "bf16s": 2}[storage]
+    e = {"f64": 8, "f32": 4, "f32plain": 4, "f16s": 2, "bf16s": 2}[storage.replace("-sr", "")]
     we = 8 if storage == "f64" else 4
     interior = p.nx * (p.ny - 4)
     out["bytes_per_launch"] = total
@@ -293,8 +341,9 @@ def main():
                     choices=["precision", "sif", "plain", "batched"])
     ap.add_argument("--batch-storage", default="f32", help="storage of the batched workload")
     ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch shape")
-    ap.add_argument("--storage", default="f16s")
-    ap.add_argument("--compare", default="f64,f32,f16s,bf16s",
+    ap.add_argument("--storage", default="f16s-sr",
+                    help='headline storage; a "-sr" suffix selects stochastic rounding')
+    ap.add_argument("--compare", default="f64,f32,f16s,f16s-sr,bf16s,bf16s-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -348,18 +397,17 @@ def main():
         print(f"calibration copy of {n} bytes done", file=sys.stderr, flush=True)
         del a, b
 
+    checkpoints = sorted({int(round(steps * f)) for f in (0.25, 0.5, 0.75, 1.0)} - {0})
     results = {}
+    ref = None
     for st in storages:
         print(f"bench: {p.name} storage={st} steps={steps} warmup={args.warmup}", file=sys.stderr,
               flush=True)
-        results[st] = run_storage(p, st, steps, args.warmup, torch)
+        results[st] = run_storage(p, st, steps, args.warmup, torch, checkpoints, ref)
+        if ref is None:
+            ref = results[st]
         print(f"bench: {st}: {results[st]['glups']:.1f} GLUPS", file=sys.stderr, flush=True)
 
-    ref = results[ref_name]
-    ok = ~np.isnan(ref["K"])
-    Kscale = np.abs(ref["K"][ok]).max() if ok.any() else 0.0
-    if not Kscale > 0:  # nothing has reached the crack yet
-        ok[:] = False
     per = {}
     for st, r in results.items():
         e = {"glups": round(r["glups"], 2), "ms_per_step": round(r["ms"] / steps, 4),
@@ -372,15 +420,11 @@ def main():
             e["interior_GBps"] = round(gbs, 1)
             e["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
         if st != ref_name:
-            dK = np.abs(r["K"][ok] - ref["K"][ok])
-            e["K_err_rel_max"] = float(dK.max() / Kscale) if ok.any() else None
-            e["K_err_rel_final"] = float(abs(r["K"][-1] - ref["K"][-1]) / abs(ref["K"][-1])) \
-                if ok[-1] and ref["K"][-1] != 0 else None
-            dw = r["w"] - ref["w"]
-            e["w_err_rel_max"] = float(np.abs(dw).max() / np.abs(ref["w"]).max())
-            e["w_err_rel_rms"] = float(np.sqrt(np.mean(dw * dw)) / np.sqrt(np.mean(ref["w"] ** 2)))
+            e.update(k_errors(r["K"], ref["K"]))
+            e["field_err_vs_" + ref_name] = {str(n): v for n, v in r["field_errors"].items()}
             e["tip_path_identical"] = bool(np.array_equal(r["tip"], ref["tip"]))
         per[st] = e
+    ref["snaps"].clear()
 
     head = results[args.storage]
     bps = head["bytes_per_site"]
@@ -408,12 +452,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": p.name, "nx": p.nx, "ny": p.ny, "crack_sites": p.ell,
                    "growth": "prescribed" if p.growth == 1 else "sif", "v_rel": p.v_rel,
-                   "tau": p.tau, "storage": args.storage, "parallelism": "single-gpu"},
+                   "tau": p.tau, "storage": args.storage.replace("-sr", ""),
+                   "rounding": "stochastic" if args.storage.endswith("-sr") else "nearest",
+                   "parallelism": "single-gpu"},
         "storages": per,
         "error_reference": ref_name,
     }
     if "f32" in results and args.storage != "f32":
         line["vs_f32_glups"] = round(head["glups"] / results["f32"]["glups"], 3)
+    if args.storage != ref_name:
+        line["K_III_error"] = {k: v for k, v in per[args.storage].items() if k.startswith("K_err")}
     line["roofline"] = roofline
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)

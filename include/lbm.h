@@ -68,6 +68,14 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_F3
 enum lbm_growth { LBM_GROW_NONE = 0, LBM_GROW_PRESCRIBED = 1, LBM_GROW_SIF = 2 };
 enum lbm_bc { LBM_BC_WALLS = 0, LBM_BC_PERIODIC = 1 /* both axes wrap; no edge loads */ };
 enum lbm_flags { LBM_FLAG_GREW = 1, LBM_FLAG_WALL = 2, LBM_FLAG_K_UNDEF = 4 };
+/* Rounding of the FP32 results to the 16-bit storages (LBM_F16S, LBM_BF16S).
+ * NEAREST: round to nearest even.  STOCHASTIC: round up or down to a
+ * neighbouring 16-bit value with probability proportional to the distance
+ * (12 random bits per value from a counter-based hash of the plate-local site
+ * index, the step and cfg->seed; FP16 values below 2^-14 round to nearest),
+ * so that rounding errors do not accumulate coherently over steps.  Results
+ * stay deterministic: they depend on (site, step, seed), not on the launch. */
+enum lbm_rounding { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
 
 typedef struct lbm_config {
   int32_t nx, ny;          /* sites; ny even and >= 2 when there is a crack      */
@@ -91,6 +99,8 @@ typedef struct lbm_config {
   const double *w0;        /* host [ny][nx] initial displacement, NULL = 0       */
   const double *wdot0;     /* host [ny][nx] initial velocity, NULL = 0           */
   int64_t trace_cap;       /* per-step K / tip / speed traces kept on device     */
+  int32_t rounding;        /* enum lbm_rounding; 16-bit storages only            */
+  uint32_t seed;           /* seed of the stochastic rounding                    */
   void *dev_buf;           /* device memory, >= lbm_state_bytes(cfg), 256-aligned */
   size_t dev_bytes;
   void *stream;            /* hipStream_t; NULL = the null stream                */
@@ -173,6 +183,16 @@ int64_t lbm_interior_sites(const lbm_handle *h);
 int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves,
                    int32_t *occupancy);
 int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy);
+
+/* The 16-bit store conversion of the sweep, applied to an array (for
+ * inspection and tests of the storage formats): out[i] is the value the sweep
+ * of step `step` with seed `seed` stores for a result x[i] at plate-local site
+ * index i (i = j nx + i_x) of population plane `plane` (0..4).  storage is
+ * LBM_F16S or LBM_BF16S, rounding an enum lbm_rounding.  x (FP32) and out
+ * (n 16-bit values) are device pointers; enqueued on `stream` (hipStream_t,
+ * NULL = the null stream). */
+int lbm_round16(const float *x, void *out, int64_t n, int32_t storage, int32_t rounding,
+                int32_t plane, uint32_t seed, int64_t step, void *stream);
 
 /* Launch-shape search.  Times every shape of a fixed grid (rows in {1, 2, 4,
  * 8}, waves in {1, 2, 4, 8}, occupancy in {0, 2, 3, 4, 5, 6}) over trial_steps

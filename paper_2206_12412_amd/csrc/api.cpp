@@ -151,6 +151,10 @@ int validate(const lbm_config *c, Store *s) {
     return fail(LBM_EINVAL, "K criterion needs K_C > 0 and v_max in [0, 1)");
   if (c->n_hist < 0 || (c->n_hist > 0 && !c->tau_hist)) return fail(LBM_EINVAL, "bad traction history");
   if (c->trace_cap < 0) return fail(LBM_EINVAL, "negative trace_cap");
+  if (c->rounding != LBM_ROUND_NEAREST && c->rounding != LBM_ROUND_STOCHASTIC)
+    return fail(LBM_EINVAL, "unknown rounding %d", c->rounding);
+  if (c->rounding == LBM_ROUND_STOCHASTIC && c->storage != LBM_F16S && c->storage != LBM_BF16S)
+    return fail(LBM_EINVAL, "stochastic rounding applies to the 16-bit storages only");
   return LBM_OK;
 }
 
@@ -260,6 +264,8 @@ int launch_sweep_typed(lbm_handle *h, int part) {
     a.skip_lo = 1;
     a.skip_hi = 0;
   }
+  a.sr = h->cfg.rounding == LBM_ROUND_STOCHASTIC;
+  a.rkey = lbmk::step_key(h->cfg.seed, h->step);
   HIP_TRY(lbmk::launch_sweep(h->store, &a, part, h->stream));
   return LBM_OK;
 }
@@ -697,6 +703,20 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
   return LBM_OK;
 }
 
+int lbm_round16(const float *x, void *out, int64_t n, int32_t storage, int32_t rounding,
+                int32_t plane, uint32_t seed, int64_t step, void *stream) {
+  if (n < 0 || (n > 0 && (!x || !out))) return fail(LBM_EINVAL, "bad arrays");
+  if (n > (int64_t)UINT32_MAX) return fail(LBM_EINVAL, "site indices are 32-bit");
+  if (storage != LBM_F16S && storage != LBM_BF16S) return fail(LBM_EINVAL, "16-bit storages only");
+  if (rounding != LBM_ROUND_NEAREST && rounding != LBM_ROUND_STOCHASTIC)
+    return fail(LBM_EINVAL, "unknown rounding %d", rounding);
+  if (plane < 0 || plane > 4) return fail(LBM_EINVAL, "plane must be in 0..4");
+  const Store s = storage == LBM_F16S ? Store::F16S : Store::BF16S;
+  HIP_TRY(lbmk::launch_round16(s, rounding == LBM_ROUND_STOCHASTIC, x, out, n, plane,
+                               lbmk::step_key(seed, step), static_cast<hipStream_t>(stream)));
+  return LBM_OK;
+}
+
 int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *rows, int32_t *waves,
                  int32_t *occupancy, double *ms_per_step) {
   if (!h) return fail(LBM_EINVAL, "null handle");
@@ -753,6 +773,7 @@ struct lbm_batch {
   double t_ms = 0;
   int64_t n_timed = 0;
   int persistent_blocks = 0;
+  int sr = 0;  // stochastic rounding (same for every plate)
 };
 
 namespace {
@@ -771,6 +792,8 @@ int batch_layout(const lbm_config *cfgs, int32_t n, BatchLayout *B, Store *store
     if (rc != LBM_OK) return fail(rc, "plate %d: %s", k, g_err.c_str());
     if (k == 0) *store = s;
     else if (s != *store) return fail(LBM_EINVAL, "plate %d: every plate of a batch needs the same storage", k);
+    if (cfgs[k].rounding != cfgs[0].rounding)
+      return fail(LBM_EINVAL, "plate %d: every plate of a batch needs the same rounding", k);
     B->off_plate.push_back(o);
     o += align_up(make_layout(cfgs[k], s).total, 256);
   }
@@ -812,6 +835,7 @@ int batch_build_desc(lbm_batch *b) {
     d.tau = reinterpret_cast<const double *>(b->base + b->off_tau_plate[k]);
     d.n_hist = (int64_t)h->tau.size();
     d.has_crack = h->cfg.has_crack;
+    d.seed = h->cfg.seed;
     d.skip_lo = h->cfg.has_crack ? h->plate.j0 : 1;
     d.skip_hi = h->cfg.has_crack ? h->plate.j0 + 1 : 0;
     // the same task maps as the single-plate kernels (sweep_core.hpp)
@@ -886,6 +910,7 @@ int lbm_batch_init(const lbm_config *cfgs, int32_t n, void *dev_buf, size_t dev_
   if (dev_bytes < B.total) return fail(LBM_ENOMEM, "dev_bytes %zu < required %zu", dev_bytes, B.total);
   lbm_batch *b = new lbm_batch();
   b->store = s;
+  b->sr = cfgs[0].rounding == LBM_ROUND_STOCHASTIC;
   b->stream = static_cast<hipStream_t>(stream);
   b->base = static_cast<char *>(dev_buf);
   b->off_plate = B.off_plate;
@@ -937,7 +962,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
         return fail(LBM_EHIP, "event creation failed");
       HIP_TRY(hipEventRecord(e0, b->stream));
     }
-    HIP_TRY(lbmk::launch_batch_step(b->store, d, (int)b->plates.size(), b->n_int, b->n_bnd, b->cur,
+    HIP_TRY(lbmk::launch_batch_step(b->store, b->sr, d, (int)b->plates.size(), b->n_int, b->n_bnd, b->cur,
                                     b->step, b->waves, lds, b->stream));
     if (b->timing) {
       HIP_TRY(hipEventRecord(e1, b->stream));
@@ -965,7 +990,7 @@ int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps) {
     HIP_TRY(hipEventRecord(e0, b->stream));
   }
   int blocks = 0;
-  hipError_t e = lbmk::launch_batch_persistent(b->store, d, (int)b->plates.size(), b->n_int, b->n_bnd,
+  hipError_t e = lbmk::launch_batch_persistent(b->store, b->sr, d, (int)b->plates.size(), b->n_int, b->n_bnd,
                                                b->cur, b->step, nsteps, sync, &blocks, b->stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
   b->persistent_blocks = blocks;

@@ -58,10 +58,12 @@ __device__ __forceinline__ SweepArgs<S, W, C> args_of(const BatchPlate &d, int c
   a.lds_bytes = 0;
   a.skip_lo = d.skip_lo;
   a.skip_hi = d.skip_hi;
+  a.sr = 0;  // the kernel's SR template argument decides
+  a.rkey = step_key(d.seed, step);
   return a;
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 __device__ __forceinline__ void interior_task(const BatchPlate *__restrict__ d, int n, int64_t task,
                                               int cur, int64_t step) {
   const int k = plate_of(d, n, task, true);
@@ -79,10 +81,10 @@ __device__ __forceinline__ void interior_task(const BatchPlate *__restrict__ d, 
   }
   if (jb > jlast) return;
   const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
-  core::interior_rows<S, W, C, VEC, SHIFT>(a.fin, a.fout, a.win, a.wout, a, strip, jb, jlast);
+  core::interior_rows<S, W, C, VEC, SHIFT, SR>(a.fin, a.fout, a.win, a.wout, a, strip, jb, jlast);
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 __device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, int n, int64_t task,
                                               int cur, int64_t step) {
   const int k = plate_of(d, n, task, false);
@@ -92,7 +94,7 @@ __device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, 
   const int r = (int)(local / q.n_strips);
   const int j = q.brow[r];
   const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
-  core::boundary_row<S, W, C, VEC, SHIFT>(a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a,
+  core::boundary_row<S, W, C, VEC, SHIFT, SR>(a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a,
                                          strip, j);
 }
 
@@ -103,23 +105,23 @@ __device__ __forceinline__ void crack_task(const BatchPlate *__restrict__ d, int
   core::crack_step_wave(c);
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 __global__ void __launch_bounds__(512)
 batch_interior(const BatchPlate *__restrict__ d, int n, int64_t n_tasks, int cur, int64_t step,
                int waves) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t task = (int64_t)blockIdx.x * waves + wave;
   if (task >= n_tasks) return;
-  interior_task<S, W, C, VEC, SHIFT>(d, n, task, cur, step);
+  interior_task<S, W, C, VEC, SHIFT, SR>(d, n, task, cur, step);
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 __global__ void __launch_bounds__(256)
 batch_boundary(const BatchPlate *__restrict__ d, int n, int64_t n_tasks, int cur, int64_t step) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t task = (int64_t)blockIdx.x * 4 + wave;
   if (task >= n_tasks) return;
-  boundary_task<S, W, C, VEC, SHIFT>(d, n, task, cur, step);
+  boundary_task<S, W, C, VEC, SHIFT, SR>(d, n, task, cur, step);
 }
 
 __global__ void __launch_bounds__(256) batch_crack(const BatchPlate *__restrict__ d, int n, int cur) {
@@ -157,7 +159,7 @@ __device__ __forceinline__ void grid_barrier(unsigned *sync, unsigned nblocks) {
   __syncthreads();
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 __global__ void __launch_bounds__(256)
 batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t n_bnd, int cur0,
                  int64_t step0, int64_t nsteps, unsigned *sync) {
@@ -168,8 +170,8 @@ batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t
     const int cur = (int)((cur0 + s) & 1);
     const int64_t step = step0 + s;
     for (int64_t t = gw; t < n_int + n_bnd; t += nw) {
-      if (t < n_int) interior_task<S, W, C, VEC, SHIFT>(d, n, t, cur, step);
-      else boundary_task<S, W, C, VEC, SHIFT>(d, n, t - n_int, cur, step);
+      if (t < n_int) interior_task<S, W, C, VEC, SHIFT, SR>(d, n, t, cur, step);
+      else boundary_task<S, W, C, VEC, SHIFT, SR>(d, n, t - n_int, cur, step);
     }
     grid_barrier(sync, gridDim.x);
     for (int64_t k = gw; k < n; k += nw) crack_task(d, (int)k, cur);
@@ -177,28 +179,28 @@ batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t
   }
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 hipError_t step_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur, int64_t step,
                   int waves, int lds, hipStream_t st) {
   if (n_int > 0) {
     const unsigned blocks = (unsigned)((n_int + waves - 1) / waves);
-    hipLaunchKernelGGL((batch_interior<S, W, C, VEC, SHIFT>), dim3(blocks), dim3(64 * waves), lds, st,
+    hipLaunchKernelGGL((batch_interior<S, W, C, VEC, SHIFT, SR>), dim3(blocks), dim3(64 * waves), lds, st,
                        d, n, n_int, cur, step, waves);
   }
   if (n_bnd > 0) {
     const unsigned blocks = (unsigned)((n_bnd + 3) / 4);
-    hipLaunchKernelGGL((batch_boundary<S, W, C, VEC, SHIFT>), dim3(blocks), dim3(256), 0, st, d, n,
+    hipLaunchKernelGGL((batch_boundary<S, W, C, VEC, SHIFT, SR>), dim3(blocks), dim3(256), 0, st, d, n,
                        n_bnd, cur, step);
   }
   hipLaunchKernelGGL(batch_crack, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, d, n, cur);
   return hipGetLastError();
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 hipError_t persistent_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
                         int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
                         hipStream_t st) {
-  auto kernel = batch_persistent<S, W, C, VEC, SHIFT>;
+  auto kernel = batch_persistent<S, W, C, VEC, SHIFT, SR>;
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -217,30 +219,54 @@ hipError_t persistent_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd
                                     args, 0, st);
 }
 
+// stochastic rounding exists for the 16-bit storages only
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+hipError_t step_r(int sr, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
+                  int64_t step, int waves, int lds, hipStream_t st) {
+  if constexpr (sizeof(S) == 2) {
+    if (sr) return step_t<S, W, C, VEC, SHIFT, true>(d, n, n_int, n_bnd, cur, step, waves, lds, st);
+  }
+  return step_t<S, W, C, VEC, SHIFT, false>(d, n, n_int, n_bnd, cur, step, waves, lds, st);
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+hipError_t persistent_r(int sr, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
+                        int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
+                        hipStream_t st) {
+  if constexpr (sizeof(S) == 2) {
+    if (sr)
+      return persistent_t<S, W, C, VEC, SHIFT, true>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
+                                                     blocks_used, st);
+  }
+  return persistent_t<S, W, C, VEC, SHIFT, false>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
+                                                  blocks_used, st);
+}
+
 }  // namespace
 
-hipError_t launch_batch_step(Store s, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+hipError_t launch_batch_step(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                              int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
                              hipStream_t st) {
   switch (s) {
-    case Store::F64: return step_t<double, double, double, 2, false>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F32_PLAIN: return step_t<float, float, float, 4, false>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F32S: return step_t<float, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F16S: return step_t<_Float16, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::BF16S: return step_t<__bf16, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F64: return step_r<double, double, double, 2, false>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F32_PLAIN: return step_r<float, float, float, 4, false>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F32S: return step_r<float, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F16S: return step_r<_Float16, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::BF16S: return step_r<__bf16, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_persistent(Store s, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
-                                   int64_t n_bnd_tasks, int cur, int64_t step, int64_t nsteps,
-                                   unsigned *sync, int *blocks_used, hipStream_t st) {
+hipError_t launch_batch_persistent(Store s, int sr, const BatchPlate *d, int n_plates,
+                                   int64_t n_int_tasks, int64_t n_bnd_tasks, int cur, int64_t step,
+                                   int64_t nsteps, unsigned *sync, int *blocks_used,
+                                   hipStream_t st) {
   switch (s) {
-    case Store::F64: return persistent_t<double, double, double, 2, false>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
-    case Store::F32_PLAIN: return persistent_t<float, float, float, 4, false>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
-    case Store::F32S: return persistent_t<float, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
-    case Store::F16S: return persistent_t<_Float16, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
-    case Store::BF16S: return persistent_t<__bf16, float, float, 4, true>(d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F64: return persistent_r<double, double, double, 2, false>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F32_PLAIN: return persistent_r<float, float, float, 4, false>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F32S: return persistent_r<float, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F16S: return persistent_r<_Float16, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::BF16S: return persistent_r<__bf16, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
   }
   return hipErrorInvalidValue;
 }

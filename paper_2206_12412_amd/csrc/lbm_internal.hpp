@@ -73,7 +73,23 @@ struct SweepArgs {
   // rows the interior kernel leaves to the boundary kernel besides the two
   // edge rows: the rows next to severable links (crack rows), lo > hi = none
   int skip_lo, skip_hi;
+  int sr;            // 16-bit storage: stochastic rounding of the stores
+  uint32_t rkey;     // per-step key of the rounding bits (step_key)
 };
+
+// Counter-based randomness of the stochastic rounding: the integer hash
+// "lowbias32" (C. Wellons' hash-prospector, 2018), and the key of one step.
+__host__ __device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__host__ __device__ inline uint32_t step_key(uint32_t seed, int64_t step) {
+  return mix32(mix32(seed ^ 0x9e3779b9u) ^ (uint32_t)step ^ mix32((uint32_t)(step >> 32)));
+}
 
 struct CrackArgs {
   DevCrack *st;
@@ -102,6 +118,7 @@ struct BatchPlate {
   const double *tau;    // device copy of the traction history
   int64_t n_hist;
   int has_crack, skip_lo, skip_hi;
+  uint32_t seed;        // stochastic rounding seed (the batch decides whether it is used)
   // task maps (same fields as the single-plate maps)
   int n_strips, rows, lo1, hi1, lo2, hi2, nc1, nc2;
   int nb, brow[4];
@@ -117,6 +134,9 @@ int sweep_vec(Store s);  // sites per lane
 hipError_t launch_sweep(Store s, const void *args, int part, hipStream_t st);
 // sites the interior kernel updates
 int64_t interior_sites(const Plate &p, int skip_lo, int skip_hi);
+// the 16-bit store conversion of the sweep applied to x[0..n) (F16S / BF16S)
+hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n, int plane,
+                          uint32_t rkey, hipStream_t st);
 
 // ---- launchers (crack.hip) ----
 hipError_t launch_crack(const CrackArgs &a, hipStream_t st);
@@ -126,13 +146,13 @@ hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const P
 // ---- launchers (batch.hip) ----
 // One step of every plate: batched interior kernel, batched boundary kernel,
 // batched crack kernel.  cur = parity of the source buffers, step = step index.
-hipError_t launch_batch_step(Store s, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+hipError_t launch_batch_step(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                              int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
                              hipStream_t st);
 // nsteps steps in one cooperative launch with grid barriers; sync[0..3] is a
 // zeroed device scratch (barrier counter, generation, error flag).  Returns
 // hipErrorCooperativeLaunchTooLarge if the grid cannot be co-resident.
-hipError_t launch_batch_persistent(Store s, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+hipError_t launch_batch_persistent(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                                    int64_t n_bnd_tasks, int cur, int64_t step, int64_t nsteps,
                                    unsigned *sync, int *blocks_used, hipStream_t st);
 

@@ -123,6 +123,83 @@ __device__ __forceinline__ void store_row(S *__restrict__ base, uint32_t off, co
   }
 }
 
+// Stochastic rounding to 16 bits with 12 random bits r (0..4095): adding r,
+// scaled to the width of the dropped mantissa field, to the FP32 bit pattern
+// and truncating rounds the magnitude up with probability (dropped part) /
+// (16-bit ulp), which makes the rounding unbiased.  In the FP16 subnormal
+// range (|x| < 2^-14, fixed ulp 2^-24) the same is done on the magnitude in
+// units of 2^-24: floor(|x| 2^24 + r / 4096), exact in FP32 there.
+template <typename S> __device__ __forceinline__ S round_sr(float x, uint32_t r);
+template <> __device__ __forceinline__ _Float16 round_sr<_Float16>(float x, uint32_t r) {
+  const uint32_t b = (__float_as_uint(x) + (r << 1)) & 0xffffe000u;
+  const float q = __builtin_floorf(__builtin_fabsf(x) * 0x1p24f + (float)r * 0x1p-12f) * 0x1p-24f;
+  const float y = (__builtin_fabsf(x) >= 0x1p-14f) ? __uint_as_float(b) : __builtin_copysignf(q, x);
+  return static_cast<_Float16>(y);  // exact
+}
+template <> __device__ __forceinline__ __bf16 round_sr<__bf16>(float x, uint32_t r) {
+  const uint32_t b = (__float_as_uint(x) + (r << 4)) & 0xffff0000u;
+  return static_cast<__bf16>(__uint_as_float(b));  // exact
+}
+
+template <typename S, typename C, int VEC>
+__device__ __forceinline__ void store_row_sr(S *__restrict__ base, uint32_t off, const C (&in)[VEC],
+                                             const uint32_t (&r)[VEC]) {
+  Pack<S, VEC> pk;
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) pk.v[k] = round_sr<S>(in[k], r[k]);
+  static_assert(sizeof(pk) == 8, "16-bit rows are stored in 8-byte pieces");
+  u32x2 v;
+  __builtin_memcpy(&v, &pk, 8);
+  __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(at(base, off)));
+}
+
+// The 12-bit rounding draws of the five planes at one site: two hashes of
+// (site, step key); planes 0 and 1 take bits 0..23 of the first, planes 2 and
+// 3 bits 0..23 of the second, plane 4 bits 24..31 of the first and 24..27 of
+// the second.
+__device__ __forceinline__ void sr_draws(uint32_t site, uint32_t rkey, uint32_t (&r)[5]) {
+  const uint32_t h1 = mix32(site ^ rkey);
+  const uint32_t h2 = mix32(h1 ^ 0x68e31da4u);
+  r[0] = h1 & 0xfffu;
+  r[1] = (h1 >> 12) & 0xfffu;
+  r[2] = h2 & 0xfffu;
+  r[3] = (h2 >> 12) & 0xfffu;
+  r[4] = (h1 >> 24) | (((h2 >> 24) & 0xfu) << 8);
+}
+
+// The five population rows of a lane's sites (site0 = plate-local index of
+// the lane's first site).
+template <typename S, typename C, int VEC, bool SR>
+__device__ __forceinline__ void store_pops(S *__restrict__ fout, size_t P, uint32_t o,
+                                           const C (&o0)[VEC], const C (&o1)[VEC],
+                                           const C (&o2)[VEC], const C (&o3)[VEC],
+                                           const C (&o4)[VEC], uint32_t site0, uint32_t rkey) {
+  if constexpr (SR) {
+    uint32_t r0[VEC], r1[VEC], r2[VEC], r3[VEC], r4[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      uint32_t r[5];
+      sr_draws(site0 + k, rkey, r);
+      r0[k] = r[0];
+      r1[k] = r[1];
+      r2[k] = r[2];
+      r3[k] = r[3];
+      r4[k] = r[4];
+    }
+    store_row_sr<S, C, VEC>(fout, o, o0, r0);
+    store_row_sr<S, C, VEC>(fout + P, o, o1, r1);
+    store_row_sr<S, C, VEC>(fout + 2 * P, o, o2, r2);
+    store_row_sr<S, C, VEC>(fout + 3 * P, o, o3, r3);
+    store_row_sr<S, C, VEC>(fout + 4 * P, o, o4, r4);
+  } else {
+    store_row<S, C, VEC>(fout, o, o0);
+    store_row<S, C, VEC>(fout + P, o, o1);
+    store_row<S, C, VEC>(fout + 2 * P, o, o2);
+    store_row<S, C, VEC>(fout + 3 * P, o, o3);
+    store_row<S, C, VEC>(fout + 4 * P, o, o4);
+  }
+}
+
 template <typename C, int VEC>
 __device__ __forceinline__ void zero_row(C (&out)[VEC]) {
 #pragma unroll
@@ -237,7 +314,7 @@ __host__ __device__ inline long boundary_task_count(const BoundaryMap &m) {
 // Rows jb .. jlast of one strip, all of them interior rows (every vertical
 // link intact); the left and right plate edges (or the periodic wrap) and the
 // ragged end of the last strip are per-lane fix-ups.
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR = false>
 __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__restrict__ fout,
                                               const W *__restrict__ win, W *__restrict__ wout,
                                               const SweepArgs<S, W, C> &a, const int strip,
@@ -342,11 +419,7 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
         if (i0 + k > last) o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
     }
     if (act) {
-      store_row<S, C, VEC>(fout, o, o0);
-      store_row<S, C, VEC>(fout + P, o, o1);
-      store_row<S, C, VEC>(fout + 2 * P, o, o2);
-      store_row<S, C, VEC>(fout + 3 * P, o, o3);
-      store_row<S, C, VEC>(fout + 4 * P, o, o4);
+      store_pops<S, C, VEC, SR>(fout, P, o, o0, o1, o2, o3, o4, (uint32_t)j * p.nx + i0, a.rkey);
       store_row<W, C, VEC>(wout, o, wo);
     }
     if (SHIFT) {
@@ -363,7 +436,7 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
 // Row j of one strip with the full boundary treatment: bounce-back at the
 // plate edges and on severed links (read from the cut bitmask in the rows the
 // mask-row range names), traction terms, periodic wrap-around.
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR = false>
 __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__restrict__ fout,
                                              const W *__restrict__ win, W *__restrict__ wout,
                                              const uint32_t *__restrict__ mV,
@@ -483,11 +556,7 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
     }
   }
   if (act) {
-    store_row<S, C, VEC>(fout, o, o0);
-    store_row<S, C, VEC>(fout + P, o, o1);
-    store_row<S, C, VEC>(fout + 2 * P, o, o2);
-    store_row<S, C, VEC>(fout + 3 * P, o, o3);
-    store_row<S, C, VEC>(fout + 4 * P, o, o4);
+    store_pops<S, C, VEC, SR>(fout, P, o, o0, o1, o2, o3, o4, (uint32_t)j * p.nx + i0, a.rkey);
     store_row<W, C, VEC>(wout, o, wo);
   }
 }

@@ -23,6 +23,7 @@ STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S,
            "f32plain": LBM_F32_PLAIN}
 GROW_NONE, GROW_PRESCRIBED, GROW_SIF = 0, 1, 2
 BC_WALLS, BC_PERIODIC = 0, 1
+ROUNDING = {"nearest": 0, "stochastic": 1}
 FLAG_GREW, FLAG_WALL, FLAG_K_UNDEF = 1, 2, 4
 
 ERRORS = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE",
@@ -35,7 +36,7 @@ EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_si
            "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
            "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
            "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
-           "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune")
+           "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune", "lbm_round16")
 
 
 class LBMError(RuntimeError):
@@ -53,7 +54,8 @@ class _Config(C.Structure):
         ("v_max", C.c_double), ("k_band", C.c_int32), ("face_traction", C.c_double),
         ("tau_hist", C.POINTER(C.c_double)), ("n_hist", C.c_int64),
         ("w0", C.POINTER(C.c_double)), ("wdot0", C.POINTER(C.c_double)),
-        ("trace_cap", C.c_int64), ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t),
+        ("trace_cap", C.c_int64), ("rounding", C.c_int32), ("seed", C.c_uint32),
+        ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t),
         ("stream", C.c_void_p),
     ]
 
@@ -116,8 +118,9 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_free.argtypes = [vp]
     lib.lbm_batch_free.restype = None
     lib.lbm_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
+    lib.lbm_round16.argtypes = [vp, vp, i64, i32, i32, i32, C.c_uint32, i64, vp]
     lib.lbm_batch_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
-    for name in ("lbm_autotune", "lbm_batch_autotune", "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
+    for name in ("lbm_round16", "lbm_autotune", "lbm_batch_autotune", "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
                  "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
         getattr(lib, name).restype = i32
     for name in ("lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
@@ -162,6 +165,8 @@ class Config:
     w0: Optional[np.ndarray] = None
     wdot0: Optional[np.ndarray] = None
     trace_cap: int = 0
+    rounding: str = "nearest"      # 16-bit storages: "nearest" or "stochastic"
+    seed: int = 0
 
     def to_c(self, keep: list) -> _Config:
         c = _Config()
@@ -171,6 +176,8 @@ class Config:
         c.storage = STORAGE[self.storage] if isinstance(self.storage, str) else int(self.storage)
         c.bc_mode = BC_PERIODIC if self.periodic else BC_WALLS
         c.has_crack = int(self.has_crack)
+        c.rounding = ROUNDING[self.rounding] if isinstance(self.rounding, str) else int(self.rounding)
+        c.seed = int(self.seed) & 0xFFFFFFFF
         if self.tau_hist is not None:
             t = np.ascontiguousarray(self.tau_hist, dtype=np.float64).ravel()
             keep.append(t)
@@ -190,6 +197,24 @@ class Config:
 def state_bytes(cfg: Config) -> int:
     keep = []
     return int(load_library().lbm_state_bytes(C.byref(cfg.to_c(keep))))
+
+
+def round16(x, storage: str = "f16s", rounding: str = "nearest", plane: int = 0, seed: int = 0,
+            step: int = 0):
+    """lbm_round16 on a CUDA float32 tensor; returns the 16-bit tensor."""
+    import torch
+
+    lib = load_library()
+    x = x.contiguous()
+    if x.dtype != torch.float32 or x.device.type != "cuda":
+        raise ValueError("x must be a float32 tensor on a GPU")
+    out = torch.empty(x.shape, dtype=torch.float16 if storage == "f16s" else torch.bfloat16,
+                      device=x.device)
+    st = torch.cuda.current_stream(x.device)
+    _check(lib.lbm_round16(x.data_ptr(), out.data_ptr(), x.numel(), STORAGE[storage],
+                           ROUNDING[rounding], int(plane), int(seed) & 0xFFFFFFFF, int(step),
+                           st.cuda_stream))
+    return out
 
 
 def _tune(fn, handle, trial_steps: int) -> dict:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "lbm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_and_binding_agree():
@@ -54,6 +54,9 @@ def init_rc(**kw):
     (dict(nx=16, ny=8, has_crack=True, crack_tip=3.5, k_band=0), -1),
     (dict(nx=16, ny=8, storage=9), -1),
     (dict(nx=16, ny=8, periodic=True, has_crack=True, crack_tip=3.5, growth=1, v_rel=0.2), -1),
+    (dict(nx=16, ny=8, storage="f32", rounding="stochastic"), -1),
+    (dict(nx=16, ny=8, storage="f64", rounding="stochastic"), -1),
+    (dict(nx=16, ny=8, storage="f16s", rounding=7), -1),
 ])
 def test_invalid_configurations_fail_before_any_gpu_call(kw, code):
     rc, msg = init_rc(**kw)

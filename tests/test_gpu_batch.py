@@ -24,7 +24,10 @@ def say(msg):
 
 
 def plate_configs(storage, steps, small=True):
-    """Uneven plates: sizes, loads, prescribed speeds and the K criterion."""
+    """Uneven plates: sizes, loads, prescribed speeds and the K criterion.  A
+    storage ending in "-sr" selects stochastic rounding (one seed per plate)."""
+    rounding = "stochastic" if storage.endswith("-sr") else "nearest"
+    storage = storage[:-3] if storage.endswith("-sr") else storage
     rng = np.random.default_rng(5)
     sizes = [(96, 48), (300, 64), (64, 130), (257, 34), (130, 200), (33, 8)] if small else \
         [(512, 512), (1024, 512), (1024, 1024), (2048, 1024)]
@@ -32,7 +35,8 @@ def plate_configs(storage, steps, small=True):
     for k, (nx, ny) in enumerate(sizes):
         ell = max(nx // 4, 1)
         tau = float(rng.uniform(5e-4, 2e-3))
-        c = Config(nx=nx, ny=ny, storage=storage, has_crack=True, crack_tip=ell - 0.5,
+        c = Config(nx=nx, ny=ny, storage=storage, rounding=rounding, seed=100 + k,
+                   has_crack=True, crack_tip=ell - 0.5,
                    tau_hist=np.array([tau]), trace_cap=steps,
                    wdot0=rng.normal(0, 1e-4, (ny, nx)))
         if k % 2 == 0:
@@ -41,8 +45,8 @@ def plate_configs(storage, steps, small=True):
             c.growth, c.K_C = 2, 1.05 * synth.k_static_edge(tau, ell)
         cfgs.append(c)
     # one plate without a crack and one periodic plate
-    cfgs.append(Config(nx=70, ny=20, storage=storage, tau_hist=np.array([1e-3])))
-    cfgs.append(Config(nx=80, ny=24, storage=storage, periodic=True,
+    cfgs.append(Config(nx=70, ny=20, storage=storage, rounding=rounding, tau_hist=np.array([1e-3])))
+    cfgs.append(Config(nx=80, ny=24, storage=storage, rounding=rounding, periodic=True,
                        wdot0=rng.normal(0, 1e-3, (24, 80))))
     return cfgs
 
@@ -59,7 +63,7 @@ def same_state(a, b, label):
         assert a.cut_events().tolist() == b.cut_events().tolist(), label
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64", "f16s"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16s", "f16s-sr", "bf16s-sr"])
 def test_batched_steps_equal_single_plates(storage):
     steps = 150
     cfgs = plate_configs(storage, steps)
@@ -86,7 +90,7 @@ def test_batch_launch_shapes_do_not_change_results():
         same_state(a.plates[k], b.plates[k], f"plate {k}")
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "bf16s-sr"])
 def test_persistent_run_equals_per_step_launches(storage):
     cfgs = plate_configs(storage, 200)
     say(f"persistent batch, {storage}: 2 steps first")
