@@ -101,6 +101,8 @@ typedef struct lbm_config {
   int64_t trace_cap;       /* per-step K / tip / speed traces kept on device     */
   int32_t rounding;        /* enum lbm_rounding; 16-bit storages only            */
   uint32_t seed;           /* seed of the stochastic rounding                    */
+  int32_t n_sensors;       /* sensor sites: w there is recorded after each step  */
+  const int32_t *sensors;  /* host [n_sensors][2] = (i, j), distinct; copied     */
   void *dev_buf;           /* device memory, >= lbm_state_bytes(cfg), 256-aligned */
   size_t dev_bytes;
   void *stream;            /* hipStream_t; NULL = the null stream                */
@@ -145,6 +147,12 @@ int lbm_sif(lbm_handle *h, double *K_out, int64_t first, int64_t count);
  * any output pointer may be NULL. */
 int lbm_traces(lbm_handle *h, double *tip_out, double *v_out, int32_t *flags_out,
                int64_t first, int64_t count);
+
+/* Sensor traces: w at the sensor sites after each step, rows [first,
+ * first + count) of the [trace_cap][n_sensors] FP64 table (row n = after step
+ * n).  out is a host pointer, or a device pointer if out_on_device != 0. */
+int lbm_sensor_traces(lbm_handle *h, double *out, int64_t first, int64_t count,
+                      int32_t out_on_device);
 
 /* Cut events: (step, column) of every link severed by growth, in order;
  * writes min(cap, total) entries and the total into *n. */
@@ -263,6 +271,49 @@ int lbm_batch_timing(lbm_batch *b, int32_t enable, double *ms, int64_t *n_timed)
 int64_t lbm_batch_sites(const lbm_batch *b);
 
 void lbm_batch_free(lbm_batch *b);
+
+/* ------------------------------------------------------------- adjoint --
+ * Discrete adjoint of the steps a handle has taken, for a loss L of its
+ * sensor traces.  One step maps the state s_n = (f_n, w_n) affinely:
+ * s_{n+1} = A_n s_n + b tau_n, where A_n holds the pull streaming with
+ * bounce-back on the links severed at step n (Sec. 3 eq. LBE, Sec. 4.1) and
+ * the collision / Euler update (eq. f-eq, eq. distrib-macro, eq.
+ * integration), and b the traction links of the top (+tau_n) and bottom
+ * (-tau_n) edges.  With lambda_T = (0, dL/dw_T) and
+ *   lambda_n = A_n^T lambda_{n+1} + (0, dL/dw_n),   dL/dtau_n = b^T lambda_{n+1},
+ * the gradient with respect to the initial fields follows from
+ * f_0 = f_eq(w_0, wdot_0).  A_n^T is evaluated as one fused sweep per step:
+ * the transposed local map, then a pull of the adjoint populations along the
+ * reversed lattice directions with the transposed bounce-back (a severed
+ * link returns the adjoint to the opposite direction at the same site).
+ * The links severed at each step come from the recorded cut events, so the
+ * sweep reads no forward state; with the K criterion the cut sequence of the
+ * forward run is held fixed (the derivative of the piecewise affine map on
+ * the path taken).  The adjoint runs in FP64 for LBM_F64 plates and in FP32
+ * otherwise. */
+typedef struct lbm_adjoint lbm_adjoint;
+
+/* Device bytes lbm_adjoint_init needs for handle h (0 if h is invalid). */
+size_t lbm_adjoint_bytes(const lbm_handle *h);
+
+/* Adjoint workspace for handle h in caller-owned device memory (256-byte
+ * aligned), on h's stream.  h must outlive the adjoint object. */
+int lbm_adjoint_init(lbm_handle *h, void *dev_buf, size_t dev_bytes, lbm_adjoint **out);
+
+/* Runs the adjoint through every step h has taken (T = steps, 1 <= T <=
+ * trace_cap).  g: device FP64 [T][n_sensors], g[n][s] = dL/dw at sensor s
+ * after step n (the gradient of L with respect to lbm_sensor_traces).
+ * Outputs (any may be NULL): dL_dtau host [T], the derivative with respect to
+ * the traction tau_n of step n; dL_dwdot0 and dL_dw0 device FP64 [ny][nx],
+ * the derivatives with respect to the initial fields.  Synchronises. */
+int lbm_adjoint_run(lbm_adjoint *a, const double *g, double *dL_dtau, double *dL_dwdot0,
+                    double *dL_dw0);
+
+/* Adjoint kernel time of the last lbm_adjoint_run (ms, HIP events around the
+ * sweeps) and its number of sweeps. */
+int lbm_adjoint_timing(lbm_adjoint *a, double *ms, int64_t *sweeps);
+
+void lbm_adjoint_free(lbm_adjoint *a);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *lbm_last_error(void);

@@ -239,6 +239,44 @@ class Oracle:
         return self._lib.orc_adjoint_step(self._h, _dp(lam_f), _dp(lam_w))
 
 
+def sensor_traces(cfg: OracleConfig, sensors: np.ndarray, steps: int) -> np.ndarray:
+    """w at the sensor sites (i, j) after each of `steps` steps, [steps][n]."""
+    s = Oracle(cfg)
+    sens = np.asarray(sensors).reshape(-1, 2)
+    out = np.empty((steps, len(sens)))
+    for n in range(steps):
+        s.step(1)
+        out[n] = s.fields()[0][sens[:, 1], sens[:, 0]]
+    return out
+
+
+def sensor_adjoint(cfg: OracleConfig, sensors: np.ndarray, g: np.ndarray):
+    """Discrete adjoint of a run of T = len(g) steps for a loss L of the
+    sensor traces with dL/dw_s(after step n) = g[n, s] (the crack must stay
+    where cfg puts it: the adjoint applies the initial mask to every step).
+
+    lambda_T = (0, dL/dw_T); lambda_{n} = A^T lambda_{n+1} + (0, dL/dw_n);
+    dL/dtau_n = b^T lambda_{n+1} (returned by each adjoint step).  The
+    initial state f_0 = f_eq(w_0, wdot_0), i.e. f^0 = wdot_0 - A0 w_0 and
+    f^k = Ak w_0, then gives dL/dwdot_0 = lambda_f^0 and
+    dL/dw_0 = lambda_w - A0 lambda_f^0 + Ak (lambda_f^1 + ... + lambda_f^4).
+    Returns (dL/dtau [T], dL/dwdot_0 [ny][nx], dL/dw_0 [ny][nx])."""
+    s = Oracle(cfg)
+    k = s.constants()
+    sens = np.asarray(sensors).reshape(-1, 2)
+    g = np.asarray(g, dtype=np.float64)
+    T = g.shape[0]
+    lam_f = np.zeros((5, cfg.ny, cfg.nx))
+    lam_w = np.zeros((cfg.ny, cfg.nx))
+    dtau = np.empty(T)
+    for n in range(T, 0, -1):
+        lam_w[sens[:, 1], sens[:, 0]] += g[n - 1]
+        dtau[n - 1] = s.adjoint_step(lam_f, lam_w)
+    dwd0 = lam_f[0].copy()
+    dw0 = lam_w + (-k["A0"] * lam_f[0] + k["Ak"] * (((lam_f[1] + lam_f[2]) + lam_f[3]) + lam_f[4]))
+    return dtau, dwd0, dw0
+
+
 def sif(delta: float, r: float, mu: float = 1.0) -> float:
     """eq. (sif): K = delta (mu/4) sqrt(2 pi / r)."""
     return _load().orc_sif(delta, r, mu)

@@ -48,6 +48,7 @@ struct Layout {
   size_t off_mV = 0, off_mH = 0, off_rf = 0, off_crack = 0;
   size_t off_trK = 0, off_trA = 0, off_trV = 0, off_trF = 0;
   size_t off_evS = 0, off_evC = 0, off_stage = 0;
+  size_t off_sens = 0, off_trS = 0;
   int64_t event_cap = 0;
   int stage_rows = 0;
   size_t total = 0;
@@ -107,6 +108,8 @@ Layout make_layout(const lbm_config &c, Store s) {
   L.event_cap = (int64_t)c.nx + 8;
   L.off_evS = o; o += align_up((size_t)L.event_cap * 8, 256);
   L.off_evC = o; o += align_up((size_t)L.event_cap * 4, 256);
+  L.off_sens = o; o += align_up((size_t)std::max(c.n_sensors, 1) * 8, 256);
+  L.off_trS = o; o += align_up(tc * (size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.stage_rows = (int)std::max<int64_t>(1, std::min<int64_t>(c.ny, (1 << 20) / std::max(1, c.nx)));
   L.off_stage = o;
   o += align_up((size_t)5 * L.stage_rows * c.nx * 8, 256);
@@ -151,6 +154,21 @@ int validate(const lbm_config *c, Store *s) {
     return fail(LBM_EINVAL, "K criterion needs K_C > 0 and v_max in [0, 1)");
   if (c->n_hist < 0 || (c->n_hist > 0 && !c->tau_hist)) return fail(LBM_EINVAL, "bad traction history");
   if (c->trace_cap < 0) return fail(LBM_EINVAL, "negative trace_cap");
+  if (c->n_sensors < 0 || c->n_sensors > (1 << 20) || (c->n_sensors > 0 && !c->sensors))
+    return fail(LBM_EINVAL, "bad sensor list");
+  if (c->n_sensors > 0) {
+    std::vector<int64_t> ids;
+    ids.reserve(c->n_sensors);
+    for (int k = 0; k < c->n_sensors; ++k) {
+      const int i = c->sensors[2 * k], j = c->sensors[2 * k + 1];
+      if (i < 0 || i >= c->nx || j < 0 || j >= c->ny)
+        return fail(LBM_EINVAL, "sensor %d at (%d, %d) is outside the plate", k, i, j);
+      ids.push_back((int64_t)j * c->nx + i);
+    }
+    std::sort(ids.begin(), ids.end());
+    if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+      return fail(LBM_EINVAL, "sensor sites must be distinct");
+  }
   if (c->rounding != LBM_ROUND_NEAREST && c->rounding != LBM_ROUND_STOCHASTIC)
     return fail(LBM_EINVAL, "unknown rounding %d", c->rounding);
   if (c->rounding == LBM_ROUND_STOCHASTIC && c->storage != LBM_F16S && c->storage != LBM_BF16S)
@@ -180,6 +198,9 @@ struct lbm_handle {
   int64_t n_timed = 0;
   lbmk::DevCrack host_crack{};
   bool in_batch = false;  // stepped by a batch; lbm_step refuses it
+  std::vector<int32_t> sensors;  // host copy of the sensor sites
+
+  bool crack_step_needed() const { return cfg.has_crack || cfg.n_sensors > 0; }
 
   void *fbuf(int b) const { return base + L.off_f[b]; }
   void *wbuf(int b) const { return base + L.off_w[b]; }
@@ -294,7 +315,11 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
   a.trF = reinterpret_cast<int32_t *>(h->base + h->L.off_trF);
   a.evStep = reinterpret_cast<int64_t *>(h->base + h->L.off_evS);
   a.evCol = reinterpret_cast<int32_t *>(h->base + h->L.off_evC);
+  a.sens = reinterpret_cast<const int32_t *>(h->base + h->L.off_sens);
+  a.trS = reinterpret_cast<double *>(h->base + h->L.off_trS);
+  a.n_sens = h->cfg.n_sensors;
   a.p = h->plate;
+  a.c.crack = h->cfg.has_crack;
   a.c.growth = h->cfg.growth;
   a.c.band = h->cfg.k_band;
   a.c.v_rel = h->cfg.v_rel;
@@ -405,6 +430,8 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   h->cfg.tau_hist = nullptr;
   h->cfg.w0 = nullptr;
   h->cfg.wdot0 = nullptr;
+  if (cfg->n_sensors > 0) h->sensors.assign(cfg->sensors, cfg->sensors + 2 * (size_t)cfg->n_sensors);
+  h->cfg.sensors = nullptr;
   h->base = static_cast<char *>(cfg->dev_buf);
   // lattice constants (Sec. 3): c = kappa c_s, dt = dh / c with dh = 1,
   // lambda = c_s^2 / (dt (1/omega - 1/2)), f_eq^0 = wdot - A0 w, f_eq^k = Ak w,
@@ -491,6 +518,10 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   }
   if (hipMemcpyAsync(h->crack(), &c0, sizeof c0, hipMemcpyHostToDevice, st) != hipSuccess)
     return bail(fail(LBM_EHIP, "crack state upload failed"));
+  if (!h->sensors.empty() &&
+      hipMemcpyAsync(h->base + L.off_sens, h->sensors.data(), h->sensors.size() * 4,
+                     hipMemcpyHostToDevice, st) != hipSuccess)
+    return bail(fail(LBM_EHIP, "sensor upload failed"));
   if (hipStreamSynchronize(st) != hipSuccess)
     return bail(fail(LBM_EHIP, "init failed: %s", hipGetErrorString(hipGetLastError())));
   *out = h;
@@ -516,7 +547,7 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     rc = launch_sweep_any(h, 1);
     if (rc != LBM_OK) return rc;
     if (h->timing) HIP_TRY(hipEventRecord(ev[2], h->stream));
-    if (h->cfg.has_crack) {
+    if (h->crack_step_needed()) {
       rc = launch_crack_step(h);
       if (rc != LBM_OK) return rc;
     }
@@ -551,9 +582,9 @@ int lbm_crack_state(lbm_handle *h, lbm_crack_info *out) {
   return LBM_OK;
 }
 
-static int check_range(lbm_handle *h, int64_t first, int64_t count) {
+static int check_range(lbm_handle *h, int64_t first, int64_t count, bool need_crack = true) {
   if (!h) return fail(LBM_EINVAL, "null handle");
-  if (!h->cfg.has_crack) return fail(LBM_ESTATE, "no crack: no traces");
+  if (need_crack && !h->cfg.has_crack) return fail(LBM_ESTATE, "no crack: no traces");
   if (first < 0 || count < 0 || first + count > std::min<int64_t>(h->step, h->cfg.trace_cap))
     return fail(LBM_EINVAL, "trace range [%lld, %lld) outside the %lld recorded steps",
                 (long long)first, (long long)(first + count),
@@ -582,6 +613,20 @@ int lbm_traces(lbm_handle *h, double *tip_out, double *v_out, int32_t *flags_out
     HIP_TRY(hipMemcpyAsync(v_out, h->base + h->L.off_trV + first * 8, count * 8, hipMemcpyDeviceToHost, h->stream));
   if (flags_out)
     HIP_TRY(hipMemcpyAsync(flags_out, h->base + h->L.off_trF + first * 4, count * 4, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_sensor_traces(lbm_handle *h, double *out, int64_t first, int64_t count,
+                      int32_t out_on_device) {
+  int rc = check_range(h, first, count, false);
+  if (rc != LBM_OK) return rc;
+  if (h->cfg.n_sensors == 0 || count == 0) return LBM_OK;
+  if (!out) return fail(LBM_EINVAL, "null output");
+  const size_t row = (size_t)h->cfg.n_sensors * 8;
+  HIP_TRY(hipMemcpyAsync(out, h->base + h->L.off_trS + first * row, count * row,
+                         out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return LBM_OK;
 }
@@ -1088,5 +1133,211 @@ void lbm_batch_free(lbm_batch *b) {
   for (lbm_handle *h : b->plates) lbm_free(h);
   delete b;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ adjoint --
+
+struct lbm_adjoint {
+  lbm_handle *h = nullptr;
+  bool fp64 = false;
+  lbmk::Plate p{};       // the plate with pitch / plane in adjoint elements
+  char *base = nullptr;
+  size_t off_m[2] = {0, 0}, off_w[2] = {0, 0}, off_cut = 0, off_part = 0, total = 0;
+  int n_parts = 0;
+  int64_t cap = 0;       // sweeps the partial-sum table holds (trace_cap + 1)
+  double ms = 0;
+  int64_t sweeps = 0;
+};
+
+namespace {
+
+struct AdjLayout {
+  size_t esize = 0, plane = 0, off_m[2] = {0, 0}, off_w[2] = {0, 0}, off_cut = 0, off_part = 0,
+         total = 0;
+  int n_parts = 0;
+  int64_t cap = 0;
+};
+
+AdjLayout adjoint_layout(const lbm_handle *h) {
+  AdjLayout A;
+  A.esize = (h->store == Store::F64) ? 8 : 4;
+  const size_t pb = align_up((size_t)h->L.pitch * h->cfg.ny * A.esize, 256) + 1024;
+  A.plane = pb / A.esize;
+  size_t o = 0;
+  for (int b = 0; b < 2; ++b) {
+    A.off_m[b] = o;
+    o += 5 * pb;
+  }
+  for (int b = 0; b < 2; ++b) {
+    A.off_w[b] = o;
+    o += pb;
+  }
+  A.off_cut = o;
+  o += align_up((size_t)h->cfg.nx * 4, 256);
+  A.n_parts = lbmk::adjoint_parts(h->cfg.nx);
+  A.cap = std::max<int64_t>(h->cfg.trace_cap, 0) + 1;
+  A.off_part = o;
+  o += align_up((size_t)A.cap * 4 * A.n_parts * 8, 256);
+  A.total = o;
+  return A;
+}
+
+template <typename C>
+int adjoint_sweep(lbm_adjoint *a, int cur, int64_t m) {
+  const lbm_handle *h = a->h;
+  lbmk::AdjArgs<C> g{};
+  g.min = reinterpret_cast<const C *>(a->base + a->off_m[cur]);
+  g.mout = reinterpret_cast<C *>(a->base + a->off_m[1 - cur]);
+  g.win = reinterpret_cast<const C *>(a->base + a->off_w[cur]);
+  g.wout = reinterpret_cast<C *>(a->base + a->off_w[1 - cur]);
+  g.p = a->p;
+  const bool init = m == 0;  // transpose of the initial equilibrium
+  g.omega = init ? C(1) : (C)h->cfg.omega;
+  g.dt = init ? C(0) : (C)h->dt;
+  g.A0 = (C)h->A0;
+  g.Ak = (C)h->Ak;
+  g.m = m;
+  g.cutstep = reinterpret_cast<const int32_t *>(a->base + a->off_cut);
+  g.has_crack = h->cfg.has_crack;
+  g.traction = h->cfg.bc_mode != LBM_BC_PERIODIC;
+  g.coef = h->coef;
+  g.dtau_part = reinterpret_cast<double *>(a->base + a->off_part) + (size_t)m * 4 * a->n_parts;
+  g.n_parts = a->n_parts;
+  if (h->cfg.has_crack) {
+    g.skip_lo = h->plate.j0;
+    g.skip_hi = h->plate.j0 + 1;
+  } else {
+    g.skip_lo = 1;
+    g.skip_hi = 0;
+  }
+  HIP_TRY(lbmk::launch_adjoint_sweep(a->fp64, &g, h->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_adjoint_bytes(const lbm_handle *h) {
+  if (!h) return 0;
+  return adjoint_layout(h).total;
+}
+
+int lbm_adjoint_init(lbm_handle *h, void *dev_buf, size_t dev_bytes, lbm_adjoint **out) {
+  if (!h || !out) return fail(LBM_EINVAL, "null argument");
+  *out = nullptr;
+  const AdjLayout A = adjoint_layout(h);
+  if (!dev_buf || reinterpret_cast<uintptr_t>(dev_buf) % 256)
+    return fail(LBM_EINVAL, "dev_buf must be a 256-byte aligned device pointer");
+  if (dev_bytes < A.total) return fail(LBM_ENOMEM, "dev_bytes %zu < required %zu", dev_bytes, A.total);
+  lbm_adjoint *a = new lbm_adjoint();
+  a->h = h;
+  a->fp64 = h->store == Store::F64;
+  a->p = h->plate;
+  a->p.plane = A.plane;
+  a->base = static_cast<char *>(dev_buf);
+  for (int b = 0; b < 2; ++b) {
+    a->off_m[b] = A.off_m[b];
+    a->off_w[b] = A.off_w[b];
+  }
+  a->off_cut = A.off_cut;
+  a->off_part = A.off_part;
+  a->total = A.total;
+  a->n_parts = A.n_parts;
+  a->cap = A.cap;
+  *out = a;
+  return LBM_OK;
+}
+
+int lbm_adjoint_run(lbm_adjoint *a, const double *g, double *dL_dtau, double *dL_dwdot0,
+                    double *dL_dw0) {
+  if (!a) return fail(LBM_EINVAL, "null adjoint");
+  lbm_handle *h = a->h;
+  const int64_t T = h->step;
+  if (T < 1) return fail(LBM_ESTATE, "the handle has taken no step");
+  if (T > h->cfg.trace_cap || T + 1 > a->cap)
+    return fail(LBM_ESTATE, "%lld steps taken, but the traces hold %lld", (long long)T,
+                (long long)h->cfg.trace_cap);
+  const int ns = h->cfg.n_sensors;
+  if (ns > 0 && !g) return fail(LBM_EINVAL, "null loss gradient");
+  hipStream_t st = h->stream;
+  // the step at which each crack-row link was severed (-1: initially)
+  std::vector<int32_t> cut(h->cfg.nx, INT32_MAX);
+  if (h->cfg.has_crack) {
+    const int lo = std::max(0, (int)std::ceil(h->cfg.crack_x0));
+    const int hi = std::min(h->cfg.nx - 1, (int)std::floor(h->cfg.crack_tip));
+    for (int i = lo; i <= hi; ++i) cut[i] = -1;
+    lbmk::DevCrack c{};
+    HIP_TRY(hipMemcpyAsync(&c, h->crack(), sizeof c, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int64_t ne = std::min<int64_t>(c.n_events, h->L.event_cap);
+    if (ne > 0) {
+      std::vector<int64_t> es(ne);
+      std::vector<int32_t> ec(ne);
+      HIP_TRY(hipMemcpyAsync(es.data(), h->base + h->L.off_evS, ne * 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(ec.data(), h->base + h->L.off_evC, ne * 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      for (int64_t k = 0; k < ne; ++k)
+        if (ec[k] >= 0 && ec[k] < h->cfg.nx) cut[ec[k]] = (int32_t)es[k];
+    }
+  }
+  // lambda_T = (0, dL/dw_T): a zero state (and zero partial sums), then the
+  // last trace row's gradient
+  HIP_TRY(lbmk::launch_zero(a->base, a->total, st));
+  HIP_TRY(hipMemcpyAsync(a->base + a->off_cut, cut.data(), cut.size() * 4, hipMemcpyHostToDevice, st));
+  const int32_t *sens = reinterpret_cast<const int32_t *>(h->base + h->L.off_sens);
+  if (ns > 0)
+    HIP_TRY(lbmk::launch_adjoint_inject(a->fp64, a->base + a->off_w[0], a->p, sens, ns,
+                                        g + (size_t)(T - 1) * ns, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, st));
+  int cur = 0;
+  for (int64_t m = T; m >= 0; --m) {
+    const int rc = a->fp64 ? adjoint_sweep<double>(a, cur, m) : adjoint_sweep<float>(a, cur, m);
+    if (rc != LBM_OK) return rc;
+    cur = 1 - cur;
+    // loss gradient at w_{m-1}, the state the sweep just produced the adjoint of
+    if (ns > 0 && m - 1 >= 1)
+      HIP_TRY(lbmk::launch_adjoint_inject(a->fp64, a->base + a->off_w[cur], a->p, sens, ns,
+                                          g + (size_t)(m - 2) * ns, st));
+  }
+  HIP_TRY(hipEventRecord(e1, st));
+  if (dL_dwdot0) HIP_TRY(lbmk::launch_adjoint_export(a->fp64, a->base + a->off_m[cur], a->p, dL_dwdot0, st));
+  if (dL_dw0) HIP_TRY(lbmk::launch_adjoint_export(a->fp64, a->base + a->off_w[cur], a->p, dL_dw0, st));
+  std::vector<double> parts;
+  if (dL_dtau) {
+    parts.resize((size_t)T * 4 * a->n_parts);
+    HIP_TRY(hipMemcpyAsync(parts.data(), a->base + a->off_part, parts.size() * 8, hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  a->ms = ms;
+  a->sweeps = T + 1;
+  if (dL_dtau) {
+    // rows the boundary kernel did not use hold zeros
+    for (int64_t n = 0; n < T; ++n) {
+      double s = 0.0;
+      for (int r = 0; r < 4; ++r)
+        for (int b = 0; b < a->n_parts; ++b) s += parts[((size_t)n * 4 + r) * a->n_parts + b];
+      dL_dtau[n] = s;
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_adjoint_timing(lbm_adjoint *a, double *ms, int64_t *sweeps) {
+  if (!a) return fail(LBM_EINVAL, "null adjoint");
+  if (ms) *ms = a->ms;
+  if (sweeps) *sweeps = a->sweeps;
+  return LBM_OK;
+}
+
+void lbm_adjoint_free(lbm_adjoint *a) { delete a; }
 
 }  // extern "C"

@@ -99,7 +99,7 @@ __device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, 
 }
 
 __device__ __forceinline__ void crack_task(const BatchPlate *__restrict__ d, int k, int cur) {
-  if (!d[k].has_crack) return;
+  if (!d[k].has_crack && d[k].crack.n_sens == 0) return;
   CrackArgs c = d[k].crack;
   c.w = d[k].w[1 - cur];  // w after the sweep of this step
   core::crack_step_wave(c);

@@ -12,7 +12,9 @@
 // new segment (a_prev, a] touches exactly the vertical links of the crack row
 // at the integer columns in that interval (the closed segment also touches
 // column a_prev when a_prev is an integer, which was severed already).
-// Each newly severed link is recorded as a cut event (step, column).
+// Each newly severed link is recorded as a cut event (step, column).  The
+// same wavefront records w at the sensor sites (also on plates without a
+// crack, where it does nothing else).
 #pragma once
 
 #include <cmath>
@@ -48,6 +50,16 @@ __device__ __forceinline__ void crack_step_wave(const CrackArgs &a) {
   DevCrack c = *a.st;
   const int64_t n = c.step;
   const int band = q.band;
+
+  // --- sensor traces: w after this step's sweep ---
+  if (a.n_sens > 0 && n < q.trace_cap) {
+    for (int s = lane; s < a.n_sens; s += 64)
+      a.trS[n * a.n_sens + s] = w_at(a, a.sens[2 * s], a.sens[2 * s + 1]);
+  }
+  if (!q.crack) {
+    if (lane == 0) a.st->step = n + 1;
+    return;
+  }
 
   // --- K at the current tip (eq. sif) ---
   const double vK = (q.growth == kGrowPrescribed) ? q.v_rel : c.v;

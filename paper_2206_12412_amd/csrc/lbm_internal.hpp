@@ -35,6 +35,7 @@ struct Plate {
 
 // Parameters of the crack step.
 struct CrackParams {
+  int crack;         // the plate has a crack (else only the sensors are recorded)
   int growth;        // LBM_GROW_*
   int band;          // columns in the K fit
   double v_rel, K_C, r0, v_max;
@@ -101,6 +102,9 @@ struct CrackArgs {
   int32_t *trF;
   int64_t *evStep;
   int32_t *evCol;
+  const int32_t *sens;  // sensor sites [n_sens][2] = (i, j)
+  double *trS;          // sensor traces [trace_cap][n_sens]
+  int n_sens;
   Plate p;
   CrackParams c;
 };
@@ -125,6 +129,42 @@ struct BatchPlate {
   int64_t itask0, btask0;  // first interior / boundary task of this plate in the batch
   CrackArgs crack;      // w is set per step from the parity
 };
+
+// Per-sweep arguments of the adjoint (adjoint.hip).  C is the adjoint's
+// arithmetic and storage type (double for FP64 plates, float otherwise).
+// Sweep m applies the transpose of step m's streaming to the adjoint of the
+// post-streaming populations of step m (min, 5 planes) and then the
+// transposed collision / Euler / moment map of step m - 1 (m = 0: of the
+// initial equilibrium, omega = 1, dt = 0).
+template <typename C>
+struct AdjArgs {
+  const C *min;          // plane 0 of the source adjoint populations
+  C *mout;               // plane 0 of the destination
+  const C *win;          // adjoint of w (source)
+  C *wout;               // destination
+  Plate p;               // pitch / plane in elements of C
+  C omega, dt, A0, Ak;
+  int64_t m;             // sweep index
+  const int32_t *cutstep;  // per column: step of the cut of the crack-row link (-1 initial)
+  int has_crack;
+  int traction;          // the edges carry tau (walls): derivative wanted
+  double coef;           // traction coefficient dt / (rho dh)
+  double *dtau_part;     // partial sums of dL/dtau_m: [4 rows][n_parts]
+  int n_parts;           // blocks per boundary row
+  int skip_lo, skip_hi;  // crack rows, handled by the boundary kernel
+};
+
+// ---- launchers (adjoint.hip) ----
+// interior and boundary kernels of one adjoint sweep
+hipError_t launch_adjoint_sweep(bool fp64, const void *args, hipStream_t st);
+// w[sensor s] += g[s] (after the sweep that wrote w)
+hipError_t launch_adjoint_inject(bool fp64, void *w, const Plate &p, const int32_t *sens, int n,
+                                 const double *g, hipStream_t st);
+// dense FP64 [ny][nx] copy of one adjoint plane
+hipError_t launch_adjoint_export(bool fp64, const void *plane, const Plate &p, double *out,
+                                 hipStream_t st);
+// blocks per boundary row of the adjoint boundary kernel
+int adjoint_parts(int nx);
 
 // ---- launchers (sweep.hip) ----
 enum class Store { F64, F32_PLAIN, F32S, F16S, BF16S };

@@ -36,7 +36,9 @@ EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_si
            "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
            "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
            "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
-           "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune", "lbm_round16")
+           "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune", "lbm_round16",
+           "lbm_sensor_traces", "lbm_adjoint_bytes", "lbm_adjoint_init", "lbm_adjoint_run",
+           "lbm_adjoint_timing", "lbm_adjoint_free")
 
 
 class LBMError(RuntimeError):
@@ -55,6 +57,7 @@ class _Config(C.Structure):
         ("tau_hist", C.POINTER(C.c_double)), ("n_hist", C.c_int64),
         ("w0", C.POINTER(C.c_double)), ("wdot0", C.POINTER(C.c_double)),
         ("trace_cap", C.c_int64), ("rounding", C.c_int32), ("seed", C.c_uint32),
+        ("n_sensors", C.c_int32), ("sensors", C.POINTER(C.c_int32)),
         ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t),
         ("stream", C.c_void_p),
     ]
@@ -119,8 +122,17 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_free.restype = None
     lib.lbm_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
     lib.lbm_round16.argtypes = [vp, vp, i64, i32, i32, i32, C.c_uint32, i64, vp]
+    lib.lbm_sensor_traces.argtypes = [vp, vp, i64, i64, i32]
+    lib.lbm_adjoint_bytes.argtypes = [vp]
+    lib.lbm_adjoint_bytes.restype = C.c_size_t
+    lib.lbm_adjoint_init.argtypes = [vp, vp, C.c_size_t, P(vp)]
+    lib.lbm_adjoint_run.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbm_adjoint_timing.argtypes = [vp, P(d), P(i64)]
+    lib.lbm_adjoint_free.argtypes = [vp]
+    lib.lbm_adjoint_free.restype = None
     lib.lbm_batch_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
-    for name in ("lbm_round16", "lbm_autotune", "lbm_batch_autotune", "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
+    for name in ("lbm_sensor_traces", "lbm_adjoint_init", "lbm_adjoint_run", "lbm_adjoint_timing",
+                 "lbm_round16", "lbm_autotune", "lbm_batch_autotune", "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
                  "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
         getattr(lib, name).restype = i32
     for name in ("lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
@@ -167,6 +179,7 @@ class Config:
     trace_cap: int = 0
     rounding: str = "nearest"      # 16-bit storages: "nearest" or "stochastic"
     seed: int = 0
+    sensors: Optional[np.ndarray] = None   # (n, 2) sites (i, j) whose w is recorded per step
 
     def to_c(self, keep: list) -> _Config:
         c = _Config()
@@ -178,6 +191,11 @@ class Config:
         c.has_crack = int(self.has_crack)
         c.rounding = ROUNDING[self.rounding] if isinstance(self.rounding, str) else int(self.rounding)
         c.seed = int(self.seed) & 0xFFFFFFFF
+        if self.sensors is not None:
+            sens = np.ascontiguousarray(self.sensors, dtype=np.int32).reshape(-1, 2)
+            keep.append(sens)
+            c.n_sensors = sens.shape[0]
+            c.sensors = sens.ctypes.data_as(C.POINTER(C.c_int32))
         if self.tau_hist is not None:
             t = np.ascontiguousarray(self.tau_hist, dtype=np.float64).ravel()
             keep.append(t)
@@ -290,6 +308,54 @@ class Solver:
             _check(self._lib.lbm_traces(self._h, _dp(tip), _dp(v),
                                         fl.ctypes.data_as(C.POINTER(C.c_int32)), int(first), int(count)))
         return {"K": K, "tip": tip, "v": v, "flags": fl}
+
+    def sensor_traces(self, first: int = 0, count: Optional[int] = None, device: bool = False):
+        """w at the sensor sites after each step, [count][n_sensors] (numpy,
+        or a float64 tensor on the solver's device)."""
+        n = 0 if self.cfg.sensors is None else len(np.asarray(self.cfg.sensors).reshape(-1, 2))
+        if count is None:
+            count = min(self.steps_done, self.cfg.trace_cap) - first
+        if device:
+            import torch
+
+            out = torch.empty((count, n), dtype=torch.float64, device=self._buf.device)
+            if count and n:
+                _check(self._lib.lbm_sensor_traces(self._h, out.data_ptr(), int(first), int(count), 1))
+            return out
+        out = np.empty((count, n))
+        if count and n:
+            _check(self._lib.lbm_sensor_traces(self._h, _dp(out), int(first), int(count), 0))
+        return out
+
+    def adjoint(self, g, timing: bool = False):
+        """Discrete adjoint through every step taken, for a loss whose
+        gradient with respect to the sensor traces is g ([steps][n_sensors],
+        float64 tensor on the solver's device).  Returns (dL/dtau per step as
+        numpy, dL/dwdot0 and dL/dw0 as float64 tensors [ny][nx]) and, with
+        timing, the adjoint kernel time in ms."""
+        import torch
+
+        lib = self._lib
+        nbytes = lib.lbm_adjoint_bytes(self._h)
+        if nbytes == 0:
+            _check(-1)
+        dev = self._buf.device
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ptr = buf.data_ptr() + (-buf.data_ptr()) % 256
+        a = C.c_void_p()
+        _check(lib.lbm_adjoint_init(self._h, ptr, nbytes, C.byref(a)))
+        try:
+            g = g.to(device=dev, dtype=torch.float64).contiguous()
+            T = self.steps_done
+            dtau = np.empty(T)
+            dwd0 = torch.empty(self.shape, dtype=torch.float64, device=dev)
+            dw0 = torch.empty(self.shape, dtype=torch.float64, device=dev)
+            _check(lib.lbm_adjoint_run(a, g.data_ptr(), _dp(dtau), dwd0.data_ptr(), dw0.data_ptr()))
+            ms = C.c_double()
+            _check(lib.lbm_adjoint_timing(a, C.byref(ms), None))
+        finally:
+            lib.lbm_adjoint_free(a)
+        return (dtau, dwd0, dw0, ms.value) if timing else (dtau, dwd0, dw0)
 
     def cut_events(self) -> np.ndarray:
         n = C.c_int64()

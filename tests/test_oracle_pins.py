@@ -568,3 +568,42 @@ def test_adjoint_is_the_transpose_and_gives_the_traction_derivative():
     s1.step(1)
     b_f, b_w = s1.pops(), s1.fields()[0]
     assert dtau == pytest.approx((b_f * y_f).sum() + (b_w * y_w).sum(), rel=1e-12)
+
+
+def test_sensor_adjoint_matches_central_differences():
+    """The loss sum_n sum_s (w_s(n) - target)^2 is quadratic in (tau history,
+    wdot_0) for a stationary crack, so the central difference is exact up to
+    rounding for any step h: the adjoint gradient must match it along random
+    directions (this also pins the loss-gradient injection and the initial-
+    equilibrium transpose)."""
+    nx, ny, T = 20, 14, 60
+    rng = np.random.default_rng(4)
+    sens = np.array([[3, 2], [10, 5], [15, 8], [7, 12], [12, 6]])
+    tau0 = 1e-3 * (1.0 + 0.3 * rng.normal(size=T))
+    wd0 = 1e-4 * rng.normal(size=(ny, nx))
+    target = 1e-3 * rng.normal(size=(T, len(sens)))
+    base = dict(nx=nx, ny=ny, has_crack=True, crack_tip=6.5, trace_cap=T)
+
+    def loss(tau, wd):
+        tr = O.sensor_traces(O.OracleConfig(tau_hist=tau, wdot0=wd, **base), sens, T)
+        return ((tr - target) ** 2).sum(), tr
+
+    L0, tr = loss(tau0, wd0)
+    dtau, dwd0, dw0 = O.sensor_adjoint(O.OracleConfig(tau_hist=tau0, wdot0=wd0, **base), sens,
+                                       2.0 * (tr - target))
+    for k in range(3):
+        d_tau, d_wd = rng.normal(size=T), rng.normal(size=(ny, nx))
+        h = 1e-2
+        fd = (loss(tau0 + h * d_tau, wd0 + h * d_wd)[0] - loss(tau0 - h * d_tau, wd0 - h * d_wd)[0]) / (2 * h)
+        ad = dtau @ d_tau + (dwd0 * d_wd).sum()
+        assert ad == pytest.approx(fd, rel=1e-9), (k, ad, fd)
+    # the initial displacement enters through the equilibrium f^0 = -A0 w0, f^k = Ak w0
+    d_w0 = rng.normal(size=(ny, nx))
+    h = 1e-2
+
+    def loss_w0(w0):
+        tr = O.sensor_traces(O.OracleConfig(tau_hist=tau0, wdot0=wd0, w0=w0, **base), sens, T)
+        return ((tr - target) ** 2).sum()
+
+    fd = (loss_w0(h * d_w0) - loss_w0(-h * d_w0)) / (2 * h)
+    assert (dw0 * d_w0).sum() == pytest.approx(fd, rel=1e-9)
