@@ -262,6 +262,98 @@ def run_batched(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def run_adjoint(args, torch):
+    """2048 x 1024 plate with a stationary 512-site crack, 5000 steps: the
+    sensor-trace loss against a run with a 10 % sinusoidal traction
+    perturbation, its gradient with respect to the traction history and the
+    initial velocity from the discrete adjoint, the adjoint's cost against the
+    forward run, and central differences (FP64 runs) along 16 unit directions."""
+    import synth
+    from paper_2206_12412_amd import Config, Solver
+
+    p = synth.config_adjoint()
+    T = args.steps if args.steps is not None else p.steps
+    sens = synth.adjoint_sensors(p.nx, p.ny)
+    storage = args.adjoint_storage
+    say = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
+    base = dict(nx=p.nx, ny=p.ny, has_crack=True, crack_x0=p.crack_x0, crack_tip=p.crack_tip,
+                sensors=sens, trace_cap=T)
+    tau0 = np.full(T, p.tau)
+
+    def run(st, tau, wd0=None):
+        """(solver after T steps, its sensor traces, ms of the T steps)"""
+        s = Solver(Config(storage=st, tau_hist=tau, wdot0=wd0, **base))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        s.step(T)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        return s, s.sensor_traces(), e0.elapsed_time(e1)
+
+    def traces(st, tau, wd0=None):
+        s, tr, _ = run(st, tau, wd0)
+        s.close()
+        return tr
+
+    say(f"adjoint: target run, {T} steps")
+    target = traces("f64", synth.adjoint_target_history(T, tau0=p.tau))
+    if args.warmup > 0:
+        w = Solver(Config(storage=storage, tau_hist=tau0, **dict(base, trace_cap=args.warmup)))
+        w.step(args.warmup)
+        torch.cuda.synchronize()
+        w.close()
+    say(f"adjoint: forward run ({storage})")
+    s, tr, fwd_ms = run(storage, tau0)
+    loss = float(((tr - target) ** 2).sum())
+    g = torch.from_numpy(2.0 * (tr - target)).cuda()
+    say("adjoint: backward run")
+    s.adjoint(g)  # first call: code objects
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dtau, dwd0, _, adj_ms = s.adjoint(g, timing=True)
+    adj_wall_ms = (time.perf_counter() - t0) * 1e3
+    s.close()
+    dwd0 = dwd0.cpu().numpy()
+    say("adjoint: central differences on FP64 runs")
+    h = 1e-4
+    fd, ad = [], []
+    for d_tau, d_wd in synth.adjoint_directions(T, (p.ny, p.nx), count=args.directions):
+        lp = float(((traces("f64", tau0 + h * d_tau, h * d_wd) - target) ** 2).sum())
+        lm = float(((traces("f64", tau0 - h * d_tau, -h * d_wd) - target) ** 2).sum())
+        fd.append((lp - lm) / (2 * h))
+        ad.append(float(dtau @ d_tau + (dwd0 * d_wd).sum()))
+    fd, ad = np.array(fd), np.array(ad)
+    sites = p.nx * p.ny
+    bps = 2.0 * (5 * (8 if storage == "f64" else 4) + (8 if storage == "f64" else 4))
+    sweep_ms = adj_ms / (T + 1)
+    achieved = sites * bps / (sweep_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(sites * (T + 1) / (adj_ms * 1e-3) / 1e9, 2),
+        "unit": "GLUPS", "n_gpus": 1, "steps": T, "warmup": args.warmup,
+        "ms_per_step": round(sweep_ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if storage == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": f"adjoint-{p.nx}x{p.ny}", "nx": p.nx, "ny": p.ny,
+                   "crack_sites": p.ell, "sensors": int(len(sens)), "storage": storage,
+                   "parallelism": "single-gpu"},
+        "loss": loss,
+        "forward_ms_per_step": round(fwd_ms / T, 4),
+        "adjoint_ms_per_step": round(sweep_ms, 4),
+        "adjoint_over_forward": round((adj_ms / (T + 1)) / (fwd_ms / T), 3),
+        "adjoint_wall_ms": round(adj_wall_ms, 1),
+        "recomputed_forward_steps": 0,
+        "gradient_check": {
+            "directions": int(len(fd)), "h": h, "reference": "central differences of FP64 runs",
+            "rel_err_norm": float(np.linalg.norm(ad - fd) / np.linalg.norm(fd)),
+            "rel_err_max": float(np.max(np.abs(ad - fd) / np.abs(fd))),
+        },
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole adjoint sweep (interior, boundary, sensor kernels)"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def _read_csv(path):
     import csv
     with open(path) as fh:
@@ -269,8 +361,10 @@ def _read_csv(path):
 
 
 def _short(name: str) -> str:
-    for key in ("sweep_interior", "sweep_boundary", "crack_kernel", "copyBuffer", "init_rows",
-                "export_rows", "zero_kernel", "init_mask"):
+    for key in ("sweep_interior", "sweep_boundary", "crack_kernel", "batch_interior",
+                "batch_boundary", "batch_crack", "batch_persistent", "adj_interior", "adj_boundary",
+                "adj_inject", "adj_export", "copyBuffer", "init_rows", "export_rows", "zero_kernel",
+                "init_mask"):
         if key in name:
             return key
     return name[:40]
@@ -338,7 +432,10 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="precision",
-                    choices=["precision", "sif", "plain", "batched"])
+                    choices=["precision", "sif", "plain", "batched", "adjoint"])
+    ap.add_argument("--adjoint-storage", default="f32", help="storage of the adjoint workload's run")
+    ap.add_argument("--directions", type=int, default=16,
+                    help="adjoint workload: random directions of the gradient check")
     ap.add_argument("--batch-storage", default="f32", help="storage of the batched workload")
     ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch shape")
     ap.add_argument("--storage", default="f16s-sr",
@@ -379,6 +476,9 @@ def main():
 
     if args.workload == "batched":
         run_batched(args, torch)
+        return
+    if args.workload == "adjoint":
+        run_adjoint(args, torch)
         return
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
          "plain": synth.config_plain_fp64}[args.workload]()

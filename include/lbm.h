@@ -253,7 +253,7 @@ int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps);
 lbm_handle *lbm_batch_plate(lbm_batch *b, int32_t k);
 
 /* Launch shape of the batched interior kernel (as lbm_set_launch) and the
- * grid of the last persistent launch (blocks of 4 waves). */
+ * grid of the last persistent launch (one workgroup of 4 waves per CU). */
 int lbm_batch_set_launch(lbm_batch *b, int32_t rows, int32_t waves, int32_t occupancy);
 int lbm_batch_get_launch(lbm_batch *b, int32_t *rows, int32_t *waves, int32_t *occupancy,
                          int32_t *persistent_blocks);

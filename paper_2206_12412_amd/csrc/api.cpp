@@ -850,7 +850,7 @@ int batch_layout(const lbm_config *cfgs, int32_t n, BatchLayout *B, Store *store
     o += align_up(sizeof(double) * (size_t)std::max<int64_t>(cfgs[k].n_hist, 1), 256);
   }
   B->off_sync = o;
-  o += 256;
+  o += 512;  // grid-barrier words on separate 128-byte lines
   B->total = o;
   return LBM_OK;
 }
@@ -1027,7 +1027,7 @@ int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps) {
   if (nsteps == 0) return LBM_OK;
   const auto *d = reinterpret_cast<const lbmk::BatchPlate *>(b->base + b->off_desc);
   unsigned *sync = reinterpret_cast<unsigned *>(b->base + b->off_sync);
-  HIP_TRY(lbmk::launch_zero(sync, 256, b->stream));
+  HIP_TRY(lbmk::launch_zero(sync, 512, b->stream));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (b->timing) {
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -1045,7 +1045,7 @@ int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps) {
     b->ev_used.push_back(e1);
   }
   unsigned flag = 0;
-  HIP_TRY(hipMemcpyAsync(&flag, sync + 2, sizeof flag, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipMemcpyAsync(&flag, sync + 64, sizeof flag, hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->cur = (int)((b->cur + nsteps) & 1);
   b->step += nsteps;

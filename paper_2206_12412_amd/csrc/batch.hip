@@ -130,25 +130,33 @@ __global__ void __launch_bounds__(256) batch_crack(const BatchPlate *__restrict_
   crack_task(d, k, cur);
 }
 
-// Grid-wide barrier: sync[0] counts arrivals, sync[1] is the generation,
-// sync[2] the time-out flag.
+// Grid-wide barrier on three words, each on its own 128-byte line so that the
+// pollers of the generation do not queue the arrivals' atomics behind them:
+// sync[kCount] counts arrivals, sync[kGen] is the generation, sync[kErr] the
+// time-out flag.
+constexpr int kCount = 0, kGen = 32, kErr = 64;
+
 __device__ __forceinline__ void grid_barrier(unsigned *sync, unsigned nblocks) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-      const unsigned gen = __hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_load(&sync[kErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      const unsigned gen = __hip_atomic_load(&sync[kGen], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
       __threadfence();
-      const unsigned arrived = atomicAdd(&sync[0], 1u);
+      const unsigned arrived = atomicAdd(&sync[kCount], 1u);
       if (arrived == nblocks - 1) {
-        __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sync[kCount], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&sync[kGen], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         unsigned tries = 0;
-        while (__hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-          __builtin_amdgcn_s_sleep(2);
-          if (++tries > (1u << 24) ||
-              __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-            atomicExch(&sync[2], 1u);
+        while (__hip_atomic_load(&sync[kGen], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          __builtin_amdgcn_s_sleep(4);
+          ++tries;
+          // bounded wait (~1 s): on time-out raise the flag; every later
+          // barrier then falls through, so all waves reach the kernel's end
+          if ((tries & 63u) == 0u &&
+              (tries > (1u << 23) ||
+               __hip_atomic_load(&sync[kErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+            atomicExch(&sync[kErr], 1u);
             break;
           }
         }
@@ -159,13 +167,16 @@ __device__ __forceinline__ void grid_barrier(unsigned *sync, unsigned nblocks) {
   __syncthreads();
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
-__global__ void __launch_bounds__(256)
+// Workgroups of the persistent kernel: WPB waves each, one workgroup per CU,
+// because every grid barrier costs one agent-scope release / acquire (L2
+// write-back and invalidation across the XCDs) per workgroup.
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, int WPB>
+__global__ void __launch_bounds__(64 * WPB)
 batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t n_bnd, int cur0,
                  int64_t step0, int64_t nsteps, unsigned *sync) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
-  const int64_t nw = (int64_t)gridDim.x * 4;
+  const int64_t gw = (int64_t)blockIdx.x * WPB + wave;
+  const int64_t nw = (int64_t)gridDim.x * WPB;
   for (int64_t s = 0; s < nsteps; ++s) {
     const int cur = (int)((cur0 + s) & 1);
     const int64_t step = step0 + s;
@@ -196,27 +207,39 @@ hipError_t step_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int 
   return hipGetLastError();
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
-hipError_t persistent_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, int WPB>
+hipError_t persistent_w(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
                         int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
                         hipStream_t st) {
-  auto kernel = batch_persistent<S, W, C, VEC, SHIFT, SR>;
+  auto kernel = batch_persistent<S, W, C, VEC, SHIFT, SR, WPB>;
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), 256, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel),
+                                                   64 * WPB, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
-  const int64_t want = (n_int + n_bnd + 3) / 4;
-  int blocks = per_cu * cus;
+  const int64_t want = (n_int + n_bnd + WPB - 1) / WPB;
+  int blocks = cus;  // one workgroup per CU
   if (want < blocks) blocks = (int)(want > 0 ? want : 1);
   *blocks_used = blocks;
   void *args[] = {(void *)&d, (void *)&n, (void *)&n_int, (void *)&n_bnd, (void *)&cur,
                   (void *)&step, (void *)&nsteps, (void *)&sync};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), dim3(blocks), dim3(256),
-                                    args, 0, st);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), dim3(blocks),
+                                    dim3(64 * WPB), args, 0, st);
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
+hipError_t persistent_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
+                        int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
+                        hipStream_t st) {
+  // one workgroup of 4 waves per CU: measured on MI355X against 1 to 16 waves
+  // and 1 to 4 workgroups per CU (more waves contend, more workgroups pay
+  // for more barrier releases / acquires)
+  return persistent_w<S, W, C, VEC, SHIFT, SR, 4>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
+                                                  blocks_used, st);
 }
 
 // stochastic rounding exists for the 16-bit storages only

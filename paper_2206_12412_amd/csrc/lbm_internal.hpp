@@ -189,9 +189,10 @@ hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const P
 hipError_t launch_batch_step(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                              int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
                              hipStream_t st);
-// nsteps steps in one cooperative launch with grid barriers; sync[0..3] is a
-// zeroed device scratch (barrier counter, generation, error flag).  Returns
-// hipErrorCooperativeLaunchTooLarge if the grid cannot be co-resident.
+// nsteps steps in one cooperative launch with grid barriers; sync is a
+// zeroed 512-byte device scratch (barrier counter, generation and time-out
+// flag at words 0, 32 and 64).  Returns hipErrorCooperativeLaunchTooLarge if
+// the grid cannot be co-resident.
 hipError_t launch_batch_persistent(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                                    int64_t n_bnd_tasks, int cur, int64_t step, int64_t nsteps,
                                    unsigned *sync, int *blocks_used, hipStream_t st);
