@@ -65,7 +65,7 @@ def traffic_for(storage: str, workload: str, sites: int):
     return t.get("bytes_per_launch")
 
 
-def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None):
+def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=True):
     """Time `steps` steps of plate p in this storage.  The run is cut at the
     checkpoints, where w is exported (outside the timed intervals); each
     segment is timed with HIP events on the solver's stream between two
@@ -82,8 +82,10 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None):
         del s
         torch.cuda.empty_cache()
     s = Solver(plate_config(p, storage, steps))
+    tuned = s.autotune(trial_steps=5) if tune else None  # on a scratch copy of the plate
     torch.cuda.synchronize()
-    s.timing(True)
+    # per-kernel HIP events on every 10th step of the timed region
+    s.timing(True, stride=10)
     ms = 0.0
     done = 0
     snaps, errs = {}, {}
@@ -112,16 +114,16 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None):
         "ms": ms,
         "glups": p.sites * steps / (ms * 1e-3) / 1e9,
         "bytes_per_site": s.bytes_per_site(),
-        "interior_sites": s.interior_sites(),
+        "sites": s.sites(),
         "launch": s.launch(),
+        "autotune": tuned,
         "K": s.sif(0, steps),
         "tip": s.traces(0, steps)["tip"],
         "snaps": snaps,
         "field_errors": errs,
     }
     if tm["steps"]:
-        out["interior_ms"] = tm["interior_ms"] / tm["steps"]
-        out["boundary_ms"] = tm["boundary_ms"] / tm["steps"]
+        out["sweep_ms"] = tm["sweep_ms"] / tm["steps"]
         out["crack_ms"] = tm["crack_ms"] / tm["steps"]
     s.close()
     del s
@@ -361,7 +363,8 @@ def _read_csv(path):
 
 
 def _short(name: str) -> str:
-    for key in ("sweep_interior", "sweep_boundary", "crack_kernel", "batch_interior",
+    for key in ("sweep_step", "sweep_interior", "sweep_boundary", "crack_kernel", "batch_step",
+                "batch_interior",
                 "batch_boundary", "batch_crack", "batch_persistent", "adj_interior", "adj_boundary",
                 "adj_inject", "adj_export", "copyBuffer", "init_rows", "export_rows", "zero_kernel",
                 "init_mask"):
@@ -386,7 +389,7 @@ def summarize_trace(dirpath: str, out_md: str, command: str):
 
 def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, copy_bytes: int,
                   command: str, out_dir: str):
-    """HBM bytes per interior-sweep launch from FETCH_SIZE and WRITE_SIZE runs,
+    """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs,
     each scaled by the same counter's reading for a device copy of copy_bytes."""
     import synth
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
@@ -399,30 +402,30 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
                 if r["Counter_Name"] == counter]
         copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
         factor = copy_bytes / (copy * 1024.0)
-        vals = [float(r["Counter_Value"]) for r in rows if "sweep_interior" in r["Kernel_Name"]]
+        vals = [float(r["Counter_Value"]) for r in rows if "sweep_step" in r["Kernel_Name"]]
         kib = sum(vals) / len(vals)
         out[counter] = {"KiB_per_launch": kib, "copy_KiB": copy, "factor": factor,
                         "bytes_per_launch": kib * 1024.0 * factor, "launches": len(vals)}
         total += kib * 1024.0 * factor
     e = {"f64": 8, "f32": 4, "f32plain": 4, "f16s": 2, "bf16s": 2}[storage.replace("-sr", "")]
     we = 8 if storage == "f64" else 4
-    interior = p.nx * (p.ny - 4)
+    sites = p.nx * p.ny
     out["bytes_per_launch"] = total
-    out["algorithmic_bytes_per_launch"] = interior * 2 * (5 * e + we)
+    out["algorithmic_bytes_per_launch"] = sites * 2 * (5 * e + we)
     out["traffic_over_algorithmic"] = total / out["algorithmic_bytes_per_launch"]
     base = os.path.join(out_dir, f"sweep_{storage}_{workload}_traffic")
     with open(base + ".json", "w") as fh:
         json.dump(out, fh, indent=1)
     f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
     with open(base + ".md", "w") as fh:
-        fh.write(f"# HBM traffic of sweep_interior ({storage}, {workload} workload)\n\n"
+        fh.write(f"# HBM traffic of sweep_step ({storage}, {workload} workload)\n\n"
                  f"Commands (one run per counter, C = FETCH_SIZE then WRITE_SIZE):\n\n    {command}\n\n"
                  f"| counter | KiB / launch | copy of {copy_bytes} B reads | scale | bytes / launch |\n"
                  f"|---|---|---|---|---|\n"
                  f"| FETCH_SIZE | {f['KiB_per_launch']:.1f} | {f['copy_KiB']:.1f} KiB | {f['factor']:.4f} | {f['bytes_per_launch']:.4e} |\n"
                  f"| WRITE_SIZE | {w['KiB_per_launch']:.1f} | {w['copy_KiB']:.1f} KiB | {w['factor']:.4f} | {w['bytes_per_launch']:.4e} |\n\n"
                  f"Total {total:.4e} B per launch against {out['algorithmic_bytes_per_launch']:.4e} algorithmic "
-                 f"({interior} interior sites x {2 * (5 * e + we)} B): ratio {out['traffic_over_algorithmic']:.4f}.\n"
+                 f"({sites} sites x {2 * (5 * e + we)} B): ratio {out['traffic_over_algorithmic']:.4f}.\n"
                  f"Kernel source sha256[:16] = {out['kernel_source_sha']}.\n")
 
 
@@ -437,7 +440,7 @@ def main():
     ap.add_argument("--directions", type=int, default=16,
                     help="adjoint workload: random directions of the gradient check")
     ap.add_argument("--batch-storage", default="f32", help="storage of the batched workload")
-    ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch shape")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--storage", default="f16s-sr",
                     help='headline storage; a "-sr" suffix selects stochastic rounding')
     ap.add_argument("--compare", default="f64,f32,f16s,f16s-sr,bf16s,bf16s-sr",
@@ -503,7 +506,8 @@ def main():
     for st in storages:
         print(f"bench: {p.name} storage={st} steps={steps} warmup={args.warmup}", file=sys.stderr,
               flush=True)
-        results[st] = run_storage(p, st, steps, args.warmup, torch, checkpoints, ref)
+        results[st] = run_storage(p, st, steps, args.warmup, torch, checkpoints, ref,
+                                  tune=not args.no_tune)
         if ref is None:
             ref = results[st]
         print(f"bench: {st}: {results[st]['glups']:.1f} GLUPS", file=sys.stderr, flush=True)
@@ -512,12 +516,11 @@ def main():
     for st, r in results.items():
         e = {"glups": round(r["glups"], 2), "ms_per_step": round(r["ms"] / steps, 4),
              "bytes_per_site": r["bytes_per_site"], "launch": r["launch"]}
-        if "interior_ms" in r:
-            gbs = r["interior_sites"] * r["bytes_per_site"] / (r["interior_ms"] * 1e-3) / 1e9
-            e["interior_kernel_ms"] = round(r["interior_ms"], 4)
-            e["boundary_kernel_ms"] = round(r["boundary_ms"], 4)
+        if "sweep_ms" in r:
+            gbs = r["sites"] * r["bytes_per_site"] / (r["sweep_ms"] * 1e-3) / 1e9
+            e["sweep_kernel_ms"] = round(r["sweep_ms"], 4)
             e["crack_kernel_ms"] = round(r["crack_ms"], 4)
-            e["interior_GBps"] = round(gbs, 1)
+            e["sweep_GBps"] = round(gbs, 1)
             e["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
         if st != ref_name:
             e.update(k_errors(r["K"], ref["K"]))
@@ -528,14 +531,14 @@ def main():
 
     head = results[args.storage]
     bps = head["bytes_per_site"]
-    alg = head["interior_sites"] * bps  # algorithmic bytes of one interior-kernel launch
-    achieved = alg / (head["interior_ms"] * 1e-3) / 1e9
+    alg = head["sites"] * bps  # algorithmic bytes of one sweep-kernel launch
+    achieved = alg / (head["sweep_ms"] * 1e-3) / 1e9
     traffic = traffic_for(args.storage, args.workload, p.sites)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": f"sweep_interior ({args.storage})",
+                "traffic": traffic, "kernel": f"sweep_step ({args.storage})",
                 "algorithmic_bytes_per_launch": alg,
-                "kernel_ms": round(head["interior_ms"], 4)}
+                "kernel_ms": round(head["sweep_ms"], 4)}
 
     line = {
         "metric": METRIC,

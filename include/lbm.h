@@ -171,16 +171,13 @@ int lbm_get_populations(lbm_handle *h, double *f_out);
 int lbm_get_mask(lbm_handle *h, uint8_t *cutV, uint8_t *cutH);
 
 /* Kernel timing with HIP events on the handle's stream.  A step launches the
- * interior sweep kernel (every row away from the plate edges and the crack
- * rows), the boundary-row sweep kernel and the crack kernel; enable = 1 starts
- * recording (and clears the sums), 0 stops.  Returns the summed durations (ms)
- * of the three kernels and the number of timed steps (synchronises the
+ * sweep kernel (interior strips and boundary rows in one launch) and the
+ * crack kernel.  enable = n > 0 starts recording (and clears the sums) on
+ * every step whose index is a multiple of n (n > 1 samples the steps, so that
+ * the events cost less); 0 stops.  Returns the summed durations (ms) of the
+ * two kernels over the timed steps and their number (synchronises the
  * stream).  Any output pointer may be NULL. */
-int lbm_timing(lbm_handle *h, int32_t enable, double *interior_ms, double *boundary_ms,
-               double *crack_ms, int64_t *n_timed);
-
-/* Sites updated by the interior sweep kernel (all but the edge and crack rows). */
-int64_t lbm_interior_sites(const lbm_handle *h);
+int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms, int64_t *n_timed);
 
 /* Launch shape of the sweep: sites per lane along x (vec, fixed by the
  * storage), rows marched per wave (rows), waves per workgroup (waves) and the

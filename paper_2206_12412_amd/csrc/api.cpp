@@ -192,9 +192,10 @@ struct lbm_handle {
   int rows = 1, waves = 4, occ = 0;
   int lds_per_cu = 65536;
   bool timing = false;
+  int timing_stride = 1;  // record the steps whose index is a multiple of this
   std::vector<hipEvent_t> ev_pool;
-  std::vector<hipEvent_t> ev_used;  // per step: before, after interior, after boundary, after crack
-  double t_int = 0, t_bnd = 0, t_crack = 0;
+  std::vector<hipEvent_t> ev_used;  // per timed step: before, after the sweep, after the crack step
+  double t_sweep = 0, t_crack = 0;
   int64_t n_timed = 0;
   lbmk::DevCrack host_crack{};
   bool in_batch = false;  // stepped by a batch; lbm_step refuses it
@@ -231,13 +232,11 @@ hipEvent_t take_event(lbm_handle *h) {
 int harvest_timing(lbm_handle *h) {
   if (h->ev_used.empty()) return LBM_OK;
   HIP_TRY(hipStreamSynchronize(h->stream));
-  for (size_t k = 0; k + 3 < h->ev_used.size(); k += 4) {
-    float a = 0, b = 0, c = 0;
+  for (size_t k = 0; k + 2 < h->ev_used.size(); k += 3) {
+    float a = 0, c = 0;
     HIP_TRY(hipEventElapsedTime(&a, h->ev_used[k], h->ev_used[k + 1]));
-    HIP_TRY(hipEventElapsedTime(&b, h->ev_used[k + 1], h->ev_used[k + 2]));
-    HIP_TRY(hipEventElapsedTime(&c, h->ev_used[k + 2], h->ev_used[k + 3]));
-    h->t_int += a;
-    h->t_bnd += b;
+    HIP_TRY(hipEventElapsedTime(&c, h->ev_used[k + 1], h->ev_used[k + 2]));
+    h->t_sweep += a;
     h->t_crack += c;
     h->n_timed += 1;
   }
@@ -247,7 +246,7 @@ int harvest_timing(lbm_handle *h) {
 }
 
 template <typename S, typename W, typename C>
-int launch_sweep_typed(lbm_handle *h, int part) {
+int launch_sweep_typed(lbm_handle *h) {
   lbmk::SweepArgs<S, W, C> a{};
   const int nxt = 1 - h->cur;
   a.fin = static_cast<const S *>(h->fbuf(h->cur));
@@ -287,17 +286,17 @@ int launch_sweep_typed(lbm_handle *h, int part) {
   }
   a.sr = h->cfg.rounding == LBM_ROUND_STOCHASTIC;
   a.rkey = lbmk::step_key(h->cfg.seed, h->step);
-  HIP_TRY(lbmk::launch_sweep(h->store, &a, part, h->stream));
+  HIP_TRY(lbmk::launch_sweep(h->store, &a, h->stream));
   return LBM_OK;
 }
 
-int launch_sweep_any(lbm_handle *h, int part) {
+int launch_sweep_any(lbm_handle *h) {
   switch (h->store) {
-    case Store::F64: return launch_sweep_typed<double, double, double>(h, part);
-    case Store::F32_PLAIN: return launch_sweep_typed<float, float, float>(h, part);
-    case Store::F32S: return launch_sweep_typed<float, float, float>(h, part);
-    case Store::F16S: return launch_sweep_typed<_Float16, float, float>(h, part);
-    case Store::BF16S: return launch_sweep_typed<__bf16, float, float>(h, part);
+    case Store::F64: return launch_sweep_typed<double, double, double>(h);
+    case Store::F32_PLAIN: return launch_sweep_typed<float, float, float>(h);
+    case Store::F32S: return launch_sweep_typed<float, float, float>(h);
+    case Store::F16S: return launch_sweep_typed<_Float16, float, float>(h);
+    case Store::BF16S: return launch_sweep_typed<__bf16, float, float>(h);
   }
   return fail(LBM_EINVAL, "bad storage");
 }
@@ -533,28 +532,26 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
   if (h->in_batch) return fail(LBM_ESTATE, "this plate is stepped by its batch (lbm_batch_step)");
   if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
   for (int64_t k = 0; k < nsteps; ++k) {
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    if (h->timing) {
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    const bool timed = h->timing && h->step % h->timing_stride == 0;
+    if (timed) {
       for (auto &e : ev) {
         e = take_event(h);
         if (!e) return fail(LBM_EHIP, "event creation failed");
       }
       HIP_TRY(hipEventRecord(ev[0], h->stream));
     }
-    int rc = launch_sweep_any(h, 0);
+    int rc = launch_sweep_any(h);
     if (rc != LBM_OK) return rc;
-    if (h->timing) HIP_TRY(hipEventRecord(ev[1], h->stream));
-    rc = launch_sweep_any(h, 1);
-    if (rc != LBM_OK) return rc;
-    if (h->timing) HIP_TRY(hipEventRecord(ev[2], h->stream));
+    if (timed) HIP_TRY(hipEventRecord(ev[1], h->stream));
     if (h->crack_step_needed()) {
       rc = launch_crack_step(h);
       if (rc != LBM_OK) return rc;
     }
-    if (h->timing) {
-      HIP_TRY(hipEventRecord(ev[3], h->stream));
+    if (timed) {
+      HIP_TRY(hipEventRecord(ev[2], h->stream));
       for (auto &e : ev) h->ev_used.push_back(e);
-      if (h->ev_used.size() >= 4 * 4096) {
+      if (h->ev_used.size() >= 3 * 4096) {
         rc = harvest_timing(h);
         if (rc != LBM_OK) return rc;
       }
@@ -711,20 +708,20 @@ int lbm_get_mask(lbm_handle *h, uint8_t *cutV, uint8_t *cutH) {
   return LBM_OK;
 }
 
-int lbm_timing(lbm_handle *h, int32_t enable, double *interior_ms, double *boundary_ms,
-               double *crack_ms, int64_t *n_timed) {
+int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms, int64_t *n_timed) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   int rc = harvest_timing(h);
   if (rc != LBM_OK) return rc;
-  if (interior_ms) *interior_ms = h->t_int;
-  if (boundary_ms) *boundary_ms = h->t_bnd;
+  if (sweep_ms) *sweep_ms = h->t_sweep;
   if (crack_ms) *crack_ms = h->t_crack;
   if (n_timed) *n_timed = h->n_timed;
+  if (enable < 0) return fail(LBM_EINVAL, "negative timing stride");
   if (enable && !h->timing) {
-    h->t_int = h->t_bnd = h->t_crack = 0;
+    h->t_sweep = h->t_crack = 0;
     h->n_timed = 0;
   }
   h->timing = enable != 0;
+  if (enable) h->timing_stride = enable;
   return LBM_OK;
 }
 
@@ -773,13 +770,6 @@ int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *rows, int32_t *wav
       [h](int64_t n) { return lbm_step(h, n); }, rows, waves, occupancy, ms_per_step);
   h->timing = was_timing;
   return rc;
-}
-
-int64_t lbm_interior_sites(const lbm_handle *h) {
-  if (!h) return 0;
-  const int lo = h->cfg.has_crack ? h->plate.j0 : 1;
-  const int hi = h->cfg.has_crack ? h->plate.j0 + 1 : 0;
-  return lbmk::interior_sites(h->plate, lo, hi);
 }
 
 double lbm_bytes_per_site(const lbm_handle *h) {

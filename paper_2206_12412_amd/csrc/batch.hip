@@ -7,8 +7,8 @@
 // batch evolves bit for bit as it does alone.
 //
 // Two ways to run a step:
-//   per-step launches: one batched interior kernel, one batched boundary
-//     kernel and one batched crack kernel (one wavefront per plate);
+//   per-step launches: one batched sweep kernel (boundary and interior tasks
+//     of all plates) and one batched crack kernel (one wavefront per plate);
 //   persistent: one cooperative launch runs many steps; every wave walks the
 //     task list with a grid stride, and two grid barriers per step separate
 //     the sweep from the crack step and the crack step from the next sweep.
@@ -105,23 +105,21 @@ __device__ __forceinline__ void crack_task(const BatchPlate *__restrict__ d, int
   core::crack_step_wave(c);
 }
 
+// One launch per step for the sweep of every plate: the first `nbb`
+// workgroups take the boundary tasks, the rest the interior tasks.
 template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 __global__ void __launch_bounds__(512)
-batch_interior(const BatchPlate *__restrict__ d, int n, int64_t n_tasks, int cur, int64_t step,
-               int waves) {
+batch_step(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t n_bnd, unsigned nbb,
+           int cur, int64_t step, int waves) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t task = (int64_t)blockIdx.x * waves + wave;
-  if (task >= n_tasks) return;
+  if (blockIdx.x < nbb) {
+    const int64_t task = (int64_t)blockIdx.x * waves + wave;
+    if (task < n_bnd) boundary_task<S, W, C, VEC, SHIFT, SR>(d, n, task, cur, step);
+    return;
+  }
+  const int64_t task = (int64_t)(blockIdx.x - nbb) * waves + wave;
+  if (task >= n_int) return;
   interior_task<S, W, C, VEC, SHIFT, SR>(d, n, task, cur, step);
-}
-
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
-__global__ void __launch_bounds__(256)
-batch_boundary(const BatchPlate *__restrict__ d, int n, int64_t n_tasks, int cur, int64_t step) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t task = (int64_t)blockIdx.x * 4 + wave;
-  if (task >= n_tasks) return;
-  boundary_task<S, W, C, VEC, SHIFT, SR>(d, n, task, cur, step);
 }
 
 __global__ void __launch_bounds__(256) batch_crack(const BatchPlate *__restrict__ d, int n, int cur) {
@@ -193,16 +191,11 @@ batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t
 template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 hipError_t step_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur, int64_t step,
                   int waves, int lds, hipStream_t st) {
-  if (n_int > 0) {
-    const unsigned blocks = (unsigned)((n_int + waves - 1) / waves);
-    hipLaunchKernelGGL((batch_interior<S, W, C, VEC, SHIFT, SR>), dim3(blocks), dim3(64 * waves), lds, st,
-                       d, n, n_int, cur, step, waves);
-  }
-  if (n_bnd > 0) {
-    const unsigned blocks = (unsigned)((n_bnd + 3) / 4);
-    hipLaunchKernelGGL((batch_boundary<S, W, C, VEC, SHIFT, SR>), dim3(blocks), dim3(256), 0, st, d, n,
-                       n_bnd, cur, step);
-  }
+  const unsigned nbb = (unsigned)((n_bnd + waves - 1) / waves);
+  const unsigned nib = (unsigned)((n_int + waves - 1) / waves);
+  if (nbb + nib > 0)
+    hipLaunchKernelGGL((batch_step<S, W, C, VEC, SHIFT, SR>), dim3(nbb + nib), dim3(64 * waves), lds,
+                       st, d, n, n_int, n_bnd, nbb, cur, step, waves);
   hipLaunchKernelGGL(batch_crack, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, d, n, cur);
   return hipGetLastError();
 }

@@ -170,10 +170,8 @@ int adjoint_parts(int nx);
 enum class Store { F64, F32_PLAIN, F32S, F16S, BF16S };
 
 int sweep_vec(Store s);  // sites per lane
-// part 0: the interior kernel, part 1: the boundary-row kernel
-hipError_t launch_sweep(Store s, const void *args, int part, hipStream_t st);
-// sites the interior kernel updates
-int64_t interior_sites(const Plate &p, int skip_lo, int skip_hi);
+// one sweep step (interior strips and boundary rows in one launch)
+hipError_t launch_sweep(Store s, const void *args, hipStream_t st);
 // the 16-bit store conversion of the sweep applied to x[0..n) (F16S / BF16S)
 hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n, int plane,
                           uint32_t rkey, hipStream_t st);
@@ -184,7 +182,7 @@ hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const P
                             int has_crack, double x0, double a0, hipStream_t st);
 
 // ---- launchers (batch.hip) ----
-// One step of every plate: batched interior kernel, batched boundary kernel,
+// One step of every plate: batched sweep kernel (boundary and interior tasks),
 // batched crack kernel.  cur = parity of the source buffers, step = step index.
 hipError_t launch_batch_step(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                              int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,

@@ -1,19 +1,33 @@
-// Single-plate sweep kernels and their launchers.  A step launches the
-// interior kernel (interior rows, no bounce-back code) and the boundary-row
-// kernel (edge rows and crack rows); both read the source buffers and write
-// disjoint sites of the destination buffers.  The arithmetic lives in
-// sweep_core.hpp.
+// Single-plate sweep kernel and its launcher.  The interior strips (no
+// bounce-back code) and the boundary rows (edge rows and crack rows) of a step
+// run in one launch; both read the source buffers and write disjoint sites of
+// the destination buffers.  The arithmetic lives in sweep_core.hpp.
 #include "sweep_core.hpp"
 
 namespace lbmk {
 namespace {
 
+// One launch per step: the first `nbb` workgroups take the boundary rows (the
+// two edge rows and the crack rows, full treatment), the rest the interior
+// strips.  The two parts write disjoint sites, so they run side by side; one
+// launch saves the dispatch gap of a second kernel (measured 0.5 % of a step
+// on 134M sites, 10 % on 2M sites).  The kernel's register count is the
+// larger of the two parts'; the occupancy cap (reserved LDS) binds first.
 template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
 __global__ void __launch_bounds__(512)
-sweep_interior(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict__ win,
-               W *__restrict__ wout, const SweepArgs<S, W, C> a, const core::InteriorMap m) {
+sweep_step(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict__ win,
+           W *__restrict__ wout, const uint32_t *__restrict__ mV, const uint32_t *__restrict__ mH,
+           const MaskRows *__restrict__ mrows, const SweepArgs<S, W, C> a, const core::InteriorMap m,
+           const core::BoundaryMap bm, const unsigned nbb) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int task = blockIdx.x * a.waves + wave;
+  if (blockIdx.x < nbb) {
+    const int task = blockIdx.x * a.waves + wave;
+    if (task >= bm.n_strips * bm.nb) return;
+    core::boundary_row<S, W, C, VEC, SHIFT, SR>(fin, fout, win, wout, mV, mH, mrows, a,
+                                                task % bm.n_strips, bm.brow[task / bm.n_strips]);
+    return;
+  }
+  const int task = (blockIdx.x - nbb) * a.waves + wave;
   const int strip = task % m.n_strips;
   const int chunk = task / m.n_strips;
   int jb, jlast;
@@ -24,54 +38,33 @@ sweep_interior(const S *__restrict__ fin, S *__restrict__ fout, const W *__restr
     jb = m.lo2 + (chunk - m.nc1) * m.rows;
     jlast = min(jb + m.rows - 1, m.hi2);
   }
-  if (jb > jlast) return;
+  if (jb > jlast) return;  // the tail of the last workgroup
   core::interior_rows<S, W, C, VEC, SHIFT, SR>(fin, fout, win, wout, a, strip, jb, jlast);
 }
 
 template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
-__global__ void __launch_bounds__(256)
-sweep_boundary(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict__ win,
-               W *__restrict__ wout, const uint32_t *__restrict__ mV,
-               const uint32_t *__restrict__ mH, const MaskRows *__restrict__ mrows,
-               const SweepArgs<S, W, C> a, const core::BoundaryMap m) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int task = blockIdx.x * 4 + wave;
-  if (task >= m.n_strips * m.nb) return;
-  const int strip = task % m.n_strips;
-  const int j = m.brow[task / m.n_strips];
-  core::boundary_row<S, W, C, VEC, SHIFT, SR>(fin, fout, win, wout, mV, mH, mrows, a, strip, j);
-}
-
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
-hipError_t launch_t(const SweepArgs<S, W, C> &a, int part, hipStream_t st) {
-  if (part == 0) {
-    const core::InteriorMap m = core::interior_map(a.p.nx, a.p.ny, VEC, a.rows, a.skip_lo, a.skip_hi);
-    const long tasks = core::interior_task_count(m);
-    if (tasks > 0) {
-      const unsigned blocks = (unsigned)((tasks + a.waves - 1) / a.waves);
-      hipLaunchKernelGGL((sweep_interior<S, W, C, VEC, SHIFT, SR>), dim3(blocks), dim3(64 * a.waves),
-                         a.lds_bytes, st, a.fin, a.fout, a.win, a.wout, a, m);
-    }
-  } else {
-    const core::BoundaryMap m = core::boundary_map(a.p.nx, a.p.ny, VEC, a.skip_lo, a.skip_hi);
-    const long tasks = core::boundary_task_count(m);
-    if (tasks > 0) {
-      const unsigned blocks = (unsigned)((tasks + 3) / 4);
-      hipLaunchKernelGGL((sweep_boundary<S, W, C, VEC, SHIFT, SR>), dim3(blocks), dim3(256), 0, st,
-                         a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a, m);
-    }
-  }
+hipError_t launch_t(const SweepArgs<S, W, C> &a, hipStream_t st) {
+  const core::InteriorMap m = core::interior_map(a.p.nx, a.p.ny, VEC, a.rows, a.skip_lo, a.skip_hi);
+  const core::BoundaryMap bm = core::boundary_map(a.p.nx, a.p.ny, VEC, a.skip_lo, a.skip_hi);
+  const long itasks = core::interior_task_count(m);
+  const long btasks = core::boundary_task_count(bm);
+  const unsigned nbb = (unsigned)((btasks + a.waves - 1) / a.waves);
+  const unsigned nib = (unsigned)((itasks + a.waves - 1) / a.waves);
+  if (nbb + nib > 0)
+    hipLaunchKernelGGL((sweep_step<S, W, C, VEC, SHIFT, SR>), dim3(nbb + nib), dim3(64 * a.waves),
+                       a.lds_bytes, st, a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a, m, bm,
+                       nbb);
   return hipGetLastError();
 }
 
 // stochastic rounding exists for the 16-bit storages only
 template <typename S, typename W, typename C, int VEC, bool SHIFT>
-hipError_t launch_r(const void *args, int part, hipStream_t st) {
+hipError_t launch_r(const void *args, hipStream_t st) {
   const auto &a = *static_cast<const SweepArgs<S, W, C> *>(args);
   if constexpr (sizeof(S) == 2) {
-    if (a.sr) return launch_t<S, W, C, VEC, SHIFT, true>(a, part, st);
+    if (a.sr) return launch_t<S, W, C, VEC, SHIFT, true>(a, st);
   }
-  return launch_t<S, W, C, VEC, SHIFT, false>(a, part, st);
+  return launch_t<S, W, C, VEC, SHIFT, false>(a, st);
 }
 
 // The store conversion of the sweep applied to an array: element i is the
@@ -107,13 +100,6 @@ hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n,
   return hipGetLastError();
 }
 
-int64_t interior_sites(const Plate &p, int skip_lo, int skip_hi) {
-  int rows = p.ny - 2;
-  for (int j = skip_lo; j <= skip_hi; ++j)
-    if (j >= 1 && j <= p.ny - 2) --rows;
-  return rows > 0 ? (int64_t)rows * p.nx : 0;
-}
-
 int sweep_vec(Store s) {
   switch (s) {
     case Store::F64: return 2;
@@ -125,13 +111,13 @@ int sweep_vec(Store s) {
   return 0;
 }
 
-hipError_t launch_sweep(Store s, const void *args, int part, hipStream_t st) {
+hipError_t launch_sweep(Store s, const void *args, hipStream_t st) {
   switch (s) {
-    case Store::F64: return launch_r<double, double, double, 2, false>(args, part, st);
-    case Store::F32_PLAIN: return launch_r<float, float, float, 4, false>(args, part, st);
-    case Store::F32S: return launch_r<float, float, float, 4, true>(args, part, st);
-    case Store::F16S: return launch_r<_Float16, float, float, 4, true>(args, part, st);
-    case Store::BF16S: return launch_r<__bf16, float, float, 4, true>(args, part, st);
+    case Store::F64: return launch_r<double, double, double, 2, false>(args, st);
+    case Store::F32_PLAIN: return launch_r<float, float, float, 4, false>(args, st);
+    case Store::F32S: return launch_r<float, float, float, 4, true>(args, st);
+    case Store::F16S: return launch_r<_Float16, float, float, 4, true>(args, st);
+    case Store::BF16S: return launch_r<__bf16, float, float, 4, true>(args, st);
   }
   return hipErrorInvalidValue;
 }

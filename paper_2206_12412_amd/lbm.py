@@ -32,7 +32,7 @@ ERRORS = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
            "lbm_cut_events", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
-           "lbm_timing", "lbm_interior_sites", "lbm_get_launch", "lbm_set_launch",
+           "lbm_timing", "lbm_get_launch", "lbm_set_launch",
            "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
            "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
            "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
@@ -96,9 +96,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_get_fields.argtypes = [vp, P(d), P(d)]
     lib.lbm_get_populations.argtypes = [vp, P(d)]
     lib.lbm_get_mask.argtypes = [vp, P(C.c_uint8), P(C.c_uint8)]
-    lib.lbm_timing.argtypes = [vp, i32, P(d), P(d), P(d), P(i64)]
-    lib.lbm_interior_sites.argtypes = [vp]
-    lib.lbm_interior_sites.restype = i64
+    lib.lbm_timing.argtypes = [vp, i32, P(d), P(d), P(i64)]
     lib.lbm_get_launch.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
     lib.lbm_set_launch.argtypes = [vp, i32, i32, i32]
     lib.lbm_bytes_per_site.argtypes = [vp]
@@ -386,18 +384,18 @@ class Solver:
         _check(self._lib.lbm_get_mask(self._h, v.ctypes.data_as(P), h.ctypes.data_as(P)))
         return v, h
 
-    def timing(self, enable: bool):
-        """Start (True) or stop (False) per-kernel HIP-event timing; returns the
-        summed interior / boundary / crack kernel times and the timed steps."""
-        i, b, k = C.c_double(), C.c_double(), C.c_double()
+    def timing(self, enable, stride: int = 1):
+        """Start (True; every `stride`-th step) or stop (False) per-kernel
+        HIP-event timing; returns the summed sweep and crack kernel times and
+        the number of timed steps."""
+        sw, k = C.c_double(), C.c_double()
         n = C.c_int64()
-        _check(self._lib.lbm_timing(self._h, int(enable), C.byref(i), C.byref(b), C.byref(k),
+        _check(self._lib.lbm_timing(self._h, int(stride) if enable else 0, C.byref(sw), C.byref(k),
                                     C.byref(n)))
-        return {"interior_ms": i.value, "boundary_ms": b.value, "crack_ms": k.value,
-                "sweep_ms": i.value + b.value, "steps": n.value}
+        return {"sweep_ms": sw.value, "crack_ms": k.value, "steps": n.value}
 
-    def interior_sites(self) -> int:
-        return int(self._lib.lbm_interior_sites(self._h))
+    def sites(self) -> int:
+        return self.cfg.nx * self.cfg.ny
 
     def launch(self):
         v, r, w, o = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
