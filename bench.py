@@ -155,24 +155,38 @@ def k_errors(K, K_ref):
 
 
 def cpu_baseline(p, budget_s: float):
-    """The oracle as it stands on this host's cores, on the same plate."""
+    """The oracle as it stands on this host's cores, on the same plate (and a
+    shorter single-core sample for reference)."""
     import oracle as O
+
+    def rate(threads, budget):
+        s = O.Oracle(O.OracleConfig(
+            nx=p.nx, ny=p.ny, kappa=p.kappa, mu=p.mu, rho=p.rho, has_crack=True,
+            crack_x0=p.crack_x0, crack_tip=p.crack_tip, growth=p.growth, v_rel=p.v_rel, K_C=p.K_C,
+            r0=p.r0, v_max=p.v_max, tau_hist=p.traction_history(), trace_cap=0, threads=threads))
+        s.step(1)  # first touch of the pages
+        n, t0 = 0, time.perf_counter()
+        while True:
+            s.step(1)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                break
+        s.close()
+        return p.sites * n / el / 1e9, n, el
+
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    s = O.Oracle(O.OracleConfig(
-        nx=p.nx, ny=p.ny, kappa=p.kappa, mu=p.mu, rho=p.rho, has_crack=True, crack_x0=p.crack_x0,
-        crack_tip=p.crack_tip, growth=p.growth, v_rel=p.v_rel, K_C=p.K_C, r0=p.r0,
-        v_max=p.v_max, tau_hist=p.traction_history(), trace_cap=0, threads=threads))
-    s.step(1)  # first touch of the pages
-    n, t0 = 0, time.perf_counter()
-    while True:
-        s.step(1)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    s.close()
-    return {"value": p.sites * n / el / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} steps of the full {p.nx}x{p.ny} plate, FP64, {el:.1f} s"}
+    v, n, el = rate(threads, budget_s)
+    v1, n1, el1 = rate(1, budget_s / 3)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": v, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of the full {p.nx}x{p.ny} plate, FP64, {el:.1f} s",
+            "single_core": {"value": v1, "sample": f"{n1} steps, {el1:.1f} s"}, "cpu_model": model}
 
 
 def run_batched(args, torch):
@@ -440,7 +454,10 @@ def main():
     ap.add_argument("--directions", type=int, default=16,
                     help="adjoint workload: random directions of the gradient check")
     ap.add_argument("--batch-storage", default="f32", help="storage of the batched workload")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch shape")
+    ap.add_argument("--tune", action="store_true",
+                    help="single plate: autotune each storage before timing (the library's "
+                         "defaults are this search's result for the precision plate)")
     ap.add_argument("--storage", default="f16s-sr",
                     help='headline storage; a "-sr" suffix selects stochastic rounding')
     ap.add_argument("--compare", default="f64,f32,f16s,f16s-sr,bf16s,bf16s-sr",
@@ -507,7 +524,7 @@ def main():
         print(f"bench: {p.name} storage={st} steps={steps} warmup={args.warmup}", file=sys.stderr,
               flush=True)
         results[st] = run_storage(p, st, steps, args.warmup, torch, checkpoints, ref,
-                                  tune=not args.no_tune)
+                                  tune=args.tune)
         if ref is None:
             ref = results[st]
         print(f"bench: {st}: {results[st]['glups']:.1f} GLUPS", file=sys.stderr, flush=True)

@@ -224,8 +224,10 @@ hipEvent_t take_event(lbm_handle *h) {
     h->ev_pool.pop_back();
     return e;
   }
+  // timing only (read after a stream synchronisation): no system-scope fence,
+  // which would add a cache write-back to every timed interval
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -450,16 +452,17 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   p.j0 = cfg->ny / 2 - 1;
   p.periodic = cfg->bc_mode == LBM_BC_PERIODIC;
   p.plane = L.plane;
-  // default launch shape, measured on MI355X on plates much larger than the
-  // caches: one row per wave streams the plate in address order, and capping
-  // the resident waves per SIMD (3 for 8-byte and 4-byte storage, 4 for
-  // 16-bit storage) keeps fewer DRAM rows open at once.  Small plates lower
-  // the march length until >= 8192 waves are in flight anyway.
+  // default launch shape, the fastest of the autotuner's grid on MI355X for a
+  // 16384 x 8192 plate (much larger than the caches): one row per wave, and a
+  // cap on the resident waves per SIMD -- 1-wave workgroups with at most 2
+  // resident waves per SIMD for 8- and 4-byte storage, 4-wave workgroups with
+  // at most 4 for 16-bit storage.  lbm_autotune searches the same grid for
+  // other plates.
   {
     const bool half = (s == Store::F16S || s == Store::BF16S);
     h->rows = 1;
-    h->waves = (s == Store::F32S || s == Store::F32_PLAIN) ? 2 : 4;
-    h->occ = half ? 4 : 3;
+    h->waves = half ? 4 : 1;
+    h->occ = half ? 4 : 2;
   }
 
   {
