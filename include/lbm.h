@@ -170,6 +170,19 @@ int lbm_get_populations(lbm_handle *h, double *f_out);
  * mode), either may be NULL. */
 int lbm_get_mask(lbm_handle *h, uint8_t *cutV, uint8_t *cutH);
 
+/* Checkpoint and restart.  lbm_checkpoint copies the state after the steps
+ * taken so far (current populations and w, cut mask, crack state, traces, cut
+ * events, sensor traces, step count) into dst, a device buffer of
+ * lbm_checkpoint_bytes(h) bytes (256-byte aligned; the caller owns it);
+ * lbm_restore makes a handle continue from such a checkpoint: the handle must
+ * have been initialised from the same configuration (checked through the
+ * recorded sizes), and its next steps then reproduce bit for bit the steps
+ * that followed the checkpoint.  Both are enqueued on h's stream and
+ * synchronise it. */
+size_t lbm_checkpoint_bytes(const lbm_handle *h);
+int lbm_checkpoint(lbm_handle *h, void *dst);
+int lbm_restore(lbm_handle *h, const void *src);
+
 /* Kernel timing with HIP events on the handle's stream.  A step launches the
  * sweep kernel (interior strips and boundary rows in one launch) and the
  * crack kernel.  enable = n > 0 starts recording (and clears the sums) on

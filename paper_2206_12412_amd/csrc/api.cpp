@@ -688,6 +688,69 @@ int lbm_get_populations(lbm_handle *h, double *f_out) {
   return export_rows(h, nullptr, nullptr, f_out);
 }
 
+// Checkpoint layout: a 256-byte header, the five current population planes,
+// the current w plane, then the layout region from the cut mask to the sensor
+// traces (mask, mask-row range, crack state, traces, events, sensors).
+namespace {
+struct CkptHeader {
+  uint64_t magic;
+  int64_t step;
+  uint64_t f_bytes, w_bytes, tail_bytes;
+  int32_t nx, ny, storage, pad;
+};
+constexpr uint64_t kCkptMagic = 0x4c424d434b505431ull;  // "LBMCKPT1"
+
+void ckpt_sizes(const lbm_handle *h, size_t *f, size_t *w, size_t *tail) {
+  *f = h->L.off_f[1] - h->L.off_f[0];
+  *w = h->L.off_w[1] - h->L.off_w[0];
+  *tail = h->L.off_stage - h->L.off_mV;
+}
+}  // namespace
+
+size_t lbm_checkpoint_bytes(const lbm_handle *h) {
+  if (!h) return 0;
+  size_t f, w, tail;
+  ckpt_sizes(h, &f, &w, &tail);
+  return 256 + f + w + tail;
+}
+
+int lbm_checkpoint(lbm_handle *h, void *dst) {
+  if (!h || !dst) return fail(LBM_EINVAL, "null argument");
+  if (h->in_batch) return fail(LBM_ESTATE, "plates of a batch are not checkpointed one by one");
+  size_t f, w, tail;
+  ckpt_sizes(h, &f, &w, &tail);
+  CkptHeader hd{kCkptMagic, h->step, f, w, tail, h->cfg.nx, h->cfg.ny, h->cfg.storage, 0};
+  char *d = static_cast<char *>(dst);
+  HIP_TRY(hipMemcpyAsync(d, &hd, sizeof hd, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(d + 256, h->fbuf(h->cur), f, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(d + 256 + f, h->wbuf(h->cur), w, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(d + 256 + f + w, h->base + h->L.off_mV, tail, hipMemcpyDeviceToDevice,
+                         h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_restore(lbm_handle *h, const void *src) {
+  if (!h || !src) return fail(LBM_EINVAL, "null argument");
+  if (h->in_batch) return fail(LBM_ESTATE, "plates of a batch are not restored one by one");
+  size_t f, w, tail;
+  ckpt_sizes(h, &f, &w, &tail);
+  CkptHeader hd{};
+  const char *s = static_cast<const char *>(src);
+  HIP_TRY(hipMemcpyAsync(&hd, s, sizeof hd, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (hd.magic != kCkptMagic || hd.f_bytes != f || hd.w_bytes != w || hd.tail_bytes != tail ||
+      hd.nx != h->cfg.nx || hd.ny != h->cfg.ny || hd.storage != h->cfg.storage)
+    return fail(LBM_EINVAL, "checkpoint does not belong to a plate of this configuration");
+  HIP_TRY(hipMemcpyAsync(h->fbuf(h->cur), s + 256, f, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->wbuf(h->cur), s + 256 + f, w, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->base + h->L.off_mV, s + 256 + f + w, tail, hipMemcpyDeviceToDevice,
+                         h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->step = hd.step;
+  return LBM_OK;
+}
+
 int lbm_get_mask(lbm_handle *h, uint8_t *cutV, uint8_t *cutH) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   const lbmk::Plate &p = h->plate;

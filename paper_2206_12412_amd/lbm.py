@@ -38,7 +38,8 @@ EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_si
            "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
            "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune", "lbm_round16",
            "lbm_sensor_traces", "lbm_adjoint_bytes", "lbm_adjoint_init", "lbm_adjoint_run",
-           "lbm_adjoint_timing", "lbm_adjoint_free")
+           "lbm_adjoint_timing", "lbm_adjoint_free", "lbm_checkpoint_bytes", "lbm_checkpoint",
+           "lbm_restore")
 
 
 class LBMError(RuntimeError):
@@ -121,6 +122,10 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
     lib.lbm_round16.argtypes = [vp, vp, i64, i32, i32, i32, C.c_uint32, i64, vp]
     lib.lbm_sensor_traces.argtypes = [vp, vp, i64, i64, i32]
+    lib.lbm_checkpoint_bytes.argtypes = [vp]
+    lib.lbm_checkpoint_bytes.restype = C.c_size_t
+    lib.lbm_checkpoint.argtypes = [vp, vp]
+    lib.lbm_restore.argtypes = [vp, vp]
     lib.lbm_adjoint_bytes.argtypes = [vp]
     lib.lbm_adjoint_bytes.restype = C.c_size_t
     lib.lbm_adjoint_init.argtypes = [vp, vp, C.c_size_t, P(vp)]
@@ -129,7 +134,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_adjoint_free.argtypes = [vp]
     lib.lbm_adjoint_free.restype = None
     lib.lbm_batch_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
-    for name in ("lbm_sensor_traces", "lbm_adjoint_init", "lbm_adjoint_run", "lbm_adjoint_timing",
+    for name in ("lbm_checkpoint", "lbm_restore", "lbm_sensor_traces", "lbm_adjoint_init", "lbm_adjoint_run", "lbm_adjoint_timing",
                  "lbm_round16", "lbm_autotune", "lbm_batch_autotune", "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
                  "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
         getattr(lib, name).restype = i32
@@ -354,6 +359,29 @@ class Solver:
         finally:
             lib.lbm_adjoint_free(a)
         return (dtau, dwd0, dw0, ms.value) if timing else (dtau, dwd0, dw0)
+
+    def checkpoint(self):
+        """The state after the steps taken so far, as a device uint8 tensor."""
+        import torch
+
+        n = self._lib.lbm_checkpoint_bytes(self._h)
+        buf = torch.empty(n + 256, dtype=torch.uint8, device=self._buf.device)
+        off = (-buf.data_ptr()) % 256
+        _check(self._lib.lbm_checkpoint(self._h, buf.data_ptr() + off))
+        return buf[off:off + n]
+
+    def restore(self, ckpt):
+        """Continue from a checkpoint of a plate with the same configuration."""
+        import torch
+
+        ptr = ckpt.data_ptr()
+        if ptr % 256:  # the library wants a 256-byte aligned block
+            tmp = torch.empty(ckpt.numel() + 256, dtype=torch.uint8, device=ckpt.device)
+            off = (-tmp.data_ptr()) % 256
+            tmp[off:off + ckpt.numel()].copy_(ckpt)
+            ckpt, ptr = tmp, tmp.data_ptr() + off
+        _check(self._lib.lbm_restore(self._h, ptr))
+        self.steps_done = int(self.crack_state()["step"])
 
     def cut_events(self) -> np.ndarray:
         n = C.c_int64()

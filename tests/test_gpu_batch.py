@@ -168,3 +168,28 @@ def test_batch_autotune_keeps_results():
         same_state(b.plates[k], ref.plates[k], f"plate {k}")
     with pytest.raises(RuntimeError):
         b.plates[0].autotune()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16s-sr"])
+def test_checkpoint_restart_reproduces_the_run(storage):
+    """A run restarted from a checkpoint (in the same or in a fresh handle)
+    repeats the original steps bit for bit, traces and cut events included."""
+    cfg = plate_configs(storage, 300)[0]   # prescribed growth
+    cfg.sensors = np.array([[10, 5], [50, 30], [80, 23]])
+    a = Solver(cfg)
+    a.step(120)
+    ck = a.checkpoint()
+    a.step(180)
+    b = Solver(cfg)
+    b.restore(ck)
+    assert b.steps_done == 120
+    b.step(180)
+    same_state(a, b, "fresh handle")
+    np.testing.assert_array_equal(a.sensor_traces(), b.sensor_traces())
+    a.restore(ck)
+    a.step(180)
+    same_state(a, b, "same handle")
+    other = Solver(plate_configs(storage, 300)[1])
+    from paper_2206_12412_amd import LBMError
+    with pytest.raises(LBMError):
+        other.restore(ck)
