@@ -365,7 +365,7 @@ def run_adjoint(args, torch):
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "whole adjoint sweep (interior, boundary, sensor kernels)"},
+                     "kernel": "adj_step (whole adjoint sweep, one launch per step)"},
     }
     print(json.dumps(line), flush=True)
 
@@ -379,7 +379,7 @@ def _read_csv(path):
 def _short(name: str) -> str:
     for key in ("sweep_step", "sweep_interior", "sweep_boundary", "crack_kernel", "batch_step",
                 "batch_interior",
-                "batch_boundary", "batch_crack", "batch_persistent", "adj_interior", "adj_boundary",
+                "batch_boundary", "batch_crack", "batch_persistent", "adj_step", "adj_interior", "adj_boundary",
                 "adj_inject", "adj_export", "copyBuffer", "init_rows", "export_rows", "zero_kernel",
                 "init_mask"):
         if key in name:

@@ -26,7 +26,9 @@
 //
 // Interior rows (all vertical links intact) run the strip code of the
 // forward sweep with the neighbour directions reversed (DPP lane shifts for
-// x, rows j +- 1 for y); the edge and crack rows run one thread per site.
+// x, rows j +- 1 for y); the edge and crack rows run one thread per site, in
+// the same launch.  The loss gradient of the state a sweep produces is added
+// to W by the thread that writes it (the sensors are indexed by row).
 // FP64 is evaluated without contraction in the order written above.
 #include "sweep_core.hpp"
 
@@ -123,6 +125,16 @@ __device__ __forceinline__ void adj_interior_row(const AdjArgs<C> &a, int strip,
     adj_local<C>(a, m0[k], l1, m2u[k], l3, m4d[k], b[k], o0[k], o1[k], o2[k], o3[k], o4[k], wo[k]);
     if (i > last) o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
   }
+  if (a.g) {  // the loss gradient at this row's sensors (a wave-uniform loop)
+    const int e0 = a.srow[j], e1 = a.srow[j + 1];
+    for (int e = e0; e < e1; ++e) {
+      const int ci = a.srt[2 * e];
+      const double gv = a.g[a.srt[2 * e + 1]];
+#pragma unroll
+      for (int k = 0; k < VEC; ++k)
+        if (ci == i0 + k) wo[k] = (C)((double)wo[k] + gv);
+    }
+  }
   if (act) {
     store_row<C, C, VEC>(a.mout, o, o0);
     store_row<C, C, VEC>(a.mout + P, o, o1);
@@ -133,18 +145,6 @@ __device__ __forceinline__ void adj_interior_row(const AdjArgs<C> &a, int strip,
   }
 }
 
-template <typename C, int VEC>
-__global__ void __launch_bounds__(256) adj_interior(const AdjArgs<C> a, const core::InteriorMap m,
-                                                    long n_tasks) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const long task = (long)blockIdx.x * 4 + wave;
-  if (task >= n_tasks) return;
-  const int strip = (int)(task % m.n_strips);
-  const int chunk = (int)(task / m.n_strips);
-  const int j = chunk < m.nc1 ? m.lo1 + chunk : m.lo2 + (chunk - m.nc1);
-  adj_interior_row<C, VEC>(a, strip, j);
-}
-
 __device__ __forceinline__ double block_sum(double x, double *lds) {
   for (int s = 32; s >= 1; s >>= 1) x += __shfl_xor(x, s, 64);
   const int wave = threadIdx.x >> 6;
@@ -153,17 +153,15 @@ __device__ __forceinline__ double block_sum(double x, double *lds) {
   return ((lds[0] + lds[1]) + lds[2]) + lds[3];
 }
 
-// Edge and crack rows, one thread per site; blockIdx.y = boundary row.
+// Edge and crack row j, one thread per site i (part = block of the row).
 template <typename C>
-__global__ void __launch_bounds__(256) adj_boundary(const AdjArgs<C> a, const core::BoundaryMap bm) {
-  __shared__ double red[4];
+__device__ __forceinline__ void adj_boundary_site(const AdjArgs<C> &a, int r, int j, int part,
+                                                  double *red) {
   const Plate p = a.p;
-  const int r = blockIdx.y;
-  const int j = bm.brow[r];
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = part * 256 + threadIdx.x;
   const int last = p.nx - 1;
   const size_t P = p.plane;
-  double part = 0.0;
+  double dtau = 0.0;
   if (i < p.nx) {
     const size_t pitch = p.pitch;
     const size_t x = (size_t)j * pitch + i;
@@ -182,6 +180,10 @@ __global__ void __launch_bounds__(256) adj_boundary(const AdjArgs<C> a, const co
     const C l4 = (jm >= 0 && !cut_dn) ? M[4 * P + (size_t)jm * pitch + i] : M[2 * P + x];
     C o0, o1, o2, o3, o4, wo;
     adj_local<C>(a, l0, l1, l2, l3, l4, a.win[x], o0, o1, o2, o3, o4, wo);
+    if (a.g) {
+      for (int e = a.srow[j]; e < a.srow[j + 1]; ++e)
+        if (a.srt[2 * e] == i) wo = (C)((double)wo + a.g[a.srt[2 * e + 1]]);
+    }
     a.mout[x] = o0;
     a.mout[P + x] = o1;
     a.mout[2 * P + x] = o2;
@@ -189,12 +191,33 @@ __global__ void __launch_bounds__(256) adj_boundary(const AdjArgs<C> a, const co
     a.mout[4 * P + x] = o4;
     a.wout[x] = wo;
     if (a.traction) {
-      if (j == p.ny - 1) part += a.coef * (double)M[4 * P + x];
-      if (j == 0) part -= a.coef * (double)M[2 * P + x];
+      if (j == p.ny - 1) dtau += a.coef * (double)M[4 * P + x];
+      if (j == 0) dtau -= a.coef * (double)M[2 * P + x];
     }
   }
-  const double s = block_sum(part, red);
-  if (threadIdx.x == 0) a.dtau_part[r * a.n_parts + blockIdx.x] = s;
+  const double s = block_sum(dtau, red);
+  if (threadIdx.x == 0) a.dtau_part[r * a.n_parts + part] = s;
+}
+
+// One adjoint sweep: the first nb * n_parts workgroups take the boundary rows
+// (one thread per site), the rest the interior strips (4 waves each).
+template <typename C, int VEC>
+__global__ void __launch_bounds__(256) adj_step(const AdjArgs<C> a, const core::InteriorMap m,
+                                                const core::BoundaryMap bm, long n_tasks) {
+  __shared__ double red[4];
+  const unsigned nbb = (unsigned)(bm.nb * a.n_parts);
+  if (blockIdx.x < nbb) {
+    const int r = blockIdx.x / a.n_parts;
+    adj_boundary_site<C>(a, r, bm.brow[r], blockIdx.x % a.n_parts, red);
+    return;
+  }
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long task = (long)(blockIdx.x - nbb) * 4 + wave;
+  if (task >= n_tasks) return;
+  const int strip = (int)(task % m.n_strips);
+  const int chunk = (int)(task / m.n_strips);
+  const int j = chunk < m.nc1 ? m.lo1 + chunk : m.lo2 + (chunk - m.nc1);
+  adj_interior_row<C, VEC>(a, strip, j);
 }
 
 template <typename C>
@@ -216,13 +239,10 @@ __global__ void adj_export(const C *plane, Plate p, double *out) {
 template <typename C, int VEC>
 hipError_t sweep_t(const AdjArgs<C> &a, hipStream_t st) {
   const core::InteriorMap m = core::interior_map(a.p.nx, a.p.ny, VEC, 1, a.skip_lo, a.skip_hi);
-  const long tasks = core::interior_task_count(m);
-  if (tasks > 0)
-    hipLaunchKernelGGL((adj_interior<C, VEC>), dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, st,
-                       a, m, tasks);
   const core::BoundaryMap bm = core::boundary_map(a.p.nx, a.p.ny, VEC, a.skip_lo, a.skip_hi);
-  hipLaunchKernelGGL((adj_boundary<C>), dim3((unsigned)a.n_parts, (unsigned)bm.nb), dim3(256), 0, st,
-                     a, bm);
+  const long tasks = core::interior_task_count(m);
+  const unsigned blocks = (unsigned)(bm.nb * a.n_parts + (tasks + 3) / 4);
+  hipLaunchKernelGGL((adj_step<C, VEC>), dim3(blocks), dim3(256), 0, st, a, m, bm, tasks);
   return hipGetLastError();
 }
 

@@ -1199,9 +1199,11 @@ struct lbm_adjoint {
   bool fp64 = false;
   lbmk::Plate p{};       // the plate with pitch / plane in adjoint elements
   char *base = nullptr;
-  size_t off_m[2] = {0, 0}, off_w[2] = {0, 0}, off_cut = 0, off_part = 0, total = 0;
+  size_t off_m[2] = {0, 0}, off_w[2] = {0, 0}, off_cut = 0, off_part = 0, off_srow = 0,
+         off_srt = 0, total = 0;
   int n_parts = 0;
   int64_t cap = 0;       // sweeps the partial-sum table holds (trace_cap + 1)
+  const double *g = nullptr;  // loss gradient of the current run
   double ms = 0;
   int64_t sweeps = 0;
 };
@@ -1210,7 +1212,7 @@ namespace {
 
 struct AdjLayout {
   size_t esize = 0, plane = 0, off_m[2] = {0, 0}, off_w[2] = {0, 0}, off_cut = 0, off_part = 0,
-         total = 0;
+         off_srow = 0, off_srt = 0, total = 0;
   int n_parts = 0;
   int64_t cap = 0;
 };
@@ -1235,6 +1237,10 @@ AdjLayout adjoint_layout(const lbm_handle *h) {
   A.cap = std::max<int64_t>(h->cfg.trace_cap, 0) + 1;
   A.off_part = o;
   o += align_up((size_t)A.cap * 4 * A.n_parts * 8, 256);
+  A.off_srow = o;  // sensors by row: first entry of each row, ny + 1 values
+  o += align_up(((size_t)h->cfg.ny + 1) * 4, 256);
+  A.off_srt = o;   // (column, sensor index) sorted by row
+  o += align_up((size_t)std::max(h->cfg.n_sensors, 1) * 8, 256);
   A.total = o;
   return A;
 }
@@ -1267,6 +1273,12 @@ int adjoint_sweep(lbm_adjoint *a, int cur, int64_t m) {
     g.skip_lo = 1;
     g.skip_hi = 0;
   }
+  // the sweep writes the adjoint of w after step m - 1; the loss gradient of
+  // that trace row (step m - 2 of the trace) joins it there (m - 1 >= 1)
+  const int ns = h->cfg.n_sensors;
+  g.g = (ns > 0 && m >= 2) ? a->g + (size_t)(m - 2) * ns : nullptr;
+  g.srow = reinterpret_cast<const int32_t *>(a->base + a->off_srow);
+  g.srt = reinterpret_cast<const int32_t *>(a->base + a->off_srt);
   HIP_TRY(lbmk::launch_adjoint_sweep(a->fp64, &g, h->stream));
   return LBM_OK;
 }
@@ -1299,6 +1311,8 @@ int lbm_adjoint_init(lbm_handle *h, void *dev_buf, size_t dev_bytes, lbm_adjoint
   }
   a->off_cut = A.off_cut;
   a->off_part = A.off_part;
+  a->off_srow = A.off_srow;
+  a->off_srt = A.off_srt;
   a->total = A.total;
   a->n_parts = A.n_parts;
   a->cap = A.cap;
@@ -1342,6 +1356,25 @@ int lbm_adjoint_run(lbm_adjoint *a, const double *g, double *dL_dtau, double *dL
   // last trace row's gradient
   HIP_TRY(lbmk::launch_zero(a->base, a->total, st));
   HIP_TRY(hipMemcpyAsync(a->base + a->off_cut, cut.data(), cut.size() * 4, hipMemcpyHostToDevice, st));
+  // sensors indexed by row for the in-sweep injection of the loss gradient
+  std::vector<int32_t> srow(h->cfg.ny + 1, 0), srt(2 * (size_t)std::max(ns, 1), 0);
+  {
+    std::vector<int32_t> order(ns);
+    for (int k = 0; k < ns; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+      const int jx = h->sensors[2 * x + 1], jy = h->sensors[2 * y + 1];
+      return jx != jy ? jx < jy : h->sensors[2 * x] < h->sensors[2 * y];
+    });
+    for (int e = 0; e < ns; ++e) {
+      srt[2 * e] = h->sensors[2 * order[e]];
+      srt[2 * e + 1] = order[e];
+      srow[h->sensors[2 * order[e] + 1] + 1] += 1;
+    }
+    for (int j = 0; j < h->cfg.ny; ++j) srow[j + 1] += srow[j];
+  }
+  HIP_TRY(hipMemcpyAsync(a->base + a->off_srow, srow.data(), srow.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(a->base + a->off_srt, srt.data(), srt.size() * 4, hipMemcpyHostToDevice, st));
+  a->g = g;
   const int32_t *sens = reinterpret_cast<const int32_t *>(h->base + h->L.off_sens);
   if (ns > 0)
     HIP_TRY(lbmk::launch_adjoint_inject(a->fp64, a->base + a->off_w[0], a->p, sens, ns,
@@ -1355,10 +1388,6 @@ int lbm_adjoint_run(lbm_adjoint *a, const double *g, double *dL_dtau, double *dL
     const int rc = a->fp64 ? adjoint_sweep<double>(a, cur, m) : adjoint_sweep<float>(a, cur, m);
     if (rc != LBM_OK) return rc;
     cur = 1 - cur;
-    // loss gradient at w_{m-1}, the state the sweep just produced the adjoint of
-    if (ns > 0 && m - 1 >= 1)
-      HIP_TRY(lbmk::launch_adjoint_inject(a->fp64, a->base + a->off_w[cur], a->p, sens, ns,
-                                          g + (size_t)(m - 2) * ns, st));
   }
   HIP_TRY(hipEventRecord(e1, st));
   if (dL_dwdot0) HIP_TRY(lbmk::launch_adjoint_export(a->fp64, a->base + a->off_m[cur], a->p, dL_dwdot0, st));

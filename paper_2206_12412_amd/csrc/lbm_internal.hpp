@@ -152,12 +152,17 @@ struct AdjArgs {
   double *dtau_part;     // partial sums of dL/dtau_m: [4 rows][n_parts]
   int n_parts;           // blocks per boundary row
   int skip_lo, skip_hi;  // crack rows, handled by the boundary kernel
+  // loss gradient added to the written W at the sensors (g == nullptr: none);
+  // the sensors of row j are srt[srow[j] .. srow[j + 1]), entries (i, index)
+  const double *g;
+  const int32_t *srow;
+  const int32_t *srt;
 };
 
 // ---- launchers (adjoint.hip) ----
-// interior and boundary kernels of one adjoint sweep
+// one adjoint sweep (boundary rows and interior strips in one launch)
 hipError_t launch_adjoint_sweep(bool fp64, const void *args, hipStream_t st);
-// w[sensor s] += g[s] (after the sweep that wrote w)
+// w[sensor s] += g[s] (the loss gradient of the last step, before the first sweep)
 hipError_t launch_adjoint_inject(bool fp64, void *w, const Plate &p, const int32_t *sens, int n,
                                  const double *g, hipStream_t st);
 // dense FP64 [ny][nx] copy of one adjoint plane
