@@ -65,8 +65,6 @@ bool store_of(int32_t s, Store *out) {
   }
 }
 
-bool shifted(Store s) { return s == Store::F32S || s == Store::F16S || s == Store::BF16S; }
-
 size_t elem_size(Store s) {
   switch (s) {
     case Store::F64: return 8;
@@ -355,7 +353,7 @@ int tune_shapes(hipStream_t st, int32_t trial_steps, Set set, Run run, int32_t *
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess) return fail(LBM_EHIP, "event creation failed");
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return fail(LBM_EHIP, "event creation failed");
   }
   int rc = LBM_OK;
@@ -385,8 +383,8 @@ int tune_shapes(hipStream_t st, int32_t trial_steps, Set set, Run run, int32_t *
     }
     if (rc != LBM_OK) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc != LBM_OK) return rc;
   rc = set(br, bw, bo);
   if (rc != LBM_OK) return rc;
@@ -846,9 +844,9 @@ double lbm_bytes_per_site(const lbm_handle *h) {
 
 void lbm_free(lbm_handle *h) {
   if (!h) return;
-  if (!h->ev_used.empty()) hipStreamSynchronize(h->stream);
-  for (hipEvent_t e : h->ev_used) hipEventDestroy(e);
-  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+  if (!h->ev_used.empty()) (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev_used) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -1162,7 +1160,7 @@ int lbm_batch_timing(lbm_batch *b, int32_t enable, double *ms, int64_t *n_timed)
       b->t_ms += t;
       b->n_timed += 1;
     }
-    for (hipEvent_t e : b->ev_used) hipEventDestroy(e);
+    for (hipEvent_t e : b->ev_used) (void)hipEventDestroy(e);
     b->ev_used.clear();
   }
   if (ms) *ms = b->t_ms;
@@ -1184,8 +1182,8 @@ int64_t lbm_batch_sites(const lbm_batch *b) {
 
 void lbm_batch_free(lbm_batch *b) {
   if (!b) return;
-  if (!b->ev_used.empty()) hipStreamSynchronize(b->stream);
-  for (hipEvent_t e : b->ev_used) hipEventDestroy(e);
+  if (!b->ev_used.empty()) (void)hipStreamSynchronize(b->stream);
+  for (hipEvent_t e : b->ev_used) (void)hipEventDestroy(e);
   for (lbm_handle *h : b->plates) lbm_free(h);
   delete b;
 }
@@ -1379,9 +1377,16 @@ int lbm_adjoint_run(lbm_adjoint *a, const double *g, double *dL_dtau, double *dL
   if (ns > 0)
     HIP_TRY(lbmk::launch_adjoint_inject(a->fp64, a->base + a->off_w[0], a->p, sens, ns,
                                         g + (size_t)(T - 1) * ns, st));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  struct Events {  // destroyed on every return path
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  HIP_TRY(hipEventCreate(&ev.e0));
+  HIP_TRY(hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   HIP_TRY(hipEventRecord(e0, st));
   int cur = 0;
   for (int64_t m = T; m >= 0; --m) {
@@ -1400,8 +1405,6 @@ int lbm_adjoint_run(lbm_adjoint *a, const double *g, double *dL_dtau, double *dL
   HIP_TRY(hipStreamSynchronize(st));
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   a->ms = ms;
   a->sweeps = T + 1;
   if (dL_dtau) {
