@@ -23,6 +23,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 GROW_NONE, GROW_PRESCRIBED, GROW_SIF = 0, 1, 2
+EDGE_BOTTOM, EDGE_TOP, EDGE_LEFT, EDGE_RIGHT = 1, 2, 4, 8
 FLAG_GREW, FLAG_WALL, FLAG_K_UNDEF = 1, 2, 4
 
 
@@ -46,6 +47,8 @@ class _Cfg(C.Structure):
         ("tau_hist", C.POINTER(C.c_double)), ("n_hist", C.c_int64),
         ("w0", C.POINTER(C.c_double)), ("wdot0", C.POINTER(C.c_double)),
         ("trace_cap", C.c_int64), ("threads", C.c_int32),
+        ("crack_row", C.c_int32), ("both_tips", C.c_int32), ("dirichlet", C.c_int32),
+        ("wD_hist", C.POINTER(C.c_double)), ("n_wD", C.c_int64),
     ]
 
 
@@ -72,6 +75,8 @@ def _load():
         lib.orc_crack.argtypes = [C.c_void_p, P(d), P(d), P(i64), P(i32)]
         lib.orc_traces.argtypes = [C.c_void_p, P(d), P(d), P(d), P(i32), i64]
         lib.orc_traces.restype = i64
+        lib.orc_traces_left.argtypes = [C.c_void_p, P(d), P(d), P(d), P(i32), i64]
+        lib.orc_traces_left.restype = i64
         lib.orc_events.argtypes = [C.c_void_p, P(i64), P(i32), P(i32), P(i32), i64]
         lib.orc_events.restype = i64
         lib.orc_constants.argtypes = [C.c_void_p, P(d)]
@@ -115,6 +120,10 @@ class OracleConfig:
     wdot0: Optional[np.ndarray] = None
     trace_cap: int = 0
     threads: int = 0
+    crack_row: int = -1           # crack line y = crack_row + 1/2; -1 = ny/2 - 1
+    both_tips: bool = False       # the left end grows in -x as well
+    dirichlet: int = 0            # EDGE_* bits of the edges with a prescribed w
+    wD_hist: Optional[np.ndarray] = None   # [n][4] w* of (bottom, top, left, right) per step
     _keep: list = field(default_factory=list, repr=False)
 
 
@@ -127,11 +136,17 @@ class Oracle:
         c = _Cfg()
         for name in ("nx", "ny", "kappa", "omega", "mu", "rho", "crack_x0", "crack_tip", "growth",
                      "v_rel", "K_C", "r0", "v_max", "k_band", "face_traction", "trace_cap",
-                     "threads"):
+                     "threads", "crack_row", "dirichlet"):
             setattr(c, name, getattr(cfg, name))
         c.periodic = int(cfg.periodic)
         c.has_crack = int(cfg.has_crack)
+        c.both_tips = int(cfg.both_tips)
         keep = []
+        if cfg.wD_hist is not None:
+            wd = np.ascontiguousarray(cfg.wD_hist, dtype=np.float64).reshape(-1, 4)
+            keep.append(wd)
+            c.wD_hist = _dp(wd)
+            c.n_wD = wd.shape[0]
         if cfg.tau_hist is not None:
             t = np.ascontiguousarray(cfg.tau_hist, dtype=np.float64)
             keep.append(t)
@@ -197,12 +212,13 @@ class Oracle:
         self._lib.orc_crack(self._h, C.byref(tip), C.byref(v), C.byref(step), C.byref(flags))
         return {"tip": tip.value, "v": v.value, "step": step.value, "flags": flags.value}
 
-    def traces(self):
+    def traces(self, tip: str = "right"):
+        """Per-step K, tip position, speed and flags of the right (or left) tip."""
         n = max(self.cfg.trace_cap, 0)
         K, a, v = np.empty(n), np.empty(n), np.empty(n)
         fl = np.empty(n, np.int32)
-        m = self._lib.orc_traces(self._h, _dp(K), _dp(a), _dp(v),
-                                 fl.ctypes.data_as(C.POINTER(C.c_int32)), n)
+        fn = self._lib.orc_traces if tip == "right" else self._lib.orc_traces_left
+        m = fn(self._h, _dp(K), _dp(a), _dp(v), fl.ctypes.data_as(C.POINTER(C.c_int32)), n)
         return {"K": K[:m], "tip": a[:m], "v": v[:m], "flags": fl[:m]}
 
     def events(self):

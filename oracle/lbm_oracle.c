@@ -29,7 +29,13 @@
  *     (dt / (rho dh)) t* to the reflected population (momentum balance);
  *   - a vertical link is severed when the closed crack segment touches it;
  *   - K uses the column i_K = floor(a - r_min), r = a - i_K, r_min from
- *     eq. r(v) with the speed of the previous step.
+ *     eq. r(v) with the speed of the previous step (mirrored for a left tip:
+ *     i_K = ceil(a + r_min), r = i_K - a);
+ *   - a Dirichlet edge holds the prescribed w* at the wall (link midpoint) by
+ *     anti-bounce-back, f_in^alpha = -f^opp + 2 f_eq^alpha(w*, 0): the ghost
+ *     site then carries 2 w* - w (the leapfrog's antisymmetric ghost);
+ *   - with two tips, K and the criterion of both are evaluated on the same
+ *     field, then both advance, the right tip's cuts recorded first.
  */
 #include "lbm_oracle.h"
 
@@ -47,22 +53,29 @@ static const int OPP[NPOP] = {0, 3, 4, 1, 2};
 
 typedef struct { int32_t i, j, o; } link_t;  /* o: 0 vertical, 1 horizontal */
 
+/* One crack tip: position, speed of the last step, flags, the boundary points
+ * of its previous increment (Alg. 1, B_prev) and its traces.  dir = +1 for
+ * the right tip (grows in +x), -1 for the left one. */
+typedef struct {
+  int dir;
+  double a, v;
+  int32_t flags;
+  int32_t *bprev, nbprev, capbprev;
+  double *trK, *trA, *trV;
+  int32_t *trF;
+} tip_t;
+
 struct orc_sim {
   orc_config cfg;
   double *tau;                       /* private copy of the traction history */
+  double *wD;                        /* private copy of the wall displacements */
   double cs, c, dt, lambda, A0, Ak, coef;
   int32_t j0;
   double yc;
   double *f, *fn, *w;
   uint8_t *cutV, *cutH;
-  double tip, v;
+  tip_t tips[2];                     /* [0] right tip, [1] left end / left tip */
   int64_t step;
-  int32_t flags;
-  /* boundary points of the previous increment (Alg. 1, B_prev) */
-  int32_t *bprev, nbprev, capbprev;
-  /* traces */
-  double *trK, *trA, *trV;
-  int32_t *trF;
   /* cut events */
   int64_t *evs;
   int32_t *evi, *evj, *evo;
@@ -152,7 +165,10 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
   else if (!(cfg->mu > 0) || !(cfg->rho > 0)) e = -1;
   /* omega = 1 is the leapfrog scheme: stable only for kappa > sqrt(2). */
   else if (cfg->kappa * cfg->kappa <= 2.0) e = -4;
-  else if (cfg->has_crack && (cfg->ny < 2 || cfg->ny % 2 != 0)) e = -1;
+  else if (cfg->has_crack && cfg->crack_row < 0 && (cfg->ny < 2 || cfg->ny % 2 != 0)) e = -1;
+  else if (cfg->has_crack && cfg->crack_row >= 0 && cfg->crack_row > cfg->ny - 2) e = -1;
+  else if (cfg->both_tips && !cfg->has_crack) e = -1;
+  else if (cfg->dirichlet && (cfg->periodic || cfg->n_wD < 1 || !cfg->wD_hist)) e = -1;
   else if (cfg->has_crack && !(cfg->crack_x0 >= -0.5 && cfg->crack_tip >= cfg->crack_x0 &&
                                cfg->crack_tip <= cfg->nx - 0.5)) e = -5;
   else if (cfg->growth != ORC_GROW_NONE && (!cfg->has_crack || cfg->periodic)) e = -1;
@@ -175,6 +191,12 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
     memcpy(s->tau, cfg->tau_hist, sizeof(double) * (size_t)cfg->n_hist);
   }
   s->cfg.tau_hist = s->tau;
+  s->wD = NULL;
+  if (cfg->dirichlet) {
+    s->wD = (double *)malloc(sizeof(double) * 4 * (size_t)cfg->n_wD);
+    memcpy(s->wD, cfg->wD_hist, sizeof(double) * 4 * (size_t)cfg->n_wD);
+  }
+  s->cfg.wD_hist = s->wD;
   s->cfg.w0 = NULL;
   s->cfg.wdot0 = NULL;
 
@@ -186,7 +208,7 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
   s->A0 = 2.0 * s->lambda / (s->c * s->c);
   s->Ak = s->lambda / (2.0 * s->c * s->c);
   s->coef = s->dt / (cfg->rho * 1.0);
-  s->j0 = cfg->ny / 2 - 1;
+  s->j0 = cfg->crack_row >= 0 ? cfg->crack_row : cfg->ny / 2 - 1;
   s->yc = s->j0 + 0.5;
 
   s->f = (double *)calloc(NPOP * n, sizeof(double));
@@ -211,11 +233,22 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
     }
 
   /* Initial crack: every link intersected by the segment x0..a0 is severed. */
-  s->tip = cfg->crack_tip;
-  s->v = 0.0;
-  s->capbprev = 64;
-  s->bprev = (int32_t *)malloc(sizeof(int32_t) * 2 * s->capbprev);
-  s->nbprev = 0;
+  for (int t = 0; t < 2; ++t) {
+    tip_t *T = &s->tips[t];
+    T->dir = t == 0 ? 1 : -1;
+    T->a = t == 0 ? cfg->crack_tip : cfg->crack_x0;
+    T->v = 0.0;
+    T->flags = 0;
+    T->capbprev = 64;
+    T->bprev = (int32_t *)malloc(sizeof(int32_t) * 2 * T->capbprev);
+    T->nbprev = 0;
+    if (cfg->trace_cap > 0) {
+      T->trK = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
+      T->trA = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
+      T->trV = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
+      T->trF = (int32_t *)calloc((size_t)cfg->trace_cap, sizeof(int32_t));
+    }
+  }
   if (cfg->has_crack) {
     for (int j = 0; j < cfg->ny; ++j)
       for (int i = 0; i < cfg->nx; ++i) {
@@ -225,21 +258,19 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
         if (link_of(s, i, j, 1, 0, &L) && seg_hits_link(s, cfg->crack_x0, cfg->crack_tip, i, j, i + 1, j))
           set_cut(s, &L);
       }
-    /* B_prev: the pair of sites around the crack line at the tip column. */
-    int c = (int)floor(cfg->crack_tip);
-    if (c < 0) c = 0;
-    if (c > cfg->nx - 1) c = cfg->nx - 1;
-    s->bprev[0] = c; s->bprev[1] = s->j0;
-    s->bprev[2] = c; s->bprev[3] = s->j0 + 1;
-    s->nbprev = 2;
+    /* B_prev: the pair of sites around the crack line at the tip column
+     * (the right tip's floor(a), the left tip's ceil(a)). */
+    for (int t = 0; t < 2; ++t) {
+      tip_t *T = &s->tips[t];
+      int c = t == 0 ? (int)floor(T->a) : (int)ceil(T->a);
+      if (c < 0) c = 0;
+      if (c > cfg->nx - 1) c = cfg->nx - 1;
+      T->bprev[0] = c; T->bprev[1] = s->j0;
+      T->bprev[2] = c; T->bprev[3] = s->j0 + 1;
+      T->nbprev = 2;
+    }
   }
 
-  if (cfg->trace_cap > 0) {
-    s->trK = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
-    s->trA = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
-    s->trV = (double *)calloc((size_t)cfg->trace_cap, sizeof(double));
-    s->trF = (int32_t *)calloc((size_t)cfg->trace_cap, sizeof(int32_t));
-  }
   s->capev = 16;
   s->evs = (int64_t *)malloc(sizeof(int64_t) * s->capev);
   s->evi = (int32_t *)malloc(sizeof(int32_t) * s->capev);
@@ -251,9 +282,12 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
 
 void orc_free(orc_sim *s) {
   if (!s) return;
-  free(s->tau); free(s->f); free(s->fn); free(s->w); free(s->cutV); free(s->cutH);
-  free(s->inq); free(s->vis); free(s->queue); free(s->touched); free(s->bprev);
-  free(s->trK); free(s->trA); free(s->trV); free(s->trF);
+  free(s->tau); free(s->wD); free(s->f); free(s->fn); free(s->w); free(s->cutV); free(s->cutH);
+  free(s->inq); free(s->vis); free(s->queue); free(s->touched);
+  for (int t = 0; t < 2; ++t) {
+    free(s->tips[t].bprev);
+    free(s->tips[t].trK); free(s->tips[t].trA); free(s->tips[t].trV); free(s->tips[t].trF);
+  }
   free(s->evs); free(s->evi); free(s->evj); free(s->evo);
   free(s);
 }
@@ -283,6 +317,27 @@ static double tau_at(const orc_sim *s, int64_t n) {
   return s->tau[n < s->cfg.n_hist ? n : s->cfg.n_hist - 1];
 }
 
+/* The wall a population pulled along alpha at site (i, j) crosses when its
+ * upstream neighbour lies outside the plate (an ORC_EDGE_* bit). */
+static int edge_of(const orc_sim *s, int i, int j, int alpha) {
+  if (alpha == 1 && i == 0) return ORC_EDGE_LEFT;
+  if (alpha == 3 && i == s->cfg.nx - 1) return ORC_EDGE_RIGHT;
+  if (alpha == 2 && j == 0) return ORC_EDGE_BOTTOM;
+  if (alpha == 4 && j == s->cfg.ny - 1) return ORC_EDGE_TOP;
+  return 0;
+}
+
+/* Prescribed wall displacement of an edge at step n. */
+static double wall_w(const orc_sim *s, int edge, int64_t n) {
+  const double *row = s->wD + 4 * (n < s->cfg.n_wD ? n : s->cfg.n_wD - 1);
+  switch (edge) {
+    case ORC_EDGE_BOTTOM: return row[0];
+    case ORC_EDGE_TOP: return row[1];
+    case ORC_EDGE_LEFT: return row[2];
+    default: return row[3];
+  }
+}
+
 static int sweep_threads(const orc_sim *s) {
 #ifdef _OPENMP
   return s->cfg.threads > 0 ? s->cfg.threads : omp_get_max_threads();
@@ -310,6 +365,10 @@ static void lbm_sweep(orc_sim *s) {
           int si = i - EX[a], sj = j - EY[a];
           if (s->cfg.periodic) { si = (si + nx) % nx; sj = (sj + ny) % ny; }
           fin[a] = POP(s, s->f, a)[IDX(s, si, sj)];
+        } else if (!inside && (s->cfg.dirichlet & edge_of(s, i, j, a))) {
+          /* anti-bounce-back: the wall (link midpoint) holds w*, i.e. the
+           * ghost site carries 2 w* - w(x); f_eq^alpha(w*, 0) = Ak w* */
+          fin[a] = -POP(s, s->f, OPP[a])[x] + 2.0 * s->Ak * wall_w(s, edge_of(s, i, j, a), s->step);
         } else {
           /* bounce-back: the population that left x towards y returns */
           fin[a] = POP(s, s->f, OPP[a])[x] + s->coef * traction(s, j, a, !inside, tau);
@@ -333,26 +392,36 @@ double orc_sif(double delta, double r, double mu) {
   return delta * (mu / 4.0) * sqrt(2.0 * M_PI / r);
 }
 
-/* K at the current tip from the displacement jump across the crack faces. */
-static double evaluate_K(const orc_sim *s, double vK, int32_t *undef) {
+/* K at a tip from the displacement jump across the crack faces.  The right
+ * tip evaluates at the column i_K = floor(a - r_min) (and i_K - 1, ... for a
+ * band), the left tip at the mirrored column ceil(a + r_min) (and + 1, ...);
+ * r is the horizontal distance from the tip.  The columns must lie on the
+ * crack, i.e. between the two ends. */
+static double evaluate_K(const orc_sim *s, const tip_t *T, double vK, int32_t *undef) {
   const int nx = s->cfg.nx;
   const double rmin = s->cfg.r0 / (1.0 - vK);
-  const double iKf = floor(s->tip - rmin);
   const int band = s->cfg.k_band;
+  const double other = s->tips[T->dir > 0 ? 1 : 0].a;  /* the crack's other end */
   *undef = 1;
-  if (!(iKf - (band - 1) >= 0.0) || !(iKf <= nx - 1) || iKf - (band - 1) < s->cfg.crack_x0)
-    return NAN;
+  double iKf;
+  if (T->dir > 0) {
+    iKf = floor(T->a - rmin);
+    if (!(iKf - (band - 1) >= 0.0) || !(iKf <= nx - 1) || iKf - (band - 1) < other) return NAN;
+  } else {
+    iKf = ceil(T->a + rmin);
+    if (!(iKf >= 0.0) || !(iKf + (band - 1) <= nx - 1) || iKf + (band - 1) > other) return NAN;
+  }
   const int iK = (int)iKf;
   *undef = 0;
   if (band == 1) {
     double delta = fabs(s->w[IDX(s, iK, s->j0 + 1)] - s->w[IDX(s, iK, s->j0)]);
-    return orc_sif(delta, s->tip - iK, s->cfg.mu);
+    return orc_sif(delta, T->dir > 0 ? T->a - iK : iK - T->a, s->cfg.mu);
   }
   /* several columns: least-squares fit of delta_i = (4K/mu) sqrt(r_i / 2 pi) */
   double num = 0.0, den = 0.0;
   for (int b = 0; b < band; ++b) {
-    int i = iK - b;
-    double r = s->tip - i;
+    int i = iK - T->dir * b;
+    double r = T->dir > 0 ? T->a - i : i - T->a;
     double sq = sqrt(r / (2.0 * M_PI));
     double delta = fabs(s->w[IDX(s, i, s->j0 + 1)] - s->w[IDX(s, i, s->j0)]);
     num += delta * sq;
@@ -420,7 +489,7 @@ static int32_t check_links_bfs(orc_sim *s, double a0, double a1, const int32_t *
 
 double orc_eval_K(const orc_sim *s, double vK) {
   int32_t undef;
-  return evaluate_K(s, vK, &undef);
+  return evaluate_K(s, &s->tips[0], vK, &undef);
 }
 
 static void record_event(orc_sim *s, const link_t *L) {
@@ -438,67 +507,96 @@ static void record_event(orc_sim *s, const link_t *L) {
   s->nev++;
 }
 
-/* Alg. 1, CrackGrowth, appended after the time integration of the step. */
-static void crack_step(orc_sim *s) {
+/* EvaluateCriterion for one tip: whether it grows this step and at which
+ * speed (relative to c_s). */
+static int criterion(const orc_sim *s, const tip_t *T, double K, double *v) {
   const orc_config *cfg = &s->cfg;
-  const double vK = (cfg->growth == ORC_GROW_PRESCRIBED) ? cfg->v_rel : s->v;
-  int32_t undef = 0;
-  const double K = evaluate_K(s, vK, &undef);
-  int32_t flags = s->flags & ORC_FLAG_WALL;
-  if (undef) flags |= ORC_FLAG_K_UNDEF;
-
-  /* EvaluateCriterion */
-  int grow = 0;
-  double v = 0.0;
-  if (!(s->flags & ORC_FLAG_WALL)) {
-    if (cfg->growth == ORC_GROW_PRESCRIBED) {
-      grow = 1;
-      v = cfg->v_rel;
-    } else if (cfg->growth == ORC_GROW_SIF && K > cfg->K_C) {
-      /* eq. (v-tanh): crack speed regularised by the overshoot of K */
-      double q = K / cfg->K_C;
-      double q2 = q * q;
-      v = cfg->v_max * tanh(sqrt(q2 * q2 - 1.0));
-      grow = 1;
-    }
+  *v = 0.0;
+  if (T->flags & ORC_FLAG_WALL) return 0;
+  if (cfg->growth == ORC_GROW_PRESCRIBED) {
+    *v = cfg->v_rel;
+    return 1;
   }
-  if (grow) {
-    /* cr_tip <- cr_tip + v dt along +x; the increment is Delta a = (v c_s) dt */
-    const double a_prev = s->tip;
-    double a_new = a_prev + (v * s->cs) * s->dt;
+  if (cfg->growth == ORC_GROW_SIF && K > cfg->K_C) {
+    /* eq. (v-tanh): crack speed regularised by the overshoot of K */
+    double q = K / cfg->K_C;
+    double q2 = q * q;
+    *v = cfg->v_max * tanh(sqrt(q2 * q2 - 1.0));
+    return 1;
+  }
+  return 0;
+}
+
+/* Advance one tip by (v c_s) dt along its direction, find the intersected
+ * links with CheckLinks and sever them (ProcessPoints). */
+static void advance(orc_sim *s, tip_t *T, double v, int32_t *flags) {
+  const orc_config *cfg = &s->cfg;
+  const double a_prev = T->a;
+  double a_new;
+  if (T->dir > 0) {
+    a_new = a_prev + (v * s->cs) * s->dt;
     if (a_new >= cfg->nx - 0.5) {
       a_new = cfg->nx - 0.5;
-      flags |= ORC_FLAG_WALL;
+      *flags |= ORC_FLAG_WALL;
     }
-    link_t hits[16];
-    int32_t bnew[32];
-    int32_t nbnew = 0;
-    int32_t nh = check_links_bfs(s, a_prev, a_new, s->bprev, s->nbprev, hits, 16, bnew, &nbnew, 16);
-    /* ProcessPoints: sever the intersected links (no exchange along them) */
-    for (int h = 0; h < nh; ++h) {
-      if (!is_cut(s, &hits[h])) {
-        set_cut(s, &hits[h]);
-        record_event(s, &hits[h]);
-      }
+  } else {
+    a_new = a_prev - (v * s->cs) * s->dt;
+    if (a_new <= -0.5) {
+      a_new = -0.5;
+      *flags |= ORC_FLAG_WALL;
     }
-    if (nbnew > 0) {
-      if (nbnew > s->capbprev) {
-        s->capbprev = nbnew;
-        s->bprev = (int32_t *)realloc(s->bprev, sizeof(int32_t) * 2 * s->capbprev);
-      }
-      memcpy(s->bprev, bnew, sizeof(int32_t) * 2 * nbnew);
-      s->nbprev = nbnew;
-    }
-    s->tip = a_new;
-    flags |= ORC_FLAG_GREW;
   }
-  s->v = v;
-  s->flags = flags;
-  if (s->step < cfg->trace_cap) {
-    s->trK[s->step] = K;
-    s->trA[s->step] = s->tip;
-    s->trV[s->step] = v;
-    s->trF[s->step] = flags;
+  link_t hits[16];
+  int32_t bnew[32];
+  int32_t nbnew = 0;
+  int32_t nh = check_links_bfs(s, a_prev, a_new, T->bprev, T->nbprev, hits, 16, bnew, &nbnew, 16);
+  for (int h = 0; h < nh; ++h) {
+    if (!is_cut(s, &hits[h])) {
+      set_cut(s, &hits[h]);
+      record_event(s, &hits[h]);
+    }
+  }
+  if (nbnew > 0) {
+    if (nbnew > T->capbprev) {
+      T->capbprev = nbnew;
+      T->bprev = (int32_t *)realloc(T->bprev, sizeof(int32_t) * 2 * T->capbprev);
+    }
+    memcpy(T->bprev, bnew, sizeof(int32_t) * 2 * nbnew);
+    T->nbprev = nbnew;
+  }
+  T->a = a_new;
+  *flags |= ORC_FLAG_GREW;
+}
+
+/* Alg. 1, CrackGrowth, appended after the time integration of the step: K
+ * and the criterion at every growing tip on the same field, then the tips
+ * advance (the right tip's cuts are recorded first). */
+static void crack_step(orc_sim *s) {
+  const orc_config *cfg = &s->cfg;
+  const int ntips = cfg->both_tips ? 2 : 1;
+  double K[2] = {NAN, NAN}, v[2] = {0.0, 0.0};
+  int32_t flags[2] = {0, 0};
+  int grow[2] = {0, 0};
+  for (int t = 0; t < ntips; ++t) {
+    tip_t *T = &s->tips[t];
+    const double vK = (cfg->growth == ORC_GROW_PRESCRIBED) ? cfg->v_rel : T->v;
+    int32_t undef = 0;
+    K[t] = evaluate_K(s, T, vK, &undef);
+    flags[t] = T->flags & ORC_FLAG_WALL;
+    if (undef) flags[t] |= ORC_FLAG_K_UNDEF;
+    grow[t] = criterion(s, T, K[t], &v[t]);
+  }
+  for (int t = 0; t < ntips; ++t) {
+    tip_t *T = &s->tips[t];
+    if (grow[t]) advance(s, T, v[t], &flags[t]);
+    T->v = v[t];
+    T->flags = flags[t];
+    if (s->step < cfg->trace_cap) {
+      T->trK[s->step] = K[t];
+      T->trA[s->step] = T->a;
+      T->trV[s->step] = v[t];
+      T->trF[s->step] = flags[t];
+    }
   }
 }
 
@@ -548,6 +646,8 @@ double orc_adjoint_step(orc_sim *s, double *lam_f, double *lam_w) {
           int si = i - EX[a], sj = j - EY[a];
           if (s->cfg.periodic) { si = (si + nx) % nx; sj = (sj + ny) % ny; }
           lam_f[a * n + IDX(s, si, sj)] += g;
+        } else if (!inside && (s->cfg.dirichlet & edge_of(s, i, j, a))) {
+          lam_f[OPP[a] * n + x] -= g;  /* anti-bounce-back: f_in = -f^opp + const */
         } else {
           lam_f[OPP[a] * n + x] += g;
           if (!inside && !s->cfg.periodic) {
@@ -592,23 +692,33 @@ void orc_get_mask(const orc_sim *s, uint8_t *cutV, uint8_t *cutH) {
 }
 
 void orc_crack(const orc_sim *s, double *tip, double *v, int64_t *step, int32_t *flags) {
-  if (tip) *tip = s->tip;
-  if (v) *v = s->v;
+  if (tip) *tip = s->tips[0].a;
+  if (v) *v = s->tips[0].v;
   if (step) *step = s->step;
-  if (flags) *flags = s->flags;
+  if (flags) *flags = s->tips[0].flags;
+}
+
+static int64_t tip_traces(const orc_sim *s, const tip_t *T, double *K, double *tip, double *v,
+                          int32_t *flags, int64_t cap) {
+  int64_t n = s->step < s->cfg.trace_cap ? s->step : s->cfg.trace_cap;
+  if (n > cap) n = cap;
+  for (int64_t k = 0; k < n; ++k) {
+    if (K) K[k] = T->trK[k];
+    if (tip) tip[k] = T->trA[k];
+    if (v) v[k] = T->trV[k];
+    if (flags) flags[k] = T->trF[k];
+  }
+  return n;
 }
 
 int64_t orc_traces(const orc_sim *s, double *K, double *tip, double *v, int32_t *flags,
                    int64_t cap) {
-  int64_t n = s->step < s->cfg.trace_cap ? s->step : s->cfg.trace_cap;
-  if (n > cap) n = cap;
-  for (int64_t k = 0; k < n; ++k) {
-    if (K) K[k] = s->trK[k];
-    if (tip) tip[k] = s->trA[k];
-    if (v) v[k] = s->trV[k];
-    if (flags) flags[k] = s->trF[k];
-  }
-  return n;
+  return tip_traces(s, &s->tips[0], K, tip, v, flags, cap);
+}
+
+int64_t orc_traces_left(const orc_sim *s, double *K, double *tip, double *v, int32_t *flags,
+                        int64_t cap) {
+  return tip_traces(s, &s->tips[1], K, tip, v, flags, cap);
 }
 
 int64_t orc_events(const orc_sim *s, int64_t *step, int32_t *i, int32_t *j, int32_t *orient,

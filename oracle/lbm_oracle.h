@@ -13,8 +13,12 @@
  *   arrays are row-major [j][i]; populations are [alpha][j][i];
  *   directions alpha: 0 rest, 1 +x, 2 +y, 3 -x, 4 -y  (Sec. 3, D2Q5 lattice);
  *   walls lie half-way between the outer sites and the (absent) ghost sites;
- *   the crack runs along y_c = j0 + 1/2 with j0 = ny/2 - 1, from x = crack_x0
- *   to the tip x = a, and grows in +x.
+ *   the crack runs along y_c = j0 + 1/2 (j0 = crack_row, default ny/2 - 1),
+ *   from x = crack_x0 to the tip x = a, and grows in +x; with both_tips its
+ *   left end is a second tip that grows in -x by the same rule.
+ *   An edge is traction-loaded (default: top +tau, bottom -tau, lateral 0) or,
+ *   if its bit is set in `dirichlet`, holds a prescribed displacement w* at
+ *   the wall by anti-bounce-back: f_in = -f^opp + 2 f_eq(w*, 0).
  */
 #ifndef LBM_ORACLE_H
 #define LBM_ORACLE_H
@@ -26,6 +30,7 @@ extern "C" {
 
 enum { ORC_GROW_NONE = 0, ORC_GROW_PRESCRIBED = 1, ORC_GROW_SIF = 2 };
 enum { ORC_FLAG_GREW = 1, ORC_FLAG_WALL = 2, ORC_FLAG_K_UNDEF = 4 };
+enum { ORC_EDGE_BOTTOM = 1, ORC_EDGE_TOP = 2, ORC_EDGE_LEFT = 4, ORC_EDGE_RIGHT = 8 };
 
 typedef struct {
   int32_t nx, ny;
@@ -47,6 +52,11 @@ typedef struct {
   const double *wdot0;     /* optional initial velocity [ny][nx] (NULL = 0)      */
   int64_t trace_cap;       /* length of the per-step K / tip / speed traces      */
   int32_t threads;         /* OpenMP threads for the sweep (0 = runtime default) */
+  int32_t crack_row;       /* j0 of the crack line y = j0 + 1/2; -1 = ny/2 - 1    */
+  int32_t both_tips;       /* 1: the left end crack_x0 grows in -x as well       */
+  int32_t dirichlet;       /* ORC_EDGE_* bits of the edges with a prescribed w   */
+  const double *wD_hist;   /* [n_wD][4] w* of (bottom, top, left, right); step n  */
+  int64_t n_wD;            /* uses row min(n, n_wD - 1)                          */
 } orc_config;
 
 typedef struct orc_sim orc_sim;
@@ -67,6 +77,9 @@ void orc_get_mask(const orc_sim *s, uint8_t *cutV, uint8_t *cutH);
 void orc_crack(const orc_sim *s, double *tip, double *v, int64_t *step, int32_t *flags);
 int64_t orc_traces(const orc_sim *s, double *K, double *tip, double *v, int32_t *flags,
                    int64_t cap);
+/* The same for the left tip (both_tips). */
+int64_t orc_traces_left(const orc_sim *s, double *K, double *tip, double *v, int32_t *flags,
+                        int64_t cap);
 /* Cut events produced by crack growth: step, site (i, j) and orientation
  * (0 = vertical link (i,j)-(i,j+1), 1 = horizontal link (i,j)-(i+1,j)). */
 int64_t orc_events(const orc_sim *s, int64_t *step, int32_t *i, int32_t *j, int32_t *orient,
@@ -91,7 +104,8 @@ double orc_eval_K(const orc_sim *s, double vK);
 /* eq. (sif): K from the crack opening delta at distance r. */
 double orc_sif(double delta, double r, double mu);
 
-/* Discrete adjoint of the affine LBM map (stationary crack, fixed mask):
+/* Discrete adjoint of the affine LBM map (stationary crack, fixed mask;
+ * a Dirichlet edge enters with the sign of its anti-bounce-back):
  * given lam_f [5][ny][nx] and lam_w [ny][nx] (adjoint of the state after a step),
  * overwrite them with the adjoint of the state before the step and return the
  * derivative of <lam, state_after> with respect to the step's traction tau. */

@@ -607,3 +607,120 @@ def test_sensor_adjoint_matches_central_differences():
 
     fd = (loss_w0(h * d_w0) - loss_w0(-h * d_w0)) / (2 * h)
     assert (dw0 * d_w0).sum() == pytest.approx(fd, rel=1e-9)
+
+
+# ------------------------------------- Dirichlet edges, crack row, two tips --
+
+def leapfrog_general(nx, ny, steps, cut_at, tau, dirichlet=0, wD=None, w0=None, wd0=None,
+                     kappa=2.0):
+    """Textbook leapfrog for w_tt = lap w (mu = rho = 1) with ghost sites:
+    traction edge -> ghost w +- dh t*/mu (top +tau, bottom -tau, sides 0);
+    Dirichlet edge with wall value w* at the midpoint -> ghost 2 w* - w;
+    severed vertical link -> mirror ghost on both sides."""
+    dt = 1.0 / kappa
+    w = np.zeros((ny, nx)) if w0 is None else w0.copy()
+    v = np.zeros((ny, nx)) if wd0 is None else wd0.copy()
+    for n in range(steps):
+        t = tau[min(n, len(tau) - 1)]
+        wb, wt, wl, wr = wD[min(n, len(wD) - 1)] if wD is not None else (0, 0, 0, 0)
+        g_l = np.empty_like(w); g_l[:, 1:] = w[:, :-1]
+        g_r = np.empty_like(w); g_r[:, :-1] = w[:, 1:]
+        g_d = np.empty_like(w); g_d[1:] = w[:-1]
+        g_u = np.empty_like(w); g_u[:-1] = w[1:]
+        g_l[:, 0] = 2 * wl - w[:, 0] if dirichlet & O.EDGE_LEFT else w[:, 0]
+        g_r[:, -1] = 2 * wr - w[:, -1] if dirichlet & O.EDGE_RIGHT else w[:, -1]
+        g_d[0] = 2 * wb - w[0] if dirichlet & O.EDGE_BOTTOM else w[0] - t
+        g_u[-1] = 2 * wt - w[-1] if dirichlet & O.EDGE_TOP else w[-1] + t
+        jj, ii = np.nonzero(cut_at(n))
+        g_u[jj, ii] = w[jj, ii]
+        g_d[jj + 1, ii] = w[jj + 1, ii]
+        lap = (g_l - w) + (g_r - w) + (g_d - w) + (g_u - w)
+        v = v + (dt * dt / dt) * lap  # c_s^2 dt / dh^2 with c_s = 1
+        w = w + dt * v
+    return w, v
+
+
+def two_tip_path(x0, a0, v, steps, nx, cs=1.0, dt=0.5):
+    """Tip positions a_n of both ends under a prescribed speed (FP64, one add
+    per step, clamped at the walls)."""
+    R, L = [a0], [x0]
+    for n in range(steps):
+        R.append(min(R[-1] + (v * cs) * dt, nx - 0.5))
+        L.append(max(L[-1] - (v * cs) * dt, -0.5))
+    return R, L
+
+
+def test_dirichlet_edges_off_centre_crack_and_two_tips_equal_leapfrog():
+    nx, ny, j0, steps, v = 36, 20, 12, 240, 0.4
+    x0, a0 = 13.5, 20.5
+    R, L = two_tip_path(x0, a0, v, steps, nx)
+
+    def cut_at(n):
+        c = np.zeros((ny, nx), bool)
+        cols = np.arange(nx)
+        c[j0, (cols >= L[n]) & (cols <= R[n])] = True
+        return c
+
+    rng = np.random.default_rng(11)
+    wd0 = rng.normal(0, 1e-4, (ny, nx))
+    n = np.arange(steps)
+    wD = np.zeros((steps, 4))
+    wD[:, 1] = 0.02 * np.sin(np.pi * n / 120.0) * (n < 120)   # top: half sine pulse
+    wD[:, 2] = 3e-3                                         # left: constant
+    dmask = O.EDGE_BOTTOM | O.EDGE_TOP | O.EDGE_LEFT
+    s = make(nx=nx, ny=ny, has_crack=True, crack_row=j0, crack_x0=x0, crack_tip=a0,
+             both_tips=True, growth=O.GROW_PRESCRIBED, v_rel=v, tau_hist=np.array([1e-3]),
+             dirichlet=dmask, wD_hist=wD, wdot0=wd0, trace_cap=steps)
+    s.step(steps)
+    w, wd = s.fields()
+    wf, vf = leapfrog_general(nx, ny, steps, cut_at, [1e-3], dirichlet=dmask, wD=wD, wd0=wd0)
+    assert np.abs(w - wf).max() < 1e-12 * np.abs(wf).max()
+    assert np.abs(wd - vf).max() < 1e-11 * np.abs(vf).max()
+    # both tips advanced as the closed form says, the left one clamped at the wall
+    tr, tl = s.traces("right"), s.traces("left")
+    np.testing.assert_array_equal(tr["tip"], R[1:])
+    np.testing.assert_array_equal(tl["tip"], L[1:])
+    assert tl["flags"][-1] & O.FLAG_WALL and not tl["flags"][0] & O.FLAG_WALL
+    mv, _ = s.mask()
+    assert mv[j0].all() and not np.delete(mv, j0, axis=0).any()
+
+
+def test_linear_profile_between_dirichlet_walls_is_static():
+    """w* = A on the top wall (y = ny - 1/2), 0 on the bottom wall (y = -1/2),
+    free sides: w = A (j + 1/2) / ny with wdot = 0 is an exact equilibrium."""
+    nx, ny, A = 14, 10, 0.3
+    J = np.arange(ny)[:, None] * np.ones((1, nx))
+    w0 = A * (J + 0.5) / ny
+    s = make(nx=nx, ny=ny, w0=w0, dirichlet=O.EDGE_BOTTOM | O.EDGE_TOP,
+             wD_hist=np.array([[0.0, A, 0.0, 0.0]]))
+    s.step(300)
+    w, wd = s.fields()
+    assert np.abs(wd).max() < 1e-15 and np.abs(w - w0).max() < 1e-15
+
+
+def test_two_tips_mirror_symmetry():
+    """A centre crack symmetric about the plate's vertical mid-line under
+    symmetric loading: the left tip mirrors the right one (K, speed, cuts),
+    for a prescribed speed and for the K criterion."""
+    nx, ny, steps = 60, 40, 600
+    x0, a0 = 21.5, (nx - 1) - 21.5
+    # v c_s dt = 0.178550: no exact tie (a_n equal to an integer column) in the run,
+    # so the rounding of the two accumulations cannot decide a cut differently
+    for growth, extra in ((O.GROW_PRESCRIBED, dict(v_rel=0.3571)),
+                          (O.GROW_SIF, dict(K_C=0.004))):
+        s = make(nx=nx, ny=ny, has_crack=True, crack_row=25, crack_x0=x0, crack_tip=a0,
+                 both_tips=True, growth=growth, tau_hist=np.array([1e-3]), trace_cap=steps,
+                 **extra)
+        s.step(steps)
+        w, _ = s.fields()
+        assert np.abs(w - w[:, ::-1]).max() <= 1e-13 * np.abs(w).max()
+        tr, tl = s.traces("right"), s.traces("left")
+        ok = ~np.isnan(tr["K"])
+        np.testing.assert_allclose(tl["K"][ok], tr["K"][ok], rtol=1e-12, atol=0)
+        np.testing.assert_array_equal(np.isnan(tl["K"]), np.isnan(tr["K"]))
+        np.testing.assert_allclose(tl["v"], tr["v"], rtol=1e-12, atol=0)
+        assert (tr["flags"] & O.FLAG_GREW).any()
+        ev = s.events()  # (step, i, j, orient)
+        right = {(int(e[0]), int(e[1])) for e in ev if e[1] > nx // 2}
+        left = {(int(e[0]), nx - 1 - int(e[1])) for e in ev if e[1] < nx // 2}
+        assert right == left and len(right) > 0
