@@ -76,6 +76,12 @@ enum lbm_flags { LBM_FLAG_GREW = 1, LBM_FLAG_WALL = 2, LBM_FLAG_K_UNDEF = 4 };
  * so that rounding errors do not accumulate coherently over steps.  Results
  * stay deterministic: they depend on (site, step, seed), not on the launch. */
 enum lbm_rounding { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
+/* Plate edges.  An edge is traction-loaded by default (top +tau_n, bottom
+ * -tau_n, lateral edges free); an edge whose bit is set in cfg->dirichlet
+ * holds a prescribed displacement w* at the wall (the link midpoint) by
+ * anti-bounce-back, f_in^alpha = -f^opp + 2 f_eq^alpha(w*, 0) (the ghost site
+ * then carries 2 w* - w), as the lower and upper edges of Sec. 5.2. */
+enum lbm_edge { LBM_EDGE_BOTTOM = 1, LBM_EDGE_TOP = 2, LBM_EDGE_LEFT = 4, LBM_EDGE_RIGHT = 8 };
 
 typedef struct lbm_config {
   int32_t nx, ny;          /* sites; ny even and >= 2 when there is a crack      */
@@ -103,6 +109,13 @@ typedef struct lbm_config {
   uint32_t seed;           /* seed of the stochastic rounding                    */
   int32_t n_sensors;       /* sensor sites: w there is recorded after each step  */
   const int32_t *sensors;  /* host [n_sensors][2] = (i, j), distinct; copied     */
+  int32_t crack_row;       /* j0 of the crack line y = j0 + 1/2 (0..ny-2); -1 =  */
+                           /* the mid-line ny/2 - 1 (then ny must be even)       */
+  int32_t both_tips;       /* 1: the left end crack_x0 is a tip too and grows in */
+                           /* -x by the same rule (Sec. 5.2: two tips)           */
+  int32_t dirichlet;       /* enum lbm_edge bits: edges holding a prescribed w   */
+  const double *wD_hist;   /* host [n_wD][4]: w* of (bottom, top, left, right);  */
+  int64_t n_wD;            /* step n uses row min(n, n_wD - 1); copied           */
   void *dev_buf;           /* device memory, >= lbm_state_bytes(cfg), 256-aligned */
   size_t dev_bytes;
   void *stream;            /* hipStream_t; NULL = the null stream                */
@@ -118,6 +131,9 @@ typedef struct lbm_crack_info {
   int32_t n_events;/* cut events recorded so far                            */
   int32_t col_K;   /* column used for that K (-1 if undefined)              */
   int32_t n_cut;   /* severed links on the crack row                        */
+  /* the left end (a tip when cfg->both_tips; otherwise crack_x0, at rest) */
+  double tip_left, v_left, K_left, r_left;
+  int32_t flags_left, col_K_left;
 } lbm_crack_info;
 
 typedef struct lbm_handle lbm_handle;
@@ -147,6 +163,11 @@ int lbm_sif(lbm_handle *h, double *K_out, int64_t first, int64_t count);
  * any output pointer may be NULL. */
 int lbm_traces(lbm_handle *h, double *tip_out, double *v_out, int32_t *flags_out,
                int64_t first, int64_t count);
+
+/* K, position, speed and flags of the left tip (cfg->both_tips), same
+ * indexing; any output pointer may be NULL. */
+int lbm_traces_left(lbm_handle *h, double *K_out, double *tip_out, double *v_out,
+                    int32_t *flags_out, int64_t first, int64_t count);
 
 /* Sensor traces: w at the sensor sites after each step, rows [first,
  * first + count) of the [trace_cap][n_sensors] FP64 table (row n = after step

@@ -120,8 +120,10 @@ __device__ __forceinline__ void adj_interior_row(const AdjArgs<C> &a, int strip,
     C l1 = (k == VEC - 1) ? ((lane == 63) ? s_right : m1R) : m1[k + 1];
     // adjoint of f^3(i): mu^3 of the left neighbour (the -x link)
     C l3 = (k == 0) ? ((lane == 0) ? s_left : m3L) : m3[k - 1];
-    if (i == last) l1 = p.periodic ? s_wrap : m3[k];
-    if (i == 0 && !p.periodic) l3 = m1[k];
+    // outside links: bounce-back returns the opposite direction's adjoint,
+    // a Dirichlet edge (anti-bounce-back) with the opposite sign
+    if (i == last) l1 = p.periodic ? s_wrap : ((a.dmask & core::kEdgeRight) ? -m3[k] : m3[k]);
+    if (i == 0 && !p.periodic) l3 = (a.dmask & core::kEdgeLeft) ? -m1[k] : m1[k];
     adj_local<C>(a, m0[k], l1, m2u[k], l3, m4d[k], b[k], o0[k], o1[k], o2[k], o3[k], o4[k], wo[k]);
     if (i > last) o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
   }
@@ -174,10 +176,15 @@ __device__ __forceinline__ void adj_boundary_site(const AdjArgs<C> &a, int r, in
     const bool cut_dn = cut && j == p.j0 + 1;
     const C *M = a.min;
     const C l0 = M[x];
-    const C l1 = i < last ? M[P + x + 1] : (p.periodic ? M[P + (size_t)j * pitch] : M[3 * P + x]);
-    const C l3 = i > 0 ? M[3 * P + x - 1] : (p.periodic ? M[3 * P + (size_t)j * pitch + last] : M[P + x]);
-    const C l2 = (jp >= 0 && !cut_up) ? M[2 * P + (size_t)jp * pitch + i] : M[4 * P + x];
-    const C l4 = (jm >= 0 && !cut_dn) ? M[4 * P + (size_t)jm * pitch + i] : M[2 * P + x];
+    // outside links of a Dirichlet edge: anti-bounce-back, sign -1
+    const C sr = (a.dmask & core::kEdgeRight) ? C(-1) : C(1);
+    const C sl = (a.dmask & core::kEdgeLeft) ? C(-1) : C(1);
+    const C st = (jp < 0 && (a.dmask & core::kEdgeTop)) ? C(-1) : C(1);
+    const C sb = (jm < 0 && (a.dmask & core::kEdgeBottom)) ? C(-1) : C(1);
+    const C l1 = i < last ? M[P + x + 1] : (p.periodic ? M[P + (size_t)j * pitch] : sr * M[3 * P + x]);
+    const C l3 = i > 0 ? M[3 * P + x - 1] : (p.periodic ? M[3 * P + (size_t)j * pitch + last] : sl * M[P + x]);
+    const C l2 = (jp >= 0 && !cut_up) ? M[2 * P + (size_t)jp * pitch + i] : st * M[4 * P + x];
+    const C l4 = (jm >= 0 && !cut_dn) ? M[4 * P + (size_t)jm * pitch + i] : sb * M[2 * P + x];
     C o0, o1, o2, o3, o4, wo;
     adj_local<C>(a, l0, l1, l2, l3, l4, a.win[x], o0, o1, o2, o3, o4, wo);
     if (a.g) {
@@ -190,9 +197,9 @@ __device__ __forceinline__ void adj_boundary_site(const AdjArgs<C> &a, int r, in
     a.mout[3 * P + x] = o3;
     a.mout[4 * P + x] = o4;
     a.wout[x] = wo;
-    if (a.traction) {
-      if (j == p.ny - 1) dtau += a.coef * (double)M[4 * P + x];
-      if (j == 0) dtau -= a.coef * (double)M[2 * P + x];
+    if (a.traction) {  // traction-loaded edges only (not the Dirichlet ones)
+      if (j == p.ny - 1 && !(a.dmask & core::kEdgeTop)) dtau += a.coef * (double)M[4 * P + x];
+      if (j == 0 && !(a.dmask & core::kEdgeBottom)) dtau -= a.coef * (double)M[2 * P + x];
     }
   }
   const double s = block_sum(dtau, red);

@@ -47,6 +47,7 @@ struct Layout {
   size_t off_w[2] = {0, 0};
   size_t off_mV = 0, off_mH = 0, off_rf = 0, off_crack = 0;
   size_t off_trK = 0, off_trA = 0, off_trV = 0, off_trF = 0;
+  size_t off_trKL = 0, off_trAL = 0, off_trVL = 0, off_trFL = 0;
   size_t off_evS = 0, off_evC = 0, off_stage = 0;
   size_t off_sens = 0, off_trS = 0;
   int64_t event_cap = 0;
@@ -103,6 +104,11 @@ Layout make_layout(const lbm_config &c, Store s) {
   L.off_trA = o; o += align_up(tc * 8, 256);
   L.off_trV = o; o += align_up(tc * 8, 256);
   L.off_trF = o; o += align_up(tc * 4, 256);
+  const size_t tl = c.both_tips ? tc : 1;  // left-tip traces (two tips)
+  L.off_trKL = o; o += align_up(tl * 8, 256);
+  L.off_trAL = o; o += align_up(tl * 8, 256);
+  L.off_trVL = o; o += align_up(tl * 8, 256);
+  L.off_trFL = o; o += align_up(tl * 4, 256);
   L.event_cap = (int64_t)c.nx + 8;
   L.off_evS = o; o += align_up((size_t)L.event_cap * 8, 256);
   L.off_evC = o; o += align_up((size_t)L.event_cap * 4, 256);
@@ -135,8 +141,11 @@ int validate(const lbm_config *c, Store *s) {
     return fail(LBM_EUNSTABLE, "omega = %g: with w integrated into f_eq the scheme is stable only at tau = dt", c->omega);
   if (c->kappa * c->kappa <= 2.0)
     return fail(LBM_EUNSTABLE, "kappa = %g: the scheme needs kappa > sqrt(2)", c->kappa);
+  if (c->crack_row < -1) return fail(LBM_EINVAL, "crack_row must be -1 (mid-line) or a row");
   if (c->has_crack) {
-    if (c->ny < 2 || c->ny % 2) return fail(LBM_EINVAL, "a crack needs an even ny >= 2");
+    if (c->crack_row < 0 && (c->ny < 2 || c->ny % 2))
+      return fail(LBM_EINVAL, "a crack on the mid-line needs an even ny >= 2");
+    if (c->crack_row > c->ny - 2) return fail(LBM_EINVAL, "crack_row must be in 0..ny-2");
     if (!(c->crack_x0 >= -0.5) || !(c->crack_tip >= c->crack_x0) || !(c->crack_tip <= c->nx - 0.5))
       return fail(LBM_ECRACK, "crack [%g, %g] not inside [-0.5, %g]", c->crack_x0, c->crack_tip, c->nx - 0.5);
     if (!(c->r0 > 0)) return fail(LBM_EINVAL, "r0 must be positive");
@@ -152,6 +161,12 @@ int validate(const lbm_config *c, Store *s) {
     return fail(LBM_EINVAL, "K criterion needs K_C > 0 and v_max in [0, 1)");
   if (c->n_hist < 0 || (c->n_hist > 0 && !c->tau_hist)) return fail(LBM_EINVAL, "bad traction history");
   if (c->trace_cap < 0) return fail(LBM_EINVAL, "negative trace_cap");
+  if (c->both_tips && !c->has_crack) return fail(LBM_EINVAL, "both_tips needs a crack");
+  if (c->dirichlet < 0 || c->dirichlet > 15) return fail(LBM_EINVAL, "dirichlet holds edge bits 1..8");
+  if (c->dirichlet && c->bc_mode == LBM_BC_PERIODIC)
+    return fail(LBM_EINVAL, "a periodic lattice has no edges");
+  if (c->dirichlet && (c->n_wD < 1 || !c->wD_hist))
+    return fail(LBM_EINVAL, "Dirichlet edges need a wall-displacement history");
   if (c->n_sensors < 0 || c->n_sensors > (1 << 20) || (c->n_sensors > 0 && !c->sensors))
     return fail(LBM_EINVAL, "bad sensor list");
   if (c->n_sensors > 0) {
@@ -198,6 +213,7 @@ struct lbm_handle {
   lbmk::DevCrack host_crack{};
   bool in_batch = false;  // stepped by a batch; lbm_step refuses it
   std::vector<int32_t> sensors;  // host copy of the sensor sites
+  std::vector<double> wD;        // host copy of the wall-displacement history [n][4]
 
   bool crack_step_needed() const { return cfg.has_crack || cfg.n_sensors > 0; }
 
@@ -286,6 +302,16 @@ int launch_sweep_typed(lbm_handle *h) {
   }
   a.sr = h->cfg.rounding == LBM_ROUND_STOCHASTIC;
   a.rkey = lbmk::step_key(h->cfg.seed, h->step);
+  a.dmask = per ? 0 : h->cfg.dirichlet;
+  if (a.dmask) {
+    const size_t r = 4 * (size_t)std::min<int64_t>(h->step, h->cfg.n_wD - 1);
+    a.wD_bot = (C)h->wD[r];
+    a.wD_top = (C)h->wD[r + 1];
+    a.wD_left = (C)h->wD[r + 2];
+    a.wD_right = (C)h->wD[r + 3];
+  } else {
+    a.wD_bot = a.wD_top = a.wD_left = a.wD_right = C(0);
+  }
   HIP_TRY(lbmk::launch_sweep(h->store, &a, h->stream));
   return LBM_OK;
 }
@@ -312,6 +338,10 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
   a.trA = reinterpret_cast<double *>(h->base + h->L.off_trA);
   a.trV = reinterpret_cast<double *>(h->base + h->L.off_trV);
   a.trF = reinterpret_cast<int32_t *>(h->base + h->L.off_trF);
+  a.trKL = reinterpret_cast<double *>(h->base + h->L.off_trKL);
+  a.trAL = reinterpret_cast<double *>(h->base + h->L.off_trAL);
+  a.trVL = reinterpret_cast<double *>(h->base + h->L.off_trVL);
+  a.trFL = reinterpret_cast<int32_t *>(h->base + h->L.off_trFL);
   a.evStep = reinterpret_cast<int64_t *>(h->base + h->L.off_evS);
   a.evCol = reinterpret_cast<int32_t *>(h->base + h->L.off_evC);
   a.sens = reinterpret_cast<const int32_t *>(h->base + h->L.off_sens);
@@ -319,6 +349,7 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
   a.n_sens = h->cfg.n_sensors;
   a.p = h->plate;
   a.c.crack = h->cfg.has_crack;
+  a.c.both = h->cfg.both_tips;
   a.c.growth = h->cfg.growth;
   a.c.band = h->cfg.k_band;
   a.c.v_rel = h->cfg.v_rel;
@@ -431,6 +462,8 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   h->cfg.wdot0 = nullptr;
   if (cfg->n_sensors > 0) h->sensors.assign(cfg->sensors, cfg->sensors + 2 * (size_t)cfg->n_sensors);
   h->cfg.sensors = nullptr;
+  if (cfg->dirichlet) h->wD.assign(cfg->wD_hist, cfg->wD_hist + 4 * (size_t)cfg->n_wD);
+  h->cfg.wD_hist = nullptr;
   h->base = static_cast<char *>(cfg->dev_buf);
   // lattice constants (Sec. 3): c = kappa c_s, dt = dh / c with dh = 1,
   // lambda = c_s^2 / (dt (1/omega - 1/2)), f_eq^0 = wdot - A0 w, f_eq^k = Ak w,
@@ -447,7 +480,7 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   p.ny = cfg->ny;
   p.pitch = L.pitch;
   p.mw = L.mw;
-  p.j0 = cfg->ny / 2 - 1;
+  p.j0 = cfg->crack_row >= 0 ? cfg->crack_row : cfg->ny / 2 - 1;
   p.periodic = cfg->bc_mode == LBM_BC_PERIODIC;
   p.plane = L.plane;
   // default launch shape, the fastest of the autotuner's grid on MI355X for a
@@ -511,6 +544,12 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   c0.flags = 0;
   c0.n_events = 0;
   c0.col_K = -1;
+  c0.tipL = cfg->has_crack ? cfg->crack_x0 : 0.0;
+  c0.vL = 0.0;
+  c0.KL = std::nan("");
+  c0.rL = std::nan("");
+  c0.flagsL = 0;
+  c0.col_KL = -1;
   if (cfg->has_crack) {
     const int lo = std::max(0, (int)std::ceil(cfg->crack_x0));
     const int hi = std::min(cfg->nx - 1, (int)std::floor(cfg->crack_tip));
@@ -577,6 +616,12 @@ int lbm_crack_state(lbm_handle *h, lbm_crack_info *out) {
   out->n_events = c.n_events;
   out->col_K = c.col_K;
   out->n_cut = c.n_cut;
+  out->tip_left = c.tipL;
+  out->v_left = c.vL;
+  out->K_left = c.KL;
+  out->r_left = c.rL;
+  out->flags_left = c.flagsL;
+  out->col_K_left = c.col_KL;
   return LBM_OK;
 }
 
@@ -612,6 +657,21 @@ int lbm_traces(lbm_handle *h, double *tip_out, double *v_out, int32_t *flags_out
   if (flags_out)
     HIP_TRY(hipMemcpyAsync(flags_out, h->base + h->L.off_trF + first * 4, count * 4, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_traces_left(lbm_handle *h, double *K_out, double *tip_out, double *v_out,
+                    int32_t *flags_out, int64_t first, int64_t count) {
+  int rc = check_range(h, first, count);
+  if (rc != LBM_OK) return rc;
+  if (!h->cfg.both_tips) return fail(LBM_ESTATE, "the crack has one tip");
+  if (count == 0) return LBM_OK;
+  const hipStream_t st = h->stream;
+  if (K_out) HIP_TRY(hipMemcpyAsync(K_out, h->base + h->L.off_trKL + first * 8, count * 8, hipMemcpyDeviceToHost, st));
+  if (tip_out) HIP_TRY(hipMemcpyAsync(tip_out, h->base + h->L.off_trAL + first * 8, count * 8, hipMemcpyDeviceToHost, st));
+  if (v_out) HIP_TRY(hipMemcpyAsync(v_out, h->base + h->L.off_trVL + first * 8, count * 8, hipMemcpyDeviceToHost, st));
+  if (flags_out) HIP_TRY(hipMemcpyAsync(flags_out, h->base + h->L.off_trFL + first * 4, count * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return LBM_OK;
 }
 
@@ -882,6 +942,11 @@ struct BatchLayout {
   size_t off_desc = 0, off_tau = 0, off_sync = 0, total = 0;
 };
 
+// offset of a plate's wall-displacement history inside its history block
+size_t wd_offset(const lbm_config &c) {
+  return align_up(sizeof(double) * (size_t)std::max<int64_t>(c.n_hist, 1), 256);
+}
+
 int batch_layout(const lbm_config *cfgs, int32_t n, BatchLayout *B, Store *store) {
   if (!cfgs || n < 1 || n > 65536) return fail(LBM_EINVAL, "a batch needs 1..65536 plates");
   size_t o = 0;
@@ -900,8 +965,9 @@ int batch_layout(const lbm_config *cfgs, int32_t n, BatchLayout *B, Store *store
   o += align_up(sizeof(lbmk::BatchPlate) * n, 256);
   B->off_tau = o;
   for (int k = 0; k < n; ++k) {
-    B->off_tau_plate.push_back(o);
+    B->off_tau_plate.push_back(o);  // traction history, then wall displacements
     o += align_up(sizeof(double) * (size_t)std::max<int64_t>(cfgs[k].n_hist, 1), 256);
+    o += align_up(sizeof(double) * 4 * (size_t)std::max<int64_t>(cfgs[k].dirichlet ? cfgs[k].n_wD : 0, 1), 256);
   }
   B->off_sync = o;
   o += 512;  // grid-barrier words on separate 128-byte lines
@@ -935,6 +1001,9 @@ int batch_build_desc(lbm_batch *b) {
     d.n_hist = (int64_t)h->tau.size();
     d.has_crack = h->cfg.has_crack;
     d.seed = h->cfg.seed;
+    d.dmask = h->cfg.bc_mode == LBM_BC_PERIODIC ? 0 : h->cfg.dirichlet;
+    d.wD = reinterpret_cast<const double *>(b->base + b->off_tau_plate[k] + wd_offset(h->cfg));
+    d.n_wD = (int64_t)h->wD.size() / 4;
     d.skip_lo = h->cfg.has_crack ? h->plate.j0 : 1;
     d.skip_hi = h->cfg.has_crack ? h->plate.j0 + 1 : 0;
     // the same task maps as the single-plate kernels (sweep_core.hpp)
@@ -1037,6 +1106,10 @@ int lbm_batch_init(const lbm_config *cfgs, int32_t n, void *dev_buf, size_t dev_
         hipMemcpy(b->base + B.off_tau_plate[k], h->tau.data(), sizeof(double) * h->tau.size(),
                   hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(LBM_EHIP, "upload of the traction history failed"));
+    if (!h->wD.empty() &&
+        hipMemcpy(b->base + B.off_tau_plate[k] + wd_offset(cfgs[k]), h->wD.data(),
+                  sizeof(double) * h->wD.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(LBM_EHIP, "upload of the wall displacements failed"));
   }
   // launch shape: that of a plate of the batch's storage
   b->rows = 1;
@@ -1261,6 +1334,7 @@ int adjoint_sweep(lbm_adjoint *a, int cur, int64_t m) {
   g.cutstep = reinterpret_cast<const int32_t *>(a->base + a->off_cut);
   g.has_crack = h->cfg.has_crack;
   g.traction = h->cfg.bc_mode != LBM_BC_PERIODIC;
+  g.dmask = h->cfg.bc_mode == LBM_BC_PERIODIC ? 0 : h->cfg.dirichlet;
   g.coef = h->coef;
   g.dtau_part = reinterpret_cast<double *>(a->base + a->off_part) + (size_t)m * 4 * a->n_parts;
   g.n_parts = a->n_parts;

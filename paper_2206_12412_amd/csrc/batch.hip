@@ -60,6 +60,16 @@ __device__ __forceinline__ SweepArgs<S, W, C> args_of(const BatchPlate &d, int c
   a.skip_hi = d.skip_hi;
   a.sr = 0;  // the kernel's SR template argument decides
   a.rkey = step_key(d.seed, step);
+  a.dmask = d.dmask;
+  if (d.dmask) {
+    const double *r = d.wD + 4 * (step < d.n_wD ? step : d.n_wD - 1);
+    a.wD_bot = (C)r[0];
+    a.wD_top = (C)r[1];
+    a.wD_left = (C)r[2];
+    a.wD_right = (C)r[3];
+  } else {
+    a.wD_bot = a.wD_top = a.wD_left = a.wD_right = C(0);
+  }
   return a;
 }
 

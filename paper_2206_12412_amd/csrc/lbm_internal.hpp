@@ -21,6 +21,9 @@ struct DevCrack {
   int32_t n_events;  // cut events recorded
   int32_t col_K;     // column of the last K (-1: undefined)
   int32_t n_cut;     // severed links on the crack row
+  // the left end: a second tip growing in -x when both tips grow
+  double tipL, vL, KL, rL;
+  int32_t flagsL, col_KL;
 };
 
 // Static description of one plate's lattice as the kernels see it.
@@ -36,6 +39,7 @@ struct Plate {
 // Parameters of the crack step.
 struct CrackParams {
   int crack;         // the plate has a crack (else only the sensors are recorded)
+  int both;          // the left end grows as well (two tips)
   int growth;        // LBM_GROW_*
   int band;          // columns in the K fit
   double v_rel, K_C, r0, v_max;
@@ -76,6 +80,8 @@ struct SweepArgs {
   int skip_lo, skip_hi;
   int sr;            // 16-bit storage: stochastic rounding of the stores
   uint32_t rkey;     // per-step key of the rounding bits (step_key)
+  int dmask;         // edges with a prescribed w (LBM_EDGE_* bits)
+  C wD_bot, wD_top, wD_left, wD_right;  // their wall values this step
 };
 
 // Counter-based randomness of the stochastic rounding: the integer hash
@@ -100,6 +106,8 @@ struct CrackArgs {
   MaskRows *mrows;
   double *trK, *trA, *trV;
   int32_t *trF;
+  double *trKL, *trAL, *trVL;  // left-tip traces (two tips)
+  int32_t *trFL;
   int64_t *evStep;
   int32_t *evCol;
   const int32_t *sens;  // sensor sites [n_sens][2] = (i, j)
@@ -123,6 +131,9 @@ struct BatchPlate {
   int64_t n_hist;
   int has_crack, skip_lo, skip_hi;
   uint32_t seed;        // stochastic rounding seed (the batch decides whether it is used)
+  int dmask;            // Dirichlet edges
+  const double *wD;     // device copy of the wall-displacement history [n_wD][4]
+  int64_t n_wD;
   // task maps (same fields as the single-plate maps)
   int n_strips, rows, lo1, hi1, lo2, hi2, nc1, nc2;
   int nb, brow[4];
@@ -148,6 +159,7 @@ struct AdjArgs {
   const int32_t *cutstep;  // per column: step of the cut of the crack-row link (-1 initial)
   int has_crack;
   int traction;          // the edges carry tau (walls): derivative wanted
+  int dmask;             // Dirichlet edges: their anti-bounce-back has sign -1
   double coef;           // traction coefficient dt / (rho dh)
   double *dtau_part;     // partial sums of dL/dtau_m: [4 rows][n_parts]
   int n_parts;           // blocks per boundary row

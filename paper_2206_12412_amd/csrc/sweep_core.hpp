@@ -208,6 +208,16 @@ __device__ __forceinline__ void zero_row(C (&out)[VEC]) {
 
 __device__ __forceinline__ bool in_range(int j, int lo, int hi) { return j >= lo && j <= hi; }
 
+constexpr int kEdgeBottom = 1, kEdgeTop = 2, kEdgeLeft = 4, kEdgeRight = 8;
+
+// 2 f_eq^k(w*, 0) = (2 Ak) w*, the constant of the anti-bounce-back of a
+// Dirichlet edge (stored populations f; shifted storage carries it in w_src)
+template <typename A, typename C>
+__device__ __forceinline__ C dirichlet_term(const A &a, C wstar) {
+#pragma clang fp contract(off)
+  return (C(2) * a.Ak) * wstar;
+}
+
 // One site: wdot, Euler update and collision from the pulled populations.
 // gl, gr, gd, gu are the values pulled along +x, -x, +y, -y (already bounced
 // where the link is severed); for shifted storage wl .. wup are the w of the
@@ -384,20 +394,35 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
           wr[k] = (k == VEC - 1) ? ((lane == 63) ? w_right : wR) : wc[k + 1];
         }
       }
-      // the left edge bounces site 0 (or wraps to nx-1, which the halo holds)
+      // the left edge bounces site 0 (or wraps to nx-1, which the halo holds);
+      // a Dirichlet edge anti-bounces: f_in = -f^opp + 2 Ak w*, i.e. the
+      // ghost site carries 2 w* - w (shifted storage: g = -g^opp, w_src = 2 w* - w)
       if (left_edge && !p.periodic && lane == 0) {
-        gl[0] = f3[0];
-        if (SHIFT) wl[0] = wc[0];
+        const C w0 = SHIFT ? wc[0] : wself[0];
+        if (a.dmask & kEdgeLeft) {
+          gl[0] = SHIFT ? -f3[0] : -f3[0] + dirichlet_term(a, a.wD_left);
+          if (SHIFT) wl[0] = C(2) * a.wD_left - w0;
+        } else {
+          gl[0] = f3[0];
+          if (SHIFT) wl[0] = w0;
+        }
       }
       // the right edge bounces site nx-1 or wraps to site 0
       if (right_edge) {
         const C s_wrap = lane_value(hs, 2);
         const C w_wrap = SHIFT ? lane_value(hw, 2) : C(0);
+        const bool dr = !p.periodic && (a.dmask & kEdgeRight);
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
           if (i0 + k == last) {
-            gr[k] = p.periodic ? s_wrap : f1[k];
-            if (SHIFT) wr[k] = p.periodic ? w_wrap : wc[k];
+            const C w0 = SHIFT ? wc[k] : wself[k];
+            if (dr) {
+              gr[k] = SHIFT ? -f1[k] : -f1[k] + dirichlet_term(a, a.wD_right);
+              if (SHIFT) wr[k] = C(2) * a.wD_right - w0;
+            } else {
+              gr[k] = p.periodic ? s_wrap : f1[k];
+              if (SHIFT) wr[k] = p.periodic ? w_wrap : w0;
+            }
           }
         }
       }
@@ -531,24 +556,39 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
     const int i = i0 + k;
     const C w0 = wc[k];
     // pull along +x (f^1 from i-1)
+    const bool dl = i == 0 && !p.periodic && (a.dmask & kEdgeLeft);
     const bool bl = (i == 0 && !p.periodic) || ((ble >> k) & 1u);
-    const C gl = bl ? f3[k] : ((k == 0) ? f1L : f1[k - 1]);
-    const C wl = (!SHIFT || bl) ? w0 : ((k == 0) ? wL : wc[k - 1]);
+    C gl = bl ? f3[k] : ((k == 0) ? f1L : f1[k - 1]);
+    C wl = (!SHIFT || bl) ? w0 : ((k == 0) ? wL : wc[k - 1]);
+    if (dl) {  // Dirichlet edge: anti-bounce-back (ghost 2 w* - w)
+      gl = SHIFT ? -f3[k] : -f3[k] + dirichlet_term(a, a.wD_left);
+      wl = SHIFT ? C(2) * a.wD_left - w0 : w0;
+    }
     // pull along -x (f^3 from i+1)
+    const bool dr = i == last && !p.periodic && (a.dmask & kEdgeRight);
     const bool br = (i == last && !p.periodic) || ((bri >> k) & 1u);
     const bool wrap = (i == last) && !br;
-    const C gr = br ? f1[k] : (wrap ? s_wrap : ((k == VEC - 1) ? f3R : f3[k + 1]));
-    const C wr = (!SHIFT || br) ? w0 : (wrap ? w_wrap : ((k == VEC - 1) ? wR : wc[k + 1]));
-    // pull along +y (f^2 from j-1)
+    C gr = br ? f1[k] : (wrap ? s_wrap : ((k == VEC - 1) ? f3R : f3[k + 1]));
+    C wr = (!SHIFT || br) ? w0 : (wrap ? w_wrap : ((k == VEC - 1) ? wR : wc[k + 1]));
+    if (dr) {
+      gr = SHIFT ? -f1[k] : -f1[k] + dirichlet_term(a, a.wD_right);
+      wr = SHIFT ? C(2) * a.wD_right - w0 : w0;
+    }
+    // pull along +y (f^2 from j-1); a Dirichlet bottom edge: f_in^2 =
+    // -f^4 + 2 Ak w* (the constant rides in td for stored f, in wdn for g)
+    const bool db = jm < 0 && (a.dmask & kEdgeBottom);
     const bool bd = (jm < 0) || ((bdn >> k) & 1u);
-    const C td = (jm < 0) ? a.t_bot : (bd ? a.t_up : C(0));
-    const C gd = bd ? f4own[k] : f2d[k];
-    const C wdn = (!SHIFT || bd) ? w0 : wm[k];
-    // pull along -y (f^4 from j+1)
+    const C td = db ? (SHIFT ? C(0) : dirichlet_term(a, a.wD_bot))
+                    : ((jm < 0) ? a.t_bot : (bd ? a.t_up : C(0)));
+    const C gd = db ? -f4own[k] : (bd ? f4own[k] : f2d[k]);
+    const C wdn = db ? (SHIFT ? C(2) * a.wD_bot - w0 : w0) : ((!SHIFT || bd) ? w0 : wm[k]);
+    // pull along -y (f^4 from j+1); a Dirichlet top edge likewise
+    const bool dt_ = jp < 0 && (a.dmask & kEdgeTop);
     const bool bu = (jp < 0) || ((bup >> k) & 1u);
-    const C tu = (jp < 0) ? a.t_top : (bu ? a.t_lo : C(0));
-    const C gu = bu ? f2own[k] : f4u[k];
-    const C wup = (!SHIFT || bu) ? w0 : wp[k];
+    const C tu = dt_ ? (SHIFT ? C(0) : dirichlet_term(a, a.wD_top))
+                     : ((jp < 0) ? a.t_top : (bu ? a.t_lo : C(0)));
+    const C gu = dt_ ? -f2own[k] : (bu ? f2own[k] : f4u[k]);
+    const C wup = dt_ ? (SHIFT ? C(2) * a.wD_top - w0 : w0) : ((!SHIFT || bu) ? w0 : wp[k]);
     site_update<C, SHIFT>(a, f0[k], gl, gr, gd, gu, w0, wl, wr, wdn, wup, bd, bu, td, tu, o0[k],
                           o1[k], o2[k], o3[k], o4[k], wo[k]);
     if (i > last) {  // padding past the row end stays zero

@@ -24,6 +24,7 @@ STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S,
 GROW_NONE, GROW_PRESCRIBED, GROW_SIF = 0, 1, 2
 BC_WALLS, BC_PERIODIC = 0, 1
 ROUNDING = {"nearest": 0, "stochastic": 1}
+EDGE_BOTTOM, EDGE_TOP, EDGE_LEFT, EDGE_RIGHT = 1, 2, 4, 8
 FLAG_GREW, FLAG_WALL, FLAG_K_UNDEF = 1, 2, 4
 
 ERRORS = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE",
@@ -39,7 +40,7 @@ EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_si
            "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune", "lbm_round16",
            "lbm_sensor_traces", "lbm_adjoint_bytes", "lbm_adjoint_init", "lbm_adjoint_run",
            "lbm_adjoint_timing", "lbm_adjoint_free", "lbm_checkpoint_bytes", "lbm_checkpoint",
-           "lbm_restore")
+           "lbm_restore", "lbm_traces_left")
 
 
 class LBMError(RuntimeError):
@@ -59,6 +60,8 @@ class _Config(C.Structure):
         ("w0", C.POINTER(C.c_double)), ("wdot0", C.POINTER(C.c_double)),
         ("trace_cap", C.c_int64), ("rounding", C.c_int32), ("seed", C.c_uint32),
         ("n_sensors", C.c_int32), ("sensors", C.POINTER(C.c_int32)),
+        ("crack_row", C.c_int32), ("both_tips", C.c_int32), ("dirichlet", C.c_int32),
+        ("wD_hist", C.POINTER(C.c_double)), ("n_wD", C.c_int64),
         ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t),
         ("stream", C.c_void_p),
     ]
@@ -67,7 +70,9 @@ class _Config(C.Structure):
 class CrackInfo(C.Structure):
     _fields_ = [("tip", C.c_double), ("v", C.c_double), ("K", C.c_double), ("r", C.c_double),
                 ("step", C.c_int64), ("flags", C.c_int32), ("n_events", C.c_int32),
-                ("col_K", C.c_int32), ("n_cut", C.c_int32)]
+                ("col_K", C.c_int32), ("n_cut", C.c_int32),
+                ("tip_left", C.c_double), ("v_left", C.c_double), ("K_left", C.c_double),
+                ("r_left", C.c_double), ("flags_left", C.c_int32), ("col_K_left", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,6 +98,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_crack_state.argtypes = [vp, P(CrackInfo)]
     lib.lbm_sif.argtypes = [vp, P(d), i64, i64]
     lib.lbm_traces.argtypes = [vp, P(d), P(d), P(i32), i64, i64]
+    lib.lbm_traces_left.argtypes = [vp, P(d), P(d), P(d), P(i32), i64, i64]
     lib.lbm_cut_events.argtypes = [vp, P(i64), P(i32), i64, P(i64)]
     lib.lbm_get_fields.argtypes = [vp, P(d), P(d)]
     lib.lbm_get_populations.argtypes = [vp, P(d)]
@@ -134,7 +140,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_adjoint_free.argtypes = [vp]
     lib.lbm_adjoint_free.restype = None
     lib.lbm_batch_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
-    for name in ("lbm_checkpoint", "lbm_restore", "lbm_sensor_traces", "lbm_adjoint_init", "lbm_adjoint_run", "lbm_adjoint_timing",
+    for name in ("lbm_traces_left", "lbm_checkpoint", "lbm_restore", "lbm_sensor_traces", "lbm_adjoint_init", "lbm_adjoint_run", "lbm_adjoint_timing",
                  "lbm_round16", "lbm_autotune", "lbm_batch_autotune", "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
                  "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
         getattr(lib, name).restype = i32
@@ -183,6 +189,10 @@ class Config:
     rounding: str = "nearest"      # 16-bit storages: "nearest" or "stochastic"
     seed: int = 0
     sensors: Optional[np.ndarray] = None   # (n, 2) sites (i, j) whose w is recorded per step
+    crack_row: int = -1                   # crack line y = crack_row + 1/2; -1 = mid-line
+    both_tips: bool = False               # the left end grows in -x as well
+    dirichlet: int = 0                    # EDGE_* bits of the edges holding a prescribed w
+    wD_hist: Optional[np.ndarray] = None  # (n, 4) wall w* of (bottom, top, left, right) per step
 
     def to_c(self, keep: list) -> _Config:
         c = _Config()
@@ -193,6 +203,14 @@ class Config:
         c.bc_mode = BC_PERIODIC if self.periodic else BC_WALLS
         c.has_crack = int(self.has_crack)
         c.rounding = ROUNDING[self.rounding] if isinstance(self.rounding, str) else int(self.rounding)
+        c.crack_row = int(self.crack_row)
+        c.both_tips = int(self.both_tips)
+        c.dirichlet = int(self.dirichlet)
+        if self.wD_hist is not None:
+            wd = np.ascontiguousarray(self.wD_hist, dtype=np.float64).reshape(-1, 4)
+            keep.append(wd)
+            c.wD_hist = _dp(wd)
+            c.n_wD = wd.shape[0]
         c.seed = int(self.seed) & 0xFFFFFFFF
         if self.sensors is not None:
             sens = np.ascontiguousarray(self.sensors, dtype=np.int32).reshape(-1, 2)
@@ -301,16 +319,21 @@ class Solver:
         _check(self._lib.lbm_sif(self._h, _dp(out), int(first), int(count)))
         return out
 
-    def traces(self, first: int = 0, count: Optional[int] = None) -> dict:
+    def traces(self, first: int = 0, count: Optional[int] = None, tip: str = "right") -> dict:
+        """Per-step K, tip position, speed and flags of the right (or, with
+        two tips, the left) tip."""
         if count is None:
             count = min(self.steps_done, self.cfg.trace_cap) - first
-        K, tip, v = np.empty(count), np.empty(count), np.empty(count)
+        K, a, v = np.empty(count), np.empty(count), np.empty(count)
         fl = np.empty(count, np.int32)
-        if count:
+        fp = fl.ctypes.data_as(C.POINTER(C.c_int32))
+        if tip == "left":
+            _check(self._lib.lbm_traces_left(self._h, _dp(K), _dp(a), _dp(v), fp, int(first),
+                                             int(count)))
+        elif count:
             _check(self._lib.lbm_sif(self._h, _dp(K), int(first), int(count)))
-            _check(self._lib.lbm_traces(self._h, _dp(tip), _dp(v),
-                                        fl.ctypes.data_as(C.POINTER(C.c_int32)), int(first), int(count)))
-        return {"K": K, "tip": tip, "v": v, "flags": fl}
+            _check(self._lib.lbm_traces(self._h, _dp(a), _dp(v), fp, int(first), int(count)))
+        return {"K": K, "tip": a, "v": v, "flags": fl}
 
     def sensor_traces(self, first: int = 0, count: Optional[int] = None, device: bool = False):
         """w at the sensor sites after each step, [count][n_sensors] (numpy,

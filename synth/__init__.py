@@ -167,3 +167,24 @@ def adjoint_directions(n_tau: int, shape: tuple, count: int = 16, seed: int = 1)
         nrm = math.sqrt(float(np.dot(dt_, dt_)) + float(np.sum(dw * dw)))
         dirs.append((dt_ / nrm, dw / nrm))
     return dirs
+
+
+def two_tip_demo(steps: int = 4000, L: int = 64) -> dict:
+    """The K-criterion example of Sec. 5.2: a plate 8L wide and 3L high
+    (dh = L/64: 512 x 192 sites), a centre crack of length L on the line 2L
+    above the lower edge (y = 2L - 1/2 in site coordinates, between rows 127
+    and 128) that can grow at both tips, K_C = 0.0055 mu sqrt(L), r0 = 0.03 L,
+    v_max = 0.85; the lower edge held at w = 0, the upper edge displaced by
+    a half sine w = 0.01 L sin(pi t / 8) for t < 8 L / c_s (t in L / c_s), the
+    lateral edges and the crack faces traction-free.  With c_s = 1 and
+    dt = 1/2 a step is 1/128 of L / c_s; step n uses t = n dt."""
+    nx, ny = 8 * L, 3 * L
+    n = np.arange(steps, dtype=np.float64)
+    t = n * 0.5 / L                       # in units of L / c_s
+    wD = np.zeros((steps, 4))
+    wD[:, 1] = np.where(t < 8.0, 0.01 * L * np.sin(np.pi * t / 8.0), 0.0)
+    centre = nx / 2 - 0.5
+    return dict(nx=nx, ny=ny, has_crack=True, crack_row=2 * L - 1, crack_x0=centre - L / 2,
+                crack_tip=centre + L / 2, both_tips=True, growth=GROW_SIF,
+                K_C=0.0055 * np.sqrt(L), r0=0.03 * L, v_max=0.85, dirichlet=1 | 2,
+                wD_hist=wD, trace_cap=steps)

@@ -190,3 +190,22 @@ def test_autograd_function_gives_the_adjoint_gradients():
     r_tau, r_wd0, _ = O.sensor_adjoint(ocfg, sens, 2.0 * (tr_o - target))
     assert rel(tau.grad.numpy(), r_tau) <= 1e-12
     assert rel(wd0.grad.numpy(), r_wd0) <= 1e-12
+
+
+def test_fp64_adjoint_with_dirichlet_edges_and_off_centre_crack():
+    nx, ny, T = 64, 30, 90
+    rng = np.random.default_rng(12)
+    sens = np.unique(np.stack([rng.integers(0, nx, 10), rng.integers(0, ny, 10)], axis=1), axis=0)
+    n = np.arange(T)
+    wD = np.zeros((T, 4))
+    wD[:, 1] = 0.01 * np.sin(np.pi * n / 50.0)
+    wD[:, 3] = -2e-3
+    kw = dict(nx=nx, ny=ny, has_crack=True, crack_row=19, crack_x0=20.5, crack_tip=35.5,
+              tau_hist=1e-3 * (1 + 0.2 * rng.normal(size=T)), dirichlet=1 | 2 | 8, wD_hist=wD,
+              wdot0=1e-4 * rng.normal(size=(ny, nx)), trace_cap=T)
+    target = 1e-3 * rng.normal(size=(T, len(sens)))
+    tr, dtau, dwd0, dw0 = gpu_grads("f64", kw, sens, target)
+    ocfg = O.OracleConfig(**kw)
+    r = O.sensor_adjoint(ocfg, sens, 2.0 * (O.sensor_traces(ocfg, sens, T) - target))
+    assert max(rel(dwd0, r[1]), rel(dw0, r[2])) <= 1e-12
+    assert rel(dtau, r[0]) <= 1e-12  # the traction acts on the (free) left edge only: none

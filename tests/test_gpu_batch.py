@@ -44,6 +44,14 @@ def plate_configs(storage, steps, small=True):
         else:
             c.growth, c.K_C = 2, 1.05 * synth.k_static_edge(tau, ell)
         cfgs.append(c)
+    # a plate with two tips, an off-centre crack row and Dirichlet edges
+    n = np.arange(steps)
+    wD = np.zeros((max(steps, 1), 4))
+    wD[:, 1] = 0.01 * np.sin(np.pi * np.arange(wD.shape[0]) / 60.0)
+    cfgs.append(Config(nx=150, ny=40, storage=storage, rounding=rounding, seed=99, has_crack=True,
+                       crack_row=12, crack_x0=60.5, crack_tip=80.5, both_tips=True, growth=1,
+                       v_rel=0.45, dirichlet=1 | 2, wD_hist=wD, trace_cap=steps,
+                       wdot0=rng.normal(0, 1e-4, (40, 150))))
     # one plate without a crack and one periodic plate
     cfgs.append(Config(nx=70, ny=20, storage=storage, rounding=rounding, tau_hist=np.array([1e-3])))
     cfgs.append(Config(nx=80, ny=24, storage=storage, rounding=rounding, periodic=True,
@@ -61,6 +69,10 @@ def same_state(a, b, label):
         for key in ("K", "tip", "v", "flags"):
             np.testing.assert_array_equal(ta[key], tb[key], err_msg=f"{label} {key}")
         assert a.cut_events().tolist() == b.cut_events().tolist(), label
+        if a.cfg.both_tips:
+            ta, tb = a.traces(tip="left"), b.traces(tip="left")
+            for key in ("K", "tip", "v", "flags"):
+                np.testing.assert_array_equal(ta[key], tb[key], err_msg=f"{label} left {key}")
 
 
 @pytest.mark.parametrize("storage", ["f32", "f64", "f16s", "f16s-sr", "bf16s-sr"])
@@ -125,6 +137,20 @@ def test_batched_plate_matches_the_oracle():
         # the K-criterion speed goes through tanh, whose last bit may differ
         np.testing.assert_allclose(b.plates[k].traces()["tip"], ref.traces()["tip"], rtol=0,
                                    atol=1e-9)
+    # the plate with two tips, its crack on row 12 and Dirichlet edges
+    c = cfgs[6]
+    assert c.both_tips
+    ref = O.Oracle(O.OracleConfig(nx=c.nx, ny=c.ny, has_crack=True, crack_row=c.crack_row,
+                                  crack_x0=c.crack_x0, crack_tip=c.crack_tip, both_tips=True,
+                                  growth=c.growth, v_rel=c.v_rel, dirichlet=c.dirichlet,
+                                  wD_hist=c.wD_hist, wdot0=c.wdot0, trace_cap=steps))
+    ref.step(steps)
+    w_ref = ref.fields()[0]
+    np.testing.assert_allclose(b.plates[6].fields()[0], w_ref, rtol=0,
+                               atol=1e-12 * np.abs(w_ref).max())
+    for tip in ("right", "left"):
+        np.testing.assert_array_equal(b.plates[6].traces(tip=tip)["tip"], ref.traces(tip)["tip"])
+    assert b.plates[6].cut_events().tolist() == ref.events()[:, :2].tolist()
 
 
 def test_plates_of_a_batch_are_not_stepped_alone():

@@ -262,3 +262,63 @@ def test_stochastic_rounding_is_deterministic_per_seed():
     for s in (a, c):
         assert relerr(s.fields()[0], w_r) <= TOL["f16s"]
 
+
+
+# ------------------------------ Dirichlet edges, crack row, two tips (Sec. 5.2) --
+
+def dirichlet_two_tip_kw(nx, ny, steps, row, x0, a0, v=0.4):
+    n = np.arange(steps)
+    wD = np.zeros((steps, 4))
+    wD[:, 1] = 0.02 * np.sin(np.pi * n / 120.0) * (n < 120)   # top: half sine pulse
+    wD[:, 2] = 3e-3                                         # left: constant
+    rng = np.random.default_rng(nx + ny)
+    return dict(nx=nx, ny=ny, has_crack=True, crack_row=row, crack_x0=x0, crack_tip=a0,
+                both_tips=True, growth=O.GROW_PRESCRIBED, v_rel=v, tau_hist=np.array([1e-3]),
+                dirichlet=1 | 2 | 4, wD_hist=wD, wdot0=rng.normal(0, 1e-4, (ny, nx)),
+                trace_cap=steps)
+
+
+@pytest.mark.parametrize("nx,ny,row,x0,a0", [(36, 20, 12, 13.5, 20.5), (300, 90, 60, 120.5, 170.5),
+                                             (513, 34, 5, 200.5, 260.5)])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s-sr"])
+def test_dirichlet_edges_off_centre_crack_two_tips(nx, ny, row, x0, a0, storage):
+    steps = 240
+    kw = dirichlet_two_tip_kw(nx, ny, steps, row, x0, a0)
+    tol = 4 * 2.0 ** -11 * math.sqrt(steps) if storage.startswith("f16s") else None
+    compare_run(storage, kw, steps, [1, 60, steps], tol=tol)
+    ref, gpu = pair(storage, **kw)
+    ref.step(steps)
+    gpu.step(steps)
+    tl_r, tl_g = ref.traces("left"), gpu.traces(tip="left")
+    np.testing.assert_array_equal(tl_g["tip"], tl_r["tip"])
+    np.testing.assert_array_equal(tl_g["flags"], tl_r["flags"])
+    ok = ~np.isnan(tl_r["K"])
+    if ok.any():
+        kerr = np.abs(tl_g["K"][ok] - tl_r["K"][ok]).max() / np.abs(tl_r["K"][ok]).max()
+        assert kerr <= KTOL[storage], kerr
+    info = gpu.crack_state()
+    assert info["tip_left"] == tl_r["tip"][-1] and info["tip"] == ref.traces()["tip"][-1]
+
+
+def test_two_tip_k_criterion_demo_fp64():
+    """The K-criterion example of Sec. 5.2 at its own size (512 x 192, two
+    tips, Dirichlet upper and lower edges, half-sine pulse): FP64 fields,
+    traces of both tips and the cut events equal the oracle's."""
+    import synth
+    d = synth.two_tip_demo(4000)
+    say("two-tip K-criterion demo, FP64, 4000 steps")
+    ref = O.Oracle(O.OracleConfig(**d))
+    gpu = Solver(Config(storage="f64", **d))
+    ref.step(4000)
+    gpu.step(4000)
+    w_r, w_g = ref.fields()[0], gpu.fields()[0]
+    assert relerr(w_g, w_r) <= 1e-12
+    for tip in ("right", "left"):
+        tr, tg = ref.traces(tip), gpu.traces(tip=tip)
+        np.testing.assert_array_equal(tg["flags"], tr["flags"])
+        np.testing.assert_allclose(tg["tip"], tr["tip"], rtol=0, atol=1e-9)
+        ok = ~np.isnan(tr["K"])
+        assert np.abs(tg["K"][ok] - tr["K"][ok]).max() <= 1e-12 * np.abs(tr["K"][ok]).max()
+    ev_r = ref.events()
+    assert gpu.cut_events().tolist() == [[int(e[0]), int(e[1])] for e in ev_r]
+    assert len(ev_r) > 10  # both tips grew
