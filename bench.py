@@ -3,14 +3,18 @@
 A step is one time step of the method: the fused collide-stream sweep over the
 whole plate followed by the crack step (K_III, criterion, tip advance, newly
 severed links).  Default workload: the 16384 x 8192 plate (134M sites) with a
-4096-site edge crack driven at 0.5 c_s, run with populations stored as FP64,
+4096-site edge crack driven at 0.5 c_s, run with the state stored as FP64,
 FP32, FP16 and BF16 (the last three shifted by the static equilibrium, FP32
-arithmetic).  The JSON line reports FP16-storage GLUPS as `value`, next to the
-FP32 GLUPS, the ratio, each storage's K_III and field error against the FP64
+arithmetic), in the five-population layout and in the equilibrium layout
+(rest population and w only; the moving populations are rebuilt from the
+equilibrium of their emitting site, exact at omega = 1).  The JSON line
+reports the headline storage's GLUPS (FP16, equilibrium layout, stochastic
+rounding) as `value`, next to the FP32 GLUPS of the same layout and of the
+five-population layout, each storage's K_III and field error against the FP64
 run of the same steps, the HBM roofline of the sweep kernel and the oracle's
 CPU throughput on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--storage f16s] [--workload precision]
+    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-sr] [--workload precision]
 """
 from __future__ import annotations
 
@@ -31,13 +35,34 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "GLUPS and % of HBM roofline, fp16-storage vs fp32 at stated K_III error"
 
 
+def parse_storage(name: str):
+    """Storage name -> (storage, rounding, layout): a "-sr" suffix selects
+    stochastic rounding of the 16-bit stores, an "-eq" part the equilibrium
+    layout (rest population and w only), e.g. "f16s-eq-sr"."""
+    rounding = "nearest"
+    if name.endswith("-sr"):
+        name, rounding = name[:-3], "stochastic"
+    layout = "full"
+    if name.endswith("-eq"):
+        name, layout = name[:-3], "eq"
+    return name, rounding, layout
+
+
+def sweep_bytes_per_site(name: str) -> float:
+    """Algorithmic bytes of one sweep per site: read and write of the stored
+    populations (five, or one in the equilibrium layout) and of w."""
+    st, _, layout = parse_storage(name)
+    e = {"f64": 8, "f32": 4, "f32plain": 4, "f16s": 2, "bf16s": 2}[st]
+    we = 8 if st == "f64" else 4
+    return 2.0 * ((1 if layout == "eq" else 5) * e + we)
+
+
 def plate_config(p, storage, trace_cap):
-    """Solver config of plate p; a storage name ending in "-sr" selects
-    stochastic rounding of the 16-bit stores."""
+    """Solver config of plate p in the named storage (see parse_storage)."""
     from paper_2206_12412_amd import Config
-    rounding = "stochastic" if storage.endswith("-sr") else "nearest"
-    storage = storage[:-3] if storage.endswith("-sr") else storage
-    return Config(nx=p.nx, ny=p.ny, storage=storage, rounding=rounding, kappa=p.kappa, mu=p.mu, rho=p.rho,
+    storage, rounding, layout = parse_storage(storage)
+    return Config(nx=p.nx, ny=p.ny, storage=storage, rounding=rounding, layout=layout,
+                  kappa=p.kappa, mu=p.mu, rho=p.rho,
                   has_crack=True, crack_x0=p.crack_x0, crack_tip=p.crack_tip, growth=p.growth,
                   v_rel=p.v_rel, K_C=p.K_C, r0=p.r0, v_max=p.v_max,
                   tau_hist=p.traction_history(), wdot0=p.wdot0(), trace_cap=trace_cap)
@@ -246,8 +271,7 @@ def run_batched(args, torch):
         equal_pers += int(np.array_equal(w1, bp.plates[k].fields()[0]))
         s1.close()
         del s1
-    bps = 2.0 * (5 * {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[storage.replace("-sr", "")] +
-                 (8 if storage == "f64" else 4))
+    bps = sweep_bytes_per_site(storage)
     g = lambda ms: sites * steps / (ms * 1e-3) / 1e9  # noqa: E731
     best_ms = min(ms_step, ms_pers)
     achieved = sites * bps / (best_ms / steps * 1e-3) / 1e9
@@ -255,7 +279,7 @@ def run_batched(args, torch):
         "metric": METRIC, "value": round(g(best_ms), 2), "unit": "GLUPS", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": round(best_ms / steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if storage == "f64" else "f32", "data": "synthetic",
+        "dtype": "f64" if parse_storage(storage)[0] == "f64" else "f32", "data": "synthetic",
         "config": {"workload": f"batched-{len(plates)}-plates", "plates": len(plates),
                    "sites": sites, "storage": storage, "parallelism": "single-gpu",
                    "mode": "per-step" if ms_step <= ms_pers else "persistent"},
@@ -421,11 +445,10 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
         out[counter] = {"KiB_per_launch": kib, "copy_KiB": copy, "factor": factor,
                         "bytes_per_launch": kib * 1024.0 * factor, "launches": len(vals)}
         total += kib * 1024.0 * factor
-    e = {"f64": 8, "f32": 4, "f32plain": 4, "f16s": 2, "bf16s": 2}[storage.replace("-sr", "")]
-    we = 8 if storage == "f64" else 4
+    bps = sweep_bytes_per_site(storage)
     sites = p.nx * p.ny
     out["bytes_per_launch"] = total
-    out["algorithmic_bytes_per_launch"] = sites * 2 * (5 * e + we)
+    out["algorithmic_bytes_per_launch"] = sites * bps
     out["traffic_over_algorithmic"] = total / out["algorithmic_bytes_per_launch"]
     base = os.path.join(out_dir, f"sweep_{storage}_{workload}_traffic")
     with open(base + ".json", "w") as fh:
@@ -439,7 +462,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
                  f"| FETCH_SIZE | {f['KiB_per_launch']:.1f} | {f['copy_KiB']:.1f} KiB | {f['factor']:.4f} | {f['bytes_per_launch']:.4e} |\n"
                  f"| WRITE_SIZE | {w['KiB_per_launch']:.1f} | {w['copy_KiB']:.1f} KiB | {w['factor']:.4f} | {w['bytes_per_launch']:.4e} |\n\n"
                  f"Total {total:.4e} B per launch against {out['algorithmic_bytes_per_launch']:.4e} algorithmic "
-                 f"({sites} sites x {2 * (5 * e + we)} B): ratio {out['traffic_over_algorithmic']:.4f}.\n"
+                 f"({sites} sites x {bps:g} B): ratio {out['traffic_over_algorithmic']:.4f}.\n"
                  f"Kernel source sha256[:16] = {out['kernel_source_sha']}.\n")
 
 
@@ -458,9 +481,11 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="single plate: autotune each storage before timing (the library's "
                          "defaults are this search's result for the precision plate)")
-    ap.add_argument("--storage", default="f16s-sr",
-                    help='headline storage; a "-sr" suffix selects stochastic rounding')
-    ap.add_argument("--compare", default="f64,f32,f16s,f16s-sr,bf16s,bf16s-sr",
+    ap.add_argument("--storage", default="f16s-eq-sr",
+                    help='headline storage; "-eq" selects the equilibrium layout, a "-sr" suffix '
+                         'stochastic rounding (e.g. f16s-eq-sr)')
+    ap.add_argument("--compare",
+                    default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -568,18 +593,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage != "f64" else "f64",
+        "dtype": "f32" if parse_storage(args.storage)[0] != "f64" else "f64",
         "data": "synthetic",
         "config": {"workload": p.name, "nx": p.nx, "ny": p.ny, "crack_sites": p.ell,
                    "growth": "prescribed" if p.growth == 1 else "sif", "v_rel": p.v_rel,
-                   "tau": p.tau, "storage": args.storage.replace("-sr", ""),
-                   "rounding": "stochastic" if args.storage.endswith("-sr") else "nearest",
+                   "tau": p.tau, "storage": parse_storage(args.storage)[0],
+                   "rounding": parse_storage(args.storage)[1],
+                   "layout": parse_storage(args.storage)[2],
                    "parallelism": "single-gpu"},
         "storages": per,
         "error_reference": ref_name,
     }
+    # FP16 storage against FP32 storage in the same layout, and against the
+    # five-plane FP32 run
+    same32 = "f32-eq" if parse_storage(args.storage)[2] == "eq" else "f32"
+    if same32 in results and args.storage != same32:
+        line["vs_f32_glups"] = round(head["glups"] / results[same32]["glups"], 3)
+        line["vs_f32_reference"] = same32
     if "f32" in results and args.storage != "f32":
-        line["vs_f32_glups"] = round(head["glups"] / results["f32"]["glups"], 3)
+        line["vs_f32_five_planes_glups"] = round(head["glups"] / results["f32"]["glups"], 3)
     if args.storage != ref_name:
         line["K_III_error"] = {k: v for k, v in per[args.storage].items() if k.startswith("K_err")}
     line["roofline"] = roofline

@@ -82,6 +82,19 @@ enum lbm_rounding { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
  * anti-bounce-back, f_in^alpha = -f^opp + 2 f_eq^alpha(w*, 0) (the ghost site
  * then carries 2 w* - w), as the lower and upper edges of Sec. 5.2. */
 enum lbm_edge { LBM_EDGE_BOTTOM = 1, LBM_EDGE_TOP = 2, LBM_EDGE_LEFT = 4, LBM_EDGE_RIGHT = 8 };
+/* Layout of the state in device memory.  FULL: the five populations and w
+ * (Sec. 3, eq. LBE), each read and written once per step.  EQ: at omega = 1
+ * (tau = dt, Sec. 3) the collision sets every population to its equilibrium,
+ * so each moving population that streams is f_eq^k(w) = Ak w of its emitting
+ * site: the sweep reads and writes only the rest population (shifted: wdot)
+ * and w, and rebuilds the moving ones from the w of the neighbours.  Needs a
+ * shifted storage (LBM_F32, LBM_F16S, LBM_BF16S; LBM_F64 is then kept in the
+ * shifted form too).  Results equal those of FULL in the same storage (the
+ * moving shifted populations are exactly zero), except that FP64 in EQ is
+ * the shifted FP64 arithmetic (within rounding of FULL's FP64).  The moving
+ * planes stay allocated and zero, so the population and checkpoint views are
+ * the same for both layouts. */
+enum lbm_layout { LBM_LAYOUT_FULL = 0, LBM_LAYOUT_EQ = 1 };
 
 typedef struct lbm_config {
   int32_t nx, ny;          /* sites; ny even and >= 2 when there is a crack      */
@@ -116,6 +129,7 @@ typedef struct lbm_config {
   int32_t dirichlet;       /* enum lbm_edge bits: edges holding a prescribed w   */
   const double *wD_hist;   /* host [n_wD][4]: w* of (bottom, top, left, right);  */
   int64_t n_wD;            /* step n uses row min(n, n_wD - 1); copied           */
+  int32_t layout;          /* enum lbm_layout                                    */
   void *dev_buf;           /* device memory, >= lbm_state_bytes(cfg), 256-aligned */
   size_t dev_bytes;
   void *stream;            /* hipStream_t; NULL = the null stream                */
@@ -245,8 +259,9 @@ int lbm_round16(const float *x, void *out, int64_t n, int32_t storage, int32_t r
 int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *rows, int32_t *waves,
                  int32_t *occupancy, double *ms_per_step);
 
-/* Algorithmic bytes moved by one sweep per site (read + write of the five
- * populations and of w), for the storage of the handle. */
+/* Algorithmic bytes moved by one sweep per site (read + write of the stored
+ * populations, five or, in the equilibrium layout, one, and of w), for the
+ * storage and layout of the handle. */
 double lbm_bytes_per_site(const lbm_handle *h);
 
 /* Release the handle (host metadata only; the device block stays the caller's). */

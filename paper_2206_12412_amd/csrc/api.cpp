@@ -55,9 +55,11 @@ struct Layout {
   size_t total = 0;
 };
 
-bool store_of(int32_t s, Store *out) {
+// storage and layout -> storage scheme (FP64 in the equilibrium layout is
+// kept in the shifted form)
+bool store_of(int32_t s, int32_t layout, Store *out) {
   switch (s) {
-    case LBM_F64: *out = Store::F64; return true;
+    case LBM_F64: *out = layout == LBM_LAYOUT_EQ ? Store::F64S : Store::F64; return true;
     case LBM_F32: *out = Store::F32S; return true;
     case LBM_F16S: *out = Store::F16S; return true;
     case LBM_BF16S: *out = Store::BF16S; return true;
@@ -66,9 +68,11 @@ bool store_of(int32_t s, Store *out) {
   }
 }
 
+bool is_fp64(Store s) { return s == Store::F64 || s == Store::F64S; }
+
 size_t elem_size(Store s) {
   switch (s) {
-    case Store::F64: return 8;
+    case Store::F64: case Store::F64S: return 8;
     case Store::F32_PLAIN: case Store::F32S: return 4;
     case Store::F16S: case Store::BF16S: return 2;
   }
@@ -78,7 +82,7 @@ size_t elem_size(Store s) {
 Layout make_layout(const lbm_config &c, Store s) {
   Layout L;
   L.elem = elem_size(s);
-  L.welem = (s == Store::F64) ? 8 : 4;
+  L.welem = is_fp64(s) ? 8 : 4;
   L.pitch = (int)align_up((size_t)c.nx, 64);
   L.mw = (int)align_up(((size_t)c.nx + 31) / 32, 2);
   // planes 256-byte aligned with a 1 KiB skew between consecutive planes
@@ -123,7 +127,11 @@ Layout make_layout(const lbm_config &c, Store s) {
 
 int validate(const lbm_config *c, Store *s) {
   if (!c) return fail(LBM_EINVAL, "null config");
-  if (!store_of(c->storage, s)) return fail(LBM_EINVAL, "unknown storage %d", c->storage);
+  if (c->layout != LBM_LAYOUT_FULL && c->layout != LBM_LAYOUT_EQ)
+    return fail(LBM_EINVAL, "unknown layout %d", c->layout);
+  if (!store_of(c->storage, c->layout, s)) return fail(LBM_EINVAL, "unknown storage %d", c->storage);
+  if (c->layout == LBM_LAYOUT_EQ && *s == Store::F32_PLAIN)
+    return fail(LBM_EINVAL, "the equilibrium layout needs a shifted storage (not F32_PLAIN)");
   if (c->nx < 1 || c->ny < 1 || c->nx > (1 << 24) || c->ny > (1 << 24))
     return fail(LBM_EINVAL, "plate size %d x %d out of range", c->nx, c->ny);
   // in-plane byte offsets are 32-bit: one plane (populations or w) < 4 GiB
@@ -212,6 +220,13 @@ struct lbm_handle {
   int64_t n_timed = 0;
   lbmk::DevCrack host_crack{};
   bool in_batch = false;  // stepped by a batch; lbm_step refuses it
+  // equilibrium layout: the sweep touches plane 0 and w only.  The moving
+  // planes of both buffers hold zeros in every state reached by a step; until
+  // two steps have run since the state was set (init, restore) the five-plane
+  // sweep runs, so that initial moving populations (the part of an FP64 w0
+  // that FP32 cannot hold) are streamed and both buffers are cleared.
+  bool eq = false;
+  int full_steps = 0;
   std::vector<int32_t> sensors;  // host copy of the sensor sites
   std::vector<double> wD;        // host copy of the wall-displacement history [n][4]
 
@@ -312,13 +327,14 @@ int launch_sweep_typed(lbm_handle *h) {
   } else {
     a.wD_bot = a.wD_top = a.wD_left = a.wD_right = C(0);
   }
-  HIP_TRY(lbmk::launch_sweep(h->store, &a, h->stream));
+  HIP_TRY(lbmk::launch_sweep(h->store, h->eq && h->full_steps == 0, &a, h->stream));
   return LBM_OK;
 }
 
 int launch_sweep_any(lbm_handle *h) {
   switch (h->store) {
     case Store::F64: return launch_sweep_typed<double, double, double>(h);
+    case Store::F64S: return launch_sweep_typed<double, double, double>(h);
     case Store::F32_PLAIN: return launch_sweep_typed<float, float, float>(h);
     case Store::F32S: return launch_sweep_typed<float, float, float>(h);
     case Store::F16S: return launch_sweep_typed<_Float16, float, float>(h);
@@ -331,7 +347,7 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
   lbmk::CrackArgs a{};
   a.st = h->crack();
   a.w = h->wbuf(1 - h->cur);  // w after the sweep just enqueued
-  a.w_is_double = h->store == Store::F64;
+  a.w_is_double = is_fp64(h->store);
   a.mV = h->mV();
   a.mrows = h->mrows();
   a.trK = reinterpret_cast<double *>(h->base + h->L.off_trK);
@@ -455,6 +471,9 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   h->cfg = *cfg;
   h->store = s;
   h->L = L;
+  h->eq = cfg->layout == LBM_LAYOUT_EQ;
+  // shifted FP64 holds w0 exactly: its initial moving populations are zero
+  h->full_steps = (h->eq && s != Store::F64S) ? 2 : 0;
   h->stream = static_cast<hipStream_t>(cfg->stream);
   if (cfg->n_hist > 0) h->tau.assign(cfg->tau_hist, cfg->tau_hist + cfg->n_hist);
   h->cfg.tau_hist = nullptr;
@@ -484,16 +503,29 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   p.periodic = cfg->bc_mode == LBM_BC_PERIODIC;
   p.plane = L.plane;
   // default launch shape, the fastest of the autotuner's grid on MI355X for a
-  // 16384 x 8192 plate (much larger than the caches): one row per wave, and a
-  // cap on the resident waves per SIMD -- 1-wave workgroups with at most 2
-  // resident waves per SIMD for 8- and 4-byte storage, 4-wave workgroups with
-  // at most 4 for 16-bit storage.  lbm_autotune searches the same grid for
-  // other plates.
+  // 16384 x 8192 plate (much larger than the caches).  Five planes: one row
+  // per wave, and a cap on the resident waves per SIMD -- 1-wave workgroups
+  // with at most 2 resident waves per SIMD for 8- and 4-byte storage, 4-wave
+  // workgroups with at most 4 for 16-bit storage.  Equilibrium layout (fewer
+  // loads per row, so more rows and waves in flight pay): FP64 4 rows per
+  // wave, 1-wave groups, at most 2 per SIMD; FP32 1 row, 4-wave groups, no
+  // cap; 16-bit 2 rows, 8-wave groups, no cap.  lbm_autotune searches the same
+  // grid for other plates.
   {
     const bool half = (s == Store::F16S || s == Store::BF16S);
-    h->rows = 1;
-    h->waves = half ? 4 : 1;
-    h->occ = half ? 4 : 2;
+    if (!h->eq) {
+      h->rows = 1;
+      h->waves = half ? 4 : 1;
+      h->occ = half ? 4 : 2;
+    } else if (is_fp64(s)) {
+      h->rows = 4;
+      h->waves = 1;
+      h->occ = 2;
+    } else {
+      h->rows = half ? 2 : 1;
+      h->waves = half ? 8 : 4;
+      h->occ = 0;
+    }
   }
 
   {
@@ -598,6 +630,7 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     }
     h->cur = 1 - h->cur;
     h->step++;
+    if (h->full_steps > 0) h->full_steps--;
   }
   return LBM_OK;
 }
@@ -754,7 +787,7 @@ struct CkptHeader {
   uint64_t magic;
   int64_t step;
   uint64_t f_bytes, w_bytes, tail_bytes;
-  int32_t nx, ny, storage, pad;
+  int32_t nx, ny, storage, scheme;  // scheme: the storage scheme (shifted or not)
 };
 constexpr uint64_t kCkptMagic = 0x4c424d434b505431ull;  // "LBMCKPT1"
 
@@ -777,7 +810,8 @@ int lbm_checkpoint(lbm_handle *h, void *dst) {
   if (h->in_batch) return fail(LBM_ESTATE, "plates of a batch are not checkpointed one by one");
   size_t f, w, tail;
   ckpt_sizes(h, &f, &w, &tail);
-  CkptHeader hd{kCkptMagic, h->step, f, w, tail, h->cfg.nx, h->cfg.ny, h->cfg.storage, 0};
+  CkptHeader hd{kCkptMagic, h->step, f, w, tail, h->cfg.nx, h->cfg.ny, h->cfg.storage,
+                (int32_t)h->store};
   char *d = static_cast<char *>(dst);
   HIP_TRY(hipMemcpyAsync(d, &hd, sizeof hd, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(d + 256, h->fbuf(h->cur), f, hipMemcpyDeviceToDevice, h->stream));
@@ -798,7 +832,8 @@ int lbm_restore(lbm_handle *h, const void *src) {
   HIP_TRY(hipMemcpyAsync(&hd, s, sizeof hd, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (hd.magic != kCkptMagic || hd.f_bytes != f || hd.w_bytes != w || hd.tail_bytes != tail ||
-      hd.nx != h->cfg.nx || hd.ny != h->cfg.ny || hd.storage != h->cfg.storage)
+      hd.nx != h->cfg.nx || hd.ny != h->cfg.ny || hd.storage != h->cfg.storage ||
+      hd.scheme != (int32_t)h->store)
     return fail(LBM_EINVAL, "checkpoint does not belong to a plate of this configuration");
   HIP_TRY(hipMemcpyAsync(h->fbuf(h->cur), s + 256, f, hipMemcpyDeviceToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(h->wbuf(h->cur), s + 256 + f, w, hipMemcpyDeviceToDevice, h->stream));
@@ -806,6 +841,7 @@ int lbm_restore(lbm_handle *h, const void *src) {
                          h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->step = hd.step;
+  h->full_steps = (h->eq && h->store != Store::F64S) ? 2 : 0;
   return LBM_OK;
 }
 
@@ -898,8 +934,8 @@ int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *rows, int32_t *wav
 
 double lbm_bytes_per_site(const lbm_handle *h) {
   if (!h) return 0.0;
-  const double e = (double)elem_size(h->store), we = (h->store == Store::F64) ? 8.0 : 4.0;
-  return 2.0 * (5.0 * e + we);
+  const double e = (double)elem_size(h->store), we = is_fp64(h->store) ? 8.0 : 4.0;
+  return 2.0 * ((h->eq ? 1.0 : 5.0) * e + we);
 }
 
 void lbm_free(lbm_handle *h) {
@@ -933,6 +969,8 @@ struct lbm_batch {
   int64_t n_timed = 0;
   int persistent_blocks = 0;
   int sr = 0;  // stochastic rounding (same for every plate)
+  bool eq = false;     // equilibrium layout (same for every plate)
+  int full_steps = 0;  // five-plane steps still to run (see lbm_handle)
 };
 
 namespace {
@@ -958,6 +996,8 @@ int batch_layout(const lbm_config *cfgs, int32_t n, BatchLayout *B, Store *store
     else if (s != *store) return fail(LBM_EINVAL, "plate %d: every plate of a batch needs the same storage", k);
     if (cfgs[k].rounding != cfgs[0].rounding)
       return fail(LBM_EINVAL, "plate %d: every plate of a batch needs the same rounding", k);
+    if (cfgs[k].layout != cfgs[0].layout)
+      return fail(LBM_EINVAL, "plate %d: every plate of a batch needs the same layout", k);
     B->off_plate.push_back(o);
     o += align_up(make_layout(cfgs[k], s).total, 256);
   }
@@ -1079,6 +1119,8 @@ int lbm_batch_init(const lbm_config *cfgs, int32_t n, void *dev_buf, size_t dev_
   lbm_batch *b = new lbm_batch();
   b->store = s;
   b->sr = cfgs[0].rounding == LBM_ROUND_STOCHASTIC;
+  b->eq = cfgs[0].layout == LBM_LAYOUT_EQ;
+  b->full_steps = (b->eq && s != Store::F64S) ? 2 : 0;
   b->stream = static_cast<hipStream_t>(stream);
   b->base = static_cast<char *>(dev_buf);
   b->off_plate = B.off_plate;
@@ -1111,8 +1153,8 @@ int lbm_batch_init(const lbm_config *cfgs, int32_t n, void *dev_buf, size_t dev_
                   sizeof(double) * h->wD.size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(LBM_EHIP, "upload of the wall displacements failed"));
   }
-  // launch shape: that of a plate of the batch's storage
-  b->rows = 1;
+  // launch shape: that of a plate of the batch's storage and layout
+  b->rows = b->plates[0]->rows;
   b->waves = b->plates[0]->waves;
   b->occ = b->plates[0]->occ;
   b->lds_per_cu = b->plates[0]->lds_per_cu;
@@ -1134,8 +1176,9 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
         return fail(LBM_EHIP, "event creation failed");
       HIP_TRY(hipEventRecord(e0, b->stream));
     }
-    HIP_TRY(lbmk::launch_batch_step(b->store, b->sr, d, (int)b->plates.size(), b->n_int, b->n_bnd, b->cur,
-                                    b->step, b->waves, lds, b->stream));
+    HIP_TRY(lbmk::launch_batch_step(b->store, b->sr, b->eq && b->full_steps == 0, d,
+                                    (int)b->plates.size(), b->n_int, b->n_bnd, b->cur, b->step,
+                                    b->waves, lds, b->stream));
     if (b->timing) {
       HIP_TRY(hipEventRecord(e1, b->stream));
       b->ev_used.push_back(e0);
@@ -1143,6 +1186,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     }
     b->cur = 1 - b->cur;
     b->step++;
+    if (b->full_steps > 0) b->full_steps--;
   }
   batch_sync_handles(b);
   return LBM_OK;
@@ -1152,6 +1196,12 @@ int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps) {
   if (!b) return fail(LBM_EINVAL, "null batch");
   if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
   if (nsteps == 0) return LBM_OK;
+  if (b->full_steps > 0) {  // the five-plane steps of a fresh state run one launch each
+    const int64_t k = std::min<int64_t>(nsteps, b->full_steps);
+    const int rc = lbm_batch_step(b, k);
+    if (rc != LBM_OK || k == nsteps) return rc;
+    nsteps -= k;
+  }
   const auto *d = reinterpret_cast<const lbmk::BatchPlate *>(b->base + b->off_desc);
   unsigned *sync = reinterpret_cast<unsigned *>(b->base + b->off_sync);
   HIP_TRY(lbmk::launch_zero(sync, 512, b->stream));
@@ -1162,7 +1212,7 @@ int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps) {
     HIP_TRY(hipEventRecord(e0, b->stream));
   }
   int blocks = 0;
-  hipError_t e = lbmk::launch_batch_persistent(b->store, b->sr, d, (int)b->plates.size(), b->n_int, b->n_bnd,
+  hipError_t e = lbmk::launch_batch_persistent(b->store, b->sr, b->eq, d, (int)b->plates.size(), b->n_int, b->n_bnd,
                                                b->cur, b->step, nsteps, sync, &blocks, b->stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
   b->persistent_blocks = blocks;
@@ -1290,7 +1340,7 @@ struct AdjLayout {
 
 AdjLayout adjoint_layout(const lbm_handle *h) {
   AdjLayout A;
-  A.esize = (h->store == Store::F64) ? 8 : 4;
+  A.esize = is_fp64(h->store) ? 8 : 4;
   const size_t pb = align_up((size_t)h->L.pitch * h->cfg.ny * A.esize, 256) + 1024;
   A.plane = pb / A.esize;
   size_t o = 0;
@@ -1373,7 +1423,7 @@ int lbm_adjoint_init(lbm_handle *h, void *dev_buf, size_t dev_bytes, lbm_adjoint
   if (dev_bytes < A.total) return fail(LBM_ENOMEM, "dev_bytes %zu < required %zu", dev_bytes, A.total);
   lbm_adjoint *a = new lbm_adjoint();
   a->h = h;
-  a->fp64 = h->store == Store::F64;
+  a->fp64 = is_fp64(h->store);
   a->p = h->plate;
   a->p.plane = A.plane;
   a->base = static_cast<char *>(dev_buf);

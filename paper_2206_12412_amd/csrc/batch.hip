@@ -73,7 +73,7 @@ __device__ __forceinline__ SweepArgs<S, W, C> args_of(const BatchPlate &d, int c
   return a;
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
 __device__ __forceinline__ void interior_task(const BatchPlate *__restrict__ d, int n, int64_t task,
                                               int cur, int64_t step) {
   const int k = plate_of(d, n, task, true);
@@ -91,10 +91,10 @@ __device__ __forceinline__ void interior_task(const BatchPlate *__restrict__ d, 
   }
   if (jb > jlast) return;
   const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
-  core::interior_rows<S, W, C, VEC, SHIFT, SR>(a.fin, a.fout, a.win, a.wout, a, strip, jb, jlast);
+  core::interior_rows<S, W, C, VEC, SHIFT, SR, EQ>(a.fin, a.fout, a.win, a.wout, a, strip, jb, jlast);
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
 __device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, int n, int64_t task,
                                               int cur, int64_t step) {
   const int k = plate_of(d, n, task, false);
@@ -104,7 +104,7 @@ __device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, 
   const int r = (int)(local / q.n_strips);
   const int j = q.brow[r];
   const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
-  core::boundary_row<S, W, C, VEC, SHIFT, SR>(a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a,
+  core::boundary_row<S, W, C, VEC, SHIFT, SR, EQ>(a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a,
                                          strip, j);
 }
 
@@ -117,19 +117,19 @@ __device__ __forceinline__ void crack_task(const BatchPlate *__restrict__ d, int
 
 // One launch per step for the sweep of every plate: the first `nbb`
 // workgroups take the boundary tasks, the rest the interior tasks.
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
 __global__ void __launch_bounds__(512)
 batch_step(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t n_bnd, unsigned nbb,
            int cur, int64_t step, int waves) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (blockIdx.x < nbb) {
     const int64_t task = (int64_t)blockIdx.x * waves + wave;
-    if (task < n_bnd) boundary_task<S, W, C, VEC, SHIFT, SR>(d, n, task, cur, step);
+    if (task < n_bnd) boundary_task<S, W, C, VEC, SHIFT, SR, EQ>(d, n, task, cur, step);
     return;
   }
   const int64_t task = (int64_t)(blockIdx.x - nbb) * waves + wave;
   if (task >= n_int) return;
-  interior_task<S, W, C, VEC, SHIFT, SR>(d, n, task, cur, step);
+  interior_task<S, W, C, VEC, SHIFT, SR, EQ>(d, n, task, cur, step);
 }
 
 __global__ void __launch_bounds__(256) batch_crack(const BatchPlate *__restrict__ d, int n, int cur) {
@@ -178,7 +178,7 @@ __device__ __forceinline__ void grid_barrier(unsigned *sync, unsigned nblocks) {
 // Workgroups of the persistent kernel: WPB waves each, one workgroup per CU,
 // because every grid barrier costs one agent-scope release / acquire (L2
 // write-back and invalidation across the XCDs) per workgroup.
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, int WPB>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ, int WPB>
 __global__ void __launch_bounds__(64 * WPB)
 batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t n_bnd, int cur0,
                  int64_t step0, int64_t nsteps, unsigned *sync) {
@@ -189,8 +189,8 @@ batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t
     const int cur = (int)((cur0 + s) & 1);
     const int64_t step = step0 + s;
     for (int64_t t = gw; t < n_int + n_bnd; t += nw) {
-      if (t < n_int) interior_task<S, W, C, VEC, SHIFT, SR>(d, n, t, cur, step);
-      else boundary_task<S, W, C, VEC, SHIFT, SR>(d, n, t - n_int, cur, step);
+      if (t < n_int) interior_task<S, W, C, VEC, SHIFT, SR, EQ>(d, n, t, cur, step);
+      else boundary_task<S, W, C, VEC, SHIFT, SR, EQ>(d, n, t - n_int, cur, step);
     }
     grid_barrier(sync, gridDim.x);
     for (int64_t k = gw; k < n; k += nw) crack_task(d, (int)k, cur);
@@ -198,23 +198,23 @@ batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t
   }
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
 hipError_t step_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur, int64_t step,
                   int waves, int lds, hipStream_t st) {
   const unsigned nbb = (unsigned)((n_bnd + waves - 1) / waves);
   const unsigned nib = (unsigned)((n_int + waves - 1) / waves);
   if (nbb + nib > 0)
-    hipLaunchKernelGGL((batch_step<S, W, C, VEC, SHIFT, SR>), dim3(nbb + nib), dim3(64 * waves), lds,
+    hipLaunchKernelGGL((batch_step<S, W, C, VEC, SHIFT, SR, EQ>), dim3(nbb + nib), dim3(64 * waves), lds,
                        st, d, n, n_int, n_bnd, nbb, cur, step, waves);
   hipLaunchKernelGGL(batch_crack, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, d, n, cur);
   return hipGetLastError();
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, int WPB>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ, int WPB>
 hipError_t persistent_w(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
                         int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
                         hipStream_t st) {
-  auto kernel = batch_persistent<S, W, C, VEC, SHIFT, SR, WPB>;
+  auto kernel = batch_persistent<S, W, C, VEC, SHIFT, SR, EQ, WPB>;
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -234,65 +234,95 @@ hipError_t persistent_w(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd
                                     dim3(64 * WPB), args, 0, st);
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
 hipError_t persistent_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
                         int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
                         hipStream_t st) {
   // one workgroup of 4 waves per CU: measured on MI355X against 1 to 16 waves
   // and 1 to 4 workgroups per CU (more waves contend, more workgroups pay
   // for more barrier releases / acquires)
-  return persistent_w<S, W, C, VEC, SHIFT, SR, 4>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
-                                                  blocks_used, st);
+  return persistent_w<S, W, C, VEC, SHIFT, SR, EQ, 4>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
+                                                      blocks_used, st);
 }
 
-// stochastic rounding exists for the 16-bit storages only
-template <typename S, typename W, typename C, int VEC, bool SHIFT>
-hipError_t step_r(int sr, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
+// stochastic rounding exists for the 16-bit storages only, the equilibrium
+// layout (eq) for the shifted storages only
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool EQ>
+hipError_t step_e(int sr, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
                   int64_t step, int waves, int lds, hipStream_t st) {
   if constexpr (sizeof(S) == 2) {
-    if (sr) return step_t<S, W, C, VEC, SHIFT, true>(d, n, n_int, n_bnd, cur, step, waves, lds, st);
+    if (sr) return step_t<S, W, C, VEC, SHIFT, true, EQ>(d, n, n_int, n_bnd, cur, step, waves, lds, st);
   }
-  return step_t<S, W, C, VEC, SHIFT, false>(d, n, n_int, n_bnd, cur, step, waves, lds, st);
+  return step_t<S, W, C, VEC, SHIFT, false, EQ>(d, n, n_int, n_bnd, cur, step, waves, lds, st);
 }
 
 template <typename S, typename W, typename C, int VEC, bool SHIFT>
-hipError_t persistent_r(int sr, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
+hipError_t step_r(int sr, bool eq, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd,
+                  int cur, int64_t step, int waves, int lds, hipStream_t st) {
+  if constexpr (SHIFT) {
+    if (eq) return step_e<S, W, C, VEC, SHIFT, true>(sr, d, n, n_int, n_bnd, cur, step, waves, lds, st);
+  } else {
+    if (eq) return hipErrorInvalidValue;
+  }
+  return step_e<S, W, C, VEC, SHIFT, false>(sr, d, n, n_int, n_bnd, cur, step, waves, lds, st);
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool EQ>
+hipError_t persistent_e(int sr, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
                         int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
                         hipStream_t st) {
   if constexpr (sizeof(S) == 2) {
     if (sr)
-      return persistent_t<S, W, C, VEC, SHIFT, true>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
-                                                     blocks_used, st);
+      return persistent_t<S, W, C, VEC, SHIFT, true, EQ>(d, n, n_int, n_bnd, cur, step, nsteps,
+                                                         sync, blocks_used, st);
   }
-  return persistent_t<S, W, C, VEC, SHIFT, false>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
+  return persistent_t<S, W, C, VEC, SHIFT, false, EQ>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
+                                                      blocks_used, st);
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT>
+hipError_t persistent_r(int sr, bool eq, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd,
+                        int cur, int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
+                        hipStream_t st) {
+  if constexpr (SHIFT) {
+    if (eq)
+      return persistent_e<S, W, C, VEC, SHIFT, true>(sr, d, n, n_int, n_bnd, cur, step, nsteps,
+                                                     sync, blocks_used, st);
+  } else {
+    if (eq) return hipErrorInvalidValue;
+  }
+  return persistent_e<S, W, C, VEC, SHIFT, false>(sr, d, n, n_int, n_bnd, cur, step, nsteps, sync,
                                                   blocks_used, st);
 }
 
 }  // namespace
 
-hipError_t launch_batch_step(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+hipError_t launch_batch_step(Store s, int sr, bool eq, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                              int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
                              hipStream_t st) {
   switch (s) {
-    case Store::F64: return step_r<double, double, double, 2, false>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F32_PLAIN: return step_r<float, float, float, 4, false>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F32S: return step_r<float, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F16S: return step_r<_Float16, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::BF16S: return step_r<__bf16, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    // shifted FP64 exists only in the equilibrium layout
+    case Store::F64S: return eq ? step_e<double, double, double, 2, true, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st) : hipErrorInvalidValue;
+    case Store::F64: return step_r<double, double, double, 2, false>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F32_PLAIN: return step_r<float, float, float, 4, false>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F32S: return step_r<float, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F16S: return step_r<_Float16, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::BF16S: return step_r<__bf16, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_persistent(Store s, int sr, const BatchPlate *d, int n_plates,
+hipError_t launch_batch_persistent(Store s, int sr, bool eq, const BatchPlate *d, int n_plates,
                                    int64_t n_int_tasks, int64_t n_bnd_tasks, int cur, int64_t step,
                                    int64_t nsteps, unsigned *sync, int *blocks_used,
                                    hipStream_t st) {
   switch (s) {
-    case Store::F64: return persistent_r<double, double, double, 2, false>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
-    case Store::F32_PLAIN: return persistent_r<float, float, float, 4, false>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
-    case Store::F32S: return persistent_r<float, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
-    case Store::F16S: return persistent_r<_Float16, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
-    case Store::BF16S: return persistent_r<__bf16, float, float, 4, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F64S: return eq ? persistent_e<double, double, double, 2, true, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st) : hipErrorInvalidValue;
+    case Store::F64: return persistent_r<double, double, double, 2, false>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F32_PLAIN: return persistent_r<float, float, float, 4, false>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F32S: return persistent_r<float, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::F16S: return persistent_r<_Float16, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
+    case Store::BF16S: return persistent_r<__bf16, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, nsteps, sync, blocks_used, st);
   }
   return hipErrorInvalidValue;
 }

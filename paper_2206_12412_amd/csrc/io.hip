@@ -124,6 +124,7 @@ hipError_t launch_init_rows(Store s, void *f, void *w, void *w2, const Plate &p,
                             hipStream_t st) {
   switch (s) {
     case Store::F64: return init_t<double, double, false>(f, w, w2, p, row0, nrows, w0, wd0, A0, Ak, st);
+    case Store::F64S: return init_t<double, double, true>(f, w, w2, p, row0, nrows, w0, wd0, A0, Ak, st);
     case Store::F32_PLAIN: return init_t<float, float, false>(f, w, w2, p, row0, nrows, w0, wd0, A0, Ak, st);
     case Store::F32S: return init_t<float, float, true>(f, w, w2, p, row0, nrows, w0, wd0, A0, Ak, st);
     case Store::F16S: return init_t<_Float16, float, true>(f, w, w2, p, row0, nrows, w0, wd0, A0, Ak, st);
@@ -137,6 +138,7 @@ hipError_t launch_export_rows(Store s, const void *f, const void *w, const Plate
                               double *f_out, hipStream_t st) {
   switch (s) {
     case Store::F64: return export_t<double, double, false>(f, w, p, row0, nrows, A0, Ak, w_out, wd_out, f_out, st);
+    case Store::F64S: return export_t<double, double, true>(f, w, p, row0, nrows, A0, Ak, w_out, wd_out, f_out, st);
     case Store::F32_PLAIN: return export_t<float, float, false>(f, w, p, row0, nrows, A0, Ak, w_out, wd_out, f_out, st);
     case Store::F32S: return export_t<float, float, true>(f, w, p, row0, nrows, A0, Ak, w_out, wd_out, f_out, st);
     case Store::F16S: return export_t<_Float16, float, true>(f, w, p, row0, nrows, A0, Ak, w_out, wd_out, f_out, st);

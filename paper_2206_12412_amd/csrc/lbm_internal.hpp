@@ -184,11 +184,13 @@ hipError_t launch_adjoint_export(bool fp64, const void *plane, const Plate &p, d
 int adjoint_parts(int nx);
 
 // ---- launchers (sweep.hip) ----
-enum class Store { F64, F32_PLAIN, F32S, F16S, BF16S };
+// F64S: FP64 in the shifted form (the equilibrium layout of FP64)
+enum class Store { F64, F64S, F32_PLAIN, F32S, F16S, BF16S };
 
 int sweep_vec(Store s);  // sites per lane
-// one sweep step (interior strips and boundary rows in one launch)
-hipError_t launch_sweep(Store s, const void *args, hipStream_t st);
+// one sweep step (interior strips and boundary rows in one launch); eq: the
+// equilibrium layout (plane 0 and w only; shifted storages)
+hipError_t launch_sweep(Store s, bool eq, const void *args, hipStream_t st);
 // the 16-bit store conversion of the sweep applied to x[0..n) (F16S / BF16S)
 hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n, int plane,
                           uint32_t rkey, hipStream_t st);
@@ -201,14 +203,14 @@ hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const P
 // ---- launchers (batch.hip) ----
 // One step of every plate: batched sweep kernel (boundary and interior tasks),
 // batched crack kernel.  cur = parity of the source buffers, step = step index.
-hipError_t launch_batch_step(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+hipError_t launch_batch_step(Store s, int sr, bool eq, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                              int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
                              hipStream_t st);
 // nsteps steps in one cooperative launch with grid barriers; sync is a
 // zeroed 512-byte device scratch (barrier counter, generation and time-out
 // flag at words 0, 32 and 64).  Returns hipErrorCooperativeLaunchTooLarge if
 // the grid cannot be co-resident.
-hipError_t launch_batch_persistent(Store s, int sr, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
+hipError_t launch_batch_persistent(Store s, int sr, bool eq, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
                                    int64_t n_bnd_tasks, int cur, int64_t step, int64_t nsteps,
                                    unsigned *sync, int *blocks_used, hipStream_t st);
 

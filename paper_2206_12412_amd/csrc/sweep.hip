@@ -13,7 +13,7 @@ namespace {
 // launch saves the dispatch gap of a second kernel (measured 0.5 % of a step
 // on 134M sites, 10 % on 2M sites).  The kernel's register count is the
 // larger of the two parts'; the occupancy cap (reserved LDS) binds first.
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
 __global__ void __launch_bounds__(512)
 sweep_step(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict__ win,
            W *__restrict__ wout, const uint32_t *__restrict__ mV, const uint32_t *__restrict__ mH,
@@ -23,7 +23,7 @@ sweep_step(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict_
   if (blockIdx.x < nbb) {
     const int task = blockIdx.x * a.waves + wave;
     if (task >= bm.n_strips * bm.nb) return;
-    core::boundary_row<S, W, C, VEC, SHIFT, SR>(fin, fout, win, wout, mV, mH, mrows, a,
+    core::boundary_row<S, W, C, VEC, SHIFT, SR, EQ>(fin, fout, win, wout, mV, mH, mrows, a,
                                                 task % bm.n_strips, bm.brow[task / bm.n_strips]);
     return;
   }
@@ -39,10 +39,10 @@ sweep_step(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict_
     jlast = min(jb + m.rows - 1, m.hi2);
   }
   if (jb > jlast) return;  // the tail of the last workgroup
-  core::interior_rows<S, W, C, VEC, SHIFT, SR>(fin, fout, win, wout, a, strip, jb, jlast);
+  core::interior_rows<S, W, C, VEC, SHIFT, SR, EQ>(fin, fout, win, wout, a, strip, jb, jlast);
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
 hipError_t launch_t(const SweepArgs<S, W, C> &a, hipStream_t st) {
   const core::InteriorMap m = core::interior_map(a.p.nx, a.p.ny, VEC, a.rows, a.skip_lo, a.skip_hi);
   const core::BoundaryMap bm = core::boundary_map(a.p.nx, a.p.ny, VEC, a.skip_lo, a.skip_hi);
@@ -51,20 +51,31 @@ hipError_t launch_t(const SweepArgs<S, W, C> &a, hipStream_t st) {
   const unsigned nbb = (unsigned)((btasks + a.waves - 1) / a.waves);
   const unsigned nib = (unsigned)((itasks + a.waves - 1) / a.waves);
   if (nbb + nib > 0)
-    hipLaunchKernelGGL((sweep_step<S, W, C, VEC, SHIFT, SR>), dim3(nbb + nib), dim3(64 * a.waves),
+    hipLaunchKernelGGL((sweep_step<S, W, C, VEC, SHIFT, SR, EQ>), dim3(nbb + nib), dim3(64 * a.waves),
                        a.lds_bytes, st, a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a, m, bm,
                        nbb);
   return hipGetLastError();
 }
 
-// stochastic rounding exists for the 16-bit storages only
+// stochastic rounding exists for the 16-bit storages only, the equilibrium
+// layout for the shifted ones only
 template <typename S, typename W, typename C, int VEC, bool SHIFT>
-hipError_t launch_r(const void *args, hipStream_t st) {
+hipError_t launch_r(const void *args, bool eq, hipStream_t st) {
   const auto &a = *static_cast<const SweepArgs<S, W, C> *>(args);
-  if constexpr (sizeof(S) == 2) {
-    if (a.sr) return launch_t<S, W, C, VEC, SHIFT, true>(a, st);
+  if constexpr (SHIFT) {
+    if (eq) {
+      if constexpr (sizeof(S) == 2) {
+        if (a.sr) return launch_t<S, W, C, VEC, SHIFT, true, true>(a, st);
+      }
+      return launch_t<S, W, C, VEC, SHIFT, false, true>(a, st);
+    }
+  } else {
+    if (eq) return hipErrorInvalidValue;
   }
-  return launch_t<S, W, C, VEC, SHIFT, false>(a, st);
+  if constexpr (sizeof(S) == 2) {
+    if (a.sr) return launch_t<S, W, C, VEC, SHIFT, true, false>(a, st);
+  }
+  return launch_t<S, W, C, VEC, SHIFT, false, false>(a, st);
 }
 
 // The store conversion of the sweep applied to an array: element i is the
@@ -103,6 +114,7 @@ hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n,
 int sweep_vec(Store s) {
   switch (s) {
     case Store::F64: return 2;
+    case Store::F64S: return 2;
     case Store::F32_PLAIN: return 4;
     case Store::F32S: return 4;
     case Store::F16S: return 4;
@@ -111,13 +123,18 @@ int sweep_vec(Store s) {
   return 0;
 }
 
-hipError_t launch_sweep(Store s, const void *args, hipStream_t st) {
+hipError_t launch_sweep(Store s, bool eq, const void *args, hipStream_t st) {
   switch (s) {
-    case Store::F64: return launch_r<double, double, double, 2, false>(args, st);
-    case Store::F32_PLAIN: return launch_r<float, float, float, 4, false>(args, st);
-    case Store::F32S: return launch_r<float, float, float, 4, true>(args, st);
-    case Store::F16S: return launch_r<_Float16, float, float, 4, true>(args, st);
-    case Store::BF16S: return launch_r<__bf16, float, float, 4, true>(args, st);
+    case Store::F64: return launch_r<double, double, double, 2, false>(args, eq, st);
+    // shifted FP64 exists only in the equilibrium layout
+    case Store::F64S:
+      return eq ? launch_t<double, double, double, 2, true, false, true>(
+                      *static_cast<const SweepArgs<double, double, double> *>(args), st)
+                : hipErrorInvalidValue;
+    case Store::F32_PLAIN: return launch_r<float, float, float, 4, false>(args, eq, st);
+    case Store::F32S: return launch_r<float, float, float, 4, true>(args, eq, st);
+    case Store::F16S: return launch_r<_Float16, float, float, 4, true>(args, eq, st);
+    case Store::BF16S: return launch_r<__bf16, float, float, 4, true>(args, eq, st);
   }
   return hipErrorInvalidValue;
 }

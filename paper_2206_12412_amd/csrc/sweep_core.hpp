@@ -23,6 +23,14 @@
 // Interior rows (every vertical link intact) and boundary rows (plate edges,
 // crack rows) are separate work items with separate code, so the interior
 // code carries no bounce-back logic and few registers.
+//
+// EQ (equilibrium layout, shifted storage only): at omega = dt / tau = 1 (the
+// paper's tau = dt, the only stable choice) the collision returns every
+// population to its equilibrium, so the shifted moving populations g^1..g^4 =
+// f^k - Ak w_emit of every reachable state are exactly zero and each pulled
+// population is rebuilt from the w of its emitting site.  The sweep then reads
+// and writes plane 0 and w only (the moving planes keep their zeros); the
+// arithmetic is the same with the g^k terms dropped.
 #pragma once
 
 #include <algorithm>
@@ -168,13 +176,23 @@ __device__ __forceinline__ void sr_draws(uint32_t site, uint32_t rkey, uint32_t 
 }
 
 // The five population rows of a lane's sites (site0 = plate-local index of
-// the lane's first site).
-template <typename S, typename C, int VEC, bool SR>
+// the lane's first site); in the equilibrium layout plane 0 only, with the
+// same rounding draw as plane 0 of the five-plane store.
+template <typename S, typename C, int VEC, bool SR, bool EQ = false>
 __device__ __forceinline__ void store_pops(S *__restrict__ fout, size_t P, uint32_t o,
                                            const C (&o0)[VEC], const C (&o1)[VEC],
                                            const C (&o2)[VEC], const C (&o3)[VEC],
                                            const C (&o4)[VEC], uint32_t site0, uint32_t rkey) {
-  if constexpr (SR) {
+  if constexpr (EQ) {
+    if constexpr (SR) {
+      uint32_t r0[VEC];
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) r0[k] = mix32((site0 + k) ^ rkey) & 0xfffu;
+      store_row_sr<S, C, VEC>(fout, o, o0, r0);
+    } else {
+      store_row<S, C, VEC>(fout, o, o0);
+    }
+  } else if constexpr (SR) {
     uint32_t r0[VEC], r1[VEC], r2[VEC], r3[VEC], r4[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
@@ -230,11 +248,21 @@ __device__ __forceinline__ C dirichlet_term(const A &a, C wstar) {
 // g = f - E(w_emit), E the static equilibrium (E^0 = -A0 w, E^k = Ak w) of
 // the emitting site; wdot and the collision are the same arithmetic regrouped
 // in these variables so that no large term cancels in FP32 (A0 = 4 Ak).
-template <typename C, bool SHIFT, typename A>
+template <typename C, bool SHIFT, bool EQ = false, typename A>
 __device__ __forceinline__ void site_update(const A &a, C f0, C gl, C gr, C gd, C gu, C w0, C wl,
                                             C wr, C wdn, C wup, bool bd, bool bu, C td, C tu,
                                             C &o0, C &o1, C &o2, C &o3, C &o4, C &wo) {
-  if constexpr (SHIFT) {
+  static_assert(SHIFT || !EQ, "the equilibrium layout is a shifted layout");
+  if constexpr (EQ) {
+    // g^1..g^4 = 0: the five-plane expression below without them
+#pragma clang fp contract(fast)
+    const C wd = f0 + a.Ak * (((wl - w0) + (wr - w0)) + ((wdn - w0) + (wup - w0))) + (td + tu);
+    const C wn = w0 + a.dt * wd;
+    const C om1 = C(1) - a.omega;
+    o0 = om1 * (f0 + a.A0 * (wn - w0)) + a.omega * wd;
+    o1 = o2 = o3 = o4 = C(0);
+    wo = wn;
+  } else if constexpr (SHIFT) {
 #pragma clang fp contract(fast)
     const C wd = f0 + ((gl + gr) + (gd + gu)) +
                  a.Ak * (((wl - w0) + (wr - w0)) + ((wdn - w0) + (wup - w0))) + (td + tu);
@@ -324,7 +352,7 @@ __host__ __device__ inline long boundary_task_count(const BoundaryMap &m) {
 // Rows jb .. jlast of one strip, all of them interior rows (every vertical
 // link intact); the left and right plate edges (or the periodic wrap) and the
 // ragged end of the last strip are per-lane fix-ups.
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR = false>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR = false, bool EQ = false>
 __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__restrict__ fout,
                                               const W *__restrict__ win, W *__restrict__ wout,
                                               const SweepArgs<S, W, C> &a, const int strip,
@@ -362,27 +390,40 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
     const uint32_t o = (uint32_t)j * pitch + il;
     C f0[VEC], f1[VEC], f3[VEC], f2d[VEC], f4u[VEC], wp[VEC], wself[VEC];
     load_row<S, C, VEC>(F0, o, f0);
-    load_row<S, C, VEC>(F1, o, f1);
-    load_row<S, C, VEC>(F3, o, f3);
-    load_row<S, C, VEC>(F2, o - pitch, f2d);
-    load_row<S, C, VEC>(F4, o + pitch, f4u);
+    if constexpr (EQ) {  // the moving planes hold zeros: not read
+      zero_row(f1);
+      zero_row(f3);
+      zero_row(f2d);
+      zero_row(f4u);
+    } else {
+      load_row<S, C, VEC>(F1, o, f1);
+      load_row<S, C, VEC>(F3, o, f3);
+      load_row<S, C, VEC>(F2, o - pitch, f2d);
+      load_row<S, C, VEC>(F4, o + pitch, f4u);
+    }
     if (SHIFT) load_row<W, C, VEC>(win, o + pitch, wp);
     else load_row<W, C, VEC>(win, o, wself);
     const uint32_t ho = (uint32_t)j * pitch + hx;
-    const C hs = to_c(*at(Fh, ho));
+    C hs = C(0);
+    if constexpr (!EQ) hs = to_c(*at(Fh, ho));
     C hw = C(0);
     if (SHIFT) hw = to_c(*at(win, ho));
 
     // pulled x-neighbours of every site: gl[k] along +x, gr[k] along -x
     C gl[VEC], gr[VEC], wl[VEC], wr[VEC];
     {
-      const C f1L = lane_prev(f1[VEC - 1]);
-      const C f3R = lane_next(f3[0]);
-      const C s_left = lane_value(hs, 0), s_right = lane_value(hs, 1);
+      if constexpr (EQ) {
+        zero_row(gl);
+        zero_row(gr);
+      } else {
+        const C f1L = lane_prev(f1[VEC - 1]);
+        const C f3R = lane_next(f3[0]);
+        const C s_left = lane_value(hs, 0), s_right = lane_value(hs, 1);
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        gl[k] = (k == 0) ? ((lane == 0) ? s_left : f1L) : f1[k - 1];
-        gr[k] = (k == VEC - 1) ? ((lane == 63) ? s_right : f3R) : f3[k + 1];
+        for (int k = 0; k < VEC; ++k) {
+          gl[k] = (k == 0) ? ((lane == 0) ? s_left : f1L) : f1[k - 1];
+          gr[k] = (k == VEC - 1) ? ((lane == 63) ? s_right : f3R) : f3[k + 1];
+        }
       }
       if (SHIFT) {
         const C wL = lane_prev(wc[VEC - 1]);
@@ -409,7 +450,7 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
       }
       // the right edge bounces site nx-1 or wraps to site 0
       if (right_edge) {
-        const C s_wrap = lane_value(hs, 2);
+        const C s_wrap = EQ ? C(0) : lane_value(hs, 2);
         const C w_wrap = SHIFT ? lane_value(hw, 2) : C(0);
         const bool dr = !p.periodic && (a.dmask & kEdgeRight);
 #pragma unroll
@@ -434,7 +475,7 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
       const C w0 = SHIFT ? wc[k] : wself[k];
       const C wdn = SHIFT ? wm[k] : w0;
       const C wup = SHIFT ? wp[k] : w0;
-      site_update<C, SHIFT>(a, f0[k], gl[k], gr[k], f2d[k], f4u[k], w0, SHIFT ? wl[k] : w0,
+      site_update<C, SHIFT, EQ>(a, f0[k], gl[k], gr[k], f2d[k], f4u[k], w0, SHIFT ? wl[k] : w0,
                             SHIFT ? wr[k] : w0, wdn, wup, false, false, C(0), C(0), o0[k], o1[k],
                             o2[k], o3[k], o4[k], wo[k]);
     }
@@ -444,7 +485,7 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
         if (i0 + k > last) o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
     }
     if (act) {
-      store_pops<S, C, VEC, SR>(fout, P, o, o0, o1, o2, o3, o4, (uint32_t)j * p.nx + i0, a.rkey);
+      store_pops<S, C, VEC, SR, EQ>(fout, P, o, o0, o1, o2, o3, o4, (uint32_t)j * p.nx + i0, a.rkey);
       store_row<W, C, VEC>(wout, o, wo);
     }
     if (SHIFT) {
@@ -461,7 +502,7 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
 // Row j of one strip with the full boundary treatment: bounce-back at the
 // plate edges and on severed links (read from the cut bitmask in the rows the
 // mask-row range names), traction terms, periodic wrap-around.
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR = false>
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR = false, bool EQ = false>
 __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__restrict__ fout,
                                              const W *__restrict__ win, W *__restrict__ wout,
                                              const uint32_t *__restrict__ mV,
@@ -487,12 +528,16 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
 
   C f0[VEC], f1[VEC], f3[VEC], f2d[VEC], f4u[VEC], f2own[VEC], f4own[VEC];
   C wc[VEC], wm[VEC], wp[VEC];
+  // (equilibrium layout: the moving planes hold zeros and are not read)
   load_row<S, C, VEC>(fin, o, f0);
-  load_row<S, C, VEC>(fin + P, o, f1);
-  load_row<S, C, VEC>(fin + 3 * P, o, f3);
+  if (!EQ) load_row<S, C, VEC>(fin + P, o, f1);
+  else zero_row(f1);
+  if (!EQ) load_row<S, C, VEC>(fin + 3 * P, o, f3);
+  else zero_row(f3);
   load_row<W, C, VEC>(win, o, wc);
   if (jm >= 0) {
-    load_row<S, C, VEC>(fin + 2 * P, (uint32_t)jm * pitch + il, f2d);
+    if (!EQ) load_row<S, C, VEC>(fin + 2 * P, (uint32_t)jm * pitch + il, f2d);
+    else zero_row(f2d);
     if (SHIFT) load_row<W, C, VEC>(win, (uint32_t)jm * pitch + il, wm);
     else zero_row(wm);
   } else {
@@ -500,7 +545,8 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
     zero_row(wm);
   }
   if (jp >= 0) {
-    load_row<S, C, VEC>(fin + 4 * P, (uint32_t)jp * pitch + il, f4u);
+    if (!EQ) load_row<S, C, VEC>(fin + 4 * P, (uint32_t)jp * pitch + il, f4u);
+    else zero_row(f4u);
     if (SHIFT) load_row<W, C, VEC>(win, (uint32_t)jp * pitch + il, wp);
     else zero_row(wp);
   } else {
@@ -510,9 +556,9 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
   // own-row f^2 / f^4 for the bounced vertical pulls
   const bool up_mask = in_range(j, mr.vlo, mr.vhi);
   const bool dn_mask = jm >= 0 && in_range(jm, mr.vlo, mr.vhi);
-  if (jp < 0 || up_mask) load_row<S, C, VEC>(fin + 2 * P, o, f2own);
+  if (!EQ && (jp < 0 || up_mask)) load_row<S, C, VEC>(fin + 2 * P, o, f2own);
   else zero_row(f2own);
-  if (jm < 0 || dn_mask) load_row<S, C, VEC>(fin + 4 * P, o, f4own);
+  if (!EQ && (jm < 0 || dn_mask)) load_row<S, C, VEC>(fin + 4 * P, o, f4own);
   else zero_row(f4own);
   // halo: lane 0 left of the strip (or the periodic wrap), lane 1 right of
   // the strip, lane 2 site 0 (the periodic neighbour of the last site)
@@ -520,7 +566,7 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
   const int hr = is + SW <= last ? is + SW : 0;
   const uint32_t hx = (lane == 0) ? hl : (lane == 1 ? hr : 0);
   const S *__restrict__ Fh = (lane == 0) ? fin + P : fin + 3 * P;
-  const C hs = to_c(*at(Fh, rj + hx));
+  const C hs = EQ ? C(0) : to_c(*at(Fh, rj + hx));
   const C hw = to_c(*at(win, rj + hx));
   // severed-link bits of the lane's sites (bit k = site i0 + k)
   const uint32_t lanebits = (1u << VEC) - 1u;
@@ -537,8 +583,8 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
 
   const C s_left = lane_value(hs, 0), s_right = lane_value(hs, 1), s_wrap = lane_value(hs, 2);
   const C w_left = lane_value(hw, 0), w_right = lane_value(hw, 1), w_wrap = lane_value(hw, 2);
-  C f1L = lane_prev(f1[VEC - 1]);
-  C f3R = lane_next(f3[0]);
+  C f1L = EQ ? C(0) : lane_prev(f1[VEC - 1]);
+  C f3R = EQ ? C(0) : lane_next(f3[0]);
   C wL = lane_prev(wc[VEC - 1]);
   C wR = lane_next(wc[0]);
   if (lane == 0) {
@@ -589,14 +635,14 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
                      : ((jp < 0) ? a.t_top : (bu ? a.t_lo : C(0)));
     const C gu = dt_ ? -f2own[k] : (bu ? f2own[k] : f4u[k]);
     const C wup = dt_ ? (SHIFT ? C(2) * a.wD_top - w0 : w0) : ((!SHIFT || bu) ? w0 : wp[k]);
-    site_update<C, SHIFT>(a, f0[k], gl, gr, gd, gu, w0, wl, wr, wdn, wup, bd, bu, td, tu, o0[k],
+    site_update<C, SHIFT, EQ>(a, f0[k], gl, gr, gd, gu, w0, wl, wr, wdn, wup, bd, bu, td, tu, o0[k],
                           o1[k], o2[k], o3[k], o4[k], wo[k]);
     if (i > last) {  // padding past the row end stays zero
       o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
     }
   }
   if (act) {
-    store_pops<S, C, VEC, SR>(fout, P, o, o0, o1, o2, o3, o4, (uint32_t)j * p.nx + i0, a.rkey);
+    store_pops<S, C, VEC, SR, EQ>(fout, P, o, o0, o1, o2, o3, o4, (uint32_t)j * p.nx + i0, a.rkey);
     store_row<W, C, VEC>(wout, o, wo);
   }
 }

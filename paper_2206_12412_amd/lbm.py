@@ -24,6 +24,10 @@ STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S,
 GROW_NONE, GROW_PRESCRIBED, GROW_SIF = 0, 1, 2
 BC_WALLS, BC_PERIODIC = 0, 1
 ROUNDING = {"nearest": 0, "stochastic": 1}
+# "full": five populations and w per site; "eq": the rest population and w
+# (the moving populations rebuilt from the equilibrium of the emitting site,
+# exact at omega = 1; shifted storages only)
+LAYOUT = {"full": 0, "eq": 1}
 EDGE_BOTTOM, EDGE_TOP, EDGE_LEFT, EDGE_RIGHT = 1, 2, 4, 8
 FLAG_GREW, FLAG_WALL, FLAG_K_UNDEF = 1, 2, 4
 
@@ -62,6 +66,7 @@ class _Config(C.Structure):
         ("n_sensors", C.c_int32), ("sensors", C.POINTER(C.c_int32)),
         ("crack_row", C.c_int32), ("both_tips", C.c_int32), ("dirichlet", C.c_int32),
         ("wD_hist", C.POINTER(C.c_double)), ("n_wD", C.c_int64),
+        ("layout", C.c_int32),
         ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t),
         ("stream", C.c_void_p),
     ]
@@ -193,6 +198,7 @@ class Config:
     both_tips: bool = False               # the left end grows in -x as well
     dirichlet: int = 0                    # EDGE_* bits of the edges holding a prescribed w
     wD_hist: Optional[np.ndarray] = None  # (n, 4) wall w* of (bottom, top, left, right) per step
+    layout: str = "full"                  # "full" (five populations) or "eq" (see LAYOUT)
 
     def to_c(self, keep: list) -> _Config:
         c = _Config()
@@ -203,6 +209,7 @@ class Config:
         c.bc_mode = BC_PERIODIC if self.periodic else BC_WALLS
         c.has_crack = int(self.has_crack)
         c.rounding = ROUNDING[self.rounding] if isinstance(self.rounding, str) else int(self.rounding)
+        c.layout = LAYOUT[self.layout] if isinstance(self.layout, str) else int(self.layout)
         c.crack_row = int(self.crack_row)
         c.both_tips = int(self.both_tips)
         c.dirichlet = int(self.dirichlet)

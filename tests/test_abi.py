@@ -92,3 +92,17 @@ def test_state_bytes_scale_with_storage():
 def test_solver_refuses_cpu_device():
     with pytest.raises(RuntimeError):
         P.Solver(P.Config(nx=16, ny=8), device="cpu")
+
+
+def test_layout_validation():
+    rc, msg = init_rc(nx=16, ny=8, layout=2)
+    assert rc == -1 and "layout" in msg
+    rc, msg = init_rc(nx=16, ny=8, storage="f32plain", layout="eq")
+    assert rc == -1 and "layout" in msg
+    for st in ("f64", "f32", "f16s", "bf16s"):
+        rc, msg = init_rc(nx=16, ny=8, storage=st, layout="eq")
+        assert rc == -1 and "dev_buf" in msg  # valid up to the missing device block
+    # the moving planes stay allocated: same state size in both layouts
+    a = P.state_bytes(P.Config(nx=300, ny=70, storage="f16s"))
+    b = P.state_bytes(P.Config(nx=300, ny=70, storage="f16s", layout="eq"))
+    assert a == b

@@ -92,14 +92,25 @@ def window_oracle(p, wd0, ic, jc, T, d):
 F16_TOL = 4 * 2.0 ** -11 * math.sqrt(T_WIN)
 
 
+def parse(name):
+    """"f16s-eq-sr" -> ("f16s", "stochastic", "eq")"""
+    rounding = "stochastic" if name.endswith("-sr") else "nearest"
+    name = name[:-3] if name.endswith("-sr") else name
+    layout = "eq" if name.endswith("-eq") else "full"
+    return (name[:-3] if layout == "eq" else name), rounding, layout
+
+
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5), ("f16s", F16_TOL),
-                                         ("f16s-sr", F16_TOL)])
+                                         ("f16s-sr", F16_TOL), ("f64-eq", 1e-12),
+                                         ("f32-eq", 1e-5), ("f16s-eq-sr", F16_TOL)])
 def test_precision_plate_windows(big_plate, storage, tol):
+    """The 134M-site plate in the launch configuration the benchmark times
+    (the library's default shapes), on sampled windows the oracle computes."""
     p, wd0 = big_plate
     T, d = T_WIN, D_BLOCK
     say(f"134M-site plate, storage {storage}, {T} steps")
-    rounding = "stochastic" if storage.endswith("-sr") else "nearest"
-    s = Solver(Config(nx=p.nx, ny=p.ny, storage=storage.replace("-sr", ""), rounding=rounding,
+    st, rounding, layout = parse(storage)
+    s = Solver(Config(nx=p.nx, ny=p.ny, storage=st, rounding=rounding, layout=layout,
                       has_crack=True, crack_x0=p.crack_x0,
                       crack_tip=p.crack_tip, growth=p.growth, v_rel=p.v_rel,
                       tau_hist=p.traction_history(), wdot0=wd0, trace_cap=T))
@@ -140,9 +151,10 @@ def sif_golden():
         return json.load(fh)
 
 
-def run_sif(storage, g):
+def run_sif(storage, g, layout="full"):
     p = synth.config_sif_fp32()
-    s = Solver(Config(nx=p.nx, ny=p.ny, storage=storage, has_crack=True, crack_x0=p.crack_x0,
+    s = Solver(Config(nx=p.nx, ny=p.ny, storage=storage, layout=layout, has_crack=True,
+                      crack_x0=p.crack_x0,
                       crack_tip=p.crack_tip, growth=p.growth, K_C=p.K_C, r0=p.r0, v_max=p.v_max,
                       tau_hist=p.traction_history(), wdot0=p.wdot0(), trace_cap=p.steps))
     sites = np.array(g["sites"])
@@ -177,6 +189,39 @@ def test_sif_workload_fp64_reproduces_the_oracle(sif_golden):
     assert kerr <= 1e-12
     assert ev.tolist() == g["events"]
     np.testing.assert_allclose(tr["tip"], g["tip"], rtol=0, atol=1e-9)
+
+
+def test_sif_workload_fp64_equilibrium_layout(sif_golden):
+    """FP64 in the equilibrium layout rounds differently from the oracle
+    (shifted arithmetic).  Up to the onset of growth the fields and K agree
+    within 1e-12; from the onset on the path is sensitive to perturbations of
+    the state at the level of rounding (the oracle itself, with wdot0 scaled
+    by 1 + 1e-14, cuts its first link 3 steps later), so the comparison is
+    the cut-column sequence and the event statistics."""
+    g = sif_golden
+    say("4096x2048 K criterion, FP64 (equilibrium layout), 20000 steps")
+    p, snaps, tr, ev = run_sif("f64", g, "eq")
+    first_growth = int(np.argmax((np.array(g["flags"]) & 1) != 0))
+    for n, (w, wd) in snaps.items():
+        ref = g["snapshots"][str(n)]
+        e = np.abs(w - np.array(ref["w"])).max() / ref["w_absmax"]
+        say(f"  step {n}: sampled w rel err {e:.2e}")
+        if n < first_growth:
+            assert e <= 1e-12
+    K_ref = np.array(g["K"])
+    ok = ~np.isnan(K_ref)
+    pre = ok & (np.arange(len(K_ref)) < first_growth)
+    kerr = np.abs(tr["K"][pre] - K_ref[pre]).max() / np.abs(K_ref[pre]).max()
+    gev = np.array(g["events"])
+    n = min(len(ev), len(gev))
+    shift = np.abs(ev[:n, 0] - gev[:n, 0])
+    say(f"  pre-onset K rel err {kerr:.2e}; events {len(ev)} vs {len(gev)}; "
+        f"max step shift {shift.max()}, mean {shift.mean():.1f}; final tip {tr['tip'][-1]:.4f} "
+        f"vs {g['tip'][-1]:.4f}")
+    assert kerr <= 1e-12
+    # the crack grows column by column from the initial tip, as in the oracle
+    assert np.array_equal(ev[:n, 1], gev[:n, 1])
+    assert abs(len(ev) - len(gev)) <= 0.02 * len(gev)
 
 
 def test_sif_workload_fp32_cut_sequence_and_margins(sif_golden):
