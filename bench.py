@@ -428,7 +428,10 @@ def summarize_trace(dirpath: str, out_md: str, command: str):
 def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, copy_bytes: int,
                   command: str, out_dir: str):
     """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs,
-    each scaled by the same counter's reading for a device copy of copy_bytes."""
+    each scaled by the same counter's reading for a device copy of copy_bytes.
+    The sweep kernel is the sweep_step instantiation with the most launches
+    (in the equilibrium layout the first two steps of a fresh plate run the
+    five-plane instantiation, which is left out)."""
     import synth
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
          "plain": synth.config_plain_fp64}[workload]()
@@ -440,10 +443,17 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
                 if r["Counter_Name"] == counter]
         copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
         factor = copy_bytes / (copy * 1024.0)
-        vals = [float(r["Counter_Value"]) for r in rows if "sweep_step" in r["Kernel_Name"]]
+        names = {}
+        for r in rows:
+            if "sweep_step" in r["Kernel_Name"]:
+                names.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        name = max(names, key=lambda k: len(names[k]))
+        vals = names[name]
         kib = sum(vals) / len(vals)
         out[counter] = {"KiB_per_launch": kib, "copy_KiB": copy, "factor": factor,
-                        "bytes_per_launch": kib * 1024.0 * factor, "launches": len(vals)}
+                        "bytes_per_launch": kib * 1024.0 * factor, "launches": len(vals),
+                        "kernel": name[:160],
+                        "other_sweep_launches": {k[:160]: len(v) for k, v in names.items() if k != name}}
         total += kib * 1024.0 * factor
     bps = sweep_bytes_per_site(storage)
     sites = p.nx * p.ny
