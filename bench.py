@@ -22,6 +22,7 @@ import argparse
 import dataclasses
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -302,6 +303,51 @@ def run_batched(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def run_strip(args, torch):
+    """The steady-growth strip of Sec. 5.1 at v = 0.2 .. 0.8: K sampled 300
+    times over the last 15 L / c_s against eq. (sif-mandal) and the paper's
+    own statistics, in the FP64 reference and the headline storage."""
+    import synth
+    from paper_2206_12412_amd import Solver
+    with open(os.path.join(ROOT, "tests", "golden", "steady_strip_table.json")) as fh:
+        table = json.load(fh)
+    paper = {r[0]: dict(zip(table["columns"], r)) for r in table["rows"]}
+    rows = {}
+    for name in ("f64", args.storage):
+        st, rd, layout = parse_storage(name)
+        for v in (0.2, 0.4, 0.6, 0.8):
+            m = synth.mandal_strip(v)
+            s = Solver(strip_config(st, rd, layout, m["config"]))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(m["steps"])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            K = s.traces()["K"][m["sample_steps"]] / math.sqrt(16.0)  # in units with L = 1
+            s.close()
+            q = np.percentile(K, [25, 50, 75])
+            rows.setdefault(name, {})[str(v)] = {
+                "K_theo": round(m["K_theo"] / 4.0, 5), "mean": round(float(K.mean()), 5),
+                "sigma": round(float(K.std()), 5), "median": round(float(q[1]), 5),
+                "minus_25": round(float(q[1] - q[0]), 5), "plus_75": round(float(q[2] - q[1]), 5),
+                "median_rel_to_theo": round(float(q[1] / (m["K_theo"] / 4.0) - 1.0), 4),
+                "paper_median_rel_to_theo": round(paper[v]["median"] / paper[v]["K_theo"] - 1.0, 4),
+                "sites": m["config"]["nx"] * m["config"]["ny"], "steps": m["steps"],
+                "ms_per_step": round(el * 1e3 / m["steps"], 4)}
+    line = {"metric": "K_III of steady crack growth in a strip against eq. (sif-mandal)",
+            "value": rows[args.storage]["0.4"]["median_rel_to_theo"], "unit": "relative",
+            "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": "steady-strip (Sec. 5.1), 2L x (0.5 + v t_f + 2.5) L, dh = L/16",
+                       "storage": args.storage},
+            "speeds": rows}
+    print(json.dumps(line), flush=True)
+
+
+def strip_config(storage, rounding, layout, kw):
+    from paper_2206_12412_amd import Config
+    return Config(storage=storage, rounding=rounding, layout=layout, **kw)
+
+
 def run_adjoint(args, torch):
     """2048 x 1024 plate with a stationary 512-site crack, 5000 steps: the
     sensor-trace loss against a run with a 10 % sinusoidal traction
@@ -320,9 +366,10 @@ def run_adjoint(args, torch):
                 sensors=sens, trace_cap=T)
     tau0 = np.full(T, p.tau)
 
-    def run(st, tau, wd0=None):
+    def run(name, tau, wd0=None):
         """(solver after T steps, its sensor traces, ms of the T steps)"""
-        s = Solver(Config(storage=st, tau_hist=tau, wdot0=wd0, **base))
+        st, rd, layout = parse_storage(name)
+        s = Solver(Config(storage=st, rounding=rd, layout=layout, tau_hist=tau, wdot0=wd0, **base))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(s.stream)
@@ -339,7 +386,9 @@ def run_adjoint(args, torch):
     say(f"adjoint: target run, {T} steps")
     target = traces("f64", synth.adjoint_target_history(T, tau0=p.tau))
     if args.warmup > 0:
-        w = Solver(Config(storage=storage, tau_hist=tau0, **dict(base, trace_cap=args.warmup)))
+        st, rd, layout = parse_storage(storage)
+        w = Solver(Config(storage=st, rounding=rd, layout=layout, tau_hist=tau0,
+                          **dict(base, trace_cap=args.warmup)))
         w.step(args.warmup)
         torch.cuda.synchronize()
         w.close()
@@ -365,14 +414,17 @@ def run_adjoint(args, torch):
         ad.append(float(dtau @ d_tau + (dwd0 * d_wd).sum()))
     fd, ad = np.array(fd), np.array(ad)
     sites = p.nx * p.ny
-    bps = 2.0 * (5 * (8 if storage == "f64" else 4) + (8 if storage == "f64" else 4))
+    # the adjoint state is FP64 or FP32 whatever the forward storage; five
+    # planes + W, or plane 0 + W in the equilibrium layout
+    ae = 8 if parse_storage(storage)[0] == "f64" else 4
+    bps = 2.0 * ((1 if parse_storage(storage)[2] == "eq" else 5) * ae + ae)
     sweep_ms = adj_ms / (T + 1)
     achieved = sites * bps / (sweep_ms * 1e-3) / 1e9
     line = {
         "metric": METRIC, "value": round(sites * (T + 1) / (adj_ms * 1e-3) / 1e9, 2),
         "unit": "GLUPS", "n_gpus": 1, "steps": T, "warmup": args.warmup,
         "ms_per_step": round(sweep_ms, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if storage == "f64" else "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if ae == 8 else "f32", "data": "synthetic",
         "config": {"workload": f"adjoint-{p.nx}x{p.ny}", "nx": p.nx, "ny": p.ny,
                    "crack_sites": p.ell, "sensors": int(len(sens)), "storage": storage,
                    "parallelism": "single-gpu"},
@@ -482,11 +534,13 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="precision",
-                    choices=["precision", "sif", "plain", "batched", "adjoint"])
-    ap.add_argument("--adjoint-storage", default="f32", help="storage of the adjoint workload's run")
+                    choices=["precision", "sif", "plain", "batched", "adjoint", "strip"])
+    ap.add_argument("--adjoint-storage", default="f32-eq",
+                    help="storage (and layout) of the adjoint workload's run")
     ap.add_argument("--directions", type=int, default=16,
                     help="adjoint workload: random directions of the gradient check")
-    ap.add_argument("--batch-storage", default="f32", help="storage of the batched workload")
+    ap.add_argument("--batch-storage", default="f32-eq",
+                    help="storage (and layout) of the batched workload")
     ap.add_argument("--no-tune", action="store_true", help="batched: keep the default launch shape")
     ap.add_argument("--tune", action="store_true",
                     help="single plate: autotune each storage before timing (the library's "
@@ -534,6 +588,9 @@ def main():
         return
     if args.workload == "adjoint":
         run_adjoint(args, torch)
+        return
+    if args.workload == "strip":
+        run_strip(args, torch)
         return
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
          "plain": synth.config_plain_fp64}[args.workload]()

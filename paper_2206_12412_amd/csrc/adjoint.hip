@@ -30,6 +30,11 @@
 // the same launch.  The loss gradient of the state a sweep produces is added
 // to W by the thread that writes it (the sensors are indexed by row).
 // FP64 is evaluated without contraction in the order written above.
+//
+// At omega = 1 every mu^a a sweep writes equals D, so the five planes hold
+// the same values.  The equilibrium-layout sweep (EQ) keeps plane 0 only and
+// reads it for every direction: the same numbers from a fifth of the
+// population traffic.
 #include "sweep_core.hpp"
 
 namespace lbmk {
@@ -75,7 +80,7 @@ __device__ __forceinline__ void adj_local(const AdjArgs<C> &a, C l0, C l1, C l2,
   wo = G;
 }
 
-template <typename C, int VEC>
+template <typename C, int VEC, bool EQ>
 __device__ __forceinline__ void adj_interior_row(const AdjArgs<C> &a, int strip, int j) {
   const Plate p = a.p;
   const int lane = threadIdx.x & 63;
@@ -87,17 +92,23 @@ __device__ __forceinline__ void adj_interior_row(const AdjArgs<C> &a, int strip,
   const uint32_t il = act ? i0 : is;
   const uint32_t pitch = p.pitch;
   const size_t P = p.plane;
+  const size_t Q = EQ ? 0 : P;  // plane stride of the reads (EQ: every direction from plane 0)
   const C *__restrict__ M0 = a.min;
-  const C *__restrict__ M1 = a.min + P;
-  const C *__restrict__ M2 = a.min + 2 * P;
-  const C *__restrict__ M3 = a.min + 3 * P;
-  const C *__restrict__ M4 = a.min + 4 * P;
+  const C *__restrict__ M1 = a.min + Q;
+  const C *__restrict__ M2 = a.min + 2 * Q;
+  const C *__restrict__ M3 = a.min + 3 * Q;
+  const C *__restrict__ M4 = a.min + 4 * Q;
   const uint32_t o = (uint32_t)j * pitch + il;
 
   C m0[VEC], m1[VEC], m3[VEC], m2u[VEC], m4d[VEC], b[VEC];
   load_row<C, C, VEC>(M0, o, m0);
-  load_row<C, C, VEC>(M1, o, m1);
-  load_row<C, C, VEC>(M3, o, m3);
+  if constexpr (EQ) {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) m1[k] = m3[k] = m0[k];
+  } else {
+    load_row<C, C, VEC>(M1, o, m1);
+    load_row<C, C, VEC>(M3, o, m3);
+  }
   load_row<C, C, VEC>(M2, o + pitch, m2u);  // mu^2 of the site above
   load_row<C, C, VEC>(M4, o - pitch, m4d);  // mu^4 of the site below
   load_row<C, C, VEC>(a.win, o, b);
@@ -139,10 +150,12 @@ __device__ __forceinline__ void adj_interior_row(const AdjArgs<C> &a, int strip,
   }
   if (act) {
     store_row<C, C, VEC>(a.mout, o, o0);
-    store_row<C, C, VEC>(a.mout + P, o, o1);
-    store_row<C, C, VEC>(a.mout + 2 * P, o, o2);
-    store_row<C, C, VEC>(a.mout + 3 * P, o, o3);
-    store_row<C, C, VEC>(a.mout + 4 * P, o, o4);
+    if constexpr (!EQ) {
+      store_row<C, C, VEC>(a.mout + P, o, o1);
+      store_row<C, C, VEC>(a.mout + 2 * P, o, o2);
+      store_row<C, C, VEC>(a.mout + 3 * P, o, o3);
+      store_row<C, C, VEC>(a.mout + 4 * P, o, o4);
+    }
     store_row<C, C, VEC>(a.wout, o, wo);
   }
 }
@@ -156,13 +169,13 @@ __device__ __forceinline__ double block_sum(double x, double *lds) {
 }
 
 // Edge and crack row j, one thread per site i (part = block of the row).
-template <typename C>
+template <typename C, bool EQ>
 __device__ __forceinline__ void adj_boundary_site(const AdjArgs<C> &a, int r, int j, int part,
                                                   double *red) {
   const Plate p = a.p;
   const int i = part * 256 + threadIdx.x;
   const int last = p.nx - 1;
-  const size_t P = p.plane;
+  const size_t P = EQ ? 0 : p.plane;  // plane stride of the reads (EQ: plane 0 only)
   double dtau = 0.0;
   if (i < p.nx) {
     const size_t pitch = p.pitch;
@@ -192,10 +205,12 @@ __device__ __forceinline__ void adj_boundary_site(const AdjArgs<C> &a, int r, in
         if (a.srt[2 * e] == i) wo = (C)((double)wo + a.g[a.srt[2 * e + 1]]);
     }
     a.mout[x] = o0;
-    a.mout[P + x] = o1;
-    a.mout[2 * P + x] = o2;
-    a.mout[3 * P + x] = o3;
-    a.mout[4 * P + x] = o4;
+    if constexpr (!EQ) {
+      a.mout[P + x] = o1;
+      a.mout[2 * P + x] = o2;
+      a.mout[3 * P + x] = o3;
+      a.mout[4 * P + x] = o4;
+    }
     a.wout[x] = wo;
     if (a.traction) {  // traction-loaded edges only (not the Dirichlet ones)
       if (j == p.ny - 1 && !(a.dmask & core::kEdgeTop)) dtau += a.coef * (double)M[4 * P + x];
@@ -208,14 +223,14 @@ __device__ __forceinline__ void adj_boundary_site(const AdjArgs<C> &a, int r, in
 
 // One adjoint sweep: the first nb * n_parts workgroups take the boundary rows
 // (one thread per site), the rest the interior strips (4 waves each).
-template <typename C, int VEC>
+template <typename C, int VEC, bool EQ>
 __global__ void __launch_bounds__(256) adj_step(const AdjArgs<C> a, const core::InteriorMap m,
                                                 const core::BoundaryMap bm, long n_tasks) {
   __shared__ double red[4];
   const unsigned nbb = (unsigned)(bm.nb * a.n_parts);
   if (blockIdx.x < nbb) {
     const int r = blockIdx.x / a.n_parts;
-    adj_boundary_site<C>(a, r, bm.brow[r], blockIdx.x % a.n_parts, red);
+    adj_boundary_site<C, EQ>(a, r, bm.brow[r], blockIdx.x % a.n_parts, red);
     return;
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -224,7 +239,7 @@ __global__ void __launch_bounds__(256) adj_step(const AdjArgs<C> a, const core::
   const int strip = (int)(task % m.n_strips);
   const int chunk = (int)(task / m.n_strips);
   const int j = chunk < m.nc1 ? m.lo1 + chunk : m.lo2 + (chunk - m.nc1);
-  adj_interior_row<C, VEC>(a, strip, j);
+  adj_interior_row<C, VEC, EQ>(a, strip, j);
 }
 
 template <typename C>
@@ -243,13 +258,13 @@ __global__ void adj_export(const C *plane, Plate p, double *out) {
   out[t] = (double)plane[j * p.pitch + i];
 }
 
-template <typename C, int VEC>
+template <typename C, int VEC, bool EQ>
 hipError_t sweep_t(const AdjArgs<C> &a, hipStream_t st) {
   const core::InteriorMap m = core::interior_map(a.p.nx, a.p.ny, VEC, 1, a.skip_lo, a.skip_hi);
   const core::BoundaryMap bm = core::boundary_map(a.p.nx, a.p.ny, VEC, a.skip_lo, a.skip_hi);
   const long tasks = core::interior_task_count(m);
   const unsigned blocks = (unsigned)(bm.nb * a.n_parts + (tasks + 3) / 4);
-  hipLaunchKernelGGL((adj_step<C, VEC>), dim3(blocks), dim3(256), 0, st, a, m, bm, tasks);
+  hipLaunchKernelGGL((adj_step<C, VEC, EQ>), dim3(blocks), dim3(256), 0, st, a, m, bm, tasks);
   return hipGetLastError();
 }
 
@@ -257,9 +272,13 @@ hipError_t sweep_t(const AdjArgs<C> &a, hipStream_t st) {
 
 int adjoint_parts(int nx) { return (nx + 255) / 256; }
 
-hipError_t launch_adjoint_sweep(bool fp64, const void *args, hipStream_t st) {
-  if (fp64) return sweep_t<double, 2>(*static_cast<const AdjArgs<double> *>(args), st);
-  return sweep_t<float, 4>(*static_cast<const AdjArgs<float> *>(args), st);
+hipError_t launch_adjoint_sweep(bool fp64, bool eq, const void *args, hipStream_t st) {
+  if (fp64) {
+    const auto &a = *static_cast<const AdjArgs<double> *>(args);
+    return eq ? sweep_t<double, 2, true>(a, st) : sweep_t<double, 2, false>(a, st);
+  }
+  const auto &a = *static_cast<const AdjArgs<float> *>(args);
+  return eq ? sweep_t<float, 4, true>(a, st) : sweep_t<float, 4, false>(a, st);
 }
 
 hipError_t launch_adjoint_inject(bool fp64, void *w, const Plate &p, const int32_t *sens, int n,

@@ -1401,7 +1401,7 @@ int adjoint_sweep(lbm_adjoint *a, int cur, int64_t m) {
   g.g = (ns > 0 && m >= 2) ? a->g + (size_t)(m - 2) * ns : nullptr;
   g.srow = reinterpret_cast<const int32_t *>(a->base + a->off_srow);
   g.srt = reinterpret_cast<const int32_t *>(a->base + a->off_srt);
-  HIP_TRY(lbmk::launch_adjoint_sweep(a->fp64, &g, h->stream));
+  HIP_TRY(lbmk::launch_adjoint_sweep(a->fp64, h->eq, &g, h->stream));
   return LBM_OK;
 }
 

@@ -173,7 +173,9 @@ struct AdjArgs {
 
 // ---- launchers (adjoint.hip) ----
 // one adjoint sweep (boundary rows and interior strips in one launch)
-hipError_t launch_adjoint_sweep(bool fp64, const void *args, hipStream_t st);
+// eq: the adjoint populations kept in plane 0 only (they are all equal at
+// omega = 1)
+hipError_t launch_adjoint_sweep(bool fp64, bool eq, const void *args, hipStream_t st);
 // w[sensor s] += g[s] (the loss gradient of the last step, before the first sweep)
 hipError_t launch_adjoint_inject(bool fp64, void *w, const Plate &p, const int32_t *sens, int n,
                                  const double *g, hipStream_t st);

@@ -188,3 +188,44 @@ def two_tip_demo(steps: int = 4000, L: int = 64) -> dict:
                 crack_tip=centre + L / 2, both_tips=True, growth=GROW_SIF,
                 K_C=0.0055 * np.sqrt(L), r0=0.03 * L, v_max=0.85, dirichlet=1 | 2,
                 wD_hist=wD, trace_cap=steps)
+
+
+# r_min / dh chosen per speed for the steady-growth strip (the second column
+# of the table of Sec. 5.1)
+STRIP_R_MIN = {0.2: 1.5, 0.4: 2.25, 0.6: 4.0, 0.8: 8.0}
+
+
+def mandal_strip(v: float, L: int = 16, w0: float = 0.2, t0: float = 10.0,
+                 t_quasi: float = 20.0) -> dict:
+    """The steady-growth strip of Sec. 5.1 (lengths in units of L, times in
+    L / c_s): a strip of height 2L (dh = L / 16: 32 rows, walls half-way past
+    the edge rows), its upper and lower edges held at +-w0/2 times the ramp
+    sin^2(pi t / (2 t0)) up to t0 and 1 after it, lateral edges and crack
+    faces traction-free; an edge crack of length L/2 on the mid-line, driven
+    at the prescribed speed v from the first step; r_min taken from the
+    table (r0 = r_min (1 - v)).  The run ends at t_f = t0 + t_quasi; the
+    right edge b = 0.5 + v t_f + 2.5 (beyond v c_s t_f + 2L).  Returns the
+    Config keyword arguments, the 300 sampled steps of [t_f - 15, t_f] and
+    the steady K of eq. (sif-mandal) in lattice units.
+
+    Lattice units: mu = 1, dh = 1, c_s = 1, dt = 1/2, so one L / c_s is 2 L
+    steps; w0 is in units of L (w0 L in lattice units), and K (stress times
+    sqrt(length)) is sqrt(L) times its value in units where L = 1."""
+    t_f = t0 + t_quasi
+    steps = int(round(t_f * 2 * L))
+    nx = int(math.ceil((0.5 + v * t_f + 2.5) * L))
+    n = np.arange(steps, dtype=np.float64)
+    t = n * 0.5 / L
+    ramp = np.where(t < t0, np.sin(0.5 * np.pi * t / t0) ** 2, 1.0)
+    wD = np.zeros((steps, 4))
+    wD[:, 0] = -0.5 * w0 * L * ramp   # bottom edge y = -L
+    wD[:, 1] = 0.5 * w0 * L * ramp    # top edge y = +L
+    r_min = STRIP_R_MIN[v]
+    beta = math.sqrt(1.0 - v * v)
+    K_theo = w0 * math.sqrt(2.0 * beta / (2.0 * beta + 1.0)) * math.sqrt(L)
+    sample = np.unique(np.round(np.linspace(steps - 1 - 15 * 2 * L, steps - 1, 300)).astype(int))
+    kw = dict(nx=nx, ny=2 * L, has_crack=True, crack_x0=-0.5, crack_tip=0.5 * L - 0.5,
+              growth=GROW_PRESCRIBED, v_rel=v, r0=r_min * (1.0 - v), dirichlet=1 | 2,
+              wD_hist=wD, trace_cap=steps)
+    return {"config": kw, "steps": steps, "sample_steps": sample, "K_theo": K_theo,
+            "t_f": t_f, "r_min": r_min}

@@ -209,3 +209,28 @@ def test_fp64_adjoint_with_dirichlet_edges_and_off_centre_crack():
     r = O.sensor_adjoint(ocfg, sens, 2.0 * (O.sensor_traces(ocfg, sens, T) - target))
     assert max(rel(dwd0, r[1]), rel(dw0, r[2])) <= 1e-12
     assert rel(dtau, r[0]) <= 1e-12  # the traction acts on the (free) left edge only: none
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("growth", [0, 1])
+def test_equilibrium_layout_adjoint_equals_five_planes(storage, growth):
+    """At omega = 1 all five adjoint populations a sweep writes are equal; the
+    equilibrium-layout adjoint keeps one plane and gives the same gradients
+    bit for bit (same loss gradient fed to both)."""
+    kw, sens, target = case(150, 44, 120, 40, seed=31, growth=growth, v=0.4)
+    n = np.arange(120)
+    wD = np.zeros((120, 4))
+    wD[:, 0] = 5e-3 * np.sin(np.pi * n / 70.0)
+    kw.update(dirichlet=1, wD_hist=wD)
+    say(f"adjoint eq vs full {storage} growth={growth}")
+    out = {}
+    for layout in ("full", "eq"):
+        s = Solver(Config(storage=storage, layout=layout, sensors=sens, **kw))
+        s.step(120)
+        if layout == "full":
+            g = torch.from_numpy(2.0 * (s.sensor_traces() - target)).cuda()
+        dtau, dwd0, dw0 = s.adjoint(g)
+        out[layout] = (np.asarray(dtau), dwd0.cpu().numpy(), dw0.cpu().numpy())
+        s.close()
+    for a, b in zip(out["full"], out["eq"]):
+        np.testing.assert_array_equal(a, b)

@@ -322,3 +322,33 @@ def test_two_tip_k_criterion_demo_fp64():
     ev_r = ref.events()
     assert gpu.cut_events().tolist() == [[int(e[0]), int(e[1])] for e in ev_r]
     assert len(ev_r) > 10  # both tips grew
+
+
+# ------------------------------------ steady growth in a strip (Sec. 5.1) --
+
+@pytest.mark.parametrize("v", [0.2, 0.8])
+@pytest.mark.parametrize("storage,layout,rounding", [("f64", "full", "nearest"),
+                                                     ("f64", "eq", "nearest"),
+                                                     ("f32", "eq", "nearest"),
+                                                     ("f16s", "eq", "stochastic")])
+def test_steady_strip_against_the_oracle(v, storage, layout, rounding):
+    """The Sec. 5.1 strip (Dirichlet +-w0/2 edges with the sin^2 ramp, edge
+    crack at a prescribed speed): tips bit-exact, fields and the sampled K
+    statistics as the oracle's within the storage's bounds."""
+    m = synth.mandal_strip(v)
+    say(f"steady strip v={v} {storage} {layout} {rounding}")
+    ref = O.Oracle(O.OracleConfig(**m["config"]))
+    gpu = Solver(Config(storage=storage, layout=layout, rounding=rounding, seed=3, **m["config"]))
+    ref.step(m["steps"])
+    gpu.step(m["steps"])
+    w_r, w_g = ref.fields()[0], gpu.fields()[0]
+    tol = {"f64": 1e-12, "f32": 1e-5, "f16s": 4 * 2.0 ** -11 * math.sqrt(m["steps"])}[storage]
+    assert relerr(w_g, w_r) <= tol
+    tr, tg = ref.traces(), gpu.traces()
+    np.testing.assert_array_equal(tg["tip"], tr["tip"])
+    assert gpu.cut_events()[:, 1].tolist() == ref.events()[:, 1].tolist()
+    K_r, K_g = tr["K"][m["sample_steps"]], tg["K"][m["sample_steps"]]
+    ktol = {"f64": 1e-12, "f32": 1e-5, "f16s": 1e-3}[storage]
+    assert np.abs(K_g - K_r).max() <= ktol * np.abs(K_r).max()
+    assert abs(np.median(K_g) / np.median(K_r) - 1.0) <= ktol
+    say(f"  median K / K_theo - 1 = {np.median(K_g) / m['K_theo'] - 1:+.4f}")
