@@ -238,11 +238,13 @@ template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool
 hipError_t persistent_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
                         int64_t step, int64_t nsteps, unsigned *sync, int *blocks_used,
                         hipStream_t st) {
-  // one workgroup of 4 waves per CU: measured on MI355X against 1 to 16 waves
-  // and 1 to 4 workgroups per CU (more waves contend, more workgroups pay
-  // for more barrier releases / acquires)
-  return persistent_w<S, W, C, VEC, SHIFT, SR, EQ, 4>(d, n, n_int, n_bnd, cur, step, nsteps, sync,
-                                                      blocks_used, st);
+  // one workgroup per CU (more workgroups pay for more barrier releases /
+  // acquires), of 16 waves in the equilibrium layout and 8 with five planes:
+  // measured on MI355X for the 64-plate FP32 batch against 4, 8 and 16 waves
+  // (equilibrium layout 114 / 183 / 256 GLUPS, five planes 84 / 103 / 87)
+  constexpr int kWaves = EQ ? 16 : 8;
+  return persistent_w<S, W, C, VEC, SHIFT, SR, EQ, kWaves>(d, n, n_int, n_bnd, cur, step, nsteps,
+                                                           sync, blocks_used, st);
 }
 
 // stochastic rounding exists for the 16-bit storages only, the equilibrium
