@@ -49,6 +49,7 @@ class _Cfg(C.Structure):
         ("trace_cap", C.c_int64), ("threads", C.c_int32),
         ("crack_row", C.c_int32), ("both_tips", C.c_int32), ("dirichlet", C.c_int32),
         ("wD_hist", C.POINTER(C.c_double)), ("n_wD", C.c_int64),
+        ("crack_dx", C.c_double), ("crack_dy", C.c_double),
     ]
 
 
@@ -124,6 +125,8 @@ class OracleConfig:
     both_tips: bool = False       # the left end grows in -x as well
     dirichlet: int = 0            # EDGE_* bits of the edges with a prescribed w
     wD_hist: Optional[np.ndarray] = None   # [n][4] w* of (bottom, top, left, right) per step
+    crack_dx: float = 1.0         # growth direction of the right tip (Alg. 1, d); (1, 0) = +x
+    crack_dy: float = 0.0
     _keep: list = field(default_factory=list, repr=False)
 
 
@@ -136,7 +139,7 @@ class Oracle:
         c = _Cfg()
         for name in ("nx", "ny", "kappa", "omega", "mu", "rho", "crack_x0", "crack_tip", "growth",
                      "v_rel", "K_C", "r0", "v_max", "k_band", "face_traction", "trace_cap",
-                     "threads", "crack_row", "dirichlet"):
+                     "threads", "crack_row", "dirichlet", "crack_dx", "crack_dy"):
             setattr(c, name, getattr(cfg, name))
         c.periodic = int(cfg.periodic)
         c.has_crack = int(cfg.has_crack)

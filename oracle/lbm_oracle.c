@@ -72,6 +72,9 @@ struct orc_sim {
   double cs, c, dt, lambda, A0, Ak, coef;
   int32_t j0;
   double yc;
+  int aligned;                       /* growth along +x on the crack row */
+  double ux, uy;                     /* unit growth direction of the right tip */
+  double a_lo, a_hi;                 /* line coordinates where the line leaves the plate */
   double *f, *fn, *w;
   uint8_t *cutV, *cutH;
   tip_t tips[2];                     /* [0] right tip, [1] left end / left tip */
@@ -150,10 +153,38 @@ static int segments_intersect(double p1x, double p1y, double p2x, double p2y,
   return 0;
 }
 
-/* Does the crack segment (a0, yc)-(a1, yc) intersect the link from site p to
- * its neighbour n?  Links are the straight lines between lattice points. */
+/* The point of the crack line at line coordinate a: (a, y_c) along +x, else
+ * S + (a - x0) u. */
+static void crack_point(const orc_sim *s, double a, double *x, double *y) {
+  if (s->aligned) {
+    *x = a;
+    *y = s->yc;
+    return;
+  }
+  const double d = a - s->cfg.crack_x0;
+  *x = s->cfg.crack_x0 + d * s->ux;
+  *y = s->yc + d * s->uy;
+}
+
+/* Does the crack segment between line coordinates a0 and a1 intersect the
+ * link from site p to its neighbour n?  Links are the straight lines between
+ * lattice points. */
 static int seg_hits_link(const orc_sim *s, double a0, double a1, int pi, int pj, int ni, int nj) {
-  return segments_intersect(a0, s->yc, a1, s->yc, (double)pi, (double)pj, (double)ni, (double)nj);
+  double x0, y0, x1, y1;
+  crack_point(s, a0, &x0, &y0);
+  crack_point(s, a1, &x1, &y1);
+  return segments_intersect(x0, y0, x1, y1, (double)pi, (double)pj, (double)ni, (double)nj);
+}
+
+/* Arc length from (x, y) along (ux, uy) to the plate's wall rectangle
+ * [-1/2, nx - 1/2] x [-1/2, ny - 1/2] (the point lies inside it). */
+static double exit_length(const orc_sim *s, double x, double y, double ux, double uy) {
+  double t = INFINITY;
+  if (ux > 0) t = fmin(t, (s->cfg.nx - 0.5 - x) / ux);
+  if (ux < 0) t = fmin(t, (-0.5 - x) / ux);
+  if (uy > 0) t = fmin(t, (s->cfg.ny - 0.5 - y) / uy);
+  if (uy < 0) t = fmin(t, (-0.5 - y) / uy);
+  return t;
 }
 
 /* ------------------------------------------------------------- creation -- */
@@ -169,8 +200,13 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
   else if (cfg->has_crack && cfg->crack_row >= 0 && cfg->crack_row > cfg->ny - 2) e = -1;
   else if (cfg->both_tips && !cfg->has_crack) e = -1;
   else if (cfg->dirichlet && (cfg->periodic || cfg->n_wD < 1 || !cfg->wD_hist)) e = -1;
-  else if (cfg->has_crack && !(cfg->crack_x0 >= -0.5 && cfg->crack_tip >= cfg->crack_x0 &&
-                               cfg->crack_tip <= cfg->nx - 0.5)) e = -5;
+  else if (!(isfinite(cfg->crack_dx) && isfinite(cfg->crack_dy))) e = -1;
+  /* the start point inside the plate, the tip on the far side of it (and,
+   * along +x, inside the plate; for another direction checked below) */
+  else if (cfg->has_crack && !(cfg->crack_x0 >= -0.5 && cfg->crack_x0 <= cfg->nx - 0.5 &&
+                               cfg->crack_tip >= cfg->crack_x0 &&
+                               (cfg->crack_tip <= cfg->nx - 0.5 ||
+                                !(cfg->crack_dy == 0.0 && cfg->crack_dx >= 0.0)))) e = -5;
   else if (cfg->growth != ORC_GROW_NONE && (!cfg->has_crack || cfg->periodic)) e = -1;
   else if (cfg->growth == ORC_GROW_PRESCRIBED && !(cfg->v_rel >= 0 && cfg->v_rel < 1)) e = -1;
   else if (cfg->growth == ORC_GROW_SIF && !(cfg->K_C > 0 && cfg->v_max >= 0 && cfg->v_max < 1))
@@ -210,6 +246,30 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
   s->coef = s->dt / (cfg->rho * 1.0);
   s->j0 = cfg->crack_row >= 0 ? cfg->crack_row : cfg->ny / 2 - 1;
   s->yc = s->j0 + 0.5;
+  /* growth direction: +x along the crack row unless another one is given */
+  s->aligned = (cfg->crack_dy == 0.0 && cfg->crack_dx >= 0.0);
+  if (s->aligned) {
+    s->ux = 1.0;
+    s->uy = 0.0;
+    s->a_lo = -0.5;
+    s->a_hi = cfg->nx - 0.5;
+  } else {
+    const double nrm = sqrt(cfg->crack_dx * cfg->crack_dx + cfg->crack_dy * cfg->crack_dy);
+    s->ux = cfg->crack_dx / nrm;
+    s->uy = cfg->crack_dy / nrm;
+    /* exact unit vectors along the axes */
+    if (cfg->crack_dx == 0.0) { s->ux = 0.0; s->uy = cfg->crack_dy > 0 ? 1.0 : -1.0; }
+    if (cfg->crack_dy == 0.0) { s->uy = 0.0; s->ux = cfg->crack_dx > 0 ? 1.0 : -1.0; }
+    s->a_hi = cfg->crack_x0 + exit_length(s, cfg->crack_x0, s->yc, s->ux, s->uy);
+    s->a_lo = cfg->crack_x0 - exit_length(s, cfg->crack_x0, s->yc, -s->ux, -s->uy);
+    if (cfg->has_crack && (cfg->crack_tip > s->a_hi || cfg->k_band != 1)) {
+      free(s->tau);
+      free(s->wD);
+      free(s);
+      if (err) *err = cfg->k_band != 1 ? -1 : -5;
+      return NULL;
+    }
+  }
 
   s->f = (double *)calloc(NPOP * n, sizeof(double));
   s->fn = (double *)calloc(NPOP * n, sizeof(double));
@@ -259,15 +319,34 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
           set_cut(s, &L);
       }
     /* B_prev: the pair of sites around the crack line at the tip column
-     * (the right tip's floor(a), the left tip's ceil(a)). */
+     * (the right tip's floor(a), the left tip's ceil(a)); for another
+     * direction the four sites of the lattice cell that holds the tip. */
     for (int t = 0; t < 2; ++t) {
       tip_t *T = &s->tips[t];
-      int c = t == 0 ? (int)floor(T->a) : (int)ceil(T->a);
-      if (c < 0) c = 0;
-      if (c > cfg->nx - 1) c = cfg->nx - 1;
-      T->bprev[0] = c; T->bprev[1] = s->j0;
-      T->bprev[2] = c; T->bprev[3] = s->j0 + 1;
-      T->nbprev = 2;
+      if (s->aligned) {
+        int c = t == 0 ? (int)floor(T->a) : (int)ceil(T->a);
+        if (c < 0) c = 0;
+        if (c > cfg->nx - 1) c = cfg->nx - 1;
+        T->bprev[0] = c; T->bprev[1] = s->j0;
+        T->bprev[2] = c; T->bprev[3] = s->j0 + 1;
+        T->nbprev = 2;
+      } else {
+        double x, y;
+        crack_point(s, T->a, &x, &y);
+        const int ci = (int)floor(x), cj = (int)floor(y);
+        T->nbprev = 0;
+        for (int dj = 0; dj <= 1; ++dj)
+          for (int di = 0; di <= 1; ++di) {
+            int pi = ci + di, pj = cj + dj;
+            if (pi < 0) pi = 0;
+            if (pi > cfg->nx - 1) pi = cfg->nx - 1;
+            if (pj < 0) pj = 0;
+            if (pj > cfg->ny - 1) pj = cfg->ny - 1;
+            T->bprev[2 * T->nbprev] = pi;
+            T->bprev[2 * T->nbprev + 1] = pj;
+            T->nbprev++;
+          }
+      }
     }
   }
 
@@ -397,7 +476,66 @@ double orc_sif(double delta, double r, double mu) {
  * band), the left tip at the mirrored column ceil(a + r_min) (and + 1, ...);
  * r is the horizontal distance from the tip.  The columns must lie on the
  * crack, i.e. between the two ends. */
+/* K at a tip of a crack along another direction than +x.  Along the line,
+ * the vertical links cross it at integer x and the horizontal ones at integer
+ * y; the pair of sites used is that of the first crossing at or beyond r_min
+ * behind the tip (for +x this is the column floor(a - r_min) of the rule
+ * above), delta the jump of w between the two sites and r the distance along
+ * the line from the tip to the projection of the pair's midpoint (for +x the
+ * midpoint lies on the line, at the crossing).  A crossing through a lattice
+ * site, off the crack or off the plate leaves K undefined. */
+static double evaluate_K_line(const orc_sim *s, const tip_t *T, double vK, int32_t *undef) {
+  const double x0 = s->cfg.crack_x0, yc = s->yc, ux = s->ux, uy = s->uy;
+  const double rmin = s->cfg.r0 / (1.0 - vK);
+  const double st = T->a - x0;                           /* the tip */
+  const double so = s->tips[T->dir > 0 ? 1 : 0].a - x0;  /* the crack's other end */
+  const double target = T->dir > 0 ? st - rmin : st + rmin;
+  *undef = 1;
+  /* candidate of each family: the crossing nearest to the target on the
+   * side away from the tip */
+  int have_v = 0, have_h = 0;
+  double sv = 0.0, sh = 0.0, iv = 0.0, jh = 0.0;
+  if (ux != 0.0) {
+    const double xt = x0 + target * ux;
+    iv = ((T->dir > 0) == (ux > 0)) ? floor(xt) : ceil(xt);
+    sv = (iv - x0) / ux;
+    have_v = 1;
+  }
+  if (uy != 0.0) {
+    const double yt = yc + target * uy;
+    jh = ((T->dir > 0) == (uy > 0)) ? floor(yt) : ceil(yt);
+    sh = (jh - yc) / uy;
+    have_h = 1;
+  }
+  int vertical;
+  if (have_v && have_h) vertical = T->dir > 0 ? (sv >= sh) : (sv <= sh);
+  else vertical = have_v;
+  const double sc = vertical ? sv : sh;
+  if (T->dir > 0 ? sc < so : sc > so) return NAN;  /* off the crack */
+  int i0, j0, i1, j1;
+  if (vertical) {
+    const double y = yc + sc * uy;
+    if (y == floor(y)) return NAN;  /* through a lattice site */
+    i0 = i1 = (int)iv;
+    j0 = (int)floor(y);
+    j1 = j0 + 1;
+  } else {
+    const double x = x0 + sc * ux;
+    if (x == floor(x)) return NAN;
+    j0 = j1 = (int)jh;
+    i0 = (int)floor(x);
+    i1 = i0 + 1;
+  }
+  if (i0 < 0 || i1 > s->cfg.nx - 1 || j0 < 0 || j1 > s->cfg.ny - 1) return NAN;
+  *undef = 0;
+  const double delta = fabs(s->w[IDX(s, i1, j1)] - s->w[IDX(s, i0, j0)]);
+  const double mx = 0.5 * (double)(i0 + i1), my = 0.5 * (double)(j0 + j1);
+  const double sm = (mx - x0) * ux + (my - yc) * uy;  /* projection of the midpoint */
+  return orc_sif(delta, T->dir > 0 ? st - sm : sm - st, s->cfg.mu);
+}
+
 static double evaluate_K(const orc_sim *s, const tip_t *T, double vK, int32_t *undef) {
+  if (!s->aligned) return evaluate_K_line(s, T, vK, undef);
   const int nx = s->cfg.nx;
   const double rmin = s->cfg.r0 / (1.0 - vK);
   const int band = s->cfg.k_band;
@@ -530,19 +668,18 @@ static int criterion(const orc_sim *s, const tip_t *T, double K, double *v) {
 /* Advance one tip by (v c_s) dt along its direction, find the intersected
  * links with CheckLinks and sever them (ProcessPoints). */
 static void advance(orc_sim *s, tip_t *T, double v, int32_t *flags) {
-  const orc_config *cfg = &s->cfg;
   const double a_prev = T->a;
   double a_new;
   if (T->dir > 0) {
     a_new = a_prev + (v * s->cs) * s->dt;
-    if (a_new >= cfg->nx - 0.5) {
-      a_new = cfg->nx - 0.5;
+    if (a_new >= s->a_hi) {
+      a_new = s->a_hi;
       *flags |= ORC_FLAG_WALL;
     }
   } else {
     a_new = a_prev - (v * s->cs) * s->dt;
-    if (a_new <= -0.5) {
-      a_new = -0.5;
+    if (a_new <= s->a_lo) {
+      a_new = s->a_lo;
       *flags |= ORC_FLAG_WALL;
     }
   }
@@ -743,9 +880,24 @@ void orc_check_links(const orc_sim *s_in, double a_prev, double a_new, int32_t b
                      int32_t cap) {
   orc_sim *s = (orc_sim *)s_in;
   link_t hits[64];
-  int32_t bp[4] = {b_col, s->j0, b_col, s->j0 + 1};
+  int32_t bp[8] = {b_col, s->j0, b_col, s->j0 + 1};
+  int32_t nbp = 2;
+  if (!s->aligned) {  /* the cell holding the point at a_prev */
+    double x, y;
+    crack_point(s, a_prev, &x, &y);
+    nbp = 0;
+    for (int dj = 0; dj <= 1; ++dj)
+      for (int di = 0; di <= 1; ++di) {
+        int pi = (int)floor(x) + di, pj = (int)floor(y) + dj;
+        pi = pi < 0 ? 0 : (pi > s->cfg.nx - 1 ? s->cfg.nx - 1 : pi);
+        pj = pj < 0 ? 0 : (pj > s->cfg.ny - 1 ? s->cfg.ny - 1 : pj);
+        bp[2 * nbp] = pi;
+        bp[2 * nbp + 1] = pj;
+        ++nbp;
+      }
+  }
   int32_t bout[128], nbout = 0;
-  int32_t nh = check_links_bfs(s, a_prev, a_new, bp, 2, hits, 64, bout, &nbout, 64);
+  int32_t nh = check_links_bfs(s, a_prev, a_new, bp, nbp, hits, 64, bout, &nbout, 64);
   *n_bfs = 0;
   for (int h = 0; h < nh && h < cap; ++h) {
     bfs_links[3 * h] = hits[h].i; bfs_links[3 * h + 1] = hits[h].j; bfs_links[3 * h + 2] = hits[h].o;

@@ -15,7 +15,12 @@
  *   walls lie half-way between the outer sites and the (absent) ghost sites;
  *   the crack runs along y_c = j0 + 1/2 (j0 = crack_row, default ny/2 - 1),
  *   from x = crack_x0 to the tip x = a, and grows in +x; with both_tips its
- *   left end is a second tip that grows in -x by the same rule.
+ *   left end is a second tip that grows in -x by the same rule.  With a
+ *   growth direction d = (crack_dx, crack_dy) other than +x (Alg. 1 takes the
+ *   direction as an input) the crack is the straight segment through
+ *   S = (crack_x0, y_c) along d: a tip at line coordinate a sits at
+ *   S + (a - crack_x0) d / |d| and advances in a; every link, vertical or
+ *   horizontal, that the closed segment touches is severed.
  *   An edge is traction-loaded (default: top +tau, bottom -tau, lateral 0) or,
  *   if its bit is set in `dirichlet`, holds a prescribed displacement w* at
  *   the wall by anti-bounce-back: f_in = -f^opp + 2 f_eq(w*, 0).
@@ -57,6 +62,8 @@ typedef struct {
   int32_t dirichlet;       /* ORC_EDGE_* bits of the edges with a prescribed w   */
   const double *wD_hist;   /* [n_wD][4] w* of (bottom, top, left, right); step n  */
   int64_t n_wD;            /* uses row min(n, n_wD - 1)                          */
+  double crack_dx, crack_dy; /* growth direction of the right tip; (0, 0) or     */
+                             /* (1, 0) = +x along the crack row                  */
 } orc_config;
 
 typedef struct orc_sim orc_sim;
@@ -88,8 +95,10 @@ int64_t orc_events(const orc_sim *s, int64_t *step, int32_t *i, int32_t *j, int3
  * Ak (lambda/(2 c^2)), traction coefficient dt/(rho dh). */
 void orc_constants(const orc_sim *s, double out[7]);
 
-/* CheckLinks for an arbitrary horizontal segment on the crack line, run from the
- * boundary pair at column b_col; writes the intersected links (i, j, orient)
+/* CheckLinks for the crack-line segment between line coordinates a_prev and
+ * a_new, run from the boundary points around the crack line at column b_col
+ * (a crack along +x) or, for another direction, the four sites of the cell
+ * holding the point at a_prev; writes the intersected links (i, j, orient)
  * found by the breadth-first search of Alg. 1 and by an exhaustive scan of every
  * link of the lattice.  Returns the counts through n_bfs / n_all. */
 void orc_check_links(const orc_sim *s, double a_prev, double a_new, int32_t b_col,

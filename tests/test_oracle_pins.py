@@ -774,3 +774,132 @@ def test_steady_strip_K_statistics(v):
     # steady: the second half of the sample has the same median as the first
     h = len(K) // 2
     assert abs(np.median(K[:h]) / np.median(K[h:]) - 1.0) < 0.03
+
+
+# ----------------------------------- a crack along another direction (Alg. 1) --
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_check_links_bfs_equals_exhaustive_scan_inclined(seed):
+    """CheckLinks' breadth-first search from the cell holding the segment's
+    start finds exactly the links an exhaustive scan finds, for segments of
+    random direction (vertical and horizontal links, through lattice points
+    too)."""
+    rng = np.random.default_rng(100 + seed)
+    nx, ny = 30, 26
+    for _ in range(40):
+        dx, dy = rng.normal(size=2)
+        if rng.random() < 0.2:
+            dx, dy = 1.0, 1.0  # 45 degrees, through lattice points
+        x0 = rng.uniform(3, 8)
+        s = make(nx=nx, ny=ny, has_crack=True, crack_row=8, crack_x0=x0, crack_tip=x0 + 0.1,
+                 crack_dx=dx, crack_dy=dy)
+        a0 = x0 + rng.uniform(0, 6)
+        a1 = a0 + rng.choice([rng.uniform(0, 0.5), rng.uniform(0, 2.5), 0.0])
+        bfs, allv = s.check_links(a0, a1, 0)
+        assert sorted(map(tuple, bfs)) == sorted(map(tuple, allv))
+        assert len(allv) <= 12
+
+
+def test_vertical_crack_equals_transposed_horizontal_crack():
+    """The D2Q5 lattice is symmetric under x <-> y: a crack growing in +y
+    (both tips, prescribed speed, Dirichlet walls on the edges parallel to it)
+    gives the transposed fields, tips, K traces and cut events (vertical links
+    become horizontal ones) of the crack growing in +x on the transposed
+    plate, within the rounding of the differently ordered sums."""
+    T, v = 160, 0.3571
+    rng = np.random.default_rng(7)
+    W0 = 1e-4 * rng.normal(size=(40, 70))
+    n = np.arange(T)
+    ramp = np.minimum(n / 40.0, 1.0)
+    wA = np.zeros((T, 4))
+    wA[:, 0], wA[:, 1] = -0.02 * ramp, 0.03 * ramp      # bottom, top
+    wB = np.zeros((T, 4))
+    wB[:, 2], wB[:, 3] = -0.02 * ramp, 0.03 * ramp      # left, right
+    A = make(nx=70, ny=40, has_crack=True, crack_row=17, crack_x0=20.5, crack_tip=35.5,
+             both_tips=True, growth=O.GROW_PRESCRIBED, v_rel=v, dirichlet=1 | 2, wD_hist=wA,
+             wdot0=W0, trace_cap=T)
+    # the same crack in the transposed plate: the line x = 17.5 from y = 20.5,
+    # tip at y = 35.5 (line coordinate 17.5 + 15)
+    B = make(nx=40, ny=70, has_crack=True, crack_row=20, crack_x0=17.5, crack_tip=32.5,
+             both_tips=True, growth=O.GROW_PRESCRIBED, v_rel=v, dirichlet=4 | 8, wD_hist=wB,
+             wdot0=W0.T.copy(), trace_cap=T, crack_dx=0.0, crack_dy=1.0)
+    mvA, mhA = A.mask()
+    mvB, mhB = B.mask()
+    np.testing.assert_array_equal(mvA, mhB.T)
+    np.testing.assert_array_equal(mhA, mvB.T)
+    A.step(T)
+    B.step(T)
+    wa, wb = A.fields()[0], B.fields()[0]
+    assert np.abs(wb.T - wa).max() <= 1e-13 * np.abs(wa).max()
+    for tip in ("right", "left"):
+        ta, tb = A.traces(tip), B.traces(tip)
+        # tip positions: x of A against y = 20.5 + (a - 17.5) of B
+        np.testing.assert_allclose(20.5 + (tb["tip"] - 17.5), ta["tip"], rtol=0, atol=1e-12)
+        ok = ~np.isnan(ta["K"])
+        assert ok.sum() > T // 2 and np.array_equal(ok, ~np.isnan(tb["K"]))
+        assert np.abs(tb["K"][ok] - ta["K"][ok]).max() <= 1e-11 * np.abs(ta["K"][ok]).max()
+    ea = sorted((int(e[0]), int(e[1]), int(e[2]), int(e[3])) for e in A.events())
+    eb = sorted((int(e[0]), int(e[2]), int(e[1]), 1 - int(e[3])) for e in B.events())
+    assert len(ea) > 10 and ea == eb
+
+
+def test_inclined_crack_K_from_the_near_tip_field():
+    """Cracks at 10 .. 80 degrees: with the asymptotic field of eq.
+    (nearTipDisplacement) written around the tip in the crack's own polar
+    coordinates, the pair of sites across the first link that crosses the
+    line at or beyond r_min, with r measured to the projection of the pair's
+    midpoint, returns K within 3 % (the sites sit off phi = +-pi); measuring r
+    to the crossing itself instead errs by up to 11 %."""
+    nx, ny, mu, K = 70, 60, 1.5, 0.05
+    for deg, L0 in [(10, 18.0), (30, 23.7), (30, 27.2), (45, 21.1), (60, 19.4), (80, 25.3)]:
+        th = math.radians(deg)
+        ux, uy = math.cos(th), math.sin(th)
+        x0, yc = 10.3, 12.5
+        s = make(nx=nx, ny=ny, has_crack=True, crack_row=12, crack_x0=x0, crack_tip=x0 + L0,
+                 mu=mu, r0=2.0, crack_dx=ux, crack_dy=uy)
+        tx, ty = x0 + L0 * ux, yc + L0 * uy
+        jj, ii = np.mgrid[0:ny, 0:nx]
+        px, py = ii - tx, jj - ty
+        xl = px * ux + py * uy        # along the crack (ahead of the tip > 0)
+        yl = -px * uy + py * ux       # across it
+        r = np.hypot(xl, yl)
+        phi = np.arctan2(yl, xl)
+        w = 2 * K / mu * np.sqrt(r / (2 * math.pi)) * np.sin(phi / 2)
+        s.set_state(np.zeros((5, ny, nx)), w)
+        assert s.eval_K(0.0) == pytest.approx(K, rel=0.03)
+        # scaling the field scales K; a uniform offset leaves it unchanged
+        s.set_state(np.zeros((5, ny, nx)), 3.0 * w + 0.7)
+        assert s.eval_K(0.0) == pytest.approx(3.0 * K, rel=0.03)
+
+
+@pytest.mark.parametrize("dx,dy", [(0.92, 0.39), (-0.3, 1.0), (0.6, -0.8)])
+def test_inclined_growth_cuts_the_links_of_the_final_segment(dx, dy):
+    """A crack with two tips growing along a fixed direction at a prescribed
+    speed: the links severed step by step by CheckLinks are exactly those the
+    whole final segment touches (the union of the masks of two fresh cracks
+    from the start point to either final tip), and each tip advances by
+    (v c_s) dt per step until it reaches the plate's edge, where it stops with
+    the wall flag."""
+    T, v = 260, 0.45
+    x0, row = 20.3, 19
+    kw = dict(nx=48, ny=40, has_crack=True, crack_row=row, crack_x0=x0,
+              tau_hist=np.array([1e-3]))
+    s = make(crack_tip=24.0, growth=O.GROW_PRESCRIBED, v_rel=v, trace_cap=T, both_tips=True,
+             crack_dx=dx, crack_dy=dy, **kw)
+    s.step(T)
+    tr, tl = s.traces(), s.traces("left")
+    a_r, a_l = tr["tip"][-1], tl["tip"][-1]
+    assert tr["flags"][-1] & O.FLAG_WALL and tl["flags"][-1] & O.FLAG_WALL
+    n = np.arange(T)
+    free = (tr["flags"] & O.FLAG_WALL) == 0
+    np.testing.assert_allclose(tr["tip"][free], 24.0 + (n[free] + 1) * v * 0.5, rtol=0, atol=1e-9)
+    # fresh cracks from the start point: forward to the right tip, and along
+    # the opposite direction to the left tip
+    fwd = make(crack_tip=a_r, crack_dx=dx, crack_dy=dy, **kw)
+    bwd = make(crack_tip=x0 + (x0 - a_l), crack_dx=-dx, crack_dy=-dy, **kw)
+    mv, mh = s.mask()
+    fv, fh = fwd.mask()
+    bv, bh = bwd.mask()
+    np.testing.assert_array_equal(mv, fv | bv)
+    np.testing.assert_array_equal(mh, fh | bh)
+    assert mv.sum() + mh.sum() > 40
