@@ -130,6 +130,14 @@ typedef struct lbm_config {
   const double *wD_hist;   /* host [n_wD][4]: w* of (bottom, top, left, right);  */
   int64_t n_wD;            /* step n uses row min(n, n_wD - 1); copied           */
   int32_t layout;          /* enum lbm_layout                                    */
+  double crack_dx, crack_dy; /* growth direction of the (right) tip, Alg. 1's   */
+                           /* input d: (0, 0) or (1, 0) = +x along crack_row;     */
+                           /* otherwise the crack is the straight segment through */
+                           /* S = (crack_x0, crack_row + 1/2) along d, the tips   */
+                           /* given by line coordinates a (the point              */
+                           /* S + (a - crack_x0) d/|d|), every vertical or        */
+                           /* horizontal link it touches severed; k_band = 1,     */
+                           /* walls only, no adjoint                             */
   void *dev_buf;           /* device memory, >= lbm_state_bytes(cfg), 256-aligned */
   size_t dev_bytes;
   void *stream;            /* hipStream_t; NULL = the null stream                */
@@ -192,6 +200,14 @@ int lbm_sensor_traces(lbm_handle *h, double *out, int64_t first, int64_t count,
 /* Cut events: (step, column) of every link severed by growth, in order;
  * writes min(cap, total) entries and the total into *n. */
 int lbm_cut_events(lbm_handle *h, int64_t *steps, int32_t *cols, int64_t cap, int64_t *n);
+
+/* Cut events with the severed link itself (Alg. 1, ProcessPoints): step,
+ * site (i, j) and orientation (0: vertical link (i,j)-(i,j+1), 1: horizontal
+ * link (i,j)-(i+1,j)); a crack along +x severs vertical links of its row only.
+ * Any output pointer may be NULL; writes min(cap, total) entries and the total
+ * into *n. */
+int lbm_cut_links(lbm_handle *h, int64_t *steps, int32_t *i, int32_t *j, int32_t *orient,
+                  int64_t cap, int64_t *n);
 
 /* Host FP64 snapshot of w and wdot = sum_alpha f^alpha (either may be NULL). */
 int lbm_get_fields(lbm_handle *h, double *w_out, double *wdot_out);

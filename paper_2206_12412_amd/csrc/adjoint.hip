@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(256) adj_step(const AdjArgs<C> a, const core::
   const unsigned nbb = (unsigned)(bm.nb * a.n_parts);
   if (blockIdx.x < nbb) {
     const int r = blockIdx.x / a.n_parts;
-    adj_boundary_site<C, EQ>(a, r, bm.brow[r], blockIdx.x % a.n_parts, red);
+    adj_boundary_site<C, EQ>(a, r, core::boundary_row_of(bm, r), blockIdx.x % a.n_parts, red);
     return;
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "crack_geom.hpp"
 #include "lbm.h"
 #include "lbm_internal.hpp"
 
@@ -48,7 +49,7 @@ struct Layout {
   size_t off_mV = 0, off_mH = 0, off_rf = 0, off_crack = 0;
   size_t off_trK = 0, off_trA = 0, off_trV = 0, off_trF = 0;
   size_t off_trKL = 0, off_trAL = 0, off_trVL = 0, off_trFL = 0;
-  size_t off_evS = 0, off_evC = 0, off_stage = 0;
+  size_t off_evS = 0, off_evC = 0, off_evJ = 0, off_evO = 0, off_stage = 0;
   size_t off_sens = 0, off_trS = 0;
   int64_t event_cap = 0;
   int stage_rows = 0;
@@ -113,9 +114,12 @@ Layout make_layout(const lbm_config &c, Store s) {
   L.off_trAL = o; o += align_up(tl * 8, 256);
   L.off_trVL = o; o += align_up(tl * 8, 256);
   L.off_trFL = o; o += align_up(tl * 4, 256);
-  L.event_cap = (int64_t)c.nx + 8;
+  // a straight crack severs at most one link per lattice line it crosses
+  L.event_cap = 2 * ((int64_t)c.nx + c.ny) + 16;
   L.off_evS = o; o += align_up((size_t)L.event_cap * 8, 256);
   L.off_evC = o; o += align_up((size_t)L.event_cap * 4, 256);
+  L.off_evJ = o; o += align_up((size_t)L.event_cap * 4, 256);
+  L.off_evO = o; o += align_up((size_t)L.event_cap * 4, 256);
   L.off_sens = o; o += align_up((size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.off_trS = o; o += align_up(tc * (size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.stage_rows = (int)std::max<int64_t>(1, std::min<int64_t>(c.ny, (1 << 20) / std::max(1, c.nx)));
@@ -123,6 +127,36 @@ Layout make_layout(const lbm_config &c, Store s) {
   o += align_up((size_t)5 * L.stage_rows * c.nx * 8, 256);
   L.total = o;
   return L;
+}
+
+// The crack line of a configuration: start point, unit growth direction
+// (exact along the axes) and the line coordinates where the line leaves the
+// plate (the walls the tips stop at).
+void crack_line(const lbm_config &c, lbmk::geom::Line *L, double *a_lo, double *a_hi) {
+  const int j0 = c.crack_row >= 0 ? c.crack_row : c.ny / 2 - 1;
+  L->x0 = c.crack_x0;
+  L->yc = j0 + 0.5;
+  L->aligned = (c.crack_dy == 0.0 && c.crack_dx >= 0.0);
+  if (L->aligned) {
+    L->ux = 1.0;
+    L->uy = 0.0;
+    *a_lo = -0.5;
+    *a_hi = c.nx - 0.5;
+    return;
+  }
+  const double n = std::sqrt(c.crack_dx * c.crack_dx + c.crack_dy * c.crack_dy);
+  L->ux = c.crack_dx / n;
+  L->uy = c.crack_dy / n;
+  if (c.crack_dx == 0.0) {
+    L->ux = 0.0;
+    L->uy = c.crack_dy > 0 ? 1.0 : -1.0;
+  }
+  if (c.crack_dy == 0.0) {
+    L->uy = 0.0;
+    L->ux = c.crack_dx > 0 ? 1.0 : -1.0;
+  }
+  *a_hi = L->x0 + lbmk::geom::wall_distance(c.nx, c.ny, L->x0, L->yc, L->ux, L->uy);
+  *a_lo = L->x0 - lbmk::geom::wall_distance(c.nx, c.ny, L->x0, L->yc, -L->ux, -L->uy);
 }
 
 int validate(const lbm_config *c, Store *s) {
@@ -154,8 +188,21 @@ int validate(const lbm_config *c, Store *s) {
     if (c->crack_row < 0 && (c->ny < 2 || c->ny % 2))
       return fail(LBM_EINVAL, "a crack on the mid-line needs an even ny >= 2");
     if (c->crack_row > c->ny - 2) return fail(LBM_EINVAL, "crack_row must be in 0..ny-2");
-    if (!(c->crack_x0 >= -0.5) || !(c->crack_tip >= c->crack_x0) || !(c->crack_tip <= c->nx - 0.5))
+    if (!std::isfinite(c->crack_dx) || !std::isfinite(c->crack_dy))
+      return fail(LBM_EINVAL, "bad crack direction");
+    const bool aligned = c->crack_dy == 0.0 && c->crack_dx >= 0.0;
+    if (!(c->crack_x0 >= -0.5) || !(c->crack_x0 <= c->nx - 0.5) || !(c->crack_tip >= c->crack_x0) ||
+        (aligned && !(c->crack_tip <= c->nx - 0.5)))
       return fail(LBM_ECRACK, "crack [%g, %g] not inside [-0.5, %g]", c->crack_x0, c->crack_tip, c->nx - 0.5);
+    if (!aligned) {
+      lbmk::geom::Line L;
+      double a_lo, a_hi;
+      crack_line(*c, &L, &a_lo, &a_hi);
+      if (!(c->crack_tip <= a_hi))
+        return fail(LBM_ECRACK, "crack tip %g beyond the plate (line coordinate <= %g)", c->crack_tip, a_hi);
+      if (c->k_band != 1) return fail(LBM_EINVAL, "a crack along another direction than +x needs k_band = 1");
+      if (c->bc_mode == LBM_BC_PERIODIC) return fail(LBM_EINVAL, "a crack along another direction needs walls");
+    }
     if (!(c->r0 > 0)) return fail(LBM_EINVAL, "r0 must be positive");
     if (c->k_band < 1 || c->k_band > 64) return fail(LBM_EINVAL, "k_band must be in 1..64");
   }
@@ -227,6 +274,10 @@ struct lbm_handle {
   // that FP32 cannot hold) are streamed and both buffers are cleared.
   bool eq = false;
   int full_steps = 0;
+  // crack line, wall limits of the tips and the rows a crack can touch
+  lbmk::geom::Line line{1, 0.0, 0.0, 1.0, 0.0};
+  double a_lo = -0.5, a_hi = 0.0;
+  int skip_lo = 1, skip_hi = 0;
   std::vector<int32_t> sensors;  // host copy of the sensor sites
   std::vector<double> wD;        // host copy of the wall-displacement history [n][4]
 
@@ -306,15 +357,9 @@ int launch_sweep_typed(lbm_handle *h) {
     const int groups = std::max(1, (h->occ * 4) / h->waves);
     a.lds_bytes = std::min(65536, (h->lds_per_cu / groups) / 256 * 256);
   }
-  // links can be severed only on the crack row j0 (vertical links between
-  // rows j0 and j0 + 1): those two rows go to the boundary kernel
-  if (h->cfg.has_crack) {
-    a.skip_lo = h->plate.j0;
-    a.skip_hi = h->plate.j0 + 1;
-  } else {
-    a.skip_lo = 1;
-    a.skip_hi = 0;
-  }
+  // the rows a crack can touch go to the boundary work
+  a.skip_lo = h->skip_lo;
+  a.skip_hi = h->skip_hi;
   a.sr = h->cfg.rounding == LBM_ROUND_STOCHASTIC;
   a.rkey = lbmk::step_key(h->cfg.seed, h->step);
   a.dmask = per ? 0 : h->cfg.dirichlet;
@@ -349,6 +394,7 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
   a.w = h->wbuf(1 - h->cur);  // w after the sweep just enqueued
   a.w_is_double = is_fp64(h->store);
   a.mV = h->mV();
+  a.mH = h->mH();
   a.mrows = h->mrows();
   a.trK = reinterpret_cast<double *>(h->base + h->L.off_trK);
   a.trA = reinterpret_cast<double *>(h->base + h->L.off_trA);
@@ -360,6 +406,8 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
   a.trFL = reinterpret_cast<int32_t *>(h->base + h->L.off_trFL);
   a.evStep = reinterpret_cast<int64_t *>(h->base + h->L.off_evS);
   a.evCol = reinterpret_cast<int32_t *>(h->base + h->L.off_evC);
+  a.evRow = reinterpret_cast<int32_t *>(h->base + h->L.off_evJ);
+  a.evOri = reinterpret_cast<int32_t *>(h->base + h->L.off_evO);
   a.sens = reinterpret_cast<const int32_t *>(h->base + h->L.off_sens);
   a.trS = reinterpret_cast<double *>(h->base + h->L.off_trS);
   a.n_sens = h->cfg.n_sensors;
@@ -376,6 +424,12 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
   a.c.dt = h->dt;
   a.c.mu = h->cfg.mu;
   a.c.x0 = h->cfg.crack_x0;
+  a.c.aligned = h->line.aligned;
+  a.c.yc = h->line.yc;
+  a.c.ux = h->line.ux;
+  a.c.uy = h->line.uy;
+  a.c.a_lo = h->a_lo;
+  a.c.a_hi = h->a_hi;
   a.c.trace_cap = h->cfg.trace_cap;
   a.c.event_cap = h->L.event_cap;
   return a;
@@ -563,9 +617,67 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
       return bail(fail(LBM_EHIP, "init kernel failed"));
     if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(LBM_EHIP, "init sync failed"));
   }
-  if (lbmk::launch_init_mask(h->mV(), h->mH(), h->mrows(), p, cfg->has_crack, cfg->crack_x0,
-                             cfg->crack_tip, st) != hipSuccess)
+  crack_line(*cfg, &h->line, &h->a_lo, &h->a_hi);
+  int64_t n_cut0 = 0;
+  if (!cfg->has_crack) {
+    h->skip_lo = 1;
+    h->skip_hi = 0;
+  } else if (h->line.aligned) {
+    // links can be severed only on the crack row j0 (vertical links between
+    // rows j0 and j0 + 1)
+    h->skip_lo = p.j0;
+    h->skip_hi = p.j0 + 1;
+  } else {
+    // every row within reach of the line between the ends the tips can reach
+    const double e0 = cfg->both_tips ? h->a_lo : cfg->crack_x0;
+    const double e1 = cfg->growth != LBM_GROW_NONE ? h->a_hi : cfg->crack_tip;
+    double x, y0, y1;
+    lbmk::geom::point_at(h->line, e0, &x, &y0);
+    lbmk::geom::point_at(h->line, e1, &x, &y1);
+    h->skip_lo = std::max(0, (int)std::ceil(std::fmin(y0, y1)) - 1);
+    h->skip_hi = std::min(cfg->ny - 1, (int)std::floor(std::fmax(y0, y1)) + 1);
+  }
+  if (lbmk::launch_init_mask(h->mV(), h->mH(), h->mrows(), p,
+                             cfg->has_crack && h->line.aligned, cfg->crack_x0, cfg->crack_tip,
+                             st) != hipSuccess)
     return bail(fail(LBM_EHIP, "mask init failed"));
+  if (cfg->has_crack && !h->line.aligned) {
+    // the initial crack along another direction: every link the segment
+    // x0 .. a0 touches (Alg. 1, "as for the initial crack"), set on the host
+    const int rows = p.ny, mw = p.mw;
+    std::vector<uint32_t> mv((size_t)rows * mw, 0u), mhv((size_t)rows * mw, 0u);
+    lbmk::MaskRows mr{1, 0, 1, 0};
+    double xa, ya, xb, yb;
+    lbmk::geom::point_at(h->line, cfg->crack_x0, &xa, &ya);
+    lbmk::geom::point_at(h->line, cfg->crack_tip, &xb, &yb);
+    const int ilo = std::max(0, (int)std::floor(std::fmin(xa, xb)) - 1);
+    const int ihi = std::min(p.nx - 1, (int)std::ceil(std::fmax(xa, xb)) + 1);
+    const int jlo = std::max(0, (int)std::floor(std::fmin(ya, yb)) - 1);
+    const int jhi = std::min(p.ny - 1, (int)std::ceil(std::fmax(ya, yb)) + 1);
+    for (int j = jlo; j <= jhi; ++j)
+      for (int i = ilo; i <= ihi; ++i) {
+        if (j + 1 < p.ny && lbmk::geom::touches_link(h->line, cfg->crack_x0, cfg->crack_tip, i, j, 0, 1)) {
+          mv[(size_t)j * mw + (i >> 5)] |= 1u << (i & 31);
+          mr.vlo = mr.vlo > mr.vhi ? j : std::min(mr.vlo, j);
+          mr.vhi = std::max(mr.vhi, j);
+          ++n_cut0;
+        }
+        if (i + 1 < p.nx && lbmk::geom::touches_link(h->line, cfg->crack_x0, cfg->crack_tip, i, j, 1, 0)) {
+          mhv[(size_t)j * mw + (i >> 5)] |= 1u << (i & 31);
+          mr.hlo = mr.hlo > mr.hhi ? j : std::min(mr.hlo, j);
+          mr.hhi = std::max(mr.hhi, j);
+          ++n_cut0;
+        }
+      }
+    const size_t off = (size_t)jlo * mw * 4, len = (size_t)(jhi - jlo + 1) * mw * 4;
+    if (hipMemcpyAsync(reinterpret_cast<char *>(h->mV()) + off, mv.data() + (size_t)jlo * mw, len,
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(reinterpret_cast<char *>(h->mH()) + off, mhv.data() + (size_t)jlo * mw, len,
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->mrows(), &mr, sizeof mr, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return bail(fail(LBM_EHIP, "upload of the initial crack failed"));
+  }
   lbmk::DevCrack &c0 = h->host_crack;
   c0 = lbmk::DevCrack{};
   c0.tip = cfg->has_crack ? cfg->crack_tip : 0.0;
@@ -582,10 +694,12 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   c0.rL = std::nan("");
   c0.flagsL = 0;
   c0.col_KL = -1;
-  if (cfg->has_crack) {
+  if (cfg->has_crack && h->line.aligned) {
     const int lo = std::max(0, (int)std::ceil(cfg->crack_x0));
     const int hi = std::min(cfg->nx - 1, (int)std::floor(cfg->crack_tip));
     c0.n_cut = hi >= lo ? hi - lo + 1 : 0;
+  } else if (cfg->has_crack) {
+    c0.n_cut = (int32_t)n_cut0;
   }
   if (hipMemcpyAsync(h->crack(), &c0, sizeof c0, hipMemcpyHostToDevice, st) != hipSuccess)
     return bail(fail(LBM_EHIP, "crack state upload failed"));
@@ -719,6 +833,24 @@ int lbm_sensor_traces(lbm_handle *h, double *out, int64_t first, int64_t count,
                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                          h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_cut_links(lbm_handle *h, int64_t *steps, int32_t *i_out, int32_t *j_out, int32_t *orient,
+                  int64_t cap, int64_t *n) {
+  if (!h || !n) return fail(LBM_EINVAL, "null argument");
+  lbmk::DevCrack c{};
+  HIP_TRY(hipMemcpyAsync(&c, h->crack(), sizeof c, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const int64_t total = c.n_events;
+  const int64_t m = std::min<int64_t>(std::min<int64_t>(total, cap), h->L.event_cap);
+  const hipStream_t st = h->stream;
+  if (m > 0 && steps) HIP_TRY(hipMemcpyAsync(steps, h->base + h->L.off_evS, m * 8, hipMemcpyDeviceToHost, st));
+  if (m > 0 && i_out) HIP_TRY(hipMemcpyAsync(i_out, h->base + h->L.off_evC, m * 4, hipMemcpyDeviceToHost, st));
+  if (m > 0 && j_out) HIP_TRY(hipMemcpyAsync(j_out, h->base + h->L.off_evJ, m * 4, hipMemcpyDeviceToHost, st));
+  if (m > 0 && orient) HIP_TRY(hipMemcpyAsync(orient, h->base + h->L.off_evO, m * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *n = total;
   return LBM_OK;
 }
 
@@ -1044,33 +1176,15 @@ int batch_build_desc(lbm_batch *b) {
     d.dmask = h->cfg.bc_mode == LBM_BC_PERIODIC ? 0 : h->cfg.dirichlet;
     d.wD = reinterpret_cast<const double *>(b->base + b->off_tau_plate[k] + wd_offset(h->cfg));
     d.n_wD = (int64_t)h->wD.size() / 4;
-    d.skip_lo = h->cfg.has_crack ? h->plate.j0 : 1;
-    d.skip_hi = h->cfg.has_crack ? h->plate.j0 + 1 : 0;
-    // the same task maps as the single-plate kernels (sweep_core.hpp)
-    const int sw = 64 * vec;
-    d.n_strips = (h->plate.nx + sw - 1) / sw;
-    d.rows = b->rows;
-    const bool has_skip = d.skip_lo <= d.skip_hi;
-    d.lo1 = 1;
-    d.hi1 = has_skip ? d.skip_lo - 1 : h->plate.ny - 2;
-    d.lo2 = has_skip ? d.skip_hi + 1 : h->plate.ny;
-    d.hi2 = h->plate.ny - 2;
-    d.nc1 = d.hi1 >= d.lo1 ? (d.hi1 - d.lo1 + d.rows) / d.rows : 0;
-    d.nc2 = d.hi2 >= d.lo2 ? (d.hi2 - d.lo2 + d.rows) / d.rows : 0;
-    d.nb = 0;
-    auto add = [&](int j) {
-      if (j < 0 || j >= h->plate.ny) return;
-      for (int q = 0; q < d.nb; ++q)
-        if (d.brow[q] == j) return;
-      d.brow[d.nb++] = j;
-    };
-    add(0);
-    add(h->plate.ny - 1);
-    for (int j = d.skip_lo; j <= d.skip_hi && d.nb < 4; ++j) add(j);
+    d.skip_lo = h->skip_lo;
+    d.skip_hi = h->skip_hi;
+    // the same task maps as the single-plate kernels
+    d.im = lbmk::core::interior_map(h->plate.nx, h->plate.ny, vec, b->rows, d.skip_lo, d.skip_hi);
+    d.bm = lbmk::core::boundary_map(h->plate.nx, h->plate.ny, vec, d.skip_lo, d.skip_hi);
     d.itask0 = ti;
     d.btask0 = tb;
-    ti += (int64_t)d.n_strips * (d.nc1 + d.nc2);
-    tb += (int64_t)d.n_strips * d.nb;
+    ti += lbmk::core::interior_task_count(d.im);
+    tb += lbmk::core::boundary_task_count(d.bm);
     d.crack = crack_args(h);
   }
   b->n_int = ti;
@@ -1421,6 +1535,8 @@ int lbm_adjoint_init(lbm_handle *h, void *dev_buf, size_t dev_bytes, lbm_adjoint
   if (!dev_buf || reinterpret_cast<uintptr_t>(dev_buf) % 256)
     return fail(LBM_EINVAL, "dev_buf must be a 256-byte aligned device pointer");
   if (dev_bytes < A.total) return fail(LBM_ENOMEM, "dev_bytes %zu < required %zu", dev_bytes, A.total);
+  if (h->cfg.has_crack && !h->line.aligned)
+    return fail(LBM_EINVAL, "the adjoint takes cracks along +x only (the cut steps are kept per column)");
   lbm_adjoint *a = new lbm_adjoint();
   a->h = h;
   a->fp64 = is_fp64(h->store);

@@ -53,7 +53,7 @@ __device__ __forceinline__ SweepArgs<S, W, C> args_of(const BatchPlate &d, int c
   a.t_bot = d.p.periodic ? C(0) : (C)(d.coef * -tau);
   a.t_up = d.p.periodic ? C(0) : (C)(d.coef * d.face);
   a.t_lo = d.p.periodic ? C(0) : (C)(d.coef * -d.face);
-  a.rows = d.rows;
+  a.rows = d.im.rows;
   a.waves = 4;
   a.lds_bytes = 0;
   a.skip_lo = d.skip_lo;
@@ -79,15 +79,16 @@ __device__ __forceinline__ void interior_task(const BatchPlate *__restrict__ d, 
   const int k = plate_of(d, n, task, true);
   const BatchPlate &q = d[k];
   const int64_t local = task - q.itask0;
-  const int strip = (int)(local % q.n_strips);
-  const int chunk = (int)(local / q.n_strips);
+  const core::InteriorMap &m = q.im;
+  const int strip = (int)(local % m.n_strips);
+  const int chunk = (int)(local / m.n_strips);
   int jb, jlast;
-  if (chunk < q.nc1) {
-    jb = q.lo1 + chunk * q.rows;
-    jlast = min(jb + q.rows - 1, q.hi1);
+  if (chunk < m.nc1) {
+    jb = m.lo1 + chunk * m.rows;
+    jlast = min(jb + m.rows - 1, m.hi1);
   } else {
-    jb = q.lo2 + (chunk - q.nc1) * q.rows;
-    jlast = min(jb + q.rows - 1, q.hi2);
+    jb = m.lo2 + (chunk - m.nc1) * m.rows;
+    jlast = min(jb + m.rows - 1, m.hi2);
   }
   if (jb > jlast) return;
   const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
@@ -100,9 +101,9 @@ __device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, 
   const int k = plate_of(d, n, task, false);
   const BatchPlate &q = d[k];
   const int64_t local = task - q.btask0;
-  const int strip = (int)(local % q.n_strips);
-  const int r = (int)(local / q.n_strips);
-  const int j = q.brow[r];
+  const int strip = (int)(local % q.bm.n_strips);
+  const int r = (int)(local / q.bm.n_strips);
+  const int j = core::boundary_row_of(q.bm, r);
   const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
   core::boundary_row<S, W, C, VEC, SHIFT, SR, EQ>(a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a,
                                          strip, j);

@@ -17,10 +17,17 @@
 // ceil(a + r_min), new columns in [a_new, a_prev)).  The same wavefront records
 // w at the sensor sites (also on plates without a crack, where it does nothing
 // else).
+//
+// A crack along another prescribed direction (crack_geom.hpp) takes K from the
+// first link that crosses its line at or beyond r_min behind the tip (r to the
+// projection of the two sites' midpoint), and severs every vertical or
+// horizontal link that the new segment touches, found by testing the links
+// around it (the segment is at most dh / kappa long).
 #pragma once
 
 #include <cmath>
 
+#include "crack_geom.hpp"
 #include "lbm_internal.hpp"
 
 namespace lbmk {
@@ -48,12 +55,74 @@ __device__ __forceinline__ double wave_sum(double x) {
 // evaluated at i_K = floor(a - r_min) (band: i_K, i_K - 1, ...); dir = -1: the
 // left tip, at the mirrored i_K = ceil(a + r_min) (band: i_K, i_K + 1, ...).
 // The columns must lie on the crack, between the tip and the other end.
+// K at one tip of a crack along another direction than +x: the first link
+// crossing the line at or beyond r_min behind the tip (vertical links cross it
+// at integer x, horizontal ones at integer y), delta the jump of w across it,
+// r the distance along the line from the tip to the projection of the link's
+// midpoint.  Undefined (NaN) when the crossing goes through a lattice site,
+// lies off the crack or off the plate.  *iK_out is the link's column.
+__device__ __forceinline__ double tip_K_line(const CrackArgs &a, int dir, double tip, double vK,
+                                            double other, double *r_out, int *iK_out,
+                                            bool *defined_out) {
+#pragma clang fp contract(off)
+  const Plate p = a.p;
+  const CrackParams q = a.c;
+  const double rmin = q.r0 / (1.0 - vK);
+  const double st = tip - q.x0;
+  const double so = other - q.x0;
+  const double target = dir > 0 ? st - rmin : st + rmin;
+  *r_out = __builtin_nan("");
+  *iK_out = -1;
+  *defined_out = false;
+  bool have_v = false, have_h = false;
+  double sv = 0.0, sh = 0.0, iv = 0.0, jh = 0.0;
+  if (q.ux != 0.0) {
+    const double xt = q.x0 + target * q.ux;
+    iv = ((dir > 0) == (q.ux > 0)) ? floor(xt) : ceil(xt);
+    sv = (iv - q.x0) / q.ux;
+    have_v = true;
+  }
+  if (q.uy != 0.0) {
+    const double yt = q.yc + target * q.uy;
+    jh = ((dir > 0) == (q.uy > 0)) ? floor(yt) : ceil(yt);
+    sh = (jh - q.yc) / q.uy;
+    have_h = true;
+  }
+  const bool vertical = (have_v && have_h) ? (dir > 0 ? sv >= sh : sv <= sh) : have_v;
+  const double sc = vertical ? sv : sh;
+  if (dir > 0 ? sc < so : sc > so) return __builtin_nan("");
+  int i0, j0, i1, j1;
+  if (vertical) {
+    const double y = q.yc + sc * q.uy;
+    if (y == floor(y)) return __builtin_nan("");
+    i0 = i1 = (int)iv;
+    j0 = (int)floor(y);
+    j1 = j0 + 1;
+  } else {
+    const double x = q.x0 + sc * q.ux;
+    if (x == floor(x)) return __builtin_nan("");
+    j0 = j1 = (int)jh;
+    i0 = (int)floor(x);
+    i1 = i0 + 1;
+  }
+  if (i0 < 0 || i1 > p.nx - 1 || j0 < 0 || j1 > p.ny - 1) return __builtin_nan("");
+  const double delta = fabs(w_at(a, i1, j1) - w_at(a, i0, j0));
+  const double mx = 0.5 * (double)(i0 + i1), my = 0.5 * (double)(j0 + j1);
+  const double sm = (mx - q.x0) * q.ux + (my - q.yc) * q.uy;
+  const double r = dir > 0 ? st - sm : sm - st;
+  *r_out = r;
+  *iK_out = i0;
+  *defined_out = true;
+  return delta * (q.mu / 4.0) * sqrt(2.0 * kPi / r);
+}
+
 __device__ __forceinline__ double tip_K(const CrackArgs &a, int dir, double tip, double vK,
                                        double other, int lane, double *r_out, int *iK_out,
                                        bool *defined_out) {
 #pragma clang fp contract(off)
   const Plate p = a.p;
   const CrackParams q = a.c;
+  if (!q.aligned) return tip_K_line(a, dir, tip, vK, other, r_out, iK_out, defined_out);
   const int band = q.band;
   const double rmin = q.r0 / (1.0 - vK);
   double iKf;
@@ -130,12 +199,64 @@ __device__ __forceinline__ bool cut_columns(const CrackArgs &a, DevCrack &c, int
       if (c.n_events < a.c.event_cap) {
         a.evStep[c.n_events] = n;
         a.evCol[c.n_events] = i;
+        a.evRow[c.n_events] = p.j0;
+        a.evOri[c.n_events] = 0;
       }
       c.n_events++;
       c.n_cut++;
       any = true;
     }
   }
+  return any;
+}
+
+// Sever the links that the crack between line coordinates a0 and a1 touches
+// (a crack along another direction than +x), recording them as cut events
+// of step n and widening the mask-row range.  The segment is short, so the
+// candidates are the links within its bounding box: vertical links at the
+// integer x inside it, horizontal links at the integer y inside it.
+__device__ __forceinline__ bool cut_segment(const CrackArgs &a, DevCrack &c, MaskRows &mr,
+                                            double a0, double a1, int64_t n) {
+  const Plate p = a.p;
+  const geom::Line L{a.c.aligned, a.c.x0, a.c.yc, a.c.ux, a.c.uy};
+  double x0, y0, x1, y1;
+  geom::point_at(L, a0, &x0, &y0);
+  geom::point_at(L, a1, &x1, &y1);
+  const double xlo = fmin(x0, x1), xhi = fmax(x0, x1), ylo = fmin(y0, y1), yhi = fmax(y0, y1);
+  bool any = false;
+  auto cut = [&](int i, int j, int o) {
+    uint32_t *m = (o == 0 ? a.mV : a.mH) + (size_t)j * p.mw;
+    const uint32_t bit = 1u << (i & 31);
+    const uint32_t word = m[i >> 5];
+    if (word & bit) return;
+    m[i >> 5] = word | bit;
+    if (c.n_events < a.c.event_cap) {
+      a.evStep[c.n_events] = n;
+      a.evCol[c.n_events] = i;
+      a.evRow[c.n_events] = j;
+      a.evOri[c.n_events] = o;
+    }
+    c.n_events++;
+    c.n_cut++;
+    any = true;
+    if (o == 0) {
+      if (mr.vlo > mr.vhi) mr.vlo = mr.vhi = j;
+      mr.vlo = min(mr.vlo, j);
+      mr.vhi = max(mr.vhi, j);
+    } else {
+      if (mr.hlo > mr.hhi) mr.hlo = mr.hhi = j;
+      mr.hlo = min(mr.hlo, j);
+      mr.hhi = max(mr.hhi, j);
+    }
+  };
+  // vertical links (i, j)-(i, j + 1): x = i in [xlo, xhi], [j, j + 1] meeting [ylo, yhi]
+  for (int i = max((int)ceil(xlo), 0); i <= min((int)floor(xhi), p.nx - 1); ++i)
+    for (int j = max((int)ceil(ylo) - 1, 0); j <= min((int)floor(yhi), p.ny - 2); ++j)
+      if (geom::touches_link(L, a0, a1, i, j, 0, 1)) cut(i, j, 0);
+  // horizontal links (i, j)-(i + 1, j): y = j in [ylo, yhi], [i, i + 1] meeting [xlo, xhi]
+  for (int j = max((int)ceil(ylo), 0); j <= min((int)floor(yhi), p.ny - 1); ++j)
+    for (int i = max((int)ceil(xlo) - 1, 0); i <= min((int)floor(xhi), p.nx - 2); ++i)
+      if (geom::touches_link(L, a0, a1, i, j, 1, 0)) cut(i, j, 1);
   return any;
 }
 
@@ -182,34 +303,44 @@ __device__ __forceinline__ void crack_step_wave(const CrackArgs &a) {
 
   // --- tip advance, CheckLinks, ProcessPoints ---
   bool any = false;
+  MaskRows mr = *a.mrows;
   if (growR) {
     const double a_prev = c.tip;
     double a_new = a_prev + (vR * q.cs) * q.dt;
-    if (a_new >= p.nx - 0.5) {
-      a_new = p.nx - 0.5;
+    if (a_new >= q.a_hi) {
+      a_new = q.a_hi;
       flagsR |= kFlagWall;
     }
-    // the new segment (a_prev, a_new] touches the columns in that interval
-    any |= cut_columns(a, c, (int)floor(a_prev) + 1, (int)floor(a_new), n);
+    if (q.aligned) {
+      // the new segment (a_prev, a_new] touches the columns in that interval
+      any |= cut_columns(a, c, (int)floor(a_prev) + 1, (int)floor(a_new), n);
+    } else {
+      any |= cut_segment(a, c, mr, a_prev, a_new, n);
+    }
     c.tip = a_new;
     flagsR |= kFlagGrew;
   }
   if (growL) {
     const double a_prev = c.tipL;
     double a_new = a_prev - (vL * q.cs) * q.dt;
-    if (a_new <= -0.5) {
-      a_new = -0.5;
+    if (a_new <= q.a_lo) {
+      a_new = q.a_lo;
       flagsL |= kFlagWall;
     }
-    // [a_new, a_prev) holds the newly touched columns
-    any |= cut_columns(a, c, (int)ceil(a_new), (int)ceil(a_prev) - 1, n);
+    if (q.aligned) {
+      // [a_new, a_prev) holds the newly touched columns
+      any |= cut_columns(a, c, (int)ceil(a_new), (int)ceil(a_prev) - 1, n);
+    } else {
+      any |= cut_segment(a, c, mr, a_new, a_prev, n);
+    }
     c.tipL = a_new;
     flagsL |= kFlagGrew;
   }
   if (any) {
-    MaskRows mr = *a.mrows;
-    if (p.j0 < mr.vlo || mr.vlo > mr.vhi) mr.vlo = p.j0;
-    if (p.j0 > mr.vhi) mr.vhi = p.j0;
+    if (q.aligned) {
+      if (p.j0 < mr.vlo || mr.vlo > mr.vhi) mr.vlo = p.j0;
+      if (p.j0 > mr.vhi) mr.vhi = p.j0;
+    }
     *a.mrows = mr;
   }
   c.v = vR;

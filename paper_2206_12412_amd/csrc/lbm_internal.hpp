@@ -36,6 +36,76 @@ struct Plate {
   size_t plane;      // elements between population planes
 };
 
+namespace core {
+
+// Interior work of a plate: the strips of 64 * VEC sites times the chunks of
+// `rows` consecutive interior rows, which are 1 .. skip_lo-1 and
+// skip_hi+1 .. ny-2 (the rows skip_lo .. skip_hi and the two edge rows belong
+// to the boundary work).  Task t -> strip t % n_strips, chunk t / n_strips.
+struct InteriorMap {
+  int n_strips, rows, lo1, hi1, lo2, hi2, nc1, nc2;
+};
+
+__host__ __device__ inline InteriorMap interior_map(int nx, int ny, int vec, int rows, int skip_lo,
+                                                    int skip_hi) {
+  InteriorMap m;
+  m.n_strips = (nx + 64 * vec - 1) / (64 * vec);
+  m.rows = rows;
+  const bool has_skip = skip_lo <= skip_hi;
+  m.lo1 = 1;
+  m.hi1 = has_skip ? skip_lo - 1 : ny - 2;
+  m.lo2 = has_skip ? skip_hi + 1 : ny;
+  m.hi2 = ny - 2;
+  m.nc1 = m.hi1 >= m.lo1 ? (m.hi1 - m.lo1 + rows) / rows : 0;
+  m.nc2 = m.hi2 >= m.lo2 ? (m.hi2 - m.lo2 + rows) / rows : 0;
+  return m;
+}
+
+__host__ __device__ inline long interior_task_count(const InteriorMap &m) {
+  return (long)m.n_strips * (m.nc1 + m.nc2);
+}
+
+// Boundary work of a plate: every strip of each boundary row, the rows being
+// row 0, the skipped rows lo .. hi (the rows a crack can ever touch) and row
+// ny - 1, each once, in that order.  Task t -> row row_of(t / n_strips).
+struct BoundaryMap {
+  int n_strips, nb;
+  int c0;      // 1 if row 0 comes first (it is not inside lo .. hi)
+  int lo, hi;  // skipped rows (lo > hi: none)
+  int top;     // row ny - 1 (listed last when it is not row 0 or inside lo .. hi)
+};
+
+__host__ __device__ inline BoundaryMap boundary_map(int nx, int ny, int vec, int skip_lo,
+                                                    int skip_hi) {
+  BoundaryMap m;
+  m.n_strips = (nx + 64 * vec - 1) / (64 * vec);
+  m.lo = skip_lo < 0 ? 0 : skip_lo;
+  m.hi = skip_hi > ny - 1 ? ny - 1 : skip_hi;
+  const bool has = m.lo <= m.hi;
+  if (!has) {
+    m.lo = 1;
+    m.hi = 0;
+  }
+  m.c0 = (!has || m.lo > 0) ? 1 : 0;
+  const bool top = ny - 1 > 0 && (!has || m.hi < ny - 1);
+  m.top = ny - 1;
+  m.nb = m.c0 + (has ? m.hi - m.lo + 1 : 0) + (top ? 1 : 0);
+  return m;
+}
+
+__host__ __device__ inline int boundary_row_of(const BoundaryMap &m, int r) {
+  if (r < m.c0) return 0;
+  r -= m.c0;
+  const int mid = m.hi >= m.lo ? m.hi - m.lo + 1 : 0;
+  return r < mid ? m.lo + r : m.top;
+}
+
+__host__ __device__ inline long boundary_task_count(const BoundaryMap &m) {
+  return (long)m.n_strips * m.nb;
+}
+
+}  // namespace core
+
 // Parameters of the crack step.
 struct CrackParams {
   int crack;         // the plate has a crack (else only the sensors are recorded)
@@ -45,6 +115,10 @@ struct CrackParams {
   double v_rel, K_C, r0, v_max;
   double cs, dt, mu;
   double x0;         // left end of the crack line
+  int aligned;       // the crack grows along +x on its row
+  double yc;         // y of the start point (x0, yc)
+  double ux, uy;     // unit growth direction of the right tip
+  double a_lo, a_hi; // line coordinates where the line leaves the plate
   int64_t trace_cap;
   int64_t event_cap;
 };
@@ -102,14 +176,16 @@ struct CrackArgs {
   DevCrack *st;
   const void *w;     // w after the sweep (double or float, see w_is_double)
   int w_is_double;
-  uint32_t *mV;
+  uint32_t *mV, *mH;  // cut bits of the vertical / horizontal links
   MaskRows *mrows;
   double *trK, *trA, *trV;
   int32_t *trF;
   double *trKL, *trAL, *trVL;  // left-tip traces (two tips)
   int32_t *trFL;
   int64_t *evStep;
-  int32_t *evCol;
+  int32_t *evCol;    // site (i, j) of the link and its orientation
+  int32_t *evRow;    // (0: vertical (i,j)-(i,j+1), 1: horizontal (i,j)-(i+1,j))
+  int32_t *evOri;
   const int32_t *sens;  // sensor sites [n_sens][2] = (i, j)
   double *trS;          // sensor traces [trace_cap][n_sens]
   int n_sens;
@@ -134,9 +210,9 @@ struct BatchPlate {
   int dmask;            // Dirichlet edges
   const double *wD;     // device copy of the wall-displacement history [n_wD][4]
   int64_t n_wD;
-  // task maps (same fields as the single-plate maps)
-  int n_strips, rows, lo1, hi1, lo2, hi2, nc1, nc2;
-  int nb, brow[4];
+  // task maps (the single-plate maps of this plate)
+  core::InteriorMap im;
+  core::BoundaryMap bm;
   int64_t itask0, btask0;  // first interior / boundary task of this plate in the batch
   CrackArgs crack;      // w is set per step from the parity
 };

@@ -24,7 +24,8 @@ sweep_step(const S *__restrict__ fin, S *__restrict__ fout, const W *__restrict_
     const int task = blockIdx.x * a.waves + wave;
     if (task >= bm.n_strips * bm.nb) return;
     core::boundary_row<S, W, C, VEC, SHIFT, SR, EQ>(fin, fout, win, wout, mV, mH, mrows, a,
-                                                task % bm.n_strips, bm.brow[task / bm.n_strips]);
+                                                    task % bm.n_strips,
+                                                    core::boundary_row_of(bm, task / bm.n_strips));
     return;
   }
   const int task = (blockIdx.x - nbb) * a.waves + wave;

@@ -292,61 +292,8 @@ __device__ __forceinline__ void site_update(const A &a, C f0, C gl, C gr, C gd, 
 }
 
 // ------------------------------------------------------------- task maps --
-// Interior work of a plate: the strips of 64 * VEC sites times the chunks of
-// `rows` consecutive interior rows, which are 1 .. skip_lo-1 and
-// skip_hi+1 .. ny-2 (the rows skip_lo .. skip_hi and the two edge rows belong
-// to the boundary work).  Task t -> strip t % n_strips, chunk t / n_strips.
-struct InteriorMap {
-  int n_strips, rows, lo1, hi1, lo2, hi2, nc1, nc2;
-};
-
-__host__ __device__ inline InteriorMap interior_map(int nx, int ny, int vec, int rows, int skip_lo,
-                                                    int skip_hi) {
-  InteriorMap m;
-  m.n_strips = (nx + 64 * vec - 1) / (64 * vec);
-  m.rows = rows;
-  const bool has_skip = skip_lo <= skip_hi;
-  m.lo1 = 1;
-  m.hi1 = has_skip ? skip_lo - 1 : ny - 2;
-  m.lo2 = has_skip ? skip_hi + 1 : ny;
-  m.hi2 = ny - 2;
-  m.nc1 = m.hi1 >= m.lo1 ? (m.hi1 - m.lo1 + rows) / rows : 0;
-  m.nc2 = m.hi2 >= m.lo2 ? (m.hi2 - m.lo2 + rows) / rows : 0;
-  return m;
-}
-
-__host__ __device__ inline long interior_task_count(const InteriorMap &m) {
-  return (long)m.n_strips * (m.nc1 + m.nc2);
-}
-
-// Boundary work of a plate: every strip of each boundary row (the two edge
-// rows and the skipped rows, each once).  Task t -> row brow[t / n_strips].
-struct BoundaryMap {
-  int n_strips, nb;
-  int brow[4];
-};
-
-__host__ __device__ inline BoundaryMap boundary_map(int nx, int ny, int vec, int skip_lo,
-                                                    int skip_hi) {
-  BoundaryMap m;
-  m.n_strips = (nx + 64 * vec - 1) / (64 * vec);
-  m.nb = 0;
-  auto add = [&](int j) {
-    if (j < 0 || j >= ny) return;
-    for (int k = 0; k < m.nb; ++k)
-      if (m.brow[k] == j) return;
-    m.brow[m.nb++] = j;
-  };
-  add(0);
-  add(ny - 1);
-  for (int j = skip_lo; j <= skip_hi && m.nb < 4; ++j) add(j);
-  for (int k = m.nb; k < 4; ++k) m.brow[k] = 0;
-  return m;
-}
-
-__host__ __device__ inline long boundary_task_count(const BoundaryMap &m) {
-  return (long)m.n_strips * m.nb;
-}
+// (the task maps, InteriorMap and BoundaryMap, are in lbm_internal.hpp: the
+// host builds them for the batched descriptors too)
 
 // ----------------------------------------------------------------- interior --
 // Rows jb .. jlast of one strip, all of them interior rows (every vertical

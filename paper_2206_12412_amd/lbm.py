@@ -36,7 +36,7 @@ ERRORS = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE
 
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
-           "lbm_cut_events", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
+           "lbm_cut_events", "lbm_cut_links", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
            "lbm_timing", "lbm_get_launch", "lbm_set_launch",
            "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
            "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
@@ -67,6 +67,7 @@ class _Config(C.Structure):
         ("crack_row", C.c_int32), ("both_tips", C.c_int32), ("dirichlet", C.c_int32),
         ("wD_hist", C.POINTER(C.c_double)), ("n_wD", C.c_int64),
         ("layout", C.c_int32),
+        ("crack_dx", C.c_double), ("crack_dy", C.c_double),
         ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t),
         ("stream", C.c_void_p),
     ]
@@ -105,6 +106,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_traces.argtypes = [vp, P(d), P(d), P(i32), i64, i64]
     lib.lbm_traces_left.argtypes = [vp, P(d), P(d), P(d), P(i32), i64, i64]
     lib.lbm_cut_events.argtypes = [vp, P(i64), P(i32), i64, P(i64)]
+    lib.lbm_cut_links.argtypes = [vp, P(i64), P(i32), P(i32), P(i32), i64, P(i64)]
     lib.lbm_get_fields.argtypes = [vp, P(d), P(d)]
     lib.lbm_get_populations.argtypes = [vp, P(d)]
     lib.lbm_get_mask.argtypes = [vp, P(C.c_uint8), P(C.c_uint8)]
@@ -150,8 +152,8 @@ def load_library(path: str = LIB_PATH):
                  "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
         getattr(lib, name).restype = i32
     for name in ("lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
-                 "lbm_cut_events", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
-                 "lbm_timing", "lbm_get_launch", "lbm_set_launch"):
+                 "lbm_cut_events", "lbm_cut_links", "lbm_get_fields", "lbm_get_populations",
+                 "lbm_get_mask", "lbm_timing", "lbm_get_launch", "lbm_set_launch"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -199,6 +201,8 @@ class Config:
     dirichlet: int = 0                    # EDGE_* bits of the edges holding a prescribed w
     wD_hist: Optional[np.ndarray] = None  # (n, 4) wall w* of (bottom, top, left, right) per step
     layout: str = "full"                  # "full" (five populations) or "eq" (see LAYOUT)
+    crack_dx: float = 1.0                 # growth direction of the right tip (Alg. 1, d);
+    crack_dy: float = 0.0                 # (1, 0) = +x along crack_row
 
     def to_c(self, keep: list) -> _Config:
         c = _Config()
@@ -210,6 +214,7 @@ class Config:
         c.has_crack = int(self.has_crack)
         c.rounding = ROUNDING[self.rounding] if isinstance(self.rounding, str) else int(self.rounding)
         c.layout = LAYOUT[self.layout] if isinstance(self.layout, str) else int(self.layout)
+        c.crack_dx, c.crack_dy = float(self.crack_dx), float(self.crack_dy)
         c.crack_row = int(self.crack_row)
         c.both_tips = int(self.both_tips)
         c.dirichlet = int(self.dirichlet)
@@ -423,6 +428,20 @@ class Solver:
                                             cols.ctypes.data_as(C.POINTER(C.c_int32)), n.value,
                                             C.byref(n)))
         return np.stack([steps, cols.astype(np.int64)], axis=1)
+
+    def cut_links(self) -> np.ndarray:
+        """(step, i, j, orientation) of every link severed by growth, in order
+        (orientation 0: vertical link (i,j)-(i,j+1), 1: horizontal (i,j)-(i+1,j))."""
+        n = C.c_int64()
+        _check(self._lib.lbm_cut_links(self._h, None, None, None, None, 0, C.byref(n)))
+        steps = np.empty(n.value, np.int64)
+        ijo = [np.empty(n.value, np.int32) for _ in range(3)]
+        if n.value:
+            P32 = C.POINTER(C.c_int32)
+            _check(self._lib.lbm_cut_links(self._h, steps.ctypes.data_as(C.POINTER(C.c_int64)),
+                                           *(a.ctypes.data_as(P32) for a in ijo), n.value,
+                                           C.byref(n)))
+        return np.stack([steps] + [a.astype(np.int64) for a in ijo], axis=1)
 
     def fields(self):
         w = np.empty(self.shape)

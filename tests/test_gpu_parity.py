@@ -352,3 +352,99 @@ def test_steady_strip_against_the_oracle(v, storage, layout, rounding):
     assert np.abs(K_g - K_r).max() <= ktol * np.abs(K_r).max()
     assert abs(np.median(K_g) / np.median(K_r) - 1.0) <= ktol
     say(f"  median K / K_theo - 1 = {np.median(K_g) / m['K_theo'] - 1:+.4f}")
+
+
+# -------------------------------- a crack along another direction (Alg. 1) --
+
+def inclined_kw(nx, ny, dx, dy, steps, v=0.45, both=True):
+    rng = np.random.default_rng(nx * 7 + ny)
+    n = np.arange(steps)
+    wD = np.zeros((steps, 4))
+    wD[:, 2] = 4e-3 * np.minimum(n / 50.0, 1.0)   # left edge held, ramped
+    return dict(nx=nx, ny=ny, has_crack=True, crack_row=ny // 2 - 3, crack_x0=nx / 2 - 2.3,
+                crack_tip=nx / 2 + 4.1, both_tips=both, growth=O.GROW_PRESCRIBED, v_rel=v,
+                crack_dx=dx, crack_dy=dy, tau_hist=np.array([1e-3]), dirichlet=4, wD_hist=wD,
+                wdot0=rng.normal(0, 1e-4, (ny, nx)), trace_cap=steps)
+
+
+def same_links(gpu, ref):
+    """Cut links per step as sets (the kernel tests the candidate links in
+    another order than the breadth-first search)."""
+    g = sorted(map(tuple, gpu.cut_links().tolist()))
+    r = sorted(map(tuple, ref.events().tolist()))
+    assert g == r and len(r) > 4
+
+
+@pytest.mark.parametrize("dx,dy", [(0.92, 0.39), (-0.3, 1.0), (0.6, -0.8), (0.0, 1.0), (1.0, 1.0)])
+@pytest.mark.parametrize("nx,ny", [(96, 70), (131, 53)])
+def test_inclined_crack_fp64_against_the_oracle(dx, dy, nx, ny):
+    steps = 220
+    kw = inclined_kw(nx, ny, dx, dy, steps)
+    for layout in ("full", "eq"):
+        say(f"inclined crack ({dx}, {dy}) {nx}x{ny} f64 {layout}")
+        ref = O.Oracle(O.OracleConfig(**kw))
+        gpu = Solver(Config(storage="f64", layout=layout, **kw))
+        mv_r, mh_r = ref.mask()
+        mv_g, mh_g = gpu.mask()
+        np.testing.assert_array_equal(mv_g, mv_r)
+        np.testing.assert_array_equal(mh_g, mh_r)
+        for n in (60, steps):
+            ref.step(n - gpu.steps_done)
+            gpu.step(n - gpu.steps_done)
+            w_r, w_g = ref.fields()[0], gpu.fields()[0]
+            assert relerr(w_g, w_r) <= 1e-12, (n, relerr(w_g, w_r))
+        for tip in ("right", "left"):
+            tr, tg = ref.traces(tip), gpu.traces(tip=tip)
+            np.testing.assert_array_equal(tg["tip"], tr["tip"])
+            np.testing.assert_array_equal(tg["flags"], tr["flags"])
+            ok = ~np.isnan(tr["K"])
+            assert np.array_equal(ok, ~np.isnan(tg["K"]))
+            if ok.any():
+                assert np.abs(tg["K"][ok] - tr["K"][ok]).max() <= 1e-12 * np.abs(tr["K"][ok]).max()
+        same_links(gpu, ref)
+        mv_r, mh_r = ref.mask()
+        mv_g, mh_g = gpu.mask()
+        np.testing.assert_array_equal(mv_g, mv_r)
+        np.testing.assert_array_equal(mh_g, mh_r)
+        gpu.close()
+
+
+@pytest.mark.parametrize("storage", ["f32-eq", "f16s-eq-sr", "f32"])
+def test_inclined_crack_reduced_precision(storage):
+    steps = 300
+    kw = inclined_kw(160, 90, 0.8, 0.45, steps)
+    st = storage.replace("-eq", "")
+    layout = "eq" if "-eq" in storage else "full"
+    ref = O.Oracle(O.OracleConfig(**kw))
+    gpu = gpu_config(st, layout=layout, **kw)
+    gpu = Solver(gpu)
+    ref.step(steps)
+    gpu.step(steps)
+    tol = TOL[st] if st in TOL else TOL["f16s"]
+    if st.startswith("f16s"):
+        tol = 4 * 2.0 ** -11 * math.sqrt(steps)
+    assert relerr(gpu.fields()[0], ref.fields()[0]) <= tol
+    np.testing.assert_array_equal(gpu.traces()["tip"], ref.traces()["tip"])
+    same_links(gpu, ref)
+
+
+def test_inclined_crack_in_a_batch_equals_the_plate_alone():
+    from paper_2206_12412_amd import Batch
+    steps = 120
+    cfgs = [Config(storage="f32", layout="eq", **inclined_kw(100, 64, -0.5, 0.7, steps)),
+            Config(storage="f32", layout="eq", **inclined_kw(90, 80, 1.0, 0.0, steps)),
+            Config(storage="f32", layout="eq", **inclined_kw(70, 90, 0.2, -1.0, steps, both=False))]
+    b = Batch(cfgs)
+    b.step(steps)
+    for k, c in enumerate(cfgs):
+        s = Solver(c)
+        s.step(steps)
+        np.testing.assert_array_equal(b.plates[k].fields()[0], s.fields()[0])
+        assert b.plates[k].cut_links().tolist() == s.cut_links().tolist()
+
+
+def test_adjoint_refuses_an_inclined_crack():
+    s = Solver(Config(storage="f32", sensors=np.array([[3, 4]]), **inclined_kw(60, 40, 0.6, 0.8, 10)))
+    s.step(10)
+    with pytest.raises(Exception):
+        s.adjoint(torch.zeros((10, 1), dtype=torch.float64, device="cuda"))
