@@ -7,14 +7,16 @@ severed links).  Default workload: the 16384 x 8192 plate (134M sites) with a
 FP32, FP16 and BF16 (the last three shifted by the static equilibrium, FP32
 arithmetic), in the five-population layout and in the equilibrium layout
 (rest population and w only; the moving populations are rebuilt from the
-equilibrium of their emitting site, exact at omega = 1).  The JSON line
-reports the headline storage's GLUPS (FP16, equilibrium layout, stochastic
-rounding) as `value`, next to the FP32 GLUPS of the same layout and of the
-five-population layout, each storage's K_III and field error against the FP64
-run of the same steps, the HBM roofline of the sweep kernel and the oracle's
-CPU throughput on a bounded sample.
+equilibrium of their emitting site, exact at omega = 1), one or two time
+steps per sweep ("-tb": two steps per sweep, each step's crack step still
+run).  The JSON line reports the headline storage's GLUPS (FP16, equilibrium
+layout, two steps per sweep, stochastic rounding) as `value`, next to the
+FP32 GLUPS of the same layout and of the five-population layout, each
+storage's K_III and field error against the FP64 run of the same steps, the
+HBM roofline of the sweep kernel and the oracle's CPU throughput on a
+bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-sr] [--workload precision]
+    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb-sr] [--workload precision]
 """
 from __future__ import annotations
 
@@ -39,14 +41,22 @@ METRIC = "GLUPS and % of HBM roofline, fp16-storage vs fp32 at stated K_III erro
 def parse_storage(name: str):
     """Storage name -> (storage, rounding, layout): a "-sr" suffix selects
     stochastic rounding of the 16-bit stores, an "-eq" part the equilibrium
-    layout (rest population and w only), e.g. "f16s-eq-sr"."""
+    layout (rest population and w only), an "-eq-tb" part that layout with
+    two time steps per sweep, e.g. "f16s-eq-tb-sr"."""
     rounding = "nearest"
     if name.endswith("-sr"):
         name, rounding = name[:-3], "stochastic"
+    if name.endswith("-tb"):
+        name = name[:-3]
     layout = "full"
     if name.endswith("-eq"):
         name, layout = name[:-3], "eq"
     return name, rounding, layout
+
+
+def time_block(name: str) -> int:
+    """Time steps per sweep of a storage name ("-tb": 2)."""
+    return 2 if "-tb" in name else 1
 
 
 def sweep_bytes_per_site(name: str) -> float:
@@ -55,7 +65,7 @@ def sweep_bytes_per_site(name: str) -> float:
     st, _, layout = parse_storage(name)
     e = {"f64": 8, "f32": 4, "f32plain": 4, "f16s": 2, "bf16s": 2}[st]
     we = 8 if st == "f64" else 4
-    return 2.0 * ((1 if layout == "eq" else 5) * e + we)
+    return 2.0 * ((1 if layout == "eq" else 5) * e + we) / time_block(name)
 
 
 def plate_config(p, storage, trace_cap):
@@ -71,7 +81,7 @@ def plate_config(p, storage, trace_cap):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep_core.hpp", "lbm_internal.hpp"):
+    for f in ("sweep.hip", "sweep2.hip", "sweep_core.hpp", "lbm_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2206_12412_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -102,6 +112,8 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=Tr
     # warm-up on a throw-away plate (clocks, code objects, page tables)
     if warmup > 0:
         s = Solver(plate_config(p, storage, 0))
+        if time_block(storage) == 2:
+            s.set_time_block(2)
         s.step(warmup)
         torch.cuda.synchronize()
         s.close()
@@ -109,6 +121,8 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=Tr
         torch.cuda.empty_cache()
     s = Solver(plate_config(p, storage, steps))
     tuned = s.autotune(trial_steps=5) if tune else None  # on a scratch copy of the plate
+    if time_block(storage) == 2:
+        s.set_time_block(2)
     torch.cuda.synchronize()
     # per-kernel HIP events on every 10th step of the timed region
     s.timing(True, stride=10)
@@ -453,11 +467,9 @@ def _read_csv(path):
 
 
 def _short(name: str) -> str:
-    for key in ("sweep_step", "sweep_interior", "sweep_boundary", "crack_kernel", "batch_step",
-                "batch_interior",
-                "batch_boundary", "batch_crack", "batch_persistent", "adj_step", "adj_interior", "adj_boundary",
-                "adj_inject", "adj_export", "copyBuffer", "init_rows", "export_rows", "zero_kernel",
-                "init_mask"):
+    for key in ("sweep_step", "sweep_pair", "crack_kernel", "batch_step", "batch_crack",
+                "batch_persistent", "adj_step", "adj_inject", "adj_export", "copyBuffer", "init_rows",
+                "export_rows", "zero_kernel", "init_mask"):
         if key in name:
             return key
     return name[:40]
@@ -481,8 +493,9 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
                   command: str, out_dir: str):
     """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs,
     each scaled by the same counter's reading for a device copy of copy_bytes.
-    The sweep kernel is the sweep_step instantiation with the most launches
-    (in the equilibrium layout the first two steps of a fresh plate run the
+    The sweep kernel is the two-step sweep_pair for a time-blocked storage
+    ("-tb"), else the sweep_step instantiation with the most launches (in the
+    equilibrium layout the first two steps of a fresh plate run the
     five-plane instantiation, which is left out)."""
     import synth
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
@@ -496,8 +509,9 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
         copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
         factor = copy_bytes / (copy * 1024.0)
         names = {}
+        want = "sweep_pair" if time_block(storage) == 2 else "sweep_step"
         for r in rows:
-            if "sweep_step" in r["Kernel_Name"]:
+            if want in r["Kernel_Name"]:
                 names.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         name = max(names, key=lambda k: len(names[k]))
         vals = names[name]
@@ -510,7 +524,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
     bps = sweep_bytes_per_site(storage)
     sites = p.nx * p.ny
     out["bytes_per_launch"] = total
-    out["algorithmic_bytes_per_launch"] = sites * bps
+    out["algorithmic_bytes_per_launch"] = sites * bps * time_block(storage)
     out["traffic_over_algorithmic"] = total / out["algorithmic_bytes_per_launch"]
     base = os.path.join(out_dir, f"sweep_{storage}_{workload}_traffic")
     with open(base + ".json", "w") as fh:
@@ -524,7 +538,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
                  f"| FETCH_SIZE | {f['KiB_per_launch']:.1f} | {f['copy_KiB']:.1f} KiB | {f['factor']:.4f} | {f['bytes_per_launch']:.4e} |\n"
                  f"| WRITE_SIZE | {w['KiB_per_launch']:.1f} | {w['copy_KiB']:.1f} KiB | {w['factor']:.4f} | {w['bytes_per_launch']:.4e} |\n\n"
                  f"Total {total:.4e} B per launch against {out['algorithmic_bytes_per_launch']:.4e} algorithmic "
-                 f"({sites} sites x {bps:g} B): ratio {out['traffic_over_algorithmic']:.4f}.\n"
+                 f"({sites} sites x {bps * time_block(storage):g} B): ratio {out['traffic_over_algorithmic']:.4f}.\n"
                  f"Kernel source sha256[:16] = {out['kernel_source_sha']}.\n")
 
 
@@ -545,11 +559,13 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="single plate: autotune each storage before timing (the library's "
                          "defaults are this search's result for the precision plate)")
-    ap.add_argument("--storage", default="f16s-eq-sr",
-                    help='headline storage; "-eq" selects the equilibrium layout, a "-sr" suffix '
-                         'stochastic rounding (e.g. f16s-eq-sr)')
+    ap.add_argument("--storage", default="f16s-eq-tb-sr",
+                    help='headline storage; "-eq" selects the equilibrium layout, "-eq-tb" that '
+                         'layout with two time steps per sweep, a "-sr" suffix stochastic '
+                         'rounding (e.g. f16s-eq-tb-sr)')
     ap.add_argument("--compare",
-                    default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr",
+                    default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr,"
+                            "f64-eq-tb,f32-eq-tb,f16s-eq-tb-sr,bf16s-eq-tb-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -640,14 +656,16 @@ def main():
 
     head = results[args.storage]
     bps = head["bytes_per_site"]
-    alg = head["sites"] * bps  # algorithmic bytes of one sweep-kernel launch
-    achieved = alg / (head["sweep_ms"] * 1e-3) / 1e9
+    tb = time_block(args.storage)
+    alg = head["sites"] * bps * tb  # algorithmic bytes of one sweep-kernel launch (tb steps)
+    achieved = alg / (head["sweep_ms"] * tb * 1e-3) / 1e9
     traffic = traffic_for(args.storage, args.workload, p.sites)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": f"sweep_step ({args.storage})",
-                "algorithmic_bytes_per_launch": alg,
-                "kernel_ms": round(head["sweep_ms"], 4)}
+                "traffic": traffic,
+                "kernel": f"{'sweep_pair' if tb == 2 else 'sweep_step'} ({args.storage})",
+                "steps_per_launch": tb, "algorithmic_bytes_per_launch": alg,
+                "kernel_ms": round(head["sweep_ms"] * tb, 4)}
 
     line = {
         "metric": METRIC,
@@ -673,7 +691,7 @@ def main():
     }
     # FP16 storage against FP32 storage in the same layout, and against the
     # five-plane FP32 run
-    same32 = "f32-eq" if parse_storage(args.storage)[2] == "eq" else "f32"
+    same32 = "f32" + args.storage[len(parse_storage(args.storage)[0]):].replace("-sr", "")
     if same32 in results and args.storage != same32:
         line["vs_f32_glups"] = round(head["glups"] / results[same32]["glups"], 3)
         line["vs_f32_reference"] = same32

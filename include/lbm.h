@@ -253,6 +253,20 @@ int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves,
                    int32_t *occupancy);
 int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy);
 
+/* Time blocking: with steps = 2, lbm_step advances two time steps per sweep
+ * (each wave computes step n for its rows and their neighbours in registers,
+ * then step n + 1, then stores), halving the bytes moved per step; the crack
+ * steps of both time steps still run (K of step n from the crack rows after
+ * step n).  FP32 and FP64 results are bit for bit those of steps = 1; 16-bit
+ * storages round only every second step.  Needs the equilibrium layout,
+ * walls, no sensors, and no crack or a crack along +x with prescribed or no
+ * growth (the K criterion decides every step; LBM_EINVAL otherwise).  rows /
+ * waves: rows finished per wave (4, 8 or 16) and waves per workgroup
+ * (1, 2, 4 or 8) of the two-step sweep (0 = keep; the defaults are the
+ * fastest measured on a 16384 x 8192 plate).  An odd step count ends with one
+ * single-step sweep.  steps = 1 restores the one-step sweep. */
+int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves);
+
 /* The 16-bit store conversion of the sweep, applied to an array (for
  * inspection and tests of the storage formats): out[i] is the value the sweep
  * of step `step` with seed `seed` stores for a result x[i] at plate-local site

@@ -50,7 +50,7 @@ struct Layout {
   size_t off_trK = 0, off_trA = 0, off_trV = 0, off_trF = 0;
   size_t off_trKL = 0, off_trAL = 0, off_trVL = 0, off_trFL = 0;
   size_t off_evS = 0, off_evC = 0, off_evJ = 0, off_evO = 0, off_stage = 0;
-  size_t off_sens = 0, off_trS = 0;
+  size_t off_sens = 0, off_trS = 0, off_wmid = 0;
   int64_t event_cap = 0;
   int stage_rows = 0;
   size_t total = 0;
@@ -120,6 +120,7 @@ Layout make_layout(const lbm_config &c, Store s) {
   L.off_evC = o; o += align_up((size_t)L.event_cap * 4, 256);
   L.off_evJ = o; o += align_up((size_t)L.event_cap * 4, 256);
   L.off_evO = o; o += align_up((size_t)L.event_cap * 4, 256);
+  L.off_wmid = o; o += align_up((size_t)2 * L.pitch * L.welem, 256);  // two-step sweep: crack rows after step n
   L.off_sens = o; o += align_up((size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.off_trS = o; o += align_up(tc * (size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.stage_rows = (int)std::max<int64_t>(1, std::min<int64_t>(c.ny, (1 << 20) / std::max(1, c.nx)));
@@ -263,6 +264,7 @@ struct lbm_handle {
   int timing_stride = 1;  // record the steps whose index is a multiple of this
   std::vector<hipEvent_t> ev_pool;
   std::vector<hipEvent_t> ev_used;  // per timed step: before, after the sweep, after the crack step
+  std::vector<int> ev_steps;        // steps covered by each recorded triple (2: a two-step sweep)
   double t_sweep = 0, t_crack = 0;
   int64_t n_timed = 0;
   lbmk::DevCrack host_crack{};
@@ -274,6 +276,10 @@ struct lbm_handle {
   // that FP32 cannot hold) are streamed and both buffers are cleared.
   bool eq = false;
   int full_steps = 0;
+  // time blocking: steps per sweep (1, or 2 with the two-step sweep) and the
+  // two-step sweep's rows per wave and waves per workgroup
+  int tblock = 1;
+  int pair_rows = 4, pair_waves = 4;
   // crack line, wall limits of the tips and the rows a crack can touch
   lbmk::geom::Line line{1, 0.0, 0.0, 1.0, 0.0};
   double a_lo = -0.5, a_hi = 0.0;
@@ -320,15 +326,18 @@ int harvest_timing(lbm_handle *h) {
     HIP_TRY(hipEventElapsedTime(&c, h->ev_used[k + 1], h->ev_used[k + 2]));
     h->t_sweep += a;
     h->t_crack += c;
-    h->n_timed += 1;
+    h->n_timed += h->ev_steps[k / 3];
   }
   for (hipEvent_t e : h->ev_used) h->ev_pool.push_back(e);
   h->ev_used.clear();
+  h->ev_steps.clear();
   return LBM_OK;
 }
 
+// Sweep arguments of step n (its traction, wall values and rounding key),
+// from the current buffers to the other ones.
 template <typename S, typename W, typename C>
-int launch_sweep_typed(lbm_handle *h) {
+lbmk::SweepArgs<S, W, C> sweep_args(const lbm_handle *h, int64_t n) {
   lbmk::SweepArgs<S, W, C> a{};
   const int nxt = 1 - h->cur;
   a.fin = static_cast<const S *>(h->fbuf(h->cur));
@@ -343,7 +352,7 @@ int launch_sweep_typed(lbm_handle *h) {
   a.dt = (C)h->dt;
   a.A0 = (C)h->A0;
   a.Ak = (C)h->Ak;
-  const double tau = h->tau_at(h->step);
+  const double tau = h->tau_at(n);
   const bool per = h->cfg.bc_mode == LBM_BC_PERIODIC;
   a.t_top = per ? C(0) : (C)(h->coef * tau);
   a.t_bot = per ? C(0) : (C)(h->coef * -tau);
@@ -361,10 +370,10 @@ int launch_sweep_typed(lbm_handle *h) {
   a.skip_lo = h->skip_lo;
   a.skip_hi = h->skip_hi;
   a.sr = h->cfg.rounding == LBM_ROUND_STOCHASTIC;
-  a.rkey = lbmk::step_key(h->cfg.seed, h->step);
+  a.rkey = lbmk::step_key(h->cfg.seed, n);
   a.dmask = per ? 0 : h->cfg.dirichlet;
   if (a.dmask) {
-    const size_t r = 4 * (size_t)std::min<int64_t>(h->step, h->cfg.n_wD - 1);
+    const size_t r = 4 * (size_t)std::min<int64_t>(n, h->cfg.n_wD - 1);
     a.wD_bot = (C)h->wD[r];
     a.wD_top = (C)h->wD[r + 1];
     a.wD_left = (C)h->wD[r + 2];
@@ -372,8 +381,44 @@ int launch_sweep_typed(lbm_handle *h) {
   } else {
     a.wD_bot = a.wD_top = a.wD_left = a.wD_right = C(0);
   }
+  return a;
+}
+
+template <typename S, typename W, typename C>
+int launch_sweep_typed(lbm_handle *h) {
+  const lbmk::SweepArgs<S, W, C> a = sweep_args<S, W, C>(h, h->step);
   HIP_TRY(lbmk::launch_sweep(h->store, h->eq && h->full_steps == 0, &a, h->stream));
   return LBM_OK;
+}
+
+// Steps n and n + 1 in one sweep (time blocking, sweep2.hip).
+template <typename S, typename W, typename C>
+int launch_pair_typed(lbm_handle *h) {
+  lbmk::PairArgs<S, W, C> A{};
+  A.s0 = sweep_args<S, W, C>(h, h->step);
+  A.s1 = sweep_args<S, W, C>(h, h->step + 1);
+  A.wmid = reinterpret_cast<W *>(h->base + h->L.off_wmid);
+  A.st = h->crack();
+  A.crack = h->cfg.has_crack;
+  A.both = h->cfg.both_tips;
+  A.grow = h->cfg.growth == LBM_GROW_PRESCRIBED;
+  A.v_rel = h->cfg.v_rel;
+  A.cs = h->cs;
+  A.dt = h->dt;
+  A.a_lo = h->a_lo;
+  A.a_hi = h->a_hi;
+  HIP_TRY(lbmk::launch_sweep_pair(h->store, &A, h->pair_rows, h->pair_waves, h->stream));
+  return LBM_OK;
+}
+
+int launch_pair_any(lbm_handle *h) {
+  switch (h->store) {
+    case Store::F64S: return launch_pair_typed<double, double, double>(h);
+    case Store::F32S: return launch_pair_typed<float, float, float>(h);
+    case Store::F16S: return launch_pair_typed<_Float16, float, float>(h);
+    case Store::BF16S: return launch_pair_typed<__bf16, float, float>(h);
+    default: return fail(LBM_EINVAL, "the two-step sweep needs the equilibrium layout");
+  }
 }
 
 int launch_sweep_any(lbm_handle *h) {
@@ -580,6 +625,10 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
       h->waves = half ? 8 : 4;
       h->occ = 0;
     }
+    // two-step sweep (lbm_set_time_block): 4 rows per wave in 4-wave groups
+    // (the fastest of rows 4 / 8 / 16 x waves 1 / 2 / 4 / 8 for every storage)
+    h->pair_rows = 4;
+    h->pair_waves = 4;
   }
 
   {
@@ -717,9 +766,13 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (h->in_batch) return fail(LBM_ESTATE, "this plate is stepped by its batch (lbm_batch_step)");
   if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
-  for (int64_t k = 0; k < nsteps; ++k) {
+  for (int64_t k = 0; k < nsteps;) {
+    // two steps in one sweep when time blocking is on and the moving planes
+    // are settled (the five-plane start-up steps run one at a time)
+    const int ns = (h->tblock == 2 && nsteps - k >= 2 && h->full_steps == 0) ? 2 : 1;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    const bool timed = h->timing && h->step % h->timing_stride == 0;
+    const bool timed = h->timing && (h->step % h->timing_stride == 0 ||
+                                     (ns == 2 && (h->step + 1) % h->timing_stride == 0));
     if (timed) {
       for (auto &e : ev) {
         e = take_event(h);
@@ -727,23 +780,32 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
       }
       HIP_TRY(hipEventRecord(ev[0], h->stream));
     }
-    int rc = launch_sweep_any(h);
+    int rc = ns == 2 ? launch_pair_any(h) : launch_sweep_any(h);
     if (rc != LBM_OK) return rc;
     if (timed) HIP_TRY(hipEventRecord(ev[1], h->stream));
     if (h->crack_step_needed()) {
+      if (ns == 2) {
+        // step n from the crack rows after step n, then step n + 1
+        lbmk::CrackArgs a = crack_args(h);
+        a.w = h->base + h->L.off_wmid;
+        a.w_row0 = h->plate.j0;
+        HIP_TRY(lbmk::launch_crack(a, h->stream));
+      }
       rc = launch_crack_step(h);
       if (rc != LBM_OK) return rc;
     }
     if (timed) {
       HIP_TRY(hipEventRecord(ev[2], h->stream));
       for (auto &e : ev) h->ev_used.push_back(e);
+      h->ev_steps.push_back(ns);
       if (h->ev_used.size() >= 3 * 4096) {
         rc = harvest_timing(h);
         if (rc != LBM_OK) return rc;
       }
     }
     h->cur = 1 - h->cur;
-    h->step++;
+    h->step += ns;
+    k += ns;
     if (h->full_steps > 0) h->full_steps--;
   }
   return LBM_OK;
@@ -1037,6 +1099,30 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
   return LBM_OK;
 }
 
+int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (steps != 1 && steps != 2) return fail(LBM_EINVAL, "steps per sweep must be 1 or 2");
+  if (rows != 0 && rows != 4 && rows != 8 && rows != 16)
+    return fail(LBM_EINVAL, "rows must be 4, 8 or 16 (0 = keep)");
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(LBM_EINVAL, "waves must be 0 (keep), 1, 2, 4 or 8");
+  if (steps == 2) {
+    if (!h->eq || h->store == Store::F32_PLAIN || h->store == Store::F64)
+      return fail(LBM_EINVAL, "the two-step sweep needs the equilibrium layout");
+    if (h->cfg.bc_mode == LBM_BC_PERIODIC) return fail(LBM_EINVAL, "the two-step sweep needs walls");
+    if (h->cfg.has_crack && !h->line.aligned)
+      return fail(LBM_EINVAL, "the two-step sweep takes a crack along +x only");
+    if (h->cfg.growth == LBM_GROW_SIF)
+      return fail(LBM_EINVAL, "the two-step sweep needs prescribed or no growth (the K criterion decides each step)");
+    if (h->cfg.n_sensors > 0) return fail(LBM_EINVAL, "the two-step sweep records no sensors");
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->tblock = steps;
+  if (rows > 0) h->pair_rows = rows;
+  if (waves > 0) h->pair_waves = waves;
+  return LBM_OK;
+}
+
 int lbm_round16(const float *x, void *out, int64_t n, int32_t storage, int32_t rounding,
                 int32_t plane, uint32_t seed, int64_t step, void *stream) {
   if (n < 0 || (n > 0 && (!x || !out))) return fail(LBM_EINVAL, "bad arrays");
@@ -1067,7 +1153,7 @@ int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *rows, int32_t *wav
 double lbm_bytes_per_site(const lbm_handle *h) {
   if (!h) return 0.0;
   const double e = (double)elem_size(h->store), we = is_fp64(h->store) ? 8.0 : 4.0;
-  return 2.0 * ((h->eq ? 1.0 : 5.0) * e + we);
+  return 2.0 * ((h->eq ? 1.0 : 5.0) * e + we) / h->tblock;
 }
 
 void lbm_free(lbm_handle *h) {

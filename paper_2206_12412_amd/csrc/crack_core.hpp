@@ -39,7 +39,7 @@ constexpr int kGrowSif = 2;
 constexpr int kFlagGrew = 1, kFlagWall = 2, kFlagKUndef = 4;
 
 __device__ __forceinline__ double w_at(const CrackArgs &a, int i, int j) {
-  const size_t x = (size_t)j * a.p.pitch + i;
+  const size_t x = (size_t)(j - a.w_row0) * a.p.pitch + i;
   return a.w_is_double ? static_cast<const double *>(a.w)[x]
                        : (double)static_cast<const float *>(a.w)[x];
 }

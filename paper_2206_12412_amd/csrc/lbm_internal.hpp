@@ -158,6 +158,18 @@ struct SweepArgs {
   C wD_bot, wD_top, wD_left, wD_right;  // their wall values this step
 };
 
+// Arguments of the two-step sweep (sweep2.hip): the per-step arguments of
+// both steps (their traction, wall values and rounding key differ) and the
+// crack state the second step's cut links follow from.
+template <typename S, typename W, typename C>
+struct PairArgs {
+  SweepArgs<S, W, C> s0, s1;  // steps n and n + 1 (s0 carries the buffers and the shape)
+  W *wmid;                    // w after step n on rows j0 and j0 + 1 ([2][pitch])
+  const DevCrack *st;         // crack state before step n's crack step
+  int crack, both, grow;      // crack present, two tips, prescribed growth
+  double v_rel, cs, dt, a_lo, a_hi;
+};
+
 // Counter-based randomness of the stochastic rounding: the integer hash
 // "lowbias32" (C. Wellons' hash-prospector, 2018), and the key of one step.
 __host__ __device__ inline uint32_t mix32(uint32_t x) {
@@ -176,6 +188,7 @@ struct CrackArgs {
   DevCrack *st;
   const void *w;     // w after the sweep (double or float, see w_is_double)
   int w_is_double;
+  int w_row0;        // row of the plate that w's first row holds (0: the whole plane)
   uint32_t *mV, *mH;  // cut bits of the vertical / horizontal links
   MaskRows *mrows;
   double *trK, *trA, *trV;
@@ -269,6 +282,9 @@ int sweep_vec(Store s);  // sites per lane
 // one sweep step (interior strips and boundary rows in one launch); eq: the
 // equilibrium layout (plane 0 and w only; shifted storages)
 hipError_t launch_sweep(Store s, bool eq, const void *args, hipStream_t st);
+// two steps in one sweep (equilibrium layout, walls, a crack along +x with
+// prescribed or no growth); args is a PairArgs of the storage's types
+hipError_t launch_sweep_pair(Store s, const void *args, int rows, int waves, hipStream_t st);
 // the 16-bit store conversion of the sweep applied to x[0..n) (F16S / BF16S)
 hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n, int plane,
                           uint32_t rkey, hipStream_t st);

@@ -37,7 +37,7 @@ ERRORS = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
            "lbm_cut_events", "lbm_cut_links", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
-           "lbm_timing", "lbm_get_launch", "lbm_set_launch",
+           "lbm_timing", "lbm_get_launch", "lbm_set_launch", "lbm_set_time_block",
            "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
            "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
            "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_traces_left.argtypes = [vp, P(d), P(d), P(d), P(i32), i64, i64]
     lib.lbm_cut_events.argtypes = [vp, P(i64), P(i32), i64, P(i64)]
     lib.lbm_cut_links.argtypes = [vp, P(i64), P(i32), P(i32), P(i32), i64, P(i64)]
+    lib.lbm_set_time_block.argtypes = [vp, i32, i32, i32]
+    lib.lbm_set_time_block.restype = i32
     lib.lbm_get_fields.argtypes = [vp, P(d), P(d)]
     lib.lbm_get_populations.argtypes = [vp, P(d)]
     lib.lbm_get_mask.argtypes = [vp, P(C.c_uint8), P(C.c_uint8)]
@@ -482,6 +484,10 @@ class Solver:
     def set_launch(self, rows: int, waves: int, occupancy: int = 0):
         _check(self._lib.lbm_set_launch(self._h, int(rows), int(waves), int(occupancy)))
 
+    def set_time_block(self, steps: int = 2, rows: int = 0, waves: int = 0):
+        """Advance `steps` (1 or 2) time steps per sweep; see lbm_set_time_block."""
+        _check(self._lib.lbm_set_time_block(self._h, int(steps), int(rows), int(waves)))
+
     def autotune(self, trial_steps: int = 8) -> dict:
         """Searches the launch-shape grid on a scratch plate built from this
         plate's config (this plate's state is untouched) and applies the
@@ -526,6 +532,9 @@ class _PlateView(Solver):
 
     def set_launch(self, rows: int, waves: int, occupancy: int = 0):
         raise RuntimeError("the launch shape of a batch is set on the batch")
+
+    def set_time_block(self, steps: int = 2, rows: int = 0, waves: int = 0):
+        raise RuntimeError("plates of a batch step one time step per sweep")
 
     def autotune(self, trial_steps: int = 8) -> dict:
         raise RuntimeError("a batch is tuned as a whole (Batch.autotune)")

@@ -93,27 +93,33 @@ F16_TOL = 4 * 2.0 ** -11 * math.sqrt(T_WIN)
 
 
 def parse(name):
-    """"f16s-eq-sr" -> ("f16s", "stochastic", "eq")"""
+    """"f16s-eq-tb-sr" -> ("f16s", "stochastic", "eq", 2)"""
     rounding = "stochastic" if name.endswith("-sr") else "nearest"
     name = name[:-3] if name.endswith("-sr") else name
+    tb = 2 if name.endswith("-tb") else 1
+    name = name[:-3] if tb == 2 else name
     layout = "eq" if name.endswith("-eq") else "full"
-    return (name[:-3] if layout == "eq" else name), rounding, layout
+    return (name[:-3] if layout == "eq" else name), rounding, layout, tb
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5), ("f16s", F16_TOL),
                                          ("f16s-sr", F16_TOL), ("f64-eq", 1e-12),
-                                         ("f32-eq", 1e-5), ("f16s-eq-sr", F16_TOL)])
+                                         ("f32-eq", 1e-5), ("f16s-eq-sr", F16_TOL),
+                                         ("f64-eq-tb", 1e-12), ("f32-eq-tb", 1e-5),
+                                         ("f16s-eq-tb-sr", F16_TOL)])
 def test_precision_plate_windows(big_plate, storage, tol):
     """The 134M-site plate in the launch configuration the benchmark times
     (the library's default shapes), on sampled windows the oracle computes."""
     p, wd0 = big_plate
     T, d = T_WIN, D_BLOCK
     say(f"134M-site plate, storage {storage}, {T} steps")
-    st, rounding, layout = parse(storage)
+    st, rounding, layout, tb = parse(storage)
     s = Solver(Config(nx=p.nx, ny=p.ny, storage=st, rounding=rounding, layout=layout,
                       has_crack=True, crack_x0=p.crack_x0,
                       crack_tip=p.crack_tip, growth=p.growth, v_rel=p.v_rel,
                       tau_hist=p.traction_history(), wdot0=wd0, trace_cap=T))
+    if tb == 2:
+        s.set_time_block(2)
     s.step(T)
     w_g, wd_g = s.fields()
     tip_g = s.traces()["tip"]

@@ -186,3 +186,100 @@ def test_batched_equilibrium_layout(storage):
             s5 = Solver(Config(**{**c.__dict__, "layout": "full"}))
             s5.step(steps)
             same(s5, b.plates[k], f"batch vs five planes {nm}", c.both_tips, c.has_crack)
+
+
+# ---------------------------------------------------------- time blocking --
+
+def tb_cases(steps):
+    rng = np.random.default_rng(17)
+    n = np.arange(steps)
+    wD = np.zeros((steps, 4))
+    wD[:, 0] = -0.01 * np.sin(np.pi * n / 60.0)
+    wD[:, 3] = 2e-3
+    return {
+        "edge-prescribed": dict(nx=517, ny=45, has_crack=True, crack_row=20, crack_tip=100.5,
+                                growth=1, v_rel=0.45,
+                                tau_hist=1e-3 * (1 + 0.1 * np.sin(n / 9.0)), trace_cap=steps,
+                                wdot0=1e-4 * rng.normal(size=(45, 517))),
+        "two-tip-dirichlet": dict(nx=300, ny=61, has_crack=True, crack_row=20, crack_x0=120.5,
+                                  crack_tip=170.5, both_tips=True, growth=1, v_rel=0.3,
+                                  dirichlet=1 | 8, wD_hist=wD, trace_cap=steps, face_traction=2e-4,
+                                  wdot0=1e-4 * rng.normal(size=(61, 300))),
+        "no-crack": dict(nx=250, ny=7, tau_hist=np.array([1e-3]),
+                         wdot0=1e-3 * rng.normal(size=(7, 250))),
+        "stationary-tiny": dict(nx=9, ny=4, has_crack=True, crack_tip=3.5, tau_hist=np.array([1e-3]),
+                                trace_cap=steps),
+        "wall-reached": dict(nx=120, ny=30, has_crack=True, crack_tip=100.5, growth=1, v_rel=0.9,
+                             tau_hist=np.array([1e-3]), trace_cap=steps),
+    }
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["edge-prescribed", "two-tip-dirichlet", "no-crack",
+                                  "stationary-tiny", "wall-reached"])
+@pytest.mark.parametrize("rows,waves", [(16, 4), (4, 1), (8, 8), (4, 2)])
+def test_two_step_sweep_equals_one_step_sweeps_bitwise(storage, name, rows, waves):
+    steps = 151  # odd: the last step runs alone
+    kw = tb_cases(steps)[name]
+    say(f"two-step sweep {name} {storage} rows={rows} waves={waves}")
+    one = Solver(Config(storage=storage, layout="eq", **kw))
+    two = Solver(Config(storage=storage, layout="eq", **kw))
+    two.set_time_block(2, rows, waves)
+    for n in (1, 2, 4, 77, steps):
+        one.step(n - one.steps_done)
+        two.step(n - two.steps_done)
+        same(one, two, f"{name} {storage} step {n}", kw.get("both_tips", False), kw.get("has_crack", False))
+    one.close()
+    two.close()
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_two_step_sweep_16bit_against_the_oracle(storage):
+    """16-bit storage rounds only after the second step: within the derived
+    bound of the oracle, tips and cut events exact, K within the storage's
+    bound."""
+    steps = 400
+    kw = tb_cases(steps)["two-tip-dirichlet"]
+    ref = O.Oracle(O.OracleConfig(**kw))
+    ref.step(steps)
+    s = Solver(Config(storage=storage, layout="eq", rounding="stochastic", seed=5, **kw))
+    s.set_time_block(2)
+    s.step(steps)
+    w_r = ref.fields()[0]
+    tol = (4 * 2.0 ** -11 if storage == "f16s" else 4 * 2.0 ** -8) * np.sqrt(steps)
+    assert np.abs(s.fields()[0] - w_r).max() <= tol * np.abs(w_r).max()
+    for tip in ("right", "left"):
+        np.testing.assert_array_equal(s.traces(tip=tip)["tip"], ref.traces(tip)["tip"])
+    assert s.cut_events()[:, 1].tolist() == ref.events()[:, 1].tolist()
+
+
+def test_two_step_sweep_refuses_what_it_cannot_do():
+    base = tb_cases(10)["edge-prescribed"]
+    with pytest.raises(Exception):
+        Solver(Config(storage="f32", **base)).set_time_block(2)                    # five planes
+    with pytest.raises(Exception):
+        Solver(Config(storage="f32", layout="eq", **dict(base, growth=2, K_C=0.1))).set_time_block(2)
+    with pytest.raises(Exception):
+        Solver(Config(storage="f32", layout="eq", sensors=np.array([[1, 1]]), **base)).set_time_block(2)
+    with pytest.raises(Exception):
+        Solver(Config(nx=64, ny=20, storage="f32", layout="eq", periodic=True)).set_time_block(2)
+
+
+def test_two_step_sweep_timing_and_checkpoints():
+    steps = 200
+    kw = tb_cases(steps)["edge-prescribed"]
+    a = Solver(Config(storage="f32", layout="eq", **kw))
+    a.set_time_block(2)
+    a.timing(True, stride=10)
+    a.step(100)
+    ck = a.checkpoint()
+    a.step(100)
+    t = a.timing(False)
+    # steps 0 and 1 run alone (the five-plane start of the layout), step 0
+    # timed; then the pairs starting at a multiple of 10 count two steps each
+    assert t["steps"] == 1 + 2 * 9 + 2 * 10 and t["sweep_ms"] > 0
+    b = Solver(Config(storage="f32", layout="eq", **kw))
+    b.set_time_block(2)
+    b.restore(ck)
+    b.step(100)
+    same(a, b, "restart", False, True)
