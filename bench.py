@@ -7,16 +7,17 @@ severed links).  Default workload: the 16384 x 8192 plate (134M sites) with a
 FP32, FP16 and BF16 (the last three shifted by the static equilibrium, FP32
 arithmetic), in the five-population layout and in the equilibrium layout
 (rest population and w only; the moving populations are rebuilt from the
-equilibrium of their emitting site, exact at omega = 1), one or two time
-steps per sweep ("-tb": two steps per sweep, each step's crack step still
-run).  The JSON line reports the headline storage's GLUPS (FP16, equilibrium
-layout, two steps per sweep, stochastic rounding) as `value`, next to the
+equilibrium of their emitting site, exact at omega = 1), one to four time
+steps per sweep ("-tb", "-tb3", "-tb4": two, three, four steps per sweep,
+each step's crack step still run).  The JSON line reports the headline
+storage's GLUPS (FP16, equilibrium layout, four steps per sweep, stochastic
+rounding) as `value`, next to the
 FP32 GLUPS of the same layout and of the five-population layout, each
 storage's K_III and field error against the FP64 run of the same steps, the
 HBM roofline of the sweep kernel and the oracle's CPU throughput on a
 bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb-sr] [--workload precision]
+    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb4-sr] [--workload precision]
 """
 from __future__ import annotations
 
@@ -26,6 +27,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -42,12 +44,12 @@ def parse_storage(name: str):
     """Storage name -> (storage, rounding, layout): a "-sr" suffix selects
     stochastic rounding of the 16-bit stores, an "-eq" part the equilibrium
     layout (rest population and w only), an "-eq-tb" part that layout with
-    two time steps per sweep, e.g. "f16s-eq-tb-sr"."""
+    two time steps per sweep ("-eq-tb3", "-eq-tb4": three, four), e.g.
+    "f16s-eq-tb3-sr"."""
     rounding = "nearest"
     if name.endswith("-sr"):
         name, rounding = name[:-3], "stochastic"
-    if name.endswith("-tb"):
-        name = name[:-3]
+    name = re.sub(r"-tb[34]?$", "", name)
     layout = "full"
     if name.endswith("-eq"):
         name, layout = name[:-3], "eq"
@@ -55,8 +57,14 @@ def parse_storage(name: str):
 
 
 def time_block(name: str) -> int:
-    """Time steps per sweep of a storage name ("-tb": 2)."""
-    return 2 if "-tb" in name else 1
+    """Time steps per sweep of a storage name ("-tb": 2, "-tb3": 3, "-tb4": 4)."""
+    m = re.search(r"-tb([34]?)(-|$)", name)
+    return (int(m.group(1)) if m.group(1) else 2) if m else 1
+
+
+def block_kernel(name: str) -> str:
+    """The sweep kernel a storage name runs."""
+    return "sweep_block" if time_block(name) >= 2 else "sweep_step"
 
 
 def sweep_bytes_per_site(name: str) -> float:
@@ -112,8 +120,8 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=Tr
     # warm-up on a throw-away plate (clocks, code objects, page tables)
     if warmup > 0:
         s = Solver(plate_config(p, storage, 0))
-        if time_block(storage) == 2:
-            s.set_time_block(2)
+        if time_block(storage) >= 2:
+            s.set_time_block(time_block(storage))
         s.step(warmup)
         torch.cuda.synchronize()
         s.close()
@@ -121,8 +129,8 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=Tr
         torch.cuda.empty_cache()
     s = Solver(plate_config(p, storage, steps))
     tuned = s.autotune(trial_steps=5) if tune else None  # on a scratch copy of the plate
-    if time_block(storage) == 2:
-        s.set_time_block(2)
+    if time_block(storage) >= 2:
+        s.set_time_block(time_block(storage))
     torch.cuda.synchronize()
     # per-kernel HIP events on every 10th step of the timed region
     s.timing(True, stride=10)
@@ -467,7 +475,7 @@ def _read_csv(path):
 
 
 def _short(name: str) -> str:
-    for key in ("sweep_step", "sweep_pair", "crack_kernel", "batch_step", "batch_crack",
+    for key in ("sweep_step", "sweep_block", "crack_kernel", "batch_step", "batch_crack",
                 "batch_persistent", "adj_step", "adj_inject", "adj_export", "copyBuffer", "init_rows",
                 "export_rows", "zero_kernel", "init_mask"):
         if key in name:
@@ -493,8 +501,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
                   command: str, out_dir: str):
     """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs,
     each scaled by the same counter's reading for a device copy of copy_bytes.
-    The sweep kernel is the two-step sweep_pair for a time-blocked storage
-    ("-tb"), else the sweep_step instantiation with the most launches (in the
+    The sweep kernel is the T-step sweep_block for a time-blocked storage
+    ("-tb", "-tb3", "-tb4"), else the sweep_step instantiation with the most launches (in the
     equilibrium layout the first two steps of a fresh plate run the
     five-plane instantiation, which is left out)."""
     import synth
@@ -509,7 +517,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
         copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
         factor = copy_bytes / (copy * 1024.0)
         names = {}
-        want = "sweep_pair" if time_block(storage) == 2 else "sweep_step"
+        want = block_kernel(storage)
         for r in rows:
             if want in r["Kernel_Name"]:
                 names.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
@@ -559,13 +567,14 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="single plate: autotune each storage before timing (the library's "
                          "defaults are this search's result for the precision plate)")
-    ap.add_argument("--storage", default="f16s-eq-tb-sr",
+    ap.add_argument("--storage", default="f16s-eq-tb4-sr",
                     help='headline storage; "-eq" selects the equilibrium layout, "-eq-tb" that '
-                         'layout with two time steps per sweep, a "-sr" suffix stochastic '
-                         'rounding (e.g. f16s-eq-tb-sr)')
+                         'layout with two time steps per sweep ("-eq-tb3", "-eq-tb4": three, '
+                         'four), a "-sr" suffix stochastic rounding (e.g. f16s-eq-tb4-sr)')
     ap.add_argument("--compare",
                     default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr,"
-                            "f64-eq-tb,f32-eq-tb,f16s-eq-tb-sr,bf16s-eq-tb-sr",
+                            "f16s-eq-tb-sr,f16s-eq-tb3-sr,"
+                            "f64-eq-tb4,f32-eq-tb4,f16s-eq-tb4-sr,bf16s-eq-tb4-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -663,7 +672,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"{'sweep_pair' if tb == 2 else 'sweep_step'} ({args.storage})",
+                "kernel": f"{block_kernel(args.storage)} ({args.storage})",
                 "steps_per_launch": tb, "algorithmic_bytes_per_launch": alg,
                 "kernel_ms": round(head["sweep_ms"] * tb, 4)}
 

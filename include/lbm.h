@@ -253,24 +253,27 @@ int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves,
                    int32_t *occupancy);
 int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy);
 
-/* Time blocking: with steps = 2, lbm_step advances two time steps per sweep
- * (each wave computes step n for its rows and their neighbours in registers,
- * then step n + 1, then stores), halving the bytes moved per step; the crack
- * steps of both time steps still run (K of step n from the crack rows after
- * step n).  FP32 and FP64 results are bit for bit those of steps = 1; 16-bit
- * storages round only every second step.  Needs the equilibrium layout,
+/* Time blocking: with steps = T (2, 3 or 4), lbm_step advances T time steps
+ * per sweep (each wave computes step n for its rows and their neighbours in
+ * registers, then step n + 1 from those, and so on, then stores), so a step
+ * moves 1 / T of the bytes of the one-step sweep; the crack steps of all T
+ * time steps still run, in order (K of step n + k from the crack rows after
+ * step n + k).  FP32 and FP64 results are bit for bit those of steps = 1;
+ * 16-bit storages round only every T-th step.  Needs the equilibrium layout,
  * walls, no sensors, and no crack or a crack along +x with prescribed or no
  * growth (the K criterion decides every step; LBM_EINVAL otherwise).  rows /
  * waves: rows finished per wave (4, 8 or 16) and waves per workgroup
- * (1, 2, 4 or 8) of the two-step sweep (0 = keep; the defaults are the
- * fastest measured on a 16384 x 8192 plate).  An odd step count ends with one
- * single-step sweep.  steps = 1 restores the one-step sweep. */
+ * (1, 2, 4 or 8) of the T-step sweep (0 = keep).  A call whose step count is
+ * not a multiple of T ends with one shorter sweep (one step: the one-step
+ * sweep).  steps = 1 restores the one-step sweep. */
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves);
 
 /* The 16-bit store conversion of the sweep, applied to an array (for
  * inspection and tests of the storage formats): out[i] is the value the sweep
- * of step `step` with seed `seed` stores for a result x[i] at plate-local site
- * index i (i = j nx + i_x) of population plane `plane` (0..4).  storage is
+ * of step `step` with seed `seed` stores for a result x[i] at site (i, 0) of
+ * population plane `plane` (0..4) of a plate with rows of n sites (the
+ * rounding draws depend on the site's row, column and plane, the plate width,
+ * the seed and the step).  storage is
  * LBM_F16S or LBM_BF16S, rounding an enum lbm_rounding.  x (FP32) and out
  * (n 16-bit values) are device pointers; enqueued on `stream` (hipStream_t,
  * NULL = the null stream). */

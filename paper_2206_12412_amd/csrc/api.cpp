@@ -120,7 +120,8 @@ Layout make_layout(const lbm_config &c, Store s) {
   L.off_evC = o; o += align_up((size_t)L.event_cap * 4, 256);
   L.off_evJ = o; o += align_up((size_t)L.event_cap * 4, 256);
   L.off_evO = o; o += align_up((size_t)L.event_cap * 4, 256);
-  L.off_wmid = o; o += align_up((size_t)2 * L.pitch * L.welem, 256);  // two-step sweep: crack rows after step n
+  // T-step sweep: the crack rows after steps n .. n + T - 2
+  L.off_wmid = o; o += align_up((size_t)2 * (lbmk::kMaxTimeBlock - 1) * L.pitch * L.welem, 256);
   L.off_sens = o; o += align_up((size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.off_trS = o; o += align_up(tc * (size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.stage_rows = (int)std::max<int64_t>(1, std::min<int64_t>(c.ny, (1 << 20) / std::max(1, c.nx)));
@@ -264,7 +265,7 @@ struct lbm_handle {
   int timing_stride = 1;  // record the steps whose index is a multiple of this
   std::vector<hipEvent_t> ev_pool;
   std::vector<hipEvent_t> ev_used;  // per timed step: before, after the sweep, after the crack step
-  std::vector<int> ev_steps;        // steps covered by each recorded triple (2: a two-step sweep)
+  std::vector<int> ev_steps;        // steps covered by each recorded triple (T: a T-step sweep)
   double t_sweep = 0, t_crack = 0;
   int64_t n_timed = 0;
   lbmk::DevCrack host_crack{};
@@ -276,10 +277,11 @@ struct lbm_handle {
   // that FP32 cannot hold) are streamed and both buffers are cleared.
   bool eq = false;
   int full_steps = 0;
-  // time blocking: steps per sweep (1, or 2 with the two-step sweep) and the
-  // two-step sweep's rows per wave and waves per workgroup
+  // time blocking: steps per sweep (1, or T = 2..4 with the T-step sweep)
+  // and the T-step sweep's rows per wave and waves per workgroup, per T
   int tblock = 1;
-  int pair_rows = 4, pair_waves = 4;
+  int blk_rows[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 8};
+  int blk_waves[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 4};
   // crack line, wall limits of the tips and the rows a crack can touch
   lbmk::geom::Line line{1, 0.0, 0.0, 1.0, 0.0};
   double a_lo = -0.5, a_hi = 0.0;
@@ -391,12 +393,18 @@ int launch_sweep_typed(lbm_handle *h) {
   return LBM_OK;
 }
 
-// Steps n and n + 1 in one sweep (time blocking, sweep2.hip).
+// Steps n .. n + T - 1 in one sweep (time blocking, sweep2.hip).
 template <typename S, typename W, typename C>
-int launch_pair_typed(lbm_handle *h) {
-  lbmk::PairArgs<S, W, C> A{};
+int launch_block_typed(lbm_handle *h, int T) {
+  lbmk::BlockArgs<S, W, C> A{};
   A.s0 = sweep_args<S, W, C>(h, h->step);
-  A.s1 = sweep_args<S, W, C>(h, h->step + 1);
+  for (int k = 0; k < T; ++k) {
+    const lbmk::SweepArgs<S, W, C> a = sweep_args<S, W, C>(h, h->step + k);
+    A.lv[k] = lbmk::StepLevel<C>{a.t_top, a.t_bot, a.t_up, a.t_lo,
+                                 a.wD_bot, a.wD_top, a.wD_left, a.wD_right};
+    A.rkey_last = a.rkey;
+  }
+  A.steps = T;
   A.wmid = reinterpret_cast<W *>(h->base + h->L.off_wmid);
   A.st = h->crack();
   A.crack = h->cfg.has_crack;
@@ -407,17 +415,17 @@ int launch_pair_typed(lbm_handle *h) {
   A.dt = h->dt;
   A.a_lo = h->a_lo;
   A.a_hi = h->a_hi;
-  HIP_TRY(lbmk::launch_sweep_pair(h->store, &A, h->pair_rows, h->pair_waves, h->stream));
+  HIP_TRY(lbmk::launch_sweep_block(h->store, &A, h->blk_rows[T], h->blk_waves[T], h->stream));
   return LBM_OK;
 }
 
-int launch_pair_any(lbm_handle *h) {
+int launch_block_any(lbm_handle *h, int T) {
   switch (h->store) {
-    case Store::F64S: return launch_pair_typed<double, double, double>(h);
-    case Store::F32S: return launch_pair_typed<float, float, float>(h);
-    case Store::F16S: return launch_pair_typed<_Float16, float, float>(h);
-    case Store::BF16S: return launch_pair_typed<__bf16, float, float>(h);
-    default: return fail(LBM_EINVAL, "the two-step sweep needs the equilibrium layout");
+    case Store::F64S: return launch_block_typed<double, double, double>(h, T);
+    case Store::F32S: return launch_block_typed<float, float, float>(h, T);
+    case Store::F16S: return launch_block_typed<_Float16, float, float>(h, T);
+    case Store::BF16S: return launch_block_typed<__bf16, float, float>(h, T);
+    default: return fail(LBM_EINVAL, "the T-step sweep needs the equilibrium layout");
   }
 }
 
@@ -625,10 +633,15 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
       h->waves = half ? 8 : 4;
       h->occ = 0;
     }
-    // two-step sweep (lbm_set_time_block): 4 rows per wave in 4-wave groups
-    // (the fastest of rows 4 / 8 / 16 x waves 1 / 2 / 4 / 8 for every storage)
-    h->pair_rows = 4;
-    h->pair_waves = 4;
+    // T-step sweep (lbm_set_time_block): rows per wave and waves per group,
+    // the fastest measured on a 16384 x 8192 plate: 4 rows in 4-wave groups
+    // for two and three steps (FP64: 8 rows in 2-wave groups), 8 rows for
+    // four steps in 4-wave groups (16-bit: 2-wave groups)
+    if (is_fp64(s)) {
+      h->blk_rows[2] = h->blk_rows[3] = 8;
+      h->blk_waves[2] = h->blk_waves[3] = 2;
+    }
+    if (half) h->blk_waves[4] = 2;
   }
 
   {
@@ -767,12 +780,13 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
   if (h->in_batch) return fail(LBM_ESTATE, "this plate is stepped by its batch (lbm_batch_step)");
   if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
   for (int64_t k = 0; k < nsteps;) {
-    // two steps in one sweep when time blocking is on and the moving planes
-    // are settled (the five-plane start-up steps run one at a time)
-    const int ns = (h->tblock == 2 && nsteps - k >= 2 && h->full_steps == 0) ? 2 : 1;
+    // T steps in one sweep when time blocking is on and the moving planes
+    // are settled (the five-plane start-up steps run one at a time); fewer
+    // at the end of the call
+    const int ns = h->full_steps == 0 ? (int)std::min<int64_t>(h->tblock, nsteps - k) : 1;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    const bool timed = h->timing && (h->step % h->timing_stride == 0 ||
-                                     (ns == 2 && (h->step + 1) % h->timing_stride == 0));
+    bool timed = false;
+    for (int m = 0; m < ns; ++m) timed |= h->timing && (h->step + m) % h->timing_stride == 0;
     if (timed) {
       for (auto &e : ev) {
         e = take_event(h);
@@ -780,14 +794,14 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
       }
       HIP_TRY(hipEventRecord(ev[0], h->stream));
     }
-    int rc = ns == 2 ? launch_pair_any(h) : launch_sweep_any(h);
+    int rc = ns >= 2 ? launch_block_any(h, ns) : launch_sweep_any(h);
     if (rc != LBM_OK) return rc;
     if (timed) HIP_TRY(hipEventRecord(ev[1], h->stream));
     if (h->crack_step_needed()) {
-      if (ns == 2) {
-        // step n from the crack rows after step n, then step n + 1
+      // steps n .. n + T - 2 from the crack rows after each, then the last
+      for (int m = 0; m + 1 < ns; ++m) {
         lbmk::CrackArgs a = crack_args(h);
-        a.w = h->base + h->L.off_wmid;
+        a.w = h->base + h->L.off_wmid + (size_t)2 * m * h->L.pitch * h->L.welem;
         a.w_row0 = h->plate.j0;
         HIP_TRY(lbmk::launch_crack(a, h->stream));
       }
@@ -1101,25 +1115,29 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
 
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves) {
   if (!h) return fail(LBM_EINVAL, "null handle");
-  if (steps != 1 && steps != 2) return fail(LBM_EINVAL, "steps per sweep must be 1 or 2");
+  if (steps < 1 || steps > lbmk::kMaxTimeBlock)
+    return fail(LBM_EINVAL, "steps per sweep must be 1, 2, 3 or 4");
   if (rows != 0 && rows != 4 && rows != 8 && rows != 16)
     return fail(LBM_EINVAL, "rows must be 4, 8 or 16 (0 = keep)");
   if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
     return fail(LBM_EINVAL, "waves must be 0 (keep), 1, 2, 4 or 8");
-  if (steps == 2) {
+  if (steps == 4 && rows == 16) return fail(LBM_EINVAL, "the four-step sweep takes 4 or 8 rows per wave");
+  if (steps == 1 && (rows != 0 || waves != 0))
+    return fail(LBM_EINVAL, "rows and waves shape the T-step sweep (steps 2..4)");
+  if (steps >= 2) {
     if (!h->eq || h->store == Store::F32_PLAIN || h->store == Store::F64)
-      return fail(LBM_EINVAL, "the two-step sweep needs the equilibrium layout");
-    if (h->cfg.bc_mode == LBM_BC_PERIODIC) return fail(LBM_EINVAL, "the two-step sweep needs walls");
+      return fail(LBM_EINVAL, "the T-step sweep needs the equilibrium layout");
+    if (h->cfg.bc_mode == LBM_BC_PERIODIC) return fail(LBM_EINVAL, "the T-step sweep needs walls");
     if (h->cfg.has_crack && !h->line.aligned)
-      return fail(LBM_EINVAL, "the two-step sweep takes a crack along +x only");
+      return fail(LBM_EINVAL, "the T-step sweep takes a crack along +x only");
     if (h->cfg.growth == LBM_GROW_SIF)
-      return fail(LBM_EINVAL, "the two-step sweep needs prescribed or no growth (the K criterion decides each step)");
-    if (h->cfg.n_sensors > 0) return fail(LBM_EINVAL, "the two-step sweep records no sensors");
+      return fail(LBM_EINVAL, "the T-step sweep needs prescribed or no growth (the K criterion decides each step)");
+    if (h->cfg.n_sensors > 0) return fail(LBM_EINVAL, "the T-step sweep records no sensors");
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->tblock = steps;
-  if (rows > 0) h->pair_rows = rows;
-  if (waves > 0) h->pair_waves = waves;
+  if (rows > 0) h->blk_rows[steps] = rows;
+  if (waves > 0) h->blk_waves[steps] = waves;
   return LBM_OK;
 }
 

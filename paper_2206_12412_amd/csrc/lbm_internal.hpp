@@ -158,15 +158,28 @@ struct SweepArgs {
   C wD_bot, wD_top, wD_left, wD_right;  // their wall values this step
 };
 
-// Arguments of the two-step sweep (sweep2.hip): the per-step arguments of
-// both steps (their traction, wall values and rounding key differ) and the
-// crack state the second step's cut links follow from.
+// Per-step values of one time level of the T-step sweep.
+template <typename C>
+struct StepLevel {
+  C t_top, t_bot, t_up, t_lo;
+  C wD_bot, wD_top, wD_left, wD_right;
+};
+
+constexpr int kMaxTimeBlock = 4;
+
+// Arguments of the T-step sweep (sweep2.hip): the per-step values of the T
+// steps (their traction and wall values differ), the rounding key of the last
+// (the only stores), and the crack state the later steps' cut links follow
+// from.
 template <typename S, typename W, typename C>
-struct PairArgs {
-  SweepArgs<S, W, C> s0, s1;  // steps n and n + 1 (s0 carries the buffers and the shape)
-  W *wmid;                    // w after step n on rows j0 and j0 + 1 ([2][pitch])
-  const DevCrack *st;         // crack state before step n's crack step
-  int crack, both, grow;      // crack present, two tips, prescribed growth
+struct BlockArgs {
+  SweepArgs<S, W, C> s0;              // step n: buffers, shape, constants
+  StepLevel<C> lv[kMaxTimeBlock];     // steps n .. n + T - 1
+  int steps;                          // T = 2, 3 or 4
+  uint32_t rkey_last;                 // rounding key of step n + T - 1
+  W *wmid;                            // w after steps n .. n + T - 2 on rows j0, j0 + 1 ([T - 1][2][pitch])
+  const DevCrack *st;                 // crack state before step n's crack step
+  int crack, both, grow;              // crack present, two tips, prescribed growth
   double v_rel, cs, dt, a_lo, a_hi;
 };
 
@@ -282,9 +295,9 @@ int sweep_vec(Store s);  // sites per lane
 // one sweep step (interior strips and boundary rows in one launch); eq: the
 // equilibrium layout (plane 0 and w only; shifted storages)
 hipError_t launch_sweep(Store s, bool eq, const void *args, hipStream_t st);
-// two steps in one sweep (equilibrium layout, walls, a crack along +x with
-// prescribed or no growth); args is a PairArgs of the storage's types
-hipError_t launch_sweep_pair(Store s, const void *args, int rows, int waves, hipStream_t st);
+// T = 2, 3 or 4 steps in one sweep (equilibrium layout, walls, a crack along
+// +x with prescribed or no growth); args is a BlockArgs of the storage's types
+hipError_t launch_sweep_block(Store s, const void *args, int rows, int waves, hipStream_t st);
 // the 16-bit store conversion of the sweep applied to x[0..n) (F16S / BF16S)
 hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n, int plane,
                           uint32_t rkey, hipStream_t st);

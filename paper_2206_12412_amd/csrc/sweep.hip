@@ -80,16 +80,16 @@ hipError_t launch_r(const void *args, bool eq, hipStream_t st) {
 }
 
 // The store conversion of the sweep applied to an array: element i is the
-// value x[i] stored at plate-local site i of plane `plane`.
+// value x[i] stored at site (i, 0) of plane `plane` of a plate n sites wide.
 template <typename S>
 __global__ void round16_kernel(const float *__restrict__ x, S *__restrict__ out, int64_t n,
                                int plane, uint32_t rkey, int sr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (sr) {
-    uint32_t r[5];
-    core::sr_draws((uint32_t)i, rkey, r);
-    out[i] = core::round_sr<S>(x[i], r[plane]);
+    uint32_t h = mix32(core::sr_pair(0u, (uint32_t)i, (uint32_t)n) ^ rkey);
+    for (int a = 1; a <= plane; ++a) h = mix32(h ^ core::kPlaneSalt);
+    out[i] = core::round_sr<S>(x[i], core::sr_half(h, (uint32_t)i & 1u));
   } else {
     out[i] = static_cast<S>(x[i]);
   }

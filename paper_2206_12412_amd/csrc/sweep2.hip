@@ -1,26 +1,29 @@
-// Two time steps in one sweep (time blocking) for the equilibrium layout:
-// each wave loads the rest population and w of its rows once, computes step
-// n for them and their neighbours in registers, then step n + 1, and stores
-// once, so a step moves half the bytes of the one-step sweep.  The per-site
-// arithmetic is that of the one-step sweep (site_update, sweep_core.hpp) with
-// the same arguments, so FP32 and FP64 results are bit for bit those of two
-// one-step sweeps; 16-bit storages round only after the second step (the
-// intermediate stays in FP32), which is more accurate than two roundings.
+// T time steps in one sweep (time blocking, T = 2, 3 or 4) for the
+// equilibrium layout: each wave loads the rest population and w of its rows
+// once, computes step n for them and their neighbours in registers, then step
+// n + 1 from those, and so on, and stores once, so a step moves 1 / T of the
+// bytes of the one-step sweep.  The per-site arithmetic is that of the
+// one-step sweep (site_update, sweep_core.hpp) with the same arguments, so
+// FP32 and FP64 results are bit for bit those of T one-step sweeps; 16-bit
+// storages round only after the last step (the intermediate levels stay in
+// FP32), which is more accurate than rounding every step.
 //
 // Scope: walls (no periodic wrap), no crack or a crack along +x on its row
-// with prescribed or no growth.  The links step n + 1 sees severed are those
-// of step n plus the ones step n's crack step will sever; with a prescribed
-// speed they follow from the tips alone, computed here with the crack step's
-// own FP64 expressions.  The crack steps of n and n + 1 run afterwards (K of
-// step n from the w of the crack rows after step n, which this kernel also
-// writes out).
+// with prescribed or no growth.  The links step n + k sees severed are those
+// of step n plus the ones the crack steps of n .. n + k - 1 will sever; with
+// a prescribed speed they follow from the tips alone, computed here with the
+// crack step's own FP64 expressions.  The T crack steps run afterwards, in
+// order (K of step n + k < n + T - 1 from the w of the crack rows after that
+// step, which this kernel also writes out).
 //
-// Geometry: a wave owns the columns of a strip of 62 * VEC sites and loads one
-// extra lane of VEC sites on either side (the values there are wrong after a
-// step by one site per step at the outer end, so two steps leave the owned
-// columns exact); it marches rows jb - 2 .. jb + R + 1 to finish rows
-// jb .. jb + R - 1 (R = 4, 8 or 16).  x-neighbours move between lanes with DPP; the plate edges
-// and the severed links are handled per site as in the one-step sweep.
+// Geometry: a wave owns the columns of a strip of (64 - 2H) * VEC sites and
+// loads H extra lanes of VEC sites on either side, H = ceil(T / VEC) (the
+// values there go wrong by one site per step from the outer end, so T steps
+// leave the owned columns exact); it marches rows jb - T .. jb + R + T - 1 to
+// finish rows jb .. jb + R - 1 (R = 4, 8 or 16).  Level k of the march holds
+// the rows after step n + k - 1; level k computes row r - k when state row r
+// arrives.  x-neighbours move between lanes with DPP; the plate edges and the
+// severed links are handled per site as in the one-step sweep.
 #include "crack_core.hpp"
 #include "sweep_core.hpp"
 
@@ -30,12 +33,10 @@ namespace {
 using core::lane_next;
 using core::lane_prev;
 
-constexpr int kOwnLanes = 62;  // lanes 1 .. 62 own their columns
-
 // Workgroups go to the 8 XCDs round robin (workgroup b to XCD b mod 8), each
 // XCD with its own L2.  Renumbering so that XCD x takes a contiguous range of
 // the task order puts vertically adjacent row chunks, which read each other's
-// two halo rows, on the same XCD shortly after one another, so those re-reads
+// halo rows, on the same XCD shortly after one another, so those re-reads
 // hit its L2 instead of HBM.
 __device__ __forceinline__ unsigned xcd_contiguous_block() {
   const unsigned nb = gridDim.x, b = blockIdx.x;
@@ -44,16 +45,38 @@ __device__ __forceinline__ unsigned xcd_contiguous_block() {
   return x * q + min(x, r) + s;
 }
 
-// Per-step values of one time level.
-template <typename C>
-struct Level {
-  C t_top, t_bot, t_up, t_lo;
-  C wD_bot, wD_top, wD_left, wD_right;
-};
+// The finished rows are stored through buffer resources: a lane that owns no
+// columns (a halo lane) passes an offset beyond the resource's size, and the
+// hardware drops such a store, so the row march has no branch around its
+// stores and the compiler can schedule the loads of later rows across them.
+constexpr uint32_t kDropOffset = 0xffffff80u;  // >= the size of any plane (< 4 GiB, 128-byte rows)
+constexpr int kNonTemporal = 2;                // cache policy bit "nt"
 
-template <typename S, typename W, typename C>
-__device__ __forceinline__ Level<C> level_of(const SweepArgs<S, W, C> &a) {
-  return Level<C>{a.t_top, a.t_bot, a.t_up, a.t_lo, a.wD_bot, a.wD_top, a.wD_left, a.wD_right};
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void buffer_store_row(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off,
+                                                 const core::Pack<T, VEC> &pk) {
+  if constexpr (sizeof(pk) == 16) {
+    core::u32x4 v;
+    __builtin_memcpy(&v, &pk, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)byte_off, 0, kNonTemporal);
+  } else {
+    static_assert(sizeof(pk) == 8, "rows are stored in 8- or 16-byte pieces");
+    core::u32x2 v;
+    __builtin_memcpy(&v, &pk, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)byte_off, 0, kNonTemporal);
+  }
+}
+
+// One row of VEC values in the storage type (one 8- or 16-byte load).
+template <typename T, int VEC>
+__device__ __forceinline__ void load_raw(const T *__restrict__ base, uint32_t off, T (&out)[VEC]) {
+  const core::Pack<T, VEC> pk = *reinterpret_cast<const core::Pack<T, VEC> *>(core::at(base, off));
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) out[k] = pk.v[k];
 }
 
 // One step for the VEC sites of a lane on row j: w of rows j - 1, j, j + 1
@@ -66,7 +89,7 @@ __device__ __forceinline__ Level<C> level_of(const SweepArgs<S, W, C> &a) {
 // other rows take the arguments of the one-step sweep's interior rows (no
 // bounce, no traction) without the per-site selects.
 template <typename S, typename W, typename C, int VEC>
-__device__ __forceinline__ void step_row(const SweepArgs<S, W, C> &a, const Level<C> &L, int j,
+__device__ __forceinline__ void step_row(const SweepArgs<S, W, C> &a, const StepLevel<C> &L, int j,
                                          int i0, const C (&wm)[VEC], const C (&wc)[VEC],
                                          const C (&wp)[VEC], const C (&g)[VEC], uint32_t cut_up,
                                          uint32_t cut_dn, bool edge_row, bool edge_strip,
@@ -125,161 +148,258 @@ __device__ __forceinline__ uint32_t range_bits(int i0, int lo, int hi) {
   return b;
 }
 
-// R rows per wave, a compile-time constant so that the row march unrolls and
-// the register windows slide by renaming instead of copies.
-template <typename S, typename W, typename C, int VEC, bool SR, int R>
-__global__ void __launch_bounds__(512)
-sweep_pair(const PairArgs<S, W, C> A, const int n_strips, const int n_chunks) {
+// The row march of one wave: state rows jb - T .. jb + R + T - 1 loaded,
+// level k (step n + k - 1) computed for rows jb - (T - k) .. jb + R - 1 +
+// (T - k), level T stored for rows jb .. jb + R - 1.  FAST (wave-uniform):
+// every row the wave loads lies in the plate, none of the rows it steps is an
+// edge or crack row, and its columns hold no plate edge, so every lane loads,
+// no row needs a range check and every site takes the interior arithmetic.
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int T, bool FAST>
+__device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int strip, const int jb,
+                                      const int lane, const bool edge_strip) {
+  constexpr int H = (T + VEC - 1) / VEC;  // halo lanes on either side
+  constexpr int OW = (64 - 2 * H) * VEC;  // owned columns of a strip
+  constexpr int NR = R + 2 * T;           // state rows loaded
+  constexpr int D = NR < 6 ? NR : 6;      // rows loaded ahead of their first use
   const SweepArgs<S, W, C> &a = A.s0;
   const Plate p = a.p;
+  const int je = FAST ? jb + R : min(jb + R, p.ny);  // rows jb .. je - 1 are finished here
+  const int i0 = strip * OW - H * VEC + lane * VEC;  // first site of this lane (may be < 0)
+  const bool inplate = FAST || ((uint32_t)i0 < (uint32_t)p.nx);
+  // (one unsigned compare and a bitwise and: no branch)
+  const bool own = ((uint32_t)(lane - H) < (uint32_t)(64 - 2 * H)) & inplate;
+  const bool loadable = FAST || (i0 >= 0 && i0 < (int)p.pitch);
+  const uint32_t il = loadable ? (uint32_t)i0 : 0u;
+  const uint32_t pitch = p.pitch;
+  const uint32_t rows_elems = pitch * (uint32_t)p.ny;
+  const __amdgpu_buffer_rsrc_t rf = plane_rsrc(a.fout, rows_elems * (uint32_t)sizeof(S));
+  const __amdgpu_buffer_rsrc_t rw = plane_rsrc(a.wout, rows_elems * (uint32_t)sizeof(W));
+
+  // severed vertical links of the crack row at step n + k: those of step n
+  // plus the ones the crack steps of n .. n + k - 1 sever (prescribed growth;
+  // the tip advance, wall clamp and cut columns of the crack step)
+  uint32_t cut[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) cut[k] = 0u;
+  if (!FAST && A.crack) {
+    if (loadable && i0 < p.nx)
+      cut[0] = (a.mV[(size_t)p.j0 * p.mw + (il >> 5)] >> (il & 31)) & ((1u << VEC) - 1u);
+#pragma unroll
+    for (int k = 1; k < T; ++k) cut[k] = cut[0];
+    if (A.grow) {
+#pragma clang fp contract(off)
+      const DevCrack c = *A.st;
+      const double da = (A.v_rel * A.cs) * A.dt;
+      double tip = c.tip, tipL = c.tipL;
+      bool wall = (c.flags & core::kFlagWall) != 0, wallL = (c.flagsL & core::kFlagWall) != 0;
+#pragma unroll
+      for (int k = 1; k < T; ++k) {
+        uint32_t add = 0u;
+        if (!wall) {
+          double a_new = tip + da;
+          if (a_new >= A.a_hi) {
+            a_new = A.a_hi;
+            wall = true;
+          }
+          add |= range_bits<VEC>(i0, (int)floor(tip) + 1, min((int)floor(a_new), p.nx - 1));
+          tip = a_new;
+        }
+        if (A.both && !wallL) {
+          double a_new = tipL - da;
+          if (a_new <= A.a_lo) {
+            a_new = A.a_lo;
+            wallL = true;
+          }
+          add |= range_bits<VEC>(i0, max((int)ceil(a_new), 0), (int)ceil(tipL) - 1);
+          tipL = a_new;
+        }
+#pragma unroll
+        for (int m = k; m < T; ++m) cut[m] |= add;
+      }
+    }
+  }
+  const int jc = A.crack ? p.j0 : -2;  // crack row (its up-links) and jc + 1 (its down-links)
+
+  // state rows in the storage types, D of them in flight ahead of their use:
+  // on this hardware a wait for a load also waits for every store issued
+  // before it, so each load is issued D rows before the stores it must not
+  // wait for
+  W wl_[NR][VEC];
+  S gl_[NR][VEC];
+  auto load = [&](int rr) {
+    const int r = jb - T + rr;
+    if (FAST || (r >= 0 && r < p.ny && r <= je + T - 1 && loadable)) {
+      const uint32_t o = (uint32_t)r * pitch + il;
+      load_raw<W, VEC>(a.win, o, wl_[rr]);
+      load_raw<S, VEC>(a.fin, o, gl_[rr]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        wl_[rr][k] = W(0);
+        gl_[rr][k] = S(0);
+      }
+    }
+  };
+#pragma unroll
+  for (int rr = 0; rr < D; ++rr) load(rr);
+
+  // level k >= 1 windows: w of its three newest rows (0 = newest), g of its
+  // two newest
+  C wv[T][3][VEC], gv[T][2][VEC];
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    core::zero_row(wv[k][0]);
+    core::zero_row(wv[k][1]);
+    core::zero_row(wv[k][2]);
+    core::zero_row(gv[k][0]);
+    core::zero_row(gv[k][1]);
+  }
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr) {
+    const int r = jb - T + rr;
+    if (!FAST && r > je + T - 1) break;
+    if (rr + D < NR) load(rr + D);
+    // level 0: the state rows r - 2, r - 1, r
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      wv[0][2][k] = wv[0][1][k];
+      wv[0][1][k] = wv[0][0][k];
+      wv[0][0][k] = core::to_c(wl_[rr][k]);
+      gv[0][1][k] = gv[0][0][k];
+      gv[0][0][k] = core::to_c(gl_[rr][k]);
+    }
+#pragma unroll
+    for (int lv = 1; lv <= T; ++lv) {
+      const int q = r - lv;  // the row level lv computes now
+      const bool valid = rr >= 2 * lv && (FAST || (q >= 0 && q < p.ny));
+      const bool er = !FAST && (q == 0 || q == p.ny - 1 || q == jc || q == jc + 1);
+      const uint32_t cu = q == jc ? cut[lv - 1] : 0u, cd = q == jc + 1 ? cut[lv - 1] : 0u;
+      C g2[VEC], w2[VEC];
+      if (valid) {
+        step_row<S, W, C, VEC>(a, A.lv[lv - 1], q, i0, wv[lv - 1][2], wv[lv - 1][1], wv[lv - 1][0],
+                               gv[lv - 1][1], cu, cd, er, !FAST && edge_strip, g2, w2);
+      } else {
+        core::zero_row(g2);
+        core::zero_row(w2);
+      }
+      if (lv < T) {
+        // w of the crack rows after step n + lv - 1, for its crack step
+        if (!FAST && valid && own && (q == jc || q == jc + 1) && q >= jb && q < je)
+          core::store_row<W, C, VEC>(A.wmid, (uint32_t)(2 * (lv - 1) + q - jc) * pitch + il, w2);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          wv[lv][2][k] = wv[lv][1][k];
+          wv[lv][1][k] = wv[lv][0][k];
+          wv[lv][0][k] = w2[k];
+          gv[lv][1][k] = gv[lv][0][k];
+          gv[lv][0][k] = g2[k];
+        }
+      } else if (rr >= 2 * T && (FAST || q < je)) {
+        // the last level: rows jb .. je - 1, stored
+        if (!FAST && i0 + VEC - 1 > p.nx - 1) {
+#pragma unroll
+          for (int k = 0; k < VEC; ++k)
+            if (i0 + k > p.nx - 1) g2[k] = w2[k] = C(0);  // padding stays zero
+        }
+        const uint32_t o = (uint32_t)q * pitch + il;
+        core::Pack<S, VEC> pg;
+        if constexpr (SR) {
+          uint32_t rd[VEC];
+          core::sr_draws0<VEC>(core::sr_pair(q, i0, p.nx), A.rkey_last, rd);
+          pg = core::pack_row_sr<S, C, VEC>(g2, rd);
+        } else {
+          pg = core::pack_row<S, C, VEC>(g2);
+        }
+        buffer_store_row<S, VEC>(rf, own ? o * (uint32_t)sizeof(S) : kDropOffset, pg);
+        buffer_store_row<W, VEC>(rw, own ? o * (uint32_t)sizeof(W) : kDropOffset,
+                                 core::pack_row<W, C, VEC>(w2));
+      }
+    }
+  }
+}
+
+// R rows per wave, a compile-time constant so that the row march unrolls and
+// the register windows slide by renaming instead of copies.
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
+__global__ void __launch_bounds__(512)
+sweep_block(const BlockArgs<S, W, C> A, const int n_strips, const int n_chunks) {
+  constexpr int H = (T + VEC - 1) / VEC;
+  constexpr int OW = (64 - 2 * H) * VEC;
+  const Plate p = A.s0.p;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int task = (int)xcd_contiguous_block() * (int)(blockDim.x >> 6) + wave;
   if (task >= n_strips * n_chunks) return;
   const int strip = task % n_strips;
   const int jb = (task / n_strips) * R;
-  const int je = min(jb + R, p.ny);  // rows jb .. je - 1 are finished here
-  constexpr int OW = kOwnLanes * VEC;
-  const int i0 = strip * OW - VEC + lane * VEC;  // first site of this lane (may be < 0)
-  const bool inplate = i0 >= 0 && i0 < p.nx;
-  const bool own = lane >= 1 && lane <= kOwnLanes && inplate;
-  const bool loadable = i0 >= 0 && i0 < (int)p.pitch;
-  const uint32_t il = loadable ? (uint32_t)i0 : 0u;
-  const uint32_t pitch = p.pitch;
-  const Level<C> L0 = level_of(A.s0), L1 = level_of(A.s1);
-
-  // severed vertical links of the crack row for step n, and for step n + 1
-  // those plus the ones step n's crack step severs (prescribed growth)
-  uint32_t cut0 = 0u, cut1 = 0u;
-  if (A.crack) {
-    if (loadable && i0 < p.nx)
-      cut0 = (a.mV[(size_t)p.j0 * p.mw + (il >> 5)] >> (il & 31)) & ((1u << VEC) - 1u);
-    cut1 = cut0;
-    if (A.grow) {
-#pragma clang fp contract(off)
-      const DevCrack c = *A.st;
-      if (!(c.flags & core::kFlagWall)) {
-        double a_new = c.tip + (A.v_rel * A.cs) * A.dt;
-        if (a_new >= A.a_hi) a_new = A.a_hi;
-        cut1 |= range_bits<VEC>(i0, (int)floor(c.tip) + 1, min((int)floor(a_new), p.nx - 1));
-      }
-      if (A.both && !(c.flagsL & core::kFlagWall)) {
-        double a_new = c.tipL - (A.v_rel * A.cs) * A.dt;
-        if (a_new <= A.a_lo) a_new = A.a_lo;
-        cut1 |= range_bits<VEC>(i0, max((int)ceil(a_new), 0), (int)ceil(c.tipL) - 1);
-      }
-    }
-  }
-  const int jc = A.crack ? p.j0 : -2;  // crack row (its up-links) and jc + 1 (its down-links)
-  // the wave's columns i0 of lanes 0 .. 63 include site 0 or site nx - 1
-  const bool edge_strip = strip == 0 || (strip + 1) * OW + VEC > p.nx - 1;
-
-  // register window: state rows r-2, r-1, r (w) and r-1, r (g); step-n rows
-  // r-3, r-2, r-1 (w) and r-2, r-1 (g)
-  C w_m2[VEC], w_m1[VEC], w_0[VEC], g_m1[VEC], g_0[VEC];
-  C v_m3[VEC], v_m2[VEC], h_m2[VEC];
-  core::zero_row(w_m2);
-  core::zero_row(w_m1);
-  core::zero_row(g_m1);
-  core::zero_row(v_m3);
-  core::zero_row(v_m2);
-  core::zero_row(h_m2);
-#pragma unroll
-  for (int rr = 0; rr < R + 4; ++rr) {
-    const int r = jb - 2 + rr;
-    if (r > je + 1) break;
-    // load state row r
-    if (r >= 0 && r < p.ny && loadable) {
-      const uint32_t o = (uint32_t)r * pitch + il;
-      core::load_row<W, C, VEC>(a.win, o, w_0);
-      core::load_row<S, C, VEC>(a.fin, o, g_0);
-    } else {
-      core::zero_row(w_0);
-      core::zero_row(g_0);
-    }
-    // step n for row r - 1
-    const int q = r - 1;
-    C v_new[VEC], h_new[VEC];
-    if (q >= 0 && q < p.ny && q >= jb - 1) {
-      const bool er = q == 0 || q == p.ny - 1 || q == jc || q == jc + 1;
-      step_row<S, W, C, VEC>(a, L0, q, i0, w_m2, w_m1, w_0, g_m1, q == jc ? cut0 : 0u,
-                             q == jc + 1 ? cut0 : 0u, er, edge_strip, h_new, v_new);
-      if (own && (q == jc || q == jc + 1) && q >= jb && q < je)
-        core::store_row<W, C, VEC>(A.wmid, (uint32_t)(q - jc) * pitch + il, v_new);
-    } else {
-      core::zero_row(v_new);
-      core::zero_row(h_new);
-    }
-    // step n + 1 for row r - 2, stored
-    const int t = r - 2;
-    if (t >= jb && t < je) {
-      C g2[VEC], w2[VEC];
-      const bool er = t == 0 || t == p.ny - 1 || t == jc || t == jc + 1;
-      step_row<S, W, C, VEC>(A.s1, L1, t, i0, v_m3, v_m2, v_new, h_m2, t == jc ? cut1 : 0u,
-                             t == jc + 1 ? cut1 : 0u, er, edge_strip, g2, w2);
-      if (i0 + VEC - 1 > p.nx - 1) {
-#pragma unroll
-        for (int k = 0; k < VEC; ++k)
-          if (i0 + k > p.nx - 1) g2[k] = w2[k] = C(0);  // padding stays zero
-      }
-      if (own) {
-        const uint32_t o = (uint32_t)t * pitch + il;
-        core::store_pops<S, C, VEC, SR, true>(a.fout, p.plane, o, g2, g2, g2, g2, g2,
-                                              (uint32_t)t * p.nx + (uint32_t)i0, A.s1.rkey);
-        core::store_row<W, C, VEC>(a.wout, o, w2);
-      }
-    }
-    // slide the windows
-    copy_row(w_m2, w_m1);
-    copy_row(w_m1, w_0);
-    copy_row(g_m1, g_0);
-    copy_row(v_m3, v_m2);
-    copy_row(v_m2, v_new);
-    copy_row(h_m2, h_new);
-  }
+  // the wave's columns (lanes 0 .. 63) include site 0 or site nx - 1
+  const bool edge_strip = strip == 0 || (strip + 1) * OW + H * VEC - 1 >= p.nx - 1;
+  const int jc = A.crack ? p.j0 : -2;
+  const bool fast = !edge_strip && jb >= T && jb + R + T - 1 <= p.ny - 1 &&
+                    (jc + 1 < jb - (T - 1) || jc > jb + R + T - 2);
+  if (fast)
+    march<S, W, C, VEC, SR, R, T, true>(A, strip, jb, lane, false);
+  else
+    march<S, W, C, VEC, SR, R, T, false>(A, strip, jb, lane, edge_strip);
 }
 
-template <typename S, typename W, typename C, int VEC, bool SR, int R>
-hipError_t pair_t(const PairArgs<S, W, C> &A, int waves, hipStream_t st) {
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
+hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st) {
+  constexpr int H = (T + VEC - 1) / VEC;
+  constexpr int OW = (64 - 2 * H) * VEC;
   const Plate &p = A.s0.p;
-  const int n_strips = (p.nx + kOwnLanes * VEC - 1) / (kOwnLanes * VEC);
+  const int n_strips = (p.nx + OW - 1) / OW;
   const int n_chunks = (p.ny + R - 1) / R;
   const long tasks = (long)n_strips * n_chunks;
   const unsigned blocks = (unsigned)((tasks + waves - 1) / waves);
-  hipLaunchKernelGGL((sweep_pair<S, W, C, VEC, SR, R>), dim3(blocks), dim3(64 * waves), 0, st, A,
-                     n_strips, n_chunks);
+  hipLaunchKernelGGL((sweep_block<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(64 * waves), 0, st,
+                     A, n_strips, n_chunks);
   return hipGetLastError();
 }
 
-template <typename S, typename W, typename C, int VEC, bool SR>
-hipError_t pair_rows(const PairArgs<S, W, C> &A, int rows, int waves, hipStream_t st) {
+// rows 4, 8 or 16 (T = 4: 4 or 8; 16 rows of four levels do not fit the
+// registers)
+template <typename S, typename W, typename C, int VEC, bool SR, int T>
+hipError_t block_rows(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st) {
   switch (rows) {
-    case 4: return pair_t<S, W, C, VEC, SR, 4>(A, waves, st);
-    case 8: return pair_t<S, W, C, VEC, SR, 8>(A, waves, st);
-    case 16: return pair_t<S, W, C, VEC, SR, 16>(A, waves, st);
+    case 4: return block_t<S, W, C, VEC, SR, 4, T>(A, waves, st);
+    case 8: return block_t<S, W, C, VEC, SR, 8, T>(A, waves, st);
+    case 16:
+      if constexpr (T < 4) return block_t<S, W, C, VEC, SR, 16, T>(A, waves, st);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename S, typename W, typename C, int VEC, bool SR>
+hipError_t block_steps(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st) {
+  switch (A.steps) {
+    case 2: return block_rows<S, W, C, VEC, SR, 2>(A, rows, waves, st);
+    case 3: return block_rows<S, W, C, VEC, SR, 3>(A, rows, waves, st);
+    case 4: return block_rows<S, W, C, VEC, SR, 4>(A, rows, waves, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename S, typename W, typename C, int VEC>
-hipError_t pair_r(const void *args, int rows, int waves, hipStream_t st) {
-  const auto &A = *static_cast<const PairArgs<S, W, C> *>(args);
+hipError_t block_r(const void *args, int rows, int waves, hipStream_t st) {
+  const auto &A = *static_cast<const BlockArgs<S, W, C> *>(args);
   if constexpr (sizeof(S) == 2) {
-    if (A.s0.sr) return pair_rows<S, W, C, VEC, true>(A, rows, waves, st);
+    if (A.s0.sr) return block_steps<S, W, C, VEC, true>(A, rows, waves, st);
   }
-  return pair_rows<S, W, C, VEC, false>(A, rows, waves, st);
+  return block_steps<S, W, C, VEC, false>(A, rows, waves, st);
 }
 
 }  // namespace
 
-hipError_t launch_sweep_pair(Store s, const void *args, int rows, int waves, hipStream_t st) {
+hipError_t launch_sweep_block(Store s, const void *args, int rows, int waves, hipStream_t st) {
   if ((rows != 4 && rows != 8 && rows != 16) || (waves != 1 && waves != 2 && waves != 4 && waves != 8))
     return hipErrorInvalidValue;
   switch (s) {
-    case Store::F64S: return pair_r<double, double, double, 2>(args, rows, waves, st);
-    case Store::F32S: return pair_r<float, float, float, 4>(args, rows, waves, st);
-    case Store::F16S: return pair_r<_Float16, float, float, 4>(args, rows, waves, st);
-    case Store::BF16S: return pair_r<__bf16, float, float, 4>(args, rows, waves, st);
+    case Store::F64S: return block_r<double, double, double, 2>(args, rows, waves, st);
+    case Store::F32S: return block_r<float, float, float, 4>(args, rows, waves, st);
+    case Store::F16S: return block_r<_Float16, float, float, 4>(args, rows, waves, st);
+    case Store::BF16S: return block_r<__bf16, float, float, 4>(args, rows, waves, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -131,84 +131,101 @@ __device__ __forceinline__ void store_row(S *__restrict__ base, uint32_t off, co
   }
 }
 
-// Stochastic rounding to 16 bits with 12 random bits r (0..4095): adding r,
-// scaled to the width of the dropped mantissa field, to the FP32 bit pattern
-// and truncating rounds the magnitude up with probability (dropped part) /
-// (16-bit ulp), which makes the rounding unbiased.  In the FP16 subnormal
-// range (|x| < 2^-14, fixed ulp 2^-24) the same is done on the magnitude in
-// units of 2^-24: floor(|x| 2^24 + r / 4096), exact in FP32 there.
+// Stochastic rounding to 16 bits with random bits r (FP16 uses the low 13,
+// BF16 all 16): adding them to the FP32 bit pattern, at the width of the
+// mantissa field the conversion drops, and truncating rounds the magnitude up
+// with probability (dropped part) / (16-bit ulp), which makes the rounding
+// unbiased at FP32 resolution.  Below the smallest FP16 normal (abs(x) <
+// 2^-14, fixed ulp 2^-24) x is first moved by c = +-2^-14 into the binade
+// [2^-14, 2^-13), where the FP32 bit 13 is worth 2^-24 as well, and moved back
+// after the truncation (exact).
 template <typename S> __device__ __forceinline__ S round_sr(float x, uint32_t r);
 template <> __device__ __forceinline__ _Float16 round_sr<_Float16>(float x, uint32_t r) {
-  const uint32_t b = (__float_as_uint(x) + (r << 1)) & 0xffffe000u;
-  const float q = __builtin_floorf(__builtin_fabsf(x) * 0x1p24f + (float)r * 0x1p-12f) * 0x1p-24f;
-  const float y = (__builtin_fabsf(x) >= 0x1p-14f) ? __uint_as_float(b) : __builtin_copysignf(q, x);
-  return static_cast<_Float16>(y);  // exact
+  const float c = (__builtin_fabsf(x) < 0x1p-14f) ? __builtin_copysignf(0x1p-14f, x) : 0.0f;
+  const uint32_t b = (__float_as_uint(x + c) + (r & 0x1fffu)) & 0xffffe000u;
+  return static_cast<_Float16>(__uint_as_float(b) - c);  // exact
 }
 template <> __device__ __forceinline__ __bf16 round_sr<__bf16>(float x, uint32_t r) {
-  const uint32_t b = (__float_as_uint(x) + (r << 4)) & 0xffff0000u;
+  const uint32_t b = (__float_as_uint(x) + (r & 0xffffu)) & 0xffff0000u;
   return static_cast<__bf16>(__uint_as_float(b));  // exact
+}
+
+template <typename S, typename C, int VEC>
+__device__ __forceinline__ Pack<S, VEC> pack_row(const C (&in)[VEC]) {
+  Pack<S, VEC> pk;
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) pk.v[k] = from_c<S>(in[k]);
+  return pk;
+}
+template <typename S, typename C, int VEC>
+__device__ __forceinline__ Pack<S, VEC> pack_row_sr(const C (&in)[VEC], const uint32_t (&r)[VEC]) {
+  Pack<S, VEC> pk;
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) pk.v[k] = round_sr<S>(in[k], r[k]);
+  return pk;
 }
 
 template <typename S, typename C, int VEC>
 __device__ __forceinline__ void store_row_sr(S *__restrict__ base, uint32_t off, const C (&in)[VEC],
                                              const uint32_t (&r)[VEC]) {
-  Pack<S, VEC> pk;
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) pk.v[k] = round_sr<S>(in[k], r[k]);
+  const Pack<S, VEC> pk = pack_row_sr<S, C, VEC>(in, r);
   static_assert(sizeof(pk) == 8, "16-bit rows are stored in 8-byte pieces");
   u32x2 v;
   __builtin_memcpy(&v, &pk, 8);
   __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(at(base, off)));
 }
 
-// The 12-bit rounding draws of the five planes at one site: two hashes of
-// (site, step key); planes 0 and 1 take bits 0..23 of the first, planes 2 and
-// 3 bits 0..23 of the second, plane 4 bits 24..31 of the first and 24..27 of
-// the second.
-__device__ __forceinline__ void sr_draws(uint32_t site, uint32_t rkey, uint32_t (&r)[5]) {
-  const uint32_t h1 = mix32(site ^ rkey);
-  const uint32_t h2 = mix32(h1 ^ 0x68e31da4u);
-  r[0] = h1 & 0xfffu;
-  r[1] = (h1 >> 12) & 0xfffu;
-  r[2] = h2 & 0xfffu;
-  r[3] = (h2 >> 12) & 0xfffu;
-  r[4] = (h1 >> 24) | (((h2 >> 24) & 0xfu) << 8);
+// The rounding draws.  One 32-bit hash serves two horizontally adjacent sites
+// (i even and i + 1 of one row) of one plane: the even site takes bits 0..15,
+// the odd site bits 16..31.  The pairs of a plate are numbered row by row,
+// pair = j * ceil(nx / 2) + i / 2; plane 0's hash of a pair is
+// mix32(pair ^ rkey), plane a's is mix32(plane a - 1's ^ kPlaneSalt).
+constexpr uint32_t kPlaneSalt = 0x68e31da4u;
+__host__ __device__ inline uint32_t sr_pair(uint32_t j, uint32_t i, uint32_t nx) {
+  return j * ((nx + 1u) >> 1) + (i >> 1);
+}
+__device__ __forceinline__ uint32_t sr_half(uint32_t h, uint32_t odd) {
+  return odd ? (h >> 16) : (h & 0xffffu);
+}
+// plane 0's draws of the VEC sites of a lane (pair0: the pair of its first site)
+template <int VEC>
+__device__ __forceinline__ void sr_draws0(uint32_t pair0, uint32_t rkey, uint32_t (&r)[VEC]) {
+  static_assert(VEC % 2 == 0, "rounding draws come in pairs of sites");
+#pragma unroll
+  for (int k = 0; k < VEC / 2; ++k) {
+    const uint32_t h = mix32((pair0 + k) ^ rkey);
+    r[2 * k] = sr_half(h, 0u);
+    r[2 * k + 1] = sr_half(h, 1u);
+  }
 }
 
-// The five population rows of a lane's sites (site0 = plate-local index of
-// the lane's first site); in the equilibrium layout plane 0 only, with the
-// same rounding draw as plane 0 of the five-plane store.
+// The five population rows of a lane's sites (pair0 = the rounding pair of
+// the lane's first site, whose column is even); in the equilibrium layout
+// plane 0 only, with the same rounding draws as plane 0 of the five-plane
+// store.
 template <typename S, typename C, int VEC, bool SR, bool EQ = false>
 __device__ __forceinline__ void store_pops(S *__restrict__ fout, size_t P, uint32_t o,
                                            const C (&o0)[VEC], const C (&o1)[VEC],
                                            const C (&o2)[VEC], const C (&o3)[VEC],
-                                           const C (&o4)[VEC], uint32_t site0, uint32_t rkey) {
-  if constexpr (EQ) {
-    if constexpr (SR) {
-      uint32_t r0[VEC];
+                                           const C (&o4)[VEC], uint32_t pair0, uint32_t rkey) {
+  if constexpr (SR) {
+    static_assert(VEC % 2 == 0, "rounding draws come in pairs of sites");
+    uint32_t h[VEC / 2], r[VEC];
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) r0[k] = mix32((site0 + k) ^ rkey) & 0xfffu;
-      store_row_sr<S, C, VEC>(fout, o, o0, r0);
-    } else {
-      store_row<S, C, VEC>(fout, o, o0);
-    }
-  } else if constexpr (SR) {
-    uint32_t r0[VEC], r1[VEC], r2[VEC], r3[VEC], r4[VEC];
+    for (int k = 0; k < VEC / 2; ++k) h[k] = mix32((pair0 + k) ^ rkey);
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      uint32_t r[5];
-      sr_draws(site0 + k, rkey, r);
-      r0[k] = r[0];
-      r1[k] = r[1];
-      r2[k] = r[2];
-      r3[k] = r[3];
-      r4[k] = r[4];
+    for (int a = 0; a < (EQ ? 1 : 5); ++a) {
+      if (a > 0) {
+#pragma unroll
+        for (int k = 0; k < VEC / 2; ++k) h[k] = mix32(h[k] ^ kPlaneSalt);
+      }
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) r[k] = sr_half(h[k >> 1], k & 1);
+      const C(&oa)[VEC] = a == 0 ? o0 : a == 1 ? o1 : a == 2 ? o2 : a == 3 ? o3 : o4;
+      store_row_sr<S, C, VEC>(fout + a * P, o, oa, r);
     }
-    store_row_sr<S, C, VEC>(fout, o, o0, r0);
-    store_row_sr<S, C, VEC>(fout + P, o, o1, r1);
-    store_row_sr<S, C, VEC>(fout + 2 * P, o, o2, r2);
-    store_row_sr<S, C, VEC>(fout + 3 * P, o, o3, r3);
-    store_row_sr<S, C, VEC>(fout + 4 * P, o, o4, r4);
+  } else if constexpr (EQ) {
+    store_row<S, C, VEC>(fout, o, o0);
   } else {
     store_row<S, C, VEC>(fout, o, o0);
     store_row<S, C, VEC>(fout + P, o, o1);
@@ -248,24 +265,36 @@ __device__ __forceinline__ C dirichlet_term(const A &a, C wstar) {
 // g = f - E(w_emit), E the static equilibrium (E^0 = -A0 w, E^k = Ak w) of
 // the emitting site; wdot and the collision are the same arithmetic regrouped
 // in these variables so that no large term cancels in FP32 (A0 = 4 Ak).
+//
+// The five-point difference is written with the forward differences of the
+// row and of the column, (wr - w0) - (w0 - wl) and (wup - w0) - (w0 - wdn):
+// a site's (w0 - wl) is bit for bit its left neighbour's (wr - w0), and its
+// (w0 - wdn) the lower neighbour's (wup - w0), so a sweep computes one new
+// difference per direction and site.  A traction term is added only where a
+// link bounced (it is zero elsewhere).
+template <typename C>
+__device__ __forceinline__ C lap5(C w0, C wl, C wr, C wdn, C wup) {
+  return ((wr - w0) - (w0 - wl)) + ((wup - w0) - (w0 - wdn));
+}
+
 template <typename C, bool SHIFT, bool EQ = false, typename A>
 __device__ __forceinline__ void site_update(const A &a, C f0, C gl, C gr, C gd, C gu, C w0, C wl,
                                             C wr, C wdn, C wup, bool bd, bool bu, C td, C tu,
                                             C &o0, C &o1, C &o2, C &o3, C &o4, C &wo) {
   static_assert(SHIFT || !EQ, "the equilibrium layout is a shifted layout");
   if constexpr (EQ) {
-    // g^1..g^4 = 0: the five-plane expression below without them
+    // g^1..g^4 = 0: the five-plane expression below without them; at
+    // omega = 1 the relaxed shifted rest population is wdot itself
 #pragma clang fp contract(fast)
-    const C wd = f0 + a.Ak * (((wl - w0) + (wr - w0)) + ((wdn - w0) + (wup - w0))) + (td + tu);
-    const C wn = w0 + a.dt * wd;
-    const C om1 = C(1) - a.omega;
-    o0 = om1 * (f0 + a.A0 * (wn - w0)) + a.omega * wd;
+    C wd = f0 + a.Ak * lap5(w0, wl, wr, wdn, wup);
+    if (bd || bu) wd = wd + (td + tu);
+    o0 = wd;
     o1 = o2 = o3 = o4 = C(0);
-    wo = wn;
+    wo = w0 + a.dt * wd;
   } else if constexpr (SHIFT) {
 #pragma clang fp contract(fast)
-    const C wd = f0 + ((gl + gr) + (gd + gu)) +
-                 a.Ak * (((wl - w0) + (wr - w0)) + ((wdn - w0) + (wup - w0))) + (td + tu);
+    C wd = f0 + ((gl + gr) + (gd + gu)) + a.Ak * lap5(w0, wl, wr, wdn, wup);
+    if (bd || bu) wd = wd + (td + tu);
     const C wn = w0 + a.dt * wd;
     const C om1 = C(1) - a.omega;
     o0 = om1 * (f0 + a.A0 * (wn - w0)) + a.omega * wd;
@@ -432,7 +461,7 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
         if (i0 + k > last) o0[k] = o1[k] = o2[k] = o3[k] = o4[k] = wo[k] = C(0);
     }
     if (act) {
-      store_pops<S, C, VEC, SR, EQ>(fout, P, o, o0, o1, o2, o3, o4, (uint32_t)j * p.nx + i0, a.rkey);
+      store_pops<S, C, VEC, SR, EQ>(fout, P, o, o0, o1, o2, o3, o4, sr_pair(j, i0, p.nx), a.rkey);
       store_row<W, C, VEC>(wout, o, wo);
     }
     if (SHIFT) {
@@ -589,7 +618,7 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
     }
   }
   if (act) {
-    store_pops<S, C, VEC, SR, EQ>(fout, P, o, o0, o1, o2, o3, o4, (uint32_t)j * p.nx + i0, a.rkey);
+    store_pops<S, C, VEC, SR, EQ>(fout, P, o, o0, o1, o2, o3, o4, sr_pair(j, i0, p.nx), a.rkey);
     store_row<W, C, VEC>(wout, o, wo);
   }
 }

@@ -93,11 +93,14 @@ F16_TOL = 4 * 2.0 ** -11 * math.sqrt(T_WIN)
 
 
 def parse(name):
-    """"f16s-eq-tb-sr" -> ("f16s", "stochastic", "eq", 2)"""
+    """"f16s-eq-tb-sr" -> ("f16s", "stochastic", "eq", 2); "-tb3" / "-tb4":
+    three / four steps per sweep"""
     rounding = "stochastic" if name.endswith("-sr") else "nearest"
     name = name[:-3] if name.endswith("-sr") else name
-    tb = 2 if name.endswith("-tb") else 1
-    name = name[:-3] if tb == 2 else name
+    tb = 1
+    for suffix, t in (("-tb", 2), ("-tb3", 3), ("-tb4", 4)):
+        if name.endswith(suffix):
+            name, tb = name[:-len(suffix)], t
     layout = "eq" if name.endswith("-eq") else "full"
     return (name[:-3] if layout == "eq" else name), rounding, layout, tb
 
@@ -106,7 +109,9 @@ def parse(name):
                                          ("f16s-sr", F16_TOL), ("f64-eq", 1e-12),
                                          ("f32-eq", 1e-5), ("f16s-eq-sr", F16_TOL),
                                          ("f64-eq-tb", 1e-12), ("f32-eq-tb", 1e-5),
-                                         ("f16s-eq-tb-sr", F16_TOL)])
+                                         ("f16s-eq-tb-sr", F16_TOL), ("f64-eq-tb4", 1e-12),
+                                         ("f32-eq-tb4", 1e-5), ("f16s-eq-tb3-sr", F16_TOL),
+                                         ("f16s-eq-tb4-sr", F16_TOL)])
 def test_precision_plate_windows(big_plate, storage, tol):
     """The 134M-site plate in the launch configuration the benchmark times
     (the library's default shapes), on sampled windows the oracle computes."""
@@ -118,8 +123,8 @@ def test_precision_plate_windows(big_plate, storage, tol):
                       has_crack=True, crack_x0=p.crack_x0,
                       crack_tip=p.crack_tip, growth=p.growth, v_rel=p.v_rel,
                       tau_hist=p.traction_history(), wdot0=wd0, trace_cap=T))
-    if tb == 2:
-        s.set_time_block(2)
+    if tb > 1:
+        s.set_time_block(tb)
     s.step(T)
     w_g, wd_g = s.fields()
     tip_g = s.traces()["tip"]

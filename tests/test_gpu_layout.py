@@ -214,36 +214,41 @@ def tb_cases(steps):
     }
 
 
+SHAPES = {2: [(16, 4), (4, 1), (8, 8), (4, 2)], 3: [(16, 2), (4, 4), (8, 1)],
+          4: [(4, 8), (8, 4), (4, 1)]}
+
+
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 @pytest.mark.parametrize("name", ["edge-prescribed", "two-tip-dirichlet", "no-crack",
                                   "stationary-tiny", "wall-reached"])
-@pytest.mark.parametrize("rows,waves", [(16, 4), (4, 1), (8, 8), (4, 2)])
-def test_two_step_sweep_equals_one_step_sweeps_bitwise(storage, name, rows, waves):
-    steps = 151  # odd: the last step runs alone
+@pytest.mark.parametrize("T,rows,waves", [(T, r, w) for T in (2, 3, 4) for r, w in SHAPES[T]])
+def test_time_blocked_sweep_equals_one_step_sweeps_bitwise(storage, name, T, rows, waves):
+    steps = 151  # not a multiple of T: the last sweep is shorter
     kw = tb_cases(steps)[name]
-    say(f"two-step sweep {name} {storage} rows={rows} waves={waves}")
+    say(f"{T}-step sweep {name} {storage} rows={rows} waves={waves}")
     one = Solver(Config(storage=storage, layout="eq", **kw))
-    two = Solver(Config(storage=storage, layout="eq", **kw))
-    two.set_time_block(2, rows, waves)
+    blk = Solver(Config(storage=storage, layout="eq", **kw))
+    blk.set_time_block(T, rows, waves)
     for n in (1, 2, 4, 77, steps):
         one.step(n - one.steps_done)
-        two.step(n - two.steps_done)
-        same(one, two, f"{name} {storage} step {n}", kw.get("both_tips", False), kw.get("has_crack", False))
+        blk.step(n - blk.steps_done)
+        same(one, blk, f"{name} {storage} T={T} step {n}", kw.get("both_tips", False),
+             kw.get("has_crack", False))
     one.close()
-    two.close()
+    blk.close()
 
 
+@pytest.mark.parametrize("T", [2, 3, 4])
 @pytest.mark.parametrize("storage", ["f16s", "bf16s"])
-def test_two_step_sweep_16bit_against_the_oracle(storage):
-    """16-bit storage rounds only after the second step: within the derived
-    bound of the oracle, tips and cut events exact, K within the storage's
-    bound."""
+def test_time_blocked_sweep_16bit_against_the_oracle(storage, T):
+    """16-bit storage rounds only after the T-th step: within the derived
+    bound of the oracle, tips and cut events exact."""
     steps = 400
     kw = tb_cases(steps)["two-tip-dirichlet"]
     ref = O.Oracle(O.OracleConfig(**kw))
     ref.step(steps)
     s = Solver(Config(storage=storage, layout="eq", rounding="stochastic", seed=5, **kw))
-    s.set_time_block(2)
+    s.set_time_block(T)
     s.step(steps)
     w_r = ref.fields()[0]
     tol = (4 * 2.0 ** -11 if storage == "f16s" else 4 * 2.0 ** -8) * np.sqrt(steps)
@@ -253,33 +258,58 @@ def test_two_step_sweep_16bit_against_the_oracle(storage):
     assert s.cut_events()[:, 1].tolist() == ref.events()[:, 1].tolist()
 
 
-def test_two_step_sweep_refuses_what_it_cannot_do():
+def test_time_blocked_sweep_refuses_what_it_cannot_do():
     base = tb_cases(10)["edge-prescribed"]
     with pytest.raises(Exception):
         Solver(Config(storage="f32", **base)).set_time_block(2)                    # five planes
     with pytest.raises(Exception):
-        Solver(Config(storage="f32", layout="eq", **dict(base, growth=2, K_C=0.1))).set_time_block(2)
+        Solver(Config(storage="f32", layout="eq", **dict(base, growth=2, K_C=0.1))).set_time_block(3)
     with pytest.raises(Exception):
         Solver(Config(storage="f32", layout="eq", sensors=np.array([[1, 1]]), **base)).set_time_block(2)
     with pytest.raises(Exception):
-        Solver(Config(nx=64, ny=20, storage="f32", layout="eq", periodic=True)).set_time_block(2)
+        Solver(Config(nx=64, ny=20, storage="f32", layout="eq", periodic=True)).set_time_block(4)
+    s = Solver(Config(storage="f32", layout="eq", **base))
+    for bad in [(5, 0, 0), (0, 0, 0), (2, 6, 0), (2, 4, 3), (4, 16, 0), (1, 4, 0)]:
+        with pytest.raises(Exception):
+            s.set_time_block(*bad)
+    s.set_time_block(3, 16, 2)
+    s.set_time_block(4)  # the shape is kept per step count
 
 
-def test_two_step_sweep_timing_and_checkpoints():
+def timed_steps(calls, T, stride):
+    """Steps the per-kernel events cover: a sweep is timed when one of its
+    steps is a multiple of the stride; the two five-plane start-up steps of
+    the equilibrium layout run alone, and a call ends with a shorter sweep
+    when its step count is not a multiple of T."""
+    step, full, total = 0, 2, 0
+    for nsteps in calls:
+        k = 0
+        while k < nsteps:
+            ns = min(T, nsteps - k) if full == 0 else 1
+            if any((step + m) % stride == 0 for m in range(ns)):
+                total += ns
+            step += ns
+            k += ns
+            full = max(full - 1, 0)
+    return total
+
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+def test_time_blocked_sweep_timing_and_checkpoints(T):
     steps = 200
     kw = tb_cases(steps)["edge-prescribed"]
     a = Solver(Config(storage="f32", layout="eq", **kw))
-    a.set_time_block(2)
+    a.set_time_block(T)
     a.timing(True, stride=10)
     a.step(100)
     ck = a.checkpoint()
     a.step(100)
     t = a.timing(False)
-    # steps 0 and 1 run alone (the five-plane start of the layout), step 0
-    # timed; then the pairs starting at a multiple of 10 count two steps each
-    assert t["steps"] == 1 + 2 * 9 + 2 * 10 and t["sweep_ms"] > 0
+    assert t["steps"] == timed_steps([100, 100], T, 10) and t["sweep_ms"] > 0
+    if T == 2:  # steps 0 and 1 alone, step 0 timed; then the pairs from a multiple of 10
+        assert t["steps"] == 1 + 2 * 9 + 2 * 10
     b = Solver(Config(storage="f32", layout="eq", **kw))
-    b.set_time_block(2)
+    b.set_time_block(T)
     b.restore(ck)
     b.step(100)
     same(a, b, "restart", False, True)
