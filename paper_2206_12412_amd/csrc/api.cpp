@@ -798,15 +798,23 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     if (rc != LBM_OK) return rc;
     if (timed) HIP_TRY(hipEventRecord(ev[1], h->stream));
     if (h->crack_step_needed()) {
-      // steps n .. n + T - 2 from the crack rows after each, then the last
-      for (int m = 0; m + 1 < ns; ++m) {
-        lbmk::CrackArgs a = crack_args(h);
-        a.w = h->base + h->L.off_wmid + (size_t)2 * m * h->L.pitch * h->L.welem;
-        a.w_row0 = h->plate.j0;
-        HIP_TRY(lbmk::launch_crack(a, h->stream));
+      if (ns >= 2) {
+        // steps n .. n + T - 2 from the crack rows after each, then the last
+        // from the new state, in one launch
+        lbmk::CrackSeq q{};
+        q.a = crack_args(h);
+        q.n = ns;
+        for (int m = 0; m < ns; ++m) {
+          const bool mid = m + 1 < ns;
+          q.w[m] = mid ? (const void *)(h->base + h->L.off_wmid + (size_t)2 * m * h->L.pitch * h->L.welem)
+                       : q.a.w;
+          q.w_row0[m] = mid ? h->plate.j0 : 0;
+        }
+        HIP_TRY(lbmk::launch_crack_seq(q, h->stream));
+      } else {
+        rc = launch_crack_step(h);
+        if (rc != LBM_OK) return rc;
       }
-      rc = launch_crack_step(h);
-      if (rc != LBM_OK) return rc;
     }
     if (timed) {
       HIP_TRY(hipEventRecord(ev[2], h->stream));

@@ -9,6 +9,19 @@ namespace {
 
 __global__ void __launch_bounds__(64) crack_kernel(const CrackArgs a) { core::crack_step_wave(a); }
 
+// The crack steps of the n time steps one T-step sweep advanced, in order, by
+// one wavefront: step m reads w from w[m] (rows from w_row0[m] on); the
+// barrier makes each step's state, mask and trace writes visible to the next.
+__global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
+  for (int m = 0; m < s.n; ++m) {
+    CrackArgs a = s.a;
+    a.w = s.w[m];
+    a.w_row0 = s.w_row0[m];
+    core::crack_step_wave(a);
+    __syncthreads();
+  }
+}
+
 // Mask words of every row: all links intact except the vertical links of the
 // crack row at the columns lo..hi (the initial crack segment x0 .. a0 touches
 // exactly those, Alg. 1 "as for the initial crack").  With a crack the
@@ -37,6 +50,12 @@ __global__ void init_mask_kernel(uint32_t *mV, uint32_t *mH, MaskRows *mrows, Pl
 
 hipError_t launch_crack(const CrackArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(crack_kernel, dim3(1), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_crack_seq(const CrackSeq &s, hipStream_t st) {
+  if (s.n < 1 || s.n > kMaxTimeBlock) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(crack_seq_kernel, dim3(1), dim3(64), 0, st, s);
   return hipGetLastError();
 }
 

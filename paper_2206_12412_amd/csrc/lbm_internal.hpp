@@ -304,6 +304,15 @@ hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n,
 
 // ---- launchers (crack.hip) ----
 hipError_t launch_crack(const CrackArgs &a, hipStream_t st);
+// the crack steps of the n <= kMaxTimeBlock time steps of one T-step sweep,
+// in order, in one launch
+struct CrackSeq {
+  CrackArgs a;                       // w and w_row0 replaced per step
+  const void *w[kMaxTimeBlock];
+  int32_t w_row0[kMaxTimeBlock];
+  int n;
+};
+hipError_t launch_crack_seq(const CrackSeq &s, hipStream_t st);
 hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const Plate &p,
                             int has_crack, double x0, double a0, hipStream_t st);
 

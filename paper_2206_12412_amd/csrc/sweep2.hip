@@ -63,11 +63,15 @@ __device__ __forceinline__ void buffer_store_row(__amdgpu_buffer_rsrc_t rs, uint
     core::u32x4 v;
     __builtin_memcpy(&v, &pk, 16);
     __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)byte_off, 0, kNonTemporal);
-  } else {
-    static_assert(sizeof(pk) == 8, "rows are stored in 8- or 16-byte pieces");
+  } else if constexpr (sizeof(pk) == 8) {
     core::u32x2 v;
     __builtin_memcpy(&v, &pk, 8);
     __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)byte_off, 0, kNonTemporal);
+  } else {
+    static_assert(sizeof(pk) == 4, "rows are stored in 4-, 8- or 16-byte pieces");
+    uint32_t v;
+    __builtin_memcpy(&v, &pk, 4);
+    __builtin_amdgcn_raw_buffer_store_b32(v, rs, (int)byte_off, 0, kNonTemporal);
   }
 }
 
