@@ -539,7 +539,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
         json.dump(out, fh, indent=1)
     f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
     with open(base + ".md", "w") as fh:
-        fh.write(f"# HBM traffic of sweep_step ({storage}, {workload} workload)\n\n"
+        fh.write(f"# HBM traffic of {block_kernel(storage)} ({storage}, {workload} workload)\n\n"
                  f"Commands (one run per counter, C = FETCH_SIZE then WRITE_SIZE):\n\n    {command}\n\n"
                  f"| counter | KiB / launch | copy of {copy_bytes} B reads | scale | bytes / launch |\n"
                  f"|---|---|---|---|---|\n"
