@@ -71,10 +71,13 @@ enum lbm_flags { LBM_FLAG_GREW = 1, LBM_FLAG_WALL = 2, LBM_FLAG_K_UNDEF = 4 };
 /* Rounding of the FP32 results to the 16-bit storages (LBM_F16S, LBM_BF16S).
  * NEAREST: round to nearest even.  STOCHASTIC: round up or down to a
  * neighbouring 16-bit value with probability proportional to the distance
- * (12 random bits per value from a counter-based hash of the plate-local site
- * index, the step and cfg->seed; FP16 values below 2^-14 round to nearest),
- * so that rounding errors do not accumulate coherently over steps.  Results
- * stay deterministic: they depend on (site, step, seed), not on the launch. */
+ * (random bits added below the kept mantissa: 13 for FP16, 16 for BF16,
+ * exactly the bits the conversion drops, so the rounding is unbiased at FP32
+ * resolution, FP16 subnormals included; one counter-based hash per pair of
+ * horizontally adjacent sites, keyed by the pair's plate-local index, the
+ * step and cfg->seed), so that rounding errors do not accumulate coherently
+ * over steps.  Results stay deterministic: they depend on (site, step, seed),
+ * not on the launch. */
 enum lbm_rounding { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
 /* Plate edges.  An edge is traction-loaded by default (top +tau_n, bottom
  * -tau_n, lateral edges free); an edge whose bit is set in cfg->dirichlet

@@ -95,7 +95,9 @@ def test_stochastic_rounding_is_unbiased(fmt, value, plane):
     p_up = float((out.astype(np.float64) == up).mean())
     p = (xv - lo) / (up - lo)
     sigma = np.sqrt(p * (1 - p) / n)
-    # 12 random bits: the probability is resolved to 2^-12
+    # 13 (FP16) or 16 (BF16) random bits: the probability is resolved to
+    # 2^-13 or better; 2^-12 leaves room for FP16 subnormals, whose move into
+    # the binade [2^-14, 2^-13) rounds at 2^-37
     assert abs(p_up - p) <= 5 * sigma + 2.0 ** -12, (p_up, p, sigma)
     mean = out.astype(np.float64).mean()
     assert abs(mean - xv) <= (up - lo) * (5 * sigma + 2.0 ** -12)
@@ -109,3 +111,19 @@ def test_draws_depend_on_seed_and_step_only():
     d = to_bits(round16(x, "f16s", "stochastic", plane=1, seed=6, step=10))
     np.testing.assert_array_equal(a, b)
     assert (a != c).any() and (a != d).any()
+
+
+@pytest.mark.parametrize("fmt", ["f16s", "bf16s"])
+def test_draws_of_the_two_sites_of_a_pair_are_uncorrelated(fmt):
+    """Two horizontally adjacent sites share one 32-bit hash (16 bits each):
+    their round-up decisions are uncorrelated, and so are those of the same
+    site in two planes (chained hashes)."""
+    n = 1 << 20
+    value = 1.0 + 0.3 * 2.0 ** -10 if fmt == "f16s" else 1.0 + 0.3 * 2.0 ** -7
+    x = np.full(n, value, dtype=np.float32)
+    up = float(neighbours(x[:1], fmt)[1][0])
+    a = round16(dev(x), fmt, "stochastic", plane=0, seed=3, step=5).cpu().float().numpy() == up
+    b = round16(dev(x), fmt, "stochastic", plane=1, seed=3, step=5).cpu().float().numpy() == up
+    bound = 5.0 / np.sqrt(n // 2)
+    assert abs(np.corrcoef(a[0::2], a[1::2])[0, 1]) < bound
+    assert abs(np.corrcoef(a, b)[0, 1]) < 5.0 / np.sqrt(n)
