@@ -8,7 +8,7 @@ FP32, FP16 and BF16 (the last three shifted by the static equilibrium, FP32
 arithmetic), in the five-population layout and in the equilibrium layout
 (rest population and w only; the moving populations are rebuilt from the
 equilibrium of their emitting site, exact at omega = 1), one to four time
-steps per sweep ("-tb", "-tb3", "-tb4": two, three, four steps per sweep,
+steps per sweep ("-tb", "-tb3", "-tb4", "-tb5": two to five steps per sweep,
 each step's crack step still run).  The JSON line reports the headline
 storage's GLUPS (FP16, equilibrium layout, four steps per sweep, stochastic
 rounding) as `value`, next to the
@@ -44,12 +44,12 @@ def parse_storage(name: str):
     """Storage name -> (storage, rounding, layout): a "-sr" suffix selects
     stochastic rounding of the 16-bit stores, an "-eq" part the equilibrium
     layout (rest population and w only), an "-eq-tb" part that layout with
-    two time steps per sweep ("-eq-tb3", "-eq-tb4": three, four), e.g.
+    two time steps per sweep ("-eq-tb3" .. "-eq-tb5": three to five), e.g.
     "f16s-eq-tb3-sr"."""
     rounding = "nearest"
     if name.endswith("-sr"):
         name, rounding = name[:-3], "stochastic"
-    name = re.sub(r"-tb[34]?$", "", name)
+    name = re.sub(r"-tb[345]?$", "", name)
     layout = "full"
     if name.endswith("-eq"):
         name, layout = name[:-3], "eq"
@@ -57,8 +57,8 @@ def parse_storage(name: str):
 
 
 def time_block(name: str) -> int:
-    """Time steps per sweep of a storage name ("-tb": 2, "-tb3": 3, "-tb4": 4)."""
-    m = re.search(r"-tb([34]?)(-|$)", name)
+    """Time steps per sweep of a storage name ("-tb": 2, "-tb3" .. "-tb5": 3 .. 5)."""
+    m = re.search(r"-tb([345]?)(-|$)", name)
     return (int(m.group(1)) if m.group(1) else 2) if m else 1
 
 
@@ -502,7 +502,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
     """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs,
     each scaled by the same counter's reading for a device copy of copy_bytes.
     The sweep kernel is the T-step sweep_block for a time-blocked storage
-    ("-tb", "-tb3", "-tb4"), else the sweep_step instantiation with the most launches (in the
+    ("-tb", "-tb3", "-tb4", "-tb5"), else the sweep_step instantiation with the most launches (in the
     equilibrium layout the first two steps of a fresh plate run the
     five-plane instantiation, which is left out)."""
     import synth
@@ -569,12 +569,12 @@ def main():
                          "defaults are this search's result for the precision plate)")
     ap.add_argument("--storage", default="f16s-eq-tb4-sr",
                     help='headline storage; "-eq" selects the equilibrium layout, "-eq-tb" that '
-                         'layout with two time steps per sweep ("-eq-tb3", "-eq-tb4": three, '
-                         'four), a "-sr" suffix stochastic rounding (e.g. f16s-eq-tb4-sr)')
+                         'layout with two time steps per sweep ("-eq-tb3" .. "-eq-tb5": three to '
+                         'five), a "-sr" suffix stochastic rounding (e.g. f16s-eq-tb4-sr)')
     ap.add_argument("--compare",
                     default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr,"
                             "f16s-eq-tb-sr,f16s-eq-tb3-sr,"
-                            "f64-eq-tb4,f32-eq-tb4,f16s-eq-tb4-sr,bf16s-eq-tb4-sr",
+                            "f64-eq-tb5,f32-eq-tb4,f32-eq-tb5,f16s-eq-tb4-sr,bf16s-eq-tb4-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")

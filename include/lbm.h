@@ -256,7 +256,7 @@ int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves,
                    int32_t *occupancy);
 int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy);
 
-/* Time blocking: with steps = T (2, 3 or 4), lbm_step advances T time steps
+/* Time blocking: with steps = T (2 to 5), lbm_step advances T time steps
  * per sweep (each wave computes step n for its rows and their neighbours in
  * registers, then step n + 1 from those, and so on, then stores), so a step
  * moves 1 / T of the bytes of the one-step sweep; the crack steps of all T
@@ -266,7 +266,8 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * walls, no sensors, and no crack or a crack along +x with prescribed or no
  * growth (the K criterion decides every step; LBM_EINVAL otherwise).  rows /
  * waves: rows finished per wave (4, 8 or 16) and waves per workgroup
- * (1, 2, 4 or 8) of the T-step sweep (0 = keep).  A call whose step count is
+ * (1, 2, 4 or 8) of the T-step sweep for this T (0 = keep; 16 rows only for
+ * T <= 3).  A call whose step count is
  * not a multiple of T ends with one shorter sweep (one step: the one-step
  * sweep).  steps = 1 restores the one-step sweep. */
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves);

@@ -280,8 +280,8 @@ struct lbm_handle {
   // time blocking: steps per sweep (1, or T = 2..4 with the T-step sweep)
   // and the T-step sweep's rows per wave and waves per workgroup, per T
   int tblock = 1;
-  int blk_rows[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 8};
-  int blk_waves[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 4};
+  int blk_rows[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 8, 8};
+  int blk_waves[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 4, 4};
   // crack line, wall limits of the tips and the rows a crack can touch
   lbmk::geom::Line line{1, 0.0, 0.0, 1.0, 0.0};
   double a_lo = -0.5, a_hi = 0.0;
@@ -636,12 +636,12 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     // T-step sweep (lbm_set_time_block): rows per wave and waves per group,
     // the fastest measured on a 16384 x 8192 plate: 4 rows in 4-wave groups
     // for two and three steps (FP64: 8 rows in 2-wave groups), 8 rows for
-    // four steps in 4-wave groups (16-bit: 2-wave groups)
+    // four and five steps in 4-wave groups (16-bit: 2-wave groups)
     if (is_fp64(s)) {
       h->blk_rows[2] = h->blk_rows[3] = 8;
       h->blk_waves[2] = h->blk_waves[3] = 2;
     }
-    if (half) h->blk_waves[4] = 2;
+    if (half) h->blk_waves[4] = h->blk_waves[5] = 2;
   }
 
   {
@@ -1124,12 +1124,12 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (steps < 1 || steps > lbmk::kMaxTimeBlock)
-    return fail(LBM_EINVAL, "steps per sweep must be 1, 2, 3 or 4");
+    return fail(LBM_EINVAL, "steps per sweep must be 1 to 5");
   if (rows != 0 && rows != 4 && rows != 8 && rows != 16)
     return fail(LBM_EINVAL, "rows must be 4, 8 or 16 (0 = keep)");
   if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
     return fail(LBM_EINVAL, "waves must be 0 (keep), 1, 2, 4 or 8");
-  if (steps == 4 && rows == 16) return fail(LBM_EINVAL, "the four-step sweep takes 4 or 8 rows per wave");
+  if (steps >= 4 && rows == 16) return fail(LBM_EINVAL, "sweeps of four or five steps take 4 or 8 rows per wave");
   if (steps == 1 && (rows != 0 || waves != 0))
     return fail(LBM_EINVAL, "rows and waves shape the T-step sweep (steps 2..4)");
   if (steps >= 2) {

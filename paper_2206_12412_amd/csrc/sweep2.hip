@@ -1,4 +1,4 @@
-// T time steps in one sweep (time blocking, T = 2, 3 or 4) for the
+// T time steps in one sweep (time blocking, T = 2 .. 5) for the
 // equilibrium layout: each wave loads the rest population and w of its rows
 // once, computes step n for them and their neighbours in registers, then step
 // n + 1 from those, and so on, and stores once, so a step moves 1 / T of the
@@ -361,8 +361,8 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st) {
   return hipGetLastError();
 }
 
-// rows 4, 8 or 16 (T = 4: 4 or 8; 16 rows of four levels do not fit the
-// registers)
+// rows 4, 8 or 16 (T >= 4: 4 or 8; 16 rows of four or more levels do not
+// fit the registers)
 template <typename S, typename W, typename C, int VEC, bool SR, int T>
 hipError_t block_rows(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st) {
   switch (rows) {
@@ -381,6 +381,7 @@ hipError_t block_steps(const BlockArgs<S, W, C> &A, int rows, int waves, hipStre
     case 2: return block_rows<S, W, C, VEC, SR, 2>(A, rows, waves, st);
     case 3: return block_rows<S, W, C, VEC, SR, 3>(A, rows, waves, st);
     case 4: return block_rows<S, W, C, VEC, SR, 4>(A, rows, waves, st);
+    case 5: return block_rows<S, W, C, VEC, SR, 5>(A, rows, waves, st);
     default: return hipErrorInvalidValue;
   }
 }
