@@ -13,17 +13,20 @@
  *     f_eq^0 = wdot - 2 lambda w / c^2, f_eq^k = lambda w / (2 c^2) (eq. f-eq,
  *     with the zeroth moment of f_eq equal to wdot), lambda = c_s^2 / (dt (tau/dt - 1/2)),
  *     c_s = sqrt(mu / rho), c = kappa c_s, dt = dh / c, dh = 1;
- *   - a straight crack along the mid-line y = ny/2 - 1/2 whose severed links
- *     exchange nothing (Sec. 4.1): the population is bounced back
- *     (traction-free face), as at the plate edges;  a traction t* on a link adds
- *     (dt / (rho dh)) t* to the bounced population;  the top edge carries
- *     sigma_yz = +tau_n, the bottom edge -tau_n, the lateral edges are free;
+ *   - a straight crack (by default along the mid-line y = ny/2 - 1/2; any
+ *     row, a second tip and any prescribed direction are configuration) whose
+ *     severed links exchange nothing (Sec. 4.1): the population is bounced
+ *     back (traction-free face), as at the plate edges;  a traction t* on a
+ *     link adds (dt / (rho dh)) t* to the bounced population;  the top edge
+ *     carries sigma_yz = +tau_n, the bottom edge -tau_n, the lateral edges are
+ *     free, unless an edge holds a prescribed w (Sec. 5.1, 5.2);
  *   - the crack step appended after the time integration (Alg. 1): K_III from
  *     the crack opening at the column i_K = floor(a - r_min), r = a - i_K
  *     (eq. sif, eq. r(v)); growth at a prescribed speed or while K > K_C
  *     with v = v_max tanh(sqrt((K/K_C)^4 - 1)) (eq. sifCriterion, eq. v-tanh);
- *     tip a <- a + (v c_s) dt in FP64; every vertical link of the crack row
- *     with a_prev < i <= a is severed (CheckLinks / ProcessPoints).
+ *     tip a <- a + (v c_s) dt in FP64; every link the new crack segment
+ *     touches is severed (CheckLinks / ProcessPoints; along +x the vertical
+ *     links of the crack row with a_prev < i <= a).
  *
  * Conventions: sites (i, j), i = 0..nx-1 along x, j = 0..ny-1 along y; all
  * host arrays are FP64 row-major [ny][nx] (populations [5][ny][nx]); lengths
