@@ -10,14 +10,14 @@ arithmetic), in the five-population layout and in the equilibrium layout
 equilibrium of their emitting site, exact at omega = 1), one to four time
 steps per sweep ("-tb", "-tb3", "-tb4", "-tb5": two to five steps per sweep,
 each step's crack step still run).  The JSON line reports the headline
-storage's GLUPS (FP16, equilibrium layout, four steps per sweep, stochastic
+storage's GLUPS (FP16, equilibrium layout, five steps per sweep, stochastic
 rounding) as `value`, next to the
 FP32 GLUPS of the same layout and of the five-population layout, each
 storage's K_III and field error against the FP64 run of the same steps, the
 HBM roofline of the sweep kernel and the oracle's CPU throughput on a
 bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb4-sr] [--workload precision]
+    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb5-sr] [--workload precision]
 """
 from __future__ import annotations
 
@@ -567,14 +567,14 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="single plate: autotune each storage before timing (the library's "
                          "defaults are this search's result for the precision plate)")
-    ap.add_argument("--storage", default="f16s-eq-tb4-sr",
+    ap.add_argument("--storage", default="f16s-eq-tb5-sr",
                     help='headline storage; "-eq" selects the equilibrium layout, "-eq-tb" that '
                          'layout with two time steps per sweep ("-eq-tb3" .. "-eq-tb5": three to '
-                         'five), a "-sr" suffix stochastic rounding (e.g. f16s-eq-tb4-sr)')
+                         'five), a "-sr" suffix stochastic rounding (e.g. f16s-eq-tb5-sr)')
     ap.add_argument("--compare",
                     default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr,"
-                            "f16s-eq-tb-sr,f16s-eq-tb3-sr,"
-                            "f64-eq-tb5,f32-eq-tb4,f32-eq-tb5,f16s-eq-tb4-sr,bf16s-eq-tb4-sr",
+                            "f16s-eq-tb-sr,f16s-eq-tb3-sr,f16s-eq-tb4-sr,"
+                            "f64-eq-tb5,f32-eq-tb4,f32-eq-tb5,f16s-eq-tb5-sr,bf16s-eq-tb5-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")

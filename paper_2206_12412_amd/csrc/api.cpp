@@ -277,11 +277,16 @@ struct lbm_handle {
   // that FP32 cannot hold) are streamed and both buffers are cleared.
   bool eq = false;
   int full_steps = 0;
-  // time blocking: steps per sweep (1, or T = 2..4 with the T-step sweep)
+  // time blocking: steps per sweep (1, or T = 2..5 with the T-step sweep)
   // and the T-step sweep's rows per wave and waves per workgroup, per T
   int tblock = 1;
+  // the side stream the T-step sweep's boundary chunks run on beside the
+  // rest, with its fork and join events (created with the first T-step
+  // sweep, on the device current then; default priority)
+  lbmk::SideStream side{nullptr, nullptr, nullptr};
   int blk_rows[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 8, 8};
   int blk_waves[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 4, 4};
+  int blk_occ[lbmk::kMaxTimeBlock + 1] = {0, 0, 0, 0, 0, 0};  // resident waves per SIMD, 0 = no cap
   // crack line, wall limits of the tips and the rows a crack can touch
   lbmk::geom::Line line{1, 0.0, 0.0, 1.0, 0.0};
   double a_lo = -0.5, a_hi = 0.0;
@@ -398,6 +403,11 @@ template <typename S, typename W, typename C>
 int launch_block_typed(lbm_handle *h, int T) {
   lbmk::BlockArgs<S, W, C> A{};
   A.s0 = sweep_args<S, W, C>(h, h->step);
+  A.s0.lds_bytes = 0;
+  if (h->blk_occ[T] > 0) {
+    const int groups = std::max(1, (h->blk_occ[T] * 4) / h->blk_waves[T]);
+    A.s0.lds_bytes = std::min(65536, (h->lds_per_cu / groups) / 256 * 256);
+  }
   for (int k = 0; k < T; ++k) {
     const lbmk::SweepArgs<S, W, C> a = sweep_args<S, W, C>(h, h->step + k);
     A.lv[k] = lbmk::StepLevel<C>{a.t_top, a.t_bot, a.t_up, a.t_lo,
@@ -415,7 +425,13 @@ int launch_block_typed(lbm_handle *h, int T) {
   A.dt = h->dt;
   A.a_lo = h->a_lo;
   A.a_hi = h->a_hi;
-  HIP_TRY(lbmk::launch_sweep_block(h->store, &A, h->blk_rows[T], h->blk_waves[T], h->stream));
+  if (!h->side.side) {
+    HIP_TRY(hipStreamCreateWithFlags(&h->side.side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming));
+  }
+  HIP_TRY(lbmk::launch_sweep_block(h->store, &A, h->blk_rows[T], h->blk_waves[T], h->stream,
+                                   h->side));
   return LBM_OK;
 }
 
@@ -633,15 +649,20 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
       h->waves = half ? 8 : 4;
       h->occ = 0;
     }
-    // T-step sweep (lbm_set_time_block): rows per wave and waves per group,
-    // the fastest measured on a 16384 x 8192 plate: 4 rows in 4-wave groups
-    // for two and three steps (FP64: 8 rows in 2-wave groups), 8 rows for
-    // four and five steps in 4-wave groups (16-bit: 2-wave groups)
-    if (is_fp64(s)) {
-      h->blk_rows[2] = h->blk_rows[3] = 8;
-      h->blk_waves[2] = h->blk_waves[3] = 2;
+    // T-step sweep (lbm_set_time_block): rows per wave, waves per group and
+    // the cap on resident waves per SIMD of the fast launch (0 = none) for
+    // T = 2 .. 5, the fastest measured on a 16384 x 8192 plate
+    static_assert(lbmk::kMaxTimeBlock == 5, "one shape per T = 2 .. 5");
+    static const int kShape[3][4][3] = {
+        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {8, 4, 0}},   // FP16 / BF16
+        {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {8, 2, 3}},   // FP32
+        {{8, 2, 0}, {8, 2, 2}, {8, 4, 2}, {8, 4, 2}}};  // FP64
+    const int kind = half ? 0 : (is_fp64(s) ? 2 : 1);
+    for (int T = 2; T <= lbmk::kMaxTimeBlock; ++T) {
+      h->blk_rows[T] = kShape[kind][T - 2][0];
+      h->blk_waves[T] = kShape[kind][T - 2][1];
+      h->blk_occ[T] = kShape[kind][T - 2][2];
     }
-    if (half) h->blk_waves[4] = h->blk_waves[5] = 2;
   }
 
   {
@@ -1184,9 +1205,15 @@ double lbm_bytes_per_site(const lbm_handle *h) {
 
 void lbm_free(lbm_handle *h) {
   if (!h) return;
-  if (!h->ev_used.empty()) (void)hipStreamSynchronize(h->stream);
+  if (!h->ev_used.empty() || h->side.side) (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->ev_used) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->side.side) {
+    (void)hipStreamSynchronize(h->side.side);
+    (void)hipEventDestroy(h->side.fork);
+    (void)hipEventDestroy(h->side.join);
+    (void)hipStreamDestroy(h->side.side);
+  }
   delete h;
 }
 

@@ -296,8 +296,17 @@ int sweep_vec(Store s);  // sites per lane
 // equilibrium layout (plane 0 and w only; shifted storages)
 hipError_t launch_sweep(Store s, bool eq, const void *args, hipStream_t st);
 // T = 2 .. 5 steps in one sweep (equilibrium layout, walls, a crack along
-// +x with prescribed or no growth); args is a BlockArgs of the storage's types
-hipError_t launch_sweep_block(Store s, const void *args, int rows, int waves, hipStream_t st);
+// +x with prescribed or no growth); args is a BlockArgs of the storage's types.
+// The chunks of the strips without a plate edge run on st; the others (edge
+// strips, the first and last chunk rows, the crack rows) on the side stream
+// side, forked from st by the event fork and joined back into st by join
+// (side == nullptr: both on st, one after the other).
+struct SideStream {
+  hipStream_t side;
+  hipEvent_t fork, join;
+};
+hipError_t launch_sweep_block(Store s, const void *args, int rows, int waves, hipStream_t st,
+                              const SideStream &ss);
 // the 16-bit store conversion of the sweep applied to x[0..n) (F16S / BF16S)
 hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n, int plane,
                           uint32_t rkey, hipStream_t st);

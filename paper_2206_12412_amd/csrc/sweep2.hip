@@ -322,89 +322,192 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
   }
 }
 
-// R rows per wave, a compile-time constant so that the row march unrolls and
-// the register windows slide by renaming instead of copies.
-template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
-__global__ void __launch_bounds__(512)
-sweep_block(const BlockArgs<S, W, C> A, const int n_strips, const int n_chunks) {
+// Whether a strip's columns include site 0 or site nx - 1, and whether a
+// chunk (rows jb .. jb + R - 1) of a strip without such a column takes the
+// fast path: every row it loads lies in the plate and none of the rows it
+// steps is an edge or crack row.
+template <int VEC, int T>
+__host__ __device__ inline bool edge_strip_of(int strip, int nx) {
   constexpr int H = (T + VEC - 1) / VEC;
   constexpr int OW = (64 - 2 * H) * VEC;
+  return strip == 0 || (strip + 1) * OW + H * VEC - 1 >= nx - 1;
+}
+template <int R, int T>
+__host__ __device__ inline bool fast_rows(int jb, int ny, int jc) {
+  return jb >= T && jb + R + T - 1 <= ny - 1 && (jc + 1 < jb - (T - 1) || jc > jb + R + T - 2);
+}
+
+// The chunk rows that strips without a plate edge cannot take on the fast
+// path (the first and last chunk rows, those around the crack rows), for the
+// boundary launch.
+constexpr int kMaxSlowChunks = 16;
+struct SlowChunks {
+  int n;
+  int c[kMaxSlowChunks];
+};
+
+// The fast launch: strips s_lo .. s_hi - 1 (no plate edge) times every chunk
+// row (the slow chunk rows return at once: a few per strip).  Only the fast
+// march is compiled in, so the kernel is sized for the registers of that
+// path alone (in one kernel with the boundary path every wave was sized for
+// the larger of the two).  R rows per wave, a compile-time constant so that
+// the row march unrolls and the register windows slide by renaming instead
+// of copies.
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
+__global__ void __launch_bounds__(512)
+sweep_block(const BlockArgs<S, W, C> A, const int s_lo, const int s_hi, const int n_chunks) {
   const Plate p = A.s0.p;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int task = (int)xcd_contiguous_block() * (int)(blockDim.x >> 6) + wave;
-  if (task >= n_strips * n_chunks) return;
-  const int strip = task % n_strips;
-  const int jb = (task / n_strips) * R;
-  // the wave's columns (lanes 0 .. 63) include site 0 or site nx - 1
-  const bool edge_strip = strip == 0 || (strip + 1) * OW + H * VEC - 1 >= p.nx - 1;
-  const int jc = A.crack ? p.j0 : -2;
-  const bool fast = !edge_strip && jb >= T && jb + R + T - 1 <= p.ny - 1 &&
-                    (jc + 1 < jb - (T - 1) || jc > jb + R + T - 2);
-  if (fast)
-    march<S, W, C, VEC, SR, R, T, true>(A, strip, jb, lane, false);
-  else
-    march<S, W, C, VEC, SR, R, T, false>(A, strip, jb, lane, edge_strip);
+  const int n_int = s_hi - s_lo;
+  if (task >= n_int * n_chunks) return;
+  const int strip = s_lo + task % n_int;
+  const int jb = (task / n_int) * R;
+  if (!fast_rows<R, T>(jb, p.ny, A.crack ? p.j0 : -2)) return;
+  march<S, W, C, VEC, SR, R, T, true>(A, strip, jb, lane, false);
+}
+
+// The boundary launch: every chunk of the strips with a plate edge (strips
+// below s_lo and from s_hi on), then the slow chunk rows of the other strips.
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
+__global__ void __launch_bounds__(256)
+sweep_block_edges(const BlockArgs<S, W, C> A, const int n_strips, const int s_lo, const int s_hi,
+                  const int n_chunks, const SlowChunks sc) {
+  const Plate p = A.s0.p;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int task = (int)(blockIdx.x * (blockDim.x >> 6)) + wave;
+  const int n_int = s_hi - s_lo, n_edge = n_strips - n_int;
+  int strip, chunk;
+  if (task < n_edge * n_chunks) {
+    const int e = task % n_edge;
+    strip = e < s_lo ? e : s_hi + (e - s_lo);
+    chunk = task / n_edge;
+  } else {
+    const int t = task - n_edge * n_chunks;
+    if (t >= n_int * sc.n) return;
+    strip = s_lo + t % n_int;
+    chunk = sc.c[t / n_int];
+  }
+  march<S, W, C, VEC, SR, R, T, false>(A, strip, chunk * R, lane, edge_strip_of<VEC, T>(strip, p.nx));
 }
 
 template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
-hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st) {
+hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const SideStream &ss) {
   constexpr int H = (T + VEC - 1) / VEC;
   constexpr int OW = (64 - 2 * H) * VEC;
   const Plate &p = A.s0.p;
   const int n_strips = (p.nx + OW - 1) / OW;
   const int n_chunks = (p.ny + R - 1) / R;
-  const long tasks = (long)n_strips * n_chunks;
-  const unsigned blocks = (unsigned)((tasks + waves - 1) / waves);
-  hipLaunchKernelGGL((sweep_block<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(64 * waves), 0, st,
-                     A, n_strips, n_chunks);
-  return hipGetLastError();
+  // the strips without a plate edge, s_lo .. s_hi - 1 (the edge strips are
+  // strip 0 and a suffix)
+  const int s_lo = std::min(1, n_strips);
+  int s_hi = n_strips;
+  while (s_hi > s_lo && edge_strip_of<VEC, T>(s_hi - 1, p.nx)) --s_hi;
+  // their slow chunk rows: the first and last ones and those around the
+  // crack rows (every chunk row outside these ranges is fast)
+  SlowChunks sc{};
+  const int jc = A.crack ? p.j0 : -2;
+  bool ok = true;
+  auto add = [&](int c) {
+    if (c < 0 || c >= n_chunks || fast_rows<R, T>(c * R, p.ny, jc)) return;
+    for (int k = 0; k < sc.n; ++k)
+      if (sc.c[k] == c) return;
+    if (sc.n == kMaxSlowChunks) {
+      ok = false;
+      return;
+    }
+    sc.c[sc.n++] = c;
+  };
+  for (int c = 0; c <= T / R + 1; ++c) {
+    add(c);
+    add(n_chunks - 1 - c);
+  }
+  if (A.crack)
+    for (int c = (jc - R - T) / R - 1; c <= (jc + T) / R + 1; ++c) add(c);
+  if (!ok) return hipErrorInvalidValue;
+  // the boundary launch goes first, on the side stream, so that its few
+  // long waves run beside the fast launch instead of after it
+  const long etasks = (long)(n_strips - (s_hi - s_lo)) * n_chunks + (long)(s_hi - s_lo) * sc.n;
+  const bool fork = ss.side != nullptr && etasks > 0 && s_hi > s_lo;
+  hipStream_t est = fork ? ss.side : st;
+  if (fork) {
+    hipError_t e = hipEventRecord(ss.fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ss.side, ss.fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  if (etasks > 0) {
+    const unsigned blocks = (unsigned)((etasks + 3) / 4);
+    hipLaunchKernelGGL((sweep_block_edges<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(256), 0, est,
+                       A, n_strips, s_lo, s_hi, n_chunks, sc);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (s_hi > s_lo) {
+    const long tasks = (long)(s_hi - s_lo) * n_chunks;
+    const unsigned blocks = (unsigned)((tasks + waves - 1) / waves);
+    // dynamic LDS only to cap the resident waves (s0.lds_bytes, 0 = no cap)
+    hipLaunchKernelGGL((sweep_block<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(64 * waves),
+                       (unsigned)A.s0.lds_bytes, st, A, s_lo, s_hi, n_chunks);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (fork) {
+    hipError_t e = hipEventRecord(ss.join, ss.side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ss.join, 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // rows 4, 8 or 16 (T >= 4: 4 or 8; 16 rows of four or more levels do not
 // fit the registers)
 template <typename S, typename W, typename C, int VEC, bool SR, int T>
-hipError_t block_rows(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st) {
+hipError_t block_rows(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st,
+                      const SideStream &ss) {
   switch (rows) {
-    case 4: return block_t<S, W, C, VEC, SR, 4, T>(A, waves, st);
-    case 8: return block_t<S, W, C, VEC, SR, 8, T>(A, waves, st);
+    case 4: return block_t<S, W, C, VEC, SR, 4, T>(A, waves, st, ss);
+    case 8: return block_t<S, W, C, VEC, SR, 8, T>(A, waves, st, ss);
     case 16:
-      if constexpr (T < 4) return block_t<S, W, C, VEC, SR, 16, T>(A, waves, st);
+      if constexpr (T < 4) return block_t<S, W, C, VEC, SR, 16, T>(A, waves, st, ss);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename S, typename W, typename C, int VEC, bool SR>
-hipError_t block_steps(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st) {
+hipError_t block_steps(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st,
+                       const SideStream &ss) {
   switch (A.steps) {
-    case 2: return block_rows<S, W, C, VEC, SR, 2>(A, rows, waves, st);
-    case 3: return block_rows<S, W, C, VEC, SR, 3>(A, rows, waves, st);
-    case 4: return block_rows<S, W, C, VEC, SR, 4>(A, rows, waves, st);
-    case 5: return block_rows<S, W, C, VEC, SR, 5>(A, rows, waves, st);
+    case 2: return block_rows<S, W, C, VEC, SR, 2>(A, rows, waves, st, ss);
+    case 3: return block_rows<S, W, C, VEC, SR, 3>(A, rows, waves, st, ss);
+    case 4: return block_rows<S, W, C, VEC, SR, 4>(A, rows, waves, st, ss);
+    case 5: return block_rows<S, W, C, VEC, SR, 5>(A, rows, waves, st, ss);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename S, typename W, typename C, int VEC>
-hipError_t block_r(const void *args, int rows, int waves, hipStream_t st) {
+hipError_t block_r(const void *args, int rows, int waves, hipStream_t st, const SideStream &ss) {
   const auto &A = *static_cast<const BlockArgs<S, W, C> *>(args);
   if constexpr (sizeof(S) == 2) {
-    if (A.s0.sr) return block_steps<S, W, C, VEC, true>(A, rows, waves, st);
+    if (A.s0.sr) return block_steps<S, W, C, VEC, true>(A, rows, waves, st, ss);
   }
-  return block_steps<S, W, C, VEC, false>(A, rows, waves, st);
+  return block_steps<S, W, C, VEC, false>(A, rows, waves, st, ss);
 }
 
 }  // namespace
 
-hipError_t launch_sweep_block(Store s, const void *args, int rows, int waves, hipStream_t st) {
+hipError_t launch_sweep_block(Store s, const void *args, int rows, int waves, hipStream_t st,
+                              const SideStream &ss) {
   if ((rows != 4 && rows != 8 && rows != 16) || (waves != 1 && waves != 2 && waves != 4 && waves != 8))
     return hipErrorInvalidValue;
   switch (s) {
-    case Store::F64S: return block_r<double, double, double, 2>(args, rows, waves, st);
-    case Store::F32S: return block_r<float, float, float, 4>(args, rows, waves, st);
-    case Store::F16S: return block_r<_Float16, float, float, 4>(args, rows, waves, st);
-    case Store::BF16S: return block_r<__bf16, float, float, 4>(args, rows, waves, st);
+    case Store::F64S: return block_r<double, double, double, 2>(args, rows, waves, st, ss);
+    case Store::F32S: return block_r<float, float, float, 4>(args, rows, waves, st, ss);
+    case Store::F16S: return block_r<_Float16, float, float, 4>(args, rows, waves, st, ss);
+    case Store::BF16S: return block_r<__bf16, float, float, 4>(args, rows, waves, st, ss);
     default: return hipErrorInvalidValue;
   }
 }

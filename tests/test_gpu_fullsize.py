@@ -112,7 +112,7 @@ def parse(name):
                                          ("f16s-eq-tb-sr", F16_TOL), ("f64-eq-tb5", 1e-12),
                                          ("f32-eq-tb5", 1e-5), ("f64-eq-tb4", 1e-12),
                                          ("f32-eq-tb4", 1e-5), ("f16s-eq-tb3-sr", F16_TOL),
-                                         ("f16s-eq-tb4-sr", F16_TOL)])
+                                         ("f16s-eq-tb4-sr", F16_TOL), ("f16s-eq-tb5-sr", F16_TOL)])
 def test_precision_plate_windows(big_plate, storage, tol):
     """The 134M-site plate in the launch configuration the benchmark times
     (the library's default shapes), on sampled windows the oracle computes."""
