@@ -501,10 +501,12 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
                   command: str, out_dir: str):
     """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs,
     each scaled by the same counter's reading for a device copy of copy_bytes.
-    The sweep kernel is the T-step sweep_block for a time-blocked storage
-    ("-tb", "-tb3", "-tb4", "-tb5"), else the sweep_step instantiation with the most launches (in the
+    The sweep is the sweep_step instantiation with the most launches (in the
     equilibrium layout the first two steps of a fresh plate run the
-    five-plane instantiation, which is left out)."""
+    five-plane instantiation, which is left out); for a time-blocked storage
+    ("-tb", "-tb3" .. "-tb5") the T-step sweep, whose two launches (sweep_block
+    over the strips without a plate edge, sweep_block_edges over the rest) are
+    summed, each the instantiation with the most launches."""
     import synth
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
          "plain": synth.config_plain_fp64}[workload]()
@@ -516,18 +518,27 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
                 if r["Counter_Name"] == counter]
         copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
         factor = copy_bytes / (copy * 1024.0)
-        names = {}
-        want = block_kernel(storage)
-        for r in rows:
-            if want in r["Kernel_Name"]:
-                names.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        name = max(names, key=lambda k: len(names[k]))
-        vals = names[name]
-        kib = sum(vals) / len(vals)
+        tb = time_block(storage)
+        parts = ["sweep_block_edges", "sweep_block"] if tb >= 2 else ["sweep_step"]
+        # the instantiation of this storage's T (a run's last sweep may be shorter)
+        of_t = (lambda k: True) if tb < 2 else \
+            (lambda k: f"ELi{tb}EEEvNS_9BlockArgs" in k or f", {tb}>(lbmk::BlockArgs" in k)
+        kib, picked, other = 0.0, [], {}
+        for want in parts:
+            names = {}
+            for r in rows:
+                k = r["Kernel_Name"]
+                if want in k and of_t(k) and not any(q in k for q in parts if q != want and want in q):
+                    names.setdefault(k, []).append(float(r["Counter_Value"]))
+            name = max(names, key=lambda k: len(names[k]))
+            vals = names[name]
+            kib += sum(vals) / len(vals)
+            picked.append((name[:160], len(vals)))
+            other.update({k[:160]: len(v) for k, v in names.items() if k != name})
         out[counter] = {"KiB_per_launch": kib, "copy_KiB": copy, "factor": factor,
-                        "bytes_per_launch": kib * 1024.0 * factor, "launches": len(vals),
-                        "kernel": name[:160],
-                        "other_sweep_launches": {k[:160]: len(v) for k, v in names.items() if k != name}}
+                        "bytes_per_launch": kib * 1024.0 * factor,
+                        "launches": picked[-1][1], "kernels": picked,
+                        "other_sweep_launches": other}
         total += kib * 1024.0 * factor
     bps = sweep_bytes_per_site(storage)
     sites = p.nx * p.ny

@@ -654,7 +654,7 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     // T = 2 .. 5, the fastest measured on a 16384 x 8192 plate
     static_assert(lbmk::kMaxTimeBlock == 5, "one shape per T = 2 .. 5");
     static const int kShape[3][4][3] = {
-        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {8, 4, 0}},   // FP16 / BF16
+        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {8, 8, 0}},   // FP16 / BF16
         {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {8, 2, 3}},   // FP32
         {{8, 2, 0}, {8, 2, 2}, {8, 4, 2}, {8, 4, 2}}};  // FP64
     const int kind = half ? 0 : (is_fp64(s) ? 2 : 1);
