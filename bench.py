@@ -8,16 +8,16 @@ FP32, FP16 and BF16 (the last three shifted by the static equilibrium, FP32
 arithmetic), in the five-population layout and in the equilibrium layout
 (rest population and w only; the moving populations are rebuilt from the
 equilibrium of their emitting site, exact at omega = 1), one to four time
-steps per sweep ("-tb", "-tb3", "-tb4", "-tb5": two to five steps per sweep,
+steps per sweep ("-tb", "-tb3" .. "-tb8": two to eight steps per sweep,
 each step's crack step still run).  The JSON line reports the headline
-storage's GLUPS (FP16, equilibrium layout, five steps per sweep, stochastic
+storage's GLUPS (FP16, equilibrium layout, six steps per sweep, stochastic
 rounding) as `value`, next to the
 FP32 GLUPS of the same layout and of the five-population layout, each
 storage's K_III and field error against the FP64 run of the same steps, the
 HBM roofline of the sweep kernel and the oracle's CPU throughput on a
 bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb5-sr] [--workload precision]
+    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb6-sr] [--workload precision]
 """
 from __future__ import annotations
 
@@ -44,12 +44,12 @@ def parse_storage(name: str):
     """Storage name -> (storage, rounding, layout): a "-sr" suffix selects
     stochastic rounding of the 16-bit stores, an "-eq" part the equilibrium
     layout (rest population and w only), an "-eq-tb" part that layout with
-    two time steps per sweep ("-eq-tb3" .. "-eq-tb5": three to five), e.g.
+    two time steps per sweep ("-eq-tb3" .. "-eq-tb8": three to eight), e.g.
     "f16s-eq-tb3-sr"."""
     rounding = "nearest"
     if name.endswith("-sr"):
         name, rounding = name[:-3], "stochastic"
-    name = re.sub(r"-tb[345]?$", "", name)
+    name = re.sub(r"-tb[2-8]?$", "", name)
     layout = "full"
     if name.endswith("-eq"):
         name, layout = name[:-3], "eq"
@@ -57,8 +57,8 @@ def parse_storage(name: str):
 
 
 def time_block(name: str) -> int:
-    """Time steps per sweep of a storage name ("-tb": 2, "-tb3" .. "-tb5": 3 .. 5)."""
-    m = re.search(r"-tb([345]?)(-|$)", name)
+    """Time steps per sweep of a storage name ("-tb": 2, "-tb3" .. "-tb8": 3 .. 8)."""
+    m = re.search(r"-tb([2-8]?)(-|$)", name)
     return (int(m.group(1)) if m.group(1) else 2) if m else 1
 
 
@@ -89,7 +89,8 @@ def plate_config(p, storage, trace_cap):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep2.hip", "sweep_core.hpp", "lbm_internal.hpp"):
+    for f in ("sweep.hip", "sweep2.hip", "sweep_block.hpp", "sweep_block_f64.hip", "sweep_block_f32.hip",
+              "sweep_block_f16.hip", "sweep_block_bf16.hip", "sweep_core.hpp", "lbm_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2206_12412_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -504,7 +505,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
     The sweep is the sweep_step instantiation with the most launches (in the
     equilibrium layout the first two steps of a fresh plate run the
     five-plane instantiation, which is left out); for a time-blocked storage
-    ("-tb", "-tb3" .. "-tb5") the T-step sweep, whose two launches (sweep_block
+    ("-tb", "-tb3" .. "-tb8") the T-step sweep, whose two launches (sweep_block
     over the strips without a plate edge, sweep_block_edges over the rest) are
     summed, each the instantiation with the most launches."""
     import synth
@@ -578,14 +579,14 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="single plate: autotune each storage before timing (the library's "
                          "defaults are this search's result for the precision plate)")
-    ap.add_argument("--storage", default="f16s-eq-tb5-sr",
+    ap.add_argument("--storage", default="f16s-eq-tb6-sr",
                     help='headline storage; "-eq" selects the equilibrium layout, "-eq-tb" that '
-                         'layout with two time steps per sweep ("-eq-tb3" .. "-eq-tb5": three to '
-                         'five), a "-sr" suffix stochastic rounding (e.g. f16s-eq-tb5-sr)')
+                         'layout with two time steps per sweep ("-eq-tb3" .. "-eq-tb8": three to '
+                         'eight), a "-sr" suffix stochastic rounding (e.g. f16s-eq-tb6-sr)')
     ap.add_argument("--compare",
                     default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr,"
-                            "f16s-eq-tb-sr,f16s-eq-tb3-sr,f16s-eq-tb4-sr,"
-                            "f64-eq-tb5,f32-eq-tb4,f32-eq-tb5,f16s-eq-tb5-sr,bf16s-eq-tb5-sr",
+                            "f16s-eq-tb-sr,f16s-eq-tb4-sr,"
+                            "f64-eq-tb8,f32-eq-tb6,f32-eq-tb8,f16s-eq-tb6-sr,bf16s-eq-tb6-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")

@@ -263,7 +263,7 @@ int lbm_get_launch(lbm_handle *h, int32_t *vec, int32_t *rows, int32_t *waves,
                    int32_t *occupancy);
 int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy);
 
-/* Time blocking: with steps = T (2 to 5), lbm_step advances T time steps
+/* Time blocking: with steps = T (2 to 8), lbm_step advances T time steps
  * per sweep (each wave computes step n for its rows and their neighbours in
  * registers, then step n + 1 from those, and so on, then stores), so a step
  * moves 1 / T of the bytes of the one-step sweep; the crack steps of all T
@@ -273,10 +273,10 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * walls, no sensors, and no crack or a crack along +x with prescribed or no
  * growth (the K criterion decides every step; LBM_EINVAL otherwise).  rows /
  * waves: rows finished per wave (4, 8 or 16) and waves per workgroup
- * (1, 2, 4 or 8) of the T-step sweep for this T (0 = keep; 16 rows only for
- * T <= 3; the defaults, and a cap on the resident waves per SIMD for FP32 and
- * FP64 with four or five steps, are the fastest measured on a 16384 x 8192
- * plate).  A call whose step count is
+ * (1, 2, 4 or 8) of the T-step sweep for this T (0 = keep; T >= 6: 16 rows
+ * only; the defaults, and
+ * a cap on the resident waves per SIMD, are the fastest measured on a
+ * 16384 x 8192 plate).  A call whose step count is
  * not a multiple of T ends with one shorter sweep (one step: the one-step
  * sweep).  steps = 1 restores the one-step sweep. */
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves);

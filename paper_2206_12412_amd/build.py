@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmcrack.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["api.cpp", "sweep.hip", "sweep2.hip", "crack.hip", "batch.hip", "io.hip", "adjoint.hip"]
+SOURCES = ["api.cpp", "sweep.hip", "sweep2.hip", "sweep_block_f64.hip", "sweep_block_f32.hip",
+           "sweep_block_f16.hip", "sweep_block_bf16.hip", "crack.hip", "batch.hip", "io.hip", "adjoint.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

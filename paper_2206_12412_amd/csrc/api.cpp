@@ -284,9 +284,9 @@ struct lbm_handle {
   // rest, with its fork and join events (created with the first T-step
   // sweep, on the device current then; default priority)
   lbmk::SideStream side{nullptr, nullptr, nullptr};
-  int blk_rows[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 8, 8};
-  int blk_waves[lbmk::kMaxTimeBlock + 1] = {0, 0, 4, 4, 4, 4};
-  int blk_occ[lbmk::kMaxTimeBlock + 1] = {0, 0, 0, 0, 0, 0};  // resident waves per SIMD, 0 = no cap
+  int blk_rows[lbmk::kMaxTimeBlock + 1] = {};
+  int blk_waves[lbmk::kMaxTimeBlock + 1] = {};
+  int blk_occ[lbmk::kMaxTimeBlock + 1] = {};  // resident waves per SIMD, 0 = no cap
   // crack line, wall limits of the tips and the rows a crack can touch
   lbmk::geom::Line line{1, 0.0, 0.0, 1.0, 0.0};
   double a_lo = -0.5, a_hi = 0.0;
@@ -651,12 +651,12 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     }
     // T-step sweep (lbm_set_time_block): rows per wave, waves per group and
     // the cap on resident waves per SIMD of the fast launch (0 = none) for
-    // T = 2 .. 5, the fastest measured on a 16384 x 8192 plate
-    static_assert(lbmk::kMaxTimeBlock == 5, "one shape per T = 2 .. 5");
-    static const int kShape[3][4][3] = {
-        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {8, 8, 0}},   // FP16 / BF16
-        {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {8, 2, 3}},   // FP32
-        {{8, 2, 0}, {8, 2, 2}, {8, 4, 2}, {8, 4, 2}}};  // FP64
+    // T = 2 .. 8, the fastest measured on a 16384 x 8192 plate
+    static_assert(lbmk::kMaxTimeBlock == 8, "one shape per T = 2 .. 8");
+    static const int kShape[3][7][3] = {
+        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {16, 2, 3}, {16, 4, 0}, {16, 4, 3}, {16, 4, 3}},   // 16-bit
+        {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}},   // FP32
+        {{8, 2, 0}, {8, 2, 2}, {8, 4, 2}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}}};  // FP64
     const int kind = half ? 0 : (is_fp64(s) ? 2 : 1);
     for (int T = 2; T <= lbmk::kMaxTimeBlock; ++T) {
       h->blk_rows[T] = kShape[kind][T - 2][0];
@@ -1145,12 +1145,13 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (steps < 1 || steps > lbmk::kMaxTimeBlock)
-    return fail(LBM_EINVAL, "steps per sweep must be 1 to 5");
+    return fail(LBM_EINVAL, "steps per sweep must be 1 to 8");
   if (rows != 0 && rows != 4 && rows != 8 && rows != 16)
     return fail(LBM_EINVAL, "rows must be 4, 8 or 16 (0 = keep)");
   if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
     return fail(LBM_EINVAL, "waves must be 0 (keep), 1, 2, 4 or 8");
-  if (steps >= 4 && rows == 16) return fail(LBM_EINVAL, "sweeps of four or five steps take 4 or 8 rows per wave");
+  if (steps >= 6 && rows != 0 && rows != 16)
+    return fail(LBM_EINVAL, "sweeps of six or more steps take 16 rows per wave");
   if (steps == 1 && (rows != 0 || waves != 0))
     return fail(LBM_EINVAL, "rows and waves shape the T-step sweep (steps 2..4)");
   if (steps >= 2) {

@@ -165,7 +165,7 @@ struct StepLevel {
   C wD_bot, wD_top, wD_left, wD_right;
 };
 
-constexpr int kMaxTimeBlock = 5;
+constexpr int kMaxTimeBlock = 8;
 
 // Arguments of the T-step sweep (sweep2.hip): the per-step values of the T
 // steps (their traction and wall values differ), the rounding key of the last
@@ -175,7 +175,7 @@ template <typename S, typename W, typename C>
 struct BlockArgs {
   SweepArgs<S, W, C> s0;              // step n: buffers, shape, constants
   StepLevel<C> lv[kMaxTimeBlock];     // steps n .. n + T - 1
-  int steps;                          // T = 2 .. 5
+  int steps;                          // T = 2 .. 8
   uint32_t rkey_last;                 // rounding key of step n + T - 1
   W *wmid;                            // w after steps n .. n + T - 2 on rows j0, j0 + 1 ([T - 1][2][pitch])
   const DevCrack *st;                 // crack state before step n's crack step
@@ -295,7 +295,7 @@ int sweep_vec(Store s);  // sites per lane
 // one sweep step (interior strips and boundary rows in one launch); eq: the
 // equilibrium layout (plane 0 and w only; shifted storages)
 hipError_t launch_sweep(Store s, bool eq, const void *args, hipStream_t st);
-// T = 2 .. 5 steps in one sweep (equilibrium layout, walls, a crack along
+// T = 2 .. 8 steps in one sweep (equilibrium layout, walls, a crack along
 // +x with prescribed or no growth); args is a BlockArgs of the storage's types.
 // The chunks of the strips without a plate edge run on st; the others (edge
 // strips, the first and last chunk rows, the crack rows) on the side stream

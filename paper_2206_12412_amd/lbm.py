@@ -485,7 +485,7 @@ class Solver:
         _check(self._lib.lbm_set_launch(self._h, int(rows), int(waves), int(occupancy)))
 
     def set_time_block(self, steps: int = 2, rows: int = 0, waves: int = 0):
-        """Advance `steps` (1 to 5) time steps per sweep; see lbm_set_time_block."""
+        """Advance `steps` (1 to 8) time steps per sweep; see lbm_set_time_block."""
         _check(self._lib.lbm_set_time_block(self._h, int(steps), int(rows), int(waves)))
 
     def autotune(self, trial_steps: int = 8) -> dict:

@@ -93,12 +93,12 @@ F16_TOL = 4 * 2.0 ** -11 * math.sqrt(T_WIN)
 
 
 def parse(name):
-    """"f16s-eq-tb-sr" -> ("f16s", "stochastic", "eq", 2); "-tb3" .. "-tb5":
-    three to five steps per sweep"""
+    """"f16s-eq-tb-sr" -> ("f16s", "stochastic", "eq", 2); "-tb3" .. "-tb8":
+    three to eight steps per sweep"""
     rounding = "stochastic" if name.endswith("-sr") else "nearest"
     name = name[:-3] if name.endswith("-sr") else name
     tb = 1
-    for suffix, t in (("-tb", 2), ("-tb3", 3), ("-tb4", 4), ("-tb5", 5)):
+    for suffix, t in (("-tb", 2),) + tuple((f"-tb{k}", k) for k in range(3, 9)):
         if name.endswith(suffix):
             name, tb = name[:-len(suffix)], t
     layout = "eq" if name.endswith("-eq") else "full"
@@ -112,7 +112,9 @@ def parse(name):
                                          ("f16s-eq-tb-sr", F16_TOL), ("f64-eq-tb5", 1e-12),
                                          ("f32-eq-tb5", 1e-5), ("f64-eq-tb4", 1e-12),
                                          ("f32-eq-tb4", 1e-5), ("f16s-eq-tb3-sr", F16_TOL),
-                                         ("f16s-eq-tb4-sr", F16_TOL), ("f16s-eq-tb5-sr", F16_TOL)])
+                                         ("f16s-eq-tb4-sr", F16_TOL), ("f16s-eq-tb5-sr", F16_TOL),
+                                         ("f16s-eq-tb6-sr", F16_TOL), ("f32-eq-tb8", 1e-5),
+                                         ("f64-eq-tb8", 1e-12)])
 def test_precision_plate_windows(big_plate, storage, tol):
     """The 134M-site plate in the launch configuration the benchmark times
     (the library's default shapes), on sampled windows the oracle computes."""
