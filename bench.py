@@ -174,6 +174,9 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=Tr
     if tm["steps"]:
         out["sweep_ms"] = tm["sweep_ms"] / tm["steps"]
         out["crack_ms"] = tm["crack_ms"] / tm["steps"]
+    if time_block(storage) >= 2:
+        # K criterion: speculative T-step sweeps and the ones run again
+        out["time_block_stats"] = s.time_block_stats()
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -668,6 +671,8 @@ def main():
             e["crack_kernel_ms"] = round(r["crack_ms"], 4)
             e["sweep_GBps"] = round(gbs, 1)
             e["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+        if r.get("time_block_stats", {}).get("sweeps"):
+            e["speculative_sweeps"] = r["time_block_stats"]
         if st != ref_name:
             e.update(k_errors(r["K"], ref["K"]))
             e["field_err_vs_" + ref_name] = {str(n): v for n, v in r["field_errors"].items()}

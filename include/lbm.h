@@ -268,11 +268,17 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * registers, then step n + 1 from those, and so on, then stores), so a step
  * moves 1 / T of the bytes of the one-step sweep; the crack steps of all T
  * time steps still run, in order (K of step n + k from the crack rows after
- * step n + k).  FP32 and FP64 results are bit for bit those of steps = 1;
- * 16-bit storages round only every T-th step.  Needs the equilibrium layout,
- * walls, no sensors, and no crack or a crack along +x with prescribed or no
- * growth (the K criterion decides every step; LBM_EINVAL otherwise).  rows /
- * waves: rows finished per wave (4, 8 or 16) and waves per workgroup
+ * step n + k; Alg. 1 takes one crack step per time step).  FP32 and FP64
+ * results are bit for bit those of steps = 1; 16-bit storages round only at
+ * the end of each sweep.  Needs the equilibrium layout, walls, no sensors,
+ * and no crack or a crack along +x.  Prescribed growth: the sweep derives
+ * the links severed at steps n + 1 .. n + T - 1 from the prescribed advance.
+ * K criterion (eq. sifCriterion): the sweep keeps the links of step n; when
+ * the crack step of some step n + m before the last severs a link, the state
+ * of step n is put back and the sweep runs again for m + 1 steps (lbm_step
+ * then reads one flag from the device per sweep, synchronising the stream;
+ * a crack that severs a link every few steps gains little from a large T).
+ * rows / waves: rows finished per wave (4, 8 or 16) and waves per workgroup
  * (1, 2, 4 or 8) of the T-step sweep for this T (0 = keep; T >= 6: 16 rows
  * only; the defaults, and
  * a cap on the resident waves per SIMD, are the fastest measured on a
@@ -280,6 +286,12 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * not a multiple of T ends with one shorter sweep (one step: the one-step
  * sweep).  steps = 1 restores the one-step sweep. */
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves);
+
+/* Counts since the handle was made: T-step sweeps run under the K criterion
+ * (speculative, see lbm_set_time_block) and how many of them were run again
+ * with fewer steps because a link was severed before their last step.  Any
+ * output pointer may be NULL. */
+int lbm_time_block_stats(lbm_handle *h, int64_t *sweeps, int64_t *reruns);
 
 /* The 16-bit store conversion of the sweep, applied to an array (for
  * inspection and tests of the storage formats): out[i] is the value the sweep

@@ -50,7 +50,7 @@ struct Layout {
   size_t off_trK = 0, off_trA = 0, off_trV = 0, off_trF = 0;
   size_t off_trKL = 0, off_trAL = 0, off_trVL = 0, off_trFL = 0;
   size_t off_evS = 0, off_evC = 0, off_evJ = 0, off_evO = 0, off_stage = 0;
-  size_t off_sens = 0, off_trS = 0, off_wmid = 0;
+  size_t off_sens = 0, off_trS = 0, off_wmid = 0, off_spec = 0;
   int64_t event_cap = 0;
   int stage_rows = 0;
   size_t total = 0;
@@ -122,6 +122,8 @@ Layout make_layout(const lbm_config &c, Store s) {
   L.off_evO = o; o += align_up((size_t)L.event_cap * 4, 256);
   // T-step sweep: the crack rows after steps n .. n + T - 2
   L.off_wmid = o; o += align_up((size_t)2 * (lbmk::kMaxTimeBlock - 1) * L.pitch * L.welem, 256);
+  // speculative T-step sweep (K criterion): the crack state and crack-row mask of step n
+  L.off_spec = o; o += align_up(sizeof(lbmk::SpecSlot), 256) + align_up((size_t)L.mw * 4, 256);
   L.off_sens = o; o += align_up((size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.off_trS = o; o += align_up(tc * (size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.stage_rows = (int)std::max<int64_t>(1, std::min<int64_t>(c.ny, (1 << 20) / std::max(1, c.nx)));
@@ -277,9 +279,14 @@ struct lbm_handle {
   // that FP32 cannot hold) are streamed and both buffers are cleared.
   bool eq = false;
   int full_steps = 0;
-  // time blocking: steps per sweep (1, or T = 2..5 with the T-step sweep)
+  // time blocking: steps per sweep (1, or T = 2..8 with the T-step sweep)
   // and the T-step sweep's rows per wave and waves per workgroup, per T
   int tblock = 1;
+  // speculative T-step sweeps (K criterion) and how many were run again;
+  // the crack state the host last read (or predicted) for the sweep lengths
+  int64_t spec_blocks = 0, spec_reruns = 0;
+  bool spec_known = false;
+  lbmk::DevCrack spec_state{};
   // the side stream the T-step sweep's boundary chunks run on beside the
   // rest, with its fork and join events (created with the first T-step
   // sweep, on the device current then; default priority)
@@ -302,6 +309,7 @@ struct lbm_handle {
   uint32_t *mH() const { return reinterpret_cast<uint32_t *>(base + L.off_mH); }
   lbmk::MaskRows *mrows() const { return reinterpret_cast<lbmk::MaskRows *>(base + L.off_rf); }
   lbmk::DevCrack *crack() const { return reinterpret_cast<lbmk::DevCrack *>(base + L.off_crack); }
+  lbmk::SpecSlot *spec_slot() const { return reinterpret_cast<lbmk::SpecSlot *>(base + L.off_spec); }
   double *stage() const { return reinterpret_cast<double *>(base + L.off_stage); }
   double tau_at(int64_t n) const {
     if (tau.empty()) return 0.0;
@@ -796,6 +804,33 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   return LBM_OK;
 }
 
+// Under the K criterion: the steps a T-step sweep can take before its last
+// crack step severs a link, if every growing tip keeps the speed of its last
+// step (the first cut at crack step ceil(gap / da), gap = distance of the tip
+// to the next column it crosses); at most T, at least 1.  Only a prediction:
+// a sweep that proves too long is run again.
+int spec_len(const lbm_handle *h, int T) {
+  if (!h->spec_known) return T;
+  const lbmk::DevCrack &c = h->spec_state;
+  double need = T;
+  auto tip = [&](int flags, double v, double gap) {
+    if (!(flags & LBM_FLAG_GREW) || (flags & LBM_FLAG_WALL) || !(v > 0)) return;
+    need = std::min(need, std::ceil(gap / ((v * h->cs) * h->dt)));
+  };
+  tip(c.flags, c.v, std::floor(c.tip) + 1.0 - c.tip);
+  if (h->cfg.both_tips) tip(c.flagsL, c.vL, c.tipL - (std::ceil(c.tipL) - 1.0));
+  return std::max(1, (int)need);
+}
+
+// The predicted crack state one step on (each growing tip at its last speed).
+void spec_advance(lbm_handle *h) {
+  lbmk::DevCrack &c = h->spec_state;
+  const double f = h->cs * h->dt;
+  if ((c.flags & LBM_FLAG_GREW) && !(c.flags & LBM_FLAG_WALL)) c.tip += c.v * f;
+  if (h->cfg.both_tips && (c.flagsL & LBM_FLAG_GREW) && !(c.flagsL & LBM_FLAG_WALL))
+    c.tipL -= c.vL * f;
+}
+
 int lbm_step(lbm_handle *h, int64_t nsteps) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (h->in_batch) return fail(LBM_ESTATE, "this plate is stepped by its batch (lbm_batch_step)");
@@ -804,47 +839,79 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     // T steps in one sweep when time blocking is on and the moving planes
     // are settled (the five-plane start-up steps run one at a time); fewer
     // at the end of the call
-    const int ns = h->full_steps == 0 ? (int)std::min<int64_t>(h->tblock, nsteps - k) : 1;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    int ns = h->full_steps == 0 ? (int)std::min<int64_t>(h->tblock, nsteps - k) : 1;
+    const bool sif_blocks = h->tblock >= 2 && h->cfg.growth == LBM_GROW_SIF;
+    if (sif_blocks && ns >= 2) ns = std::min(ns, spec_len(h, ns));
     bool timed = false;
     for (int m = 0; m < ns; ++m) timed |= h->timing && (h->step + m) % h->timing_stride == 0;
-    if (timed) {
-      for (auto &e : ev) {
-        e = take_event(h);
-        if (!e) return fail(LBM_EHIP, "event creation failed");
-      }
-      HIP_TRY(hipEventRecord(ev[0], h->stream));
-    }
-    int rc = ns >= 2 ? launch_block_any(h, ns) : launch_sweep_any(h);
-    if (rc != LBM_OK) return rc;
-    if (timed) HIP_TRY(hipEventRecord(ev[1], h->stream));
-    if (h->crack_step_needed()) {
-      if (ns >= 2) {
-        // steps n .. n + T - 2 from the crack rows after each, then the last
-        // from the new state, in one launch
-        lbmk::CrackSeq q{};
-        q.a = crack_args(h);
-        q.n = ns;
-        for (int m = 0; m < ns; ++m) {
-          const bool mid = m + 1 < ns;
-          q.w[m] = mid ? (const void *)(h->base + h->L.off_wmid + (size_t)2 * m * h->L.pitch * h->L.welem)
-                       : q.a.w;
-          q.w_row0[m] = mid ? h->plate.j0 : 0;
+    // Under the K criterion the T-step sweep keeps the links of step n; when
+    // a crack step before the last severs one, the crack kernel puts back the
+    // state of step n and the sweep runs again, from the same source buffers,
+    // for the steps that were right (fewer each time, so this ends).
+    for (;;) {
+      hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+      if (timed) {
+        for (auto &e : ev) {
+          e = take_event(h);
+          if (!e) return fail(LBM_EHIP, "event creation failed");
         }
-        HIP_TRY(lbmk::launch_crack_seq(q, h->stream));
-      } else {
-        rc = launch_crack_step(h);
-        if (rc != LBM_OK) return rc;
+        HIP_TRY(hipEventRecord(ev[0], h->stream));
       }
-    }
-    if (timed) {
-      HIP_TRY(hipEventRecord(ev[2], h->stream));
-      for (auto &e : ev) h->ev_used.push_back(e);
-      h->ev_steps.push_back(ns);
-      if (h->ev_used.size() >= 3 * 4096) {
-        rc = harvest_timing(h);
-        if (rc != LBM_OK) return rc;
+      int rc = ns >= 2 ? launch_block_any(h, ns) : launch_sweep_any(h);
+      if (rc != LBM_OK) return rc;
+      if (timed) HIP_TRY(hipEventRecord(ev[1], h->stream));
+      bool spec = false;
+      if (h->crack_step_needed()) {
+        if (ns >= 2) {
+          // steps n .. n + T - 2 from the crack rows after each, then the last
+          // from the new state, in one launch
+          lbmk::CrackSeq q{};
+          q.a = crack_args(h);
+          q.n = ns;
+          for (int m = 0; m < ns; ++m) {
+            const bool mid = m + 1 < ns;
+            q.w[m] = mid ? (const void *)(h->base + h->L.off_wmid + (size_t)2 * m * h->L.pitch * h->L.welem)
+                         : q.a.w;
+            q.w_row0[m] = mid ? h->plate.j0 : 0;
+          }
+          spec = h->cfg.growth == LBM_GROW_SIF;
+          if (spec) {
+            q.spec = h->spec_slot();
+            q.spec_mask = reinterpret_cast<uint32_t *>(h->base + h->L.off_spec +
+                                                       align_up(sizeof(lbmk::SpecSlot), 256));
+          }
+          HIP_TRY(lbmk::launch_crack_seq(q, h->stream));
+        } else {
+          rc = launch_crack_step(h);
+          if (rc != LBM_OK) return rc;
+        }
       }
+      if (timed) HIP_TRY(hipEventRecord(ev[2], h->stream));
+      int32_t valid = ns;
+      if (spec) {
+        lbmk::SpecSlot slot;
+        HIP_TRY(hipMemcpyAsync(&slot, h->spec_slot(), sizeof slot, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        valid = slot.valid;
+        if (valid < 1 || valid > ns) return fail(LBM_EHIP, "bad speculation count %d", valid);
+        h->spec_blocks++;
+        if (valid < ns) h->spec_reruns++;
+        h->spec_state = slot.now;
+        h->spec_known = true;
+      } else if (sif_blocks) {
+        for (int m = 0; m < ns; ++m) spec_advance(h);
+      }
+      if (timed) {
+        // a sweep that is run again counts its time but not its steps
+        for (auto &e : ev) h->ev_used.push_back(e);
+        h->ev_steps.push_back(valid == ns ? ns : 0);
+        if (h->ev_used.size() >= 3 * 4096) {
+          rc = harvest_timing(h);
+          if (rc != LBM_OK) return rc;
+        }
+      }
+      if (valid == ns) break;
+      ns = valid;
     }
     h->cur = 1 - h->cur;
     h->step += ns;
@@ -1079,6 +1146,7 @@ int lbm_restore(lbm_handle *h, const void *src) {
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->step = hd.step;
   h->full_steps = (h->eq && h->store != Store::F64S) ? 2 : 0;
+  h->spec_known = false;
   return LBM_OK;
 }
 
@@ -1153,21 +1221,27 @@ int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves
   if (steps >= 6 && rows != 0 && rows != 16)
     return fail(LBM_EINVAL, "sweeps of six or more steps take 16 rows per wave");
   if (steps == 1 && (rows != 0 || waves != 0))
-    return fail(LBM_EINVAL, "rows and waves shape the T-step sweep (steps 2..4)");
+    return fail(LBM_EINVAL, "rows and waves shape the T-step sweep (steps 2..8)");
   if (steps >= 2) {
     if (!h->eq || h->store == Store::F32_PLAIN || h->store == Store::F64)
       return fail(LBM_EINVAL, "the T-step sweep needs the equilibrium layout");
     if (h->cfg.bc_mode == LBM_BC_PERIODIC) return fail(LBM_EINVAL, "the T-step sweep needs walls");
     if (h->cfg.has_crack && !h->line.aligned)
       return fail(LBM_EINVAL, "the T-step sweep takes a crack along +x only");
-    if (h->cfg.growth == LBM_GROW_SIF)
-      return fail(LBM_EINVAL, "the T-step sweep needs prescribed or no growth (the K criterion decides each step)");
     if (h->cfg.n_sensors > 0) return fail(LBM_EINVAL, "the T-step sweep records no sensors");
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->tblock = steps;
+  h->spec_known = false;
   if (rows > 0) h->blk_rows[steps] = rows;
   if (waves > 0) h->blk_waves[steps] = waves;
+  return LBM_OK;
+}
+
+int lbm_time_block_stats(lbm_handle *h, int64_t *sweeps, int64_t *reruns) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (sweeps) *sweeps = h->spec_blocks;
+  if (reruns) *reruns = h->spec_reruns;
   return LBM_OK;
 }
 

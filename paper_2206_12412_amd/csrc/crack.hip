@@ -12,14 +12,43 @@ __global__ void __launch_bounds__(64) crack_kernel(const CrackArgs a) { core::cr
 // The crack steps of the n time steps one T-step sweep advanced, in order, by
 // one wavefront: step m reads w from w[m] (rows from w_row0[m] on); the
 // barrier makes each step's state, mask and trace writes visible to the next.
+// Speculative sweeps (s.spec set): the state at the start is kept; when step
+// m < n - 1 severs a link, the sweep of steps m + 2 .. n went without it, so
+// the state of the start is put back and valid = m + 1 tells the host to run
+// the sweep again for m + 1 steps (whose last crack step then severs it).
 __global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
+  const int lane = threadIdx.x & 63;
+  const Plate p = s.a.p;
+  uint32_t *row = s.a.mV + (size_t)p.j0 * p.mw;
+  int32_t cut0 = 0;
+  if (s.spec) {
+    const DevCrack c0 = *s.a.st;
+    cut0 = c0.n_cut;
+    for (int k = lane; k < p.mw; k += 64) s.spec_mask[k] = row[k];
+    if (lane == 0) {
+      s.spec->st = c0;
+      s.spec->mr = *s.a.mrows;
+      s.spec->valid = s.n;
+    }
+  }
   for (int m = 0; m < s.n; ++m) {
     CrackArgs a = s.a;
     a.w = s.w[m];
     a.w_row0 = s.w_row0[m];
     core::crack_step_wave(a);
     __syncthreads();
+    if (s.spec && m + 1 < s.n && s.a.st->n_cut != cut0) {
+      for (int k = lane; k < p.mw; k += 64) row[k] = s.spec_mask[k];
+      if (lane == 0) {
+        *s.a.st = s.spec->st;
+        *s.a.mrows = s.spec->mr;
+        s.spec->valid = m + 1;
+        s.spec->now = s.spec->st;
+      }
+      return;
+    }
   }
+  if (s.spec && lane == 0) s.spec->now = *s.a.st;
 }
 
 // Mask words of every row: all links intact except the vertical links of the

@@ -312,6 +312,17 @@ hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n,
                           uint32_t rkey, hipStream_t st);
 
 // ---- launchers (crack.hip) ----
+// Speculative T-step sweep under the K criterion: the sweep keeps the links
+// of step n for all T steps, which holds while no crack step of n .. n+T-2
+// severs a link.  The crack steps stop at the first one that does, put back
+// the crack state, mask-row range and crack-row mask of step n, and report
+// how many steps were right (the sweep is then run again with that many).
+struct SpecSlot {
+  DevCrack st;
+  MaskRows mr;
+  int32_t valid;   // steps found right (n when none cut before the last)
+  DevCrack now;    // the crack state the launch leaves
+};
 hipError_t launch_crack(const CrackArgs &a, hipStream_t st);
 // the crack steps of the n <= kMaxTimeBlock time steps of one T-step sweep,
 // in order, in one launch
@@ -320,6 +331,8 @@ struct CrackSeq {
   const void *w[kMaxTimeBlock];
   int32_t w_row0[kMaxTimeBlock];
   int n;
+  SpecSlot *spec;                    // non-null: the sweep assumed no cuts (K criterion)
+  uint32_t *spec_mask;               // mw words: the crack row's mask at the start
 };
 hipError_t launch_crack_seq(const CrackSeq &s, hipStream_t st);
 hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const Plate &p,
