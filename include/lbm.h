@@ -38,7 +38,10 @@
  * T-step sweep (lbm_set_time_block) runs its boundary chunks on a side stream
  * that the handle creates with its first such sweep (default priority), forked
  * from and joined back into the caller's stream, so that work enqueued on the
- * caller's stream after lbm_step still follows all of it.  Host arrays passed
+ * caller's stream after lbm_step still follows all of it; under the K
+ * criterion it also allocates a small pinned host buffer (hipHostMalloc) that
+ * the crack kernel writes each speculative sweep's verdict to, freed by
+ * lbm_free.  Host arrays passed
  * to lbm_init are copied.  All calls on one handle must come
  * from one host thread at a time.
  *
@@ -276,7 +279,7 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * K criterion (eq. sifCriterion): the sweep keeps the links of step n; when
  * the crack step of some step n + m before the last severs a link, the state
  * of step n is put back and the sweep runs again for m + 1 steps (lbm_step
- * then reads one flag from the device per sweep, synchronising the stream;
+ * then synchronises the stream once per sweep to read the verdict;
  * a crack that severs a link every few steps gains little from a large T).
  * rows / waves: rows finished per wave (4, 8 or 16) and waves per workgroup
  * (1, 2, 4 or 8) of the T-step sweep for this T (0 = keep; T >= 6: 16 rows

@@ -287,6 +287,9 @@ struct lbm_handle {
   int64_t spec_blocks = 0, spec_reruns = 0;
   bool spec_known = false;
   lbmk::DevCrack spec_state{};
+  // the speculative sweep's verdict, written by the crack kernel into pinned
+  // host memory (allocated with the first such sweep) and its device address
+  lbmk::SpecOut *spec_host = nullptr, *spec_dev = nullptr;
   // the side stream the T-step sweep's boundary chunks run on beside the
   // rest, with its fork and join events (created with the first T-step
   // sweep, on the device current then; default priority)
@@ -876,6 +879,13 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
           }
           spec = h->cfg.growth == LBM_GROW_SIF;
           if (spec) {
+            if (!h->spec_host) {
+              HIP_TRY(hipHostMalloc((void **)&h->spec_host, sizeof(lbmk::SpecOut),
+                                    hipHostMallocMapped | hipHostMallocCoherent));
+              HIP_TRY(hipHostGetDevicePointer((void **)&h->spec_dev, h->spec_host, 0));
+            }
+            *(volatile int32_t *)&h->spec_host->valid = -1;
+            q.spec_out = h->spec_dev;
             q.spec = h->spec_slot();
             q.spec_mask = reinterpret_cast<uint32_t *>(h->base + h->L.off_spec +
                                                        align_up(sizeof(lbmk::SpecSlot), 256));
@@ -889,14 +899,12 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
       if (timed) HIP_TRY(hipEventRecord(ev[2], h->stream));
       int32_t valid = ns;
       if (spec) {
-        lbmk::SpecSlot slot;
-        HIP_TRY(hipMemcpyAsync(&slot, h->spec_slot(), sizeof slot, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
-        valid = slot.valid;
+        valid = *(volatile int32_t *)&h->spec_host->valid;
         if (valid < 1 || valid > ns) return fail(LBM_EHIP, "bad speculation count %d", valid);
         h->spec_blocks++;
         if (valid < ns) h->spec_reruns++;
-        h->spec_state = slot.now;
+        std::memcpy(&h->spec_state, (const void *)&h->spec_host->now, sizeof h->spec_state);
         h->spec_known = true;
       } else if (sif_blocks) {
         for (int m = 0; m < ns; ++m) spec_advance(h);
@@ -1289,6 +1297,7 @@ void lbm_free(lbm_handle *h) {
     (void)hipEventDestroy(h->side.join);
     (void)hipStreamDestroy(h->side.side);
   }
+  if (h->spec_host) (void)hipHostFree(h->spec_host);
   delete h;
 }
 

@@ -28,7 +28,6 @@ __global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
     if (lane == 0) {
       s.spec->st = c0;
       s.spec->mr = *s.a.mrows;
-      s.spec->valid = s.n;
     }
   }
   for (int m = 0; m < s.n; ++m) {
@@ -42,13 +41,16 @@ __global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
       if (lane == 0) {
         *s.a.st = s.spec->st;
         *s.a.mrows = s.spec->mr;
-        s.spec->valid = m + 1;
-        s.spec->now = s.spec->st;
+        s.spec_out->now = s.spec->st;
+        s.spec_out->valid = m + 1;
       }
       return;
     }
   }
-  if (s.spec && lane == 0) s.spec->now = *s.a.st;
+  if (s.spec && lane == 0) {
+    s.spec_out->now = *s.a.st;
+    s.spec_out->valid = s.n;
+  }
 }
 
 // Mask words of every row: all links intact except the vertical links of the

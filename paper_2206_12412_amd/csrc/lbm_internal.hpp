@@ -320,6 +320,10 @@ hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n,
 struct SpecSlot {
   DevCrack st;
   MaskRows mr;
+};
+// What the host reads after the launch (pinned host memory, written by the
+// kernel so that no copy has to be queued).
+struct SpecOut {
   int32_t valid;   // steps found right (n when none cut before the last)
   DevCrack now;    // the crack state the launch leaves
 };
@@ -333,6 +337,7 @@ struct CrackSeq {
   int n;
   SpecSlot *spec;                    // non-null: the sweep assumed no cuts (K criterion)
   uint32_t *spec_mask;               // mw words: the crack row's mask at the start
+  SpecOut *spec_out;                 // device address of the host's SpecOut
 };
 hipError_t launch_crack_seq(const CrackSeq &s, hipStream_t st);
 hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const Plate &p,
