@@ -276,11 +276,13 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * the end of each sweep.  Needs the equilibrium layout, walls, no sensors,
  * and no crack or a crack along +x.  Prescribed growth: the sweep derives
  * the links severed at steps n + 1 .. n + T - 1 from the prescribed advance.
- * K criterion (eq. sifCriterion): the sweep keeps the links of step n; when
- * the crack step of some step n + m before the last severs a link, the state
- * of step n is put back and the sweep runs again for m + 1 steps (lbm_step
- * then synchronises the stream once per sweep to read the verdict;
- * a crack that severs a link every few steps gains little from a large T).
+ * K criterion (eq. sifCriterion): the sweep severs links as if each tip kept
+ * the speed of its last step; when the crack step of some step n + m before
+ * the last leaves a tip in another column than that prediction, the state of
+ * step n is put back and the sweep runs again for m + 1 steps (lbm_step then
+ * synchronises the stream once per sweep to read the verdict; after a sweep
+ * that was run again the next may take half as many steps, growing back by
+ * one per sweep that held).
  * rows / waves: rows finished per wave (4, 8 or 16) and waves per workgroup
  * (1, 2, 4 or 8) of the T-step sweep for this T (0 = keep; T >= 6: 16 rows
  * only; the defaults, and
@@ -292,7 +294,8 @@ int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves
 
 /* Counts since the handle was made: T-step sweeps run under the K criterion
  * (speculative, see lbm_set_time_block) and how many of them were run again
- * with fewer steps because a link was severed before their last step.  Any
+ * with fewer steps because a tip left the predicted column before their last
+ * step.  Any
  * output pointer may be NULL. */
 int lbm_time_block_stats(lbm_handle *h, int64_t *sweeps, int64_t *reruns);
 

@@ -283,10 +283,10 @@ struct lbm_handle {
   // and the T-step sweep's rows per wave and waves per workgroup, per T
   int tblock = 1;
   // speculative T-step sweeps (K criterion) and how many were run again;
-  // the crack state the host last read (or predicted) for the sweep lengths
+  // the length the next one may take (halved by a sweep run again, one more
+  // after each sweep that held, at most T)
   int64_t spec_blocks = 0, spec_reruns = 0;
-  bool spec_known = false;
-  lbmk::DevCrack spec_state{};
+  int spec_cap = lbmk::kMaxTimeBlock;
   // the speculative sweep's verdict, written by the crack kernel into pinned
   // host memory (allocated with the first such sweep) and its device address
   lbmk::SpecOut *spec_host = nullptr, *spec_dev = nullptr;
@@ -430,7 +430,8 @@ int launch_block_typed(lbm_handle *h, int T) {
   A.st = h->crack();
   A.crack = h->cfg.has_crack;
   A.both = h->cfg.both_tips;
-  A.grow = h->cfg.growth == LBM_GROW_PRESCRIBED;
+  A.grow = h->cfg.growth == LBM_GROW_PRESCRIBED || h->cfg.growth == LBM_GROW_SIF;
+  A.sif = h->cfg.growth == LBM_GROW_SIF;
   A.v_rel = h->cfg.v_rel;
   A.cs = h->cs;
   A.dt = h->dt;
@@ -807,33 +808,6 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   return LBM_OK;
 }
 
-// Under the K criterion: the steps a T-step sweep can take before its last
-// crack step severs a link, if every growing tip keeps the speed of its last
-// step (the first cut at crack step ceil(gap / da), gap = distance of the tip
-// to the next column it crosses); at most T, at least 1.  Only a prediction:
-// a sweep that proves too long is run again.
-int spec_len(const lbm_handle *h, int T) {
-  if (!h->spec_known) return T;
-  const lbmk::DevCrack &c = h->spec_state;
-  double need = T;
-  auto tip = [&](int flags, double v, double gap) {
-    if (!(flags & LBM_FLAG_GREW) || (flags & LBM_FLAG_WALL) || !(v > 0)) return;
-    need = std::min(need, std::ceil(gap / ((v * h->cs) * h->dt)));
-  };
-  tip(c.flags, c.v, std::floor(c.tip) + 1.0 - c.tip);
-  if (h->cfg.both_tips) tip(c.flagsL, c.vL, c.tipL - (std::ceil(c.tipL) - 1.0));
-  return std::max(1, (int)need);
-}
-
-// The predicted crack state one step on (each growing tip at its last speed).
-void spec_advance(lbm_handle *h) {
-  lbmk::DevCrack &c = h->spec_state;
-  const double f = h->cs * h->dt;
-  if ((c.flags & LBM_FLAG_GREW) && !(c.flags & LBM_FLAG_WALL)) c.tip += c.v * f;
-  if (h->cfg.both_tips && (c.flagsL & LBM_FLAG_GREW) && !(c.flagsL & LBM_FLAG_WALL))
-    c.tipL -= c.vL * f;
-}
-
 int lbm_step(lbm_handle *h, int64_t nsteps) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (h->in_batch) return fail(LBM_ESTATE, "this plate is stepped by its batch (lbm_batch_step)");
@@ -844,13 +818,14 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     // at the end of the call
     int ns = h->full_steps == 0 ? (int)std::min<int64_t>(h->tblock, nsteps - k) : 1;
     const bool sif_blocks = h->tblock >= 2 && h->cfg.growth == LBM_GROW_SIF;
-    if (sif_blocks && ns >= 2) ns = std::min(ns, spec_len(h, ns));
+    if (sif_blocks) ns = std::min(ns, std::max(2, h->spec_cap));
     bool timed = false;
     for (int m = 0; m < ns; ++m) timed |= h->timing && (h->step + m) % h->timing_stride == 0;
-    // Under the K criterion the T-step sweep keeps the links of step n; when
-    // a crack step before the last severs one, the crack kernel puts back the
-    // state of step n and the sweep runs again, from the same source buffers,
-    // for the steps that were right (fewer each time, so this ends).
+    // Under the K criterion the T-step sweep severs links as if each tip kept
+    // its last speed; when a crack step before the last leaves a tip in
+    // another column, the crack kernel puts back the state of step n and the
+    // sweep runs again, from the same source buffers, for the steps that were
+    // right (fewer each time, so this ends).
     for (;;) {
       hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
       if (timed) {
@@ -903,11 +878,12 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
         valid = *(volatile int32_t *)&h->spec_host->valid;
         if (valid < 1 || valid > ns) return fail(LBM_EHIP, "bad speculation count %d", valid);
         h->spec_blocks++;
-        if (valid < ns) h->spec_reruns++;
-        std::memcpy(&h->spec_state, (const void *)&h->spec_host->now, sizeof h->spec_state);
-        h->spec_known = true;
-      } else if (sif_blocks) {
-        for (int m = 0; m < ns; ++m) spec_advance(h);
+        if (valid < ns) {
+          h->spec_reruns++;
+          h->spec_cap = std::max(2, ns / 2);
+        } else {
+          h->spec_cap = std::min(h->tblock, h->spec_cap + 1);
+        }
       }
       if (timed) {
         // a sweep that is run again counts its time but not its steps
@@ -1154,7 +1130,6 @@ int lbm_restore(lbm_handle *h, const void *src) {
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->step = hd.step;
   h->full_steps = (h->eq && h->store != Store::F64S) ? 2 : 0;
-  h->spec_known = false;
   return LBM_OK;
 }
 
@@ -1240,7 +1215,7 @@ int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->tblock = steps;
-  h->spec_known = false;
+  h->spec_cap = steps;
   if (rows > 0) h->blk_rows[steps] = rows;
   if (waves > 0) h->blk_waves[steps] = waves;
   return LBM_OK;

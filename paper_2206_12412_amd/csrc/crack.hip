@@ -12,18 +12,29 @@ __global__ void __launch_bounds__(64) crack_kernel(const CrackArgs a) { core::cr
 // The crack steps of the n time steps one T-step sweep advanced, in order, by
 // one wavefront: step m reads w from w[m] (rows from w_row0[m] on); the
 // barrier makes each step's state, mask and trace writes visible to the next.
-// Speculative sweeps (s.spec set): the state at the start is kept; when step
-// m < n - 1 severs a link, the sweep of steps m + 2 .. n went without it, so
-// the state of the start is put back and valid = m + 1 tells the host to run
-// the sweep again for m + 1 steps (whose last crack step then severs it).
+// Speculative sweeps (s.spec set): the sweep severed the links of its later
+// steps as if each tip kept the speed of its last step.  The state at the
+// start is kept; when crack step m < n - 1 leaves a tip in another column
+// than that prediction (the links the sweep of steps m + 2 .. n used differ
+// from the real ones), the state of the start is put back and valid = m + 1
+// tells the host to run the sweep again for m + 1 steps.
 __global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
+#pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
   const Plate p = s.a.p;
+  const CrackParams q = s.a.c;
   uint32_t *row = s.a.mV + (size_t)p.j0 * p.mw;
-  int32_t cut0 = 0;
+  // the predicted tips (the sweep's own recurrence)
+  double pR = 0.0, pL = 0.0, daR = 0.0, daL = 0.0;
+  bool wR = true, wL = true;
   if (s.spec) {
     const DevCrack c0 = *s.a.st;
-    cut0 = c0.n_cut;
+    pR = c0.tip;
+    pL = c0.tipL;
+    daR = (c0.v * q.cs) * q.dt;
+    daL = (c0.vL * q.cs) * q.dt;
+    wR = (c0.flags & core::kFlagWall) != 0;
+    wL = (c0.flagsL & core::kFlagWall) != 0;
     for (int k = lane; k < p.mw; k += 64) s.spec_mask[k] = row[k];
     if (lane == 0) {
       s.spec->st = c0;
@@ -36,21 +47,33 @@ __global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
     a.w_row0 = s.w_row0[m];
     core::crack_step_wave(a);
     __syncthreads();
-    if (s.spec && m + 1 < s.n && s.a.st->n_cut != cut0) {
+    if (!s.spec || m + 1 == s.n) continue;
+    if (!wR) {
+      pR = pR + daR;
+      if (pR >= q.a_hi) {
+        pR = q.a_hi;
+        wR = true;
+      }
+    }
+    if (q.both && !wL) {
+      pL = pL - daL;
+      if (pL <= q.a_lo) {
+        pL = q.a_lo;
+        wL = true;
+      }
+    }
+    const DevCrack c = *s.a.st;
+    if (floor(c.tip) != floor(pR) || (q.both && ceil(c.tipL) != ceil(pL))) {
       for (int k = lane; k < p.mw; k += 64) row[k] = s.spec_mask[k];
       if (lane == 0) {
         *s.a.st = s.spec->st;
         *s.a.mrows = s.spec->mr;
-        s.spec_out->now = s.spec->st;
         s.spec_out->valid = m + 1;
       }
       return;
     }
   }
-  if (s.spec && lane == 0) {
-    s.spec_out->now = *s.a.st;
-    s.spec_out->valid = s.n;
-  }
+  if (s.spec && lane == 0) s.spec_out->valid = s.n;
 }
 
 // Mask words of every row: all links intact except the vertical links of the

@@ -179,7 +179,8 @@ struct BlockArgs {
   uint32_t rkey_last;                 // rounding key of step n + T - 1
   W *wmid;                            // w after steps n .. n + T - 2 on rows j0, j0 + 1 ([T - 1][2][pitch])
   const DevCrack *st;                 // crack state before step n's crack step
-  int crack, both, grow;              // crack present, two tips, prescribed growth
+  int crack, both, grow;              // crack present, two tips, growing tips
+  int sif;                            // K criterion: each tip keeps its last speed (predicted)
   double v_rel, cs, dt, a_lo, a_hi;
 };
 
@@ -312,11 +313,13 @@ hipError_t launch_round16(Store s, int sr, const float *x, void *out, int64_t n,
                           uint32_t rkey, hipStream_t st);
 
 // ---- launchers (crack.hip) ----
-// Speculative T-step sweep under the K criterion: the sweep keeps the links
-// of step n for all T steps, which holds while no crack step of n .. n+T-2
-// severs a link.  The crack steps stop at the first one that does, put back
-// the crack state, mask-row range and crack-row mask of step n, and report
-// how many steps were right (the sweep is then run again with that many).
+// Speculative T-step sweep under the K criterion: the sweep severs the links
+// of steps n + 1 .. n + T - 1 as if each tip kept the speed of its last step,
+// which holds while every crack step of n .. n + T - 2 leaves its tip in the
+// column that prediction gives.  The crack steps stop at the first one that
+// does not, put back the crack state, mask-row range and crack-row mask of
+// step n, and report how many steps were right (the sweep is then run again
+// with that many).
 struct SpecSlot {
   DevCrack st;
   MaskRows mr;
@@ -324,8 +327,7 @@ struct SpecSlot {
 // What the host reads after the launch (pinned host memory, written by the
 // kernel so that no copy has to be queued).
 struct SpecOut {
-  int32_t valid;   // steps found right (n when none cut before the last)
-  DevCrack now;    // the crack state the launch leaves
+  int32_t valid;   // steps found right (n when every prediction held)
 };
 hipError_t launch_crack(const CrackArgs &a, hipStream_t st);
 // the crack steps of the n <= kMaxTimeBlock time steps of one T-step sweep,

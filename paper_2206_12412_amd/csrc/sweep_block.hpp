@@ -182,8 +182,10 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
   const __amdgpu_buffer_rsrc_t rw = plane_rsrc(a.wout, rows_elems * (uint32_t)sizeof(W));
 
   // severed vertical links of the crack row at step n + k: those of step n
-  // plus the ones the crack steps of n .. n + k - 1 sever (prescribed growth;
-  // the tip advance, wall clamp and cut columns of the crack step)
+  // plus the ones the crack steps of n .. n + k - 1 sever (the tip advance,
+  // wall clamp and cut columns of the crack step, at the prescribed speed or,
+  // under the K criterion, at each tip's last speed: a prediction the crack
+  // steps check)
   uint32_t cut[T];
 #pragma unroll
   for (int k = 0; k < T; ++k) cut[k] = 0u;
@@ -195,7 +197,8 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
     if (A.grow) {
 #pragma clang fp contract(off)
       const DevCrack c = *A.st;
-      const double da = (A.v_rel * A.cs) * A.dt;
+      const double da = ((A.sif ? c.v : A.v_rel) * A.cs) * A.dt;
+      const double daL = ((A.sif ? c.vL : A.v_rel) * A.cs) * A.dt;
       double tip = c.tip, tipL = c.tipL;
       bool wall = (c.flags & core::kFlagWall) != 0, wallL = (c.flagsL & core::kFlagWall) != 0;
 #pragma unroll
@@ -211,7 +214,7 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
           tip = a_new;
         }
         if (A.both && !wallL) {
-          double a_new = tipL - da;
+          double a_new = tipL - daL;
           if (a_new <= A.a_lo) {
             a_new = A.a_lo;
             wallL = true;
