@@ -278,7 +278,8 @@ def test_time_blocked_sweep_16bit_against_the_oracle(storage, case, T):
 
 def sif_cases(steps):
     """K-criterion plates whose tips stand still for tens of steps, then sever
-    links every few steps (so that some T-step sweeps are run again)."""
+    links every few steps at changing speeds (so that some T-step sweeps are
+    run again)."""
     rng = np.random.default_rng(23)
     n = np.arange(steps)
     wD = np.zeros((steps, 4))
@@ -302,10 +303,11 @@ def sif_cases(steps):
 @pytest.mark.parametrize("name", ["sif-edge", "sif-two-tip", "sif-dirichlet"])
 @pytest.mark.parametrize("T", range(2, 9))
 def test_time_blocked_sweep_under_the_K_criterion_equals_one_step_sweeps_bitwise(storage, name, T):
-    """Eq. (sifCriterion) decides each step's advance: the T-step sweep keeps
-    the links of its first step and is run again, with fewer steps, when a
-    crack step before its last severs a link.  Fields, traces and cut events
-    equal those of one step per sweep, bit for bit."""
+    """Eq. (sifCriterion) decides each step's advance: the T-step sweep
+    predicts the links of its later steps from each tip's last speed and is
+    run again, with fewer steps, when a crack step before its last leaves a
+    tip in another column.  Fields, traces and cut events equal those of one
+    step per sweep, bit for bit."""
     steps = 300
     kw = sif_cases(steps)[name]
     say(f"{T}-step sweep, K criterion, {name} {storage}")
