@@ -131,7 +131,10 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=Tr
     s = Solver(plate_config(p, storage, steps))
     tuned = s.autotune(trial_steps=5) if tune else None  # on a scratch copy of the plate
     if time_block(storage) >= 2:
-        s.set_time_block(time_block(storage))
+        if tune:  # the T-step sweep's own shapes, also on a scratch copy
+            tuned = {"one_step": tuned, "time_block": s.autotune_time_block(time_block(storage))}
+        else:
+            s.set_time_block(time_block(storage))
     torch.cuda.synchronize()
     # per-kernel HIP events on every 10th step of the timed region
     s.timing(True, stride=10)
@@ -671,6 +674,8 @@ def main():
             e["crack_kernel_ms"] = round(r["crack_ms"], 4)
             e["sweep_GBps"] = round(gbs, 1)
             e["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+        if r.get("autotune"):
+            e["autotune"] = r["autotune"]
         if r.get("time_block_stats", {}).get("sweeps"):
             e["speculative_sweeps"] = r["time_block_stats"]
         if st != ref_name:

@@ -292,6 +292,17 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * sweep).  steps = 1 restores the one-step sweep. */
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves);
 
+/* Times every shape of the T-step sweep for steps = T (rows 4, 8 or 16 per
+ * wave, 16 only for T >= 6; waves 1, 2, 4 or 8 per workgroup) over
+ * trial_sweeps sweeps of h itself (h advances: tune a scratch plate made from
+ * the same configuration), then sets the fastest with lbm_set_time_block and
+ * returns it with its time per step.  The defaults were measured on a
+ * 16384 x 8192 plate; on smaller plates the sweep is bound by the latency of
+ * one wave's march rather than by bytes, and another shape can win.  Same
+ * refusals as lbm_set_time_block; trial_sweeps in 1..1000. */
+int lbm_autotune_time_block(lbm_handle *h, int32_t steps, int32_t trial_sweeps, int32_t *rows,
+                            int32_t *waves, double *ms_per_step);
+
 /* Counts since the handle was made: T-step sweeps run under the K criterion
  * (speculative, see lbm_set_time_block) and how many of them were run again
  * with fewer steps because a tip left the predicted column before their last

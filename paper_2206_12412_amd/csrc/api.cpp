@@ -1255,6 +1255,62 @@ int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *rows, int32_t *wav
   return rc;
 }
 
+int lbm_autotune_time_block(lbm_handle *h, int32_t steps, int32_t trial_sweeps, int32_t *rows,
+                            int32_t *waves, double *ms_per_step) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (h->in_batch) return fail(LBM_ESTATE, "plates of a batch step one time step per sweep");
+  if (steps < 2 || steps > lbmk::kMaxTimeBlock) return fail(LBM_EINVAL, "steps must be 2 to 8");
+  if (trial_sweeps < 1 || trial_sweeps > 1000)
+    return fail(LBM_EINVAL, "trial_sweeps must be in 1..1000");
+  static const int kRows[] = {4, 8, 16};
+  static const int kWaves[] = {1, 2, 4, 8};
+  int rc = lbm_set_time_block(h, steps, 0, 0);  // refuses plates the T-step sweep cannot take
+  if (rc != LBM_OK) return rc;
+  const bool was_timing = h->timing;
+  h->timing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    h->timing = was_timing;
+    return fail(LBM_EHIP, "event creation failed");
+  }
+  float best = -1.0f;
+  int br = h->blk_rows[steps], bw = h->blk_waves[steps];
+  for (int r : kRows) {
+    if (steps >= 6 && r != 16) continue;
+    for (int w : kWaves) {
+      rc = lbm_set_time_block(h, steps, r, w);
+      if (rc == LBM_OK) rc = lbm_step(h, steps);
+      if (rc == LBM_OK && hipEventRecord(e0, h->stream) != hipSuccess)
+        rc = fail(LBM_EHIP, "event record failed");
+      if (rc == LBM_OK) rc = lbm_step(h, (int64_t)trial_sweeps * steps);
+      if (rc == LBM_OK && hipEventRecord(e1, h->stream) != hipSuccess)
+        rc = fail(LBM_EHIP, "event record failed");
+      float t = 0.0f;
+      if (rc == LBM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        rc = fail(LBM_EHIP, "event timing failed");
+      if (rc != LBM_OK) break;
+      if (best < 0.0f || t < best) {
+        best = t;
+        br = r;
+        bw = w;
+      }
+    }
+    if (rc != LBM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->timing = was_timing;
+  if (rc != LBM_OK) return rc;
+  rc = lbm_set_time_block(h, steps, br, bw);
+  if (rc != LBM_OK) return rc;
+  if (rows) *rows = br;
+  if (waves) *waves = bw;
+  if (ms_per_step) *ms_per_step = (double)best / ((double)trial_sweeps * steps);
+  return LBM_OK;
+}
+
 double lbm_bytes_per_site(const lbm_handle *h) {
   if (!h) return 0.0;
   const double e = (double)elem_size(h->store), we = is_fp64(h->store) ? 8.0 : 4.0;

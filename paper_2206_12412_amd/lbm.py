@@ -38,6 +38,7 @@ ERRORS = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE
 EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
            "lbm_cut_events", "lbm_cut_links", "lbm_get_fields", "lbm_get_populations", "lbm_get_mask",
            "lbm_timing", "lbm_get_launch", "lbm_set_launch", "lbm_set_time_block", "lbm_time_block_stats",
+           "lbm_autotune_time_block",
            "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
            "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
            "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
@@ -111,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_set_time_block.restype = i32
     lib.lbm_time_block_stats.argtypes = [vp, P(i64), P(i64)]
     lib.lbm_time_block_stats.restype = i32
+    lib.lbm_autotune_time_block.argtypes = [vp, i32, i32, P(i32), P(i32), P(d)]
+    lib.lbm_autotune_time_block.restype = i32
     lib.lbm_get_fields.argtypes = [vp, P(d), P(d)]
     lib.lbm_get_populations.argtypes = [vp, P(d)]
     lib.lbm_get_mask.argtypes = [vp, P(C.c_uint8), P(C.c_uint8)]
@@ -489,6 +492,22 @@ class Solver:
     def set_time_block(self, steps: int = 2, rows: int = 0, waves: int = 0):
         """Advance `steps` (1 to 8) time steps per sweep; see lbm_set_time_block."""
         _check(self._lib.lbm_set_time_block(self._h, int(steps), int(rows), int(waves)))
+
+    def autotune_time_block(self, steps: int, trial_sweeps: int = 4) -> dict:
+        """Searches the T-step sweep's shapes (steps = T) on a scratch plate
+        built from this plate's config (this plate's state is untouched) and
+        sets steps = T with the fastest shape here."""
+        scratch = Solver(dataclasses.replace(self.cfg, trace_cap=0), device=str(self._buf.device),
+                         stream=self.stream)
+        r, w, ms = C.c_int32(), C.c_int32(), C.c_double()
+        try:
+            _check(self._lib.lbm_autotune_time_block(scratch._h, int(steps), int(trial_sweeps),
+                                                     C.byref(r), C.byref(w), C.byref(ms)))
+        finally:
+            scratch.close()
+            del scratch
+        self.set_time_block(steps, r.value, w.value)
+        return {"steps": int(steps), "rows": r.value, "waves": w.value, "ms_per_step": ms.value}
 
     def time_block_stats(self) -> dict:
         """T-step sweeps run under the K criterion and how many were run again

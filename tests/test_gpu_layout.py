@@ -351,6 +351,29 @@ def test_time_blocked_sweep_under_the_K_criterion_16bit_against_the_oracle(stora
     assert np.abs(ev_g[:, 0] - ev_r[:, 0]).max() <= 3
 
 
+@pytest.mark.parametrize("T,name", [(4, "sif-edge"), (6, "sif-two-tip"), (3, "sif-dirichlet")])
+def test_time_block_autotune_picks_a_shape_and_keeps_the_results(T, name):
+    """lbm_autotune_time_block times the T-step shapes on a scratch plate and
+    sets the fastest: a shape of the grid, this plate's state untouched, the
+    results bit for bit those of one step per sweep."""
+    steps = 120
+    kw = sif_cases(steps)[name]
+    one = Solver(Config(storage="f32", layout="eq", **kw))
+    blk = Solver(Config(storage="f32", layout="eq", **kw))
+    out = blk.autotune_time_block(T, trial_sweeps=2)
+    say(f"autotune T={T} {name}: {out}")
+    assert out["steps"] == T and out["waves"] in (1, 2, 4, 8) and out["ms_per_step"] > 0
+    assert out["rows"] in ((16,) if T >= 6 else (4, 8, 16))
+    assert blk.steps_done == 0
+    one.step(steps)
+    blk.step(steps)
+    same(one, blk, f"autotuned T={T} {name}", kw.get("both_tips", False))
+    with pytest.raises(Exception):
+        blk.autotune_time_block(9)
+    one.close()
+    blk.close()
+
+
 def test_time_blocked_sweep_refuses_what_it_cannot_do():
     base = tb_cases(10)["edge-prescribed"]
     with pytest.raises(Exception):
