@@ -854,10 +854,17 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
           }
           spec = h->cfg.growth == LBM_GROW_SIF;
           if (spec) {
-            if (!h->spec_host) {
-              HIP_TRY(hipHostMalloc((void **)&h->spec_host, sizeof(lbmk::SpecOut),
+            if (!h->spec_dev) {  // both pointers or neither
+              lbmk::SpecOut *hp = nullptr;
+              void *dp = nullptr;
+              HIP_TRY(hipHostMalloc((void **)&hp, sizeof(lbmk::SpecOut),
                                     hipHostMallocMapped | hipHostMallocCoherent));
-              HIP_TRY(hipHostGetDevicePointer((void **)&h->spec_dev, h->spec_host, 0));
+              if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess || !dp) {
+                (void)hipHostFree(hp);
+                return fail(LBM_EHIP, "no device address for the pinned verdict buffer");
+              }
+              h->spec_host = hp;
+              h->spec_dev = static_cast<lbmk::SpecOut *>(dp);
             }
             *(volatile int32_t *)&h->spec_host->valid = -1;
             q.spec_out = h->spec_dev;
