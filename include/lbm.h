@@ -253,7 +253,10 @@ int lbm_restore(lbm_handle *h, const void *src);
  * every step whose index is a multiple of n (n > 1 samples the steps, so that
  * the events cost less); 0 stops.  Returns the summed durations (ms) of the
  * two kernels over the timed steps and their number (synchronises the
- * stream).  Any output pointer may be NULL. */
+ * stream).  With time blocking a sweep and its crack steps are timed
+ * together when one of its steps is sampled; a speculative sweep that is run
+ * again (K criterion) adds its time but not its steps.  Any output pointer
+ * may be NULL. */
 int lbm_timing(lbm_handle *h, int32_t enable, double *sweep_ms, double *crack_ms, int64_t *n_timed);
 
 /* Launch shape of the sweep: sites per lane along x (vec, fixed by the
