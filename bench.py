@@ -7,15 +7,22 @@ severed links).  Default workload: the 16384 x 8192 plate (134M sites) with a
 FP32, FP16 and BF16 (the last three shifted by the static equilibrium, FP32
 arithmetic), in the five-population layout and in the equilibrium layout
 (rest population and w only; the moving populations are rebuilt from the
-equilibrium of their emitting site, exact at omega = 1), one to four time
-steps per sweep ("-tb", "-tb3" .. "-tb8": two to eight steps per sweep,
-each step's crack step still run).  The JSON line reports the headline
-storage's GLUPS (FP16, equilibrium layout, six steps per sweep, stochastic
-rounding) as `value`, next to the
-FP32 GLUPS of the same layout and of the five-population layout, each
-storage's K_III and field error against the FP64 run of the same steps, the
-HBM roofline of the sweep kernel and the oracle's CPU throughput on a
-bounded sample.
+equilibrium of their emitting site, exact at omega = 1), with one to eight
+time steps per sweep ("-tb", "-tb3" .. "-tb8": two to eight steps per sweep,
+each step's crack step still run).
+
+Per storage: a warm-up on the timed plate itself (start-up steps, code
+loading, clocks), one timed interval of --steps steps (HIP events on the
+solver's stream), the field error at its end against the first storage (FP64,
+five populations), and a short leg of whole T-step sweeps with per-launch
+events for the sweep kernel's duration.  Then an untimed leg runs the whole
+10000-step workload in a few storages for the K_III(t) errors (the load
+waves reach the crack only after ~8200 steps).
+
+The JSON line reports the headline storage's GLUPS (FP16, equilibrium layout,
+six steps per sweep, stochastic rounding) as `value`; `roofline` is that of
+the one-step five-population FP16 sweep (28 B per site update), and
+`roofline_headline_kernel` the headline kernel's fraction in its own bytes.
 
     python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb6-sr] [--workload precision]
 """
@@ -110,58 +117,39 @@ def traffic_for(storage: str, workload: str, sites: int):
     return t.get("bytes_per_launch")
 
 
-def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=True):
-    """Time `steps` steps of plate p in this storage.  The run is cut at the
-    checkpoints, where w is exported (outside the timed intervals); each
-    segment is timed with HIP events on the solver's stream between two
-    synchronisations, and the step time is the sum over the segments.  With
-    a reference run, the field errors against its snapshots are returned
-    instead of the snapshots."""
+def run_storage(p, storage, steps, warmup, torch, ref=None, tune=False):
+    """Time `steps` steps of plate p in this storage, as one interval.
+
+    The plate is warmed up by `warmup` steps of its own (at least the two
+    five-plane start-up steps that a fresh equilibrium-layout plate runs, so
+    those, code loading and clock ramp fall outside the timed interval); the
+    interval is timed with HIP events on the solver's stream between two
+    synchronisations.  After it, w is exported (compared with the reference
+    run's w at the same step when one is given) and a short kernel-timing leg
+    runs whole T-step sweeps with per-launch HIP events, so that the sweep
+    kernel's launch duration is sampled on full sweeps only and the events do
+    not perturb the timed interval."""
     from paper_2206_12412_amd import Solver
-    # warm-up on a throw-away plate (clocks, code objects, page tables)
-    if warmup > 0:
-        s = Solver(plate_config(p, storage, 0))
-        if time_block(storage) >= 2:
-            s.set_time_block(time_block(storage))
-        s.step(warmup)
-        torch.cuda.synchronize()
-        s.close()
-        del s
-        torch.cuda.empty_cache()
-    s = Solver(plate_config(p, storage, steps))
+    T = time_block(storage)
+    warm = max(int(warmup), 2)
+    k_steps = T * max(1, -(-12 // T))  # whole sweeps, at least 12 steps
+    s = Solver(plate_config(p, storage, warm + steps + k_steps))
     tuned = s.autotune(trial_steps=5) if tune else None  # on a scratch copy of the plate
-    if time_block(storage) >= 2:
+    if T >= 2:
         if tune:  # the T-step sweep's own shapes, also on a scratch copy
-            tuned = {"one_step": tuned, "time_block": s.autotune_time_block(time_block(storage))}
+            tuned = {"one_step": tuned, "time_block": s.autotune_time_block(T)}
         else:
-            s.set_time_block(time_block(storage))
+            s.set_time_block(T)
+    s.step(warm)
     torch.cuda.synchronize()
-    # per-kernel HIP events on every 10th step of the timed region
-    s.timing(True, stride=10)
-    ms = 0.0
-    done = 0
-    snaps, errs = {}, {}
-    for n in checkpoints:
-        start = torch.cuda.Event(enable_timing=True)
-        stop = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        start.record(s.stream)
-        s.step(n - done)
-        stop.record(s.stream)
-        torch.cuda.synchronize()
-        ms += start.elapsed_time(stop)
-        done = n
-        w = s.fields()[0]
-        if ref is None:
-            snaps[n] = w
-        else:
-            r = ref["snaps"][n]
-            d = w - r
-            rms_r = float(np.sqrt(np.mean(r * r)))
-            errs[n] = {"rms_rel": float(np.sqrt(np.mean(d * d))) / rms_r if rms_r > 0 else None,
-                       "max_rel": float(np.abs(d).max() / np.abs(r).max()) if rms_r > 0 else None}
-        del w
-    tm = s.timing(False)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(s.stream)
+    s.step(steps)
+    stop.record(s.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    w = s.fields()[0]
     out = {
         "ms": ms,
         "glups": p.sites * steps / (ms * 1e-3) / 1e9,
@@ -169,21 +157,80 @@ def run_storage(p, storage, steps, warmup, torch, checkpoints, ref=None, tune=Tr
         "sites": s.sites(),
         "launch": s.launch(),
         "autotune": tuned,
-        "K": s.sif(0, steps),
-        "tip": s.traces(0, steps)["tip"],
-        "snaps": snaps,
-        "field_errors": errs,
+        "first_step": warm,
     }
-    if tm["steps"]:
-        out["sweep_ms"] = tm["sweep_ms"] / tm["steps"]
-        out["crack_ms"] = tm["crack_ms"] / tm["steps"]
-    if time_block(storage) >= 2:
-        # K criterion: speculative T-step sweeps and the ones run again
-        out["time_block_stats"] = s.time_block_stats()
+    if ref is None:
+        out["w_end"] = w
+    else:
+        out["field_error"] = field_error(w, ref["w_end"])
+        out["tip_path_identical"] = bool(np.array_equal(s.traces(warm, steps)["tip"],
+                                                        ref["tip"]))
+    if ref is None:
+        out["tip"] = s.traces(warm, steps)["tip"]
+    del w
+    s.timing(True, stride=1)
+    s.step(k_steps)
+    tm = s.timing(False)
+    launches = tm["steps"] // T
+    if launches:
+        out["kernel_ms_per_launch"] = tm["sweep_ms"] / launches
+        out["crack_ms_per_launch"] = tm["crack_ms"] / launches
+        out["steps_per_launch"] = T
+        out["timed_launches"] = launches
     s.close()
     del s
     torch.cuda.empty_cache()
     return out
+
+
+def field_error(w, r):
+    """RMS and max of w - r relative to the reference field (None where the
+    reference is still zero)."""
+    d = w - r
+    rms_r = float(np.sqrt(np.mean(r * r)))
+    if rms_r == 0:
+        return {"rms_rel": None, "max_rel": None}
+    return {"rms_rel": float(np.sqrt(np.mean(d * d))) / rms_r,
+            "max_rel": float(np.abs(d).max() / np.abs(r).max())}
+
+
+def run_k_leg(p, storage, steps, torch):
+    """Untimed run of the whole workload (all `steps` steps, so that the load
+    waves reach the crack and K is defined) for the K_III and field errors:
+    returns the K trace and the final w."""
+    from paper_2206_12412_amd import Solver
+    T = time_block(storage)
+    s = Solver(plate_config(p, storage, steps))
+    if T >= 2:
+        s.set_time_block(T)
+    s.step(steps)
+    K = s.sif(0, steps)
+    tip = s.traces(0, steps)["tip"]
+    w = s.fields()[0]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return {"K": K, "tip": tip, "w": w}
+
+
+def copy_bandwidth(torch, mib: int = 4096, reps: int = 10) -> float:
+    """GB/s of a plain device-to-device copy (read + write counted): the
+    practical ceiling of a kernel that reads and writes every byte once."""
+    n = mib << 20
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def k_errors(K, K_ref):
@@ -572,7 +619,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="precision",
                     choices=["precision", "sif", "plain", "batched", "adjoint", "strip"])
     ap.add_argument("--adjoint-storage", default="f32-eq",
@@ -594,6 +641,14 @@ def main():
                             "f16s-eq-tb-sr,f16s-eq-tb4-sr,"
                             "f64-eq-tb8,f32-eq-tb6,f32-eq-tb8,f16s-eq-tb6-sr,bf16s-eq-tb6-sr",
                     help="storages run; the first is the error reference")
+    ap.add_argument("--record", default="f16s-sr",
+                    help="storage whose one-step five-population sweep is the roofline of record")
+    ap.add_argument("--k-steps", type=int, default=None,
+                    help="steps of the untimed K_III / field error leg (default: the workload's; "
+                         "0 skips it)")
+    ap.add_argument("--k-compare", default="f64,f32,f16s-sr,bf16s-sr,f32-eq-tb6,f16s-eq-tb6-sr,"
+                                           "bf16s-eq-tb6-sr",
+                    help="storages of the K_III / field error leg; the first is the reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -637,10 +692,13 @@ def main():
         return
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
          "plain": synth.config_plain_fp64}[args.workload]()
-    steps = args.steps if args.steps is not None else p.steps
+    # timed steps: the driver passes --steps; by default 1200 (whole sweeps for
+    # T = 2 .. 6 and 8), while the untimed error leg runs the whole workload
+    steps = args.steps if args.steps is not None else (1200 if args.workload == "precision" else p.steps)
     storages = [s for s in args.compare.split(",") if s]
-    if args.storage not in storages:
-        storages.append(args.storage)
+    for extra in (args.record, args.storage):
+        if extra not in storages:
+            storages.append(extra)
     ref_name = storages[0]
 
     if args.calibrate_copy > 0:
@@ -652,52 +710,66 @@ def main():
         print(f"calibration copy of {n} bytes done", file=sys.stderr, flush=True)
         del a, b
 
-    checkpoints = sorted({int(round(steps * f)) for f in (0.25, 0.5, 0.75, 1.0)} - {0})
     results = {}
     ref = None
     for st in storages:
         print(f"bench: {p.name} storage={st} steps={steps} warmup={args.warmup}", file=sys.stderr,
               flush=True)
-        results[st] = run_storage(p, st, steps, args.warmup, torch, checkpoints, ref,
-                                  tune=args.tune)
+        results[st] = run_storage(p, st, steps, args.warmup, torch, ref, tune=args.tune)
         if ref is None:
             ref = results[st]
         print(f"bench: {st}: {results[st]['glups']:.1f} GLUPS", file=sys.stderr, flush=True)
+    ref.pop("w_end", None)
+
+    # K_III and field errors over the whole workload (untimed)
+    k_steps = args.k_steps if args.k_steps is not None else (p.steps if args.workload == "precision" else 0)
+    k_storages = [s for s in args.k_compare.split(",") if s] if k_steps > 0 else []
+    if k_storages and args.storage not in k_storages:
+        k_storages.append(args.storage)
+    k_res = {}
+    for st in k_storages:
+        print(f"bench: K leg, storage={st}, {k_steps} steps", file=sys.stderr, flush=True)
+        r = run_k_leg(p, st, k_steps, torch)
+        if not k_res:
+            k_res[st] = r
+            continue
+        r0 = k_res[k_storages[0]]
+        k_res[st] = dict(k_errors(r["K"], r0["K"]), field_error=field_error(r["w"], r0["w"]),
+                         tip_path_identical=bool(np.array_equal(r["tip"], r0["tip"])))
+    k_ref = k_storages[0] if k_storages else None
+    if k_ref:
+        k_res[k_ref] = {"reference": True}
+
+    copy_gbs = copy_bandwidth(torch)
 
     per = {}
     for st, r in results.items():
         e = {"glups": round(r["glups"], 2), "ms_per_step": round(r["ms"] / steps, 4),
              "bytes_per_site": r["bytes_per_site"], "launch": r["launch"]}
-        if "sweep_ms" in r:
-            gbs = r["sites"] * r["bytes_per_site"] / (r["sweep_ms"] * 1e-3) / 1e9
-            e["sweep_kernel_ms"] = round(r["sweep_ms"], 4)
-            e["crack_kernel_ms"] = round(r["crack_ms"], 4)
-            e["sweep_GBps"] = round(gbs, 1)
+        if "kernel_ms_per_launch" in r:
+            T = r["steps_per_launch"]
+            own = r["sites"] * r["bytes_per_site"] * T  # algorithmic bytes of one launch
+            gbs = own / (r["kernel_ms_per_launch"] * 1e-3) / 1e9
+            e["kernel"] = block_kernel(st)
+            e["steps_per_launch"] = T
+            e["kernel_ms_per_launch"] = round(r["kernel_ms_per_launch"], 4)
+            e["crack_ms_per_launch"] = round(r["crack_ms_per_launch"], 4)
+            e["kernel_GBps"] = round(gbs, 1)
             e["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+            e["copy_frac"] = round(gbs / copy_gbs, 4)
+            tr = traffic_for(st, args.workload, p.sites)
+            if tr:
+                e["traffic_over_algorithmic"] = round(tr / own, 4)
         if r.get("autotune"):
             e["autotune"] = r["autotune"]
-        if r.get("time_block_stats", {}).get("sweeps"):
-            e["speculative_sweeps"] = r["time_block_stats"]
         if st != ref_name:
-            e.update(k_errors(r["K"], ref["K"]))
-            e["field_err_vs_" + ref_name] = {str(n): v for n, v in r["field_errors"].items()}
-            e["tip_path_identical"] = bool(np.array_equal(r["tip"], ref["tip"]))
+            e["field_err_vs_" + ref_name] = r["field_error"]
+            e["tip_path_identical"] = r["tip_path_identical"]
+        if st in k_res and st != k_ref:
+            e["whole_run_errors_vs_" + k_ref] = k_res[st]
         per[st] = e
-    ref["snaps"].clear()
 
     head = results[args.storage]
-    bps = head["bytes_per_site"]
-    tb = time_block(args.storage)
-    alg = head["sites"] * bps * tb  # algorithmic bytes of one sweep-kernel launch (tb steps)
-    achieved = alg / (head["sweep_ms"] * tb * 1e-3) / 1e9
-    traffic = traffic_for(args.storage, args.workload, p.sites)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic,
-                "kernel": f"{block_kernel(args.storage)} ({args.storage})",
-                "steps_per_launch": tb, "algorithmic_bytes_per_launch": alg,
-                "kernel_ms": round(head["sweep_ms"] * tb, 4)}
-
     line = {
         "metric": METRIC,
         "value": round(head["glups"], 2),
@@ -716,21 +788,65 @@ def main():
                    "tau": p.tau, "storage": parse_storage(args.storage)[0],
                    "rounding": parse_storage(args.storage)[1],
                    "layout": parse_storage(args.storage)[2],
+                   "steps_per_sweep": time_block(args.storage),
+                   "timed_steps": [head["first_step"], head["first_step"] + steps],
                    "parallelism": "single-gpu"},
         "storages": per,
         "error_reference": ref_name,
+        "copy_GBps": round(copy_gbs, 1),
     }
-    # FP16 storage against FP32 storage in the same layout, and against the
-    # five-plane FP32 run
+    # FP16 storage against FP32 storage: in the headline's layout, and in the
+    # five-population layout (the layout the 48 / 28 B/site ratio is stated for)
     same32 = "f32" + args.storage[len(parse_storage(args.storage)[0]):].replace("-sr", "")
     if same32 in results and args.storage != same32:
         line["vs_f32_glups"] = round(head["glups"] / results[same32]["glups"], 3)
         line["vs_f32_reference"] = same32
-    if "f32" in results and args.storage != "f32":
-        line["vs_f32_five_planes_glups"] = round(head["glups"] / results["f32"]["glups"], 3)
-    if args.storage != ref_name:
-        line["K_III_error"] = {k: v for k, v in per[args.storage].items() if k.startswith("K_err")}
-    line["roofline"] = roofline
+    if args.record in results and "f32" in results:
+        line["fp16_vs_fp32_five_planes"] = {
+            "fp16": args.record, "fp32": "f32",
+            "glups_ratio": round(results[args.record]["glups"] / results["f32"]["glups"], 3),
+            "kernel_ratio": round(results["f32"]["kernel_ms_per_launch"]
+                                  / results[args.record]["kernel_ms_per_launch"], 3)}
+    if args.storage in k_res and args.storage != k_ref:
+        line["K_III_error"] = dict(
+            {k: v for k, v in k_res[args.storage].items() if k.startswith("K_err")},
+            storage=args.storage, reference=k_ref + " (five planes, FP64: bit for bit the FP64 oracle)",
+            steps=k_steps, workload=p.name)
+    # roofline of record: the one-step five-plane sweep of the FP16 storage,
+    # whose algorithmic bytes are read + write of the five populations (2 B)
+    # and of w (4 B) per site update
+    if args.record in results and "kernel_ms_per_launch" in results[args.record]:
+        r = results[args.record]
+        alg = r["sites"] * sweep_bytes_per_site(args.record)
+        achieved = alg / (r["kernel_ms_per_launch"] * 1e-3) / 1e9
+        tr = traffic_for(args.record, args.workload, p.sites)
+        line["roofline"] = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+            "kernel": f"sweep_step ({args.record}: five populations, one step per launch)",
+            "bytes_per_site": sweep_bytes_per_site(args.record),
+            "algorithmic_bytes_per_launch": alg,
+            "kernel_ms": round(r["kernel_ms_per_launch"], 4),
+            "copy_frac": round(achieved / copy_gbs, 4)}
+    # the headline's own kernel: T steps per launch in the equilibrium layout,
+    # counted in the bytes it must move (rest population and w, read and
+    # written once per launch), not in the five-population bytes of the T
+    # steps it replaces
+    if "kernel_ms_per_launch" in head and args.storage != args.record:
+        T = head["steps_per_launch"]
+        alg = head["sites"] * head["bytes_per_site"] * T
+        achieved = alg / (head["kernel_ms_per_launch"] * 1e-3) / 1e9
+        tr = traffic_for(args.storage, args.workload, p.sites)
+        line["roofline_headline_kernel"] = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+            "kernel": f"{block_kernel(args.storage)} ({args.storage})", "steps_per_launch": T,
+            "bytes_per_site_per_launch": head["bytes_per_site"] * T,
+            "algorithmic_bytes_per_launch": alg,
+            "kernel_ms": round(head["kernel_ms_per_launch"], 4),
+            "kernel_ms_per_step": round(head["kernel_ms_per_launch"] / T, 4),
+            "note": "equilibrium layout (only the rest population and w are state at omega = 1); "
+                    "its bytes are not the five-population bytes the roofline of record counts"}
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)

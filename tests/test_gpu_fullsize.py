@@ -20,6 +20,7 @@ import pytest
 
 import oracle as O
 import synth
+from _errlog import record
 
 pytestmark = pytest.mark.gpu
 
@@ -153,6 +154,7 @@ def test_precision_plate_windows(big_plate, storage, tol):
         worst = max(worst, e)
         say(f"  window ({ic},{jc}): w rel err {e:.2e}, wdot rel err {ed:.2e}")
         assert e <= tol, (storage, ic, jc, e)
+    record("w", worst, storage=storage)
     say(f"  worst {worst:.2e}")
 
 
@@ -250,40 +252,70 @@ def test_sif_workload_fp64_equilibrium_layout(sif_golden):
     assert tip_dev <= 3 * max(ptip, 0.5)
 
 
-def test_sif_workload_fp32_cut_sequence_and_margins(sif_golden):
-    """FP32: fields within 1e-5 before the crack grows; the cut sequence
-    equals the oracle's up to the first step at which the oracle's guard
-    margin |K/K_C - 1| falls inside the measured FP32 K error band."""
+def test_sif_workload_fp32_decisions_and_path(sif_golden):
+    """FP32 on the 4096 x 2048 K-criterion workload.
+
+    * Fields within 1e-5 and K within 1e-5 of the oracle's up to the onset of
+      growth.
+    * Every criterion decision (K > K_C or not) equals the oracle's for all
+      steps before the horizon, the first step whose margin |K/K_C - 1| lies
+      within 10x the measured K error.  The horizon must lie past the oracle's
+      onset step (3283, margin 1.85e-4), so the onset itself and the 3283
+      decisions before it are compared.
+    * From the onset on, the tanh law's infinite slope at K = K_C makes the
+      path sensitive to the state at the level of rounding (the oracle with
+      its initial velocity scaled by 1 + 1e-14 cuts its first link 3 steps
+      later), so the cut events are compared as for the other arithmetic
+      that is not bit-identical to the oracle's: the same columns, the event
+      count and the step shifts within the envelope of that perturbed oracle
+      run.  Bit-exact event parity under the K criterion is asserted on a
+      plate whose margins hold throughout (test_gpu_parity)."""
     g = sif_golden
     say("4096x2048 K criterion, FP32 (shifted storage), 20000 steps")
     p, snaps, tr, ev = run_sif("f32", g)
-    first_growth = int(np.argmax((np.array(g["flags"]) & 1) != 0))
+    flags_r = np.array(g["flags"])
+    onset = int(np.argmax((flags_r & 1) != 0))
     for n, (w, wd) in snaps.items():
         ref = g["snapshots"][str(n)]
         e = np.abs(w - np.array(ref["w"])).max() / ref["w_absmax"]
         say(f"  step {n}: sampled w rel err {e:.2e}")
-        if n < first_growth:
+        if n < onset:
             assert e <= 1e-5
     K_ref = np.array(g["K"])
     ok = ~np.isnan(K_ref)
-    pre = ok & (np.arange(len(K_ref)) < first_growth)
+    pre = ok & (np.arange(len(K_ref)) < onset)
     kerr = np.abs(tr["K"][pre] - K_ref[pre]).max() / np.abs(K_ref[pre]).max()
+    record("K_pre_onset", kerr, storage="f32")
     margin = np.abs(K_ref / p.K_C - 1)
     band = 10 * kerr
     risky = np.nonzero(ok & (margin < band))[0]
     horizon = int(risky[0]) if len(risky) else len(K_ref)
-    ref_ev = [e for e in g["events"] if e[0] < horizon]
-    got_ev = [e for e in ev.tolist() if e[0] < horizon]
-    same = 0
-    for a, b in zip(ref_ev, ev.tolist()):
-        if a != b:
-            break
-        same += 1
-    say(f"  pre-growth K rel err {kerr:.2e}; first step with margin < {band:.1e}: {horizon}; "
-        f"events identical before it: {got_ev == ref_ev} ({len(ref_ev)}); leading identical "
-        f"events overall: {same} of {len(g['events'])}")
-    assert got_ev == ref_ev
+    grew_r, grew_g = (flags_r & 1) != 0, (tr["flags"] & 1) != 0
+    decided = int(np.sum(ok[:horizon]))
+    first_diff = np.nonzero(grew_r != grew_g)[0]
+    say(f"  pre-onset K rel err {kerr:.2e}; band {band:.1e}; horizon {horizon} (onset {onset}, "
+        f"margin there {margin[onset]:.2e}); decisions compared {decided}; first differing "
+        f"decision {int(first_diff[0]) if len(first_diff) else None}")
     assert kerr <= 1e-5
+    assert horizon > onset, (horizon, onset)
+    assert decided >= onset
+    assert np.array_equal(grew_g[:horizon], grew_r[:horizon])
+    # after the onset: the envelope of the oracle perturbed at the level of rounding
+    with open(os.path.join(HERE, "golden", "sif_4096x2048_perturbed.json")) as fh:
+        q = json.load(fh)
+    gev, pev = np.array(g["events"]), np.array(q["events"])
+    n = min(len(ev), len(gev))
+    shift = np.abs(ev[:n, 0] - gev[:n, 0])
+    pshift = int(np.abs(pev[:min(len(pev), len(gev)), 0] - gev[:min(len(pev), len(gev)), 0]).max())
+    ptip = float(np.abs(np.array(q["tip"]) - np.array(g["tip"])).max())
+    tip_dev = float(np.abs(tr["tip"] - np.array(g["tip"])).max())
+    say(f"  events {len(ev)} vs {len(gev)} (perturbed oracle {len(pev)}); max step shift "
+        f"{shift.max()} (perturbed oracle {pshift}); tip deviation {tip_dev:.3f} (perturbed "
+        f"oracle {ptip:.3f})")
+    assert n > 3000 and np.array_equal(ev[:n, 1], gev[:n, 1])
+    assert abs(len(ev) - len(gev)) <= max(2, 2 * abs(len(pev) - len(gev)))
+    assert shift.max() <= 3 * max(pshift, 1)
+    assert tip_dev <= 3 * max(ptip, 0.5)
 
 
 # ------------------------------------------------------- batched workload --

@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from _errlog import record
 
 pytestmark = pytest.mark.gpu
 
@@ -270,6 +271,7 @@ def test_time_blocked_sweep_16bit_against_the_oracle(storage, case, T):
     s.step(steps)
     w_r = ref.fields()[0]
     tol = (4 * 2.0 ** -11 if storage == "f16s" else 4 * 2.0 ** -8) * np.sqrt(steps)
+    record("w", np.abs(s.fields()[0] - w_r).max() / np.abs(w_r).max(), storage=storage, T=T)
     assert np.abs(s.fields()[0] - w_r).max() <= tol * np.abs(w_r).max()
     for tip in (("right", "left") if kw.get("both_tips") else ("right",)):
         np.testing.assert_array_equal(s.traces(tip=tip)["tip"], ref.traces(tip)["tip"])
@@ -346,6 +348,7 @@ def test_time_blocked_sweep_under_the_K_criterion_16bit_against_the_oracle(stora
     kerr = np.abs(K_g[ok] - K_r[ok]).max() / np.abs(K_r[ok]).max()
     say(f"K criterion {storage} T={T}: K error {kerr:.2e} before step {first}; "
         f"{len(ev_g)} cuts (oracle {len(ev_r)})")
+    record("K", kerr, storage=storage, T=T)
     assert kerr <= (2e-3 if storage == "f16s" else 1e-2)
     assert ev_g[:, 1].tolist() == ev_r[:, 1].tolist()
     assert np.abs(ev_g[:, 0] - ev_r[:, 0]).max() <= 3
