@@ -270,7 +270,9 @@ def test_time_blocked_sweep_16bit_against_the_oracle(storage, case, T):
     s.set_time_block(T)
     s.step(steps)
     w_r = ref.fields()[0]
-    tol = (4 * 2.0 ** -11 if storage == "f16s" else 4 * 2.0 ** -8) * np.sqrt(steps)
+    # about three times the largest error measured over T = 2 .. 8 (FP16
+    # 3.1e-4, BF16 2.0e-3)
+    tol = 1e-3 if storage == "f16s" else 6e-3
     record("w", np.abs(s.fields()[0] - w_r).max() / np.abs(w_r).max(), storage=storage, T=T)
     assert np.abs(s.fields()[0] - w_r).max() <= tol * np.abs(w_r).max()
     for tip in (("right", "left") if kw.get("both_tips") else ("right",)):
@@ -349,7 +351,8 @@ def test_time_blocked_sweep_under_the_K_criterion_16bit_against_the_oracle(stora
     say(f"K criterion {storage} T={T}: K error {kerr:.2e} before step {first}; "
         f"{len(ev_g)} cuts (oracle {len(ev_r)})")
     record("K", kerr, storage=storage, T=T)
-    assert kerr <= (2e-3 if storage == "f16s" else 1e-2)
+    # about three times the largest measured K error (FP16 6.1e-5, BF16 1.0e-3)
+    assert kerr <= (2e-4 if storage == "f16s" else 3e-3)
     assert ev_g[:, 1].tolist() == ev_r[:, 1].tolist()
     assert np.abs(ev_g[:, 0] - ev_r[:, 0]).max() <= 3
 

@@ -24,10 +24,15 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 from paper_2206_12412_amd import Config, Solver  # noqa: E402
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "f32plain": 2e-3, "f16s": 2e-3, "bf16s": 3e-2}
-KTOL = {"f64": 1e-12, "f32": 1e-5, "f32plain": 5e-3, "f16s": 1e-3, "bf16s": 2e-2}
-# "-sr": the same storage with stochastic rounding of the 16-bit stores (the
-# same bounds hold: each stored value is still within one 16-bit ulp)
+# FP64 and FP32: the bars of the method's statement.  The reduced
+# precisions (unshifted FP32, FP16 and BF16 storage) are held to about three
+# times the largest error measured on MI355X over this file's cases (the
+# 2000-step plain workload: w 2.3e-5 / 1.2e-4 / 1.2e-3, K 1.1e-5 / 8e-5 /
+# 5.9e-4), so that a regression of a few times shows; K of FP16 storage keeps
+# the 1e-3 bar of the precision extension (largest measured 5.3e-4).
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32plain": 7e-5, "f16s": 4e-4, "bf16s": 4e-3}
+KTOL = {"f64": 1e-12, "f32": 1e-5, "f32plain": 5e-5, "f16s": 1e-3, "bf16s": 2e-3}
+# "-sr": the same storage with stochastic rounding of the 16-bit stores
 for _d in (TOL, KTOL):
     _d.update({"f16s-sr": _d["f16s"], "bf16s-sr": _d["bf16s"]})
 
@@ -146,9 +151,10 @@ def test_ragged_sizes(nx, ny, ell, storage):
     kw = plain_kw(nx, ny, max(ell, 0), v=0.6, steps=steps)
     rng = np.random.default_rng(nx * 1000 + ny)
     kw["wdot0"] = rng.normal(0, 1e-4, (ny, nx))
-    # noise-only fields: the stored 16-bit wdot is rounded by u = 2^-11 each
-    # step; a random walk over n steps, max-norm factor 4: 4 u sqrt(n)
-    tol = 4 * 2.0 ** -11 * math.sqrt(steps) if storage.startswith("f16s") else None
+    # noise-only fields, relative to the largest |w| of small plates: about
+    # three times the largest error measured (4.8e-3 nearest, 9.5e-4
+    # stochastic rounding, over all sizes)
+    tol = {"f16s": 1.5e-2, "f16s-sr": 3e-3}.get(storage)
     compare_run(storage, kw, steps, [1, 7, steps], tol=tol)
 
 
@@ -301,7 +307,7 @@ def test_stochastic_rounding_is_deterministic_per_seed():
     w_r = ref.fields()[0]
     for s in (a, c):
         record("w", relerr(s.fields()[0], w_r), storage="f16s-sr")
-        assert relerr(s.fields()[0], w_r) <= TOL["f16s"]
+        assert relerr(s.fields()[0], w_r) <= 7e-4  # 3x the largest measured (2.3e-4)
 
 
 
@@ -325,7 +331,7 @@ def dirichlet_two_tip_kw(nx, ny, steps, row, x0, a0, v=0.4):
 def test_dirichlet_edges_off_centre_crack_two_tips(nx, ny, row, x0, a0, storage):
     steps = 240
     kw = dirichlet_two_tip_kw(nx, ny, steps, row, x0, a0)
-    tol = 4 * 2.0 ** -11 * math.sqrt(steps) if storage.startswith("f16s") else None
+    tol = 2e-3 if storage.startswith("f16s") else None  # 3x the largest measured (7.1e-4)
     compare_run(storage, kw, steps, [1, 60, steps], tol=tol)
     ref, gpu = pair(storage, **kw)
     ref.step(steps)
@@ -384,7 +390,8 @@ def test_steady_strip_against_the_oracle(v, storage, layout, rounding):
     ref.step(m["steps"])
     gpu.step(m["steps"])
     w_r, w_g = ref.fields()[0], gpu.fields()[0]
-    tol = {"f64": 1e-12, "f32": 1e-5, "f16s": 4 * 2.0 ** -11 * math.sqrt(m["steps"])}[storage]
+    # FP16: 3x the largest error measured over the four speeds (4.2e-4)
+    tol = {"f64": 1e-12, "f32": 1e-5, "f16s": 1.3e-3}[storage]
     record("w", relerr(w_g, w_r), storage=storage, layout=layout)
     assert relerr(w_g, w_r) <= tol
     tr, tg = ref.traces(), gpu.traces()
@@ -502,9 +509,7 @@ def test_inclined_crack_reduced_precision(storage):
     gpu = Solver(gpu)
     ref.step(steps)
     gpu.step(steps)
-    tol = TOL[st] if st in TOL else TOL["f16s"]
-    if st.startswith("f16s"):
-        tol = 4 * 2.0 ** -11 * math.sqrt(steps)
+    tol = TOL[st] if st in TOL else 5e-4  # FP16: 3x the measured 1.4e-4
     record("w", relerr(gpu.fields()[0], ref.fields()[0]), storage=storage)
     assert relerr(gpu.fields()[0], ref.fields()[0]) <= tol
     np.testing.assert_array_equal(gpu.traces()["tip"], ref.traces()["tip"])
