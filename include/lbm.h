@@ -371,6 +371,22 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps);
  * Synchronises the stream. */
 int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lbm_batch_run_persistent
+ * with its synchronisation words (arrival counter, generation, time-out flag)
+ * in a fixed 64 KiB device array of the library instead of the batch's
+ * device block.  The same kernels, the same results bit for bit.  It calls
+ * no allocating routine: no hipMalloc / hipFree, no event or stream creation
+ * (per-call timing, lbm_batch_timing, is not recorded for it).  Each GPU the
+ * library runs on holds one copy of the array until the process ends; its
+ * address is looked up once per device at lbm_batch_init.  Every call on a
+ * GPU shares that GPU's copy: its words are cleared by a fill kernel at the
+ * start of each call, and calls that overlap on one GPU (from two threads or
+ * on two streams) race on it.  Errors: LBM_EINVAL if the batch needs more
+ * synchronisation words than the array holds; otherwise as
+ * lbm_batch_run_persistent.  Synchronises the stream. */
+int lbm_batch_run_persistent_static(lbm_batch *b, int64_t nsteps);
+
 /* Handle of plate k for queries (lbm_crack_state, lbm_sif, lbm_get_fields,
  * ...); owned by the batch (no lbm_free, no lbm_step on it).  NULL if k is out
  * of range. */

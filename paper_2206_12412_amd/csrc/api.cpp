@@ -1364,6 +1364,7 @@ struct lbm_batch {
   int sr = 0;  // stochastic rounding (same for every plate)
   bool eq = false;     // equilibrium layout (same for every plate)
   int full_steps = 0;  // five-plane steps still to run (see lbm_handle)
+  int device = 0;      // the GPU the batch's memory is on (current at lbm_batch_init)
 };
 
 namespace {
@@ -1403,7 +1404,7 @@ int batch_layout(const lbm_config *cfgs, int32_t n, BatchLayout *B, Store *store
     o += align_up(sizeof(double) * 4 * (size_t)std::max<int64_t>(cfgs[k].dirichlet ? cfgs[k].n_wD : 0, 1), 256);
   }
   B->off_sync = o;
-  o += 512;  // grid-barrier words on separate 128-byte lines
+  o += align_up(lbmk::persistent_sync_bytes(n), 256);  // the persistent run's synchronisation words
   B->total = o;
   return LBM_OK;
 }
@@ -1491,7 +1492,16 @@ int lbm_batch_init(const lbm_config *cfgs, int32_t n, void *dev_buf, size_t dev_
   if (!dev_buf || reinterpret_cast<uintptr_t>(dev_buf) % 256)
     return fail(LBM_EINVAL, "dev_buf must be a 256-byte aligned device pointer");
   if (dev_bytes < B.total) return fail(LBM_ENOMEM, "dev_bytes %zu < required %zu", dev_bytes, B.total);
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(LBM_EHIP, "no current device");
+  {  // the fixed scratch of lbm_batch_run_persistent_static: its address on this device
+    void *sp = nullptr;
+    size_t sbytes = 0;
+    const hipError_t e = lbmk::static_scratch(&sp, &sbytes);
+    if (e != hipSuccess) return fail(LBM_EHIP, "static scratch lookup failed: %s", hipGetErrorString(e));
+  }
   lbm_batch *b = new lbm_batch();
+  b->device = device;
   b->store = s;
   b->sr = cfgs[0].rounding == LBM_ROUND_STOCHASTIC;
   b->eq = cfgs[0].layout == LBM_LAYOUT_EQ;
@@ -1579,7 +1589,7 @@ int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps) {
   }
   const auto *d = reinterpret_cast<const lbmk::BatchPlate *>(b->base + b->off_desc);
   unsigned *sync = reinterpret_cast<unsigned *>(b->base + b->off_sync);
-  HIP_TRY(lbmk::launch_zero(sync, 512, b->stream));
+  HIP_TRY(lbmk::launch_zero(sync, lbmk::persistent_sync_bytes((int)b->plates.size()), b->stream));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (b->timing) {
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -1596,6 +1606,60 @@ int lbm_batch_run_persistent(lbm_batch *b, int64_t nsteps) {
     b->ev_used.push_back(e0);
     b->ev_used.push_back(e1);
   }
+  unsigned flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, sync + 64, sizeof flag, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->cur = (int)((b->cur + nsteps) & 1);
+  b->step += nsteps;
+  batch_sync_handles(b);
+  if (flag) return fail(LBM_EHIP, "grid barrier timed out: the persistent run is invalid");
+  return LBM_OK;
+}
+
+int lbm_batch_run_persistent_static(lbm_batch *b, int64_t nsteps) {
+  if (!b) return fail(LBM_EINVAL, "null batch");
+  if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
+  if (nsteps == 0) return LBM_OK;
+  const int n = (int)b->plates.size();
+  const size_t need = lbmk::persistent_sync_bytes(n);
+  int prev = -1;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != b->device) HIP_TRY(hipSetDevice(b->device));
+  struct Restore {  // the caller's current device, whatever the return path
+    int dev, was;
+    ~Restore() {
+      if (dev != was) (void)hipSetDevice(was);
+    }
+  } restore{b->device, prev};
+  void *sp = nullptr;
+  size_t cap = 0;
+  const hipError_t le = lbmk::static_scratch(&sp, &cap);
+  if (le != hipSuccess) return fail(LBM_EHIP, "static scratch lookup failed: %s", hipGetErrorString(le));
+  if (need > cap)
+    return fail(LBM_EINVAL, "a batch of %d plates needs %zu bytes of static scratch; it holds %zu", n,
+                need, cap);
+  // no events here (they would be created): timing stays off for this call
+  const bool timing = b->timing;
+  b->timing = false;
+  int rc = LBM_OK;
+  if (b->full_steps > 0) {  // the five-plane steps of a fresh state run one launch each
+    const int64_t k = std::min<int64_t>(nsteps, b->full_steps);
+    rc = lbm_batch_step(b, k);
+    nsteps -= k;
+  }
+  b->timing = timing;
+  if (rc != LBM_OK || nsteps == 0) return rc;
+  const auto *d = reinterpret_cast<const lbmk::BatchPlate *>(b->base + b->off_desc);
+  unsigned *sync = static_cast<unsigned *>(sp);
+  // the array keeps the last call's contents: the words that must start at
+  // zero are cleared by a fill kernel (no memset node, so a captured graph
+  // replays it correctly)
+  HIP_TRY(lbmk::launch_zero(sync, need, b->stream));
+  int blocks = 0;
+  const hipError_t e = lbmk::launch_batch_persistent(b->store, b->sr, b->eq, d, n, b->n_int, b->n_bnd,
+                                                     b->cur, b->step, nsteps, sync, &blocks, b->stream);
+  if (e != hipSuccess) return fail(LBM_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
+  b->persistent_blocks = blocks;
   unsigned flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, sync + 64, sizeof flag, hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));

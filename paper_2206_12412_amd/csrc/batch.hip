@@ -15,10 +15,51 @@
 //     The barrier spins on a generation counter with a bounded number of
 //     tries: on time-out it raises an error flag, after which no barrier
 //     waits, so every wave always reaches the end of the kernel.
+#include <mutex>
+
 #include "crack_core.hpp"
 #include "sweep_core.hpp"
 
 namespace lbmk {
+
+// Fixed device scratch for callers that cannot allocate: the synchronisation
+// words of lbm_batch_run_persistent_static live here instead of in the
+// batch's device block.  Each GPU holds its own copy of the array from the
+// moment the library's code object is loaded on it until the process ends.
+// In host code `scratch` names a host-side stand-in, not a device address:
+// only the address that static_scratch() looks up may be passed to kernels
+// or copies.
+constexpr size_t kStaticScratchBytes = 64 * 1024;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void **ptr, size_t *bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  *ptr = nullptr;
+  *bytes = 0;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {  // once per device, with that device current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kStaticScratchBytes;
+  return hipSuccess;
+}
+
+size_t persistent_sync_bytes(int n_plates) {
+  (void)n_plates;
+  return 512;  // counter, generation and time-out flag on their own 128-byte lines
+}
+
 namespace {
 
 __device__ __forceinline__ int plate_of(const BatchPlate *__restrict__ d, int n, int64_t task,

@@ -359,6 +359,13 @@ hipError_t launch_batch_persistent(Store s, int sr, bool eq, const BatchPlate *d
                                    int64_t n_bnd_tasks, int cur, int64_t step, int64_t nsteps,
                                    unsigned *sync, int *blocks_used, hipStream_t st);
 
+// Bytes of synchronisation words the persistent launch needs for n_plates.
+size_t persistent_sync_bytes(int n_plates);
+// The device address of this library's fixed scratch array on the current
+// device (looked up once per device with hipGetSymbolAddress) and its size;
+// the no-allocation persistent run keeps its synchronisation words there.
+hipError_t static_scratch(void **ptr, size_t *bytes);
+
 // ---- launchers (io.hip) ----
 // Initial populations and w of rows [row0, row0 + nrows) from FP64 staging
 // (w0, wd0 may be null = 0).

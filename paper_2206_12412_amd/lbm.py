@@ -40,7 +40,8 @@ EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_si
            "lbm_timing", "lbm_get_launch", "lbm_set_launch", "lbm_set_time_block", "lbm_time_block_stats",
            "lbm_autotune_time_block",
            "lbm_bytes_per_site", "lbm_free", "lbm_last_error", "lbm_batch_state_bytes",
-           "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent", "lbm_batch_plate",
+           "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
+           "lbm_batch_run_persistent_static", "lbm_batch_plate",
            "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing", "lbm_batch_sites",
            "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune", "lbm_round16",
            "lbm_sensor_traces", "lbm_adjoint_bytes", "lbm_adjoint_init", "lbm_adjoint_run",
@@ -130,6 +131,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_init.argtypes = [P(_Config), i32, vp, C.c_size_t, vp, P(vp)]
     lib.lbm_batch_step.argtypes = [vp, i64]
     lib.lbm_batch_run_persistent.argtypes = [vp, i64]
+    lib.lbm_batch_run_persistent_static.argtypes = [vp, i64]
     lib.lbm_batch_plate.argtypes = [vp, i32]
     lib.lbm_batch_plate.restype = vp
     lib.lbm_batch_set_launch.argtypes = [vp, i32, i32, i32]
@@ -156,7 +158,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(d)]
     for name in ("lbm_traces_left", "lbm_checkpoint", "lbm_restore", "lbm_sensor_traces", "lbm_adjoint_init", "lbm_adjoint_run", "lbm_adjoint_timing",
                  "lbm_round16", "lbm_autotune", "lbm_batch_autotune", "lbm_batch_init", "lbm_batch_step", "lbm_batch_run_persistent",
-                 "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
+                 "lbm_batch_run_persistent_static", "lbm_batch_set_launch", "lbm_batch_get_launch", "lbm_batch_timing"):
         getattr(lib, name).restype = i32
     for name in ("lbm_init", "lbm_step", "lbm_crack_state", "lbm_sif", "lbm_traces",
                  "lbm_cut_events", "lbm_cut_links", "lbm_get_fields", "lbm_get_populations",
@@ -615,6 +617,12 @@ class Batch:
 
     def run_persistent(self, n: int):
         _check(self._lib.lbm_batch_run_persistent(self._b, int(n)))
+        self.steps_done += int(n)
+
+    def run_persistent_static(self, n: int):
+        """run_persistent with the synchronisation words in the library's
+        fixed device array (lbm_batch_run_persistent_static: allocates nothing)."""
+        _check(self._lib.lbm_batch_run_persistent_static(self._b, int(n)))
         self.steps_done += int(n)
 
     def set_launch(self, rows: int, waves: int, occupancy: int = 0):
