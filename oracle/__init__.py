@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 GROW_NONE, GROW_PRESCRIBED, GROW_SIF = 0, 1, 2
 EDGE_BOTTOM, EDGE_TOP, EDGE_LEFT, EDGE_RIGHT = 1, 2, 4, 8
 FLAG_GREW, FLAG_WALL, FLAG_K_UNDEF = 1, 2, 4
+BC_LINK, BC_MACRO = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -49,7 +50,7 @@ class _Cfg(C.Structure):
         ("trace_cap", C.c_int64), ("threads", C.c_int32),
         ("crack_row", C.c_int32), ("both_tips", C.c_int32), ("dirichlet", C.c_int32),
         ("wD_hist", C.POINTER(C.c_double)), ("n_wD", C.c_int64),
-        ("crack_dx", C.c_double), ("crack_dy", C.c_double),
+        ("crack_dx", C.c_double), ("crack_dy", C.c_double), ("bc_scheme", C.c_int32),
     ]
 
 
@@ -127,6 +128,7 @@ class OracleConfig:
     wD_hist: Optional[np.ndarray] = None   # [n][4] w* of (bottom, top, left, right) per step
     crack_dx: float = 1.0         # growth direction of the right tip (Alg. 1, d); (1, 0) = +x
     crack_dy: float = 0.0
+    bc_scheme: int = 0            # BC_LINK (per-link bounce-back) or BC_MACRO (Sec. 3.1)
     _keep: list = field(default_factory=list, repr=False)
 
 
@@ -139,7 +141,7 @@ class Oracle:
         c = _Cfg()
         for name in ("nx", "ny", "kappa", "omega", "mu", "rho", "crack_x0", "crack_tip", "growth",
                      "v_rel", "K_C", "r0", "v_max", "k_band", "face_traction", "trace_cap",
-                     "threads", "crack_row", "dirichlet", "crack_dx", "crack_dy"):
+                     "threads", "crack_row", "dirichlet", "crack_dx", "crack_dy", "bc_scheme"):
             setattr(c, name, getattr(cfg, name))
         c.periodic = int(cfg.periodic)
         c.has_crack = int(cfg.has_crack)
@@ -179,7 +181,9 @@ class Oracle:
     __del__ = close
 
     def step(self, n: int = 1):
-        self._lib.orc_step(self._h, int(n))
+        rc = self._lib.orc_step(self._h, int(n))
+        if rc != 0:
+            raise RuntimeError(f"oracle step failed (code {rc})")
 
     @property
     def shape(self):

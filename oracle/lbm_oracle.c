@@ -15,6 +15,9 @@
  *   2. particle velocity wdot = sum_alpha f^alpha          (eq. distrib-macro);
  *   3. Euler update w += dt * wdot                          (eq. integration);
  *   4. BGK collision towards f_eq(w, wdot)                  (eq. LBE, eq. f-eq);
+ *   4a. (macroscopic boundary scheme only) w at the boundary points from
+ *      the boundary conditions, S w_B = R; missing populations from eq.
+ *      (f-macro-bc); collision at those points (Sec. 3.1);
  *   5. crack step appended after the integration (Alg. 1): evaluate the
  *      criterion with K from eq. (sif), advance the tip, find the intersected
  *      links by the breadth-first CheckLinks search, sever them.
@@ -35,7 +38,13 @@
  *     anti-bounce-back, f_in^alpha = -f^opp + 2 f_eq^alpha(w*, 0): the ghost
  *     site then carries 2 w* - w (the leapfrog's antisymmetric ghost);
  *   - with two tips, K and the criterion of both are evaluated on the same
- *     field, then both advance, the right tip's cuts recorded first.
+ *     field, then both advance, the right tip's cuts recorded first;
+ *   - the macroscopic boundary scheme (ORC_BC_MACRO, Sec. 3.1): the two
+ *     interior points of a boundary point are the next two lattice points
+ *     along the inward normal of its missing link (the boundary half a
+ *     spacing beyond the point); a point with several missing links takes
+ *     the mean of their polynomials; it applies after the whole sweep, before
+ *     the crack step, so K reads the boundary values.
  */
 #include "lbm_oracle.h"
 
@@ -86,6 +95,10 @@ struct orc_sim {
   /* scratch for the breadth-first search */
   uint8_t *inq, *vis;
   int32_t *queue, *touched;
+  /* macroscopic boundary scheme: w before the step, and the weights of the
+   * quadratic polynomial for a prescribed w and for a traction */
+  double *wold;
+  double qw_dir[3], qw_trac[3];
 };
 
 static inline size_t IDX(const orc_sim *s, int i, int j) {
@@ -189,6 +202,51 @@ static double exit_length(const orc_sim *s, double x, double y, double ux, doubl
 
 /* ------------------------------------------------------------- creation -- */
 
+/* ------------------------------------------ macroscopic boundary scheme -- */
+
+/* Sec. 3.1: near a boundary point x_B the displacement is approximated by a
+ * quadratic polynomial p(s) = c0 + c1 s + c2 s^2 along the inward boundary
+ * normal, s the distance from the boundary.  With the lattice-aligned walls
+ * and crack of this solver the boundary lies half a spacing beyond x_B
+ * (s_B = 1/2), and the two interior points are the next lattice points along
+ * the normal, x_I at s = 3/2 and x_II at s = 5/2 (so the bilinear
+ * interpolation of the paper returns their lattice values).  The polynomial
+ * is fixed by p(0) = w* (prescribed w) or p'(0) = dw/ds (traction) and by
+ * p(s_I) = w(x_I), p(s_II) = w(x_II); then w(x_B) = p(s_B) = q[0] b + q[1]
+ * w(x_I) + q[2] w(x_II), b the boundary value.  The weights q solve
+ * M^T q = (1, s_B, s_B^2), M the 3 x 3 matrix of the three conditions acting
+ * on (c0, c1, c2): Gaussian elimination with partial pivoting. */
+static void quad_weights(int prescribed_w, double q[3]) {
+  const double sB = 0.5, sI = 1.5, sII = 2.5;
+  const double M[3][3] = {{prescribed_w ? 1.0 : 0.0, prescribed_w ? 0.0 : 1.0, 0.0},
+                          {1.0, sI, sI * sI},
+                          {1.0, sII, sII * sII}};
+  double A[3][4];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) A[r][c] = M[c][r]; /* the transpose */
+  }
+  A[0][3] = 1.0;
+  A[1][3] = sB;
+  A[2][3] = sB * sB;
+  for (int k = 0; k < 3; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < 3; ++r)
+      if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+    for (int c = 0; c < 4; ++c) {
+      double t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t;
+    }
+    for (int r = k + 1; r < 3; ++r) {
+      const double m = A[r][k] / A[k][k];
+      for (int c = k; c < 4; ++c) A[r][c] -= m * A[k][c];
+    }
+  }
+  for (int r = 2; r >= 0; --r) {
+    double acc = A[r][3];
+    for (int c = r + 1; c < 3; ++c) acc -= A[r][c] * q[c];
+    q[r] = acc / A[r][r];
+  }
+}
+
 orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
   int32_t e = 0;
   if (cfg->nx < 1 || cfg->ny < 1) e = -1;
@@ -214,6 +272,19 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
   else if (cfg->has_crack && !(cfg->r0 > 0)) e = -1;
   else if (cfg->has_crack && cfg->k_band < 1) e = -1;
   else if (cfg->n_hist < 0 || (cfg->n_hist > 0 && !cfg->tau_hist)) e = -1;
+  else if (cfg->bc_scheme != ORC_BC_LINK && cfg->bc_scheme != ORC_BC_MACRO) e = -1;
+  /* the macroscopic scheme: walls, a crack along +x, and two interior points
+   * along the normal of every boundary point on its own side of the crack */
+  else if (cfg->bc_scheme == ORC_BC_MACRO &&
+           (cfg->periodic || cfg->nx < 3 || cfg->ny < 3 ||
+            (cfg->has_crack && !(cfg->crack_dy == 0.0 && cfg->crack_dx >= 0.0)))) e = -1;
+  else if (cfg->bc_scheme == ORC_BC_MACRO && cfg->has_crack) {
+    /* three rows on either side of the crack line: the interior points of a
+     * crack face are then no edge points (and no edge point reaches back to
+     * a face), so S couples no point to itself */
+    const int jc = cfg->crack_row >= 0 ? cfg->crack_row : cfg->ny / 2 - 1;
+    if (jc < 3 || jc + 4 > cfg->ny - 1) e = -1;
+  }
   if (e) {
     if (err) *err = e;
     return NULL;
@@ -280,6 +351,11 @@ orc_sim *orc_create(const orc_config *cfg, int32_t *err) {
   s->vis = (uint8_t *)calloc(n, 1);
   s->queue = (int32_t *)malloc(sizeof(int32_t) * n);
   s->touched = (int32_t *)malloc(sizeof(int32_t) * n);
+  if (cfg->bc_scheme == ORC_BC_MACRO) {
+    s->wold = (double *)malloc(sizeof(double) * n);
+    quad_weights(1, s->qw_dir);
+    quad_weights(0, s->qw_trac);
+  }
 
   /* Initial state: at rest or the given fields, populations in equilibrium. */
   for (int j = 0; j < cfg->ny; ++j)
@@ -368,6 +444,7 @@ void orc_free(orc_sim *s) {
     free(s->tips[t].trK); free(s->tips[t].trA); free(s->tips[t].trV); free(s->tips[t].trF);
   }
   free(s->evs); free(s->evi); free(s->evj); free(s->evo);
+  free(s->wold);
   free(s);
 }
 
@@ -463,6 +540,150 @@ static void lbm_sweep(orc_sim *s) {
     }
   }
   double *t = s->f; s->f = s->fn; s->fn = t;
+}
+
+/* Sec. 3.1, after the streaming, moment and integration of every site:
+ * boundary points (sites with a severed link or a link leaving the plate)
+ * take w from the boundary conditions instead.  For each missing link of
+ * x_B, whose outward normal is that link's direction, the polynomial through
+ * the boundary condition on it and the interior points x_B - c, x_B - 2c
+ * gives one equation; a point with several missing links (a corner) takes
+ * the mean of them.  Values at interior points are this step's, and where
+ * an interior point is itself a boundary point its w is an unknown: the
+ * equations form S w_B = R.  S = I - N, N holding those couplings; the chain
+ * of couplings ends at points whose interior points are interior sites, so N
+ * is nilpotent and the Jacobi iteration w_B <- R + N w_B reaches the exact
+ * solution after at most as many sweeps as the longest chain (it is run
+ * until it no longer changes, and fails if it has not stopped after n_B + 2
+ * sweeps).  Then the missing populations follow from eq. (f-macro-bc) with
+ * wdot_B = (w_B(t + dt) - w_B(t)) / dt, and x_B collides as any site. */
+static int macro_boundary(orc_sim *s) {
+  const int nx = s->cfg.nx, ny = s->cfg.ny;
+  const size_t n = (size_t)nx * ny;
+  const double tau = tau_at(s, s->step);
+  const double omega = s->cfg.omega;
+  int32_t *bidx = (int32_t *)malloc(sizeof(int32_t) * n);
+  int32_t nb = 0;
+  for (size_t x = 0; x < n; ++x) bidx[x] = -1;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      for (int b = 1; b < NPOP; ++b) {
+        link_t L;
+        if (!link_of(s, i, j, EX[b], EY[b], &L) || is_cut(s, &L)) {
+          bidx[IDX(s, i, j)] = nb++;
+          break;
+        }
+      }
+  /* rows of S w_B = R: R[b], and up to 8 couplings (column, weight) */
+  double *R = (double *)calloc((size_t)nb + 1, sizeof(double));
+  int32_t *ncol = (int32_t *)calloc((size_t)nb + 1, sizeof(int32_t));
+  int32_t *col = (int32_t *)malloc(sizeof(int32_t) * 8 * ((size_t)nb + 1));
+  double *wt = (double *)malloc(sizeof(double) * 8 * ((size_t)nb + 1));
+  size_t *site = (size_t *)malloc(sizeof(size_t) * ((size_t)nb + 1));
+  int rc = 0;
+  for (int j = 0; j < ny && !rc; ++j)
+    for (int i = 0; i < nx && !rc; ++i) {
+      const size_t x = IDX(s, i, j);
+      const int32_t r = bidx[x];
+      if (r < 0) continue;
+      site[r] = x;
+      int miss[NPOP], m = 0, outside[NPOP];
+      for (int b = 1; b < NPOP; ++b) {
+        link_t L;
+        const int in = link_of(s, i, j, EX[b], EY[b], &L);
+        if (!in || is_cut(s, &L)) { outside[m] = !in; miss[m++] = b; }
+      }
+      for (int k = 0; k < m; ++k) {
+        const int b = miss[k];
+        /* the interior points, inward along -c_b, on this side of the crack */
+        const int i1 = i - EX[b], j1 = j - EY[b], i2 = i - 2 * EX[b], j2 = j - 2 * EY[b];
+        link_t L1, L2;
+        if (!link_of(s, i, j, -EX[b], -EY[b], &L1) || is_cut(s, &L1) ||
+            !link_of(s, i1, j1, -EX[b], -EY[b], &L2) || is_cut(s, &L2)) {
+          rc = -7;
+          break;
+        }
+        const double *q;
+        double bval;
+        /* the population that would have arrived through the missing link
+         * is the one pulled along OPP[b]: its edge / traction rules */
+        const int edge = outside[k] ? edge_of(s, i, j, OPP[b]) : 0;
+        if (edge && (s->cfg.dirichlet & edge)) {
+          q = s->qw_dir;
+          bval = wall_w(s, edge, s->step);
+        } else {
+          /* traction t* = mu dw/dn on the outward normal c_b: the slope
+           * along the inward normal is -t* / mu */
+          q = s->qw_trac;
+          bval = -traction(s, j, OPP[b], outside[k], tau) / s->cfg.mu;
+        }
+        R[r] += q[0] * bval / m;
+        const size_t p[2] = {IDX(s, i1, j1), IDX(s, i2, j2)};
+        for (int e = 0; e < 2; ++e) {
+          const double c = q[1 + e] / m;
+          if (bidx[p[e]] >= 0) {
+            col[8 * r + ncol[r]] = bidx[p[e]];
+            wt[8 * r + ncol[r]] = c;
+            ncol[r]++;
+          } else {
+            R[r] += c * s->w[p[e]];
+          }
+        }
+      }
+    }
+  double *wb = (double *)malloc(sizeof(double) * ((size_t)nb + 1));
+  double *wn = (double *)malloc(sizeof(double) * ((size_t)nb + 1));
+  if (!rc) {
+    for (int32_t r = 0; r < nb; ++r) wb[r] = R[r];
+    int done = 0;
+    for (int it = 0; it < nb + 2 && !done; ++it) {
+      done = 1;
+      for (int32_t r = 0; r < nb; ++r) {
+        double acc = R[r];
+        for (int k = 0; k < ncol[r]; ++k) acc += wt[8 * r + k] * wb[col[8 * r + k]];
+        wn[r] = acc;
+        if (acc != wb[r]) done = 0;
+      }
+      double *t = wb; wb = wn; wn = t;
+    }
+    if (!done) rc = -7;
+  }
+  if (!rc) {
+    /* eq. (f-macro-bc) and the collision at every boundary point; the
+     * source populations of this step are in s->fn (swapped by the sweep) */
+    for (int32_t r = 0; r < nb; ++r) {
+      const size_t x = site[r];
+      const int i = (int)(x % (size_t)nx), j = (int)(x / (size_t)nx);
+      const double w_new = wb[r];
+      const double wd = (w_new - s->wold[x]) / s->dt;
+      double fin[NPOP];
+      int known[NPOP];
+      double sum_known = POP(s, s->fn, 0)[x];
+      int n_miss = 0;
+      fin[0] = sum_known;
+      known[0] = 1;
+      for (int a = 1; a < NPOP; ++a) {
+        link_t L;
+        const int in = link_of(s, i, j, -EX[a], -EY[a], &L);
+        known[a] = in && !is_cut(s, &L);
+        if (known[a]) {
+          fin[a] = POP(s, s->fn, a)[IDX(s, i - EX[a], j - EY[a])];
+          sum_known += fin[a];
+        } else {
+          n_miss++;
+        }
+      }
+      for (int a = 1; a < NPOP; ++a)
+        if (!known[a]) fin[a] = (wd - sum_known) / n_miss;
+      double feq[NPOP];
+      feq[0] = wd - s->A0 * w_new;
+      for (int a = 1; a < NPOP; ++a) feq[a] = s->Ak * w_new;
+      for (int a = 0; a < NPOP; ++a) POP(s, s->f, a)[x] = fin[a] - omega * (fin[a] - feq[a]);
+      s->w[x] = w_new;
+    }
+  }
+  free(bidx); free(R); free(ncol); free(col); free(wt); free(site); free(wb); free(wn);
+  return rc;
 }
 
 /* -------------------------------------------------------- crack handling -- */
@@ -739,7 +960,13 @@ static void crack_step(orc_sim *s) {
 
 int32_t orc_step(orc_sim *s, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
+    const int macro = s->cfg.bc_scheme == ORC_BC_MACRO;
+    if (macro) memcpy(s->wold, s->w, sizeof(double) * (size_t)s->cfg.nx * (size_t)s->cfg.ny);
     lbm_sweep(s);
+    if (macro) {
+      const int rc = macro_boundary(s);
+      if (rc) return rc;
+    }
     if (s->cfg.has_crack) crack_step(s);
     s->step++;
   }

@@ -36,6 +36,13 @@ extern "C" {
 enum { ORC_GROW_NONE = 0, ORC_GROW_PRESCRIBED = 1, ORC_GROW_SIF = 2 };
 enum { ORC_FLAG_GREW = 1, ORC_FLAG_WALL = 2, ORC_FLAG_K_UNDEF = 4 };
 enum { ORC_EDGE_BOTTOM = 1, ORC_EDGE_TOP = 2, ORC_EDGE_LEFT = 4, ORC_EDGE_RIGHT = 8 };
+/* ORC_BC_LINK: a population whose link is severed or leaves the plate is
+ * bounced back (anti-bounce-back at a prescribed-w edge), per link.
+ * ORC_BC_MACRO: the macroscopic scheme of Sec. 3.1: w at every boundary
+ * point from a quadratic polynomial along the boundary normal through the
+ * boundary condition and two interior points, assembled into S w_B = R and
+ * solved; the missing populations from eq. (f-macro-bc). */
+enum { ORC_BC_LINK = 0, ORC_BC_MACRO = 1 };
 
 typedef struct {
   int32_t nx, ny;
@@ -64,6 +71,7 @@ typedef struct {
   int64_t n_wD;            /* uses row min(n, n_wD - 1)                          */
   double crack_dx, crack_dy; /* growth direction of the right tip; (0, 0) or     */
                              /* (1, 0) = +x along the crack row                  */
+  int32_t bc_scheme;       /* ORC_BC_*: how boundary points are treated          */
 } orc_config;
 
 typedef struct orc_sim orc_sim;

@@ -537,6 +537,13 @@ def test_threads_do_not_change_results():
     dict(nx=8, ny=8, has_crack=True, crack_tip=2.5, growth=O.GROW_PRESCRIBED, v_rel=1.0),
     dict(nx=8, ny=8, has_crack=True, crack_tip=2.5, growth=O.GROW_SIF, K_C=0.0),
     dict(nx=8, ny=8, mu=-1.0),
+    # the macroscopic boundary scheme: walls only, a crack along +x with three
+    # rows on either side, a known scheme
+    dict(nx=8, ny=8, periodic=True, bc_scheme=O.BC_MACRO),
+    dict(nx=8, ny=6, has_crack=True, crack_tip=2.5, bc_scheme=O.BC_MACRO),
+    dict(nx=12, ny=12, has_crack=True, crack_row=5, crack_tip=2.5, crack_dx=0.6, crack_dy=0.8,
+         bc_scheme=O.BC_MACRO),
+    dict(nx=8, ny=8, bc_scheme=7),
 ])
 def test_invalid_configurations_are_rejected(bad):
     with pytest.raises(ValueError):
@@ -903,3 +910,220 @@ def test_inclined_growth_cuts_the_links_of_the_final_segment(dx, dy):
     np.testing.assert_array_equal(mv, fv | bv)
     np.testing.assert_array_equal(mh, fh | bh)
     assert mv.sum() + mh.sum() > 40
+
+
+# ------------------------------------ macroscopic boundary scheme (Sec. 3.1) --
+
+# Weights of the quadratic along the inward normal of a boundary point, written
+# out by hand (independently of the oracle, which solves the 3 x 3 system): the
+# boundary at s = 0, the point at s = 1/2, the interior lattice points at
+# s = 3/2 and 5/2.  Prescribed w (Lagrange basis on 0, 3/2, 5/2 at s = 1/2):
+#   (1/2 - 3/2)(1/2 - 5/2) / (3/2 * 5/2) = 8/15, (1/2)(1/2 - 5/2) / (3/2 (3/2 - 5/2)) = 2/3,
+#   (1/2)(1/2 - 3/2) / (5/2 (5/2 - 3/2)) = -1/5.
+# Prescribed slope q: p = a + q s + c s^2 through w_I, w_II gives
+#   c = (w_II - w_I - q) / 4, a = w_I - 3q/2 - 9c/4, p(1/2) = 3/2 w_I - 1/2 w_II - 1/2 q.
+MACRO_DIR = (8 / 15, 2 / 3, -1 / 5)     # (w*, w_I, w_II)
+MACRO_TRAC = (-1 / 2, 3 / 2, -1 / 2)    # (dw/ds at the wall, w_I, w_II)
+
+
+def leapfrog_macro(nx, ny, steps, cut_at, tau_hist, dirichlet=0, wD=None, wd0=None, w0=None,
+                   face=0.0, mu=1.0, rho=1.0, kappa=2.0, j0=None):
+    """The omega = 1 scheme as a leapfrog in (w, wdot) with the macroscopic
+    boundary scheme, written independently of the oracle: every site first
+    takes the five-point update from its intact links; then each boundary
+    point (a site with a severed link or a link leaving the plate) takes w
+    from the polynomial of every missing link (the mean over several) through
+    the boundary value and the updated w of the next two sites inward, and
+    wdot = (w_new - w_old) / dt.  Where one of those sites is itself a
+    boundary point, its new value is used: points are evaluated in
+    dependency order (substitution)."""
+    cs = math.sqrt(mu / rho)
+    dt = 1.0 / (kappa * cs)
+    k = cs * cs * dt  # c_s^2 dt / dh^2 of the five-point update
+    j0 = ny // 2 - 1 if j0 is None else j0
+    w = np.zeros((ny, nx)) if w0 is None else w0.copy()
+    v = np.zeros((ny, nx)) if wd0 is None else wd0.copy()
+    dirs = ((1, 0), (0, 1), (-1, 0), (0, -1))
+    for n in range(steps):
+        cut = cut_at(n)  # cut[j, i]: the vertical link between (i, j) and (i, j + 1) is severed
+        tau = tau_hist[min(n, len(tau_hist) - 1)]
+
+        def missing(i, j, dx, dy):
+            ii, jj = i + dx, j + dy
+            if not (0 <= ii < nx and 0 <= jj < ny):
+                return True
+            return dy != 0 and cut[min(j, jj), i]
+
+        lap = np.zeros((ny, nx))
+        for j in range(ny):
+            for i in range(nx):
+                for dx, dy in dirs:
+                    if not missing(i, j, dx, dy):
+                        lap[j, i] += w[j + dy, i + dx] - w[j, i]
+        vn = v + k * lap
+        wn = w + dt * vn
+        bnd = {}
+        for j in range(ny):
+            for i in range(nx):
+                m = [(dx, dy) for dx, dy in dirs if missing(i, j, dx, dy)]
+                if m:
+                    bnd[(j, i)] = m
+
+        def estimate(i, j, dx, dy, vals):
+            ii, jj = i + dx, j + dy
+            if not (0 <= ii < nx and 0 <= jj < ny):   # a wall
+                edge = {(0, -1): 1, (0, 1): 2, (-1, 0): 4, (1, 0): 8}[(dx, dy)]
+                if dirichlet & edge:
+                    g = wD[min(n, len(wD) - 1)][{1: 0, 2: 1, 4: 2, 8: 3}[edge]]
+                    c = MACRO_DIR
+                    return c[0] * g + c[1] * vals[j - dy, i - dx] + c[2] * vals[j - 2 * dy, i - 2 * dx]
+                t = tau if (dx, dy) == (0, 1) else (-tau if (dx, dy) == (0, -1) else 0.0)
+            else:                                      # a crack face
+                t = -face if dy == 1 else face
+            c = MACRO_TRAC
+            return c[0] * (-t / mu) + c[1] * vals[j - dy, i - dx] + c[2] * vals[j - 2 * dy, i - 2 * dx]
+
+        # substitution: a boundary point is evaluated once every boundary
+        # point among its interior points has its new value
+        out = wn.copy()
+        todo = dict(bnd)
+        while todo:
+            ready = [(j, i) for (j, i), m in todo.items()
+                     if all((j - q * dy, i - q * dx) not in todo for dx, dy in m for q in (1, 2))]
+            assert ready, "cyclic boundary couplings"
+            for (j, i) in ready:
+                m = todo.pop((j, i))
+                out[j, i] = sum(estimate(i, j, dx, dy, out) for dx, dy in m) / len(m)
+        for (j, i) in bnd:
+            vn[j, i] = (out[j, i] - w[j, i]) / dt
+        w, v = out, vn
+    return w, v
+
+
+def _cuts_growing(nx, ny, j0, x0, a0, v, steps, both=False):
+    R, L = two_tip_path(x0, a0, v, steps, nx)
+
+    def cut_at(n):
+        c = np.zeros((ny, nx), bool)
+        cols = np.arange(nx)
+        lo = L[n] if both else x0
+        c[j0, (cols >= lo) & (cols <= R[n])] = True
+        return c
+    return cut_at
+
+
+@pytest.mark.parametrize("case", ["edge-crack", "two-tips"])
+def test_macro_bc_equals_leapfrog_with_polynomial_boundaries(case):
+    """The oracle's macroscopic scheme (populations, S w_B = R by iteration,
+    eq. f-macro-bc, collision) equals the independent leapfrog above: a
+    growing edge crack with face tractions under a top-edge pulse (prescribed
+    w) and a bottom-edge traction; a growing centre crack with a held left
+    edge."""
+    rng = np.random.default_rng(5)
+    if case == "edge-crack":
+        nx, ny, j0, steps, v = 40, 22, 10, 160, 0.45
+        x0, a0, both = -0.5, 9.5, False
+        dmask = O.EDGE_TOP
+        face = 4e-4
+    else:
+        nx, ny, j0, steps, v = 36, 20, 12, 160, 0.4
+        x0, a0, both = 13.5, 20.5, True
+        dmask = O.EDGE_LEFT | O.EDGE_TOP
+        face = 0.0
+    n = np.arange(steps)
+    wD = np.zeros((steps, 4))
+    wD[:, 1] = 0.02 * np.sin(np.pi * n / 90.0) * (n < 90)
+    wD[:, 2] = 2e-3
+    wd0 = rng.normal(0, 1e-4, (ny, nx))
+    tau = np.array([1e-3])
+    s = make(nx=nx, ny=ny, has_crack=True, crack_row=j0, crack_x0=x0, crack_tip=a0,
+             both_tips=both, growth=O.GROW_PRESCRIBED, v_rel=v, tau_hist=tau, dirichlet=dmask,
+             wD_hist=wD, wdot0=wd0, face_traction=face, trace_cap=steps, bc_scheme=O.BC_MACRO)
+    s.step(steps)
+    w, wd = s.fields()
+    wf, vf = leapfrog_macro(nx, ny, steps, _cuts_growing(nx, ny, j0, x0, a0, v, steps, both),
+                            tau, dirichlet=dmask, wD=wD, wd0=wd0, face=face, j0=j0)
+    assert np.abs(wf).max() > 1e-3
+    assert np.abs(w - wf).max() < 1e-12 * np.abs(wf).max()
+    assert np.abs(wd - vf).max() < 1e-11 * np.abs(vf).max()
+    # the boundary scheme is not the per-link one
+    b = make(nx=nx, ny=ny, has_crack=True, crack_row=j0, crack_x0=x0, crack_tip=a0,
+             both_tips=both, growth=O.GROW_PRESCRIBED, v_rel=v, tau_hist=tau, dirichlet=dmask,
+             wD_hist=wD, wdot0=wd0, face_traction=face, trace_cap=steps)
+    b.step(steps)
+    assert np.abs(b.fields()[0] - w).max() > 1e-3 * np.abs(w).max()
+
+
+def test_macro_bc_linear_fields_are_static():
+    """The quadratic reproduces linear fields exactly, and the five-point
+    update leaves them unchanged: a linear profile between prescribed-w top
+    and bottom walls (free sides), and the uniform shear w = tau (y - y_m) / mu
+    under the top (+tau) and bottom (-tau) tractions, stay as they are."""
+    nx, ny, A = 14, 10, 0.3
+    J = np.arange(ny)[:, None] * np.ones((1, nx))
+    w0 = A * (J + 0.5) / ny
+    s = make(nx=nx, ny=ny, w0=w0, dirichlet=O.EDGE_BOTTOM | O.EDGE_TOP,
+             wD_hist=np.array([[0.0, A, 0.0, 0.0]]), bc_scheme=O.BC_MACRO)
+    s.step(300)
+    w, wd = s.fields()
+    assert np.abs(wd).max() < 1e-13 and np.abs(w - w0).max() < 1e-13
+    for mu, tau in ((1.0, 1e-3), (2.5, -3e-3)):
+        w0 = tau * (J - (ny - 1) / 2) / mu
+        s = make(nx=nx, ny=ny, w0=w0, mu=mu, tau_hist=np.array([tau]), bc_scheme=O.BC_MACRO)
+        s.step(300)
+        w, wd = s.fields()
+        assert np.abs(w - w0).max() < 1e-12 * np.abs(w0).max()
+
+
+def test_macro_bc_standing_wave_converges_at_second_order():
+    """The fundamental mode between two walls held at w = 0 (y = -1/2 and
+    ny - 1/2), free sides: w = sin(pi (y + 1/2) / ny) cos(omega t) with
+    omega = c_s pi / ny.  The half period between two zero crossings of the
+    middle row converges to the continuum one at second order in the spacing
+    (a wall misplaced by half a spacing would put the error near 1.6e-2 at
+    ny = 32, and make it first order)."""
+    errs = []
+    for ny in (16, 32, 64):
+        nx = 5
+        J = np.arange(ny)[:, None] * np.ones((1, nx))
+        w0 = np.sin(np.pi * (J + 0.5) / ny)
+        s = make(nx=nx, ny=ny, w0=w0, dirichlet=O.EDGE_BOTTOM | O.EDGE_TOP,
+                 wD_hist=np.zeros((1, 4)), bc_scheme=O.BC_MACRO)
+        dt = 0.5
+        prev, n, cross = w0[ny // 2, 2], 0, []
+        while len(cross) < 2:
+            s.step(1)
+            n += 1
+            cur = s.fields()[0][ny // 2, 2]
+            if (cur <= 0) != (prev <= 0):
+                cross.append((n - 1 + prev / (prev - cur)) * dt)
+            prev = cur
+        omega = math.pi / (cross[1] - cross[0])
+        errs.append(abs(omega / (math.pi / ny) - 1))
+    assert errs[1] < 1e-3, errs
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+@pytest.mark.parametrize("v", [0.2, 0.4, 0.6, 0.8])
+def test_macro_bc_steady_strip_is_close_to_the_paper(v):
+    """The strip of Sec. 5.1 with the paper's own (macroscopic) boundary
+    scheme: the median of the 300 sampled K lies within 3.5 % of eq.
+    (sif-mandal) at every speed (the paper's table: +0.8 % .. 0.0 %), much
+    closer than with per-link bounce-back (-10.4 % at v = 0.2); K_theo lies
+    inside the sample's 25 .. 75 % band at v = 0.2 .. 0.6 (at v = 0.8 the
+    band lies 0.7 % above it)."""
+    import synth
+    m = synth.mandal_strip(v)
+    K = {}
+    for scheme in (O.BC_LINK, O.BC_MACRO):
+        s = O.Oracle(O.OracleConfig(bc_scheme=scheme, **m["config"]))
+        s.step(m["steps"])
+        K[scheme] = s.traces()["K"][m["sample_steps"]]
+        s.close()
+    q = np.percentile(K[O.BC_MACRO], [25, 50, 75])
+    rel = q[1] / m["K_theo"] - 1.0
+    rel_link = np.median(K[O.BC_LINK]) / m["K_theo"] - 1.0
+    assert abs(rel) <= 0.035, rel
+    assert abs(rel) < abs(rel_link)
+    if v <= 0.6:
+        assert q[0] <= m["K_theo"] <= q[2]
