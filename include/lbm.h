@@ -108,6 +108,19 @@ enum lbm_edge { LBM_EDGE_BOTTOM = 1, LBM_EDGE_TOP = 2, LBM_EDGE_LEFT = 4, LBM_ED
  * planes stay allocated and zero, so the population and checkpoint views are
  * the same for both layouts. */
 enum lbm_layout { LBM_LAYOUT_FULL = 0, LBM_LAYOUT_EQ = 1 };
+/* Treatment of boundary points (sites with a severed link or a link leaving
+ * the plate).  LINK: per link, bounce-back at the link midpoint (with the
+ * traction term) or, at a prescribed-w edge, anti-bounce-back.  MACRO: the
+ * macroscopic scheme of Sec. 3.1: w at a boundary point from a quadratic
+ * polynomial along the inward normal of each missing link, through the
+ * boundary condition on the wall or crack face half a spacing beyond the
+ * point (w* or the traction slope -t* / mu) and this step's w at the next two
+ * lattice points inward (the mean over several missing links); the missing
+ * populations then follow from eq. (f-macro-bc), so that they sum to
+ * (w_B(t + dt) - w_B(t)) / dt.  MACRO needs walls, no crack or a crack
+ * along +x with at least three rows on either side of the crack line, and
+ * one step per sweep; no batches, no adjoint. */
+enum lbm_bc_scheme { LBM_BC_LINK = 0, LBM_BC_MACRO = 1 };
 
 typedef struct lbm_config {
   int32_t nx, ny;          /* sites; ny even and >= 2 when there is a crack      */
@@ -151,6 +164,7 @@ typedef struct lbm_config {
                            /* S + (a - crack_x0) d/|d|), every vertical or        */
                            /* horizontal link it touches severed; k_band = 1,     */
                            /* walls only, no adjoint                             */
+  int32_t bc_scheme;       /* enum lbm_bc_scheme                                 */
   void *dev_buf;           /* device memory, >= lbm_state_bytes(cfg), 256-aligned */
   size_t dev_bytes;
   void *stream;            /* hipStream_t; NULL = the null stream                */

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmcrack.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["api.cpp", "sweep.hip", "sweep2.hip", "sweep_block_f64.hip", "sweep_block_f32.hip",
-           "sweep_block_f16.hip", "sweep_block_bf16.hip", "crack.hip", "batch.hip", "io.hip", "adjoint.hip"]
+           "sweep_block_f16.hip", "sweep_block_bf16.hip", "crack.hip", "batch.hip", "io.hip", "adjoint.hip", "macro_bc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -50,7 +50,7 @@ struct Layout {
   size_t off_trK = 0, off_trA = 0, off_trV = 0, off_trF = 0;
   size_t off_trKL = 0, off_trAL = 0, off_trVL = 0, off_trFL = 0;
   size_t off_evS = 0, off_evC = 0, off_evJ = 0, off_evO = 0, off_stage = 0;
-  size_t off_sens = 0, off_trS = 0, off_wmid = 0, off_spec = 0;
+  size_t off_sens = 0, off_trS = 0, off_wmid = 0, off_spec = 0, off_merr = 0;
   int64_t event_cap = 0;
   int stage_rows = 0;
   size_t total = 0;
@@ -129,6 +129,8 @@ Layout make_layout(const lbm_config &c, Store s) {
   L.stage_rows = (int)std::max<int64_t>(1, std::min<int64_t>(c.ny, (1 << 20) / std::max(1, c.nx)));
   L.off_stage = o;
   o += align_up((size_t)5 * L.stage_rows * c.nx * 8, 256);
+  L.off_merr = o;  // error flag of the macroscopic boundary scheme
+  o += 256;
   L.total = o;
   return L;
 }
@@ -241,6 +243,21 @@ int validate(const lbm_config *c, Store *s) {
     if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
       return fail(LBM_EINVAL, "sensor sites must be distinct");
   }
+  if (c->bc_scheme != LBM_BC_LINK && c->bc_scheme != LBM_BC_MACRO)
+    return fail(LBM_EINVAL, "unknown bc_scheme %d", c->bc_scheme);
+  if (c->bc_scheme == LBM_BC_MACRO) {
+    if (c->bc_mode == LBM_BC_PERIODIC) return fail(LBM_EINVAL, "the macroscopic scheme needs walls");
+    if (c->nx < 3 || c->ny < 3) return fail(LBM_EINVAL, "the macroscopic scheme needs nx, ny >= 3");
+    if (c->has_crack) {
+      if (!(c->crack_dy == 0.0 && c->crack_dx >= 0.0))
+        return fail(LBM_EINVAL, "the macroscopic scheme takes cracks along +x only");
+      // three rows on either side of the crack line: every boundary point's
+      // two interior points then resolve within two levels
+      const int j0 = c->crack_row >= 0 ? c->crack_row : c->ny / 2 - 1;
+      if (j0 < 3 || j0 + 4 > c->ny - 1)
+        return fail(LBM_EINVAL, "the macroscopic scheme needs three rows on either side of the crack line");
+    }
+  }
   if (c->rounding != LBM_ROUND_NEAREST && c->rounding != LBM_ROUND_STOCHASTIC)
     return fail(LBM_EINVAL, "unknown rounding %d", c->rounding);
   if (c->rounding == LBM_ROUND_STOCHASTIC && c->storage != LBM_F16S && c->storage != LBM_BF16S)
@@ -304,6 +321,7 @@ struct lbm_handle {
   std::vector<int32_t> sensors;  // host copy of the sensor sites
   std::vector<double> wD;        // host copy of the wall-displacement history [n][4]
 
+  bool macro() const { return cfg.bc_scheme == LBM_BC_MACRO; }
   bool crack_step_needed() const { return cfg.has_crack || cfg.n_sensors > 0; }
 
   void *fbuf(int b) const { return base + L.off_f[b]; }
@@ -519,6 +537,47 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
 int launch_crack_step(lbm_handle *h) {
   const lbmk::CrackArgs a = crack_args(h);
   HIP_TRY(lbmk::launch_crack(a, h->stream));
+  return LBM_OK;
+}
+
+// The macroscopic boundary scheme of step n = h->step on the buffers the
+// sweep just wrote (Sec. 3.1).
+int launch_macro(lbm_handle *h) {
+  lbmk::MacroArgs m{};
+  const int nxt = 1 - h->cur;
+  m.fout = h->fbuf(nxt);
+  m.win = h->wbuf(h->cur);
+  m.wout = h->wbuf(nxt);
+  m.mV = h->mV();
+  m.p = h->plate;
+  m.has_crack = h->cfg.has_crack;
+  m.dmask = h->cfg.dirichlet;
+  if (h->cfg.dirichlet) {
+    const size_t r = 4 * (size_t)std::min<int64_t>(h->step, h->cfg.n_wD - 1);
+    for (int k = 0; k < 4; ++k) m.wD[k] = h->wD[r + k];
+  }
+  const double tau = h->tau_at(h->step);
+  m.t_top = tau;
+  m.t_bot = -tau;
+  m.t_face = h->cfg.face_traction;
+  m.mu = h->cfg.mu;
+  m.dt = h->dt;
+  m.A0 = h->A0;
+  m.Ak = h->Ak;
+  m.rkey = lbmk::step_key(h->cfg.seed, h->step);
+  m.err = reinterpret_cast<int *>(h->base + h->L.off_merr);
+  HIP_TRY(lbmk::launch_macro_bc(h->store, h->cfg.rounding == LBM_ROUND_STOCHASTIC,
+                                h->eq && h->full_steps == 0, m, h->stream));
+  return LBM_OK;
+}
+
+// Reports (and clears) the macroscopic scheme's error flag; synchronises.
+int check_macro(lbm_handle *h) {
+  if (!h->macro()) return LBM_OK;
+  int err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, h->base + h->L.off_merr, sizeof err, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (err) return fail(LBM_EHIP, "a boundary point of the macroscopic scheme depends deeper than two levels");
   return LBM_OK;
 }
 
@@ -836,6 +895,7 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
         HIP_TRY(hipEventRecord(ev[0], h->stream));
       }
       int rc = ns >= 2 ? launch_block_any(h, ns) : launch_sweep_any(h);
+      if (rc == LBM_OK && h->macro()) rc = launch_macro(h);
       if (rc != LBM_OK) return rc;
       if (timed) HIP_TRY(hipEventRecord(ev[1], h->stream));
       bool spec = false;
@@ -914,6 +974,8 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
 
 int lbm_crack_state(lbm_handle *h, lbm_crack_info *out) {
   if (!h || !out) return fail(LBM_EINVAL, "null argument");
+  const int rc = check_macro(h);
+  if (rc != LBM_OK) return rc;
   lbmk::DevCrack c{};
   HIP_TRY(hipMemcpyAsync(&c, h->crack(), sizeof c, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1066,6 +1128,8 @@ static int export_rows(lbm_handle *h, double *w_out, double *wd_out, double *f_o
 int lbm_get_fields(lbm_handle *h, double *w_out, double *wdot_out) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (!w_out && !wdot_out) return LBM_OK;
+  const int rc = check_macro(h);
+  if (rc != LBM_OK) return rc;
   return export_rows(h, w_out, wdot_out, nullptr);
 }
 
@@ -1219,6 +1283,7 @@ int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves
     if (h->cfg.has_crack && !h->line.aligned)
       return fail(LBM_EINVAL, "the T-step sweep takes a crack along +x only");
     if (h->cfg.n_sensors > 0) return fail(LBM_EINVAL, "the T-step sweep records no sensors");
+    if (h->macro()) return fail(LBM_EINVAL, "the macroscopic boundary scheme runs one step per sweep");
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->tblock = steps;
@@ -1386,6 +1451,8 @@ int batch_layout(const lbm_config *cfgs, int32_t n, BatchLayout *B, Store *store
     Store s;
     int rc = validate(&cfgs[k], &s);
     if (rc != LBM_OK) return fail(rc, "plate %d: %s", k, g_err.c_str());
+    if (cfgs[k].bc_scheme != LBM_BC_LINK)
+      return fail(LBM_EINVAL, "plate %d: the batched kernels bounce back per link (bc_scheme LINK)", k);
     if (k == 0) *store = s;
     else if (s != *store) return fail(LBM_EINVAL, "plate %d: every plate of a batch needs the same storage", k);
     if (cfgs[k].rounding != cfgs[0].rounding)
@@ -1860,6 +1927,8 @@ int lbm_adjoint_init(lbm_handle *h, void *dev_buf, size_t dev_bytes, lbm_adjoint
   if (!dev_buf || reinterpret_cast<uintptr_t>(dev_buf) % 256)
     return fail(LBM_EINVAL, "dev_buf must be a 256-byte aligned device pointer");
   if (dev_bytes < A.total) return fail(LBM_ENOMEM, "dev_bytes %zu < required %zu", dev_bytes, A.total);
+  if (h->macro())
+    return fail(LBM_EINVAL, "the adjoint transposes the per-link boundary scheme only (bc_scheme LINK)");
   if (h->cfg.has_crack && !h->line.aligned)
     return fail(LBM_EINVAL, "the adjoint takes cracks along +x only (the cut steps are kept per column)");
   lbm_adjoint *a = new lbm_adjoint();

@@ -366,6 +366,27 @@ size_t persistent_sync_bytes(int n_plates);
 // the no-allocation persistent run keeps its synchronisation words there.
 hipError_t static_scratch(void **ptr, size_t *bytes);
 
+// ---- launchers (macro_bc.hip) ----
+// The macroscopic boundary scheme of Sec. 3.1 after a one-step sweep: w and
+// the rest population (all five populations for the unshifted storages) of
+// every boundary point from the boundary conditions (see macro_bc.hip).
+struct MacroArgs {
+  void *fout;           // plane 0 of the destination populations
+  const void *win;      // w before the step
+  void *wout;           // w after the step: the sweep's values, boundary points replaced
+  const uint32_t *mV;   // cut bits of the vertical links
+  Plate p;
+  int has_crack;        // the crack row j0 may hold severed links
+  int dmask;            // edges with a prescribed w (LBM_EDGE_* bits)
+  double wD[4];         // their wall values this step (bottom, top, left, right)
+  double t_top, t_bot;  // traction t* of the top / bottom edge this step
+  double t_face;        // traction t* of the crack face above the crack (-t_face below)
+  double mu, dt, A0, Ak;
+  uint32_t rkey;        // rounding key of the step (stochastic rounding of plane 0)
+  int *err;             // set to 1 if a boundary point depends deeper than two levels
+};
+hipError_t launch_macro_bc(Store s, int sr, bool eq, const MacroArgs &a, hipStream_t st);
+
 // ---- launchers (io.hip) ----
 // Initial populations and w of rows [row0, row0 + nrows) from FP64 staging
 // (w0, wd0 may be null = 0).

@@ -28,6 +28,8 @@ ROUNDING = {"nearest": 0, "stochastic": 1}
 # (the moving populations rebuilt from the equilibrium of the emitting site,
 # exact at omega = 1; shifted storages only)
 LAYOUT = {"full": 0, "eq": 1}
+# boundary points: "link" bounce-back per link, "macro" the scheme of Sec. 3.1
+BC_SCHEME = {"link": 0, "macro": 1}
 EDGE_BOTTOM, EDGE_TOP, EDGE_LEFT, EDGE_RIGHT = 1, 2, 4, 8
 FLAG_GREW, FLAG_WALL, FLAG_K_UNDEF = 1, 2, 4
 
@@ -69,7 +71,7 @@ class _Config(C.Structure):
         ("crack_row", C.c_int32), ("both_tips", C.c_int32), ("dirichlet", C.c_int32),
         ("wD_hist", C.POINTER(C.c_double)), ("n_wD", C.c_int64),
         ("layout", C.c_int32),
-        ("crack_dx", C.c_double), ("crack_dy", C.c_double),
+        ("crack_dx", C.c_double), ("crack_dy", C.c_double), ("bc_scheme", C.c_int32),
         ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t),
         ("stream", C.c_void_p),
     ]
@@ -212,6 +214,7 @@ class Config:
     layout: str = "full"                  # "full" (five populations) or "eq" (see LAYOUT)
     crack_dx: float = 1.0                 # growth direction of the right tip (Alg. 1, d);
     crack_dy: float = 0.0                 # (1, 0) = +x along crack_row
+    bc_scheme: str = "link"               # "link" (bounce-back per link) or "macro" (Sec. 3.1)
 
     def to_c(self, keep: list) -> _Config:
         c = _Config()
@@ -224,6 +227,7 @@ class Config:
         c.rounding = ROUNDING[self.rounding] if isinstance(self.rounding, str) else int(self.rounding)
         c.layout = LAYOUT[self.layout] if isinstance(self.layout, str) else int(self.layout)
         c.crack_dx, c.crack_dy = float(self.crack_dx), float(self.crack_dy)
+        c.bc_scheme = BC_SCHEME[self.bc_scheme] if isinstance(self.bc_scheme, str) else int(self.bc_scheme)
         c.crack_row = int(self.crack_row)
         c.both_tips = int(self.both_tips)
         c.dirichlet = int(self.dirichlet)

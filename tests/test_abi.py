@@ -106,3 +106,22 @@ def test_layout_validation():
     a = P.state_bytes(P.Config(nx=300, ny=70, storage="f16s"))
     b = P.state_bytes(P.Config(nx=300, ny=70, storage="f16s", layout="eq"))
     assert a == b
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=16, ny=8, periodic=True, bc_scheme="macro"),
+    dict(nx=16, ny=6, has_crack=True, crack_tip=3.5, bc_scheme="macro"),
+    dict(nx=16, ny=16, has_crack=True, crack_row=7, crack_tip=3.5, crack_dx=0.6, crack_dy=0.8,
+         bc_scheme="macro"),
+    dict(nx=16, ny=8, bc_scheme=5),
+])
+def test_macroscopic_scheme_refuses_what_it_cannot_take(kw):
+    rc, msg = init_rc(**kw)
+    assert rc == -1 and msg
+
+
+def test_batch_refuses_the_macroscopic_scheme():
+    keep = []
+    arr = (L._Config * 2)(P.Config(nx=16, ny=8).to_c(keep),
+                          P.Config(nx=16, ny=8, bc_scheme="macro").to_c(keep))
+    assert P.load_library().lbm_batch_state_bytes(arr, 2) == 0
