@@ -654,7 +654,7 @@ def main():
                     help="steps of the untimed K_III / field error leg (default: the workload's; "
                          "0 skips it)")
     ap.add_argument("--k-compare", default="f64,f32,f16s-sr,bf16s-sr,f32-eq-tb6,f16s-eq-tb6-sr,"
-                                           "bf16s-eq-tb6-sr",
+                                           "bf16s-eq-tb6-sr,bf16s-eq-tb8-sr",
                     help="storages of the K_III / field error leg; the first is the reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")

@@ -797,7 +797,7 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     return bail(fail(LBM_EHIP, "mask init failed"));
   if (cfg->has_crack && !h->line.aligned) {
     // the initial crack along another direction: every link the segment
-    // x0 .. a0 touches (Alg. 1, "as for the initial crack"), set on the host
+    // x0 .. a0 touches, severed like a grown segment's links (Sec. 4.1), set on the host
     const int rows = p.ny, mw = p.mw;
     std::vector<uint32_t> mv((size_t)rows * mw, 0u), mhv((size_t)rows * mw, 0u);
     lbmk::MaskRows mr{1, 0, 1, 0};

@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
 
 // Mask words of every row: all links intact except the vertical links of the
 // crack row at the columns lo..hi (the initial crack segment x0 .. a0 touches
-// exactly those, Alg. 1 "as for the initial crack").  With a crack the
+// exactly those; Sec. 4.1 treats the initial crack's links like those of a
+// grown segment).  With a crack the
 // mask-row range names the crack row from the start (growth cuts only there).
 __global__ void init_mask_kernel(uint32_t *mV, uint32_t *mH, MaskRows *mrows, Plate p, int lo,
                                  int hi, int has_crack) {

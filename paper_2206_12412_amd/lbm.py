@@ -99,6 +99,10 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: run paper_2206_12412_amd/build.py (or "
                            "__graft_entry__.build()) first; there is no CPU fallback")
+    # torch first: its HIP runtime is then the one the library binds to, so
+    # that both see the same devices, streams and memory (loading the library
+    # first would bind it to another copy of the runtime, without a context)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P, d, i32, i64, vp = C.POINTER, C.c_double, C.c_int32, C.c_int64, C.c_void_p
     lib.lbm_state_bytes.argtypes = [P(_Config)]
