@@ -311,6 +311,13 @@ struct lbm_handle {
   // rest, with its fork and join events (created with the first T-step
   // sweep, on the device current then; default priority)
   lbmk::SideStream side{nullptr, nullptr, nullptr};
+  // a T-step sweep's crack steps under a prescribed speed (or none) run on
+  // the side stream right after the sweep's boundary launch (the crack rows
+  // and the side buffer of the inner steps are all they read), beside the
+  // fast chunks of this sweep and the next, which read neither the crack
+  // rows nor the crack state; crack_pending says the side stream holds crack
+  // steps the caller's stream has not yet joined
+  bool crack_pending = false;
   int blk_rows[lbmk::kMaxTimeBlock + 1] = {};
   int blk_waves[lbmk::kMaxTimeBlock + 1] = {};
   int blk_occ[lbmk::kMaxTimeBlock + 1] = {};  // resident waves per SIMD, 0 = no cap
@@ -880,6 +887,14 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     if (sif_blocks) ns = std::min(ns, std::max(2, h->spec_cap));
     bool timed = false;
     for (int m = 0; m < ns; ++m) timed |= h->timing && (h->step + m) % h->timing_stride == 0;
+    // a one-step sweep, a speculative sweep and a timed sweep run their crack
+    // steps on the caller's stream: the crack steps still running on the side
+    // stream come first (the sweep's crack rows read their mask and state)
+    if (h->crack_pending && (ns < 2 || sif_blocks || timed)) {
+      HIP_TRY(hipEventRecord(h->side.join, h->side.side));
+      HIP_TRY(hipStreamWaitEvent(h->stream, h->side.join, 0));
+      h->crack_pending = false;
+    }
     // Under the K criterion the T-step sweep severs links as if each tip kept
     // its last speed; when a crack step before the last leaves a tip in
     // another column, the crack kernel puts back the state of step n and the
@@ -932,7 +947,14 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
             q.spec_mask = reinterpret_cast<uint32_t *>(h->base + h->L.off_spec +
                                                        align_up(sizeof(lbmk::SpecSlot), 256));
           }
-          HIP_TRY(lbmk::launch_crack_seq(q, h->stream));
+          if (!spec && !timed && h->side.side) {
+            // on the side stream right after the boundary launch, whose rows
+            // are all it reads: beside the rest of this sweep and the next
+            HIP_TRY(lbmk::launch_crack_seq(q, h->side.side));
+            h->crack_pending = true;
+          } else {
+            HIP_TRY(lbmk::launch_crack_seq(q, h->stream));
+          }
         } else {
           rc = launch_crack_step(h);
           if (rc != LBM_OK) return rc;
@@ -968,6 +990,12 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     h->step += ns;
     k += ns;
     if (h->full_steps > 0) h->full_steps--;
+  }
+  if (h->crack_pending) {
+    // work the caller enqueues after lbm_step sees every crack step
+    HIP_TRY(hipEventRecord(h->side.join, h->side.side));
+    HIP_TRY(hipStreamWaitEvent(h->stream, h->side.join, 0));
+    h->crack_pending = false;
   }
   return LBM_OK;
 }

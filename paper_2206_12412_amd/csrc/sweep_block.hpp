@@ -433,9 +433,11 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
     for (int c = (jc - R - T) / R - 1; c <= (jc + T) / R + 1; ++c) add(c);
   if (!ok) return hipErrorInvalidValue;
   // the boundary launch goes first, on the side stream, so that its few
-  // long waves run beside the fast launch instead of after it
+  // long waves run beside the fast launch instead of after it (always there
+  // when a side stream exists: the crack steps of the previous sweep may
+  // still run on it, and only the boundary launch reads what they write)
   const long etasks = (long)(n_strips - (s_hi - s_lo)) * n_chunks + (long)(s_hi - s_lo) * sc.n;
-  const bool fork = ss.side != nullptr && etasks > 0 && s_hi > s_lo;
+  const bool fork = ss.side != nullptr && etasks > 0;
   hipStream_t est = fork ? ss.side : st;
   if (fork) {
     hipError_t e = hipEventRecord(ss.fork, st);
