@@ -46,7 +46,7 @@ struct Layout {
   size_t plane = 0;             // elements between planes
   size_t off_f[2] = {0, 0};
   size_t off_w[2] = {0, 0};
-  size_t off_mV = 0, off_mH = 0, off_rf = 0, off_crack = 0;
+  size_t off_mV = 0, off_mH = 0, off_rf = 0, off_crack = 0, off_crack2 = 0, off_fargs = 0;
   size_t off_trK = 0, off_trA = 0, off_trV = 0, off_trF = 0;
   size_t off_trKL = 0, off_trAL = 0, off_trVL = 0, off_trFL = 0;
   size_t off_evS = 0, off_evC = 0, off_evJ = 0, off_evO = 0, off_stage = 0;
@@ -104,6 +104,7 @@ Layout make_layout(const lbm_config &c, Store s) {
   L.off_mH = o; o += mbytes;
   L.off_rf = o; o += 256;
   L.off_crack = o; o += 256;
+  L.off_crack2 = o; o += 256;  // second slot: a crack step folded into the next sweep
   const size_t tc = c.trace_cap > 0 ? (size_t)c.trace_cap : 1;
   L.off_trK = o; o += align_up(tc * 8, 256);
   L.off_trA = o; o += align_up(tc * 8, 256);
@@ -131,6 +132,11 @@ Layout make_layout(const lbm_config &c, Store s) {
   o += align_up((size_t)5 * L.stage_rows * c.nx * 8, 256);
   L.off_merr = o;  // error flag of the macroscopic boundary scheme
   o += 256;
+  // the arguments of a crack step folded into the next sweep, per (current
+  // buffer, state slot): device addresses of this handle, so after the part
+  // a checkpoint holds (off_mV .. off_stage)
+  L.off_fargs = o;
+  o += 4 * align_up(sizeof(lbmk::CrackArgs), 256);
   L.total = o;
   return L;
 }
@@ -288,6 +294,7 @@ struct lbm_handle {
   double t_sweep = 0, t_crack = 0;
   int64_t n_timed = 0;
   lbmk::DevCrack host_crack{};
+  lbmk::CrackArgs host_fargs[4]{};  // host side of the fused_args upload
   bool in_batch = false;  // stepped by a batch; lbm_step refuses it
   // equilibrium layout: the sweep touches plane 0 and w only.  The moving
   // planes of both buffers hold zeros in every state reached by a step; until
@@ -318,6 +325,12 @@ struct lbm_handle {
   // rows nor the crack state; crack_pending says the side stream holds crack
   // steps the caller's stream has not yet joined
   bool crack_pending = false;
+  // one-step sweeps run the crack step of the step before them (fold_crack):
+  // crack_deferred says the crack step of step `step - 1` has not run yet; the
+  // state before it is in slot cslot (0: off_crack, 1: off_crack2).  Between
+  // calls of lbm_step nothing is deferred and the state is in slot 0.
+  bool crack_deferred = false;
+  int cslot = 0;
   int blk_rows[lbmk::kMaxTimeBlock + 1] = {};
   int blk_waves[lbmk::kMaxTimeBlock + 1] = {};
   int blk_occ[lbmk::kMaxTimeBlock + 1] = {};  // resident waves per SIMD, 0 = no cap
@@ -337,6 +350,21 @@ struct lbm_handle {
   uint32_t *mH() const { return reinterpret_cast<uint32_t *>(base + L.off_mH); }
   lbmk::MaskRows *mrows() const { return reinterpret_cast<lbmk::MaskRows *>(base + L.off_rf); }
   lbmk::DevCrack *crack() const { return reinterpret_cast<lbmk::DevCrack *>(base + L.off_crack); }
+  // device copy of the arguments of the crack step a one-step sweep runs:
+  // w in buffer cur, state in slot cslot, going to the other slot
+  const lbmk::CrackArgs *fused_args(int cur_buf, int slot) const {
+    return reinterpret_cast<const lbmk::CrackArgs *>(
+        base + L.off_fargs + (size_t)(2 * cur_buf + slot) * align_up(sizeof(lbmk::CrackArgs), 256));
+  }
+  lbmk::DevCrack *crack_slot(int k) const {
+    return reinterpret_cast<lbmk::DevCrack *>(base + (k ? L.off_crack2 : L.off_crack));
+  }
+  // a one-step sweep can run the previous step's crack step itself: a crack
+  // along +x or none (sensors only), not under the macroscopic boundary scheme
+  // (its kernel runs between the sweep and the crack step)
+  bool fold_crack() const {
+    return crack_step_needed() && !macro() && (!cfg.has_crack || line.aligned);
+  }
   lbmk::SpecSlot *spec_slot() const { return reinterpret_cast<lbmk::SpecSlot *>(base + L.off_spec); }
   double *stage() const { return reinterpret_cast<double *>(base + L.off_stage); }
   double tau_at(int64_t n) const {
@@ -428,9 +456,9 @@ lbmk::SweepArgs<S, W, C> sweep_args(const lbm_handle *h, int64_t n) {
 }
 
 template <typename S, typename W, typename C>
-int launch_sweep_typed(lbm_handle *h) {
+int launch_sweep_typed(lbm_handle *h, const lbmk::CrackArgs *fc) {
   const lbmk::SweepArgs<S, W, C> a = sweep_args<S, W, C>(h, h->step);
-  HIP_TRY(lbmk::launch_sweep(h->store, h->eq && h->full_steps == 0, &a, h->stream));
+  HIP_TRY(lbmk::launch_sweep(h->store, h->eq && h->full_steps == 0, &a, h->stream, fc));
   return LBM_OK;
 }
 
@@ -482,14 +510,16 @@ int launch_block_any(lbm_handle *h, int T) {
   }
 }
 
-int launch_sweep_any(lbm_handle *h) {
+// fc: device copy of the arguments of the previous step's crack step, run
+// by this sweep (null: none)
+int launch_sweep_any(lbm_handle *h, const lbmk::CrackArgs *fc) {
   switch (h->store) {
-    case Store::F64: return launch_sweep_typed<double, double, double>(h);
-    case Store::F64S: return launch_sweep_typed<double, double, double>(h);
-    case Store::F32_PLAIN: return launch_sweep_typed<float, float, float>(h);
-    case Store::F32S: return launch_sweep_typed<float, float, float>(h);
-    case Store::F16S: return launch_sweep_typed<_Float16, float, float>(h);
-    case Store::BF16S: return launch_sweep_typed<__bf16, float, float>(h);
+    case Store::F64: return launch_sweep_typed<double, double, double>(h, fc);
+    case Store::F64S: return launch_sweep_typed<double, double, double>(h, fc);
+    case Store::F32_PLAIN: return launch_sweep_typed<float, float, float>(h, fc);
+    case Store::F32S: return launch_sweep_typed<float, float, float>(h, fc);
+    case Store::F16S: return launch_sweep_typed<_Float16, float, float>(h, fc);
+    case Store::BF16S: return launch_sweep_typed<__bf16, float, float>(h, fc);
   }
   return fail(LBM_EINVAL, "bad storage");
 }
@@ -544,6 +574,27 @@ lbmk::CrackArgs crack_args(const lbm_handle *h) {
 int launch_crack_step(lbm_handle *h) {
   const lbmk::CrackArgs a = crack_args(h);
   HIP_TRY(lbmk::launch_crack(a, h->stream));
+  return LBM_OK;
+}
+
+// The arguments of the crack step of step h->step - 1, deferred by the last
+// one-step sweep: the current w is the w after that step, the state before
+// it is in slot cslot.
+lbmk::CrackArgs deferred_crack_args(const lbm_handle *h) {
+  lbmk::CrackArgs a = crack_args(h);
+  a.w = h->wbuf(h->cur);
+  a.st = h->crack_slot(h->cslot);
+  return a;
+}
+
+// The deferred crack step (if any) on its own, its state going to slot 0.
+int flush_deferred_crack(lbm_handle *h) {
+  if (!h->crack_deferred) return LBM_OK;
+  lbmk::CrackArgs a = deferred_crack_args(h);
+  a.st_out = h->cslot ? h->crack_slot(0) : nullptr;
+  HIP_TRY(lbmk::launch_crack(a, h->stream));
+  h->crack_deferred = false;
+  h->cslot = 0;
   return LBM_OK;
 }
 
@@ -709,9 +760,10 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   // with at most 2 resident waves per SIMD for 8- and 4-byte storage, 4-wave
   // workgroups with at most 4 for 16-bit storage.  Equilibrium layout (fewer
   // loads per row, so more rows and waves in flight pay): FP64 4 rows per
-  // wave, 1-wave groups, at most 2 per SIMD; FP32 1 row, 4-wave groups, no
-  // cap; 16-bit 2 rows, 8-wave groups, no cap.  lbm_autotune searches the same
-  // grid for other plates.
+  // wave, 1-wave groups, at most 2 per SIMD; FP32 1 row, 8-wave groups, no
+  // cap (with the crack step run by the sweep; 4-wave groups are 1 % faster
+  // without it); 16-bit 2 rows, 8-wave groups, no cap.  lbm_autotune searches
+  // the same grid for other plates.
   {
     const bool half = (s == Store::F16S || s == Store::BF16S);
     if (!h->eq) {
@@ -724,7 +776,7 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
       h->occ = 2;
     } else {
       h->rows = half ? 2 : 1;
-      h->waves = half ? 8 : 4;
+      h->waves = 8;
       h->occ = 0;
     }
     // T-step sweep (lbm_set_time_block): rows per wave, waves per group and
@@ -864,6 +916,23 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
   }
   if (hipMemcpyAsync(h->crack(), &c0, sizeof c0, hipMemcpyHostToDevice, st) != hipSuccess)
     return bail(fail(LBM_EHIP, "crack state upload failed"));
+  if (h->fold_crack()) {
+    // the four argument sets of a crack step run by a one-step sweep
+    const int cur0 = h->cur, slot0 = h->cslot;
+    for (int b = 0; b < 2; ++b)
+      for (int k = 0; k < 2; ++k) {
+        h->cur = b;
+        h->cslot = k;
+        lbmk::CrackArgs &a = h->host_fargs[2 * b + k];
+        a = deferred_crack_args(h);
+        a.st_out = h->crack_slot(1 - k);
+        if (hipMemcpyAsync(const_cast<lbmk::CrackArgs *>(h->fused_args(b, k)), &a, sizeof a,
+                           hipMemcpyHostToDevice, st) != hipSuccess)
+          return bail(fail(LBM_EHIP, "crack argument upload failed"));
+      }
+    h->cur = cur0;
+    h->cslot = slot0;
+  }
   if (!h->sensors.empty() &&
       hipMemcpyAsync(h->base + L.off_sens, h->sensors.data(), h->sensors.size() * 4,
                      hipMemcpyHostToDevice, st) != hipSuccess)
@@ -895,6 +964,14 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
       HIP_TRY(hipStreamWaitEvent(h->stream, h->side.join, 0));
       h->crack_pending = false;
     }
+    // A one-step sweep runs the crack step of the step before it (which then
+    // leaves its own to the next sweep, or to the launch at the end); other
+    // sweeps find the crack steps done.
+    const bool fold = ns < 2 && h->fold_crack();
+    if (!fold) {
+      const int rc = flush_deferred_crack(h);
+      if (rc != LBM_OK) return rc;
+    }
     // Under the K criterion the T-step sweep severs links as if each tip kept
     // its last speed; when a crack step before the last leaves a tip in
     // another column, the crack kernel puts back the state of step n and the
@@ -909,7 +986,18 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
         }
         HIP_TRY(hipEventRecord(ev[0], h->stream));
       }
-      int rc = ns >= 2 ? launch_block_any(h, ns) : launch_sweep_any(h);
+      int rc = LBM_OK;
+      if (ns >= 2) {
+        rc = launch_block_any(h, ns);
+      } else if (h->crack_deferred) {
+        rc = launch_sweep_any(h, h->fused_args(h->cur, h->cslot));
+        if (rc == LBM_OK) {
+          h->cslot = 1 - h->cslot;
+          h->crack_deferred = false;
+        }
+      } else {
+        rc = launch_sweep_any(h, nullptr);
+      }
       if (rc == LBM_OK && h->macro()) rc = launch_macro(h);
       if (rc != LBM_OK) return rc;
       if (timed) HIP_TRY(hipEventRecord(ev[1], h->stream));
@@ -955,6 +1043,8 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
           } else {
             HIP_TRY(lbmk::launch_crack_seq(q, h->stream));
           }
+        } else if (fold) {
+          h->crack_deferred = true;
         } else {
           rc = launch_crack_step(h);
           if (rc != LBM_OK) return rc;
@@ -990,6 +1080,10 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     h->step += ns;
     k += ns;
     if (h->full_steps > 0) h->full_steps--;
+  }
+  {
+    const int rc = flush_deferred_crack(h);
+    if (rc != LBM_OK) return rc;
   }
   if (h->crack_pending) {
     // work the caller enqueues after lbm_step sees every crack step

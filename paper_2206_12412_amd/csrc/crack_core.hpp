@@ -116,13 +116,17 @@ __device__ __forceinline__ double tip_K_line(const CrackArgs &a, int dir, double
   return delta * (q.mu / 4.0) * sqrt(2.0 * kPi / r);
 }
 
+// ANY_LINE false: the crack grows along +x (code for other lines left out).
+template <bool ANY_LINE = true>
 __device__ __forceinline__ double tip_K(const CrackArgs &a, int dir, double tip, double vK,
                                        double other, int lane, double *r_out, int *iK_out,
                                        bool *defined_out) {
 #pragma clang fp contract(off)
   const Plate p = a.p;
   const CrackParams q = a.c;
-  if (!q.aligned) return tip_K_line(a, dir, tip, vK, other, r_out, iK_out, defined_out);
+  if constexpr (ANY_LINE) {
+    if (!q.aligned) return tip_K_line(a, dir, tip, vK, other, r_out, iK_out, defined_out);
+  }
   const int band = q.band;
   const double rmin = q.r0 / (1.0 - vK);
   double iKf;
@@ -260,15 +264,102 @@ __device__ __forceinline__ bool cut_segment(const CrackArgs &a, DevCrack &c, Mas
   return any;
 }
 
+// The decision of one crack step (Alg. 1: K at each tip, EvaluateCriterion,
+// the tip advance with the wall clamp) from the crack state c before it, by
+// all lanes of a wavefront (the band fit reduces over the lanes).  WITH_K
+// false: only the new tip positions, for a prescribed speed, where they do
+// not depend on K.
+struct CrackDecision {
+  double KR, KL, rR, rL;
+  int iKR, iKL;
+  bool growR, growL;
+  double vR, vL;
+  double aR, aL;       // the tips after the step
+  int flagsR, flagsL;  // the step's flags
+};
+
+template <bool WITH_K, bool ANY_LINE = true>
+__device__ __forceinline__ CrackDecision crack_decide(const CrackArgs &a, const DevCrack &c,
+                                                      int lane) {
+#pragma clang fp contract(off)
+  const CrackParams q = a.c;
+  CrackDecision d;
+  d.KR = d.KL = d.rR = d.rL = __builtin_nan("");
+  d.iKR = d.iKL = -1;
+  bool defR = true, defL = true;
+  if constexpr (WITH_K) {
+    d.KR = tip_K<ANY_LINE>(a, 1, c.tip, (q.growth == kGrowPrescribed) ? q.v_rel : c.v, c.tipL, lane, &d.rR,
+                 &d.iKR, &defR);
+    if (q.both)
+      d.KL = tip_K<ANY_LINE>(a, -1, c.tipL, (q.growth == kGrowPrescribed) ? q.v_rel : c.vL, c.tip, lane,
+                   &d.rL, &d.iKL, &defL);
+  }
+  d.flagsR = c.flags & kFlagWall;
+  d.flagsL = c.flagsL & kFlagWall;
+  if (!defR) d.flagsR |= kFlagKUndef;
+  if (q.both && !defL) d.flagsL |= kFlagKUndef;
+  d.vR = d.vL = 0.0;
+  d.growR = tip_criterion(q, c.flags & kFlagWall, d.KR, &d.vR);
+  d.growL = q.both && tip_criterion(q, c.flagsL & kFlagWall, d.KL, &d.vL);
+  d.aR = c.tip;
+  d.aL = c.tipL;
+  if (d.growR) {
+    double a_new = c.tip + (d.vR * q.cs) * q.dt;
+    if (a_new >= q.a_hi) {
+      a_new = q.a_hi;
+      d.flagsR |= kFlagWall;
+    }
+    d.aR = a_new;
+    d.flagsR |= kFlagGrew;
+  }
+  if (d.growL) {
+    double a_new = c.tipL - (d.vL * q.cs) * q.dt;
+    if (a_new <= q.a_lo) {
+      a_new = q.a_lo;
+      d.flagsL |= kFlagWall;
+    }
+    d.aL = a_new;
+    d.flagsL |= kFlagGrew;
+  }
+  return d;
+}
+
+// The columns of the crack row (a crack along +x) whose vertical links the
+// crack step from state c severs (those not severed yet among them are new):
+// the right tip's [*lo_r, *hi_r] and the left tip's [*lo_l, *hi_l] (lo > hi:
+// none), by all lanes of a wavefront.  The sweep of the next step uses this
+// to run that crack step's cuts itself (see crack_step_wave).
+__device__ __forceinline__ void crack_cut_columns(const CrackArgs &a, const DevCrack &c, int lane,
+                                                  int *lo_r, int *hi_r, int *lo_l, int *hi_l) {
+  const CrackDecision d = a.c.growth == kGrowSif ? crack_decide<true, false>(a, c, lane)
+                                                 : crack_decide<false, false>(a, c, lane);
+  *lo_r = 1;
+  *hi_r = 0;
+  *lo_l = 1;
+  *hi_l = 0;
+  if (d.growR) {
+    *lo_r = (int)floor(c.tip) + 1;
+    *hi_r = (int)floor(d.aR);
+  }
+  if (d.growL) {
+    *lo_l = (int)ceil(d.aL);
+    *hi_l = (int)ceil(c.tipL) - 1;
+  }
+}
+
 // The crack step of one plate, executed by one wavefront (lanes 0..63): K and
 // the criterion of each growing tip on the same field, then the tips advance
-// (the right tip's cuts are recorded first).
+// (the right tip's cuts are recorded first).  It reads the crack state from
+// a.st and writes the state after the step to a.st_out (a.st if null).
+// ANY_LINE false: only for a crack along +x (fewer registers).
+template <bool ANY_LINE = true>
 __device__ __forceinline__ void crack_step_wave(const CrackArgs &a) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
   const Plate p = a.p;
   const CrackParams q = a.c;
   DevCrack c = *a.st;
+  DevCrack *out = a.st_out ? a.st_out : a.st;
   const int64_t n = c.step;
 
   // --- sensor traces: w after this step's sweep ---
@@ -277,98 +368,72 @@ __device__ __forceinline__ void crack_step_wave(const CrackArgs &a) {
       a.trS[n * a.n_sens + s] = w_at(a, a.sens[2 * s], a.sens[2 * s + 1]);
   }
   if (!q.crack) {
-    if (lane == 0) a.st->step = n + 1;
+    if (lane == 0) {
+      c.step = n + 1;
+      *out = c;
+    }
     return;
   }
 
-  // --- K at the tips (eq. sif) ---
-  double rR, rL = __builtin_nan("");
-  int iKR, iKL = -1;
-  bool defR, defL = true;
-  const double KR = tip_K(a, 1, c.tip, (q.growth == kGrowPrescribed) ? q.v_rel : c.v, c.tipL,
-                          lane, &rR, &iKR, &defR);
-  double KL = __builtin_nan("");
-  if (q.both)
-    KL = tip_K(a, -1, c.tipL, (q.growth == kGrowPrescribed) ? q.v_rel : c.vL, c.tip, lane, &rL,
-               &iKL, &defL);
+  // --- K at the tips (eq. sif), EvaluateCriterion, tip advance ---
+  const CrackDecision d = crack_decide<true, ANY_LINE>(a, c, lane);
+  const bool aligned = !ANY_LINE || q.aligned;
   if (lane != 0) return;
 
-  // --- EvaluateCriterion ---
-  int flagsR = c.flags & kFlagWall, flagsL = c.flagsL & kFlagWall;
-  if (!defR) flagsR |= kFlagKUndef;
-  if (q.both && !defL) flagsL |= kFlagKUndef;
-  double vR = 0.0, vL = 0.0;
-  const bool growR = tip_criterion(q, c.flags & kFlagWall, KR, &vR);
-  const bool growL = q.both && tip_criterion(q, c.flagsL & kFlagWall, KL, &vL);
-
-  // --- tip advance, CheckLinks, ProcessPoints ---
+  // --- CheckLinks, ProcessPoints ---
   bool any = false;
   MaskRows mr = *a.mrows;
-  if (growR) {
-    const double a_prev = c.tip;
-    double a_new = a_prev + (vR * q.cs) * q.dt;
-    if (a_new >= q.a_hi) {
-      a_new = q.a_hi;
-      flagsR |= kFlagWall;
-    }
-    if (q.aligned) {
+  if (d.growR) {
+    if (aligned) {
       // the new segment (a_prev, a_new] touches the columns in that interval
-      any |= cut_columns(a, c, (int)floor(a_prev) + 1, (int)floor(a_new), n);
-    } else {
-      any |= cut_segment(a, c, mr, a_prev, a_new, n);
+      any |= cut_columns(a, c, (int)floor(c.tip) + 1, (int)floor(d.aR), n);
+    } else if constexpr (ANY_LINE) {
+      any |= cut_segment(a, c, mr, c.tip, d.aR, n);
     }
-    c.tip = a_new;
-    flagsR |= kFlagGrew;
+    c.tip = d.aR;
   }
-  if (growL) {
-    const double a_prev = c.tipL;
-    double a_new = a_prev - (vL * q.cs) * q.dt;
-    if (a_new <= q.a_lo) {
-      a_new = q.a_lo;
-      flagsL |= kFlagWall;
-    }
-    if (q.aligned) {
+  if (d.growL) {
+    if (aligned) {
       // [a_new, a_prev) holds the newly touched columns
-      any |= cut_columns(a, c, (int)ceil(a_new), (int)ceil(a_prev) - 1, n);
-    } else {
-      any |= cut_segment(a, c, mr, a_new, a_prev, n);
+      any |= cut_columns(a, c, (int)ceil(d.aL), (int)ceil(c.tipL) - 1, n);
+    } else if constexpr (ANY_LINE) {
+      any |= cut_segment(a, c, mr, d.aL, c.tipL, n);
     }
-    c.tipL = a_new;
-    flagsL |= kFlagGrew;
+    c.tipL = d.aL;
   }
   if (any) {
-    if (q.aligned) {
+    if (aligned) {
       if (p.j0 < mr.vlo || mr.vlo > mr.vhi) mr.vlo = p.j0;
       if (p.j0 > mr.vhi) mr.vhi = p.j0;
     }
     *a.mrows = mr;
   }
-  c.v = vR;
-  c.K = KR;
-  c.r = rR;
-  c.col_K = iKR;
-  c.flags = flagsR;
+  c.v = d.vR;
+  c.K = d.KR;
+  c.r = d.rR;
+  c.col_K = d.iKR;
+  c.flags = d.flagsR;
   if (q.both) {
-    c.vL = vL;
-    c.KL = KL;
-    c.rL = rL;
-    c.col_KL = iKL;
-    c.flagsL = flagsL;
+    c.vL = d.vL;
+    c.KL = d.KL;
+    c.rL = d.rL;
+    c.col_KL = d.iKL;
+    c.flagsL = d.flagsL;
   }
   if (n < q.trace_cap) {
-    a.trK[n] = KR;
+    a.trK[n] = d.KR;
     a.trA[n] = c.tip;
-    a.trV[n] = vR;
-    a.trF[n] = flagsR;
+    a.trV[n] = d.vR;
+    a.trF[n] = d.flagsR;
     if (q.both) {
-      a.trKL[n] = KL;
+      a.trKL[n] = d.KL;
       a.trAL[n] = c.tipL;
-      a.trVL[n] = vL;
-      a.trFL[n] = flagsL;
+      a.trVL[n] = d.vL;
+      a.trFL[n] = d.flagsL;
     }
   }
   c.step = n + 1;
-  *a.st = c;
+  *out = c;
 }
 
 }  // namespace core

@@ -199,7 +199,8 @@ __host__ __device__ inline uint32_t step_key(uint32_t seed, int64_t step) {
 }
 
 struct CrackArgs {
-  DevCrack *st;
+  DevCrack *st;      // the crack state before the step
+  DevCrack *st_out;  // where the state after it goes (null: st)
   const void *w;     // w after the sweep (double or float, see w_is_double)
   int w_is_double;
   int w_row0;        // row of the plate that w's first row holds (0: the whole plane)
@@ -295,7 +296,16 @@ enum class Store { F64, F64S, F32_PLAIN, F32S, F16S, BF16S };
 int sweep_vec(Store s);  // sites per lane
 // one sweep step (interior strips and boundary rows in one launch); eq: the
 // equilibrium layout (plane 0 and w only; shifted storages)
-hipError_t launch_sweep(Store s, bool eq, const void *args, hipStream_t st);
+// fused: null, or the DEVICE address of the arguments of a crack step that
+// this sweep runs besides (single plate, one-step sweeps, a crack along +x or
+// none): one more wave of the boundary part executes it, and the crack-row
+// waves forecast the links it severs from the same state and field, so that
+// the sweep's bounce-back already sees them.  Its w is the sweep's source w
+// (w after the step the crack step belongs to), st the state before it and
+// st_out a second slot for the state after it (the forecast reads st while
+// the crack wave runs).
+hipError_t launch_sweep(Store s, bool eq, const void *args, hipStream_t st,
+                        const CrackArgs *fused = nullptr);
 // T = 2 .. 8 steps in one sweep (equilibrium layout, walls, a crack along
 // +x with prescribed or no growth); args is a BlockArgs of the storage's types.
 // The chunks of the strips without a plate edge run on st; the others (edge

@@ -478,6 +478,27 @@ __device__ __forceinline__ void interior_rows(const S *__restrict__ fin, S *__re
 // Row j of one strip with the full boundary treatment: bounce-back at the
 // plate edges and on severed links (read from the cut bitmask in the rows the
 // mask-row range names), traction terms, periodic wrap-around.
+// The vertical links of one lattice row (links (i, row)-(i, row + 1)) that a
+// crack step running beside the sweep in the same launch severs: columns
+// lo_r..hi_r and lo_l..hi_l (lo > hi: none).  row < 0: no such crack step.
+struct CutForecast {
+  int row = -1;
+  int lo_r = 1, hi_r = 0, lo_l = 1, hi_l = 0;
+
+  // bit k: the link of column i + k in link row r is among them
+  template <int VEC>
+  __device__ __forceinline__ uint32_t bits(int r, uint32_t i) const {
+    if (r != row) return 0u;
+    uint32_t b = 0u;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      const int c = (int)i + k;
+      if ((c >= lo_r && c <= hi_r) || (c >= lo_l && c <= hi_l)) b |= 1u << k;
+    }
+    return b;
+  }
+};
+
 template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR = false, bool EQ = false>
 __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__restrict__ fout,
                                              const W *__restrict__ win, W *__restrict__ wout,
@@ -485,7 +506,7 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
                                              const uint32_t *__restrict__ mH,
                                              const MaskRows *__restrict__ mrows,
                                              const SweepArgs<S, W, C> &a, const int strip,
-                                             const int j) {
+                                             const int j, const CutForecast &cf = CutForecast{}) {
   const Plate p = a.p;
   const int lane = threadIdx.x & 63;
   constexpr int SW = 64 * VEC;
@@ -496,7 +517,15 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
   const int last = p.nx - 1;
   const uint32_t pitch = p.pitch;
   const size_t P = p.plane;
-  const MaskRows mr = *mrows;
+  MaskRows mr = *mrows;
+  if (cf.row >= 0) {  // the forecast row counts as a row with severed links
+    if (mr.vlo > mr.vhi) {
+      mr.vlo = mr.vhi = cf.row;
+    } else {
+      mr.vlo = min(mr.vlo, cf.row);
+      mr.vhi = max(mr.vhi, cf.row);
+    }
+  }
   const int jm = j > 0 ? j - 1 : (p.periodic ? p.ny - 1 : -1);
   const int jp = j < p.ny - 1 ? j + 1 : (p.periodic ? 0 : -1);
   const uint32_t o = (uint32_t)j * pitch + il;
@@ -547,8 +576,8 @@ __device__ __forceinline__ void boundary_row(const S *__restrict__ fin, S *__res
   // severed-link bits of the lane's sites (bit k = site i0 + k)
   const uint32_t lanebits = (1u << VEC) - 1u;
   uint32_t bup = 0u, bdn = 0u, bri = 0u, ble = 0u;
-  if (up_mask) bup = (mV[(size_t)j * p.mw + (il >> 5)] >> (il & 31)) & lanebits;
-  if (dn_mask) bdn = (mV[(size_t)jm * p.mw + (il >> 5)] >> (il & 31)) & lanebits;
+  if (up_mask) bup = ((mV[(size_t)j * p.mw + (il >> 5)] >> (il & 31)) | cf.bits<VEC>(j, il)) & lanebits;
+  if (dn_mask) bdn = ((mV[(size_t)jm * p.mw + (il >> 5)] >> (il & 31)) | cf.bits<VEC>(jm, il)) & lanebits;
   if (in_range(j, mr.hlo, mr.hhi)) {
     const uint32_t *h = mH + (size_t)j * p.mw;
     bri = (h[il >> 5] >> (il & 31)) & lanebits;
