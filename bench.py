@@ -536,7 +536,7 @@ def _read_csv(path):
 
 
 def _short(name: str) -> str:
-    for key in ("sweep_step", "sweep_block_edges", "sweep_block", "crack_seq", "crack_kernel", "batch_step", "batch_crack",
+    for key in ("sweep_step", "sweep_block_edges", "sweep_block_tall", "sweep_block", "crack_seq", "crack_kernel", "batch_step", "batch_crack",
                 "batch_persistent", "adj_step", "adj_inject", "adj_export", "copyBuffer", "init_rows",
                 "export_rows", "zero_kernel", "init_mask"):
         if key in name:

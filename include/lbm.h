@@ -300,17 +300,20 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * synchronises the stream once per sweep to read the verdict; after a sweep
  * that was run again the next may take half as many steps, growing back by
  * one per sweep that held).
- * rows / waves: rows finished per wave (4, 8 or 16) and waves per workgroup
- * (1, 2, 4 or 8) of the T-step sweep for this T (0 = keep; T >= 6: 16 rows
- * only; the defaults, and
+ * rows / waves: rows finished per wave (4, 8 or 16; or 32: chunks of 16
+ * rows, two per wave of the launch away from the plate edges and crack rows,
+ * which loads and steps the rows around them once per wave instead of once
+ * per chunk) and waves per workgroup (1, 2, 4 or 8)
+ * of the T-step sweep for this T (0 = keep; T >= 6: 16 rows or more; the
+ * defaults, and
  * a cap on the resident waves per SIMD, are the fastest measured on a
  * 16384 x 8192 plate).  A call whose step count is
  * not a multiple of T ends with one shorter sweep (one step: the one-step
  * sweep).  steps = 1 restores the one-step sweep. */
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves);
 
-/* Times every shape of the T-step sweep for steps = T (rows 4, 8 or 16 per
- * wave, 16 only for T >= 6; waves 1, 2, 4 or 8 per workgroup) over
+/* Times every shape of the T-step sweep for steps = T (rows 4, 8, 16 or 32
+ * per wave, 16 or 32 for T >= 6; waves 1, 2, 4 or 8 per workgroup) over
  * trial_sweeps sweeps of h itself (h advances: tune a scratch plate made from
  * the same configuration), then sets the fastest with lbm_set_time_block and
  * returns it with its time per step.  The defaults were measured on a

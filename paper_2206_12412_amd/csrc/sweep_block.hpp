@@ -232,20 +232,25 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
   // state rows in the storage types, D of them in flight ahead of their use:
   // on this hardware a wait for a load also waits for every store issued
   // before it, so each load is issued D rows before the stores it must not
-  // wait for
-  W wl_[NR][VEC];
-  S gl_[NR][VEC];
+  // wait for.  In a fast march of more than 28 rows, row rr goes to slot
+  // rr % 8 (an array of NR rows was kept in scratch memory for NR = 44 and
+  // more); elsewhere each row has its own (with slots the boundary launch
+  // took 45 % longer).
+  constexpr int RING = (FAST && NR > 28) ? 8 : NR;
+  static_assert(D < RING || RING == NR, "a slot is reused only after its row was taken");
+  W wl_[RING][VEC];
+  S gl_[RING][VEC];
   auto load = [&](int rr) {
     const int r = jb - T + rr;
     if (FAST || (r >= 0 && r < p.ny && r <= je + T - 1 && loadable)) {
       const uint32_t o = (uint32_t)r * pitch + il;
-      load_raw<W, VEC>(a.win, o, wl_[rr]);
-      load_raw<S, VEC>(a.fin, o, gl_[rr]);
+      load_raw<W, VEC>(a.win, o, wl_[rr % RING]);
+      load_raw<S, VEC>(a.fin, o, gl_[rr % RING]);
     } else {
 #pragma unroll
       for (int k = 0; k < VEC; ++k) {
-        wl_[rr][k] = W(0);
-        gl_[rr][k] = S(0);
+        wl_[rr % RING][k] = W(0);
+        gl_[rr % RING][k] = S(0);
       }
     }
   };
@@ -273,9 +278,9 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
     for (int k = 0; k < VEC; ++k) {
       wv[0][2][k] = wv[0][1][k];
       wv[0][1][k] = wv[0][0][k];
-      wv[0][0][k] = core::to_c(wl_[rr][k]);
+      wv[0][0][k] = core::to_c(wl_[rr % RING][k]);
       gv[0][1][k] = gv[0][0][k];
-      gv[0][0][k] = core::to_c(gl_[rr][k]);
+      gv[0][0][k] = core::to_c(gl_[rr % RING][k]);
     }
 #pragma unroll
     for (int lv = 1; lv <= T; ++lv) {
@@ -345,7 +350,7 @@ __host__ __device__ inline bool fast_rows(int jb, int ny, int jc) {
 // The chunk rows that strips without a plate edge cannot take on the fast
 // path (the first and last chunk rows, those around the crack rows), for the
 // boundary launch.
-constexpr int kMaxSlowChunks = 16;
+constexpr int kMaxSlowChunks = 24;
 struct SlowChunks {
   int n;
   int c[kMaxSlowChunks];
@@ -357,7 +362,10 @@ struct SlowChunks {
 // path alone (in one kernel with the boundary path every wave was sized for
 // the larger of the two).  R rows per wave, a compile-time constant so that
 // the row march unrolls and the register windows slide by renaming instead
-// of copies.
+// of copies.  The waves of a workgroup take neighbouring strips of one chunk
+// row.  (Tried: the waves of a workgroup on consecutive chunks of one strip,
+// the odd ones marching upwards so that both waves at a chunk boundary read
+// the rows around it at the same time: 7 % slower.)
 template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
 __global__ void __launch_bounds__(512)
 sweep_block(const BlockArgs<S, W, C> A, const int s_lo, const int s_hi, const int n_chunks) {
@@ -371,6 +379,42 @@ sweep_block(const BlockArgs<S, W, C> A, const int s_lo, const int s_hi, const in
   const int jb = (task / n_int) * R;
   if (!fast_rows<R, T>(jb, p.ny, A.crack ? p.j0 : -2)) return;
   march<S, W, C, VEC, SR, R, T, true>(A, strip, jb, lane, false);
+}
+
+// The runs of consecutive fast chunk rows (at most kMaxRuns: the crack rows
+// split the plate in two), cut into groups of G chunks (a run's last chunk
+// when its length is odd in G goes to the boundary launch); group g of run k
+// (g0[k] <= g < g0[k + 1]) starts at chunk c0[k] + (g - g0[k]) G.
+constexpr int kMaxRuns = 4;
+struct FastRuns {
+  int n, G, n_groups;
+  int c0[kMaxRuns], g0[kMaxRuns];
+};
+
+// The fast launch with waves of G = RF / R chunks: strips s_lo .. s_hi - 1
+// times the groups of fast chunk rows, each wave marching its RF rows in one
+// pass (the rows around them are loaded and stepped once per RF rows instead
+// of once per R: per 16 rows march loads 16 + 2T rows and steps
+// sum_k (16 + 2 (T - k)), i.e. at T = 6 it loads 1.75 and steps 1.31 times
+// the rows it finishes, at RF = 32 1.38 and 1.16).  The march stays
+// unrolled: RF = 64 overflows the instruction cache (three times slower), and
+// as a loop over row blocks the rows loaded ahead for the next pass needed
+// register copies at the back edge, or waits for every load and store in
+// flight at each row.
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int RF, int T>
+__global__ void __launch_bounds__(512)
+sweep_block_tall(const BlockArgs<S, W, C> A, const int s_lo, const int s_hi, const FastRuns fr) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int task = (int)xcd_contiguous_block() * (int)(blockDim.x >> 6) + wave;
+  const int n_int = s_hi - s_lo;
+  if (task >= n_int * fr.n_groups) return;
+  const int strip = s_lo + task % n_int;
+  const int g = task / n_int;
+  int k = 0;
+  while (k + 1 < fr.n && g >= fr.g0[k + 1]) ++k;
+  const int c = fr.c0[k] + (g - fr.g0[k]) * (RF / R);
+  march<S, W, C, VEC, SR, RF, T, true>(A, strip, c * R, lane, false);
 }
 
 // The boundary launch: every chunk of the strips with a plate edge (strips
@@ -398,10 +442,14 @@ sweep_block_edges(const BlockArgs<S, W, C> A, const int n_strips, const int s_lo
   march<S, W, C, VEC, SR, R, T, false>(A, strip, chunk * R, lane, edge_strip_of<VEC, T>(strip, p.nx));
 }
 
-template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
+// RF: rows per wave of the fast launch, R (sweep_block) or a multiple of R
+// (sweep_block_tall); the boundary launch takes chunks of R rows.
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int RF, int T>
 hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const SideStream &ss) {
   constexpr int H = (T + VEC - 1) / VEC;
   constexpr int OW = (64 - 2 * H) * VEC;
+  constexpr int G = RF / R;
+  static_assert(RF % R == 0, "a fast wave takes whole chunks");
   const Plate &p = A.s0.p;
   const int n_strips = (p.nx + OW - 1) / OW;
   const int n_chunks = (p.ny + R - 1) / R;
@@ -415,8 +463,8 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
   SlowChunks sc{};
   const int jc = A.crack ? p.j0 : -2;
   bool ok = true;
-  auto add = [&](int c) {
-    if (c < 0 || c >= n_chunks || fast_rows<R, T>(c * R, p.ny, jc)) return;
+  auto add = [&](int c, bool fast_too) {
+    if (c < 0 || c >= n_chunks || (!fast_too && fast_rows<R, T>(c * R, p.ny, jc))) return;
     for (int k = 0; k < sc.n; ++k)
       if (sc.c[k] == c) return;
     if (sc.n == kMaxSlowChunks) {
@@ -426,11 +474,38 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
     sc.c[sc.n++] = c;
   };
   for (int c = 0; c <= T / R + 1; ++c) {
-    add(c);
-    add(n_chunks - 1 - c);
+    add(c, false);
+    add(n_chunks - 1 - c, false);
   }
   if (A.crack)
-    for (int c = (jc - R - T) / R - 1; c <= (jc + T) / R + 1; ++c) add(c);
+    for (int c = (jc - R - T) / R - 1; c <= (jc + T) / R + 1; ++c) add(c, false);
+  // the runs of fast chunk rows, in groups of G (the last chunks of a run
+  // that do not fill a group go to the boundary launch)
+  FastRuns fr{};
+  fr.G = G;
+  if constexpr (G > 1) {
+    for (int c = 0; c < n_chunks && ok;) {
+      if (!fast_rows<R, T>(c * R, p.ny, jc)) {
+        ++c;
+        continue;
+      }
+      int e = c;
+      while (e < n_chunks && fast_rows<R, T>(e * R, p.ny, jc)) ++e;
+      const int groups = (e - c) / G;
+      if (groups > 0) {
+        if (fr.n == kMaxRuns) {
+          ok = false;
+          break;
+        }
+        fr.c0[fr.n] = c;
+        fr.g0[fr.n] = fr.n_groups;
+        fr.n_groups += groups;
+        fr.n++;
+      }
+      for (int k = c + groups * G; k < e; ++k) add(k, true);
+      c = e;
+    }
+  }
   if (!ok) return hipErrorInvalidValue;
   // the boundary launch goes first, on the side stream, so that its few
   // long waves run beside the fast launch instead of after it (always there
@@ -451,14 +526,25 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (s_hi > s_lo) {
-    const long tasks = (long)(s_hi - s_lo) * n_chunks;
-    const unsigned blocks = (unsigned)((tasks + waves - 1) / waves);
-    // dynamic LDS only to cap the resident waves (s0.lds_bytes, 0 = no cap)
-    hipLaunchKernelGGL((sweep_block<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(64 * waves),
-                       (unsigned)A.s0.lds_bytes, st, A, s_lo, s_hi, n_chunks);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  // dynamic LDS only to cap the resident waves (s0.lds_bytes, 0 = no cap)
+  if constexpr (G > 1) {
+    if (s_hi > s_lo && fr.n_groups > 0) {
+      const long tasks = (long)(s_hi - s_lo) * fr.n_groups;
+      const unsigned blocks = (unsigned)((tasks + waves - 1) / waves);
+      hipLaunchKernelGGL((sweep_block_tall<S, W, C, VEC, SR, R, RF, T>), dim3(blocks),
+                         dim3(64 * waves), (unsigned)A.s0.lds_bytes, st, A, s_lo, s_hi, fr);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  } else {
+    if (s_hi > s_lo) {
+      const long tasks = (long)(s_hi - s_lo) * n_chunks;
+      const unsigned blocks = (unsigned)((tasks + waves - 1) / waves);
+      hipLaunchKernelGGL((sweep_block<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(64 * waves),
+                         (unsigned)A.s0.lds_bytes, st, A, s_lo, s_hi, n_chunks);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   if (fork) {
     hipError_t e = hipEventRecord(ss.join, ss.side);
@@ -468,19 +554,21 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
   return hipSuccess;
 }
 
-// rows 4, 8 or 16 (T >= 6: 16; shorter chunks would recompute their halo
-// levels more often than they advance their own rows)
+// rows 4, 8 or 16 (T >= 6: 16 or more; shorter chunks would recompute their
+// halo levels more often than they advance their own rows), or 32 for the
+// fast launch (chunks of 16 rows, two per wave; the boundary launch keeps 16)
 template <typename S, typename W, typename C, int VEC, bool SR, int T>
 hipError_t block_rows(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st,
                       const SideStream &ss) {
   switch (rows) {
     case 4:
-      if constexpr (T <= 5) return block_t<S, W, C, VEC, SR, 4, T>(A, waves, st, ss);
+      if constexpr (T <= 5) return block_t<S, W, C, VEC, SR, 4, 4, T>(A, waves, st, ss);
       return hipErrorInvalidValue;
     case 8:
-      if constexpr (T <= 5) return block_t<S, W, C, VEC, SR, 8, T>(A, waves, st, ss);
+      if constexpr (T <= 5) return block_t<S, W, C, VEC, SR, 8, 8, T>(A, waves, st, ss);
       return hipErrorInvalidValue;
-    case 16: return block_t<S, W, C, VEC, SR, 16, T>(A, waves, st, ss);
+    case 16: return block_t<S, W, C, VEC, SR, 16, 16, T>(A, waves, st, ss);
+    case 32: return block_t<S, W, C, VEC, SR, 16, 32, T>(A, waves, st, ss);
     default: return hipErrorInvalidValue;
   }
 }

@@ -218,6 +218,11 @@ def tb_cases(steps):
                      crack_tip=420.5, both_tips=True, growth=1, v_rel=0.6,
                      tau_hist=1e-3 * (1 + 0.1 * np.sin(n / 7.0)), trace_cap=steps,
                      wdot0=1e-4 * rng.normal(size=(230, 1000))),
+        # runs of 20 and more fast chunk rows on either side of the crack rows
+        # (groups of up to 16 chunks and shorter remainders)
+        "taller": dict(nx=530, ny=700, has_crack=True, crack_row=333, crack_tip=80.5, growth=1,
+                       v_rel=0.5, tau_hist=1e-3 * (1 + 0.1 * np.sin(n / 11.0)), trace_cap=steps,
+                       wdot0=1e-4 * rng.normal(size=(700, 530))),
         # crack rows next to the bottom edge (a Dirichlet top edge), and next to
         # the top edge with two tips: the crack rows and the edge rows share chunks
         "crack-bottom": dict(nx=700, ny=90, has_crack=True, crack_row=0, crack_tip=200.5, growth=1,
@@ -230,15 +235,19 @@ def tb_cases(steps):
     }
 
 
-SHAPES = {2: [(16, 4), (4, 1), (8, 8), (4, 2)], 3: [(16, 2), (4, 4), (8, 1)],
-          4: [(4, 8), (8, 4), (16, 2)], 5: [(8, 2), (4, 4), (16, 4)], 6: [(16, 4), (16, 1)],
-          7: [(16, 2)], 8: [(16, 4), (16, 8)]}
+# rows 32: chunks of 16 rows, two of them per wave of the fast launch, the
+# runs of fast chunk rows cut into such pairs (an odd chunk goes to the
+# boundary launch)
+SHAPES = {2: [(16, 4), (4, 1), (8, 8), (4, 2), (32, 4)], 3: [(16, 2), (4, 4), (8, 1), (32, 1)],
+          4: [(4, 8), (8, 4), (16, 2), (32, 2)], 5: [(8, 2), (4, 4), (16, 4), (32, 8)],
+          6: [(16, 4), (16, 1), (32, 4), (32, 2)], 7: [(16, 2), (32, 4)],
+          8: [(16, 4), (16, 8), (32, 4)]}
 
 
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 @pytest.mark.parametrize("name", ["edge-prescribed", "two-tip-dirichlet", "no-crack",
-                                  "stationary-tiny", "wall-reached", "tall", "crack-bottom",
-                                  "crack-top"])
+                                  "stationary-tiny", "wall-reached", "tall", "taller",
+                                  "crack-bottom", "crack-top"])
 @pytest.mark.parametrize("T,rows,waves", [(T, r, w) for T in range(2, 9) for r, w in SHAPES[T]])
 def test_time_blocked_sweep_equals_one_step_sweeps_bitwise(storage, name, T, rows, waves):
     steps = 151  # not a multiple of T: the last sweep is shorter
@@ -254,6 +263,26 @@ def test_time_blocked_sweep_equals_one_step_sweeps_bitwise(storage, name, T, row
              kw.get("has_crack", False))
     one.close()
     blk.close()
+
+
+@pytest.mark.parametrize("storage,rounding", [("f16s", "stochastic"), ("bf16s", "nearest")])
+@pytest.mark.parametrize("T,rows", [(6, 32), (4, 32), (8, 32), (2, 32)])
+@pytest.mark.parametrize("name", ["tall", "taller"])
+def test_tall_waves_equal_16_row_waves_16bit(storage, rounding, T, rows, name):
+    """16-bit storages round once per T-step sweep, after its last step; a
+    wave of several chunks rounds the same FP32 values with the same draws, so
+    its bits equal those of 16-row waves."""
+    steps = 151
+    kw = tb_cases(steps)[name]
+    say(f"{T}-step sweep {name} {storage} {rounding}: rows {rows} against 16")
+    a = Solver(Config(storage=storage, layout="eq", rounding=rounding, seed=3, **kw))
+    b = Solver(Config(storage=storage, layout="eq", rounding=rounding, seed=3, **kw))
+    a.set_time_block(T, 16, 4)
+    b.set_time_block(T, rows, 4)
+    a.step(steps)
+    b.step(steps)
+    same(a, b, f"{name} {storage} T={T} rows={rows}", kw.get("both_tips", False),
+         kw.get("has_crack", False))
 
 
 @pytest.mark.parametrize("T", [2, 3, 4, 5, 6, 8])
