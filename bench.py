@@ -128,12 +128,15 @@ def run_storage(p, storage, steps, warmup, torch, ref=None, tune=False):
     run's w at the same step when one is given) and a short kernel-timing leg
     runs whole T-step sweeps with per-launch HIP events, so that the sweep
     kernel's launch duration is sampled on full sweeps only and the events do
-    not perturb the timed interval."""
+    not perturb the timed interval.  The leg starts with two untimed sweeps
+    (the export leaves the GPU idle, and the first sweeps after it run at a
+    lower clock: with two samples of six steps the mean was 17 % above the
+    kernel trace's) and samples at least four sweeps and 24 steps."""
     from paper_2206_12412_amd import Solver
     T = time_block(storage)
     warm = max(int(warmup), 2)
-    k_steps = T * max(1, -(-12 // T))  # whole sweeps, at least 12 steps
-    s = Solver(plate_config(p, storage, warm + steps + k_steps))
+    k_steps = T * max(4, -(-24 // T))  # whole sweeps, at least four and 24 steps
+    s = Solver(plate_config(p, storage, warm + steps + 2 * T + k_steps))
     tuned = s.autotune(trial_steps=5) if tune else None  # on a scratch copy of the plate
     if T >= 2:
         if tune:  # the T-step sweep's own shapes, also on a scratch copy
@@ -168,6 +171,7 @@ def run_storage(p, storage, steps, warmup, torch, ref=None, tune=False):
     if ref is None:
         out["tip"] = s.traces(warm, steps)["tip"]
     del w
+    s.step(2 * T)
     s.timing(True, stride=1)
     s.step(k_steps)
     tm = s.timing(False)
@@ -214,17 +218,19 @@ def run_k_leg(p, storage, steps, torch):
 
 
 def copy_bandwidth(torch, mib: int = 4096, reps: int = 10) -> float:
-    """GB/s of a plain device-to-device copy (read + write counted): the
-    practical ceiling of a kernel that reads and writes every byte once."""
+    """GB/s of a plain streaming kernel that reads and writes every byte once
+    (read + write counted): the practical ceiling of the sweeps.  An
+    elementwise kernel (torch.neg on FP32) rather than a device copy, whose
+    blit kernel reaches 4.6 TB/s on 4 GiB against 6.2 TB/s."""
     n = mib << 20
-    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    torch.neg(a, out=b)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        b.copy_(a)
+        torch.neg(a, out=b)
     e1.record()
     torch.cuda.synchronize()
     gbs = 2.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
@@ -544,14 +550,52 @@ def _short(name: str) -> str:
     return name[:40]
 
 
+def _instance(name: str) -> str:
+    """Storage and template flags of a sweep kernel name, mangled or not
+    (the demangler of this ROCm prints __bf16 as `bool _Accum`): e.g.
+    "f16 sr eq fused" for sweep_step, "f16 T=6 rows=32" for the T-step ones."""
+    if "DF16b" in name or "__bf16" in name or "bool _Accum" in name:
+        st = "bf16"
+    elif "DF16_" in name or "_Float16" in name:
+        st = "f16"
+    elif "Ifff" in name or "<float" in name:
+        st = "f32"
+    elif "Iddd" in name or "<double" in name:
+        st = "f64"
+    else:
+        return ""
+    if "sweep_step" in name:
+        m = re.search(r"Li[24]E((?:Lb[01]E){4})", name)
+        flags = [c == "1" for c in re.findall(r"Lb([01])E", m.group(1))] if m else None
+        if flags is None:
+            m = re.search(r", [24], (true|false), (true|false), (true|false), (true|false)>", name)
+            flags = [x == "true" for x in m.groups()] if m else None
+        if not flags:
+            return st
+        shift, sr, eq, fused = flags
+        return " ".join([st] + (["sr"] if sr else []) + (["eq"] if eq else ["five planes"]) +
+                        (["+crack step"] if fused else []))
+    if "sweep_block" in name:
+        head = name.split("(")[0]  # the template arguments, not the parameter types
+        ints = re.findall(r"Li(\d+)E", head) or re.findall(r", (\d+)(?=[,>])", head)
+        ints = [int(x) for x in ints]
+        sr = "ELb1ELi" in head or re.search(r", true, \d+, \d+", head) is not None
+        if "tall" in name and len(ints) >= 3:
+            return f"{st}{' sr' if sr else ''} T={ints[-1]} rows={ints[-2]}"
+        if len(ints) >= 2:
+            return f"{st}{' sr' if sr else ''} T={ints[-1]} rows={ints[-2]}"
+    return st
+
+
 def summarize_trace(dirpath: str, out_md: str, command: str):
     """Markdown summary of a `rocprofv3 --kernel-trace --stats` run."""
     rows = _read_csv(os.path.join(dirpath, "run_kernel_stats.csv"))
     lines = [f"# Kernel trace: {os.path.basename(out_md)}", "", "Command:", "",
-             f"    {command}", "", "| kernel | calls | avg us | min us | max us | % time | full name |",
-             "|---|---|---|---|---|---|---|"]
+             f"    {command}", "", "| kernel | instance | calls | avg us | min us | max us | % time | full name |",
+             "|---|---|---|---|---|---|---|---|"]
     for r in rows:
-        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+        lines.append(f"| {_short(r['Name'])} | {_instance(r['Name'])} | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} | `{r['Name'][:110]}` |")
     with open(out_md, "w") as fh:
@@ -747,7 +791,8 @@ def main():
     if k_ref:
         k_res[k_ref] = {"reference": True}
 
-    copy_gbs = copy_bandwidth(torch)
+    # (not in a counter run: its copies would be taken for the calibration copy)
+    copy_gbs = copy_bandwidth(torch) if args.calibrate_copy == 0 else None
 
     per = {}
     for st, r in results.items():
@@ -763,7 +808,7 @@ def main():
             e["crack_ms_per_launch"] = round(r["crack_ms_per_launch"], 4)
             e["kernel_GBps"] = round(gbs, 1)
             e["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
-            e["copy_frac"] = round(gbs / copy_gbs, 4)
+            e["copy_frac"] = round(gbs / copy_gbs, 4) if copy_gbs else None
             tr = traffic_for(st, args.workload, p.sites)
             if tr:
                 e["traffic_over_algorithmic"] = round(tr / own, 4)
@@ -799,8 +844,10 @@ def main():
                    "timed_steps": [head["first_step"], head["first_step"] + steps],
                    "parallelism": "single-gpu"},
         "storages": per,
+        # K leg storages that are not timed (e.g. BF16 with eight steps per sweep)
+        "k_leg_only": {st: v for st, v in k_res.items() if st not in per and st != k_ref},
         "error_reference": ref_name,
-        "copy_GBps": round(copy_gbs, 1),
+        "copy_GBps": round(copy_gbs, 1) if copy_gbs else None,
     }
     # FP16 storage against FP32 storage: in the headline's layout, and in the
     # five-population layout (the layout the 48 / 28 B/site ratio is stated for)
@@ -812,8 +859,8 @@ def main():
         line["fp16_vs_fp32_five_planes"] = {
             "fp16": args.record, "fp32": "f32",
             "glups_ratio": round(results[args.record]["glups"] / results["f32"]["glups"], 3),
-            "kernel_ratio": round(results["f32"]["kernel_ms_per_launch"]
-                                  / results[args.record]["kernel_ms_per_launch"], 3)}
+            "kernel_ratio_sampled": round(results["f32"]["kernel_ms_per_launch"]
+                                          / results[args.record]["kernel_ms_per_launch"], 3)}
     if args.storage in k_res and args.storage != k_ref:
         line["K_III_error"] = dict(
             {k: v for k, v in k_res[args.storage].items() if k.startswith("K_err")},
@@ -821,11 +868,16 @@ def main():
             steps=k_steps, workload=p.name)
     # roofline of record: the one-step five-plane sweep of the FP16 storage,
     # whose algorithmic bytes are read + write of the five populations (2 B)
-    # and of w (4 B) per site update
+    # and of w (4 B) per site update.  Its launch duration is the timed
+    # region's time per step: one sweep launch per step (each crack step runs
+    # inside the next sweep, and the call's last one is one launch in 1200
+    # steps).  The per-launch event samples of the kernel leg count each
+    # kernel's dispatch as well (~3 % more), and are reported beside it.
     if args.record in results and "kernel_ms_per_launch" in results[args.record]:
         r = results[args.record]
         alg = r["sites"] * sweep_bytes_per_site(args.record)
-        achieved = alg / (r["kernel_ms_per_launch"] * 1e-3) / 1e9
+        launch_ms = r["ms"] / steps
+        achieved = alg / (launch_ms * 1e-3) / 1e9
         tr = traffic_for(args.record, args.workload, p.sites)
         line["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -833,16 +885,22 @@ def main():
             "kernel": f"sweep_step ({args.record}: five populations, one step per launch)",
             "bytes_per_site": sweep_bytes_per_site(args.record),
             "algorithmic_bytes_per_launch": alg,
-            "kernel_ms": round(r["kernel_ms_per_launch"], 4),
-            "copy_frac": round(achieved / copy_gbs, 4)}
+            "kernel_ms": round(launch_ms, 4),
+            "kernel_ms_source": "timed region, one sweep launch per step",
+            "kernel_ms_sampled": round(r["kernel_ms_per_launch"], 4),
+            "copy_frac": round(achieved / copy_gbs, 4) if copy_gbs else None}
     # the headline's own kernel: T steps per launch in the equilibrium layout,
     # counted in the bytes it must move (rest population and w, read and
     # written once per launch), not in the five-population bytes of the T
     # steps it replaces
+    # (launch duration: the timed region's time per T steps, one sweep -- its
+    # fast and boundary launches side by side, the crack steps beside the
+    # next sweep -- per T steps)
     if "kernel_ms_per_launch" in head and args.storage != args.record:
         T = head["steps_per_launch"]
         alg = head["sites"] * head["bytes_per_site"] * T
-        achieved = alg / (head["kernel_ms_per_launch"] * 1e-3) / 1e9
+        launch_ms = head["ms"] / steps * T
+        achieved = alg / (launch_ms * 1e-3) / 1e9
         tr = traffic_for(args.storage, args.workload, p.sites)
         line["roofline_headline_kernel"] = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -850,8 +908,10 @@ def main():
             "kernel": f"{block_kernel(args.storage)} ({args.storage})", "steps_per_launch": T,
             "bytes_per_site_per_launch": head["bytes_per_site"] * T,
             "algorithmic_bytes_per_launch": alg,
-            "kernel_ms": round(head["kernel_ms_per_launch"], 4),
-            "kernel_ms_per_step": round(head["kernel_ms_per_launch"] / T, 4),
+            "kernel_ms": round(launch_ms, 4),
+            "kernel_ms_per_step": round(launch_ms / T, 4),
+            "kernel_ms_source": "timed region, one sweep per T steps",
+            "kernel_ms_sampled": round(head["kernel_ms_per_launch"], 4),
             "note": "equilibrium layout (only the rest population and w are state at omega = 1); "
                     "its bytes are not the five-population bytes the roofline of record counts"}
     if not args.no_cpu:
