@@ -625,9 +625,20 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
         factor = copy_bytes / (copy * 1024.0)
         tb = time_block(storage)
         parts = ["sweep_block_edges", "sweep_block"] if tb >= 2 else ["sweep_step"]
-        # the instantiation of this storage's T (a run's last sweep may be shorter)
-        of_t = (lambda k: True) if tb < 2 else \
-            (lambda k: f"ELi{tb}EEEvNS_9BlockArgs" in k or f", {tb}>(lbmk::BlockArgs" in k)
+        # the instantiations of this storage: its type, rounding, layout and T
+        # (the run also times the record storage, and a run's last sweep may be
+        # shorter)
+        st_name, st_round, st_layout = parse_storage(storage)
+        want_type = {"f64": "f64", "f32": "f32", "f32plain": "f32", "f16s": "f16",
+                     "bf16s": "bf16"}[st_name]
+
+        def of_t(k):
+            words = _instance(k).split()
+            if not words or words[0] != want_type or (("sr" in words) != (st_round == "stochastic")):
+                return False
+            if tb >= 2:
+                return f"T={tb}" in words
+            return ("eq" in words) == (st_layout == "eq")
         kib, picked, other = 0.0, [], {}
         for want in parts:
             names = {}
