@@ -296,8 +296,10 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * K criterion (eq. sifCriterion): the sweep severs links as if each tip kept
  * the speed of its last step; when the crack step of some step n + m before
  * the last leaves a tip in another column than that prediction, the state of
- * step n is put back and the sweep runs again for m + 1 steps (lbm_step then
- * synchronises the stream once per sweep to read the verdict; after a sweep
+ * step n is put back and the sweep runs again for m + 1 steps (lbm_step
+ * queues up to four such sweeps ahead of the verdicts it has read, gated on a
+ * device word that a wrong one closes, and rewinds at a wrong one; while
+ * per-kernel timing is on it waits for each verdict instead; after a sweep
  * that was run again the next may take half as many steps, growing back by
  * one per sweep that held).
  * rows / waves: rows finished per wave (4, 8 or 16; or 32: chunks of 16

@@ -124,7 +124,8 @@ Layout make_layout(const lbm_config &c, Store s) {
   // T-step sweep: the crack rows after steps n .. n + T - 2
   L.off_wmid = o; o += align_up((size_t)2 * (lbmk::kMaxTimeBlock - 1) * L.pitch * L.welem, 256);
   // speculative T-step sweep (K criterion): the crack state and crack-row mask of step n
-  L.off_spec = o; o += align_up(sizeof(lbmk::SpecSlot), 256) + align_up((size_t)L.mw * 4, 256);
+  // (and the gate of the speculative sweeps in flight)
+  L.off_spec = o; o += align_up(sizeof(lbmk::SpecSlot), 256) + align_up((size_t)L.mw * 4, 256) + 256;
   L.off_sens = o; o += align_up((size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.off_trS = o; o += align_up(tc * (size_t)std::max(c.n_sensors, 1) * 8, 256);
   L.stage_rows = (int)std::max<int64_t>(1, std::min<int64_t>(c.ny, (1 << 20) / std::max(1, c.nx)));
@@ -273,6 +274,9 @@ int validate(const lbm_config *c, Store *s) {
 
 }  // namespace
 
+// K-criterion T-step sweeps in flight at once (see spec_pipeline)
+constexpr int kSpecDepth = 4;
+
 struct lbm_handle {
   lbm_config cfg{};
   Store store = Store::F64;
@@ -311,9 +315,12 @@ struct lbm_handle {
   // after each sweep that held, at most T)
   int64_t spec_blocks = 0, spec_reruns = 0;
   int spec_cap = lbmk::kMaxTimeBlock;
-  // the speculative sweep's verdict, written by the crack kernel into pinned
-  // host memory (allocated with the first such sweep) and its device address
+  // the speculative sweeps' verdicts, written by the crack kernel into pinned
+  // host memory (allocated with the first such sweep; one per sweep in
+  // flight) and their device address
   lbmk::SpecOut *spec_host = nullptr, *spec_dev = nullptr;
+  // the gate the T-step launches pass on (null: ungated)
+  const int32_t *blk_gate = nullptr;
   // the side stream the T-step sweep's boundary chunks run on beside the
   // rest, with its fork and join events (created with the first T-step
   // sweep, on the device current then; default priority)
@@ -366,6 +373,13 @@ struct lbm_handle {
     return crack_step_needed() && !macro() && (!cfg.has_crack || line.aligned);
   }
   lbmk::SpecSlot *spec_slot() const { return reinterpret_cast<lbmk::SpecSlot *>(base + L.off_spec); }
+  uint32_t *spec_mask() const {
+    return reinterpret_cast<uint32_t *>(base + L.off_spec + align_up(sizeof(lbmk::SpecSlot), 256));
+  }
+  int32_t *spec_gate() const {
+    return reinterpret_cast<int32_t *>(base + L.off_spec + align_up(sizeof(lbmk::SpecSlot), 256) +
+                                       align_up((size_t)L.mw * 4, 256));
+  }
   double *stage() const { return reinterpret_cast<double *>(base + L.off_stage); }
   double tau_at(int64_t n) const {
     if (tau.empty()) return 0.0;
@@ -490,6 +504,7 @@ int launch_block_typed(lbm_handle *h, int T) {
   A.dt = h->dt;
   A.a_lo = h->a_lo;
   A.a_hi = h->a_hi;
+  A.gate = h->blk_gate;
   if (!h->side.side) {
     HIP_TRY(hipStreamCreateWithFlags(&h->side.side, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming));
@@ -596,6 +611,159 @@ int flush_deferred_crack(lbm_handle *h) {
   h->crack_deferred = false;
   h->cslot = 0;
   return LBM_OK;
+}
+
+// The pinned verdict buffers of the speculative sweeps (one per sweep in
+// flight), made with the first such sweep.
+int ensure_spec_out(lbm_handle *h) {
+  if (h->spec_dev) return LBM_OK;  // both pointers or neither
+  lbmk::SpecOut *hp = nullptr;
+  void *dp = nullptr;
+  HIP_TRY(hipHostMalloc((void **)&hp, kSpecDepth * sizeof(lbmk::SpecOut),
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess || !dp) {
+    (void)hipHostFree(hp);
+    return fail(LBM_EHIP, "no device address for the pinned verdict buffer");
+  }
+  h->spec_host = hp;
+  h->spec_dev = static_cast<lbmk::SpecOut *>(dp);
+  return LBM_OK;
+}
+
+// The crack steps of a T-step sweep of ns steps just enqueued: steps
+// n .. n + ns - 2 from the crack rows after each (the side buffer), the last
+// from the new state.
+lbmk::CrackSeq crack_seq_args(const lbm_handle *h, int ns) {
+  lbmk::CrackSeq q{};
+  q.a = crack_args(h);
+  q.n = ns;
+  for (int m = 0; m < ns; ++m) {
+    const bool mid = m + 1 < ns;
+    q.w[m] = mid ? (const void *)(h->base + h->L.off_wmid + (size_t)2 * m * h->L.pitch * h->L.welem)
+                 : q.a.w;
+    q.w_row0[m] = mid ? h->plate.j0 : 0;
+  }
+  return q;
+}
+
+// K-criterion T-step sweeps with up to kSpecDepth of them in flight.  A
+// speculative sweep is right or is run again with the steps its crack
+// sequence found right (see lbm_step); instead of waiting for each verdict
+// before queueing the next sweep, the host queues the next sweeps on the
+// assumption that the pending ones hold, each gated on a device word: a
+// crack sequence that finds a prediction wrong puts the start state back and
+// closes the gate, so that everything queued after it returns at once and
+// leaves buffers, mask and crack state as they were.  The host reads the
+// verdicts in order (an event after each crack sequence); at a wrong one it
+// rewinds to that sweep's start, opens the gate and queues the steps found
+// right.  The kernels, their arguments and their order on the stream are
+// those of one sweep at a time, so the results are the same bits.  The host
+// polls the pinned verdicts (an event per verdict put one more marker between
+// a crack sequence and the next sweep).  Returns in *done the steps advanced
+// (every sweep resolved).
+int spec_pipeline(lbm_handle *h, int64_t max_steps, int64_t *done) {
+  *done = 0;
+  int rc = ensure_spec_out(h);
+  if (rc != LBM_OK) return rc;
+  int32_t *gate = h->spec_gate();
+  HIP_TRY(lbmk::launch_set_flag(gate, 1, h->stream));
+  struct Pending {
+    int64_t step0;
+    int cur0, ns, slot;
+  };
+  Pending q[kSpecDepth];
+  int qh = 0, qn = 0, next_slot = 0;
+  int64_t queued = 0;  // steps queued (resolved or not)
+  int force = 0;       // the next sweep's length after a wrong one (0: planned)
+  h->blk_gate = gate;
+  for (;;) {
+    while (qn < kSpecDepth && (force > 0 || max_steps - queued >= 2)) {
+      int ns = force > 0 ? force
+                         : (int)std::min<int64_t>(std::min(h->tblock, std::max(2, h->spec_cap)),
+                                                  max_steps - queued);
+      force = 0;
+      if (ns == 1) {
+        // one step found right: the one-step sweep and its crack step
+        rc = launch_sweep_any(h, nullptr);
+        if (rc == LBM_OK) rc = launch_crack_step(h);
+        if (rc != LBM_OK) break;
+        h->cur = 1 - h->cur;
+        h->step += 1;
+        queued += 1;
+        *done += 1;
+        continue;
+      }
+      const int slot = next_slot;
+      next_slot = (next_slot + 1) % kSpecDepth;
+      *(volatile int32_t *)&h->spec_host[slot].valid = -1;
+      rc = launch_block_any(h, ns);
+      if (rc != LBM_OK) break;
+      lbmk::CrackSeq cs = crack_seq_args(h, ns);
+      cs.spec_out = h->spec_dev + slot;
+      cs.spec = h->spec_slot();
+      cs.spec_mask = h->spec_mask();
+      cs.gate = gate;
+      if (lbmk::launch_crack_seq(cs, h->stream) != hipSuccess) {
+        rc = fail(LBM_EHIP, "queueing a speculative sweep failed");
+        break;
+      }
+      q[(qh + qn) % kSpecDepth] = Pending{h->step, h->cur, ns, slot};
+      qn++;
+      h->cur = 1 - h->cur;
+      h->step += ns;
+      queued += ns;
+    }
+    if (rc != LBM_OK || qn == 0) break;
+    const Pending f = q[qh];
+    // the oldest verdict: its crack sequence runs (every one before it held),
+    // and writes it into pinned memory; the host polls for it (a stream that
+    // is idle with no verdict would be a fault, not a wait)
+    int32_t valid = -1;
+    for (int64_t it = 0;; ++it) {
+      valid = *(volatile int32_t *)&h->spec_host[f.slot].valid;
+      if (valid != -1) break;
+      if ((it & 1023) == 1023) {
+        const hipError_t e = hipStreamQuery(h->stream);
+        if (e == hipSuccess) {
+          valid = *(volatile int32_t *)&h->spec_host[f.slot].valid;
+          if (valid == -1) rc = fail(LBM_EHIP, "a speculative sweep left no verdict");
+          break;
+        }
+        if (e != hipErrorNotReady) {
+          rc = fail(LBM_EHIP, "waiting for a speculative sweep failed: %s", hipGetErrorString(e));
+          break;
+        }
+      }
+    }
+    if (rc != LBM_OK) break;
+    if (valid < 1 || valid > f.ns) {
+      rc = fail(LBM_EHIP, "bad speculation count %d", valid);
+      break;
+    }
+    h->spec_blocks++;
+    qh = (qh + 1) % kSpecDepth;
+    qn--;
+    if (valid == f.ns) {
+      h->spec_cap = std::min(h->tblock, h->spec_cap + 1);
+      *done += f.ns;
+      continue;
+    }
+    // wrong from crack step `valid` on: the sweeps queued after it did nothing
+    h->spec_reruns++;
+    h->spec_cap = std::max(2, f.ns / 2);
+    h->cur = f.cur0;
+    h->step = f.step0;
+    queued = *done;
+    qn = 0;
+    qh = 0;
+    if (lbmk::launch_set_flag(gate, 1, h->stream) != hipSuccess) {
+      rc = fail(LBM_EHIP, "reopening the gate failed");
+      break;
+    }
+    force = valid;
+  }
+  h->blk_gate = nullptr;
+  return rc;
 }
 
 // The macroscopic boundary scheme of step n = h->step on the buffers the
@@ -975,6 +1143,14 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
       const int rc = flush_deferred_crack(h);
       if (rc != LBM_OK) return rc;
     }
+    // untimed speculative sweeps: several in flight
+    if (sif_blocks && ns >= 2 && !h->timing) {
+      int64_t done = 0;
+      const int rc = spec_pipeline(h, nsteps - k, &done);
+      if (rc != LBM_OK) return rc;
+      k += done;
+      continue;
+    }
     // Under the K criterion the T-step sweep severs links as if each tip kept
     // its last speed; when a crack step before the last leaves a tip in
     // another column, the crack kernel puts back the state of step n and the
@@ -1009,34 +1185,15 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
         if (ns >= 2) {
           // steps n .. n + T - 2 from the crack rows after each, then the last
           // from the new state, in one launch
-          lbmk::CrackSeq q{};
-          q.a = crack_args(h);
-          q.n = ns;
-          for (int m = 0; m < ns; ++m) {
-            const bool mid = m + 1 < ns;
-            q.w[m] = mid ? (const void *)(h->base + h->L.off_wmid + (size_t)2 * m * h->L.pitch * h->L.welem)
-                         : q.a.w;
-            q.w_row0[m] = mid ? h->plate.j0 : 0;
-          }
+          lbmk::CrackSeq q = crack_seq_args(h, ns);
           spec = h->cfg.growth == LBM_GROW_SIF;
           if (spec) {
-            if (!h->spec_dev) {  // both pointers or neither
-              lbmk::SpecOut *hp = nullptr;
-              void *dp = nullptr;
-              HIP_TRY(hipHostMalloc((void **)&hp, sizeof(lbmk::SpecOut),
-                                    hipHostMallocMapped | hipHostMallocCoherent));
-              if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess || !dp) {
-                (void)hipHostFree(hp);
-                return fail(LBM_EHIP, "no device address for the pinned verdict buffer");
-              }
-              h->spec_host = hp;
-              h->spec_dev = static_cast<lbmk::SpecOut *>(dp);
-            }
+            rc = ensure_spec_out(h);
+            if (rc != LBM_OK) return rc;
             *(volatile int32_t *)&h->spec_host->valid = -1;
             q.spec_out = h->spec_dev;
             q.spec = h->spec_slot();
-            q.spec_mask = reinterpret_cast<uint32_t *>(h->base + h->L.off_spec +
-                                                       align_up(sizeof(lbmk::SpecSlot), 256));
+            q.spec_mask = h->spec_mask();
           }
           if (!spec && !timed && h->side.side) {
             // on the side stream right after the boundary launch, whose rows

@@ -17,10 +17,13 @@ __global__ void __launch_bounds__(64) crack_kernel(const CrackArgs a) { core::cr
 // start is kept; when crack step m < n - 1 leaves a tip in another column
 // than that prediction (the links the sweep of steps m + 2 .. n used differ
 // from the real ones), the state of the start is put back and valid = m + 1
-// tells the host to run the sweep again for m + 1 steps.
+// tells the host to run the sweep again for m + 1 steps; with a gate (several
+// sweeps in flight) it also closes the gate, so that the sweeps and crack
+// sequences queued after this one return at once and leave the state alone.
 __global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
+  if (s.gate && *s.gate == 0) return;
   const Plate p = s.a.p;
   const CrackParams q = s.a.c;
   uint32_t *row = s.a.mV + (size_t)p.j0 * p.mw;
@@ -69,6 +72,7 @@ __global__ void __launch_bounds__(64) crack_seq_kernel(const CrackSeq s) {
         *s.a.st = s.spec->st;
         *s.a.mrows = s.spec->mr;
         s.spec_out->valid = m + 1;
+        if (s.gate) *s.gate = 0;
       }
       return;
     }
@@ -101,7 +105,14 @@ __global__ void init_mask_kernel(uint32_t *mV, uint32_t *mH, MaskRows *mrows, Pl
   if (t == 0) *mrows = has_crack ? MaskRows{p.j0, p.j0, 1, 0} : MaskRows{1, 0, 1, 0};
 }
 
+__global__ void set_flag_kernel(int32_t *p, int32_t v) { *p = v; }
+
 }  // namespace
+
+hipError_t launch_set_flag(int32_t *p, int32_t v, hipStream_t st) {
+  hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_crack(const CrackArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(crack_kernel, dim3(1), dim3(64), 0, st, a);

@@ -182,6 +182,10 @@ struct BlockArgs {
   int crack, both, grow;              // crack present, two tips, growing tips
   int sif;                            // K criterion: each tip keeps its last speed (predicted)
   double v_rel, cs, dt, a_lo, a_hi;
+  // K criterion, several sweeps in flight: the sweep runs only while *gate is
+  // nonzero (a crack sequence that found a prediction wrong closes it, and the
+  // sweeps queued after it return at once); null = always
+  const int32_t *gate;
 };
 
 // Counter-based randomness of the stochastic rounding: the integer hash
@@ -350,8 +354,13 @@ struct CrackSeq {
   SpecSlot *spec;                    // non-null: the sweep assumed no cuts (K criterion)
   uint32_t *spec_mask;               // mw words: the crack row's mask at the start
   SpecOut *spec_out;                 // device address of the host's SpecOut
+  // with several sweeps in flight (see BlockArgs::gate): the sequence runs only
+  // while *gate is nonzero, and closes it when it puts the start state back
+  int32_t *gate;
 };
 hipError_t launch_crack_seq(const CrackSeq &s, hipStream_t st);
+// *p = v by a kernel (capturable, unlike a memset node)
+hipError_t launch_set_flag(int32_t *p, int32_t v, hipStream_t st);
 hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const Plate &p,
                             int has_crack, double x0, double a0, hipStream_t st);
 

@@ -369,6 +369,7 @@ struct SlowChunks {
 template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
 __global__ void __launch_bounds__(512)
 sweep_block(const BlockArgs<S, W, C> A, const int s_lo, const int s_hi, const int n_chunks) {
+  if (A.gate && *A.gate == 0) return;  // a sweep queued after a wrong prediction
   const Plate p = A.s0.p;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -404,6 +405,7 @@ struct FastRuns {
 template <typename S, typename W, typename C, int VEC, bool SR, int R, int RF, int T>
 __global__ void __launch_bounds__(512)
 sweep_block_tall(const BlockArgs<S, W, C> A, const int s_lo, const int s_hi, const FastRuns fr) {
+  if (A.gate && *A.gate == 0) return;  // a sweep queued after a wrong prediction
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int task = (int)xcd_contiguous_block() * (int)(blockDim.x >> 6) + wave;
@@ -423,6 +425,7 @@ template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
 __global__ void __launch_bounds__(256)
 sweep_block_edges(const BlockArgs<S, W, C> A, const int n_strips, const int s_lo, const int s_hi,
                   const int n_chunks, const SlowChunks sc) {
+  if (A.gate && *A.gate == 0) return;
   const Plate p = A.s0.p;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

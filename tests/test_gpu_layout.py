@@ -359,6 +359,31 @@ def test_time_blocked_sweep_under_the_K_criterion_equals_one_step_sweeps_bitwise
     blk.close()
 
 
+@pytest.mark.parametrize("T", [4, 8])
+@pytest.mark.parametrize("name", ["sif-two-tip", "sif-dirichlet"])
+def test_speculative_sweeps_in_flight_equal_one_at_a_time(name, T):
+    """Untimed K-criterion T-step sweeps are queued several at a time, gated on
+    a device word that a wrong prediction closes; timed ones run one at a time,
+    the host reading each verdict before the next sweep.  The sweep lengths
+    may differ (the in-flight path plans with verdicts it has not read yet),
+    the results may not."""
+    steps = 300
+    kw = sif_cases(steps)[name]
+    a = Solver(Config(storage="f32", layout="eq", **kw))
+    b = Solver(Config(storage="f32", layout="eq", **kw))
+    a.set_time_block(T)
+    b.set_time_block(T)
+    b.timing(True, stride=1)
+    for n in (7, 150, steps):
+        a.step(n - a.steps_done)
+        b.step(n - b.steps_done)
+        same(a, b, f"{name} T={T} step {n}", kw.get("both_tips", False))
+    b.timing(False)
+    sa, sb = a.time_block_stats(), b.time_block_stats()
+    say(f"  in flight: {sa}; one at a time: {sb}")
+    assert sa["reruns"] > 0 and sb["reruns"] > 0
+
+
 @pytest.mark.parametrize("T", [2, 6, 8])
 @pytest.mark.parametrize("storage", ["f16s", "bf16s"])
 def test_time_blocked_sweep_under_the_K_criterion_16bit_against_the_oracle(storage, T):
