@@ -1712,6 +1712,13 @@ struct lbm_batch {
   bool eq = false;     // equilibrium layout (same for every plate)
   int full_steps = 0;  // five-plane steps still to run (see lbm_handle)
   int device = 0;      // the GPU the batch's memory is on (current at lbm_batch_init)
+  // fold: every plate that has a crack step has its crack along +x, so the
+  // sweep of step n + 1 runs the crack steps of step n (as a single plate's
+  // one-step sweeps do); crack_deferred and cslot as in lbm_handle.  Between
+  // calls nothing is deferred and every state is in slot 0.
+  bool fold = false;
+  bool crack_deferred = false;
+  int cslot = 0;
 };
 
 namespace {
@@ -1797,7 +1804,16 @@ int batch_build_desc(lbm_batch *b) {
     ti += lbmk::core::interior_task_count(d.im);
     tb += lbmk::core::boundary_task_count(d.bm);
     d.crack = crack_args(h);
+    d.st2 = h->crack_slot(1);
+    for (int c = 0; c < 2; ++c)
+      for (int k2 = 0; k2 < 2; ++k2) d.fargs[2 * c + k2] = h->fused_args(c, k2);
   }
+  bool any = false, all = true;
+  for (const lbm_handle *h : b->plates) {
+    any |= h->crack_step_needed();
+    all &= !h->crack_step_needed() || h->fold_crack();
+  }
+  b->fold = any && all;
   b->n_int = ti;
   b->n_bnd = tb;
   HIP_TRY(hipMemcpyAsync(b->base + b->off_desc, b->desc.data(), sizeof(lbmk::BatchPlate) * n,
@@ -1902,6 +1918,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
   if (!b) return fail(LBM_EINVAL, "null batch");
   if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
   const auto *d = reinterpret_cast<const lbmk::BatchPlate *>(b->base + b->off_desc);
+  const int n = (int)b->plates.size();
   const int lds = batch_lds(b);
   for (int64_t k = 0; k < nsteps; ++k) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1910,17 +1927,27 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
         return fail(LBM_EHIP, "event creation failed");
       HIP_TRY(hipEventRecord(e0, b->stream));
     }
-    HIP_TRY(lbmk::launch_batch_step(b->store, b->sr, b->eq && b->full_steps == 0, d,
-                                    (int)b->plates.size(), b->n_int, b->n_bnd, b->cur, b->step,
-                                    b->waves, lds, b->stream));
+    // with fold: this sweep runs the crack steps of the step before it (if
+    // deferred) and leaves its own to the next sweep or to the launch after
+    // the call's last step
+    const int slot = b->fold && b->crack_deferred ? b->cslot : -1;
+    HIP_TRY(lbmk::launch_batch_sweep(b->store, b->sr, b->eq && b->full_steps == 0, d, n, b->n_int,
+                                     b->n_bnd, b->cur, b->step, b->waves, lds, slot, b->stream));
+    if (slot >= 0) b->cslot = 1 - b->cslot;
+    b->cur = 1 - b->cur;
+    b->step++;
+    if (b->full_steps > 0) b->full_steps--;
+    if (b->fold) b->crack_deferred = true;
+    if (!b->fold || k + 1 == nsteps) {
+      HIP_TRY(lbmk::launch_batch_crack(d, n, b->cur, b->cslot, b->stream));
+      b->crack_deferred = false;
+      b->cslot = 0;
+    }
     if (b->timing) {
       HIP_TRY(hipEventRecord(e1, b->stream));
       b->ev_used.push_back(e0);
       b->ev_used.push_back(e1);
     }
-    b->cur = 1 - b->cur;
-    b->step++;
-    if (b->full_steps > 0) b->full_steps--;
   }
   batch_sync_handles(b);
   return LBM_OK;

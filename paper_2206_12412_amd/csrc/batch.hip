@@ -8,7 +8,9 @@
 //
 // Two ways to run a step:
 //   per-step launches: one batched sweep kernel (boundary and interior tasks
-//     of all plates) and one batched crack kernel (one wavefront per plate);
+//     of all plates) and one batched crack kernel (one wavefront per plate),
+//     or, when every plate's crack runs along +x, the crack step of step n
+//     folded into the sweep of step n + 1 and one crack launch at the end;
 //   persistent: one cooperative launch runs many steps; every wave walks the
 //     task list with a grid stride, and two grid barriers per step separate
 //     the sweep from the crack step and the crack step from the next sweep.
@@ -136,9 +138,14 @@ __device__ __forceinline__ void interior_task(const BatchPlate *__restrict__ d, 
   core::interior_rows<S, W, C, VEC, SHIFT, SR, EQ>(a.fin, a.fout, a.win, a.wout, a, strip, jb, jlast);
 }
 
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
+// crack state slot k of plate q
+__device__ __forceinline__ DevCrack *crack_slot(const BatchPlate &q, int k) {
+  return k ? q.st2 : q.crack.st;
+}
+
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ, bool FUSED>
 __device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, int n, int64_t task,
-                                              int cur, int64_t step) {
+                                              int cur, int64_t step, int slot) {
   const int k = plate_of(d, n, task, false);
   const BatchPlate &q = d[k];
   const int64_t local = task - q.btask0;
@@ -146,27 +153,51 @@ __device__ __forceinline__ void boundary_task(const BatchPlate *__restrict__ d, 
   const int r = (int)(local / q.bm.n_strips);
   const int j = core::boundary_row_of(q.bm, r);
   const SweepArgs<S, W, C> a = args_of<S, W, C>(q, cur, step);
+  core::CutForecast cf;
+  if (FUSED && (j == q.p.j0 || j == q.p.j0 + 1) && q.crack.c.crack) {
+    // the links the folded crack step severs (it runs on the source w)
+    const CrackArgs &fc = *q.fargs[2 * cur + slot];
+    cf.row = q.p.j0;
+    core::crack_cut_columns(fc, *fc.st, threadIdx.x & 63, &cf.lo_r, &cf.hi_r, &cf.lo_l, &cf.hi_l);
+  }
   core::boundary_row<S, W, C, VEC, SHIFT, SR, EQ>(a.fin, a.fout, a.win, a.wout, a.mV, a.mH, a.mrows, a,
-                                         strip, j);
+                                                  strip, j, cf);
 }
 
-__device__ __forceinline__ void crack_task(const BatchPlate *__restrict__ d, int k, int cur) {
+// The crack step of plate k on w buffer wbuf, from the state in slot `in`
+// into slot `out`.
+__device__ __forceinline__ void crack_task(const BatchPlate *__restrict__ d, int k, int wbuf, int in,
+                                           int out) {
   if (!d[k].has_crack && d[k].crack.n_sens == 0) return;
   CrackArgs c = d[k].crack;
-  c.w = d[k].w[1 - cur];  // w after the sweep of this step
+  c.w = d[k].w[wbuf];
+  c.st = crack_slot(d[k], in);
+  c.st_out = out == in ? nullptr : crack_slot(d[k], out);
   core::crack_step_wave(c);
 }
 
 // One launch per step for the sweep of every plate: the first `nbb`
-// workgroups take the boundary tasks, the rest the interior tasks.
-template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
-__global__ void __launch_bounds__(512)
+// workgroups take the boundary tasks, the rest the interior tasks.  FUSED:
+// after the boundary tasks one wave per plate runs the crack step of the
+// previous step (on the source w, state slot `slot` into the other slot),
+// and the crack-row tasks forecast the links it severs, as the single-plate
+// sweep does; its equilibrium-layout forms keep the occupancy of the plain
+// ones (eight waves per SIMD).
+template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ, bool FUSED>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((FUSED && EQ) ? 8 : 1)))
 batch_step(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t n_bnd, unsigned nbb,
-           int cur, int64_t step, int waves) {
+           int cur, int64_t step, int waves, int slot) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (blockIdx.x < nbb) {
     const int64_t task = (int64_t)blockIdx.x * waves + wave;
-    if (task < n_bnd) boundary_task<S, W, C, VEC, SHIFT, SR, EQ>(d, n, task, cur, step);
+    if (task < n_bnd) {
+      boundary_task<S, W, C, VEC, SHIFT, SR, EQ, FUSED>(d, n, task, cur, step, slot);
+    } else if constexpr (FUSED) {
+      if (task < n_bnd + n) {  // a crack along +x, or none
+        const BatchPlate &q = d[task - n_bnd];
+        if (q.has_crack || q.crack.n_sens > 0) core::crack_step_wave<false>(*q.fargs[2 * cur + slot]);
+      }
+    }
     return;
   }
   const int64_t task = (int64_t)(blockIdx.x - nbb) * waves + wave;
@@ -174,10 +205,11 @@ batch_step(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t n_bnd
   interior_task<S, W, C, VEC, SHIFT, SR, EQ>(d, n, task, cur, step);
 }
 
-__global__ void __launch_bounds__(256) batch_crack(const BatchPlate *__restrict__ d, int n, int cur) {
+__global__ void __launch_bounds__(256) batch_crack(const BatchPlate *__restrict__ d, int n, int wbuf,
+                                                   int slot) {
   const int k = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (k >= n) return;
-  crack_task(d, k, cur);
+  crack_task(d, k, wbuf, slot, 0);
 }
 
 // Grid-wide barrier on three words, each on its own 128-byte line so that the
@@ -232,23 +264,27 @@ batch_persistent(const BatchPlate *__restrict__ d, int n, int64_t n_int, int64_t
     const int64_t step = step0 + s;
     for (int64_t t = gw; t < n_int + n_bnd; t += nw) {
       if (t < n_int) interior_task<S, W, C, VEC, SHIFT, SR, EQ>(d, n, t, cur, step);
-      else boundary_task<S, W, C, VEC, SHIFT, SR, EQ>(d, n, t - n_int, cur, step);
+      else boundary_task<S, W, C, VEC, SHIFT, SR, EQ, false>(d, n, t - n_int, cur, step, 0);
     }
     grid_barrier(sync, gridDim.x);
-    for (int64_t k = gw; k < n; k += nw) crack_task(d, (int)k, cur);
+    for (int64_t k = gw; k < n; k += nw) crack_task(d, (int)k, 1 - cur, 0, 0);
     grid_barrier(sync, gridDim.x);
   }
 }
 
 template <typename S, typename W, typename C, int VEC, bool SHIFT, bool SR, bool EQ>
 hipError_t step_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur, int64_t step,
-                  int waves, int lds, hipStream_t st) {
-  const unsigned nbb = (unsigned)((n_bnd + waves - 1) / waves);
+                  int waves, int lds, int slot, hipStream_t st) {
+  const int64_t btasks = n_bnd + (slot >= 0 ? n : 0);
+  const unsigned nbb = (unsigned)((btasks + waves - 1) / waves);
   const unsigned nib = (unsigned)((n_int + waves - 1) / waves);
-  if (nbb + nib > 0)
-    hipLaunchKernelGGL((batch_step<S, W, C, VEC, SHIFT, SR, EQ>), dim3(nbb + nib), dim3(64 * waves), lds,
-                       st, d, n, n_int, n_bnd, nbb, cur, step, waves);
-  hipLaunchKernelGGL(batch_crack, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, d, n, cur);
+  if (nbb + nib == 0) return hipSuccess;
+  if (slot >= 0)
+    hipLaunchKernelGGL((batch_step<S, W, C, VEC, SHIFT, SR, EQ, true>), dim3(nbb + nib),
+                       dim3(64 * waves), lds, st, d, n, n_int, n_bnd, nbb, cur, step, waves, slot);
+  else
+    hipLaunchKernelGGL((batch_step<S, W, C, VEC, SHIFT, SR, EQ, false>), dim3(nbb + nib),
+                       dim3(64 * waves), lds, st, d, n, n_int, n_bnd, nbb, cur, step, waves, 0);
   return hipGetLastError();
 }
 
@@ -293,22 +329,22 @@ hipError_t persistent_t(const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd
 // layout (eq) for the shifted storages only
 template <typename S, typename W, typename C, int VEC, bool SHIFT, bool EQ>
 hipError_t step_e(int sr, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd, int cur,
-                  int64_t step, int waves, int lds, hipStream_t st) {
+                  int64_t step, int waves, int lds, int slot, hipStream_t st) {
   if constexpr (sizeof(S) == 2) {
-    if (sr) return step_t<S, W, C, VEC, SHIFT, true, EQ>(d, n, n_int, n_bnd, cur, step, waves, lds, st);
+    if (sr) return step_t<S, W, C, VEC, SHIFT, true, EQ>(d, n, n_int, n_bnd, cur, step, waves, lds, slot, st);
   }
-  return step_t<S, W, C, VEC, SHIFT, false, EQ>(d, n, n_int, n_bnd, cur, step, waves, lds, st);
+  return step_t<S, W, C, VEC, SHIFT, false, EQ>(d, n, n_int, n_bnd, cur, step, waves, lds, slot, st);
 }
 
 template <typename S, typename W, typename C, int VEC, bool SHIFT>
 hipError_t step_r(int sr, bool eq, const BatchPlate *d, int n, int64_t n_int, int64_t n_bnd,
-                  int cur, int64_t step, int waves, int lds, hipStream_t st) {
+                  int cur, int64_t step, int waves, int lds, int slot, hipStream_t st) {
   if constexpr (SHIFT) {
-    if (eq) return step_e<S, W, C, VEC, SHIFT, true>(sr, d, n, n_int, n_bnd, cur, step, waves, lds, st);
+    if (eq) return step_e<S, W, C, VEC, SHIFT, true>(sr, d, n, n_int, n_bnd, cur, step, waves, lds, slot, st);
   } else {
     if (eq) return hipErrorInvalidValue;
   }
-  return step_e<S, W, C, VEC, SHIFT, false>(sr, d, n, n_int, n_bnd, cur, step, waves, lds, st);
+  return step_e<S, W, C, VEC, SHIFT, false>(sr, d, n, n_int, n_bnd, cur, step, waves, lds, slot, st);
 }
 
 template <typename S, typename W, typename C, int VEC, bool SHIFT, bool EQ>
@@ -341,19 +377,29 @@ hipError_t persistent_r(int sr, bool eq, const BatchPlate *d, int n, int64_t n_i
 
 }  // namespace
 
-hipError_t launch_batch_step(Store s, int sr, bool eq, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
-                             int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
-                             hipStream_t st) {
+hipError_t launch_batch_sweep(Store s, int sr, bool eq, const BatchPlate *d, int n_plates,
+                              int64_t n_int_tasks, int64_t n_bnd_tasks, int cur, int64_t step,
+                              int waves, int lds_bytes, int fused_slot, hipStream_t st) {
+  const int n = n_plates;
+  const int64_t ni = n_int_tasks, nb = n_bnd_tasks;
+  const int fs = fused_slot < 0 ? -1 : (fused_slot & 1);
   switch (s) {
     // shifted FP64 exists only in the equilibrium layout
-    case Store::F64S: return eq ? step_e<double, double, double, 2, true, true>(sr, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st) : hipErrorInvalidValue;
-    case Store::F64: return step_r<double, double, double, 2, false>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F32_PLAIN: return step_r<float, float, float, 4, false>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F32S: return step_r<float, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::F16S: return step_r<_Float16, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
-    case Store::BF16S: return step_r<__bf16, float, float, 4, true>(sr, eq, d, n_plates, n_int_tasks, n_bnd_tasks, cur, step, waves, lds_bytes, st);
+    case Store::F64S: return eq ? step_e<double, double, double, 2, true, true>(sr, d, n, ni, nb, cur, step, waves, lds_bytes, fs, st) : hipErrorInvalidValue;
+    case Store::F64: return step_r<double, double, double, 2, false>(sr, eq, d, n, ni, nb, cur, step, waves, lds_bytes, fs, st);
+    case Store::F32_PLAIN: return step_r<float, float, float, 4, false>(sr, eq, d, n, ni, nb, cur, step, waves, lds_bytes, fs, st);
+    case Store::F32S: return step_r<float, float, float, 4, true>(sr, eq, d, n, ni, nb, cur, step, waves, lds_bytes, fs, st);
+    case Store::F16S: return step_r<_Float16, float, float, 4, true>(sr, eq, d, n, ni, nb, cur, step, waves, lds_bytes, fs, st);
+    case Store::BF16S: return step_r<__bf16, float, float, 4, true>(sr, eq, d, n, ni, nb, cur, step, waves, lds_bytes, fs, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_crack(const BatchPlate *d, int n_plates, int wbuf, int slot, hipStream_t st) {
+  if (n_plates < 1) return hipSuccess;
+  hipLaunchKernelGGL(batch_crack, dim3((unsigned)((n_plates + 3) / 4)), dim3(256), 0, st, d, n_plates,
+                     wbuf & 1, slot & 1);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_persistent(Store s, int sr, bool eq, const BatchPlate *d, int n_plates,

@@ -247,6 +247,10 @@ struct BatchPlate {
   core::BoundaryMap bm;
   int64_t itask0, btask0;  // first interior / boundary task of this plate in the batch
   CrackArgs crack;      // w is set per step from the parity
+  DevCrack *st2;        // the second crack-state slot (crack.st is the first)
+  // device arguments of a crack step folded into a sweep, [2 * cur + slot]:
+  // w in buffer cur, state in slot `slot`, going to the other slot
+  const CrackArgs *fargs[4];
 };
 
 // Per-sweep arguments of the adjoint (adjoint.hip).  C is the adjoint's
@@ -365,11 +369,18 @@ hipError_t launch_init_mask(uint32_t *mV, uint32_t *mH, MaskRows *mrows, const P
                             int has_crack, double x0, double a0, hipStream_t st);
 
 // ---- launchers (batch.hip) ----
-// One step of every plate: batched sweep kernel (boundary and interior tasks),
-// batched crack kernel.  cur = parity of the source buffers, step = step index.
-hipError_t launch_batch_step(Store s, int sr, bool eq, const BatchPlate *d, int n_plates, int64_t n_int_tasks,
-                             int64_t n_bnd_tasks, int cur, int64_t step, int waves, int lds_bytes,
-                             hipStream_t st);
+// The sweep of one step of every plate (boundary and interior tasks).  cur =
+// parity of the source buffers, step = step index.  fused_slot >= 0 folds in
+// the crack step of the step before (every plate's crack along +x, or none):
+// one wave per plate runs it on the source w from its state in that slot
+// (0: crack.st, 1: st2) into the other slot, and the crack-row tasks forecast
+// the links it severs.  fused_slot < 0: the sweep alone.
+hipError_t launch_batch_sweep(Store s, int sr, bool eq, const BatchPlate *d, int n_plates,
+                              int64_t n_int_tasks, int64_t n_bnd_tasks, int cur, int64_t step,
+                              int waves, int lds_bytes, int fused_slot, hipStream_t st);
+// The crack step of every plate, one wave each, on w buffer wbuf, from the
+// state in slot `slot` into slot 0.
+hipError_t launch_batch_crack(const BatchPlate *d, int n_plates, int wbuf, int slot, hipStream_t st);
 // nsteps steps in one cooperative launch with grid barriers; sync is a
 // zeroed 512-byte device scratch (barrier counter, generation and time-out
 // flag at words 0, 32 and 64).  Returns hipErrorCooperativeLaunchTooLarge if

@@ -5,7 +5,8 @@ links it severs from the same state and field), and lbm_step ends with that
 call's last crack step in a launch of its own.  A plate stepped N steps in one
 call therefore takes the fused path N - 1 times, the same plate stepped one
 step per call never: the two must agree bit for bit, fields, traces, cut
-events and sensor traces included."""
+events and sensor traces included.  Batched plates fold their crack steps the
+same way when every plate's crack runs along +x (or it has none)."""
 import sys
 
 import numpy as np
@@ -19,7 +20,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2206_12412_amd import Config, Solver  # noqa: E402
+from paper_2206_12412_amd import Batch, Config, Solver  # noqa: E402
 
 
 def say(msg):
@@ -132,3 +133,26 @@ def test_calls_of_mixed_lengths_and_a_checkpoint_in_between():
     b.restore(ck)
     b.step(100)
     same(a, b, "mixed", a.cfg)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32-eq", "f16s-sr", "bf16s-sr-eq"])
+def test_batched_fused_crack_steps_equal_separate_crack_launches(storage):
+    """A batch of the plates above (and one plate with no crack step at all)
+    stepped N steps in one call folds N - 1 crack steps of every plate into
+    the next batched sweep; stepped one step per call it folds none."""
+    steps = 120
+    kw = cases(steps)
+    cfgs = [make(storage, **kw[c]) for c in ("prescribed", "from-nothing", "sif", "two-tips",
+                                              "sensors-only")]
+    cfgs.append(make(storage, nx=70, ny=20, tau_hist=np.array([1e-3])))
+    say(f"batched fused crack step: {storage}, {len(cfgs)} plates, {steps} steps")
+    a = Batch(cfgs)
+    b = Batch(cfgs)
+    for n in (1, steps - 41, 40):  # the first call steps one step alone
+        a.step(n)
+    for _ in range(steps):
+        b.step(1)
+    for k, c in enumerate(cfgs):
+        same(a.plates[k], b.plates[k], f"{storage} plate {k}", c)
+        if c.has_crack and c.growth == 1:
+            assert len(a.plates[k].cut_events()) > 0
