@@ -192,7 +192,8 @@ size_t lbm_state_bytes(const lbm_config *cfg);
 
 /* Validate cfg, lay the state out in cfg->dev_buf and enqueue its
  * initialisation on cfg->stream: f = f_eq(w0, wdot0), w = w0, the links
- * severed by the initial crack segment (Alg. 1 "as for the initial crack").
+ * severed by the initial crack segment (Sec. 4.1 severs them the same way as
+ * those a growing tip crosses).
  * Returns LBM_EINVAL / LBM_EUNSTABLE / LBM_ECRACK / LBM_ENOMEM without
  * touching the GPU when cfg is unusable. */
 int lbm_init(const lbm_config *cfg, lbm_handle **out);
