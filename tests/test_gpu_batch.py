@@ -25,7 +25,10 @@ def say(msg):
 
 def plate_configs(storage, steps, small=True):
     """Uneven plates: sizes, loads, prescribed speeds and the K criterion.  A
-    storage ending in "-sr" selects stochastic rounding (one seed per plate)."""
+    storage ending in "-eq" selects the equilibrium layout, then "-sr"
+    stochastic rounding (one seed per plate)."""
+    layout = "eq" if storage.endswith("-eq") else "full"
+    storage = storage[:-3] if storage.endswith("-eq") else storage
     rounding = "stochastic" if storage.endswith("-sr") else "nearest"
     storage = storage[:-3] if storage.endswith("-sr") else storage
     rng = np.random.default_rng(5)
@@ -35,7 +38,7 @@ def plate_configs(storage, steps, small=True):
     for k, (nx, ny) in enumerate(sizes):
         ell = max(nx // 4, 1)
         tau = float(rng.uniform(5e-4, 2e-3))
-        c = Config(nx=nx, ny=ny, storage=storage, rounding=rounding, seed=100 + k,
+        c = Config(nx=nx, ny=ny, storage=storage, rounding=rounding, layout=layout, seed=100 + k,
                    has_crack=True, crack_tip=ell - 0.5,
                    tau_hist=np.array([tau]), trace_cap=steps,
                    wdot0=rng.normal(0, 1e-4, (ny, nx)))
@@ -48,13 +51,15 @@ def plate_configs(storage, steps, small=True):
     n = np.arange(steps)
     wD = np.zeros((max(steps, 1), 4))
     wD[:, 1] = 0.01 * np.sin(np.pi * np.arange(wD.shape[0]) / 60.0)
-    cfgs.append(Config(nx=150, ny=40, storage=storage, rounding=rounding, seed=99, has_crack=True,
+    cfgs.append(Config(nx=150, ny=40, storage=storage, rounding=rounding, layout=layout, seed=99,
+                       has_crack=True,
                        crack_row=12, crack_x0=60.5, crack_tip=80.5, both_tips=True, growth=1,
                        v_rel=0.45, dirichlet=1 | 2, wD_hist=wD, trace_cap=steps,
                        wdot0=rng.normal(0, 1e-4, (40, 150))))
     # one plate without a crack and one periodic plate
-    cfgs.append(Config(nx=70, ny=20, storage=storage, rounding=rounding, tau_hist=np.array([1e-3])))
-    cfgs.append(Config(nx=80, ny=24, storage=storage, rounding=rounding, periodic=True,
+    cfgs.append(Config(nx=70, ny=20, storage=storage, rounding=rounding, layout=layout,
+                       tau_hist=np.array([1e-3])))
+    cfgs.append(Config(nx=80, ny=24, storage=storage, rounding=rounding, layout=layout, periodic=True,
                        wdot0=rng.normal(0, 1e-3, (24, 80))))
     return cfgs
 
@@ -102,8 +107,11 @@ def test_batch_launch_shapes_do_not_change_results():
         same_state(a.plates[k], b.plates[k], f"plate {k}")
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64", "bf16s-sr"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "bf16s-sr", "f32-eq", "f64-eq", "f16s-sr-eq"])
 def test_persistent_run_equals_per_step_launches(storage):
+    """In the equilibrium layout the persistent kernel takes interior tasks of
+    its own height (loads of the next rows in flight); the plates include
+    ragged widths and heights below and above that height."""
     cfgs = plate_configs(storage, 200)
     say(f"persistent batch, {storage}: 2 steps first")
     a = Batch(cfgs)
