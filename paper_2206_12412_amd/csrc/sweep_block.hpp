@@ -24,6 +24,13 @@
 // the rows after step n + k - 1; level k computes row r - k when state row r
 // arrives.  x-neighbours move between lanes with DPP; the plate edges and the
 // severed links are handled per site as in the one-step sweep.
+//
+// Three launches: the fast chunks (rows away from the plate's top and bottom
+// and the crack rows) of the strips without a plate edge, with only the
+// interior arithmetic compiled in; the slow chunk rows of every strip, with
+// the general march; the other chunks of the strips with a plate edge, whose
+// march adds the left and right edge treatment to the fast one.  The last two
+// run on a side stream beside the first.
 #pragma once
 
 #include "crack_core.hpp"
@@ -104,11 +111,18 @@ __device__ __forceinline__ void step_row(const SweepArgs<S, W, C> &a, const Step
   const int last = p.nx - 1;
   const C wL = lane_prev(wc[VEC - 1]);
   const C wR = lane_next(wc[0]);
-  if (!edge_row && !edge_strip) {
+  if (!edge_row) {
+    // every vertical link intact and no traction: the interior arithmetic,
+    // with the neighbour beyond a left or right plate edge replaced (the
+    // site itself for bounce-back, 2 w* - w for a Dirichlet edge)
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
-      const C wl = (k == 0) ? wL : wc[k - 1];
-      const C wr = (k == VEC - 1) ? wR : wc[k + 1];
+      C wl = (k == 0) ? wL : wc[k - 1];
+      C wr = (k == VEC - 1) ? wR : wc[k + 1];
+      if (edge_strip) {
+        if (i0 + k == 0) wl = (a.dmask & core::kEdgeLeft) ? C(2) * L.wD_left - wc[k] : wc[k];
+        if (i0 + k == last) wr = (a.dmask & core::kEdgeRight) ? C(2) * L.wD_right - wc[k] : wc[k];
+      }
       C o1, o2, o3, o4;
       core::site_update<C, true, true>(a, g[k], C(0), C(0), C(0), C(0), wc[k], wl, wr, wm[k], wp[k],
                                        false, false, C(0), C(0), g_out[k], o1, o2, o3, o4, w_out[k]);
@@ -160,16 +174,21 @@ __device__ __forceinline__ uint32_t range_bits(int i0, int lo, int hi) {
 // every row the wave loads lies in the plate, none of the rows it steps is an
 // edge or crack row, and its columns hold no plate edge, so every lane loads,
 // no row needs a range check and every site takes the interior arithmetic.
-template <typename S, typename W, typename C, int VEC, bool SR, int R, int T, bool FAST>
+// XEDGE: the rows as for FAST, but the columns may hold a plate edge (lanes
+// outside the plate, the left and right edge treatment).
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int T, bool FAST,
+          bool XEDGE = false>
 __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int strip, const int jb,
                                       const int lane, const bool edge_strip) {
+  static_assert(!(FAST && XEDGE), "FAST columns hold no plate edge");
+  constexpr bool ROWS = FAST || XEDGE;  // the rows of a fast chunk
   constexpr int H = (T + VEC - 1) / VEC;  // halo lanes on either side
   constexpr int OW = (64 - 2 * H) * VEC;  // owned columns of a strip
   constexpr int NR = R + 2 * T;           // state rows loaded
   constexpr int D = NR < 6 ? NR : 6;      // rows loaded ahead of their first use
   const SweepArgs<S, W, C> &a = A.s0;
   const Plate p = a.p;
-  const int je = FAST ? jb + R : min(jb + R, p.ny);  // rows jb .. je - 1 are finished here
+  const int je = ROWS ? jb + R : min(jb + R, p.ny);  // rows jb .. je - 1 are finished here
   const int i0 = strip * OW - H * VEC + lane * VEC;  // first site of this lane (may be < 0)
   const bool inplate = FAST || ((uint32_t)i0 < (uint32_t)p.nx);
   // (one unsigned compare and a bitwise and: no branch)
@@ -189,7 +208,7 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
   uint32_t cut[T];
 #pragma unroll
   for (int k = 0; k < T; ++k) cut[k] = 0u;
-  if (!FAST && A.crack) {
+  if (!ROWS && A.crack) {
     if (loadable && i0 < p.nx)
       cut[0] = (a.mV[(size_t)p.j0 * p.mw + (il >> 5)] >> (il & 31)) & ((1u << VEC) - 1u);
 #pragma unroll
@@ -232,17 +251,20 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
   // state rows in the storage types, D of them in flight ahead of their use:
   // on this hardware a wait for a load also waits for every store issued
   // before it, so each load is issued D rows before the stores it must not
-  // wait for.  In a fast march of more than 28 rows, row rr goes to slot
+  // wait for.  In a march of more than 28 fast-chunk rows, row rr goes to slot
   // rr % 8 (an array of NR rows was kept in scratch memory for NR = 44 and
   // more); elsewhere each row has its own (with slots the boundary launch
   // took 45 % longer).
-  constexpr int RING = (FAST && NR > 28) ? 8 : NR;
+  constexpr int RING = (ROWS && NR > 28) ? 8 : NR;
   static_assert(D < RING || RING == NR, "a slot is reused only after its row was taken");
   W wl_[RING][VEC];
   S gl_[RING][VEC];
   auto load = [&](int rr) {
     const int r = jb - T + rr;
-    if (FAST || (r >= 0 && r < p.ny && r <= je + T - 1 && loadable)) {
+    // (XEDGE: the lanes outside the row load its first columns instead; no
+    // site of the plate reads them, the edge treatment replaces its
+    // neighbours beyond an edge)
+    if (ROWS || (r >= 0 && r < p.ny && r <= je + T - 1 && loadable)) {
       const uint32_t o = (uint32_t)r * pitch + il;
       load_raw<W, VEC>(a.win, o, wl_[rr % RING]);
       load_raw<S, VEC>(a.fin, o, gl_[rr % RING]);
@@ -271,7 +293,7 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
 #pragma unroll
   for (int rr = 0; rr < NR; ++rr) {
     const int r = jb - T + rr;
-    if (!FAST && r > je + T - 1) break;
+    if (!ROWS && r > je + T - 1) break;
     if (rr + D < NR) load(rr + D);
     // level 0: the state rows r - 2, r - 1, r
 #pragma unroll
@@ -285,9 +307,10 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
 #pragma unroll
     for (int lv = 1; lv <= T; ++lv) {
       const int q = r - lv;  // the row level lv computes now
-      const bool valid = rr >= 2 * lv && (FAST || (q >= 0 && q < p.ny));
-      const bool er = !FAST && (q == 0 || q == p.ny - 1 || q == jc || q == jc + 1);
-      const uint32_t cu = q == jc ? cut[lv - 1] : 0u, cd = q == jc + 1 ? cut[lv - 1] : 0u;
+      const bool valid = rr >= 2 * lv && (ROWS || (q >= 0 && q < p.ny));
+      const bool er = !ROWS && (q == 0 || q == p.ny - 1 || q == jc || q == jc + 1);
+      const uint32_t cu = (!ROWS && q == jc) ? cut[lv - 1] : 0u;
+      const uint32_t cd = (!ROWS && q == jc + 1) ? cut[lv - 1] : 0u;
       C g2[VEC], w2[VEC];
       if (valid) {
         step_row<S, W, C, VEC>(a, A.lv[lv - 1], q, i0, wv[lv - 1][2], wv[lv - 1][1], wv[lv - 1][0],
@@ -298,7 +321,7 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
       }
       if (lv < T) {
         // w of the crack rows after step n + lv - 1, for its crack step
-        if (!FAST && valid && own && (q == jc || q == jc + 1) && q >= jb && q < je)
+        if (!ROWS && valid && own && (q == jc || q == jc + 1) && q >= jb && q < je)
           core::store_row<W, C, VEC>(A.wmid, (uint32_t)(2 * (lv - 1) + q - jc) * pitch + il, w2);
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
@@ -308,7 +331,7 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
           gv[lv][1][k] = gv[lv][0][k];
           gv[lv][0][k] = g2[k];
         }
-      } else if (rr >= 2 * T && (FAST || q < je)) {
+      } else if (rr >= 2 * T && (ROWS || q < je)) {
         // the last level: rows jb .. je - 1, stored
         if (!FAST && i0 + VEC - 1 > p.nx - 1) {
 #pragma unroll
@@ -419,30 +442,46 @@ sweep_block_tall(const BlockArgs<S, W, C> A, const int s_lo, const int s_hi, con
   march<S, W, C, VEC, SR, RF, T, true>(A, strip, c * R, lane, false);
 }
 
-// The boundary launch: every chunk of the strips with a plate edge (strips
-// below s_lo and from s_hi on), then the slow chunk rows of the other strips.
+// The boundary launch: the slow chunk rows (the first and last ones, those
+// around the crack rows, and the fast ones a run of the fast launch leaves
+// over) of every strip.
 template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
 __global__ void __launch_bounds__(256)
-sweep_block_edges(const BlockArgs<S, W, C> A, const int n_strips, const int s_lo, const int s_hi,
+sweep_block_edges(const BlockArgs<S, W, C> A, const int n_strips, const SlowChunks sc) {
+  if (A.gate && *A.gate == 0) return;
+  const Plate p = A.s0.p;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int task = (int)(blockIdx.x * (blockDim.x >> 6)) + wave;
+  if (task >= n_strips * sc.n) return;
+  const int strip = task % n_strips;
+  const int chunk = sc.c[task / n_strips];
+  march<S, W, C, VEC, SR, R, T, false>(A, strip, chunk * R, lane, edge_strip_of<VEC, T>(strip, p.nx));
+}
+
+// The edge-column launch: the other chunk rows of the strips with a plate
+// edge (strips below s_lo and from s_hi on), whose rows are those of a fast
+// chunk: the march needs the left and right edge treatment and range checks
+// on its columns only.  (In the boundary launch these chunks took most of its
+// time: its general march keeps about 180 registers and spills.)
+template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
+__global__ void __launch_bounds__(512)
+sweep_block_xedge(const BlockArgs<S, W, C> A, const int n_strips, const int s_lo, const int s_hi,
                   const int n_chunks, const SlowChunks sc) {
   if (A.gate && *A.gate == 0) return;
   const Plate p = A.s0.p;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int task = (int)(blockIdx.x * (blockDim.x >> 6)) + wave;
-  const int n_int = s_hi - s_lo, n_edge = n_strips - n_int;
-  int strip, chunk;
-  if (task < n_edge * n_chunks) {
-    const int e = task % n_edge;
-    strip = e < s_lo ? e : s_hi + (e - s_lo);
-    chunk = task / n_edge;
-  } else {
-    const int t = task - n_edge * n_chunks;
-    if (t >= n_int * sc.n) return;
-    strip = s_lo + t % n_int;
-    chunk = sc.c[t / n_int];
-  }
-  march<S, W, C, VEC, SR, R, T, false>(A, strip, chunk * R, lane, edge_strip_of<VEC, T>(strip, p.nx));
+  const int n_edge = n_strips - (s_hi - s_lo);
+  if (task >= n_edge * n_chunks) return;
+  const int e = task % n_edge;
+  const int strip = e < s_lo ? e : s_hi + (e - s_lo);
+  const int chunk = task / n_edge;
+  if (!fast_rows<R, T>(chunk * R, p.ny, A.crack ? p.j0 : -2)) return;
+  for (int k = 0; k < sc.n; ++k)
+    if (sc.c[k] == chunk) return;  // the boundary launch takes it
+  march<S, W, C, VEC, SR, R, T, false, true>(A, strip, chunk * R, lane, true);
 }
 
 // RF: rows per wave of the fast launch, R (sweep_block) or a multiple of R
@@ -510,12 +549,14 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
     }
   }
   if (!ok) return hipErrorInvalidValue;
-  // the boundary launch goes first, on the side stream, so that its few
-  // long waves run beside the fast launch instead of after it (always there
-  // when a side stream exists: the crack steps of the previous sweep may
-  // still run on it, and only the boundary launch reads what they write)
-  const long etasks = (long)(n_strips - (s_hi - s_lo)) * n_chunks + (long)(s_hi - s_lo) * sc.n;
-  const bool fork = ss.side != nullptr && etasks > 0;
+  // the boundary and edge-column launches go first, on the side stream, so
+  // that their few long waves run beside the fast launch instead of after it
+  // (always there when a side stream exists: the crack steps of the previous
+  // sweep may still run on it, and only the boundary launch reads what they
+  // write)
+  const long etasks = (long)n_strips * sc.n;
+  const long xtasks = (long)(n_strips - (s_hi - s_lo)) * n_chunks;
+  const bool fork = ss.side != nullptr && etasks + xtasks > 0;
   hipStream_t est = fork ? ss.side : st;
   if (fork) {
     hipError_t e = hipEventRecord(ss.fork, st);
@@ -525,6 +566,13 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
   if (etasks > 0) {
     const unsigned blocks = (unsigned)((etasks + 3) / 4);
     hipLaunchKernelGGL((sweep_block_edges<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(256), 0, est,
+                       A, n_strips, sc);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (xtasks > 0) {
+    const unsigned blocks = (unsigned)((xtasks + 3) / 4);
+    hipLaunchKernelGGL((sweep_block_xedge<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(256), 0, est,
                        A, n_strips, s_lo, s_hi, n_chunks, sc);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

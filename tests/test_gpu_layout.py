@@ -423,7 +423,7 @@ def test_time_block_autotune_picks_a_shape_and_keeps_the_results(T, name):
     out = blk.autotune_time_block(T, trial_sweeps=2)
     say(f"autotune T={T} {name}: {out}")
     assert out["steps"] == T and out["waves"] in (1, 2, 4, 8) and out["ms_per_step"] > 0
-    assert out["rows"] in ((16,) if T >= 6 else (4, 8, 16))
+    assert out["rows"] in ((16, 32) if T >= 6 else (4, 8, 16, 32))
     assert blk.steps_done == 0
     one.step(steps)
     blk.step(steps)
