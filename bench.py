@@ -542,7 +542,7 @@ def _read_csv(path):
 
 
 def _short(name: str) -> str:
-    for key in ("sweep_step", "sweep_block_edges", "sweep_block_xedge", "sweep_block_tall", "sweep_block",
+    for key in ("sweep_step", "sweep_block_edges", "sweep_block_tall", "sweep_block",
                 "crack_seq", "crack_kernel", "batch_step", "batch_crack",
                 "batch_persistent", "adj_step", "adj_inject", "adj_export", "copyBuffer", "init_rows",
                 "export_rows", "zero_kernel", "init_mask"):
@@ -610,11 +610,10 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
     The sweep is the sweep_step instantiation with the most launches (in the
     equilibrium layout the first two steps of a fresh plate run the
     five-plane instantiation, which is left out); for a time-blocked storage
-    ("-tb", "-tb3" .. "-tb8") the T-step sweep, whose three launches
+    ("-tb", "-tb3" .. "-tb8") the T-step sweep, whose two launches
     (sweep_block or sweep_block_tall over the fast chunks of the strips without
-    a plate edge, sweep_block_edges over the slow chunk rows of every strip,
-    sweep_block_xedge over the other chunks of the strips with a plate edge)
-    are summed, each the instantiation with the most launches."""
+    a plate edge, sweep_block_edges over the rest) are summed, each the
+    instantiation with the most launches."""
     import synth
     p = {"precision": synth.config_precision, "sif": synth.config_sif_fp32,
          "plain": synth.config_plain_fp64}[workload]()
@@ -627,7 +626,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, storage: str, workload: str, c
         copy = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
         factor = copy_bytes / (copy * 1024.0)
         tb = time_block(storage)
-        parts = ["sweep_block_edges", "sweep_block_xedge", "sweep_block"] if tb >= 2 else ["sweep_step"]
+        parts = ["sweep_block_edges", "sweep_block"] if tb >= 2 else ["sweep_step"]
         # the instantiations of this storage: its type, rounding, layout and T
         # (the run also times the record storage, and a run's last sweep may be
         # shorter)
@@ -910,8 +909,8 @@ def main():
     # written once per launch), not in the five-population bytes of the T
     # steps it replaces
     # (launch duration: the timed region's time per T steps, one sweep -- its
-    # fast launch, with the boundary and edge-column launches beside it, the
-    # crack steps beside the next sweep -- per T steps)
+    # fast launch, with the boundary launch beside it, the crack steps beside
+    # the next sweep -- per T steps)
     if "kernel_ms_per_launch" in head and args.storage != args.record:
         T = head["steps_per_launch"]
         alg = head["sites"] * head["bytes_per_site"] * T

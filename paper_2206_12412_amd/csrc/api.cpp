@@ -326,8 +326,7 @@ struct lbm_handle {
   // sweep, on the device current then; default priority)
   lbmk::SideStream side{nullptr, nullptr, nullptr};
   // a T-step sweep's crack steps under a prescribed speed (or none) run on
-  // the side stream right after the sweep's boundary and edge-column
-  // launches (the boundary launch writes the crack rows; the crack rows
+  // the side stream right after the sweep's boundary launch (the crack rows
   // and the side buffer of the inner steps are all they read), beside the
   // fast chunks of this sweep and the next, which read neither the crack
   // rows nor the crack state; crack_pending says the side stream holds crack
@@ -1197,9 +1196,8 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
             q.spec_mask = h->spec_mask();
           }
           if (!spec && !timed && h->side.side) {
-            // on the side stream right after the boundary and edge-column
-            // launches (the crack rows it reads are the boundary launch's):
-            // beside the rest of this sweep and the next
+            // on the side stream right after the boundary launch, whose rows
+            // are all it reads: beside the rest of this sweep and the next
             HIP_TRY(lbmk::launch_crack_seq(q, h->side.side));
             h->crack_pending = true;
           } else {

@@ -25,12 +25,12 @@
 // arrives.  x-neighbours move between lanes with DPP; the plate edges and the
 // severed links are handled per site as in the one-step sweep.
 //
-// Three launches: the fast chunks (rows away from the plate's top and bottom
+// Two launches: the fast chunks (rows away from the plate's top and bottom
 // and the crack rows) of the strips without a plate edge, with only the
-// interior arithmetic compiled in; the slow chunk rows of every strip, with
-// the general march; the other chunks of the strips with a plate edge, whose
-// march adds the left and right edge treatment to the fast one.  The last two
-// run on a side stream beside the first.
+// interior arithmetic compiled in; and, on a side stream beside it, the slow
+// chunk rows of every strip with the general march and the other chunks of
+// the strips with a plate edge, whose march adds the left and right edge
+// treatment to the fast one.
 #pragma once
 
 #include "crack_core.hpp"
@@ -442,45 +442,41 @@ sweep_block_tall(const BlockArgs<S, W, C> A, const int s_lo, const int s_hi, con
   march<S, W, C, VEC, SR, RF, T, true>(A, strip, c * R, lane, false);
 }
 
-// The boundary launch: the slow chunk rows (the first and last ones, those
-// around the crack rows, and the fast ones a run of the fast launch leaves
-// over) of every strip.
+// The boundary launch: first the slow chunk rows (the first and last ones,
+// those around the crack rows, and the fast ones a run of the fast launch
+// leaves over) of every strip, with the general march; then the other chunk
+// rows of the strips with a plate edge (strips below s_lo and from s_hi on),
+// whose rows are those of a fast chunk, so their march needs the left and
+// right edge treatment and range checks on its columns only.  (Taken by the
+// general march, these chunks held most of this launch's time: it keeps
+// about 180 registers and spills.  As a launch of their own after this one,
+// on the same side stream, they cost a launch gap on small plates.)
 template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
 __global__ void __launch_bounds__(256)
-sweep_block_edges(const BlockArgs<S, W, C> A, const int n_strips, const SlowChunks sc) {
-  if (A.gate && *A.gate == 0) return;
-  const Plate p = A.s0.p;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int task = (int)(blockIdx.x * (blockDim.x >> 6)) + wave;
-  if (task >= n_strips * sc.n) return;
-  const int strip = task % n_strips;
-  const int chunk = sc.c[task / n_strips];
-  march<S, W, C, VEC, SR, R, T, false>(A, strip, chunk * R, lane, edge_strip_of<VEC, T>(strip, p.nx));
-}
-
-// The edge-column launch: the other chunk rows of the strips with a plate
-// edge (strips below s_lo and from s_hi on), whose rows are those of a fast
-// chunk: the march needs the left and right edge treatment and range checks
-// on its columns only.  (In the boundary launch these chunks took most of its
-// time: its general march keeps about 180 registers and spills.)
-template <typename S, typename W, typename C, int VEC, bool SR, int R, int T>
-__global__ void __launch_bounds__(512)
-sweep_block_xedge(const BlockArgs<S, W, C> A, const int n_strips, const int s_lo, const int s_hi,
+sweep_block_edges(const BlockArgs<S, W, C> A, const int n_strips, const int s_lo, const int s_hi,
                   const int n_chunks, const SlowChunks sc) {
   if (A.gate && *A.gate == 0) return;
   const Plate p = A.s0.p;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int task = (int)(blockIdx.x * (blockDim.x >> 6)) + wave;
+  const int n_slow = n_strips * sc.n;
+  if (task < n_slow) {
+    const int strip = task % n_strips;
+    const int chunk = sc.c[task / n_strips];
+    march<S, W, C, VEC, SR, R, T, false>(A, strip, chunk * R, lane,
+                                         edge_strip_of<VEC, T>(strip, p.nx));
+    return;
+  }
+  const int t = task - n_slow;
   const int n_edge = n_strips - (s_hi - s_lo);
-  if (task >= n_edge * n_chunks) return;
-  const int e = task % n_edge;
+  if (t >= n_edge * n_chunks) return;
+  const int e = t % n_edge;
   const int strip = e < s_lo ? e : s_hi + (e - s_lo);
-  const int chunk = task / n_edge;
+  const int chunk = t / n_edge;
   if (!fast_rows<R, T>(chunk * R, p.ny, A.crack ? p.j0 : -2)) return;
   for (int k = 0; k < sc.n; ++k)
-    if (sc.c[k] == chunk) return;  // the boundary launch takes it
+    if (sc.c[k] == chunk) return;  // a slow chunk row, taken above
   march<S, W, C, VEC, SR, R, T, false, true>(A, strip, chunk * R, lane, true);
 }
 
@@ -549,14 +545,13 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
     }
   }
   if (!ok) return hipErrorInvalidValue;
-  // the boundary and edge-column launches go first, on the side stream, so
-  // that their few long waves run beside the fast launch instead of after it
+  // the boundary launch goes first, on the side stream, so that its few
+  // long waves run beside the fast launch instead of after it
   // (always there when a side stream exists: the crack steps of the previous
   // sweep may still run on it, and only the boundary launch reads what they
   // write)
-  const long etasks = (long)n_strips * sc.n;
-  const long xtasks = (long)(n_strips - (s_hi - s_lo)) * n_chunks;
-  const bool fork = ss.side != nullptr && etasks + xtasks > 0;
+  const long etasks = (long)n_strips * sc.n + (long)(n_strips - (s_hi - s_lo)) * n_chunks;
+  const bool fork = ss.side != nullptr && etasks > 0;
   hipStream_t est = fork ? ss.side : st;
   if (fork) {
     hipError_t e = hipEventRecord(ss.fork, st);
@@ -566,13 +561,6 @@ hipError_t block_t(const BlockArgs<S, W, C> &A, int waves, hipStream_t st, const
   if (etasks > 0) {
     const unsigned blocks = (unsigned)((etasks + 3) / 4);
     hipLaunchKernelGGL((sweep_block_edges<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(256), 0, est,
-                       A, n_strips, sc);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (xtasks > 0) {
-    const unsigned blocks = (unsigned)((xtasks + 3) / 4);
-    hipLaunchKernelGGL((sweep_block_xedge<S, W, C, VEC, SR, R, T>), dim3(blocks), dim3(256), 0, est,
                        A, n_strips, s_lo, s_hi, n_chunks, sc);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
