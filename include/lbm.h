@@ -264,7 +264,11 @@ int lbm_restore(lbm_handle *h, const void *src);
 
 /* Kernel timing with HIP events on the handle's stream.  A step launches the
  * sweep kernel (interior strips and boundary rows in one launch) and the
- * crack kernel.  enable = n > 0 starts recording (and clears the sums) on
+ * crack kernel; a one-step sweep of a plate whose crack runs along +x (or
+ * that has none) runs the crack step of the step before it instead, so its
+ * time counts as sweep time and the crack time of such steps is about zero
+ * (the crack launch that ends each lbm_step call is not timed).
+ * enable = n > 0 starts recording (and clears the sums) on
  * every step whose index is a multiple of n (n > 1 samples the steps, so that
  * the events cost less); 0 stops.  Returns the summed durations (ms) of the
  * two kernels over the timed steps and their number (synchronises the
@@ -379,8 +383,12 @@ size_t lbm_batch_state_bytes(const lbm_config *cfgs, int32_t n);
 int lbm_batch_init(const lbm_config *cfgs, int32_t n, void *dev_buf, size_t dev_bytes, void *stream,
                    lbm_batch **out);
 
-/* nsteps steps; each step is one batched interior launch, one batched
- * boundary-row launch and one batched crack launch (one wavefront per plate).
+/* nsteps steps; each step is one batched sweep launch (the boundary and
+ * interior tasks of every plate) and one batched crack launch (one wavefront
+ * per plate).  When every plate's crack runs along +x (or it has none), the
+ * crack steps of step n run inside the sweep launch of step n + 1 (one more
+ * wavefront per plate; the crack-row tasks take the links it severs) and the
+ * call ends with one crack launch; the results are the same bit for bit.
  * Asynchronous. */
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
@@ -413,7 +421,8 @@ int lbm_batch_run_persistent_static(lbm_batch *b, int64_t nsteps);
 lbm_handle *lbm_batch_plate(lbm_batch *b, int32_t k);
 
 /* Launch shape of the batched interior kernel (as lbm_set_launch) and the
- * grid of the last persistent launch (one workgroup of 4 waves per CU). */
+ * grid of the last persistent launch (one workgroup per CU: 16 waves in the
+ * equilibrium layout, 8 with five planes). */
 int lbm_batch_set_launch(lbm_batch *b, int32_t rows, int32_t waves, int32_t occupancy);
 int lbm_batch_get_launch(lbm_batch *b, int32_t *rows, int32_t *waves, int32_t *occupancy,
                          int32_t *persistent_blocks);
