@@ -197,6 +197,9 @@ def tb_cases(steps):
     wD = np.zeros((steps, 4))
     wD[:, 0] = -0.01 * np.sin(np.pi * n / 60.0)
     wD[:, 3] = 2e-3
+    wD_sides = np.zeros((steps, 4))
+    wD_sides[:, 2] = 0.01 * np.sin(np.pi * n / 40.0)
+    wD_sides[:, 3] = -1e-3
     return {
         "edge-prescribed": dict(nx=517, ny=45, has_crack=True, crack_row=20, crack_tip=100.5,
                                 growth=1, v_rel=0.45,
@@ -232,6 +235,12 @@ def tb_cases(steps):
                           crack_tip=330.5, both_tips=True, growth=1, v_rel=0.4,
                           tau_hist=np.array([1e-3]), trace_cap=steps,
                           wdot0=1e-4 * rng.normal(size=(70, 600))),
+        # Dirichlet left and right edges on a plate with fast chunk rows, so
+        # the edge strips take the edge-column march beside the general one
+        "dirichlet-sides": dict(nx=610, ny=160, has_crack=True, crack_row=60, crack_tip=150.5,
+                                growth=1, v_rel=0.5, dirichlet=4 | 8, wD_hist=wD_sides,
+                                tau_hist=np.array([1e-3]), trace_cap=steps,
+                                wdot0=1e-4 * rng.normal(size=(160, 610))),
     }
 
 
@@ -247,7 +256,7 @@ SHAPES = {2: [(16, 4), (4, 1), (8, 8), (4, 2), (32, 4)], 3: [(16, 2), (4, 4), (8
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 @pytest.mark.parametrize("name", ["edge-prescribed", "two-tip-dirichlet", "no-crack",
                                   "stationary-tiny", "wall-reached", "tall", "taller",
-                                  "crack-bottom", "crack-top"])
+                                  "crack-bottom", "crack-top", "dirichlet-sides"])
 @pytest.mark.parametrize("T,rows,waves", [(T, r, w) for T in range(2, 9) for r, w in SHAPES[T]])
 def test_time_blocked_sweep_equals_one_step_sweeps_bitwise(storage, name, T, rows, waves):
     steps = 151  # not a multiple of T: the last sweep is shorter
@@ -287,7 +296,8 @@ def test_tall_waves_equal_16_row_waves_16bit(storage, rounding, T, rows, name):
 
 @pytest.mark.parametrize("T", [2, 3, 4, 5, 6, 8])
 @pytest.mark.parametrize("storage,case", [("f16s", "two-tip-dirichlet"), ("bf16s", "two-tip-dirichlet"),
-                                          ("f16s", "tall"), ("f16s", "crack-bottom"), ("f16s", "crack-top")])
+                                          ("f16s", "tall"), ("f16s", "crack-bottom"), ("f16s", "crack-top"),
+                                          ("f16s", "dirichlet-sides")])
 def test_time_blocked_sweep_16bit_against_the_oracle(storage, case, T):
     """16-bit storage rounds only after the T-th step: within the derived
     bound of the oracle, tips and cut events exact."""
