@@ -107,6 +107,34 @@ def test_counter_summary_scales_by_the_copy(tmp_path):
     assert out["kernel_source_sha"] == bench.kernel_source_hash()
 
 
+def test_counter_summary_sums_the_two_launches_of_a_t_step_sweep(tmp_path):
+    """A T-step sweep is a fast launch (sweep_block_tall here) and a boundary
+    launch (sweep_block_edges): the summary adds one of each per sweep, of this
+    storage's instantiations only (the BF16 decoy has more launches)."""
+    copy = 1 << 30
+    fd, wd = str(tmp_path / "f"), str(tmp_path / "w")
+    st = "f16s-eq-tb6-sr"
+    p = synth.config_precision()
+    alg = p.nx * p.ny * bench.sweep_bytes_per_site(st) * bench.time_block(st)
+    tall = "_ZN4lbmk3blk16sweep_block_tallIDF16_ffLi4ELb1ELi16ELi32ELi6EEEvNS_9BlockArgsIT_T0_T1_EEiiNS0_8FastRunsE"
+    edges = "_ZN4lbmk3blk17sweep_block_edgesIDF16_ffLi4ELb1ELi16ELi6EEEvNS_9BlockArgsIT_T0_T1_EEiiiiNS0_10SlowChunksE"
+    decoy = "_ZN4lbmk3blk11sweep_blockIDF16bffLi4ELb1ELi16ELi6EEEvNS_9BlockArgsIT_T0_T1_EEiii"
+    # FETCH_SIZE counts half the bytes: the fast launch fetches 1.1, the
+    # boundary launch 0.1 of the algorithmic reads; writes 0.97 and 0.06
+    _write_counters(fd, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", copy / 2 / 1024)]
+                    + [(tall, alg / 2 * 1.1 / 2 / 1024), (edges, alg / 2 * 0.1 / 2 / 1024)] * 2
+                    + [(decoy, alg / 1024)] * 3)
+    _write_counters(wd, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", copy / 1024)]
+                    + [(tall, alg / 2 * 0.97 / 1024), (edges, alg / 2 * 0.06 / 1024)] * 2
+                    + [(decoy, alg / 1024)] * 3)
+    bench.summarize_pmc(fd, wd, st, "precision", copy, "cmd", str(tmp_path))
+    out = json.load(open(tmp_path / f"sweep_{st}_precision_traffic.json"))
+    assert [k[1] for k in out["FETCH_SIZE"]["kernels"]] == [2, 2]
+    assert out["FETCH_SIZE"]["bytes_per_launch"] == pytest.approx(alg / 2 * 1.2)
+    assert out["WRITE_SIZE"]["bytes_per_launch"] == pytest.approx(alg / 2 * 1.03)
+    assert out["traffic_over_algorithmic"] == pytest.approx((1.2 + 1.03) / 2)
+
+
 def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, cwd=ROOT)
