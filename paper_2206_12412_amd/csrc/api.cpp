@@ -953,16 +953,19 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     static_assert(lbmk::kMaxTimeBlock == 8, "one shape per T = 2 .. 8");
     static const int kShape[3][7][3] = {
         {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {16, 2, 3}, {16, 4, 0}, {16, 4, 3}, {16, 4, 3}},   // 16-bit
-        {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}},   // FP32
-        {{8, 2, 0}, {8, 2, 2}, {8, 4, 2}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}}};  // FP64
+        {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {16, 4, 3}, {32, 4, 3}, {32, 4, 3}, {16, 4, 3}},   // FP32
+        {{8, 2, 0}, {8, 2, 2}, {8, 4, 2}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}, {32, 4, 3}}};  // FP64
     const int kind = half ? 0 : (is_fp64(s) ? 2 : 1);
     for (int T = 2; T <= lbmk::kMaxTimeBlock; ++T) {
       h->blk_rows[T] = kShape[kind][T - 2][0];
       h->blk_waves[T] = kShape[kind][T - 2][1];
       h->blk_occ[T] = kShape[kind][T - 2][2];
     }
-    // FP16 at T = 6: two chunks per fast wave, 60.7 against 61.5 us per step
-    // (BF16, with more code per row, and T = 8 are slower that way)
+    // FP16 at T = 6: two chunks per fast wave, 58.1 against 59.4 us per step
+    // (BF16, with more code per row, and 16-bit T = 7 / 8 are slower that
+    // way); rows 32 in the table: FP32 T = 6 70.5 against 71.3 us, T = 7
+    // 61.9 against 66.1, FP64 T = 8 106.6 against 110.4 (FP32 T = 8 is
+    // slower: 86.1 against 59.3)
     if (s == Store::F16S) h->blk_rows[6] = 32;
   }
 
