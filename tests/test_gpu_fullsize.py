@@ -228,12 +228,14 @@ def sif_golden():
         return json.load(fh)
 
 
-def run_sif(storage, g, layout="full"):
+def run_sif(storage, g, layout="full", T=1):
     p = synth.config_sif_fp32()
     s = Solver(Config(nx=p.nx, ny=p.ny, storage=storage, layout=layout, has_crack=True,
                       crack_x0=p.crack_x0,
                       crack_tip=p.crack_tip, growth=p.growth, K_C=p.K_C, r0=p.r0, v_max=p.v_max,
                       tau_hist=p.traction_history(), wdot0=p.wdot0(), trace_cap=p.steps))
+    if T > 1:
+        s.set_time_block(T)
     sites = np.array(g["sites"])
     snaps = {}
     done = 0
@@ -381,6 +383,25 @@ def test_sif_workload_fp32_decisions_and_path(sif_golden):
     assert abs(len(ev) - len(gev)) <= max(2, 2 * abs(len(pev) - len(gev)))
     assert shift.max() <= 3 * max(pshift, 1)
     assert tip_dev <= 3 * max(ptip, 0.5)
+
+
+def test_sif_workload_fp32_as_timed_equals_one_step_five_planes(sif_golden):
+    """The K-criterion workload in the configuration its bench line times
+    (FP32, equilibrium layout, three steps per speculative sweep, four sweeps
+    in flight) against FP32 with five planes and one step per sweep, the run
+    the oracle checks above: the same bits in every sampled field, the K, tip,
+    speed and flag traces and every cut event over the 20000 steps."""
+    g = sif_golden
+    say("4096x2048 K criterion, FP32 equilibrium layout, 3 steps per sweep, against five planes")
+    _, snaps_a, tr_a, ev_a = run_sif("f32", g)
+    _, snaps_b, tr_b, ev_b = run_sif("f32", g, layout="eq", T=3)
+    for n in snaps_a:
+        np.testing.assert_array_equal(snaps_a[n][0], snaps_b[n][0], err_msg=f"w at step {n}")
+        np.testing.assert_array_equal(snaps_a[n][1], snaps_b[n][1], err_msg=f"wdot at step {n}")
+    for key in ("K", "tip", "v", "flags"):
+        np.testing.assert_array_equal(tr_a[key], tr_b[key], err_msg=key)
+    say(f"  {len(ev_b)} cut events, all equal")
+    assert len(ev_a) > 3000 and ev_a.tolist() == ev_b.tolist()
 
 
 # ------------------------------------------------------- batched workload --
