@@ -315,9 +315,41 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * defaults, and
  * a cap on the resident waves per SIMD, are the fastest measured on a
  * 16384 x 8192 plate).  A call whose step count is
- * not a multiple of T ends with one shorter sweep (one step: the one-step
- * sweep).  steps = 1 restores the one-step sweep. */
+ * not a multiple of T ends with the sweeps lbm_plan_tail gives (or, with
+ * lbm_set_tail_plan(h, 0), with one shorter sweep; a sweep of one step is
+ * the one-step sweep); under the K criterion the speculative sweeps choose
+ * their own lengths.  steps = 1 restores the one-step sweep. */
 int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves);
+
+/* The end of a call whose step count is not a multiple of T.  A sweep moves
+ * the same bytes whatever its step count, so on a large plate a sweep of two
+ * steps costs nearly as much as one of six: a call of 20 steps at T = 6 runs
+ * faster as 7 + 7 + 6 than as 6 + 6 + 6 + 2.  With on = 1 (the default)
+ * lbm_step re-splits the rest and up to three T-step sweeps before it into
+ * the sweeps of 1 to 8 steps that lbm_plan_tail gives; on = 0 ends the call
+ * with one shorter sweep.  Results are the same bit for bit either way
+ * (every sweep length computes the same steps).  EINVAL for on other than 0
+ * or 1. */
+int lbm_set_tail_plan(lbm_handle *h, int32_t on);
+
+/* Host only (no device work).  The sweeps, longest first, that end a call of
+ * nsteps steps at steps_per_sweep = T on a plate of this storage (an enum
+ * lbm_storage; the T-step sweep runs FP64 plates in the shifted storage)
+ * while the tail plan is on: the call runs (nsteps - sum of tail) / T sweeps
+ * of T steps, then tail[0 .. *n_tail - 1] (each 1 to 8 steps; at most 32
+ * entries: the caller's array holds 32).  A step count that is a multiple of
+ * T, and T = 1, give no tail.  Otherwise the rest nsteps mod T and the last
+ * j = 0 .. 3 sweeps of T steps before it are split into the sweeps of least
+ * total time by lbm_sweep_cost, over every j (ties: the smaller j).  EINVAL
+ * for an unknown storage, T outside 1..8, negative nsteps or null outputs. */
+int lbm_plan_tail(int32_t storage, int32_t steps_per_sweep, int64_t nsteps, int32_t *tail,
+                  int32_t *n_tail);
+
+/* Host only.  The time (us) of one sweep of `steps` (1 to 8) time steps of
+ * this storage that lbm_plan_tail works from: per-sweep HIP events with the
+ * default shapes on a 16384 x 8192 plate in the equilibrium layout, a crack
+ * growing at a prescribed speed.  EINVAL as lbm_plan_tail. */
+int lbm_sweep_cost(int32_t storage, int32_t steps, double *us);
 
 /* Times every shape of the T-step sweep for steps = T (rows 4, 8, 16 or 32
  * per wave, 16 or 32 for T >= 6; waves 1, 2, 4 or 8 per workgroup) over

@@ -310,6 +310,9 @@ struct lbm_handle {
   // time blocking: steps per sweep (1, or T = 2..8 with the T-step sweep)
   // and the T-step sweep's rows per wave and waves per workgroup, per T
   int tblock = 1;
+  // a call whose step count is not a multiple of T ends with the sweeps of
+  // plan_tail (on) or with one shorter sweep (off)
+  bool tail_plan = true;
   // speculative T-step sweeps (K criterion) and how many were run again;
   // the length the next one may take (halved by a sweep run again, one more
   // after each sweep that held, at most T)
@@ -862,6 +865,72 @@ int tune_shapes(hipStream_t st, int32_t trial_steps, Set set, Run run, int32_t *
   return LBM_OK;
 }
 
+// Time of one sweep of T = 1 .. 8 steps with the default shapes, in
+// microseconds, measured on a 16384 x 8192 plate in the equilibrium layout
+// with a crack growing at a prescribed speed (per-sweep HIP events over
+// twenty sweeps in one call, best of three).  The sweep of six or eight
+// steps costs little more than a short one: it moves the same bytes.  Only
+// the ratios matter to the tail plan.
+const double kSweepUs[4][lbmk::kMaxTimeBlock] = {
+    {268.6, 319.0, 322.2, 342.4, 336.6, 347.9, 408.7, 496.9},   // FP16
+    {270.0, 313.1, 323.6, 345.6, 337.7, 347.9, 426.8, 450.8},   // BF16
+    {354.0, 388.5, 407.2, 417.2, 407.6, 418.5, 426.6, 461.6},   // FP32
+    {684.7, 850.9, 846.7, 846.0, 881.4, 896.7, 862.1, 849.2}};  // FP64
+
+int cost_row(Store s) {
+  switch (s) {
+    case Store::F16S: return 0;
+    case Store::BF16S: return 1;
+    case Store::F32S:
+    case Store::F32_PLAIN: return 2;
+    default: return 3;
+  }
+}
+
+constexpr int kMaxTail = 32;  // 3 sweeps of at most 8 steps and a rest of at most 7
+
+// The sweeps that end a call of n steps at T steps per sweep: the call runs
+// (n - their sum) / T sweeps of T steps, then these.  A call whose step count
+// is a multiple of T ends with none.  Otherwise the rest n mod T and the last
+// j = 0 .. 3 sweeps of T steps before it are split anew into sweeps of 1 .. 8
+// steps, taking the split of least predicted time over every j (ties: the
+// smaller j); the sweeps come longest first.  Returns their number.
+int plan_tail(int row, int T, int64_t n, int32_t *tail) {
+  if (T < 2 || n <= 0 || n % T == 0) return 0;
+  const double *c = kSweepUs[row];
+  const int64_t q = n / T;
+  const int r = (int)(n % T);
+  const int jmax = (int)std::min<int64_t>(q, 3);
+  const int mmax = jmax * T + r;
+  // best[m]: least time of m steps in sweeps of 1 .. 8 steps; first[m]: one
+  // sweep of that split (the longest where several splits tie)
+  double best[kMaxTail] = {0.0};
+  int first[kMaxTail] = {0};
+  for (int m = 1; m <= mmax; ++m) {
+    best[m] = 1e300;
+    for (int t = std::min(m, lbmk::kMaxTimeBlock); t >= 1; --t) {
+      const double v = c[t - 1] + best[m - t];
+      if (v < best[m]) {
+        best[m] = v;
+        first[m] = t;
+      }
+    }
+  }
+  int jbest = 0;
+  double vbest = 1e300;
+  for (int j = 0; j <= jmax; ++j) {
+    const double v = (double)(jmax - j) * c[T - 1] + best[j * T + r];
+    if (v < vbest) {
+      vbest = v;
+      jbest = j;
+    }
+  }
+  int k = 0;
+  for (int m = jbest * T + r; m > 0; m -= first[m]) tail[k++] = first[m];
+  std::sort(tail, tail + k, [](int32_t a, int32_t b) { return a > b; });
+  return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1121,12 +1190,27 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (h->in_batch) return fail(LBM_ESTATE, "this plate is stepped by its batch (lbm_batch_step)");
   if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
+  const bool sif_blocks = h->tblock >= 2 && h->cfg.growth == LBM_GROW_SIF;
+  // the sweeps that end this call (planned when the start-up steps are done;
+  // the speculative sweeps of the K criterion take lengths of their own)
+  int32_t tail[kMaxTail];
+  int n_tail = -1, i_tail = 0;
+  int64_t tail_steps = 0;
   for (int64_t k = 0; k < nsteps;) {
     // T steps in one sweep when time blocking is on and the moving planes
     // are settled (the five-plane start-up steps run one at a time); fewer
     // at the end of the call
     int ns = h->full_steps == 0 ? (int)std::min<int64_t>(h->tblock, nsteps - k) : 1;
-    const bool sif_blocks = h->tblock >= 2 && h->cfg.growth == LBM_GROW_SIF;
+    if (h->full_steps == 0 && h->tblock >= 2 && h->tail_plan && !sif_blocks) {
+      if (n_tail < 0) {
+        n_tail = plan_tail(cost_row(h->store), h->tblock, nsteps - k, tail);
+        for (int m = 0; m < n_tail; ++m) tail_steps += tail[m];
+      }
+      if (nsteps - k <= tail_steps) {
+        if (i_tail >= n_tail) return fail(LBM_EINVAL, "sweep plan out of step");
+        ns = tail[i_tail++];
+      }
+    }
     if (sif_blocks) ns = std::min(ns, std::max(2, h->spec_cap));
     bool timed = false;
     for (int m = 0; m < ns; ++m) timed |= h->timing && (h->step + m) % h->timing_stride == 0;
@@ -1575,6 +1659,36 @@ int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves
   h->spec_cap = steps;
   if (rows > 0) h->blk_rows[steps] = rows;
   if (waves > 0) h->blk_waves[steps] = waves;
+  return LBM_OK;
+}
+
+int lbm_set_tail_plan(lbm_handle *h, int32_t on) {
+  if (!h) return fail(LBM_EINVAL, "null handle");
+  if (on != 0 && on != 1) return fail(LBM_EINVAL, "on must be 0 or 1");
+  h->tail_plan = on != 0;
+  return LBM_OK;
+}
+
+int lbm_plan_tail(int32_t storage, int32_t steps_per_sweep, int64_t nsteps, int32_t *tail,
+                  int32_t *n_tail) {
+  if (storage < LBM_F64 || storage > LBM_F32_PLAIN) return fail(LBM_EINVAL, "unknown storage %d", storage);
+  if (steps_per_sweep < 1 || steps_per_sweep > lbmk::kMaxTimeBlock)
+    return fail(LBM_EINVAL, "steps per sweep must be 1 to 8");
+  if (nsteps < 0) return fail(LBM_EINVAL, "negative step count");
+  if (!tail || !n_tail) return fail(LBM_EINVAL, "null output");
+  const Store s = storage == LBM_F16S ? Store::F16S : storage == LBM_BF16S ? Store::BF16S
+                  : storage == LBM_F64 ? Store::F64S : Store::F32S;
+  *n_tail = plan_tail(cost_row(s), steps_per_sweep, nsteps, tail);
+  return LBM_OK;
+}
+
+int lbm_sweep_cost(int32_t storage, int32_t steps, double *us) {
+  if (storage < LBM_F64 || storage > LBM_F32_PLAIN) return fail(LBM_EINVAL, "unknown storage %d", storage);
+  if (steps < 1 || steps > lbmk::kMaxTimeBlock) return fail(LBM_EINVAL, "steps must be 1 to 8");
+  if (!us) return fail(LBM_EINVAL, "null output");
+  const Store s = storage == LBM_F16S ? Store::F16S : storage == LBM_BF16S ? Store::BF16S
+                  : storage == LBM_F64 ? Store::F64S : Store::F32S;
+  *us = kSweepUs[cost_row(s)][steps - 1];
   return LBM_OK;
 }
 

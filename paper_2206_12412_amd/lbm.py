@@ -48,7 +48,7 @@ EXPORTS = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_crack_state", "lbm_si
            "lbm_batch_free", "lbm_autotune", "lbm_batch_autotune", "lbm_round16",
            "lbm_sensor_traces", "lbm_adjoint_bytes", "lbm_adjoint_init", "lbm_adjoint_run",
            "lbm_adjoint_timing", "lbm_adjoint_free", "lbm_checkpoint_bytes", "lbm_checkpoint",
-           "lbm_restore", "lbm_traces_left")
+           "lbm_restore", "lbm_traces_left", "lbm_set_tail_plan", "lbm_plan_tail", "lbm_sweep_cost")
 
 
 class LBMError(RuntimeError):
@@ -120,6 +120,12 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_time_block_stats.argtypes = [vp, P(i64), P(i64)]
     lib.lbm_time_block_stats.restype = i32
     lib.lbm_autotune_time_block.argtypes = [vp, i32, i32, P(i32), P(i32), P(d)]
+    lib.lbm_set_tail_plan.argtypes = [vp, i32]
+    lib.lbm_set_tail_plan.restype = i32
+    lib.lbm_plan_tail.argtypes = [i32, i32, i64, P(i32), P(i32)]
+    lib.lbm_plan_tail.restype = i32
+    lib.lbm_sweep_cost.argtypes = [i32, i32, P(d)]
+    lib.lbm_sweep_cost.restype = i32
     lib.lbm_autotune_time_block.restype = i32
     lib.lbm_get_fields.argtypes = [vp, P(d), P(d)]
     lib.lbm_get_populations.argtypes = [vp, P(d)]
@@ -283,6 +289,24 @@ def round16(x, storage: str = "f16s", rounding: str = "nearest", plane: int = 0,
                            ROUNDING[rounding], int(plane), int(seed) & 0xFFFFFFFF, int(step),
                            st.cuda_stream))
     return out
+
+
+def plan_tail(storage: str, steps_per_sweep: int, nsteps: int) -> list:
+    """lbm_plan_tail: the sweep lengths that end a call of nsteps steps at
+    steps_per_sweep steps per sweep (host only)."""
+    tail = (C.c_int32 * 32)()
+    n = C.c_int32()
+    _check(load_library().lbm_plan_tail(STORAGE[storage], int(steps_per_sweep), int(nsteps), tail,
+                                        C.byref(n)))
+    return [int(tail[k]) for k in range(n.value)]
+
+
+def sweep_cost(storage: str, steps: int) -> float:
+    """lbm_sweep_cost: the time (us) of one sweep of `steps` steps the plan
+    works from (host only)."""
+    us = C.c_double()
+    _check(load_library().lbm_sweep_cost(STORAGE[storage], int(steps), C.byref(us)))
+    return us.value
 
 
 def _tune(fn, handle, trial_steps: int) -> dict:
@@ -502,6 +526,12 @@ class Solver:
     def set_time_block(self, steps: int = 2, rows: int = 0, waves: int = 0):
         """Advance `steps` (1 to 8) time steps per sweep; see lbm_set_time_block."""
         _check(self._lib.lbm_set_time_block(self._h, int(steps), int(rows), int(waves)))
+
+    def set_tail_plan(self, on: bool = True):
+        """Whether a call whose step count is not a multiple of T ends with
+        the planned sweeps (plan_tail) or with one shorter sweep; see
+        lbm_set_tail_plan."""
+        _check(self._lib.lbm_set_tail_plan(self._h, 1 if on else 0))
 
     def autotune_time_block(self, steps: int, trial_sweeps: int = 4) -> dict:
         """Searches the T-step sweep's shapes (steps = T) on a scratch plate

@@ -125,3 +125,60 @@ def test_batch_refuses_the_macroscopic_scheme():
     arr = (L._Config * 2)(P.Config(nx=16, ny=8).to_c(keep),
                           P.Config(nx=16, ny=8, bc_scheme="macro").to_c(keep))
     assert P.load_library().lbm_batch_state_bytes(arr, 2) == 0
+
+
+def splits(m, largest=8):
+    """Every split of m steps into sweeps of 1 .. largest steps, longest first."""
+    if m == 0:
+        yield ()
+        return
+    for t in range(min(m, largest), 0, -1):
+        for rest in splits(m - t, t):
+            yield (t,) + rest
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s", "f32", "f64"])
+def test_tail_plan_is_the_cheapest_end_of_a_call(storage):
+    """lbm_plan_tail (host only): the call runs whole sweeps of T steps, then
+    the tail; checked against every split of the rest and of up to three
+    T-step sweeps before it, enumerated here."""
+    cost = {t: P.sweep_cost(storage, t) for t in range(1, 9)}
+    best_of = {}
+    for m in range(0, 32):
+        best_of[m] = min(sum(cost[t] for t in s) for s in splits(m))
+    for T in range(1, 9):
+        for n in list(range(0, 70)) + [1199, 1200, 1201, 10 ** 6 + 5]:
+            tail = P.plan_tail(storage, T, n)
+            assert all(1 <= t <= 8 for t in tail) and len(tail) <= 32
+            assert list(tail) == sorted(tail, reverse=True)
+            bulk = n - sum(tail)
+            assert bulk >= 0 and bulk % T == 0, (T, n, tail)
+            if T == 1 or n % T == 0:
+                assert tail == [], (T, n, tail)
+                continue
+            q, r = divmod(n, T)
+            jmax = min(q, 3)
+            want = min((jmax - j) * cost[T] + best_of[j * T + r] for j in range(jmax + 1))
+            got = (jmax * T + r - sum(tail)) // T * cost[T] + sum(cost[t] for t in tail)
+            assert got == pytest.approx(want, rel=1e-12), (T, n, tail)
+            # never slower than ending with one shorter sweep
+            assert got <= jmax * cost[T] + cost[r] + 1e-9
+
+
+def test_tail_plan_examples_and_refusals():
+    assert P.plan_tail("f16s", 6, 20) == [7, 7]      # 6 + 7 + 7 instead of 6 + 6 + 6 + 2
+    assert P.plan_tail("f16s", 6, 1200) == []
+    assert P.plan_tail("f16s", 1, 7) == []
+    assert P.plan_tail("f64", 8, 20) == [4]
+    lib = P.load_library()
+    tail = (C.c_int32 * 32)()
+    n = C.c_int32()
+    assert lib.lbm_plan_tail(0, 0, 10, tail, C.byref(n)) == -1
+    assert lib.lbm_plan_tail(0, 9, 10, tail, C.byref(n)) == -1
+    assert lib.lbm_plan_tail(7, 6, 10, tail, C.byref(n)) == -1
+    assert lib.lbm_plan_tail(0, 6, -1, tail, C.byref(n)) == -1
+    assert lib.lbm_plan_tail(0, 6, 10, None, C.byref(n)) == -1
+    us = C.c_double()
+    assert lib.lbm_sweep_cost(2, 0, C.byref(us)) == -1
+    assert lib.lbm_sweep_cost(2, 6, None) == -1
+    assert lib.lbm_set_tail_plan(None, 1) == -1

@@ -25,7 +25,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2206_12412_amd import Batch, Config, Solver  # noqa: E402
+from paper_2206_12412_amd import Batch, Config, Solver, plan_tail  # noqa: E402
 
 
 def say(msg):
@@ -259,7 +259,7 @@ SHAPES = {2: [(16, 4), (4, 1), (8, 8), (4, 2), (32, 4)], 3: [(16, 2), (4, 4), (8
                                   "crack-bottom", "crack-top", "dirichlet-sides"])
 @pytest.mark.parametrize("T,rows,waves", [(T, r, w) for T in range(2, 9) for r, w in SHAPES[T]])
 def test_time_blocked_sweep_equals_one_step_sweeps_bitwise(storage, name, T, rows, waves):
-    steps = 151  # not a multiple of T: the last sweep is shorter
+    steps = 151  # not a multiple of T: each call ends with the planned sweeps
     kw = tb_cases(steps)[name]
     say(f"{T}-step sweep {name} {storage} rows={rows} waves={waves}")
     one = Solver(Config(storage=storage, layout="eq", **kw))
@@ -460,22 +460,72 @@ def test_time_blocked_sweep_refuses_what_it_cannot_do():
     s.set_time_block(4)  # the shape is kept per step count
 
 
-def timed_steps(calls, T, stride):
+def timed_steps(calls, T, stride, storage="f32"):
     """Steps the per-kernel events cover: a sweep is timed when one of its
     steps is a multiple of the stride; the two five-plane start-up steps of
-    the equilibrium layout run alone, and a call ends with a shorter sweep
-    when its step count is not a multiple of T."""
+    the equilibrium layout run alone, and a call whose step count is not a
+    multiple of T ends with the sweeps of plan_tail."""
     step, full, total = 0, 2, 0
     for nsteps in calls:
         k = 0
+        tail = None
         while k < nsteps:
-            ns = min(T, nsteps - k) if full == 0 else 1
+            if full > 0:
+                ns = 1
+            else:
+                if tail is None:
+                    tail = plan_tail(storage, T, nsteps - k)
+                    tail_steps = sum(tail)
+                ns = T if nsteps - k > tail_steps else tail.pop(0)
             if any((step + m) % stride == 0 for m in range(ns)):
                 total += ns
             step += ns
             k += ns
             full = max(full - 1, 0)
     return total
+
+
+def planned_sweeps(storage, T, n, startup):
+    """The sweeps lbm_step runs for a call of n steps at T steps per sweep:
+    the five-plane start-up steps still due one at a time, then whole sweeps
+    of T steps, then the sweeps of plan_tail."""
+    first = [1] * min(startup, n)
+    tail = plan_tail(storage, T, n - len(first))
+    return first + [T] * ((n - len(first) - sum(tail)) // T) + tail
+
+
+@pytest.mark.parametrize("storage,rounding,T", [("f16s", "stochastic", 6), ("bf16s", "stochastic", 6),
+                                                ("f32", "nearest", 6), ("f32", "nearest", 8),
+                                                ("f64", "nearest", 8), ("f16s", "nearest", 3)])
+@pytest.mark.parametrize("name", ["two-tip-dirichlet", "taller"])
+def test_planned_call_ends(storage, rounding, T, name):
+    """A call whose step count is not a multiple of T ends with the sweeps of
+    plan_tail (up to eight steps each).  It equals the same sweeps run one per
+    call, bit for bit; FP32 and FP64 results also equal those of calls that
+    end with one shorter sweep (the plan off).  16-bit storages round once
+    per sweep, so there the split of a call is part of the result."""
+    calls = (5, 20, 13, 1, 47, 2 * T, 30)
+    steps = sum(calls)
+    kw = tb_cases(steps)[name]
+    say(f"planned call ends {name} {storage} {rounding} T={T}: calls {calls}")
+    assert any(plan_tail(storage, T, n) for n in calls)
+    mk = lambda: Solver(Config(storage=storage, layout="eq", rounding=rounding, seed=5, **kw))
+    a, b, c = mk(), mk(), mk()
+    a.set_time_block(T)
+    c.set_time_block(T)
+    c.set_tail_plan(False)
+    startup = 2
+    for n in calls:
+        a.step(n)
+        for t in planned_sweeps(storage, T, n, startup):
+            b.set_time_block(t)
+            b.step(t)
+        startup = max(startup - n, 0)
+        label = f"{name} {storage} T={T} after {a.steps_done}"
+        same(a, b, label, kw.get("both_tips", False), kw.get("has_crack", False))
+        if storage in ("f32", "f64"):
+            c.step(n)
+            same(a, c, label + " (plan off)", kw.get("both_tips", False), kw.get("has_crack", False))
 
 
 @pytest.mark.parametrize("T", [2, 3, 4, 5, 8])
