@@ -197,6 +197,56 @@ def run_storage(p, storage, steps, warmup, torch, ref=None, tune=False):
     return out
 
 
+def sweep_costs(p, storages, torch, out_md):
+    """Time of one sweep of T = 1 .. 8 steps with the default shapes on plate
+    p, per storage (per-sweep mean of twenty sweeps in one call, best of
+    three), beside the table the library plans call ends from; writes a
+    markdown summary."""
+    from paper_2206_12412_amd import Solver, sweep_cost
+    rows = []
+    for storage in storages:
+        st = parse_storage(storage)[0]
+        s = Solver(plate_config(p, storage, 4000))
+        s.step(4)
+        got = {}
+        for T in range(1, 9):
+            s.set_time_block(T)
+            s.step(2 * T)
+            best = float("inf")
+            for _ in range(3):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(s.stream)
+                s.step(20 * T)
+                b.record(s.stream)
+                torch.cuda.synchronize()
+                best = min(best, a.elapsed_time(b) * 1e3 / 20)
+            got[T] = best
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        rows.append((storage, got, {T: sweep_cost(st, T) for T in range(1, 9)}))
+        print(f"bench: sweep costs {storage}: " + ", ".join(f"{T}: {v:.1f}" for T, v in got.items()),
+              file=sys.stderr, flush=True)
+    cmd = "python3 bench.py " + " ".join(sys.argv[1:])
+    out = [f"# Sweep time per step count: {os.path.basename(out_md)}", "",
+           "Command:", "", "    " + cmd, "",
+           f"Plate {p.nx} x {p.ny} ({p.name}), equilibrium layout, default launch shapes; "
+           "us per sweep of T steps (20 sweeps in one call, best of three), and in brackets the "
+           "table lbm_plan_tail works from (lbm_sweep_cost).", "",
+           "| storage | " + " | ".join(f"T = {T}" for T in range(1, 9)) + " |",
+           "|---|" + "---|" * 8]
+    for storage, got, lib in rows:
+        out.append(f"| {storage} | " + " | ".join(f"{got[T]:.1f} ({lib[T]:.1f})" for T in range(1, 9))
+                   + " |")
+    out += ["", "Per step (us), measured: "]
+    for storage, got, _ in rows:
+        out.append(f"* {storage}: " + ", ".join(f"T = {T} {got[T] / T:.1f}" for T in range(1, 9)))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print(f"wrote {out_md}", file=sys.stderr, flush=True)
+
+
 def field_error(w, r):
     """RMS and max of w - r relative to the reference field (None where the
     reference is still zero)."""
@@ -733,6 +783,9 @@ def main():
                     help="write a markdown summary of a rocprofv3 kernel-trace directory and exit")
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"),
                     help="where --summarize-pmc writes its summary")
+    ap.add_argument("--sweep-costs", metavar="OUT_MD",
+                    help="time one sweep of 1 .. 8 steps for the --compare storages on the "
+                         "workload's plate, write a markdown summary and exit")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB", "COMMAND"),
                     help="write profiles/sweep_<storage>_<workload>_traffic.{json,md} and exit")
     args = ap.parse_args()
@@ -770,6 +823,9 @@ def main():
          "plain": synth.config_plain_fp64}[args.workload]()
     # timed steps: the driver passes --steps; by default 1200 (whole sweeps for
     # T = 2 .. 6 and 8), while the untimed error leg runs the whole workload
+    if args.sweep_costs:
+        sweep_costs(p, [s for s in args.compare.split(",") if s], torch, args.sweep_costs)
+        return
     steps = args.steps if args.steps is not None else (1200 if args.workload == "precision" else p.steps)
     storages = [s for s in args.compare.split(",") if s]
     for extra in (args.record, args.storage):

@@ -327,9 +327,10 @@ int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves
  * faster as 7 + 7 + 6 than as 6 + 6 + 6 + 2.  With on = 1 (the default)
  * lbm_step re-splits the rest and up to three T-step sweeps before it into
  * the sweeps of 1 to 8 steps that lbm_plan_tail gives; on = 0 ends the call
- * with one shorter sweep.  Results are the same bit for bit either way
- * (every sweep length computes the same steps).  EINVAL for on other than 0
- * or 1. */
+ * with one shorter sweep.  FP32 and FP64 results are the same bit for bit
+ * either way; the 16-bit storages round once per sweep, so their results
+ * follow the split (as for calls of other lengths).  EINVAL for on other
+ * than 0 or 1. */
 int lbm_set_tail_plan(lbm_handle *h, int32_t on);
 
 /* Host only (no device work).  The sweeps, longest first, that end a call of
