@@ -20,11 +20,11 @@ events for the sweep kernel's duration.  Then an untimed leg runs the whole
 waves reach the crack only after ~8200 steps).
 
 The JSON line reports the headline storage's GLUPS (FP16, equilibrium layout,
-six steps per sweep, stochastic rounding) as `value`; `roofline` is that of
+seven steps per sweep, stochastic rounding) as `value`; `roofline` is that of
 the one-step five-population FP16 sweep (28 B per site update), and
 `roofline_headline_kernel` the headline kernel's fraction in its own bytes.
 
-    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb6-sr] [--workload precision]
+    python bench.py [--steps K] [--warmup W] [--storage f16s-eq-tb7-sr] [--workload precision]
 """
 from __future__ import annotations
 
@@ -758,22 +758,23 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="single plate: autotune each storage before timing (the library's "
                          "defaults are this search's result for the precision plate)")
-    ap.add_argument("--storage", default="f16s-eq-tb6-sr",
+    ap.add_argument("--storage", default="f16s-eq-tb7-sr",
                     help='headline storage; "-eq" selects the equilibrium layout, "-eq-tb" that '
                          'layout with two time steps per sweep ("-eq-tb3" .. "-eq-tb8": three to '
                          'eight), a "-sr" suffix stochastic rounding (e.g. f16s-eq-tb6-sr)')
     ap.add_argument("--compare",
                     default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr,"
                             "f16s-eq-tb-sr,f16s-eq-tb4-sr,"
-                            "f64-eq-tb8,f32-eq-tb6,f32-eq-tb8,f16s-eq-tb6-sr,bf16s-eq-tb6-sr",
+                            "f64-eq-tb8,f32-eq-tb6,f32-eq-tb7,f32-eq-tb8,f16s-eq-tb6-sr,"
+                            "f16s-eq-tb7-sr,bf16s-eq-tb7-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--record", default="f16s-sr",
                     help="storage whose one-step five-population sweep is the roofline of record")
     ap.add_argument("--k-steps", type=int, default=None,
                     help="steps of the untimed K_III / field error leg (default: the workload's; "
                          "0 skips it)")
-    ap.add_argument("--k-compare", default="f64,f32,f16s-sr,bf16s-sr,f32-eq-tb6,f16s-eq-tb6-sr,"
-                                           "bf16s-eq-tb6-sr,bf16s-eq-tb8-sr",
+    ap.add_argument("--k-compare", default="f64,f32,f16s-sr,bf16s-sr,f32-eq-tb7,f16s-eq-tb6-sr,"
+                                           "f16s-eq-tb7-sr,bf16s-eq-tb7-sr,bf16s-eq-tb8-sr",
                     help="storages of the K_III / field error leg; the first is the reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")

@@ -872,10 +872,10 @@ int tune_shapes(hipStream_t st, int32_t trial_steps, Set set, Run run, int32_t *
 // steps costs little more than a short one: it moves the same bytes.  Only
 // the ratios matter to the tail plan.
 const double kSweepUs[4][lbmk::kMaxTimeBlock] = {
-    {268.6, 319.0, 322.2, 342.4, 336.6, 347.9, 408.7, 496.9},   // FP16
-    {270.0, 313.1, 323.6, 345.6, 337.7, 347.9, 426.8, 450.8},   // BF16
-    {354.0, 388.5, 407.2, 417.2, 407.6, 418.5, 426.6, 461.6},   // FP32
-    {684.7, 850.9, 846.7, 846.0, 881.4, 896.7, 862.1, 849.2}};  // FP64
+    {269.1, 317.0, 319.3, 341.3, 336.5, 347.9, 391.3, 468.9},   // FP16
+    {269.4, 310.8, 322.1, 345.2, 337.0, 346.7, 380.5, 448.1},   // BF16
+    {352.5, 390.6, 405.3, 417.5, 408.6, 418.8, 425.3, 461.0},   // FP32
+    {682.9, 849.8, 845.2, 842.3, 880.1, 896.5, 859.9, 849.0}};  // FP64
 
 int cost_row(Store s) {
   switch (s) {

@@ -303,6 +303,12 @@ __device__ __forceinline__ void march(const BlockArgs<S, W, C> &A, const int str
       wv[0][0][k] = core::to_c(wl_[rr % RING][k]);
       gv[0][1][k] = gv[0][0][k];
       gv[0][0][k] = core::to_c(gl_[rr % RING][k]);
+      // 16-bit rows of sweeps of seven and eight steps: the rest population
+      // is converted to FP32 where its row arrives, not folded into the
+      // mixed-precision FMAs that use it (FP16 T = 8 holds 179 VGPRs instead
+      // of 202; 467 against 496 us per sweep, BF16 T = 7 382 against 428;
+      // at T = 6 it gains nothing)
+      if constexpr (sizeof(S) == 2 && T >= 7) asm volatile("" : "+v"(gv[0][0][k]));
     }
 #pragma unroll
     for (int lv = 1; lv <= T; ++lv) {

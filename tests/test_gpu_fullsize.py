@@ -114,7 +114,8 @@ def parse(name):
                                          ("f32-eq-tb5", 1e-5), ("f64-eq-tb4", 1e-12),
                                          ("f32-eq-tb4", 1e-5), ("f16s-eq-tb3-sr", F16_TOL),
                                          ("f16s-eq-tb4-sr", F16_TOL), ("f16s-eq-tb5-sr", F16_TOL),
-                                         ("f16s-eq-tb6-sr", F16_TOL), ("f32-eq-tb8", 1e-5),
+                                         ("f16s-eq-tb6-sr", F16_TOL), ("f16s-eq-tb7-sr", F16_TOL),
+                                         ("f32-eq-tb7", 1e-5), ("f32-eq-tb8", 1e-5),
                                          ("f64-eq-tb8", 1e-12)])
 def test_precision_plate_windows(big_plate, storage, tol):
     """The 134M-site plate in the launch configuration the benchmark times
@@ -183,13 +184,15 @@ def scaled_precision_ref():
 @pytest.mark.parametrize("storage,ktol,wtol", [("f32", 1e-5, 1e-5), ("f32-eq-tb6", 1e-5, 1e-5),
                                                ("f16s-sr", 1e-3, 2e-4),
                                                ("f16s-eq-tb6-sr", 1e-3, 2e-4),
-                                               ("bf16s-eq-tb6-sr", 2.5e-3, 8e-4)])
+                                               ("f16s-eq-tb7-sr", 1e-3, 2e-4),
+                                               ("bf16s-eq-tb6-sr", 2.5e-3, 8e-4),
+                                               ("bf16s-eq-tb7-sr", 2.5e-3, 8e-4)])
 def test_precision_workload_K_error(scaled_precision_ref, storage, ktol, wtol):
     """K_III(t) of the reduced-precision storages against the oracle on the
     precision workload scaled to 1536 x 768: max_n |K_n - K_n^ref| /
     max_n |K_n^ref| within 1e-5 for FP32 and within the 1e-3 bar of the
     precision extension for FP16 storage with stochastic rounding, one step
-    per sweep (five populations) and six (the benchmark's headline); tips
+    per sweep (five populations), six and seven (the benchmark's headline); tips
     bit-exact.  BF16 (8-bit mantissa) is held to three times its measured
     error instead: on the full-size workload it does not meet 1e-3."""
     p, tr, w_ref = scaled_precision_ref
