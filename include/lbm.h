@@ -310,7 +310,8 @@ int lbm_set_launch(lbm_handle *h, int32_t rows, int32_t waves, int32_t occupancy
  * rows / waves: rows finished per wave (4, 8 or 16; or 32: chunks of 16
  * rows, two per wave of the launch away from the plate edges and crack rows,
  * which loads and steps the rows around them once per wave instead of once
- * per chunk) and waves per workgroup (1, 2, 4 or 8)
+ * per chunk; or, for T >= 6, 24: chunks of 8 rows, three per such wave) and
+ * waves per workgroup (1, 2, 4 or 8)
  * of the T-step sweep for this T (0 = keep; T >= 6: 16 rows or more; the
  * defaults, and
  * a cap on the resident waves per SIMD, are the fastest measured on a
@@ -353,7 +354,7 @@ int lbm_plan_tail(int32_t storage, int32_t steps_per_sweep, int64_t nsteps, int3
 int lbm_sweep_cost(int32_t storage, int32_t steps, double *us);
 
 /* Times every shape of the T-step sweep for steps = T (rows 4, 8, 16 or 32
- * per wave, 16 or 32 for T >= 6; waves 1, 2, 4 or 8 per workgroup) over
+ * per wave, 16, 24 or 32 for T >= 6; waves 1, 2, 4 or 8 per workgroup) over
  * trial_sweeps sweeps of h itself (h advances: tune a scratch plate made from
  * the same configuration), then sets the fastest with lbm_set_time_block and
  * returns it with its time per step.  The defaults were measured on a

@@ -872,10 +872,10 @@ int tune_shapes(hipStream_t st, int32_t trial_steps, Set set, Run run, int32_t *
 // steps costs little more than a short one: it moves the same bytes.  Only
 // the ratios matter to the tail plan.
 const double kSweepUs[4][lbmk::kMaxTimeBlock] = {
-    {269.1, 317.0, 319.3, 341.3, 336.5, 347.9, 391.3, 468.9},   // FP16
-    {269.4, 310.8, 322.1, 345.2, 337.0, 346.7, 380.5, 448.1},   // BF16
-    {352.5, 390.6, 405.3, 417.5, 408.6, 418.8, 425.3, 461.0},   // FP32
-    {682.9, 849.8, 845.2, 842.3, 880.1, 896.5, 859.9, 849.0}};  // FP64
+    {268.7, 319.3, 321.7, 342.6, 337.1, 348.4, 374.5, 466.8},   // FP16
+    {269.7, 312.5, 324.1, 345.7, 337.2, 348.6, 363.9, 393.9},   // BF16
+    {354.5, 388.8, 406.2, 418.3, 409.2, 419.2, 426.1, 445.2},   // FP32
+    {685.0, 852.5, 846.7, 843.2, 880.9, 897.1, 861.5, 849.2}};  // FP64
 
 int cost_row(Store s) {
   switch (s) {
@@ -1021,8 +1021,8 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     // T = 2 .. 8, the fastest measured on a 16384 x 8192 plate
     static_assert(lbmk::kMaxTimeBlock == 8, "one shape per T = 2 .. 8");
     static const int kShape[3][7][3] = {
-        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {16, 2, 3}, {16, 4, 0}, {16, 4, 3}, {16, 4, 3}},   // 16-bit
-        {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {16, 4, 3}, {32, 4, 3}, {32, 4, 3}, {16, 4, 3}},   // FP32
+        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {16, 2, 3}, {16, 4, 0}, {24, 4, 3}, {16, 4, 3}},   // 16-bit
+        {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {16, 4, 3}, {32, 4, 3}, {32, 4, 3}, {24, 4, 3}},   // FP32
         {{8, 2, 0}, {8, 2, 2}, {8, 4, 2}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}, {32, 4, 3}}};  // FP64
     const int kind = half ? 0 : (is_fp64(s) ? 2 : 1);
     for (int T = 2; T <= lbmk::kMaxTimeBlock; ++T) {
@@ -1036,6 +1036,13 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     // 61.9 against 66.1, FP64 T = 8 106.6 against 110.4 (FP32 T = 8 is
     // slower: 86.1 against 59.3)
     if (s == Store::F16S) h->blk_rows[6] = 32;
+    // rows 24 (three 8-row chunks per fast wave): FP16 T = 7 53.5 against
+    // 56.1 us per step with 16 rows, BF16 T = 7 51.9 against 54.5, BF16
+    // T = 8 49.0 against 55.9, FP32 T = 8 56.2 against 58.8; not for FP16
+    // T = 8 (182 us per step: its march no longer fits the instruction
+    // cache), FP32 T = 7 (62.8 against 62.1 with 32 rows) or FP64 T = 8
+    // (107.5 against 106.4)
+    if (s == Store::BF16S) h->blk_rows[8] = 24;
   }
 
   {
@@ -1637,10 +1644,11 @@ int lbm_set_time_block(lbm_handle *h, int32_t steps, int32_t rows, int32_t waves
   if (!h) return fail(LBM_EINVAL, "null handle");
   if (steps < 1 || steps > lbmk::kMaxTimeBlock)
     return fail(LBM_EINVAL, "steps per sweep must be 1 to 8");
-  if (rows != 0 && rows != 4 && rows != 8 && rows != 16 && rows != 32)
-    return fail(LBM_EINVAL, "rows must be 4, 8, 16 or 32 (0 = keep)");
+  if (rows != 0 && rows != 4 && rows != 8 && rows != 16 && rows != 24 && rows != 32)
+    return fail(LBM_EINVAL, "rows must be 4, 8, 16, 24 (T >= 6) or 32 (0 = keep)");
   if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
     return fail(LBM_EINVAL, "waves must be 0 (keep), 1, 2, 4 or 8");
+  if (rows == 24 && steps < 6) return fail(LBM_EINVAL, "24 rows per wave: sweeps of six or more steps");
   if (steps >= 6 && rows != 0 && rows < 16)
     return fail(LBM_EINVAL, "sweeps of six or more steps take 16 or more rows per wave");
   if (steps == 1 && (rows != 0 || waves != 0))
@@ -1733,7 +1741,7 @@ int lbm_autotune_time_block(lbm_handle *h, int32_t steps, int32_t trial_sweeps, 
   if (steps < 2 || steps > lbmk::kMaxTimeBlock) return fail(LBM_EINVAL, "steps must be 2 to 8");
   if (trial_sweeps < 1 || trial_sweeps > 1000)
     return fail(LBM_EINVAL, "trial_sweeps must be in 1..1000");
-  static const int kRows[] = {4, 8, 16, 32};
+  static const int kRows[] = {4, 8, 16, 24, 32};
   static const int kWaves[] = {1, 2, 4, 8};
   int rc = lbm_set_time_block(h, steps, 0, 0);  // refuses plates the T-step sweep cannot take
   if (rc != LBM_OK) return rc;
@@ -1748,7 +1756,7 @@ int lbm_autotune_time_block(lbm_handle *h, int32_t steps, int32_t trial_sweeps, 
   float best = -1.0f;
   int br = h->blk_rows[steps], bw = h->blk_waves[steps];
   for (int r : kRows) {
-    if (steps >= 6 && r < 16) continue;
+    if ((steps >= 6 && r < 16) || (steps < 6 && r == 24)) continue;
     for (int w : kWaves) {
       rc = lbm_set_time_block(h, steps, r, w);
       if (rc == LBM_OK) rc = lbm_step(h, steps);

@@ -15,7 +15,7 @@ hipError_t launch_sweep_block_bf16(const void *args, int rows, int waves, hipStr
 
 hipError_t launch_sweep_block(Store s, const void *args, int rows, int waves, hipStream_t st,
                               const SideStream &ss) {
-  const bool rows_ok = rows == 4 || rows == 8 || rows == 16 || rows == 32;
+  const bool rows_ok = rows == 4 || rows == 8 || rows == 16 || rows == 24 || rows == 32;
   if (!rows_ok || (waves != 1 && waves != 2 && waves != 4 && waves != 8)) return hipErrorInvalidValue;
   switch (s) {
     case Store::F64S: return launch_sweep_block_f64(args, rows, waves, st, ss);

@@ -613,6 +613,9 @@ hipError_t block_rows(const BlockArgs<S, W, C> &A, int rows, int waves, hipStrea
       if constexpr (T <= 5) return block_t<S, W, C, VEC, SR, 8, 8, T>(A, waves, st, ss);
       return hipErrorInvalidValue;
     case 16: return block_t<S, W, C, VEC, SR, 16, 16, T>(A, waves, st, ss);
+    case 24:
+      if constexpr (T >= 6) return block_t<S, W, C, VEC, SR, 8, 24, T>(A, waves, st, ss);
+      return hipErrorInvalidValue;
     case 32: return block_t<S, W, C, VEC, SR, 16, 32, T>(A, waves, st, ss);
     default: return hipErrorInvalidValue;
   }

@@ -246,11 +246,12 @@ def tb_cases(steps):
 
 # rows 32: chunks of 16 rows, two of them per wave of the fast launch, the
 # runs of fast chunk rows cut into such pairs (an odd chunk goes to the
-# boundary launch)
+# boundary launch); rows 24 (T >= 6): chunks of 8 rows, three per fast wave
+# (the chunks of a run left over go to the boundary launch)
 SHAPES = {2: [(16, 4), (4, 1), (8, 8), (4, 2), (32, 4)], 3: [(16, 2), (4, 4), (8, 1), (32, 1)],
           4: [(4, 8), (8, 4), (16, 2), (32, 2)], 5: [(8, 2), (4, 4), (16, 4), (32, 8)],
-          6: [(16, 4), (16, 1), (32, 4), (32, 2)], 7: [(16, 2), (32, 4)],
-          8: [(16, 4), (16, 8), (32, 4)]}
+          6: [(16, 4), (16, 1), (32, 4), (32, 2), (24, 4)], 7: [(16, 2), (32, 4), (24, 4), (24, 1)],
+          8: [(16, 4), (16, 8), (32, 4), (24, 4)]}
 
 
 @pytest.mark.parametrize("storage", ["f32", "f64"])
@@ -275,7 +276,7 @@ def test_time_blocked_sweep_equals_one_step_sweeps_bitwise(storage, name, T, row
 
 
 @pytest.mark.parametrize("storage,rounding", [("f16s", "stochastic"), ("bf16s", "nearest")])
-@pytest.mark.parametrize("T,rows", [(6, 32), (4, 32), (8, 32), (2, 32)])
+@pytest.mark.parametrize("T,rows", [(6, 32), (4, 32), (8, 32), (2, 32), (6, 24), (7, 24), (8, 24)])
 @pytest.mark.parametrize("name", ["tall", "taller"])
 def test_tall_waves_equal_16_row_waves_16bit(storage, rounding, T, rows, name):
     """16-bit storages round once per T-step sweep, after its last step; a
@@ -433,7 +434,7 @@ def test_time_block_autotune_picks_a_shape_and_keeps_the_results(T, name):
     out = blk.autotune_time_block(T, trial_sweeps=2)
     say(f"autotune T={T} {name}: {out}")
     assert out["steps"] == T and out["waves"] in (1, 2, 4, 8) and out["ms_per_step"] > 0
-    assert out["rows"] in ((16, 32) if T >= 6 else (4, 8, 16, 32))
+    assert out["rows"] in ((16, 24, 32) if T >= 6 else (4, 8, 16, 32))
     assert blk.steps_done == 0
     one.step(steps)
     blk.step(steps)
@@ -453,10 +454,12 @@ def test_time_blocked_sweep_refuses_what_it_cannot_do():
     with pytest.raises(Exception):
         Solver(Config(nx=64, ny=20, storage="f32", layout="eq", periodic=True)).set_time_block(4)
     s = Solver(Config(storage="f32", layout="eq", **base))
-    for bad in [(9, 0, 0), (0, 0, 0), (2, 6, 0), (2, 4, 3), (1, 4, 0), (6, 8, 0)]:
+    for bad in [(9, 0, 0), (0, 0, 0), (2, 6, 0), (2, 4, 3), (1, 4, 0), (6, 8, 0), (5, 24, 0),
+                (7, 12, 0)]:
         with pytest.raises(Exception):
             s.set_time_block(*bad)
     s.set_time_block(3, 16, 2)
+    s.set_time_block(7, 24, 4)
     s.set_time_block(4)  # the shape is kept per step count
 
 
