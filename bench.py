@@ -766,7 +766,7 @@ def main():
                     default="f64,f32,f16s,f16s-sr,bf16s-sr,f64-eq,f32-eq,f16s-eq-sr,bf16s-eq-sr,"
                             "f16s-eq-tb-sr,f16s-eq-tb4-sr,"
                             "f64-eq-tb8,f32-eq-tb6,f32-eq-tb7,f32-eq-tb8,f16s-eq-tb6-sr,"
-                            "f16s-eq-tb7-sr,bf16s-eq-tb7-sr",
+                            "f16s-eq-tb7-sr,bf16s-eq-tb7-sr,bf16s-eq-tb8-sr",
                     help="storages run; the first is the error reference")
     ap.add_argument("--record", default="f16s-sr",
                     help="storage whose one-step five-population sweep is the roofline of record")
