@@ -11,7 +11,11 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmcrack.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["api.cpp", "sweep.hip", "sweep2.hip", "sweep_block_f64.hip", "sweep_block_f32.hip",
-           "sweep_block_f16.hip", "sweep_block_bf16.hip", "crack.hip", "batch.hip", "io.hip", "adjoint.hip", "macro_bc.hip"]
+           "sweep_block_f16.hip", "sweep_block_f16_t8.hip", "sweep_block_bf16.hip", "crack.hip",
+           "batch.hip", "io.hip", "adjoint.hip", "macro_bc.hip"]
+# per-source flags: the FP16 sweep of eight steps unrolls its 24-row march in
+# full (see that file)
+EXTRA = {"sweep_block_f16_t8.hip": ["-mllvm", "-pragma-unroll-threshold=65536"]}
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -27,8 +31,8 @@ def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     compile_flags = [f for f in FLAGS if f != "-shared"]
-    cmds = [[hipcc, *compile_flags, "-I" + INCLUDE, "-c", os.path.join(CSRC, src), "-o",
-             os.path.join(bdir, src + ".o")] for src in SOURCES]
+    cmds = [[hipcc, *compile_flags, *EXTRA.get(src, []), "-I" + INCLUDE, "-c", os.path.join(CSRC, src),
+             "-o", os.path.join(bdir, src + ".o")] for src in SOURCES]
     if verbose:
         for c in cmds:
             print(" ".join(c), flush=True)

@@ -872,10 +872,10 @@ int tune_shapes(hipStream_t st, int32_t trial_steps, Set set, Run run, int32_t *
 // steps costs little more than a short one: it moves the same bytes.  Only
 // the ratios matter to the tail plan.
 const double kSweepUs[4][lbmk::kMaxTimeBlock] = {
-    {268.7, 319.3, 321.7, 342.6, 337.1, 348.4, 374.5, 466.8},   // FP16
-    {269.7, 312.5, 324.1, 345.7, 337.2, 348.6, 363.9, 393.9},   // BF16
-    {354.5, 388.8, 406.2, 418.3, 409.2, 419.2, 426.1, 445.2},   // FP32
-    {685.0, 852.5, 846.7, 843.2, 880.9, 897.1, 861.5, 849.2}};  // FP64
+    {269.3, 317.4, 322.0, 342.6, 337.3, 347.9, 374.8, 408.4},   // FP16
+    {270.0, 315.1, 325.1, 347.3, 338.6, 348.6, 364.8, 392.9},   // BF16
+    {354.9, 389.6, 407.1, 417.3, 408.7, 421.3, 427.3, 446.8},   // FP32
+    {686.0, 854.3, 844.3, 846.7, 882.9, 898.1, 862.6, 852.0}};  // FP64
 
 int cost_row(Store s) {
   switch (s) {
@@ -1021,7 +1021,7 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     // T = 2 .. 8, the fastest measured on a 16384 x 8192 plate
     static_assert(lbmk::kMaxTimeBlock == 8, "one shape per T = 2 .. 8");
     static const int kShape[3][7][3] = {
-        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {16, 2, 3}, {16, 4, 0}, {24, 4, 3}, {16, 4, 3}},   // 16-bit
+        {{4, 4, 3}, {8, 4, 2}, {8, 4, 0}, {16, 2, 3}, {16, 4, 0}, {24, 4, 3}, {24, 4, 3}},   // 16-bit
         {{4, 4, 3}, {4, 4, 2}, {8, 4, 3}, {16, 4, 3}, {32, 4, 3}, {32, 4, 3}, {24, 4, 3}},   // FP32
         {{8, 2, 0}, {8, 2, 2}, {8, 4, 2}, {16, 4, 3}, {16, 4, 3}, {16, 4, 3}, {32, 4, 3}}};  // FP64
     const int kind = half ? 0 : (is_fp64(s) ? 2 : 1);
@@ -1036,13 +1036,11 @@ int lbm_init(const lbm_config *cfg, lbm_handle **out) {
     // 61.9 against 66.1, FP64 T = 8 106.6 against 110.4 (FP32 T = 8 is
     // slower: 86.1 against 59.3)
     if (s == Store::F16S) h->blk_rows[6] = 32;
-    // rows 24 (three 8-row chunks per fast wave): FP16 T = 7 53.5 against
-    // 56.1 us per step with 16 rows, BF16 T = 7 51.9 against 54.5, BF16
-    // T = 8 49.0 against 55.9, FP32 T = 8 56.2 against 58.8; not for FP16
-    // T = 8 (182 us per step: its march no longer fits the instruction
-    // cache), FP32 T = 7 (62.8 against 62.1 with 32 rows) or FP64 T = 8
-    // (107.5 against 106.4)
-    if (s == Store::BF16S) h->blk_rows[8] = 24;
+    // rows 24 in the table (three 8-row chunks per fast wave): FP16 T = 7
+    // 53.5 against 56.1 us per step with 16 rows, T = 8 51.0 against 54.3,
+    // BF16 T = 7 51.9 against 54.5, T = 8 49.0 against 55.9, FP32 T = 8 56.2
+    // against 58.8; not for FP32 T = 7 (62.8 against 62.1 with 32 rows) or
+    // FP64 T = 8 (107.5 against 106.4)
   }
 
   {

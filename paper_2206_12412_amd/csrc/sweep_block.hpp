@@ -621,28 +621,33 @@ hipError_t block_rows(const BlockArgs<S, W, C> &A, int rows, int waves, hipStrea
   }
 }
 
-template <typename S, typename W, typename C, int VEC, bool SR>
+// T = TLO .. THI only (a translation unit may hold some of the step counts,
+// built with other compiler limits)
+template <typename S, typename W, typename C, int VEC, bool SR, int TLO, int THI>
 hipError_t block_steps(const BlockArgs<S, W, C> &A, int rows, int waves, hipStream_t st,
                        const SideStream &ss) {
-  switch (A.steps) {
-    case 2: return block_rows<S, W, C, VEC, SR, 2>(A, rows, waves, st, ss);
-    case 3: return block_rows<S, W, C, VEC, SR, 3>(A, rows, waves, st, ss);
-    case 4: return block_rows<S, W, C, VEC, SR, 4>(A, rows, waves, st, ss);
-    case 5: return block_rows<S, W, C, VEC, SR, 5>(A, rows, waves, st, ss);
-    case 6: return block_rows<S, W, C, VEC, SR, 6>(A, rows, waves, st, ss);
-    case 7: return block_rows<S, W, C, VEC, SR, 7>(A, rows, waves, st, ss);
-    case 8: return block_rows<S, W, C, VEC, SR, 8>(A, rows, waves, st, ss);
-    default: return hipErrorInvalidValue;
+  const int T = A.steps;
+  if (T < TLO || T > THI) return hipErrorInvalidValue;
+  switch (T) {
+    case 2: if constexpr (TLO <= 2 && 2 <= THI) return block_rows<S, W, C, VEC, SR, 2>(A, rows, waves, st, ss); break;
+    case 3: if constexpr (TLO <= 3 && 3 <= THI) return block_rows<S, W, C, VEC, SR, 3>(A, rows, waves, st, ss); break;
+    case 4: if constexpr (TLO <= 4 && 4 <= THI) return block_rows<S, W, C, VEC, SR, 4>(A, rows, waves, st, ss); break;
+    case 5: if constexpr (TLO <= 5 && 5 <= THI) return block_rows<S, W, C, VEC, SR, 5>(A, rows, waves, st, ss); break;
+    case 6: if constexpr (TLO <= 6 && 6 <= THI) return block_rows<S, W, C, VEC, SR, 6>(A, rows, waves, st, ss); break;
+    case 7: if constexpr (TLO <= 7 && 7 <= THI) return block_rows<S, W, C, VEC, SR, 7>(A, rows, waves, st, ss); break;
+    case 8: if constexpr (TLO <= 8 && 8 <= THI) return block_rows<S, W, C, VEC, SR, 8>(A, rows, waves, st, ss); break;
+    default: break;
   }
+  return hipErrorInvalidValue;
 }
 
-template <typename S, typename W, typename C, int VEC>
+template <typename S, typename W, typename C, int VEC, int TLO = 2, int THI = kMaxTimeBlock>
 hipError_t block_r(const void *args, int rows, int waves, hipStream_t st, const SideStream &ss) {
   const auto &A = *static_cast<const BlockArgs<S, W, C> *>(args);
   if constexpr (sizeof(S) == 2) {
-    if (A.s0.sr) return block_steps<S, W, C, VEC, true>(A, rows, waves, st, ss);
+    if (A.s0.sr) return block_steps<S, W, C, VEC, true, TLO, THI>(A, rows, waves, st, ss);
   }
-  return block_steps<S, W, C, VEC, false>(A, rows, waves, st, ss);
+  return block_steps<S, W, C, VEC, false, TLO, THI>(A, rows, waves, st, ss);
 }
 
 }  // namespace blk

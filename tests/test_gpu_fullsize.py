@@ -115,6 +115,7 @@ def parse(name):
                                          ("f32-eq-tb4", 1e-5), ("f16s-eq-tb3-sr", F16_TOL),
                                          ("f16s-eq-tb4-sr", F16_TOL), ("f16s-eq-tb5-sr", F16_TOL),
                                          ("f16s-eq-tb6-sr", F16_TOL), ("f16s-eq-tb7-sr", F16_TOL),
+                                         ("f16s-eq-tb8-sr", F16_TOL),
                                          ("f32-eq-tb7", 1e-5), ("f32-eq-tb8", 1e-5),
                                          ("f64-eq-tb8", 1e-12)])
 def test_precision_plate_windows(big_plate, storage, tol):
@@ -185,6 +186,7 @@ def scaled_precision_ref():
                                                ("f16s-sr", 1e-3, 2e-4),
                                                ("f16s-eq-tb6-sr", 1e-3, 2e-4),
                                                ("f16s-eq-tb7-sr", 1e-3, 2e-4),
+                                               ("f16s-eq-tb8-sr", 1e-3, 2e-4),
                                                ("bf16s-eq-tb6-sr", 2.5e-3, 8e-4),
                                                ("bf16s-eq-tb7-sr", 2.5e-3, 8e-4)])
 def test_precision_workload_K_error(scaled_precision_ref, storage, ktol, wtol):
@@ -192,7 +194,7 @@ def test_precision_workload_K_error(scaled_precision_ref, storage, ktol, wtol):
     precision workload scaled to 1536 x 768: max_n |K_n - K_n^ref| /
     max_n |K_n^ref| within 1e-5 for FP32 and within the 1e-3 bar of the
     precision extension for FP16 storage with stochastic rounding, one step
-    per sweep (five populations), six and seven (the benchmark's headline); tips
+    per sweep (five populations), six, seven and eight (the benchmark's headline); tips
     bit-exact.  BF16 (8-bit mantissa) is held to three times its measured
     error instead: on the full-size workload it does not meet 1e-3."""
     p, tr, w_ref = scaled_precision_ref
