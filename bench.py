@@ -94,11 +94,16 @@ def plate_config(p, storage, trace_cap):
                   tau_hist=p.traction_history(), wdot0=p.wdot0(), trace_cap=trace_cap)
 
 
+# the files (under csrc/) that shape the sweep kernels: their sources and the
+# build flags
+KERNEL_SOURCES = ("sweep.hip", "sweep2.hip", "sweep_block.hpp", "sweep_block_f64.hip",
+                  "sweep_block_f32.hip", "sweep_block_f16.hip", "sweep_block_f16_t8.hip",
+                  "sweep_block_bf16.hip", "sweep_core.hpp", "lbm_internal.hpp", "../build.py")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep2.hip", "sweep_block.hpp", "sweep_block_f64.hip", "sweep_block_f32.hip",
-              "sweep_block_f16.hip", "sweep_block_f16_t8.hip", "sweep_block_bf16.hip", "sweep_core.hpp",
-              "lbm_internal.hpp", "../build.py"):  # the build flags shape the kernels too
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2206_12412_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

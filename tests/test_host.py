@@ -139,3 +139,15 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, cwd=ROOT)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_build_lists_every_source_and_the_traffic_hash_covers_the_sweeps():
+    """Every HIP source in csrc is compiled, per-source flags name listed
+    sources, and the hash that gates the stored traffic counters covers every
+    sweep source and the build flags (a change to any of them voids them)."""
+    from paper_2206_12412_amd import build as B
+    srcs = sorted(f for f in os.listdir(B.CSRC) if f.endswith((".hip", ".cpp")))
+    assert sorted(B.SOURCES) == srcs
+    assert set(B.EXTRA) <= set(B.SOURCES)
+    sweeps = {f for f in os.listdir(B.CSRC) if f.startswith("sweep")}
+    assert sweeps | {"lbm_internal.hpp", "../build.py"} == set(bench.KERNEL_SOURCES)
